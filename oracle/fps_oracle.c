@@ -1,0 +1,525 @@
+/*
+ * CPU oracle for the filtered Paterson-Stockmeyer (PS) evaluation of a
+ * matrix power series  F(Z) = sum_{k=0..m} c_k Z^k  on a sparse Z.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; it exists so that tests and the CPU-baseline timing can
+ * check the HIP implementation against a plain, slow, obviously correct
+ * version written from the paper.  It shares no code with the HIP path.
+ *
+ * Paper: "A filtering technique for the matrix power series being
+ * near-sparse" (arXiv 2208.05683).
+ *
+ * What is computed (paper Section 2.1 eqs. 2-6, Section 3.1.2 eqs. 11, 13,
+ * 14, Algorithm 2 with a fixed entry threshold tau in place of the adaptive
+ * filter of Algorithm 1; the "simple filtering method" of Section 3.1.1):
+ *
+ *   N = m+1, q = s, b = ceil(N/q), g = [N - q(b-1) == 1]          (eq. 6)
+ *   P_1 = Z,  P_{j+1} = D_tau(Z (x) P_j)                            (eq. 11)
+ *   Bhat_i = sum_{j<q} c_{iq+j} P_j,  P_0 = I, not filtered          (eq. 13)
+ *   S_0 = Bhat_{b-1};  if g: S_1 = Bhat_{b-2} + c_{(b-1)q} P_q,
+ *                           no product and no filter                (eq. 14)
+ *   S_i = D_tau(Bhat_{b-1-i} + P_q (x) S_{i-1})                     (eq. 14)
+ *   F   = S_{b-1}
+ *
+ * Readings of points the paper leaves open (fixed here, shared by every
+ * implementation that claims parity with this file):
+ *   - D_tau drops an entry x iff x == 0 or |x| < tau (|x| == tau is kept);
+ *     exact zeros are dropped everywhere, also where nothing is filtered.
+ *   - (x) is Gustavson's row-wise product: for output row r, for the stored
+ *     k of row r of the left operand in ascending order, acc += a_rk * B_k,:
+ *     with one fused multiply-add per term, acc starting at +0.
+ *   - Bhat_i and the g-shortcut sum accumulate the terms c_j P_j in
+ *     ascending j with fused multiply-adds from +0; terms with c_j == 0
+ *     are skipped.  The g-shortcut sum is Bhat_{b-2} extended by the term
+ *     j = q, i.e. sum_{j=0..q} c_{(b-2)q+j} P_j in one ascending pass.
+ *   - In a Horner step the block enters with one addition: x = bhat + prod.
+ *   - The left factor is Z for the powers (eq. 11) and P_q for the Horner
+ *     steps (eq. 14), as the paper writes them.
+ *   - Powers are formed up to J = q when b >= 2, else up to J = m.
+ *
+ * Rows are independent; OpenMP splits rows across threads for timing only.
+ * Each row is computed by one thread in the order above, so results do not
+ * depend on the thread count.  Only the dropped-norm statistic (a sum over
+ * rows per column) may differ in its last bits between thread counts.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    int64_t *row_ptr; /* n+1 */
+    int32_t *col;     /* nnz, sorted and unique per row */
+    double *val;      /* nnz */
+} orc_csr;
+
+typedef struct {
+    int32_t kind;   /* 0 power P_{index}, 1 block Bhat_{index}, 2 g-shortcut S_1, 3 Horner S_{index} */
+    int32_t index;
+    int64_t products;    /* scalar multiply-adds of the product part */
+    int64_t nnz_struct;  /* distinct structural entries before dropping */
+    int64_t nnz_kept;
+    int64_t n_dropped;   /* nonzero entries removed by the tau test */
+    int64_t n_zero;      /* entries removed because they were exactly zero */
+    double dropped_1norm; /* max over columns of the sum of |dropped| */
+    double dropped_max;   /* largest |dropped| (0 if none) */
+    double kept_min;      /* smallest |kept| (inf if none) */
+} orc_stage_stats;
+
+enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_ENOMEM = 3 };
+
+/* ------------------------------------------------------------------ */
+/* small helpers                                                        */
+/* ------------------------------------------------------------------ */
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+void orc_csr_free(orc_csr *m)
+{
+    if (!m) return;
+    free(m->row_ptr);
+    free(m->col);
+    free(m->val);
+    m->row_ptr = NULL;
+    m->col = NULL;
+    m->val = NULL;
+    m->nnz = 0;
+}
+
+static int nthreads_or_default(int nt)
+{
+#ifdef _OPENMP
+    return nt > 0 ? nt : omp_get_max_threads();
+#else
+    (void)nt;
+    return 1;
+#endif
+}
+
+/* per-thread growable output of kept entries */
+typedef struct {
+    int32_t *col;
+    double *val;
+    int64_t len, cap;
+} rowbuf;
+
+static int rowbuf_push(rowbuf *b, int32_t c, double v)
+{
+    if (b->len == b->cap) {
+        int64_t nc = b->cap ? 2 * b->cap : 1024;
+        int32_t *c2 = realloc(b->col, (size_t)nc * sizeof(int32_t));
+        if (!c2) return -1;
+        b->col = c2;
+        double *v2 = realloc(b->val, (size_t)nc * sizeof(double));
+        if (!v2) return -1;
+        b->val = v2;
+        b->cap = nc;
+    }
+    b->col[b->len] = c;
+    b->val[b->len] = v;
+    b->len++;
+    return 0;
+}
+
+/*
+ * One "term source" per output row: the generic row computation below is
+ *     x[c] = extra[c] + sum_t  a_t * R_t[c]
+ * accumulated term by term in the given order with fma from +0, then the
+ * extra row (if any) enters with one addition, then the drop test.
+ * For a product A (x) B the terms of row r are (A_rk, B_k,:) over k in A_r;
+ * for a coefficient sum they are (c_j, P_j[r,:]).
+ */
+typedef struct {
+    /* mode 0: product; mode 1: coefficient sum */
+    int mode;
+    const orc_csr *A, *B;      /* product operands */
+    int nterms;
+    const double *coef;        /* coefficient-sum weights */
+    const orc_csr *const *mat; /* coefficient-sum matrices; NULL = identity */
+    const orc_csr *extra;      /* row added after the products (may be NULL) */
+    double tau;                /* drop |x| < tau; 0 drops exact zeros only */
+    int64_t n;
+} orc_job;
+
+typedef struct {
+    double *acc;
+    int64_t *mark; /* mark[c] == r+1 if column c touched in row r */
+    int32_t *list;
+    double *drop_colsum;
+    rowbuf out;
+    int64_t products, nnz_struct, n_dropped, n_zero;
+    double dropped_max, kept_min;
+    int err;
+} orc_ws;
+
+static void compute_row(const orc_job *jb, orc_ws *w, int64_t r, int64_t *row_off, int64_t *row_len)
+{
+    int64_t nl = 0;
+    const int64_t tag = r + 1;
+#define TOUCH(c)                                  \
+    do {                                          \
+        if (w->mark[(c)] != tag) {                \
+            w->mark[(c)] = tag;                   \
+            w->acc[(c)] = 0.0;                    \
+            w->list[nl++] = (int32_t)(c);         \
+        }                                         \
+    } while (0)
+
+    if (jb->mode == 0) {
+        const orc_csr *A = jb->A, *B = jb->B;
+        for (int64_t p = A->row_ptr[r]; p < A->row_ptr[r + 1]; ++p) {
+            const int64_t k = A->col[p];
+            const double a = A->val[p];
+            for (int64_t t = B->row_ptr[k]; t < B->row_ptr[k + 1]; ++t) {
+                const int32_t c = B->col[t];
+                TOUCH(c);
+                w->acc[c] = fma(a, B->val[t], w->acc[c]);
+                w->products++;
+            }
+        }
+    } else {
+        for (int t = 0; t < jb->nterms; ++t) {
+            const double a = jb->coef[t];
+            const orc_csr *M = jb->mat[t];
+            if (M == NULL) { /* identity: row r has the single entry (r, 1) */
+                TOUCH(r);
+                w->acc[r] = fma(a, 1.0, w->acc[r]);
+                w->products++;
+            } else {
+                for (int64_t p = M->row_ptr[r]; p < M->row_ptr[r + 1]; ++p) {
+                    const int32_t c = M->col[p];
+                    TOUCH(c);
+                    w->acc[c] = fma(a, M->val[p], w->acc[c]);
+                    w->products++;
+                }
+            }
+        }
+    }
+    if (jb->extra) {
+        const orc_csr *E = jb->extra;
+        for (int64_t p = E->row_ptr[r]; p < E->row_ptr[r + 1]; ++p) {
+            const int32_t c = E->col[p];
+            TOUCH(c);
+            w->acc[c] = E->val[p] + w->acc[c];
+        }
+    }
+#undef TOUCH
+    qsort(w->list, (size_t)nl, sizeof(int32_t), cmp_i32);
+    w->nnz_struct += nl;
+    *row_off = w->out.len;
+    for (int64_t i = 0; i < nl; ++i) {
+        const int32_t c = w->list[i];
+        const double x = w->acc[c];
+        if (x == 0.0) {
+            w->n_zero++;
+            continue;
+        }
+        if (fabs(x) < jb->tau) {
+            w->n_dropped++;
+            w->drop_colsum[c] += fabs(x);
+            if (fabs(x) > w->dropped_max) w->dropped_max = fabs(x);
+            continue;
+        }
+        if (fabs(x) < w->kept_min) w->kept_min = fabs(x);
+        if (rowbuf_push(&w->out, c, x)) w->err = 1;
+    }
+    *row_len = w->out.len - *row_off;
+}
+
+static int run_job(const orc_job *jb, orc_csr *C, orc_stage_stats *st, int nthreads)
+{
+    const int64_t n = jb->n;
+    const int nt = nthreads_or_default(nthreads);
+    orc_ws *ws = calloc((size_t)nt, sizeof(orc_ws));
+    int64_t *off = malloc((size_t)(n + 1) * sizeof(int64_t));
+    int64_t *len = malloc((size_t)(n + 1) * sizeof(int64_t));
+    int32_t *owner = malloc((size_t)(n + 1) * sizeof(int32_t));
+    if (!ws || !off || !len || !owner) {
+        free(ws); free(off); free(len); free(owner);
+        return ORC_ENOMEM;
+    }
+    int err = 0;
+    for (int t = 0; t < nt; ++t) {
+        ws[t].acc = malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+        ws[t].mark = calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+        ws[t].list = malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+        ws[t].drop_colsum = calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+        ws[t].kept_min = INFINITY;
+        if (!ws[t].acc || !ws[t].mark || !ws[t].list || !ws[t].drop_colsum) err = 1;
+    }
+    if (!err) {
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+        {
+#ifdef _OPENMP
+            const int t = omp_get_thread_num();
+#else
+            const int t = 0;
+#endif
+#ifdef _OPENMP
+#pragma omp for schedule(static)
+#endif
+            for (int64_t r = 0; r < n; ++r) {
+                compute_row(jb, &ws[t], r, &off[r], &len[r]);
+                owner[r] = t;
+            }
+        }
+    }
+    for (int t = 0; t < nt; ++t) err |= ws[t].err;
+    if (!err) {
+        C->n = n;
+        C->row_ptr = malloc((size_t)(n + 1) * sizeof(int64_t));
+        if (!C->row_ptr) err = 1;
+    }
+    if (!err) {
+        C->row_ptr[0] = 0;
+        for (int64_t r = 0; r < n; ++r) C->row_ptr[r + 1] = C->row_ptr[r] + len[r];
+        C->nnz = C->row_ptr[n];
+        C->col = malloc((size_t)(C->nnz > 0 ? C->nnz : 1) * sizeof(int32_t));
+        C->val = malloc((size_t)(C->nnz > 0 ? C->nnz : 1) * sizeof(double));
+        if (!C->col || !C->val) err = 1;
+    }
+    if (!err) {
+        for (int64_t r = 0; r < n; ++r) {
+            const rowbuf *b = &ws[owner[r]].out;
+            memcpy(C->col + C->row_ptr[r], b->col + off[r], (size_t)len[r] * sizeof(int32_t));
+            memcpy(C->val + C->row_ptr[r], b->val + off[r], (size_t)len[r] * sizeof(double));
+        }
+        if (st) {
+            memset(st, 0, sizeof(*st));
+            st->kept_min = INFINITY;
+            double *colsum = calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+            if (!colsum) err = 1;
+            for (int t = 0; t < nt && !err; ++t) {
+                st->products += ws[t].products;
+                st->nnz_struct += ws[t].nnz_struct;
+                st->n_dropped += ws[t].n_dropped;
+                st->n_zero += ws[t].n_zero;
+                if (ws[t].dropped_max > st->dropped_max) st->dropped_max = ws[t].dropped_max;
+                if (ws[t].kept_min < st->kept_min) st->kept_min = ws[t].kept_min;
+                for (int64_t c = 0; c < n; ++c) colsum[c] += ws[t].drop_colsum[c];
+            }
+            if (!err) {
+                double mx = 0.0;
+                for (int64_t c = 0; c < n; ++c)
+                    if (colsum[c] > mx) mx = colsum[c];
+                st->dropped_1norm = mx;
+                st->nnz_kept = C->nnz;
+            }
+            free(colsum);
+        }
+    }
+    for (int t = 0; t < nt; ++t) {
+        free(ws[t].acc); free(ws[t].mark); free(ws[t].list); free(ws[t].drop_colsum);
+        free(ws[t].out.col); free(ws[t].out.val);
+    }
+    free(ws); free(off); free(len); free(owner);
+    if (err) {
+        orc_csr_free(C);
+        return ORC_ENOMEM;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* single stages                                                        */
+/* ------------------------------------------------------------------ */
+
+/*
+ * C = D_tau(E + A (x) B): one filtered product (eq. 11 with E absent,
+ * eq. 14 with E = Bhat).  tau = 0 drops exact zeros only.
+ */
+int orc_spgemm(const orc_csr *A, const orc_csr *B, const orc_csr *E, double tau,
+               orc_csr *C, orc_stage_stats *st, int nthreads)
+{
+    if (!A || !B || !C || A->n != B->n || (E && E->n != A->n) || !(tau >= 0.0)) return ORC_EINVAL;
+    orc_job jb = {0};
+    jb.mode = 0;
+    jb.A = A;
+    jb.B = B;
+    jb.extra = E;
+    jb.tau = tau;
+    jb.n = A->n;
+    return run_job(&jb, C, st, nthreads);
+}
+
+/*
+ * C = sum_t coef[t] * M_t in the given order (M_t == NULL means I), exact
+ * zeros dropped, nothing else (eq. 13: the blocks are not filtered).
+ */
+int orc_axpy(int64_t n, int nterms, const double *coef, const orc_csr *const *mats,
+             orc_csr *C, orc_stage_stats *st, int nthreads)
+{
+    if (!C || n < 0 || nterms < 0) return ORC_EINVAL;
+    for (int t = 0; t < nterms; ++t)
+        if (mats[t] && mats[t]->n != n) return ORC_EINVAL;
+    orc_job jb = {0};
+    jb.mode = 1;
+    jb.nterms = nterms;
+    jb.coef = coef;
+    jb.mat = mats;
+    jb.tau = 0.0;
+    jb.n = n;
+    return run_job(&jb, C, st, nthreads);
+}
+
+/* ------------------------------------------------------------------ */
+/* schedule (eqs. 5-6 with q = s given)                                 */
+/* ------------------------------------------------------------------ */
+
+int orc_schedule(int m, int s, int *N, int *q, int *b, int *g, int *J, int *start, int *n_spgemm)
+{
+    if (m < 0 || s < 1) return ORC_EINVAL;
+    const int NN = m + 1, qq = s, bb = (NN + qq - 1) / qq;
+    const int gg = (NN - qq * (bb - 1) == 1) ? 1 : 0;
+    const int JJ = (bb >= 2) ? qq : m;
+    *N = NN; *q = qq; *b = bb; *g = gg; *J = JJ;
+    *start = (bb >= 2) ? 1 + gg : 0;
+    *n_spgemm = (JJ >= 1 ? JJ - 1 : 0) + (bb >= 2 ? bb - 1 - gg : 0);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* the filtered PS evaluation (Algorithm 2 with a fixed tau)             */
+/* ------------------------------------------------------------------ */
+
+static void record(orc_stage_stats *stats, int max_stats, int *ns, const orc_stage_stats *st,
+                   int kind, int index)
+{
+    if (*ns < max_stats) {
+        stats[*ns] = *st;
+        stats[*ns].kind = kind;
+        stats[*ns].index = index;
+    }
+    (*ns)++;
+}
+
+/* block i of eq. 13 extended to the coefficient indices [lo, hi] of the
+ * series: sum over j with lo <= i*q+j <= hi of c_{iq+j} P_j, ascending j. */
+static int coefficient_block(const orc_csr *const *P, const double *c, int m, int q, int i, int jmax,
+                             int64_t n, orc_csr *out, orc_stage_stats *st, int nthreads)
+{
+    double coef[256];
+    const orc_csr *mats[256];
+    int nt = 0;
+    for (int j = 0; j <= jmax; ++j) {
+        const int k = i * q + j;
+        if (k > m) break;
+        if (c[k] == 0.0) continue;
+        if (nt >= 256) return ORC_EINVAL;
+        coef[nt] = c[k];
+        mats[nt] = (j == 0) ? NULL : P[j];
+        nt++;
+    }
+    return orc_axpy(n, nt, coef, mats, out, st, nthreads);
+}
+
+int orc_filtered_ps(const orc_csr *Z, const double *c, int m, int s, double tau, orc_csr *F,
+                    orc_stage_stats *stats, int max_stats, int *n_stats, int nthreads)
+{
+    int N, q, b, g, J, start, nsp;
+    if (!Z || !c || !F || !(tau >= 0.0) || orc_schedule(m, s, &N, &q, &b, &g, &J, &start, &nsp))
+        return ORC_EINVAL;
+    if (q > 255) return ORC_EINVAL;
+    const int64_t n = Z->n;
+    int ns = 0, rc = ORC_OK;
+    orc_stage_stats st;
+    orc_csr *P = calloc((size_t)(J + 2), sizeof(orc_csr));
+    const orc_csr **Pp = calloc((size_t)(J + 2), sizeof(orc_csr *));
+    if (!P || !Pp) { free(P); free(Pp); return ORC_ENOMEM; }
+    Pp[0] = NULL;
+    if (J >= 1) Pp[1] = Z;
+
+    /* step 1: filtered powers, P_{j+1} = D_tau(Z (x) P_j) (eq. 11) */
+    for (int j = 1; j + 1 <= J && rc == ORC_OK; ++j) {
+        rc = orc_spgemm(Z, Pp[j], NULL, tau, &P[j + 1], &st, nthreads);
+        if (rc == ORC_OK) {
+            Pp[j + 1] = &P[j + 1];
+            record(stats, max_stats, &ns, &st, 0, j + 1);
+        }
+    }
+
+    orc_csr S = {0}, T = {0}, Bh = {0};
+    if (rc == ORC_OK && b == 1) {
+        /* one block only: F = Bhat_0, not filtered (eq. 13) */
+        rc = coefficient_block(Pp, c, m, q, 0, q - 1, n, &S, &st, nthreads);
+        if (rc == ORC_OK) record(stats, max_stats, &ns, &st, 1, 0);
+    } else if (rc == ORC_OK) {
+        if (g) {
+            /* S_1 = Bhat_{b-2} + c_{(b-1)q} P_q: no product, no filter (eq. 14) */
+            rc = coefficient_block(Pp, c, m, q, b - 2, q, n, &S, &st, nthreads);
+            if (rc == ORC_OK) record(stats, max_stats, &ns, &st, 2, 1);
+        } else {
+            /* S_0 = Bhat_{b-1} (eq. 14) */
+            rc = coefficient_block(Pp, c, m, q, b - 1, q - 1, n, &S, &st, nthreads);
+            if (rc == ORC_OK) record(stats, max_stats, &ns, &st, 1, b - 1);
+        }
+        /* S_i = D_tau(Bhat_{b-1-i} + P_q (x) S_{i-1}) (eq. 14) */
+        for (int i = start; i <= b - 1 && rc == ORC_OK; ++i) {
+            rc = coefficient_block(Pp, c, m, q, b - 1 - i, q - 1, n, &Bh, &st, nthreads);
+            if (rc != ORC_OK) break;
+            record(stats, max_stats, &ns, &st, 1, b - 1 - i);
+            rc = orc_spgemm(Pp[q], &S, &Bh, tau, &T, &st, nthreads);
+            orc_csr_free(&Bh);
+            if (rc != ORC_OK) break;
+            record(stats, max_stats, &ns, &st, 3, i);
+            orc_csr_free(&S);
+            S = T;
+            memset(&T, 0, sizeof(T));
+        }
+    }
+    for (int j = 2; j <= J; ++j) orc_csr_free(&P[j]);
+    free(P);
+    free(Pp);
+    if (rc != ORC_OK) {
+        orc_csr_free(&S);
+        return rc;
+    }
+    *F = S;
+    if (n_stats) *n_stats = ns;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* plain definition, long double: P_m(Z) by Horner (Qin) on dense Z     */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Y = c_m I; for k = m-1..0: Y = Y Z + c_k I  (eq. 1 evaluated by the Qin /
+ * Horner scheme of Section 2.1), in long double on a dense n x n matrix
+ * (row-major).  For brute-force checks on small n.
+ */
+int orc_dense_horner_ld(int64_t n, const double *Zd, const double *c, int m, long double *Y)
+{
+    if (n < 0 || m < 0 || !Zd || !c || !Y) return ORC_EINVAL;
+    long double *T = malloc((size_t)(n * n > 0 ? n * n : 1) * sizeof(long double));
+    long double *Zl = malloc((size_t)(n * n > 0 ? n * n : 1) * sizeof(long double));
+    if (!T || !Zl) { free(T); free(Zl); return ORC_ENOMEM; }
+    for (int64_t i = 0; i < n * n; ++i) Zl[i] = (long double)Zd[i];
+    for (int64_t i = 0; i < n * n; ++i) Y[i] = 0.0L;
+    for (int64_t i = 0; i < n; ++i) Y[i * n + i] = (long double)c[m];
+    for (int k = m - 1; k >= 0; --k) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j) {
+                long double s = 0.0L;
+                for (int64_t t = 0; t < n; ++t) s += Y[i * n + t] * Zl[t * n + j];
+                T[i * n + j] = s;
+            }
+        for (int64_t i = 0; i < n * n; ++i) Y[i] = T[i];
+        for (int64_t i = 0; i < n; ++i) Y[i * n + i] += (long double)c[k];
+    }
+    free(T);
+    free(Zl);
+    return ORC_OK;
+}

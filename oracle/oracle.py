@@ -1,0 +1,219 @@
+"""ctypes wrapper around the C oracle plus the dense double reference.
+
+Test infrastructure only (see the package docstring).
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+from fps_inputs.generators import CSR
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+# ORACLE_LIB lets the mutation tests point the wrapper at a deliberately broken build
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+_lib = None
+_lock = threading.Lock()
+
+
+class _Csr(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64),
+        ("nnz", C.c_int64),
+        ("row_ptr", C.POINTER(C.c_int64)),
+        ("col", C.POINTER(C.c_int32)),
+        ("val", C.POINTER(C.c_double)),
+    ]
+
+
+class _Stats(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32),
+        ("index", C.c_int32),
+        ("products", C.c_int64),
+        ("nnz_struct", C.c_int64),
+        ("nnz_kept", C.c_int64),
+        ("n_dropped", C.c_int64),
+        ("n_zero", C.c_int64),
+        ("dropped_1norm", C.c_double),
+        ("dropped_max", C.c_double),
+        ("kept_min", C.c_double),
+    ]
+
+
+STAGE_KINDS = {0: "power", 1: "block", 2: "gstep", 3: "horner"}
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH):
+                from . import build as _b
+
+                _b.build()
+            lib = C.CDLL(_LIB_PATH)
+            P = C.POINTER
+            lib.orc_spgemm.argtypes = [P(_Csr), P(_Csr), P(_Csr), C.c_double, P(_Csr), P(_Stats), C.c_int]
+            lib.orc_spgemm.restype = C.c_int
+            lib.orc_axpy.argtypes = [C.c_int64, C.c_int, P(C.c_double), P(P(_Csr)), P(_Csr), P(_Stats), C.c_int]
+            lib.orc_axpy.restype = C.c_int
+            lib.orc_schedule.argtypes = [C.c_int, C.c_int] + [P(C.c_int)] * 7
+            lib.orc_schedule.restype = C.c_int
+            lib.orc_filtered_ps.argtypes = [P(_Csr), P(C.c_double), C.c_int, C.c_int, C.c_double, P(_Csr),
+                                            P(_Stats), C.c_int, P(C.c_int), C.c_int]
+            lib.orc_filtered_ps.restype = C.c_int
+            lib.orc_dense_horner_ld.argtypes = [C.c_int64, P(C.c_double), P(C.c_double), C.c_int,
+                                                P(C.c_longdouble)]
+            lib.orc_dense_horner_ld.restype = C.c_int
+            lib.orc_csr_free.argtypes = [P(_Csr)]
+            lib.orc_csr_free.restype = None
+            _lib = lib
+    return _lib
+
+
+def _view(m, keep):
+    rp = np.ascontiguousarray(m.row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(m.col, dtype=np.int32)
+    vl = np.ascontiguousarray(m.val, dtype=np.float64)
+    keep.extend([rp, cl, vl])
+    s = _Csr()
+    s.n = int(m.n)
+    s.nnz = int(rp[-1])
+    s.row_ptr = rp.ctypes.data_as(C.POINTER(C.c_int64))
+    s.col = cl.ctypes.data_as(C.POINTER(C.c_int32))
+    s.val = vl.ctypes.data_as(C.POINTER(C.c_double))
+    return s
+
+
+def _take(out: _Csr) -> CSR:
+    lib = _load()
+    n = int(out.n)
+    nnz = int(out.nnz)
+    rp = np.ctypeslib.as_array(out.row_ptr, shape=(n + 1,)).copy()
+    cl = np.ctypeslib.as_array(out.col, shape=(max(nnz, 1),))[:nnz].copy()
+    vl = np.ctypeslib.as_array(out.val, shape=(max(nnz, 1),))[:nnz].copy()
+    lib.orc_csr_free(C.byref(out))
+    return CSR(n, rp, cl, vl)
+
+
+def _stats_dict(s: _Stats) -> dict:
+    d = {f: getattr(s, f) for f, _ in _Stats._fields_}
+    d["kind_name"] = STAGE_KINDS.get(d["kind"], "?")
+    return d
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def schedule(m: int, s: int) -> dict:
+    """N, q, b, g of eq. 6 with q = s given; J = highest power formed; start =
+    first filtered Horner step; n_spgemm = number of sparse products."""
+    lib = _load()
+    vals = [C.c_int() for _ in range(7)]
+    _check(lib.orc_schedule(m, s, *[C.byref(v) for v in vals]), "schedule")
+    keys = ["N", "q", "b", "g", "J", "start", "n_spgemm"]
+    return {k: v.value for k, v in zip(keys, vals)}
+
+
+def spgemm(A, B, E=None, tau: float = 0.0, nthreads: int = 0):
+    """D_tau(E + A (x) B) with Gustavson rows, k-ascending fma accumulation."""
+    lib = _load()
+    keep = []
+    a, b = _view(A, keep), _view(B, keep)
+    e = _view(E, keep) if E is not None else None
+    out, st = _Csr(), _Stats()
+    _check(lib.orc_spgemm(C.byref(a), C.byref(b), C.byref(e) if e is not None else None, float(tau),
+                          C.byref(out), C.byref(st), int(nthreads)), "spgemm")
+    return _take(out), _stats_dict(st)
+
+
+def axpy(n: int, coefs, mats, nthreads: int = 0):
+    """sum_t coefs[t] * mats[t] in the given order (None = identity); exact zeros dropped."""
+    lib = _load()
+    keep = []
+    views = [None if m is None else _view(m, keep) for m in mats]
+    arr = (C.POINTER(_Csr) * max(len(mats), 1))()
+    for i, v in enumerate(views):
+        arr[i] = C.pointer(v) if v is not None else C.POINTER(_Csr)()
+    cf = np.ascontiguousarray(coefs, dtype=np.float64)
+    out, st = _Csr(), _Stats()
+    _check(lib.orc_axpy(int(n), len(mats), cf.ctypes.data_as(C.POINTER(C.c_double)), arr, C.byref(out),
+                        C.byref(st), int(nthreads)), "axpy")
+    return _take(out), _stats_dict(st)
+
+
+def filtered_ps(Z, coeffs, m: int, s: int, tau: float, nthreads: int = 0):
+    """Filtered PS evaluation with a fixed tau.  Returns (F, per-stage stats)."""
+    lib = _load()
+    keep = []
+    z = _view(Z, keep)
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    if c.size < m + 1:
+        raise ValueError("need m+1 coefficients")
+    max_stats = 4 * (m + 4) + 8
+    stats = (_Stats * max_stats)()
+    ns = C.c_int()
+    out = _Csr()
+    _check(lib.orc_filtered_ps(C.byref(z), c.ctypes.data_as(C.POINTER(C.c_double)), int(m), int(s),
+                               float(tau), C.byref(out), stats, max_stats, C.byref(ns), int(nthreads)),
+           "filtered_ps")
+    return _take(out), [_stats_dict(stats[i]) for i in range(min(ns.value, max_stats))]
+
+
+def unfiltered_ps(Z, coeffs, m: int, s: int, nthreads: int = 0):
+    """PS scheme (eqs. 2-4) with nothing filtered (tau = 0; exact zeros dropped)."""
+    return filtered_ps(Z, coeffs, m, s, 0.0, nthreads)
+
+
+def dense_horner(Zd: np.ndarray, coeffs, m: int | None = None) -> np.ndarray:
+    """P_m(Z) = sum c_k Z^k by the Qin/Horner scheme: Y = c_m I, Y = Y Z + c_k I."""
+    c = np.asarray(coeffs, dtype=np.float64)
+    if m is None:
+        m = c.size - 1
+    n = Zd.shape[0]
+    Y = c[m] * np.eye(n)
+    for k in range(m - 1, -1, -1):
+        Y = Y @ Zd
+        Y[np.diag_indices(n)] += c[k]
+    return Y
+
+
+def dense_horner_ld(Zd: np.ndarray, coeffs, m: int | None = None) -> np.ndarray:
+    """Same definition evaluated in long double (x87 extended) in C."""
+    lib = _load()
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    if m is None:
+        m = c.size - 1
+    Zc = np.ascontiguousarray(Zd, dtype=np.float64)
+    n = Zc.shape[0]
+    Y = np.zeros((n, n), dtype=np.longdouble)
+    _check(lib.orc_dense_horner_ld(n, Zc.ctypes.data_as(C.POINTER(C.c_double)),
+                                   c.ctypes.data_as(C.POINTER(C.c_double)), int(m),
+                                   Y.ctypes.data_as(C.POINTER(C.c_longdouble))), "dense_horner_ld")
+    return Y
+
+
+def norm1(M) -> float:
+    """Max column absolute sum of a dense array or CSR."""
+    if isinstance(M, np.ndarray):
+        return float(np.max(np.sum(np.abs(M), axis=0))) if M.size else 0.0
+    cs = np.zeros(M.n)
+    np.add.at(cs, M.col, np.abs(M.val))
+    return float(cs.max()) if M.n else 0.0
+
+
+def fro_norm(M) -> float:
+    if isinstance(M, np.ndarray):
+        return float(np.sqrt(np.sum(np.abs(M) ** 2)))
+    return float(np.sqrt(np.sum(M.val ** 2)))

@@ -1,0 +1,63 @@
+"""Planted mistakes in a copy of the oracle must be caught by its pins.
+
+Each case applies one textual change to a temporary copy of the C oracle
+(never to the committed file), builds it with gcc, and runs the pin suite
+against that build in a subprocess; the suite must fail.  CPU only.
+"""
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "fps_oracle.c")
+
+MUTANTS = {
+    "tie_dropped": ("if (fabs(x) < jb->tau) {", "if (fabs(x) <= jb->tau) {"),
+    "zeros_kept": ("if (x == 0.0) {", "if (x != x) {"),
+    "block_skipped_in_step": ("w->acc[c] = E->val[p] + w->acc[c];", "w->acc[c] = 0.0 + w->acc[c];"),
+    "identity_term_lost": ("w->acc[r] = fma(a, 1.0, w->acc[r]);", "w->acc[r] = fma(a, 0.0, w->acc[r]);"),
+    "coefficient_index_shift": ("const int k = i * q + j;", "const int k = i * q + j + (j > 0);"),
+    "shortcut_ignored": ("        if (g) {\n", "        if (0) {\n"),
+    "horner_step_missing": ("for (int i = start; i <= b - 1 && rc == ORC_OK; ++i)",
+                            "for (int i = start + 1; i <= b - 1 && rc == ORC_OK; ++i)"),
+    "powers_not_filtered": ("rc = orc_spgemm(Z, Pp[j], NULL, tau, &P[j + 1], &st, nthreads);",
+                            "rc = orc_spgemm(Z, Pp[j], NULL, 0.0, &P[j + 1], &st, nthreads);"),
+    "horner_not_filtered": ("rc = orc_spgemm(Pp[q], &S, &Bh, tau, &T, &st, nthreads);",
+                            "rc = orc_spgemm(Pp[q], &S, &Bh, 0.0, &T, &st, nthreads);"),
+    "transposed_left_operand": ("const double a = A->val[p];\n            for (int64_t t = B->row_ptr[k];",
+                                "const double a = A->val[p];\n            for (int64_t t = B->row_ptr[k]; (void)0,"),
+    "product_weight_dropped": ("w->acc[c] = fma(a, B->val[t], w->acc[c]);",
+                               "w->acc[c] = fma(1.0, B->val[t], w->acc[c]);"),
+    "dropped_norm_not_recorded": ("w->drop_colsum[c] += fabs(x);", "w->drop_colsum[c] += 0.0;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    if name == "transposed_left_operand":
+        # replace the product loop by one over the transpose of the left operand:
+        # row r takes column r of A (a transposed operand), found by a scan
+        old = ("        for (int64_t p = A->row_ptr[r]; p < A->row_ptr[r + 1]; ++p) {\n"
+               "            const int64_t k = A->col[p];\n"
+               "            const double a = A->val[p];\n")
+        new = ("        for (int64_t kk = 0; kk < A->n; ++kk)\n"
+               "        for (int64_t p = A->row_ptr[kk]; p < A->row_ptr[kk + 1]; ++p) {\n"
+               "            if (A->col[p] != r) continue;\n"
+               "            const int64_t k = kk;\n"
+               "            const double a = A->val[p];\n")
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(old, new))
+    lib = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                    "-o", str(lib), str(mut), "-lm"], check=True)
+    env = dict(os.environ, ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"

@@ -1,0 +1,428 @@
+"""Pins for the CPU oracle: closed forms, brute force, the paper's operation
+count and error bound, invariants and an independent second implementation.
+
+Each test ties the oracle to something other than itself, so that a plausible
+mistake in it (a dropped term, a wrong coefficient index, a transposed
+operand, a filter applied at the wrong stage) fails at least one of them.
+"""
+
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle as O
+from oracle.bound import filtering_bound, power_norms, rounding_slack
+from fps_inputs import generators as G
+
+
+def check_canonical(M):
+    rp, cl, vl = M.row_ptr, M.col, M.val
+    assert rp[0] == 0 and rp[-1] == cl.size == vl.size
+    assert np.all(np.diff(rp) >= 0)
+    for r in range(M.n):
+        c = cl[rp[r]:rp[r + 1]]
+        assert np.all(np.diff(c) > 0), f"row {r} not sorted/unique"
+    if cl.size:
+        assert cl.min() >= 0 and cl.max() < M.n
+    assert np.all(vl != 0.0)
+    assert np.all(np.isfinite(vl))
+
+
+def rel_fro(X, Y):
+    return float(np.linalg.norm(X - Y) / np.linalg.norm(Y))
+
+
+# ---------------------------------------------------------------------------
+# P8: schedule and number of sparse products (eqs. 5-6)
+# ---------------------------------------------------------------------------
+
+def test_schedule_counts_match_eq5():
+    for m in range(0, 41):
+        N = m + 1
+        for s in range(1, 13):
+            sc = O.schedule(m, s)
+            q, b = s, -(-N // s)
+            g = 1 if N - q * (b - 1) == 1 else 0
+            assert (sc["q"], sc["b"], sc["g"]) == (q, b, g)
+            if b >= 2:
+                assert sc["n_spgemm"] == q + b - 2 - g  # eq. 5
+            else:
+                assert sc["n_spgemm"] == max(m - 1, 0)
+
+
+def test_paper_q_choice_gives_eq5_minimum():
+    # with q = floor(sqrt(N-1)) (eq. 6) and N > 2 the count is mt(N) of eq. 5
+    for N in range(3, 60):
+        q = math.isqrt(N - 1)
+        b = -(-N // q)
+        g = 1 if N - q * (b - 1) == 1 else 0
+        assert O.schedule(N - 1, q)["n_spgemm"] == q + b - 2 - g
+
+
+@pytest.mark.parametrize("m,s", [(16, 4), (30, 6), (24, 5), (7, 1), (9, 3), (3, 8)])
+def test_stage_log_matches_schedule(m, s):
+    Z = G.random_banded(60, 2, 0.6, 1.0, seed=1)
+    _, st = O.filtered_ps(Z, G.exp_coeffs(m), m, s, 1e-12)
+    n_products = sum(1 for x in st if x["kind"] in (0, 3))
+    assert n_products == O.schedule(m, s)["n_spgemm"]
+
+
+# ---------------------------------------------------------------------------
+# P1: nilpotent shift matrices, exact closed form (bitwise)
+# ---------------------------------------------------------------------------
+
+def shift_expected(n, v, c, m, s, tau):
+    """F for Z = v*J (J the upper shift) with v a power of two.
+
+    Every product then has a single term, so no rounding happens.  The filtered
+    power P_j = v^j J^j (eq. 11) is dropped whole once |v^j| < tau (j >= 2),
+    and every later power with it.  Block i enters the Horner recurrence at
+    step b-1-i (eq. 14) with the value c_k v^j on the k-th superdiagonal; with
+    g = 1 the last coefficient rides with block b-2 as its j = q term.  Each
+    later step multiplies by P_q (or annihilates if P_q was dropped); steps
+    start..b-1 are filtered and drop the entry once its magnitude is below tau."""
+    sc = O.schedule(m, s)
+    q, b, g, start = sc["q"], sc["b"], sc["g"], sc["start"]
+    J = sc["J"]
+    alive = [True] * (J + 2)
+    for j in range(2, J + 1):
+        alive[j] = alive[j - 1] and abs(v ** j) >= tau and j < n
+    E = np.zeros((n, n))
+    for k in range(0, min(m, n - 1) + 1):
+        if c[k] == 0.0:
+            continue
+        if b >= 2 and g == 1 and k == m:
+            i, j = b - 2, q
+        else:
+            i, j = divmod(k, q)
+        if j >= 1 and not alive[j]:
+            continue
+        val, e = c[k] * v ** j, j
+        dropped = False
+        if b >= 2:
+            entry = b - 1 - i
+            for t in range(entry, b):
+                if t > entry:
+                    if not alive[q]:
+                        dropped = True
+                        break
+                    val, e = val * v ** q, e + q
+                if e >= n:
+                    dropped = True
+                    break
+                if t >= start and abs(val) < tau:
+                    dropped = True
+                    break
+        if not dropped:
+            assert val == c[k] * v ** k
+            E[np.arange(n - k), np.arange(k, n)] = val
+    return E
+
+
+@pytest.mark.parametrize("n,v,m,s,tau", [
+    (12, 1.0, 16, 4, 1e-14),    # b=5, g=1
+    (12, 0.5, 16, 4, 1e-9),     # values shrink through the steps
+    (20, 2.0, 9, 3, 1e-3),      # values grow: the first filtered step decides
+    (9, 1.0, 5, 8, 1e-2),       # b=1: nothing is filtered at all
+    (9, 1.0, 4, 3, 1e-2),       # b=2, g=1: the only Horner step is the shortcut
+    (9, 0.5, 6, 3, 5e-3),       # b=3, g=1
+    (30, 0.5, 24, 5, 1e-10),    # b=5, g=0 (config-3 shape)
+    (7, 1.0, 12, 1, 1e-4),      # s=1: plain filtered Horner
+    (40, 1.0, 30, 6, 1e-12),    # config-2 shape
+    (12, 0.0625, 16, 4, 1e-4),  # P_4 itself drops, so every Horner product vanishes
+    (16, 0.125, 14, 5, 1e-5),   # P_5 drops (q = 5): only the coefficient sums survive
+    (16, 0.25, 11, 3, 2e-3),    # P_3 survives narrowly, later values drop
+    (12, 0.0625, 5, 8, 1e-4),   # b=1: a dropped power is the only filter applied
+    (12, 0.0625, 4, 4, 1e-4),   # b=2, g=1: P_q drops before the unfiltered shortcut
+])
+def test_shift_matrix_closed_form(n, v, m, s, tau):
+    Z = G.shift_matrix(n, 1, v)
+    c = G.exp_coeffs(m)
+    F, _ = O.filtered_ps(Z, c, m, s, tau)
+    check_canonical(F)
+    np.testing.assert_array_equal(F.to_dense(), shift_expected(n, v, c, m, s, tau))
+
+
+def test_shift_matrix_transpose_is_lower():
+    # the transpose of the problem must give the transposed (lower) answer
+    n, m, s = 10, 8, 3
+    Z = G.shift_matrix(n, 1, 1.0)
+    Zt = G.from_dense(Z.to_dense().T)
+    c = G.exp_coeffs(m)
+    F, _ = O.filtered_ps(Z, c, m, s, 0.0)
+    Ft, _ = O.filtered_ps(Zt, c, m, s, 0.0)
+    np.testing.assert_array_equal(Ft.to_dense(), F.to_dense().T)
+    assert np.allclose(np.tril(F.to_dense(), -1), 0)
+
+
+# ---------------------------------------------------------------------------
+# P2: strictly upper triangular Z with m >= n-1 terminates exactly
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_nilpotent_series_terminates(seed):
+    n = 12
+    Z = G.random_sparse(n, 0.5, seed, scale=0.7, strictly_upper=True)
+    Zd = Z.to_dense()
+    m = 20  # >= n-1, so exp(Z) = P_m(Z) exactly
+    c = G.exp_coeffs(m)
+    F, _ = O.unfiltered_ps(Z, c, m, 4)
+    # exp of a nilpotent matrix by its finite Taylor sum in long double
+    E = np.eye(n, dtype=np.longdouble)
+    T = np.eye(n, dtype=np.longdouble)
+    for k in range(1, n):
+        T = T @ Zd.astype(np.longdouble) / k
+        E = E + T
+    assert float(np.max(np.abs(F.to_dense() - E.astype(np.float64)))) <= 1e-14 * float(np.max(np.abs(E)))
+
+
+# ---------------------------------------------------------------------------
+# P3: diagonal Z reduces to scalar series
+# ---------------------------------------------------------------------------
+
+def test_diagonal_exp_and_cos_closed_form():
+    rng = np.random.default_rng(7)
+    lam = rng.uniform(-1.0, 1.0, 50)
+    Z = G.diagonal(lam)
+    m = 22
+    F, _ = O.filtered_ps(Z, G.exp_coeffs(m), m, 5, 1e-300)
+    d = F.to_dense()
+    assert np.allclose(d, np.diag(np.diag(d)), atol=0)
+    # truncation |lam|^(m+1) e^|lam| / (m+1)! < 1e-22, so only rounding remains
+    np.testing.assert_allclose(np.diag(d), np.exp(lam), rtol=4e-16 * (m + 1), atol=0)
+    F, _ = O.filtered_ps(Z, G.cos_coeffs(m), m, 5, 1e-300)
+    np.testing.assert_allclose(np.diag(F.to_dense()), np.cos(lam), rtol=4e-16 * (m + 1), atol=1e-16)
+
+
+def test_diagonal_exact_rationals():
+    # lam = 1/2, 1/4, 1/8 and s = 1 (plain Horner): compare with the exact
+    # rational polynomial value; the computed value is within (m+1) ulps
+    lam = [0.5, 0.25, -0.125]
+    Z = G.diagonal(lam)
+    m = 10
+    c = G.exp_coeffs(m)
+    for s in (1, 3, 4, 11):
+        F, _ = O.unfiltered_ps(Z, c, m, s)
+        got = np.diag(F.to_dense())
+        for i, x in enumerate(lam):
+            exact = sum(Fraction(c[k]) * Fraction(x) ** k for k in range(m + 1))
+            assert abs(Fraction(float(got[i])) - exact) <= Fraction(2 * (m + 1)) * Fraction(2.0 ** -52) * abs(exact)
+
+
+# ---------------------------------------------------------------------------
+# P4: special cases
+# ---------------------------------------------------------------------------
+
+def test_zero_matrix_gives_c0_identity():
+    n = 5
+    Z = G.empty_matrix(n)
+    for m, s in [(0, 3), (5, 2), (16, 4), (30, 6)]:
+        c = G.exp_coeffs(m)
+        F, _ = O.filtered_ps(Z, c, m, s, 1e-12)
+        np.testing.assert_array_equal(F.to_dense(), np.eye(n))
+
+
+def test_zero_matrix_small_c0_filtered_only_if_a_filtered_step_runs():
+    n = 4
+    Z = G.empty_matrix(n)
+    c = np.array([1e-20, 1.0, 1.0, 1.0, 1.0])
+    # m=4, s=2: b=3, g=1, one filtered step (i=2) -> c_0 I dropped
+    F, _ = O.filtered_ps(Z, c, 4, 2, 1e-12)
+    assert F.nnz == 0
+    # m=4, s=8: b=1, nothing filtered -> c_0 I kept
+    F, _ = O.filtered_ps(Z, c, 4, 8, 1e-12)
+    np.testing.assert_array_equal(F.to_dense(), 1e-20 * np.eye(n))
+
+
+def test_scalar_n1_equals_polynomial():
+    Z = G.diagonal([0.75])
+    m = 14
+    c = G.exp_coeffs(m)
+    for s in range(1, 16):
+        F, _ = O.unfiltered_ps(Z, c, m, s)
+        assert abs(F.val[0] - sum(c[k] * 0.75 ** k for k in range(m + 1))) <= 1e-15
+
+
+def test_s1_is_plain_horner_count():
+    Z = G.random_banded(30, 2, 0.6, 1.0, seed=3)
+    m = 9
+    _, st = O.filtered_ps(Z, G.exp_coeffs(m), m, 1, 1e-14)
+    assert sum(1 for x in st if x["kind"] in (0, 3)) == m - 1
+
+
+# ---------------------------------------------------------------------------
+# P5 / P6: unfiltered PS against Horner (double) and long-double brute force
+# ---------------------------------------------------------------------------
+
+def test_config1_unfiltered_matches_dense_horner():
+    cfg = G.config1()
+    F, _ = O.unfiltered_ps(cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"])
+    Y = O.dense_horner(cfg["Z"].to_dense(), cfg["coeffs"])
+    assert rel_fro(F.to_dense(), Y) <= 1e-14
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_small_random_nonsymmetric_against_long_double(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(2, 40))
+    Z = G.random_sparse(n, 0.2, seed, scale=0.4)
+    m = int(rng.integers(3, 25))
+    s = int(rng.integers(1, 7))
+    c = G.exp_coeffs(m) if seed % 2 == 0 else G.random_series_coeffs(m, rng)
+    Yld = O.dense_horner_ld(Z.to_dense(), c)
+    Y = Yld.astype(np.float64)
+    F, _ = O.unfiltered_ps(Z, c, m, s)
+    assert rel_fro(F.to_dense(), Y) <= 1e-14
+    # and the result is not symmetric, so a transposed operand would show
+    if np.linalg.norm(Y - Y.T) > 1e-3 * np.linalg.norm(Y):
+        assert rel_fro(F.to_dense().T, Y) > 1e-6
+
+
+# ---------------------------------------------------------------------------
+# P7: the paper's a-posteriori filtering bound (eq. 23)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["c1", "lap2d_side20", "band_big_tau", "rand_small", "cos3d"])
+def test_filtering_error_within_eq23_bound(case):
+    if case == "c1":
+        cfg = G.config1()
+        Z, c, m, s, tau = cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"]
+    elif case == "lap2d_side20":
+        Z, c, m, s, tau = G.laplacian_2d(20, 2.0), G.exp_coeffs(30), 30, 6, 1e-8
+    elif case == "band_big_tau":
+        Z, c, m, s, tau = G.random_banded(300, 3, 0.6, 1.5, seed=11), G.exp_coeffs(20), 20, 4, 1e-6
+    elif case == "rand_small":
+        Z, c, m, s, tau = G.random_sparse(40, 0.1, 5, 0.5), G.exp_coeffs(18), 18, 3, 1e-5
+    else:
+        Z, c, m, s, tau = G.laplacian_3d_perturbed(6, seed=3), G.cos_coeffs(24), 24, 5, 1e-7
+    F, st = O.filtered_ps(Z, c, m, s, tau)
+    if Z.n <= 64:
+        P = O.dense_horner_ld(Z.to_dense(), c).astype(np.float64)
+    else:
+        P = O.dense_horner(Z.to_dense(), c)
+    err = O.norm1(F.to_dense() - P)
+    z = power_norms(Z, s * (-(-(m + 1) // s)))
+    bd = filtering_bound(c, m, s, st, z)
+    slack = rounding_slack(c, m, O.norm1(Z))
+    assert sum(x["n_dropped"] for x in st) > 0, "case must exercise the filter"
+    assert err > 0
+    assert err <= bd["bound"] * (1 + 1e-3) + slack, (err, bd["bound"], slack)
+
+
+# ---------------------------------------------------------------------------
+# P9: invariants
+# ---------------------------------------------------------------------------
+
+def test_invariants_and_structure_subset():
+    Z = G.laplacian_2d(30, 2.0)
+    m, s, tau = 30, 6, 1e-10
+    c = G.exp_coeffs(m)
+    F, st = O.filtered_ps(Z, c, m, s, tau)
+    F0, _ = O.unfiltered_ps(Z, c, m, s)
+    check_canonical(F)
+    check_canonical(F0)
+    for x in st:
+        if x["kind"] in (0, 3):  # filtered stages
+            assert x["dropped_max"] < tau
+            assert x["kept_min"] >= tau or x["nnz_kept"] == 0
+        else:  # coefficient sums drop exact zeros only
+            assert x["n_dropped"] == 0
+    assert np.all(np.abs(F.val) >= tau)
+    # filtering only removes structure (Section 4: PSSCF results are sparser)
+    s_f = set(zip(np.repeat(np.arange(F.n), np.diff(F.row_ptr)), F.col))
+    s_0 = set(zip(np.repeat(np.arange(F0.n), np.diff(F0.row_ptr)), F0.col))
+    assert s_f <= s_0
+    assert F.nnz < F0.nnz
+
+
+def test_tie_at_tau_is_kept():
+    # Z = diag(0.5): P_2 = 0.25 exactly; tau = 0.25 keeps it, tau = nextafter drops it
+    Z = G.diagonal([0.5])
+    A, _ = O.spgemm(Z, Z, None, 0.25)
+    assert A.nnz == 1 and A.val[0] == 0.25
+    B, _ = O.spgemm(Z, Z, None, np.nextafter(0.25, 1.0))
+    assert B.nnz == 0
+
+
+def test_exact_cancellation_dropped_even_without_filter():
+    Z = G.from_dense(np.array([[1.0, 1.0], [1.0, -1.0]]))
+    # Z^2 = 2 I: off-diagonals cancel exactly and must not be stored
+    P, st = O.spgemm(Z, Z, None, 0.0)
+    np.testing.assert_array_equal(P.to_dense(), 2 * np.eye(2))
+    assert st["n_zero"] == 2
+
+
+# ---------------------------------------------------------------------------
+# P10: regrouping invariance (eq. 2 is an exact regrouping)
+# ---------------------------------------------------------------------------
+
+def test_unfiltered_result_independent_of_s():
+    Z = G.random_banded(200, 3, 0.6, 1.2, seed=9)
+    m = 20
+    c = G.exp_coeffs(m)
+    ref, _ = O.unfiltered_ps(Z, c, m, 1)
+    R = ref.to_dense()
+    for s in range(2, 10):
+        F, _ = O.unfiltered_ps(Z, c, m, s)
+        assert rel_fro(F.to_dense(), R) <= 1e-14
+
+
+# ---------------------------------------------------------------------------
+# P12: an independent second implementation (scipy sparse products)
+# ---------------------------------------------------------------------------
+
+def _scipy_filtered_ps(Z, c, m, s, tau):
+    n = Z.n
+    A = Z.to_scipy().tocsr()
+    N = m + 1
+    q, b = s, -(-N // s)
+    g = N - q * (b - 1) == 1
+
+    def filt(M):
+        M = M.tocsr()
+        M.data[np.abs(M.data) < tau] = 0.0
+        M.eliminate_zeros()
+        return M
+
+    J = q if b >= 2 else m
+    P = [sp.identity(n, format="csr"), A]
+    for _ in range(2, J + 1):
+        P.append(filt(A @ P[-1]))
+
+    def block(i, jmax):
+        out = sp.csr_matrix((n, n))
+        for j in range(0, jmax + 1):
+            if i * q + j <= m:
+                out = out + c[i * q + j] * P[j]
+        return out
+
+    if b == 1:
+        return block(0, q - 1)
+    if g:
+        S = block(b - 2, q)
+        start = 2
+    else:
+        S = block(b - 1, q - 1)
+        start = 1
+    for i in range(start, b):
+        S = filt(block(b - 1 - i, q - 1) + P[q] @ S)
+    return S
+
+
+@pytest.mark.parametrize("case", ["c1", "band", "lap2d", "rand"])
+def test_against_scipy_implementation(case):
+    if case == "c1":
+        cfg = G.config1()
+        Z, c, m, s, tau = cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"]
+    elif case == "band":
+        Z, c, m, s, tau = G.random_banded(500, 4, 0.6, 1.7, seed=2), G.exp_coeffs(20), 20, 5, 1e-12
+    elif case == "lap2d":
+        Z, c, m, s, tau = G.laplacian_2d(40, 2.0), G.cos_coeffs(30), 30, 6, 1e-12
+    else:
+        Z, c, m, s, tau = G.random_sparse(80, 0.05, 4, 0.8), G.exp_coeffs(15), 15, 4, 0.0
+    F, _ = O.filtered_ps(Z, c, m, s, tau)
+    R = _scipy_filtered_ps(Z, c, m, s, tau).toarray()
+    assert rel_fro(F.to_dense(), R) <= (1e-14 if tau == 0 else 1e-10)
