@@ -1,0 +1,147 @@
+#!/usr/bin/env python3
+"""Throughput of the filtered Paterson-Stockmeyer hot path on one MI355X.
+
+One step = one full evaluation F(Z) = sum_k c_k Z^k by filtered PS (all
+powers, coefficient blocks and Horner steps) of the 2D 5-point Laplacian on a
+200 x 200 grid (n = 40000, ||Z||_1 = 2), exp series m = 30, s = 6,
+tau = 1e-12, with Z resident in HBM.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload lap2d|lap1d]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from fps_inputs import generators as G
+
+    if name == "lap2d":
+        return G.config2()
+    if name == "lap1d":
+        return G.config1()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(cfg, budget_s: float):
+    """The CPU oracle timed on this host's cores on whole evaluations."""
+    import oracle as O
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+    Z, c, m, s, tau = cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"]
+    O.filtered_ps(Z, c, m, s, tau, nthreads=threads)  # warm-up
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        O.filtered_ps(Z, c, m, s, tau, nthreads=threads)
+        k += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or k >= 50:
+            break
+    return {"value": k / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} full evaluations of the same workload after 1 warm-up ({el:.1f} s), "
+                      f"{threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="lap2d")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle timing (0 skips)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(how the evaluation would shard is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps > 64:
+        log("note: kernel timings average the last 64 evaluations")
+
+    import torch
+    from paper_2208_05683_amd import api, binding as B
+
+    cfg = workload(args.workload)
+    Z = cfg["Z"]
+    log(f"workload {cfg['name']}: n={Z.n} nnz={Z.nnz}")
+    Zd = api.to_device(Z.row_ptr, Z.col, Z.val)
+    stream = torch.cuda.current_stream()
+    plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"], flags=B.FPS_FLAG_TIMING)
+
+    for i in range(args.warmup):
+        plan.eval(stream)
+    torch.cuda.synchronize()
+    log(f"warm-up done ({args.warmup} evals), F nnz = {plan.nnz()}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.eval(stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = plan.stats()
+    if st["resizes"]:
+        log(f"warning: {st['resizes']} evaluations re-sized buffers")
+    ms_per_step = 1e3 * el / args.steps
+    evals_per_s = args.steps / el
+    log(f"timed {args.steps} evals: {ms_per_step:.3f} ms/eval")
+
+    # roofline of the dominant kernel: the shared-memory numeric kernel of the
+    # product stages (HIP events on the plan's stream around every launch)
+    launches = st["numeric_launches"]
+    kern_ms = st["numeric_ms"]
+    bytes_eval = st["bytes_algorithmic"]
+    achieved = (bytes_eval / (kern_ms * 1e-3)) / 1e9 if kern_ms > 0 else 0.0
+    products = st["products"]
+    prod_per_s = products / (ms_per_step * 1e-3)
+
+    res = {
+        "metric": "series evals/s + SpGEMM HBM GB/s vs plain filtered PS; p50/p99 latency at QPS",
+        "value": evals_per_s,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "n": Z.n, "nnz_Z": Z.nnz, "m": cfg["m"], "s": cfg["s"],
+                   "tau": cfg["tau"], "series": "exp", "nnz_F": st["nnz_out"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_numeric_lds (product stages)",
+                     "launches_per_step": launches,
+                     "avg_launch_ms": kern_ms / launches if launches else None,
+                     "algorithmic_bytes_per_step": bytes_eval},
+        "products_per_s": prod_per_s,
+        "products_per_step": products,
+        "products_skipped_per_step": st["products_skipped"],
+        "stage_ms": {f"{['power', 'block', 'gstep', 'horner'][k]}{i}": round(ms, 4)
+                     for k, i, ms in zip(st["kind"], st["index"], st["stage_ms"])},
+    }
+    if args.cpu_budget > 0:
+        log("timing the CPU oracle ...")
+        res["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
+    plan.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

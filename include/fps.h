@@ -1,0 +1,200 @@
+/*
+ * fps.h -- C ABI of libfps, the MI355X (gfx950) implementation of the
+ * filtered Paterson-Stockmeyer (PS) evaluation of a matrix power series
+ *
+ *     F(Z) = sum_{k=0..m} c_k Z^k          (paper eqs. 1 and 8)
+ *
+ * on a sparse n x n matrix Z, following "A filtering technique for the matrix
+ * power series being near-sparse" (arXiv 2208.05683), Section 3 and
+ * Algorithm 2, with a fixed entry threshold tau (the simple filter of
+ * Section 3.1.1) in place of the adaptive filter of Algorithm 1.
+ *
+ * Computation (all on the GPU, all in IEEE binary64):
+ *   N = m+1, q = s, b = ceil(N/q), g = [N - q(b-1) == 1]          (eq. 6)
+ *   P_1 = Z, P_{j+1} = D_tau(Z (x) P_j)   for j < q  (or < m if b == 1)  (eq. 11)
+ *   Bhat_i = sum_{j<q} c_{iq+j} P_j  with P_0 = I, not filtered        (eq. 13)
+ *   S_0 = Bhat_{b-1};  if g == 1: S_1 = Bhat_{b-2} + c_{(b-1)q} P_q,
+ *                                 with no product and no filter         (eq. 14)
+ *   S_i = D_tau(Bhat_{b-1-i} + P_q (x) S_{i-1})                         (eq. 14)
+ *   F = S_{b-1}
+ * where D_tau drops x iff x == 0 or |x| < tau, and (x) is the row-wise
+ * (Gustavson) product accumulating A_rk * B_k,: over ascending k with one
+ * fused multiply-add per term from +0; Bhat and the g = 1 sum accumulate
+ * c_j P_j over ascending j with fused multiply-adds from +0 (terms with
+ * c_j == 0 skipped); a Horner step adds the block with one addition,
+ * x = bhat + product.  With these conventions results are reproducible
+ * bit for bit, independent of launch configuration.
+ *
+ * Conventions for every entry point:
+ *   - CSR views hold DEVICE pointers: row_ptr int64[n+1] with row_ptr[0] = 0,
+ *     col int32[nnz] strictly increasing within each row, val double[nnz]
+ *     finite.  Views are borrowed: the library never frees them.
+ *   - Streams are hipStream_t values (NULL = the default stream).  Work is
+ *     ordered on the stream passed in.
+ *   - Functions return an fps_status; nothing throws across the ABI and
+ *     nothing aborts.  fps_last_error() gives a thread-local message for the
+ *     last failure on the calling thread.  Asynchronous device faults are
+ *     reported by the next call that synchronises.
+ *   - A plan or matrix handle must not be used from two host threads at once.
+ */
+#ifndef FPS_H
+#define FPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FPS_ABI_VERSION 1
+
+typedef int32_t fps_status;
+#define FPS_OK 0
+#define FPS_ERR_INVALID_ARG 1   /* bad scalar argument or null pointer */
+#define FPS_ERR_BAD_CSR 2       /* input matrix fails validation */
+#define FPS_ERR_OUT_OF_MEMORY 3 /* device allocation failed */
+#define FPS_ERR_HIP 4           /* a HIP runtime call or kernel failed */
+#define FPS_ERR_CAPACITY 5      /* a size limit of this build was exceeded */
+#define FPS_ERR_NOT_READY 6     /* result requested before any evaluation */
+
+/* largest PS block size s accepted (the g = 1 sum has s+1 terms) */
+#define FPS_MAX_S 31
+/* number of per-stage records kept in fps_stats */
+#define FPS_MAX_STAGES 96
+
+/* plan flags */
+#define FPS_FLAG_NO_SKIP 0x1ull      /* disable the exact bound-based row skip */
+#define FPS_FLAG_FORCE_GLOBAL 0x2ull /* route every row through the global-memory kernel */
+#define FPS_FLAG_TIMING 0x4ull       /* record HIP events around every shared-memory numeric launch */
+#define FPS_FLAG_NO_VALIDATE 0x8ull  /* skip the device-side CSR check of Z at plan time */
+#define FPS_FLAG_SYNC_SIZES 0x10ull  /* size every stage from a host read (no learned capacities) */
+
+typedef struct ihipStream_t *fps_stream; /* same type as hipStream_t */
+
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int64_t *row_ptr; /* device, n+1 */
+    const int32_t *col;     /* device, nnz */
+    const double *val;      /* device, nnz */
+} fps_csr_view;
+
+typedef struct fps_plan_s *fps_plan;
+typedef struct fps_matrix_s *fps_matrix;
+
+/* stage kinds in fps_stats */
+#define FPS_STAGE_POWER 0  /* P_{index} = D_tau(Z (x) P_{index-1})            (eq. 11) */
+#define FPS_STAGE_BLOCK 1  /* Bhat_{index}, coefficient sum                     (eq. 13) */
+#define FPS_STAGE_GSTEP 2  /* S_1 = Bhat_{b-2} + c_{(b-1)q} P_q, no filter       (eq. 14) */
+#define FPS_STAGE_HORNER 3 /* S_{index} = D_tau(Bhat + P_q (x) S_{index-1})    (eq. 14) */
+
+typedef struct {
+    int32_t N, q, b, g, J, start; /* schedule (eq. 6; J = highest power formed) */
+    int32_t n_spgemm;             /* sparse products per evaluation: q+b-2-g when b >= 2 (eq. 5) */
+    int32_t n_stages;             /* stage records below */
+    int64_t evals;                /* evaluations run on this plan */
+    int64_t nnz_out;              /* stored entries of F after the last evaluation */
+    int64_t products;             /* multiply-adds performed in the last evaluation */
+    int64_t products_skipped;     /* multiply-adds avoided by the exact bound test */
+    int64_t rows_skipped;         /* output rows proven empty by the bound test */
+    int64_t rows_global;          /* rows handled by the global-memory kernel */
+    int64_t resizes;              /* evaluations that had to re-size a buffer */
+    double bytes_algorithmic;     /* sum over products of 12 (nnz A + nnz B + nnz E + nnz kept) + 8 (n+1) * operands */
+    double numeric_ms;            /* FPS_FLAG_TIMING: numeric-kernel time of the product stages per
+                                     evaluation, averaged over the last (up to 64) evaluations */
+    int32_t numeric_launches;     /* FPS_FLAG_TIMING: product-stage numeric launches per evaluation */
+    int32_t kind[FPS_MAX_STAGES];
+    int32_t index[FPS_MAX_STAGES];
+    int64_t stage_products[FPS_MAX_STAGES];
+    int64_t stage_nnz[FPS_MAX_STAGES]; /* kept entries of the stage output */
+    double stage_ms[FPS_MAX_STAGES];   /* FPS_FLAG_TIMING: numeric-kernel time per stage, same average */
+} fps_stats;
+
+/* ---------------------------------------------------------------------- */
+/* Version and errors                                                       */
+/* ---------------------------------------------------------------------- */
+
+int32_t fps_abi_version(void);
+const char *fps_status_string(fps_status s);
+/* Thread-local text of the last error on this thread ("" if none).  The
+ * pointer stays valid until the next fps_* call on the same thread. */
+const char *fps_last_error(void);
+
+/* Schedule of eq. 6 with q = s given (host only, no device work).  Any
+ * output pointer may be NULL.  INVALID_ARG if m < 0 or s < 1. */
+fps_status fps_schedule(int32_t m, int32_t s, int32_t *N, int32_t *q, int32_t *b, int32_t *g, int32_t *J,
+                        int32_t *start, int32_t *n_spgemm);
+
+/* ---------------------------------------------------------------------- */
+/* Plan / evaluate (Algorithm 2 with a fixed tau)                           */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Create a plan for F(Z) with coefficients coeffs[0..m] (HOST array, copied),
+ * PS block size s (1 <= s <= FPS_MAX_S) and filter threshold tau (finite,
+ * >= 0; tau = 0 drops exact zeros only, i.e. the unfiltered PS scheme).
+ * Z is borrowed: its device arrays must stay valid and unchanged while any
+ * fps_eval of this plan is in flight.  Unless FPS_FLAG_NO_VALIDATE is set,
+ * Z is checked on the device (synchronising `stream`); failure gives
+ * FPS_ERR_BAD_CSR.  The plan owns all device workspace.
+ */
+fps_status fps_plan_create(fps_plan *out, const fps_csr_view *Z, const double *coeffs, int32_t m, int32_t s,
+                           double tau, uint64_t flags, fps_stream stream);
+
+/*
+ * Evaluate F(Z) on `stream`.  Once the plan has learned its buffer sizes
+ * (after its first evaluation, or always with FPS_FLAG_SYNC_SIZES) this only
+ * enqueues work; otherwise it synchronises `stream` once per stage to size
+ * the outputs.  If Z's values changed so that a learned size no longer fits,
+ * the kernels flag it and fps_result_nnz re-runs the evaluation with sizing.
+ */
+fps_status fps_eval(fps_plan p, fps_stream stream);
+
+/* Number of stored entries of F (synchronises the plan's last stream).
+ * NOT_READY before the first fps_eval. */
+fps_status fps_result_nnz(fps_plan p, int64_t *nnz);
+
+/* Copy F as canonical CSR into caller-owned DEVICE buffers: row_ptr int64[n+1],
+ * col int32[nnz], val double[nnz] with nnz from fps_result_nnz.  Enqueued on
+ * `stream` after the evaluation. */
+fps_status fps_result_copy(fps_plan p, int64_t *row_ptr, int32_t *col, double *val, fps_stream stream);
+
+/* Statistics of the last evaluation (synchronises). */
+fps_status fps_get_stats(fps_plan p, fps_stats *st);
+
+/* Release the plan and its workspace (synchronises its stream first). */
+void fps_plan_destroy(fps_plan p);
+
+/* ---------------------------------------------------------------------- */
+/* Single stages (the building blocks of fps_eval, for tests and tools)     */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * C = D_tau(E + A (x) B): one filtered sparse product with an optional extra
+ * matrix E added to the product before the drop test (eq. 11 with E = NULL,
+ * one step of eq. 14 with E = Bhat).  A, B, E are n x n canonical CSR (E may
+ * be NULL).  The result is a library-owned canonical CSR matrix.
+ * Synchronises `stream` (to size the output).
+ */
+fps_status fps_spgemm(fps_matrix *out, const fps_csr_view *A, const fps_csr_view *B, const fps_csr_view *E,
+                      double tau, fps_stream stream);
+
+/*
+ * C = sum_t coefs[t] * M_t accumulated in the order t = 0..nterms-1 (eq. 13);
+ * exact zeros are dropped, nothing else.  coefs is a HOST array; terms[t] is a
+ * canonical n x n CSR view, or the identity when terms[t].row_ptr == NULL.
+ * 1 <= nterms <= FPS_MAX_S + 1.  Synchronises `stream`.
+ */
+fps_status fps_axpy(fps_matrix *out, int64_t n, int32_t nterms, const double *coefs, const fps_csr_view *terms,
+                    fps_stream stream);
+
+fps_status fps_matrix_nnz(fps_matrix m, int64_t *nnz);
+/* Copy a library matrix into caller-owned DEVICE buffers (see fps_result_copy). */
+fps_status fps_matrix_copy(fps_matrix m, int64_t *row_ptr, int32_t *col, double *val, fps_stream stream);
+void fps_matrix_destroy(fps_matrix m);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPS_H */

@@ -1,0 +1,95 @@
+"""Torch-facing convenience layer over the C ABI (argument marshalling only).
+
+    Zd = api.to_device(row_ptr, col, val)          # device tensors
+    plan = api.Plan(Zd, coeffs, m=30, s=6, tau=1e-12)
+    plan.eval()
+    row_ptr, col, val = plan.result()              # canonical CSR of F on the device
+"""
+
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def to_device(row_ptr, col, val, device="cuda"):
+    """Host arrays (numpy or torch) of a canonical CSR -> contiguous device tensors."""
+    rp = torch.as_tensor(np.asarray(row_ptr, dtype=np.int64)).to(device)
+    cl = torch.as_tensor(np.asarray(col, dtype=np.int32)).to(device)
+    vl = torch.as_tensor(np.asarray(val, dtype=np.float64)).to(device)
+    return rp.contiguous(), cl.contiguous(), vl.contiguous()
+
+
+def _alloc_csr(n, nnz, device):
+    return (torch.empty(n + 1, dtype=torch.int64, device=device),
+            torch.empty(nnz, dtype=torch.int32, device=device),
+            torch.empty(nnz, dtype=torch.float64, device=device))
+
+
+class Plan:
+    """A plan for F(Z) = sum_k c_k Z^k by filtered PS (fps_plan_create)."""
+
+    def __init__(self, Z, coeffs, m: int, s: int, tau: float, flags: int = 0, stream=None):
+        self.Z = tuple(Z)  # keep the borrowed device arrays alive
+        self.n = self.Z[0].numel() - 1
+        self.device = self.Z[0].device
+        self.view = B.csr_view(*self.Z)
+        self.handle = B.fps_plan_create(self.view, list(coeffs), m, s, tau, flags, stream)
+
+    def eval(self, stream=None):
+        B.fps_eval(self.handle, stream)
+
+    def nnz(self) -> int:
+        return B.fps_result_nnz(self.handle)
+
+    def result(self, stream=None):
+        nnz = self.nnz()
+        out = _alloc_csr(self.n, nnz, self.device)
+        B.fps_result_copy(self.handle, *out, stream=stream)
+        torch.cuda.current_stream(self.device).synchronize() if stream is None else stream.synchronize()
+        return out
+
+    def stats(self) -> dict:
+        return B.fps_get_stats(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            B.fps_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _take_matrix(h, n, device):
+    try:
+        nnz = B.fps_matrix_nnz(h)
+        out = _alloc_csr(n, nnz, device)
+        B.fps_matrix_copy(h, *out)
+        torch.cuda.synchronize(device)
+        return out
+    finally:
+        B.fps_matrix_destroy(h)
+
+
+def spgemm(A, Bm, E=None, tau: float = 0.0):
+    """D_tau(E + A (x) B) for canonical device CSR triples."""
+    n = A[0].numel() - 1
+    h = B.fps_spgemm(B.csr_view(*A), B.csr_view(*Bm), B.csr_view(*E) if E is not None else None, tau)
+    return _take_matrix(h, n, A[0].device)
+
+
+def axpy(n: int, coefs, terms, device="cuda"):
+    """sum_t coefs[t] * terms[t] (None = identity) for canonical device CSR triples."""
+    views = [None if t is None else B.csr_view(*t) for t in terms]
+    h = B.fps_axpy(n, coefs, views)
+    return _take_matrix(h, n, device)
+
+
+def schedule(m: int, s: int) -> dict:
+    return B.fps_schedule(m, s)

@@ -1,0 +1,230 @@
+"""ctypes binding of libfps (include/fps.h), names as in the C ABI.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libfps.so.  PyTorch supplies device memory (CUDA/HIP tensors) and
+stream handles.  If the library is not built, importing this module raises
+ImportError: there is no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfps.so")
+HEADER = os.path.join(os.path.dirname(PKG), "include", "fps.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2208_05683_amd.build` "
+        "(hipcc, gfx950); there is no non-HIP implementation")
+
+_lib = C.CDLL(LIB_PATH)
+
+
+def _header_constants():
+    out = {}
+    with open(HEADER) as f:
+        for line in f:
+            m = re.match(r"#define\s+(FPS_\w+)\s+(0x[0-9a-fA-F]+|\d+)(ull)?\b", line)
+            if m:
+                out[m.group(1)] = int(m.group(2), 0)
+    return out
+
+
+_consts = _header_constants()
+globals().update(_consts)
+
+FPS_MAX_STAGES = _consts["FPS_MAX_STAGES"]
+
+
+class fps_csr_view(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64),
+        ("nnz", C.c_int64),
+        ("row_ptr", C.c_void_p),
+        ("col", C.c_void_p),
+        ("val", C.c_void_p),
+    ]
+
+
+class fps_stats(C.Structure):
+    _fields_ = [
+        ("N", C.c_int32), ("q", C.c_int32), ("b", C.c_int32), ("g", C.c_int32), ("J", C.c_int32),
+        ("start", C.c_int32), ("n_spgemm", C.c_int32), ("n_stages", C.c_int32),
+        ("evals", C.c_int64), ("nnz_out", C.c_int64), ("products", C.c_int64),
+        ("products_skipped", C.c_int64), ("rows_skipped", C.c_int64), ("rows_global", C.c_int64),
+        ("resizes", C.c_int64), ("bytes_algorithmic", C.c_double), ("numeric_ms", C.c_double),
+        ("numeric_launches", C.c_int32),
+        ("kind", C.c_int32 * FPS_MAX_STAGES), ("index", C.c_int32 * FPS_MAX_STAGES),
+        ("stage_products", C.c_int64 * FPS_MAX_STAGES), ("stage_nnz", C.c_int64 * FPS_MAX_STAGES),
+        ("stage_ms", C.c_double * FPS_MAX_STAGES),
+    ]
+
+
+_P = C.POINTER
+_vp = C.c_void_p
+_SIGS = {
+    "fps_abi_version": (C.c_int32, []),
+    "fps_status_string": (C.c_char_p, [C.c_int32]),
+    "fps_last_error": (C.c_char_p, []),
+    "fps_schedule": (C.c_int32, [C.c_int32, C.c_int32] + [_P(C.c_int32)] * 7),
+    "fps_plan_create": (C.c_int32, [_P(_vp), _P(fps_csr_view), _P(C.c_double), C.c_int32, C.c_int32,
+                                    C.c_double, C.c_uint64, _vp]),
+    "fps_eval": (C.c_int32, [_vp, _vp]),
+    "fps_result_nnz": (C.c_int32, [_vp, _P(C.c_int64)]),
+    "fps_result_copy": (C.c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "fps_get_stats": (C.c_int32, [_vp, _P(fps_stats)]),
+    "fps_plan_destroy": (None, [_vp]),
+    "fps_spgemm": (C.c_int32, [_P(_vp), _P(fps_csr_view), _P(fps_csr_view), _P(fps_csr_view), C.c_double, _vp]),
+    "fps_axpy": (C.c_int32, [_P(_vp), C.c_int64, C.c_int32, _P(C.c_double), _P(fps_csr_view), _vp]),
+    "fps_matrix_nnz": (C.c_int32, [_vp, _P(C.c_int64)]),
+    "fps_matrix_copy": (C.c_int32, [_vp, _vp, _vp, _vp, _vp]),
+    "fps_matrix_destroy": (None, [_vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class FpsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.fps_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_lib.fps_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise FpsError(st, where)
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def csr_view(row_ptr, col, val) -> fps_csr_view:
+    """fps_csr_view of device tensors (int64 row_ptr, int32 col, float64 val)."""
+    import torch
+
+    for t, dt, nm in ((row_ptr, torch.int64, "row_ptr"), (col, torch.int32, "col"), (val, torch.float64, "val")):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise TypeError(f"{nm} must be a contiguous {dt} device tensor")
+    v = fps_csr_view()
+    v.n = row_ptr.numel() - 1
+    v.nnz = col.numel()
+    v.row_ptr = row_ptr.data_ptr()
+    v.col = col.data_ptr() if col.numel() else None
+    v.val = val.data_ptr() if val.numel() else None
+    return v
+
+
+# ---- functions with the C ABI's names ------------------------------------------
+
+def fps_abi_version() -> int:
+    return _lib.fps_abi_version()
+
+
+def fps_schedule(m: int, s: int) -> dict:
+    vals = [C.c_int32() for _ in range(7)]
+    _check(_lib.fps_schedule(m, s, *[C.byref(v) for v in vals]), "fps_schedule")
+    return dict(zip(["N", "q", "b", "g", "J", "start", "n_spgemm"], [v.value for v in vals]))
+
+
+def fps_plan_create(Z: fps_csr_view, coeffs, m: int, s: int, tau: float, flags: int = 0, stream=None):
+    arr = (C.c_double * (m + 1))(*[float(x) for x in coeffs[: m + 1]])
+    h = C.c_void_p()
+    _check(_lib.fps_plan_create(C.byref(h), C.byref(Z), arr, m, s, float(tau), C.c_uint64(flags),
+                                _stream_handle(stream)), "fps_plan_create")
+    return h
+
+
+def fps_eval(plan, stream=None):
+    _check(_lib.fps_eval(plan, _stream_handle(stream)), "fps_eval")
+
+
+def fps_result_nnz(plan) -> int:
+    v = C.c_int64()
+    _check(_lib.fps_result_nnz(plan, C.byref(v)), "fps_result_nnz")
+    return v.value
+
+
+def fps_result_copy(plan, row_ptr, col, val, stream=None):
+    _check(_lib.fps_result_copy(plan, row_ptr.data_ptr(), col.data_ptr() if col.numel() else None,
+                                val.data_ptr() if val.numel() else None, _stream_handle(stream)),
+           "fps_result_copy")
+
+
+def fps_get_stats(plan) -> dict:
+    st = fps_stats()
+    _check(_lib.fps_get_stats(plan, C.byref(st)), "fps_get_stats")
+    d = {}
+    for name, _ in fps_stats._fields_:
+        v = getattr(st, name)
+        if isinstance(v, C.Array):
+            v = list(v)[: st.n_stages]
+        d[name] = v
+    return d
+
+
+def fps_plan_destroy(plan):
+    _lib.fps_plan_destroy(plan)
+
+
+def fps_spgemm(A: fps_csr_view, B: fps_csr_view, E: fps_csr_view | None, tau: float, stream=None):
+    h = C.c_void_p()
+    _check(_lib.fps_spgemm(C.byref(h), C.byref(A), C.byref(B), C.byref(E) if E is not None else None, float(tau),
+                           _stream_handle(stream)), "fps_spgemm")
+    return h
+
+
+def fps_axpy(n: int, coefs, terms, stream=None):
+    """terms: list of fps_csr_view or None (identity)."""
+    k = len(coefs)
+    arr = (C.c_double * k)(*[float(x) for x in coefs])
+    views = (fps_csr_view * k)()
+    for i, t in enumerate(terms):
+        if t is None:
+            views[i].n = n
+            views[i].nnz = 0
+            views[i].row_ptr = None
+        else:
+            views[i] = t
+    h = C.c_void_p()
+    _check(_lib.fps_axpy(C.byref(h), n, k, arr, views, _stream_handle(stream)), "fps_axpy")
+    return h
+
+
+def fps_matrix_nnz(m) -> int:
+    v = C.c_int64()
+    _check(_lib.fps_matrix_nnz(m, C.byref(v)), "fps_matrix_nnz")
+    return v.value
+
+
+def fps_matrix_copy(m, row_ptr, col, val, stream=None):
+    _check(_lib.fps_matrix_copy(m, row_ptr.data_ptr(), col.data_ptr() if col.numel() else None,
+                                val.data_ptr() if val.numel() else None, _stream_handle(stream)),
+           "fps_matrix_copy")
+
+
+def fps_matrix_destroy(m):
+    _lib.fps_matrix_destroy(m)
+
+
+def exported_symbols():
+    """Names of the functions declared in include/fps.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fps_\w+)\s*\(", text)))
+
+
+def library():
+    return _lib

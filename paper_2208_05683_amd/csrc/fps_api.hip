@@ -1,0 +1,859 @@
+// Host side of libfps: plans, the stage schedule of Algorithm 2 (fixed tau),
+// device buffers, and the C ABI declared in include/fps.h.
+#include "fps.h"
+#include "fps_device.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace fps;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fps_status set_error(fps_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                                          \
+    do {                                                                                                       \
+        hipError_t e_ = (expr);                                                                                \
+        if (e_ != hipSuccess) {                                                                                \
+            (void)hipGetLastError();                                                                           \
+            return set_error(e_ == hipErrorOutOfMemory ? FPS_ERR_OUT_OF_MEMORY : FPS_ERR_HIP, "%s: %s (%s:%d)", \
+                             #expr, hipGetErrorString(e_), __FILE__, __LINE__);                                \
+        }                                                                                                      \
+    } while (0)
+
+#define FPS_TRY(expr)                      \
+    do {                                   \
+        fps_status s_ = (expr);            \
+        if (s_ != FPS_OK) return s_;       \
+    } while (0)
+
+// Grow-only device allocation.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    fps_status ensure(size_t want)
+    {
+        if (want <= bytes && p) return FPS_OK;
+        release();
+        const size_t b = std::max<size_t>(want, 256);
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return set_error(FPS_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
+        }
+        bytes = b;
+        return FPS_OK;
+    }
+    template <typename T>
+    T* as() const
+    {
+        return static_cast<T*>(p);
+    }
+};
+
+// A stage output in slack layout (see OutView).
+struct SlackMatrix {
+    int64_t n = 0;
+    int64_t cap = 0;
+    DevBuf off, end, span, amax, col, val;
+    fps_status ensure_rows(int64_t nn)
+    {
+        n = nn;
+        FPS_TRY(off.ensure(sizeof(int64_t) * (size_t)(nn + 1)));
+        FPS_TRY(end.ensure(sizeof(int64_t) * (size_t)std::max<int64_t>(nn, 1)));
+        FPS_TRY(span.ensure(sizeof(int2) * (size_t)std::max<int64_t>(nn, 1)));
+        FPS_TRY(amax.ensure(sizeof(double) * (size_t)std::max<int64_t>(nn, 1)));
+        return FPS_OK;
+    }
+    fps_status ensure_cap(int64_t c)
+    {
+        if (c <= cap && col.p) return FPS_OK;
+        const int64_t want = std::max<int64_t>(c + c / 8, 64);
+        FPS_TRY(col.ensure(sizeof(int32_t) * (size_t)want));
+        FPS_TRY(val.ensure(sizeof(double) * (size_t)want));
+        cap = want;
+        return FPS_OK;
+    }
+    MatView view() const
+    {
+        return MatView{off.as<int64_t>(), end.as<int64_t>(), col.as<int32_t>(), val.as<double>(), span.as<int2>(),
+                       amax.as<double>()};
+    }
+    OutView out() const
+    {
+        return OutView{off.as<int64_t>(), end.as<int64_t>(), col.as<int32_t>(), val.as<double>(), span.as<int2>(),
+                       amax.as<double>(), cap};
+    }
+};
+
+// A canonical CSR owned by the library.
+struct CanonMatrix {
+    int64_t n = 0;
+    int64_t cap = 0;
+    DevBuf rp, col, val, len_tmp, scan_tmp;
+};
+
+// Per-row workspace shared by the stages of one engine.
+struct Workspace {
+    int64_t n = 0;
+    DevBuf W, lo, ub, fb, scan_tmp, zspan, zamax, gscratch, counters, part;
+    int64_t g_words = 0, g_cap = 0, g_stride = 0;
+    int64_t part_stride = 0;
+    int32_t g_slots = 0;
+    int max_stages = 0;
+
+    fps_status init(int64_t nn, int stages)
+    {
+        n = nn;
+        max_stages = stages;
+        const size_t rows = (size_t)std::max<int64_t>(nn, 1);
+        FPS_TRY(W.ensure(sizeof(int32_t) * rows));
+        FPS_TRY(lo.ensure(sizeof(int32_t) * rows));
+        FPS_TRY(ub.ensure(sizeof(int64_t) * rows));
+        FPS_TRY(fb.ensure(sizeof(int64_t) * rows));
+        FPS_TRY(scan_tmp.ensure(sizeof(int64_t) * scan_tmp_elems(nn)));
+        FPS_TRY(zspan.ensure(sizeof(int2) * rows));
+        FPS_TRY(zamax.ensure(sizeof(double) * rows));
+        FPS_TRY(counters.ensure(sizeof(StageCounters) * (size_t)stages));
+        part_stride = std::max({analyze_blocks(kModeProduct, nn), analyze_blocks(kModeSum, nn), numeric_blocks(nn)}) + 1;
+        FPS_TRY(part.ensure(sizeof(unsigned long long) * (size_t)(kPartCount * part_stride * stages)));
+        // global-memory kernel: per slot byte map + bitmap + prefix + accumulator for a full row
+        g_words = (nn + 31) / 32;
+        g_cap = std::max<int64_t>(nn, 1);
+        const int64_t per_slot_u32 = (g_words * 8 + 2 * g_words + 3 * g_cap + 63) / 64 * 64;
+        g_stride = per_slot_u32;
+        const int64_t budget = int64_t(1) << 31;  // 2 GiB of workspace at most
+        int64_t slots = std::min<int64_t>(256, std::max<int64_t>(4, budget / (4 * per_slot_u32)));
+        slots = std::min<int64_t>(slots, std::max<int64_t>(4, ((nn + 3) / 4) * 4));
+        slots = (slots + numeric_waves_per_block() - 1) / numeric_waves_per_block() * numeric_waves_per_block();
+        g_slots = (int32_t)slots;
+        FPS_TRY(gscratch.ensure(sizeof(uint32_t) * (size_t)(per_slot_u32 * slots)));
+        return FPS_OK;
+    }
+};
+
+enum class Kind { Power = FPS_STAGE_POWER, Block = FPS_STAGE_BLOCK, GStep = FPS_STAGE_GSTEP, Horner = FPS_STAGE_HORNER };
+
+constexpr int kTimingRing = 64;  // evaluations whose kernel times are kept
+
+struct StageRecord {
+    int kind = 0, index = 0;
+    int a_src = -1, b_src = -1, e_src = -1;  // stage that produced the operand (-1: Z or none)
+    bool a_is_z = false, b_is_z = false;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // events of the current evaluation (ring slot)
+};
+
+struct Schedule {
+    int N = 0, q = 0, b = 0, g = 0, J = 0, start = 0, nsp = 0;
+};
+
+bool make_schedule(int m, int s, Schedule* sc)
+{
+    if (m < 0 || s < 1) return false;
+    sc->N = m + 1;
+    sc->q = s;
+    sc->b = (sc->N + s - 1) / s;
+    sc->g = (sc->N - sc->q * (sc->b - 1) == 1) ? 1 : 0;
+    sc->J = (sc->b >= 2) ? sc->q : m;
+    sc->start = (sc->b >= 2) ? 1 + sc->g : 0;
+    sc->nsp = (sc->J >= 1 ? sc->J - 1 : 0) + (sc->b >= 2 ? sc->b - 1 - sc->g : 0);
+    return true;
+}
+
+// Runs row-accumulation stages with one workspace.
+struct Engine {
+    Workspace ws;
+    uint64_t flags = 0;
+    std::vector<int64_t> learned;  // per stage index: output capacity learned by a sizing run
+    std::vector<bool> learned_global;
+
+    StageCounters* ctr(int i) const { return ws.counters.as<StageCounters>() + i; }
+    unsigned long long* part(int i) const
+    {
+        return ws.part.as<unsigned long long>() + (size_t)i * kPartCount * (size_t)ws.part_stride;
+    }
+
+    // Host reduction of a stage's per-block partial sums.
+    fps_status stage_totals(int i, int32_t mode, unsigned long long out[kPartCount])
+    {
+        const int64_t na = analyze_blocks(mode, ws.n), nk = numeric_blocks(ws.n);
+        std::vector<unsigned long long> h((size_t)(kPartCount * ws.part_stride));
+        HIP_TRY(hipMemcpy(h.data(), part(i), sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
+        for (int k = 0; k < kPartCount; ++k) {
+            const int64_t cnt = (k == kPartKept) ? nk : na;
+            unsigned long long t = 0;
+            for (int64_t b = 0; b < cnt; ++b) t += h[(size_t)(k * ws.part_stride + b)];
+            out[k] = t;
+        }
+        StageCounters c{};
+        HIP_TRY(hipMemcpy(&c, ctr(i), sizeof(c), hipMemcpyDeviceToHost));
+        out[kPartKept] += c.kept_global;
+        return FPS_OK;
+    }
+
+    fps_status init(int64_t n, int stages, uint64_t fl)
+    {
+        flags = fl;
+        learned.assign((size_t)stages, -1);
+        learned_global.assign((size_t)stages, false);
+        return ws.init(n, stages);
+    }
+
+    // Runs one stage into `out`.  With `size` true the stream is synchronised to
+    // read the output bound and the buffers are grown to fit; otherwise the
+    // capacities learned earlier are used as they are.
+    fps_status run(int idx, StageArgs& a, SlackMatrix& out, hipStream_t s, bool size, StageRecord* rec)
+    {
+        const int64_t n = ws.n;
+        a.n = n;
+        a.W = ws.W.as<int32_t>();
+        a.lo = ws.lo.as<int32_t>();
+        a.ub = ws.ub.as<int64_t>();
+        a.ctr = ctr(idx);
+        a.part = part(idx);
+        a.part_stride = ws.part_stride;
+        a.fb_list = ws.fb.as<int64_t>();
+        a.g_scratch = ws.gscratch.as<uint32_t>();
+        a.g_slot_words = ws.g_words;
+        a.g_slot_cap = ws.g_cap;
+        a.g_slot_stride = ws.g_stride;
+        a.g_slots = ws.g_slots;
+        a.force_global = (flags & FPS_FLAG_FORCE_GLOBAL) ? 1 : 0;
+        FPS_TRY(out.ensure_rows(n));
+        HIP_TRY(launch_analyze(a, s));
+        HIP_TRY(launch_scan(ws.ub.as<int64_t>(), out.off.as<int64_t>(), n, ws.scan_tmp.as<int64_t>(), s));
+        bool run_global = true;
+        if (size || learned[(size_t)idx] < 0) {
+            int64_t total = 0;
+            HIP_TRY(hipMemcpyAsync(&total, out.off.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            FPS_TRY(out.ensure_cap(total));
+            learned[(size_t)idx] = std::max<int64_t>(learned[(size_t)idx], total);
+        } else {
+            FPS_TRY(out.ensure_cap(learned[(size_t)idx]));
+            run_global = learned_global[(size_t)idx] || a.force_global;
+        }
+        a.out = out.out();
+        a.global_planned = run_global ? 1 : 0;
+        if (rec && rec->ev0) HIP_TRY(hipEventRecord(rec->ev0, s));
+        HIP_TRY(launch_numeric_lds(a, 0, s));
+        if (rec && rec->ev1) HIP_TRY(hipEventRecord(rec->ev1, s));
+        if (run_global) HIP_TRY(launch_numeric_global(a, numeric_global_blocks(ws.g_slots), s));
+        if (size) {
+            // learn whether this stage needs the global-memory kernel
+            StageCounters c{};
+            HIP_TRY(hipMemcpyAsync(&c, ctr(idx), sizeof(c), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (c.fb_count > 0) learned_global[(size_t)idx] = true;
+        }
+        return FPS_OK;
+    }
+
+    // Canonical compaction of a slack matrix.
+    fps_status compact(const SlackMatrix& m, CanonMatrix& c, hipStream_t s)
+    {
+        const int64_t n = m.n;
+        c.n = n;
+        FPS_TRY(c.rp.ensure(sizeof(int64_t) * (size_t)(n + 1)));
+        FPS_TRY(c.len_tmp.ensure(sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)));
+        FPS_TRY(c.scan_tmp.ensure(sizeof(int64_t) * scan_tmp_elems(n)));
+        const int64_t want = std::max<int64_t>(m.cap, 1);
+        if (want > c.cap) {
+            FPS_TRY(c.col.ensure(sizeof(int32_t) * (size_t)want));
+            FPS_TRY(c.val.ensure(sizeof(double) * (size_t)want));
+            c.cap = want;
+        }
+        HIP_TRY(launch_row_lengths(m.off.as<int64_t>(), m.end.as<int64_t>(), n, c.len_tmp.as<int64_t>(), s));
+        HIP_TRY(launch_scan(c.len_tmp.as<int64_t>(), c.rp.as<int64_t>(), n, c.scan_tmp.as<int64_t>(), s));
+        HIP_TRY(launch_compact(m.off.as<int64_t>(), m.end.as<int64_t>(), m.col.as<int32_t>(), m.val.as<double>(), n,
+                               c.rp.as<int64_t>(), c.col.as<int32_t>(), c.val.as<double>(), s));
+        return FPS_OK;
+    }
+};
+
+fps_status check_view(const fps_csr_view* v, const char* what, int64_t n_expect)
+{
+    if (!v) return set_error(FPS_ERR_INVALID_ARG, "%s is NULL", what);
+    if (v->n < 1 || v->n > INT32_MAX - 1) return set_error(FPS_ERR_INVALID_ARG, "%s: n = %lld out of range", what, (long long)v->n);
+    if (n_expect >= 0 && v->n != n_expect) return set_error(FPS_ERR_INVALID_ARG, "%s: dimension mismatch", what);
+    if (v->nnz < 0) return set_error(FPS_ERR_INVALID_ARG, "%s: negative nnz", what);
+    if (!v->row_ptr || (v->nnz > 0 && (!v->col || !v->val)))
+        return set_error(FPS_ERR_INVALID_ARG, "%s: null device pointer", what);
+    return FPS_OK;
+}
+
+fps_status validate_on_device(const fps_csr_view* v, const char* what, hipStream_t s)
+{
+    DevBuf err;
+    FPS_TRY(err.ensure(sizeof(unsigned long long)));
+    HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(unsigned long long), s));
+    HIP_TRY(launch_validate_csr(v->row_ptr, v->col, v->val, v->n, v->nnz, err.as<unsigned long long>(), s));
+    unsigned long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, err.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h) return set_error(FPS_ERR_BAD_CSR, "%s is not a canonical CSR (row pointers, sorted in-range columns, finite values)", what);
+    return FPS_OK;
+}
+
+// View of a canonical CSR for the kernels, with row info in (span, amax).
+MatView canon_view(const fps_csr_view* v, const int2* span, const double* amax)
+{
+    return MatView{v->row_ptr, v->row_ptr + 1, v->col, v->val, span, amax};
+}
+
+}  // namespace
+
+// ===========================================================================
+// Plan
+// ===========================================================================
+
+struct fps_plan_s {
+    fps_csr_view Z{};
+    std::vector<double> c;
+    int m = 0, s = 0;
+    double tau = 0.0;
+    uint64_t flags = 0;
+    Schedule sc;
+    Engine eng;
+    std::vector<std::unique_ptr<SlackMatrix>> P;  // P[j], j >= 2
+    SlackMatrix S[2], Bh;
+    CanonMatrix result;
+    int final_idx = -1;  // which slack matrix holds F (0/1 = S, 2 = Bh not used)
+    const SlackMatrix* final_m = nullptr;
+    std::vector<StageRecord> rec;
+    std::vector<hipEvent_t> ring;  // [slot][stage][2] when timing
+    int n_stages = 0;
+    hipStream_t last_stream = nullptr;
+    int64_t evals = 0;
+    int64_t resizes = 0;
+    bool evaluated = false;
+    bool sized_once = false;
+
+    int stage_count() const
+    {
+        // powers + at most (b blocks + b-1 products + 1 shortcut)
+        return (sc.J > 1 ? sc.J - 1 : 0) + 2 * sc.b + 2;
+    }
+
+    // Terms of block i over series indices i*q + j, j = 0..jmax (eq. 13).
+    void block_terms(int i, int jmax, Terms* T, const MatView& zv) const
+    {
+        T->n = 0;
+        for (int j = 0; j <= jmax; ++j) {
+            const int k = i * sc.q + j;
+            if (k > m) break;
+            if (c[(size_t)k] == 0.0) continue;
+            const int t = T->n++;
+            T->coef[t] = c[(size_t)k];
+            if (j == 0) {
+                T->beg[t] = nullptr;
+                T->end[t] = nullptr;
+                T->col[t] = nullptr;
+                T->val[t] = nullptr;
+                T->span[t] = nullptr;
+            } else {
+                const MatView v = (j == 1) ? zv : P[(size_t)j]->view();
+                T->beg[t] = v.beg;
+                T->end[t] = v.end;
+                T->col[t] = v.col;
+                T->val[t] = v.val;
+                T->span[t] = v.span;
+            }
+        }
+    }
+
+    fps_status run_eval(hipStream_t s, bool size)
+    {
+        const int64_t n = Z.n;
+        n_stages = 0;
+        HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(eng.ws.counters.p),
+                                (int64_t)(sizeof(StageCounters) / 8) * eng.ws.max_stages, 0ull, s));
+        int2* zspan = eng.ws.zspan.as<int2>();
+        double* zamax = eng.ws.zamax.as<double>();
+        HIP_TRY(launch_rowinfo_csr(Z.row_ptr, Z.col, Z.val, n, zspan, zamax, s));
+        const MatView zv = canon_view(&Z, zspan, zamax);
+        const double skip_tau = (flags & FPS_FLAG_NO_SKIP) || tau <= 0.0 ? 0.0 : tau * (1.0 - 1e-6);
+
+        const int nst = stage_count();
+        const size_t slot = (size_t)(evals % kTimingRing);
+        auto begin_stage = [&](Kind k, int index) -> StageRecord* {
+            StageRecord* r = &rec[(size_t)n_stages];
+            r->kind = (int)k;
+            r->index = index;
+            r->a_src = r->b_src = r->e_src = -1;
+            r->a_is_z = r->b_is_z = false;
+            if (!ring.empty()) {
+                r->ev0 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2];
+                r->ev1 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2 + 1];
+            }
+            return r;
+        };
+
+        std::vector<int> pow_stage((size_t)sc.J + 2, -1);
+        // step 1: filtered powers P_{j+1} = D_tau(Z (x) P_j)   (eq. 11)
+        for (int j = 1; j + 1 <= sc.J; ++j) {
+            StageArgs a{};
+            a.mode = kModeProduct;
+            a.tau = tau;
+            a.skip_tau = skip_tau;
+            a.A = zv;
+            a.B = (j == 1) ? zv : P[(size_t)j]->view();
+            a.has_e = 0;
+            StageRecord* r = begin_stage(Kind::Power, j + 1);
+            r->a_is_z = true;
+            r->b_is_z = (j == 1);
+            r->b_src = (j == 1) ? -1 : pow_stage[(size_t)j];
+            FPS_TRY(eng.run(n_stages, a, *P[(size_t)j + 1], s, size, r));
+            pow_stage[(size_t)j + 1] = n_stages++;
+        }
+
+        auto run_sum = [&](Kind k, int index, int block, int jmax, SlackMatrix& out) -> fps_status {
+            StageArgs a{};
+            a.mode = kModeSum;
+            a.tau = 0.0;
+            a.skip_tau = 0.0;
+            block_terms(block, jmax, &a.T, zv);
+            a.has_e = 0;
+            StageRecord* r = begin_stage(k, index);
+            FPS_TRY(eng.run(n_stages, a, out, s, size, r));
+            n_stages++;
+            return FPS_OK;
+        };
+
+        if (sc.b == 1) {
+            FPS_TRY(run_sum(Kind::Block, 0, 0, sc.q - 1, S[0]));
+            final_m = &S[0];
+        } else {
+            int cur = 0;
+            if (sc.g) {
+                FPS_TRY(run_sum(Kind::GStep, 1, sc.b - 2, sc.q, S[cur]));  // eq. 14, g = 1
+            } else {
+                FPS_TRY(run_sum(Kind::Block, sc.b - 1, sc.b - 1, sc.q - 1, S[cur]));
+            }
+            int s_stage = n_stages - 1;
+            for (int i = sc.start; i <= sc.b - 1; ++i) {
+                FPS_TRY(run_sum(Kind::Block, sc.b - 1 - i, sc.b - 1 - i, sc.q - 1, Bh));
+                const int bh_stage = n_stages - 1;
+                StageArgs a{};
+                a.mode = kModeProduct;
+                a.tau = tau;
+                a.skip_tau = skip_tau;
+                a.A = (sc.q == 1) ? zv : P[(size_t)sc.q]->view();
+                a.B = S[cur].view();
+                a.E = Bh.view();
+                a.has_e = 1;
+                StageRecord* r = begin_stage(Kind::Horner, i);
+                r->a_is_z = (sc.q == 1);
+                r->a_src = (sc.q == 1) ? -1 : pow_stage[(size_t)sc.q];
+                r->b_src = s_stage;
+                r->e_src = bh_stage;
+                FPS_TRY(eng.run(n_stages, a, S[1 - cur], s, size, r));
+                s_stage = n_stages++;
+                cur = 1 - cur;
+            }
+            final_m = &S[cur];
+        }
+        FPS_TRY(eng.compact(*final_m, result, s));
+        return FPS_OK;
+    }
+};
+
+extern "C" {
+
+int32_t fps_abi_version(void) { return FPS_ABI_VERSION; }
+
+const char* fps_status_string(fps_status s)
+{
+    switch (s) {
+    case FPS_OK: return "ok";
+    case FPS_ERR_INVALID_ARG: return "invalid argument";
+    case FPS_ERR_BAD_CSR: return "bad CSR input";
+    case FPS_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case FPS_ERR_HIP: return "HIP error";
+    case FPS_ERR_CAPACITY: return "capacity exceeded";
+    case FPS_ERR_NOT_READY: return "not ready";
+    default: return "unknown status";
+    }
+}
+
+const char* fps_last_error(void) { return g_last_error.c_str(); }
+
+fps_status fps_schedule(int32_t m, int32_t s, int32_t* N, int32_t* q, int32_t* b, int32_t* g, int32_t* J,
+                        int32_t* start, int32_t* n_spgemm)
+{
+    Schedule sc;
+    if (!make_schedule(m, s, &sc)) return set_error(FPS_ERR_INVALID_ARG, "need m >= 0 and s >= 1");
+    if (N) *N = sc.N;
+    if (q) *q = sc.q;
+    if (b) *b = sc.b;
+    if (g) *g = sc.g;
+    if (J) *J = sc.J;
+    if (start) *start = sc.start;
+    if (n_spgemm) *n_spgemm = sc.nsp;
+    return FPS_OK;
+}
+
+fps_status fps_plan_create(fps_plan* out, const fps_csr_view* Z, const double* coeffs, int32_t m, int32_t s,
+                           double tau, uint64_t flags, fps_stream stream)
+{
+    g_last_error.clear();
+    if (!out) return set_error(FPS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    FPS_TRY(check_view(Z, "Z", -1));
+    if (!coeffs) return set_error(FPS_ERR_INVALID_ARG, "coeffs is NULL");
+    if (m < 0) return set_error(FPS_ERR_INVALID_ARG, "m must be >= 0");
+    if (s < 1 || s > FPS_MAX_S) return set_error(FPS_ERR_INVALID_ARG, "s must be in [1, %d]", FPS_MAX_S);
+    if (!std::isfinite(tau) || tau < 0.0) return set_error(FPS_ERR_INVALID_ARG, "tau must be finite and >= 0");
+    for (int k = 0; k <= m; ++k)
+        if (!std::isfinite(coeffs[k])) return set_error(FPS_ERR_INVALID_ARG, "coefficient %d is not finite", k);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (!(flags & FPS_FLAG_NO_VALIDATE)) FPS_TRY(validate_on_device(Z, "Z", st));
+
+    std::unique_ptr<fps_plan_s> p(new (std::nothrow) fps_plan_s());
+    if (!p) return set_error(FPS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->Z = *Z;
+    p->c.assign(coeffs, coeffs + m + 1);
+    p->m = m;
+    p->s = s;
+    p->tau = tau;
+    p->flags = flags;
+    make_schedule(m, s, &p->sc);
+    const int stages = p->stage_count();
+    if (stages > FPS_MAX_STAGES)
+        return set_error(FPS_ERR_CAPACITY, "schedule needs %d stages, at most %d supported", stages, FPS_MAX_STAGES);
+    FPS_TRY(p->eng.init(Z->n, stages, flags));
+    p->P.resize((size_t)std::max(p->sc.J, 1) + 2);
+    for (auto& x : p->P) x.reset(new SlackMatrix());
+    p->rec.assign((size_t)stages, StageRecord{});
+    if (flags & FPS_FLAG_TIMING) {
+        p->ring.assign((size_t)kTimingRing * (size_t)stages * 2, nullptr);
+        for (auto& e : p->ring) HIP_TRY(hipEventCreate(&e));
+    }
+    *out = p.release();
+    return FPS_OK;
+}
+
+fps_status fps_eval(fps_plan p, fps_stream stream)
+{
+    if (!p) return set_error(FPS_ERR_INVALID_ARG, "plan is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const bool size = (p->flags & FPS_FLAG_SYNC_SIZES) || !p->sized_once;
+    p->last_stream = s;
+    fps_status st = p->run_eval(s, size);
+    if (st != FPS_OK) return st;
+    if (size) p->sized_once = true;
+    p->evals++;
+    p->evaluated = true;
+    return FPS_OK;
+}
+
+static fps_status read_errors(fps_plan p, unsigned long long* err)
+{
+    std::vector<StageCounters> c((size_t)p->n_stages);
+    if (p->n_stages > 0)
+        HIP_TRY(hipMemcpy(c.data(), p->eng.ws.counters.p, sizeof(StageCounters) * (size_t)p->n_stages,
+                          hipMemcpyDeviceToHost));
+    unsigned long long e = 0;
+    for (auto& x : c) e |= x.errors;
+    *err = e;
+    return FPS_OK;
+}
+
+// Synchronises, checks the device error flags and re-runs with sizing if a
+// learned capacity turned out too small.
+static fps_status finish(fps_plan p)
+{
+    HIP_TRY(hipStreamSynchronize(p->last_stream));
+    unsigned long long err = 0;
+    FPS_TRY(read_errors(p, &err));
+    if (err & kErrColumnOutsideWindow) return set_error(FPS_ERR_HIP, "internal error: column outside its row window");
+    if (err & (kErrCapacity | kErrNeedsGlobal)) {
+        p->resizes++;
+        FPS_TRY(p->run_eval(p->last_stream, true));
+        HIP_TRY(hipStreamSynchronize(p->last_stream));
+        FPS_TRY(read_errors(p, &err));
+        if (err) return set_error(FPS_ERR_CAPACITY, "stage workspace exceeded after re-sizing (flags %llx)", err);
+    }
+    return FPS_OK;
+}
+
+fps_status fps_result_nnz(fps_plan p, int64_t* nnz)
+{
+    if (!p || !nnz) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    if (!p->evaluated) return set_error(FPS_ERR_NOT_READY, "no evaluation has run on this plan");
+    FPS_TRY(finish(p));
+    HIP_TRY(hipMemcpy(nnz, p->result.rp.as<int64_t>() + p->Z.n, sizeof(int64_t), hipMemcpyDeviceToHost));
+    return FPS_OK;
+}
+
+fps_status fps_result_copy(fps_plan p, int64_t* row_ptr, int32_t* col, double* val, fps_stream stream)
+{
+    if (!p || !row_ptr) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    if (!p->evaluated) return set_error(FPS_ERR_NOT_READY, "no evaluation has run on this plan");
+    int64_t nnz = 0;
+    FPS_TRY(fps_result_nnz(p, &nnz));
+    if (nnz > 0 && (!col || !val)) return set_error(FPS_ERR_INVALID_ARG, "null col/val with nnz > 0");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t n = p->Z.n;
+    HIP_TRY(hipMemcpyAsync(row_ptr, p->result.rp.p, sizeof(int64_t) * (size_t)(n + 1), hipMemcpyDeviceToDevice, s));
+    if (nnz > 0) {
+        HIP_TRY(hipMemcpyAsync(col, p->result.col.p, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(val, p->result.val.p, sizeof(double) * (size_t)nnz, hipMemcpyDeviceToDevice, s));
+    }
+    return FPS_OK;
+}
+
+fps_status fps_get_stats(fps_plan p, fps_stats* st)
+{
+    if (!p || !st) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    std::memset(st, 0, sizeof(*st));
+    st->N = p->sc.N;
+    st->q = p->sc.q;
+    st->b = p->sc.b;
+    st->g = p->sc.g;
+    st->J = p->sc.J;
+    st->start = p->sc.start;
+    st->n_spgemm = p->sc.nsp;
+    st->evals = p->evals;
+    st->resizes = p->resizes;
+    if (!p->evaluated) return FPS_OK;
+    FPS_TRY(finish(p));
+    const int ns = p->n_stages;
+    std::vector<StageCounters> c((size_t)ns);
+    HIP_TRY(hipMemcpy(c.data(), p->eng.ws.counters.p, sizeof(StageCounters) * (size_t)ns, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(&st->nnz_out, p->result.rp.as<int64_t>() + p->Z.n, sizeof(int64_t), hipMemcpyDeviceToHost));
+    std::vector<std::array<unsigned long long, kPartCount>> tot((size_t)ns);
+    for (int i = 0; i < ns; ++i) {
+        const int kind = p->rec[(size_t)i].kind;
+        const int32_t mode = (kind == FPS_STAGE_POWER || kind == FPS_STAGE_HORNER) ? kModeProduct : kModeSum;
+        FPS_TRY(p->eng.stage_totals(i, mode, tot[(size_t)i].data()));
+    }
+    st->n_stages = std::min(ns, FPS_MAX_STAGES);
+    const double n1 = (double)(p->Z.n + 1);
+    double bytes = 0.0, ms_total = 0.0;
+    int launches = 0;
+    auto kept = [&](int i) { return (double)tot[(size_t)i][kPartKept]; };
+    for (int i = 0; i < ns && i < FPS_MAX_STAGES; ++i) {
+        const StageRecord& r = p->rec[(size_t)i];
+        st->kind[i] = r.kind;
+        st->index[i] = r.index;
+        st->stage_products[i] = (int64_t)tot[(size_t)i][kPartProducts];
+        st->stage_nnz[i] = (int64_t)tot[(size_t)i][kPartKept];
+        st->products += (int64_t)tot[(size_t)i][kPartProducts];
+        st->products_skipped += (int64_t)tot[(size_t)i][kPartProductsSkipped];
+        st->rows_skipped += (int64_t)tot[(size_t)i][kPartRowsSkipped];
+        st->rows_global += (int64_t)c[(size_t)i].fb_count;
+        if (r.kind == FPS_STAGE_POWER || r.kind == FPS_STAGE_HORNER) {
+            const double za = (double)p->Z.nnz;
+            const double na = r.a_is_z ? za : (r.a_src >= 0 ? kept(r.a_src) : 0.0);
+            const double nb = r.b_is_z ? za : (r.b_src >= 0 ? kept(r.b_src) : 0.0);
+            const double ne = r.e_src >= 0 ? kept(r.e_src) : 0.0;
+            const int operands = (r.e_src >= 0) ? 4 : 3;
+            bytes += 12.0 * (na + nb + ne + kept(i)) + 8.0 * n1 * operands;
+        }
+        if (!p->ring.empty()) {
+            // average over the evaluations still held in the event ring
+            const int64_t held = std::min<int64_t>(p->evals, kTimingRing);
+            const size_t nst = (size_t)p->stage_count();
+            double sum = 0.0;
+            for (int64_t e = p->evals - held; e < p->evals; ++e) {
+                const size_t slot = (size_t)(e % kTimingRing);
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, p->ring[(slot * nst + (size_t)i) * 2],
+                                            p->ring[(slot * nst + (size_t)i) * 2 + 1]));
+                sum += ms;
+            }
+            const double avg = held > 0 ? sum / (double)held : 0.0;
+            st->stage_ms[i] = avg;
+            if (r.kind == FPS_STAGE_POWER || r.kind == FPS_STAGE_HORNER) {
+                ms_total += avg;
+                launches++;
+            }
+        }
+    }
+    st->bytes_algorithmic = bytes;
+    st->numeric_ms = ms_total;
+    st->numeric_launches = launches;
+    return FPS_OK;
+}
+
+void fps_plan_destroy(fps_plan p)
+{
+    if (!p) return;
+    (void)hipStreamSynchronize(p->last_stream);
+    for (auto& e : p->ring)
+        if (e) (void)hipEventDestroy(e);
+    delete p;
+}
+
+// ===========================================================================
+// Single stages
+// ===========================================================================
+
+struct fps_matrix_s {
+    CanonMatrix m;
+    int64_t nnz = 0;
+};
+
+static fps_status finish_single(Engine& eng, SlackMatrix& out, hipStream_t s, fps_matrix* res)
+{
+    std::unique_ptr<fps_matrix_s> mm(new (std::nothrow) fps_matrix_s());
+    if (!mm) return set_error(FPS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    FPS_TRY(eng.compact(out, mm->m, s));
+    StageCounters c{};
+    HIP_TRY(hipMemcpyAsync(&c, eng.ctr(0), sizeof(c), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&mm->nnz, mm->m.rp.as<int64_t>() + out.n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c.errors) return set_error(FPS_ERR_CAPACITY, "stage failed (device flags %llx)", c.errors);
+    *res = mm.release();
+    return FPS_OK;
+}
+
+fps_status fps_spgemm(fps_matrix* out, const fps_csr_view* A, const fps_csr_view* B, const fps_csr_view* E,
+                      double tau, fps_stream stream)
+{
+    g_last_error.clear();
+    if (!out) return set_error(FPS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    FPS_TRY(check_view(A, "A", -1));
+    FPS_TRY(check_view(B, "B", A->n));
+    if (E) FPS_TRY(check_view(E, "E", A->n));
+    if (!std::isfinite(tau) || tau < 0.0) return set_error(FPS_ERR_INVALID_ARG, "tau must be finite and >= 0");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    FPS_TRY(validate_on_device(A, "A", s));
+    FPS_TRY(validate_on_device(B, "B", s));
+    if (E) FPS_TRY(validate_on_device(E, "E", s));
+    const int64_t n = A->n;
+    Engine eng;
+    FPS_TRY(eng.init(n, 1, 0));
+    DevBuf info;
+    const size_t per = (sizeof(int2) + sizeof(double)) * (size_t)n;
+    FPS_TRY(info.ensure(3 * per));
+    int2* sp[3];
+    double* am[3];
+    for (int i = 0; i < 3; ++i) {
+        sp[i] = reinterpret_cast<int2*>(static_cast<char*>(info.p) + i * per);
+        am[i] = reinterpret_cast<double*>(static_cast<char*>(info.p) + i * per + sizeof(int2) * (size_t)n);
+    }
+    HIP_TRY(launch_rowinfo_csr(A->row_ptr, A->col, A->val, n, sp[0], am[0], s));
+    HIP_TRY(launch_rowinfo_csr(B->row_ptr, B->col, B->val, n, sp[1], am[1], s));
+    if (E) HIP_TRY(launch_rowinfo_csr(E->row_ptr, E->col, E->val, n, sp[2], am[2], s));
+    HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(eng.ws.counters.p), sizeof(StageCounters) / 8, 0ull, s));
+    StageArgs a{};
+    a.mode = kModeProduct;
+    a.tau = tau;
+    a.skip_tau = tau > 0.0 ? tau * (1.0 - 1e-6) : 0.0;
+    a.A = canon_view(A, sp[0], am[0]);
+    a.B = canon_view(B, sp[1], am[1]);
+    a.has_e = E ? 1 : 0;
+    if (E) a.E = canon_view(E, sp[2], am[2]);
+    SlackMatrix res;
+    FPS_TRY(eng.run(0, a, res, s, true, nullptr));
+    return finish_single(eng, res, s, out);
+}
+
+fps_status fps_axpy(fps_matrix* out, int64_t n, int32_t nterms, const double* coefs, const fps_csr_view* terms,
+                    fps_stream stream)
+{
+    g_last_error.clear();
+    if (!out) return set_error(FPS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > INT32_MAX - 1) return set_error(FPS_ERR_INVALID_ARG, "n out of range");
+    if (nterms < 1 || nterms > kMaxTerms) return set_error(FPS_ERR_INVALID_ARG, "nterms must be in [1, %d]", kMaxTerms);
+    if (!coefs || !terms) return set_error(FPS_ERR_INVALID_ARG, "null coefs/terms");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    for (int t = 0; t < nterms; ++t) {
+        if (!std::isfinite(coefs[t])) return set_error(FPS_ERR_INVALID_ARG, "coefficient %d not finite", t);
+        if (terms[t].row_ptr) {
+            FPS_TRY(check_view(&terms[t], "term", n));
+            FPS_TRY(validate_on_device(&terms[t], "term", s));
+        }
+    }
+    Engine eng;
+    FPS_TRY(eng.init(n, 1, 0));
+    DevBuf info;
+    const size_t per = (sizeof(int2) + sizeof(double)) * (size_t)n;
+    FPS_TRY(info.ensure(per * (size_t)nterms));
+    StageArgs a{};
+    a.mode = kModeSum;
+    a.tau = 0.0;
+    a.skip_tau = 0.0;
+    a.T.n = nterms;
+    for (int t = 0; t < nterms; ++t) {
+        a.T.coef[t] = coefs[t];
+        if (!terms[t].row_ptr) {
+            a.T.beg[t] = a.T.end[t] = nullptr;
+            a.T.col[t] = nullptr;
+            a.T.val[t] = nullptr;
+            a.T.span[t] = nullptr;
+            continue;
+        }
+        int2* sp = reinterpret_cast<int2*>(static_cast<char*>(info.p) + t * per);
+        double* am = reinterpret_cast<double*>(static_cast<char*>(info.p) + t * per + sizeof(int2) * (size_t)n);
+        HIP_TRY(launch_rowinfo_csr(terms[t].row_ptr, terms[t].col, terms[t].val, n, sp, am, s));
+        a.T.beg[t] = terms[t].row_ptr;
+        a.T.end[t] = terms[t].row_ptr + 1;
+        a.T.col[t] = terms[t].col;
+        a.T.val[t] = terms[t].val;
+        a.T.span[t] = sp;
+    }
+    HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(eng.ws.counters.p), sizeof(StageCounters) / 8, 0ull, s));
+    SlackMatrix res;
+    FPS_TRY(eng.run(0, a, res, s, true, nullptr));
+    return finish_single(eng, res, s, out);
+}
+
+fps_status fps_matrix_nnz(fps_matrix m, int64_t* nnz)
+{
+    if (!m || !nnz) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    *nnz = m->nnz;
+    return FPS_OK;
+}
+
+fps_status fps_matrix_copy(fps_matrix m, int64_t* row_ptr, int32_t* col, double* val, fps_stream stream)
+{
+    if (!m || !row_ptr) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    if (m->nnz > 0 && (!col || !val)) return set_error(FPS_ERR_INVALID_ARG, "null col/val with nnz > 0");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(row_ptr, m->m.rp.p, sizeof(int64_t) * (size_t)(m->m.n + 1), hipMemcpyDeviceToDevice, s));
+    if (m->nnz > 0) {
+        HIP_TRY(hipMemcpyAsync(col, m->m.col.p, sizeof(int32_t) * (size_t)m->nnz, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(val, m->m.val.p, sizeof(double) * (size_t)m->nnz, hipMemcpyDeviceToDevice, s));
+    }
+    return FPS_OK;
+}
+
+void fps_matrix_destroy(fps_matrix m) { delete m; }
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal declarations shared by the HIP kernels and the host library.
+// Not part of the public ABI (include/fps.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fps {
+
+constexpr int kWave = 64;
+constexpr int kMaxTerms = 32;  // FPS_MAX_S + 1
+
+// Row-range sparse matrix on the device.  Row r holds entries
+// [beg[r], end[r]) of col/val, columns strictly increasing.  A canonical CSR
+// is the special case end = row_ptr + 1.  span[r] = (first, last) column of
+// the row (first > last when empty); amax[r] = max |value| of the row.
+struct MatView {
+    const int64_t* beg;
+    const int64_t* end;
+    const int32_t* col;
+    const double* val;
+    const int2* span;
+    const double* amax;
+};
+
+// Coefficient-sum operands: term t contributes coef[t] * M_t, with M_t the
+// identity when beg[t] == nullptr.
+struct Terms {
+    int32_t n;
+    double coef[kMaxTerms];
+    const int64_t* beg[kMaxTerms];
+    const int64_t* end[kMaxTerms];
+    const int32_t* col[kMaxTerms];
+    const double* val[kMaxTerms];
+    const int2* span[kMaxTerms];
+};
+
+// Output of a stage in slack layout: row r may use [off[r], off[r+1]) and
+// the kernel writes end[r] = off[r] + kept entries.
+struct OutView {
+    const int64_t* off;  // n+1 (exclusive scan of the per-row upper bounds)
+    int64_t* end;        // n
+    int32_t* col;
+    double* val;
+    int2* span;
+    double* amax;
+    int64_t cap;  // capacity of col/val
+};
+
+// Per-stage device counters (zeroed before each evaluation).  Only rare
+// events use them; per-row statistics go to per-block partial sums (below)
+// so that no hot path contends on one address.
+struct StageCounters {
+    unsigned long long fb_count;     // rows appended to the fallback list
+    unsigned long long fb_next;      // dynamic fetch, global-memory kernel
+    unsigned long long errors;       // bit flags, see kErr*
+    unsigned long long kept_global;  // stored entries written by the global-memory kernel
+    unsigned long long pad[4];
+};
+
+// Per-stage partial sums, one entry per block, layout [kPartCount][part_stride]:
+enum PartIndex : int { kPartProducts = 0, kPartProductsSkipped = 1, kPartRowsSkipped = 2, kPartKept = 3, kPartCount = 4 };
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
+
+constexpr unsigned long long kErrColumnOutsideWindow = 1;  // span info inconsistent with data
+constexpr unsigned long long kErrCapacity = 2;             // output total above capacity
+constexpr unsigned long long kErrBadCsr = 4;               // validation failure
+constexpr unsigned long long kErrNeedsGlobal = 8;          // a row needed the global-memory kernel that was not scheduled
+
+enum StageMode : int32_t { kModeProduct = 0, kModeSum = 1 };
+
+struct StageArgs {
+    int32_t mode;
+    int32_t has_e;
+    int64_t n;
+    double tau;
+    double skip_tau;  // rows whose bound is below this are empty (0 disables the test)
+    MatView A, B, E;
+    Terms T;
+    // analysis outputs
+    int32_t* W;   // window width (0 = empty row)
+    int32_t* lo;  // first column of the window
+    int64_t* ub;  // upper bound of the row's stored entries (scanned in place into OutView::off)
+    OutView out;
+    StageCounters* ctr;
+    unsigned long long* part;  // this stage's partial sums
+    int64_t part_stride;
+    int64_t* fb_list;       // n entries
+    uint32_t* g_scratch;    // global-memory kernel workspace
+    int64_t g_slot_words;   // bitmap words per slot
+    int64_t g_slot_cap;     // accumulator entries per slot
+    int64_t g_slot_stride;  // 4-byte units between slots (multiple of 64)
+    int32_t g_slots;
+    int32_t force_global;
+    int32_t global_planned;  // 0: the global-memory kernel will not run for this stage
+};
+
+// ---- launch wrappers (fps_kernels.hip) ---------------------------------
+hipError_t launch_rowinfo_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n,
+                              int2* span, double* amax, hipStream_t s);
+hipError_t launch_validate_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n,
+                               int64_t nnz, unsigned long long* err, hipStream_t s);
+hipError_t launch_analyze(const StageArgs& a, hipStream_t s);
+// exclusive scan of x[0..n) into y[0..n], y[n] = total; tmp needs scan_tmp_elems(n)
+size_t scan_tmp_elems(int64_t n);
+hipError_t launch_scan(const int64_t* x, int64_t* y, int64_t n, int64_t* tmp, hipStream_t s);
+hipError_t launch_numeric_lds(const StageArgs& a, int grid, hipStream_t s);
+hipError_t launch_numeric_global(const StageArgs& a, int grid, hipStream_t s);
+// row lengths end[r]-beg[r] into len[r]
+hipError_t launch_row_lengths(const int64_t* beg, const int64_t* end, int64_t n, int64_t* len, hipStream_t s);
+hipError_t launch_compact(const int64_t* beg, const int64_t* end, const int32_t* col, const double* val,
+                          int64_t n, const int64_t* row_ptr, int32_t* ocol, double* oval, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, hipStream_t s);
+int numeric_waves_per_block();
+int numeric_global_blocks(int slots);
+// number of blocks each kernel writes partials for (host-side reduction)
+int64_t analyze_blocks(int32_t mode, int64_t n);
+int64_t numeric_blocks(int64_t n);
+
+}  // namespace fps

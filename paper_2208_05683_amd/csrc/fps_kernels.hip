@@ -1,0 +1,794 @@
+// HIP kernels (gfx950) for the filtered Paterson-Stockmeyer series.
+//
+// Every stage of the method is one "row-accumulation" stage:
+//
+//     out_r = D_tau( e_r + sum_t a_t * R_t )                          (*)
+//
+// where the terms (a_t, R_t) of output row r are
+//   - product stage (eq. 11, eq. 14): a_t = A_rk, R_t = row k of B, for the
+//     stored k of row r of A in ascending order;
+//   - coefficient-sum stage (eq. 13): a_t = c_j, R_t = row r of P_j
+//     (P_0 = I), in ascending j;
+// e_r is row r of an optional extra matrix (the block Bhat in a Horner step)
+// and D_tau drops x iff x == 0 or |x| < tau.  Each row is owned by one
+// 64-lane wavefront, which accumulates the terms strictly in order with one
+// fma per term into a per-row accumulator, so the result does not depend on
+// the launch configuration and matches a sequential row-wise product.
+//
+// Per stage:  analyze  -> per-row column window [lo, lo+W), upper bound of
+//                         stored entries, and the exact empty-row test
+//             scan     -> slack output offsets
+//             numeric  -> structure bitmap of the window, rank of every
+//                         column = its slot in a dense sorted accumulator,
+//                         ordered fma accumulation, drop test fused into
+//                         the (sorted, coalesced) write-out.
+// Rows whose window or structure does not fit the shared-memory workspace
+// are finished by a second kernel with per-wave workspace in device memory.
+#include "fps_device.h"
+
+#include <climits>
+
+namespace fps {
+namespace {
+
+constexpr int kLdsWords = 256;  // window of up to 8192 columns in shared memory
+constexpr int kLdsCap = 512;    // up to 512 structural entries per row in shared memory
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlock = kWave * kWavesPerBlock;
+
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+// Orders this wavefront's shared/device memory accesses around the call
+// (lanes of one wavefront see each other's stores after it).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_sum(T x)
+{
+    const int l = lane();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const T y = __shfl_up(x, d, kWave);
+        if (l >= d) x += y;
+    }
+    return x;
+}
+
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T x)
+{
+#pragma unroll
+    for (int d = G / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, G);
+    return x;
+}
+template <int G, typename T>
+__device__ __forceinline__ T group_min(T x)
+{
+#pragma unroll
+    for (int d = G / 2; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, G));
+    return x;
+}
+template <int G, typename T>
+__device__ __forceinline__ T group_max(T x)
+{
+#pragma unroll
+    for (int d = G / 2; d >= 1; d >>= 1) x = max(x, __shfl_xor(x, d, G));
+    return x;
+}
+
+__device__ __forceinline__ unsigned lanes_below(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// Block order that keeps consecutive logical blocks (consecutive rows) on one
+// XCD: the hardware hands blocks to the 8 XCDs round-robin, so block b runs on
+// XCD b % 8; logical ranges are contiguous per XCD and the map is a bijection.
+__device__ __forceinline__ int64_t xcd_logical_block()
+{
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned q = nb / kXcds, rm = nb % kXcds, x = b % kXcds, i = b / kXcds;
+    return (int64_t)x * q + (int64_t)min(x, rm) + i;
+}
+
+__device__ __forceinline__ void flag_error(const StageArgs& P, unsigned long long bit)
+{
+    atomicOr(&P.ctr->errors, bit);
+}
+
+// Block-wide sum of one value per thread; result valid in thread 0.
+template <typename T>
+__device__ __forceinline__ T block_sum_256(T x, T* sh)
+{
+    x = group_sum<kWave>(x);
+    if (lane() == 0) sh[threadIdx.x / kWave] = x;
+    __syncthreads();
+    T t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / kWave; ++i) t += sh[i];
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Row information of a canonical CSR: (first, last) column and max |value|.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_rowinfo_csr(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val, int64_t n, int2* span,
+                                                        double* amax)
+{
+    constexpr int G = 16;
+    const int64_t r = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+    const int gl = threadIdx.x % G;
+    if (r >= n) return;
+    const int64_t b = rp[r], e = rp[r + 1];
+    double m = 0.0;
+    for (int64_t p = b + gl; p < e; p += G) m = fmax(m, fabs(val[p]));
+    m = group_max<G>(m);
+    if (gl == 0) {
+        span[r] = (e > b) ? make_int2(col[b], col[e - 1]) : make_int2(1, 0);
+        amax[r] = m;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Device-side check of a canonical CSR (row pointers, column order/range,
+// finite values).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_validate_csr(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                         const double* __restrict__ val, int64_t n, int64_t nnz,
+                                                         unsigned long long* err)
+{
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicOr(err, kErrBadCsr);
+    if (r >= n) return;
+    const int64_t b = rp[r], e = rp[r + 1];
+    if (b > e || b < 0 || e > nnz) {
+        atomicOr(err, kErrBadCsr);
+        return;
+    }
+    int32_t prev = -1;
+    for (int64_t p = b; p < e; ++p) {
+        const int32_t c = col[p];
+        const double v = val[p];
+        if (c <= prev || c >= n || !isfinite(v)) {
+            atomicOr(err, kErrBadCsr);
+            return;
+        }
+        prev = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Analysis: window, upper bound, exact empty-row test.
+//
+// For a product row, |e_r| + sum_k |A_rk| max|B_k,:| bounds every entry of
+// (*) in exact arithmetic; the computed values exceed it by at most a
+// relative (terms+2) u, far below the 1e-6 margin folded into skip_tau, so a
+// row whose bound is below skip_tau would be dropped entirely by D_tau and is
+// marked empty without computing it.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
+{
+    constexpr int G = 16;
+    __shared__ unsigned long long sh[3][kBlock / G];
+    const int64_t blk = xcd_logical_block();
+    const int64_t r = (blk * kBlock + threadIdx.x) / G;
+    const int gl = threadIdx.x % G;
+    const int grp = threadIdx.x / G;
+    unsigned long long prod_done = 0, prod_skip = 0, row_skip = 0;
+    if (r < P.n) {
+        int32_t lo = INT_MAX, hi = -1;
+        int64_t prod = 0;
+        double bnd = 0.0;
+        const int64_t pb = P.A.beg[r], pe = P.A.end[r];
+        for (int64_t p = pb + gl; p < pe; p += G) {
+            const int32_t k = P.A.col[p];
+            const int64_t len = P.B.end[k] - P.B.beg[k];
+            if (len > 0) {
+                const int2 sp = P.B.span[k];
+                lo = min(lo, sp.x);
+                hi = max(hi, sp.y);
+                prod += len;
+                bnd += fabs(P.A.val[p]) * P.B.amax[k];
+            }
+        }
+        lo = group_min<G>(lo);
+        hi = group_max<G>(hi);
+        prod = group_sum<G>(prod);
+        bnd = group_sum<G>(bnd);
+        int64_t elen = 0;
+        double emax = 0.0;
+        if (P.has_e) {
+            elen = P.E.end[r] - P.E.beg[r];
+            if (elen > 0) {
+                const int2 sp = P.E.span[r];
+                lo = min(lo, sp.x);
+                hi = max(hi, sp.y);
+                emax = P.E.amax[r];
+            }
+        }
+        if (gl == 0) {
+            const bool empty = (prod == 0 && elen == 0);
+            const bool skip = !empty && P.skip_tau > 0.0 && (emax + bnd) < P.skip_tau;
+            int32_t W = 0;
+            int64_t ub = 0;
+            if (!empty && !skip) {
+                W = hi - lo + 1;
+                ub = min(prod + elen, (int64_t)W);
+            }
+            P.W[r] = W;
+            P.lo[r] = lo;
+            P.ub[r] = ub;
+            if (skip) {
+                prod_skip = (unsigned long long)prod;
+                row_skip = 1;
+            } else {
+                prod_done = (unsigned long long)prod;
+            }
+        }
+    }
+    if (gl == 0) {
+        sh[0][grp] = prod_done;
+        sh[1][grp] = prod_skip;
+        sh[2][grp] = row_skip;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kBlock / G; ++i) t += sh[threadIdx.x][i];
+        P.part[threadIdx.x * P.part_stride + blk] = t;  // kPartProducts, kPartProductsSkipped, kPartRowsSkipped
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_analyze_sum(StageArgs P)
+{
+    __shared__ unsigned long long sh[kBlock / kWave];
+    const int64_t blk = xcd_logical_block();
+    const int64_t r = blk * kBlock + threadIdx.x;
+    unsigned long long prod_done = 0;
+    if (r < P.n) {
+        int32_t lo = INT_MAX, hi = -1;
+        int64_t prod = 0;
+        for (int t = 0; t < P.T.n; ++t) {
+            if (P.T.beg[t] == nullptr) {
+                lo = min(lo, (int32_t)r);
+                hi = max(hi, (int32_t)r);
+                prod += 1;
+            } else {
+                const int64_t len = P.T.end[t][r] - P.T.beg[t][r];
+                if (len > 0) {
+                    const int2 sp = P.T.span[t][r];
+                    lo = min(lo, sp.x);
+                    hi = max(hi, sp.y);
+                    prod += len;
+                }
+            }
+        }
+        int32_t W = 0;
+        int64_t ub = 0;
+        if (prod > 0) {
+            W = hi - lo + 1;
+            ub = min(prod, (int64_t)W);
+        }
+        P.W[r] = W;
+        P.lo[r] = lo;
+        P.ub[r] = ub;
+        prod_done = (unsigned long long)prod;
+    }
+    const unsigned long long t = block_sum_256(prod_done, sh);
+    if (threadIdx.x == 0) {
+        P.part[kPartProducts * P.part_stride + blk] = t;
+        P.part[kPartProductsSkipped * P.part_stride + blk] = 0;
+        P.part[kPartRowsSkipped * P.part_stride + blk] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of int64 (two passes: tile sums, then tile scans with the
+// tile offset reduced from the preceding tile sums).
+// ---------------------------------------------------------------------------
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kBlock * kScanPer;
+
+__global__ void __launch_bounds__(kBlock) k_scan_tiles(const int64_t* __restrict__ x, int64_t n, int64_t* tile_sum)
+{
+    __shared__ int64_t sh[kBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t s = 0;
+    for (int i = 0; i < kScanPer; ++i) {
+        const int64_t j = base + (int64_t)i * kBlock + threadIdx.x;
+        if (j < n) s += x[j];
+    }
+    const int64_t t = block_sum_256(s, sh);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kBlock) k_scan_apply(const int64_t* __restrict__ x, int64_t n,
+                                                      const int64_t* __restrict__ tile_sum, int64_t* y)
+{
+    __shared__ int64_t sh[kBlock / kWave];
+    __shared__ int64_t wsum[kBlock / kWave];
+    __shared__ int64_t base_off;
+    // offset of this tile
+    int64_t s = 0;
+    for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kBlock) s += tile_sum[i];
+    const int64_t off = block_sum_256(s, sh);
+    if (threadIdx.x == 0) base_off = off;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int64_t v[kScanPer];
+    int64_t local = 0;
+    for (int i = 0; i < kScanPer; ++i) {
+        const int64_t j = base + i;
+        v[i] = (j < n) ? x[j] : 0;
+        local += v[i];
+    }
+    const int64_t inc = wave_incl_sum(local);
+    const int w = threadIdx.x / kWave;
+    if (lane() == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    int64_t wpre = 0;
+    for (int i = 0; i < w; ++i) wpre += wsum[i];
+    int64_t run = base_off + wpre + inc - local;
+    for (int i = 0; i < kScanPer; ++i) {
+        const int64_t j = base + i;
+        if (j < n) y[j] = run;
+        run += v[i];
+    }
+    if (base < n && base + kScanPer >= n) y[n] = run;  // the thread holding the last element
+}
+
+// ---------------------------------------------------------------------------
+// Numeric stage.
+// ---------------------------------------------------------------------------
+struct WaveStage {
+    int32_t excl[kWave];  // exclusive prefix of term lengths in the current chunk
+    int64_t beg[kWave];   // first entry of the term's row (-1: identity row)
+    double a[kWave];      // term weight
+};
+
+struct LdsWave {
+    uint32_t bm[kLdsWords];
+    uint32_t pre[kLdsWords];
+    double acc[kLdsCap];
+    int32_t cols[kLdsCap];
+    WaveStage st;
+};
+
+__device__ __forceinline__ uint32_t rank_of(const uint32_t* bm, const uint32_t* pre, uint32_t d)
+{
+    const uint32_t w = d >> 5;
+    return pre[w] + (uint32_t)__popc(bm[w] & ((1u << (d & 31u)) - 1u));
+}
+
+// One pass over the ordered terms of row r.  kAccum = false marks the
+// structure (bitmap in shared memory, byte map in device memory);
+// kAccum = true performs acc[rank(c)] = fma(a, v, acc[rank(c)]) with the
+// terms applied strictly in order: a chunk of 64 consecutive products is
+// loaded at once, and the read-modify-writes are issued one term at a time
+// (the products of one term have distinct columns, so they never collide).
+template <bool kAccum, bool kGlobal>
+__device__ __forceinline__ void term_pass(const StageArgs& P, int64_t r, int32_t lo, uint32_t W, uint8_t* bytes,
+                                          uint32_t* bm, const uint32_t* pre, double* acc, WaveStage& st)
+{
+    const int l = lane();
+    int64_t tb, te;
+    if (P.mode == kModeProduct) {
+        tb = P.A.beg[r];
+        te = P.A.end[r];
+    } else {
+        tb = 0;
+        te = P.T.n;
+    }
+    for (int64_t t0 = tb; t0 < te; t0 += kWave) {
+        const int64_t t = t0 + l;
+        int32_t len = 0;
+        int64_t bb = 0;
+        double a = 0.0;
+        if (t < te) {
+            if (P.mode == kModeProduct) {
+                const int32_t k = P.A.col[t];
+                a = P.A.val[t];
+                bb = P.B.beg[k];
+                len = (int32_t)(P.B.end[k] - bb);
+            } else {
+                const int ti = (int)t;
+                a = P.T.coef[ti];
+                if (P.T.beg[ti] == nullptr) {
+                    bb = -1;
+                    len = 1;
+                } else {
+                    bb = P.T.beg[ti][r];
+                    len = (int32_t)(P.T.end[ti][r] - bb);
+                }
+            }
+        }
+        const int32_t inc = wave_incl_sum(len);
+        const int32_t total = __shfl(inc, kWave - 1, kWave);
+        st.excl[l] = inc - len;
+        st.beg[l] = bb;
+        st.a[l] = a;
+        wave_sync();
+        for (int32_t q0 = 0; q0 < total; q0 += kWave) {
+            const int32_t qq = q0 + l;
+            bool valid = qq < total;
+            int kidx = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1)
+                if (st.excl[kidx + step] <= qq) kidx += step;
+            int32_t c = 0;
+            double v = 0.0, av = 0.0;
+            if (valid) {
+                const int64_t b0 = st.beg[kidx];
+                const int32_t o = qq - st.excl[kidx];
+                av = st.a[kidx];
+                if (b0 < 0) {
+                    c = (int32_t)r;
+                    v = 1.0;
+                } else if (P.mode == kModeProduct) {
+                    c = P.B.col[b0 + o];
+                    v = P.B.val[b0 + o];
+                } else {
+                    const int ti = (int)(t0 + kidx);
+                    c = P.T.col[ti][b0 + o];
+                    v = P.T.val[ti][b0 + o];
+                }
+            }
+            const uint32_t d = (uint32_t)(c - lo);
+            if (valid && d >= W) {
+                flag_error(P, kErrColumnOutsideWindow);
+                valid = false;
+            }
+            if (!kAccum) {
+                if (valid) {
+                    if (kGlobal)
+                        bytes[d] = 1;
+                    else
+                        atomicOr(&bm[d >> 5], 1u << (d & 31u));
+                }
+            } else {
+                const uint32_t slot = valid ? rank_of(bm, pre, d) : 0u;
+                const int kf = __shfl(kidx, 0, kWave);
+                const int last_lane = min(kWave - 1, total - q0 - 1);
+                const int kl = __shfl(kidx, last_lane, kWave);
+                for (int kk = kf; kk <= kl; ++kk) {
+                    if (valid && kidx == kk) acc[slot] = fma(av, v, acc[slot]);
+                    wave_sync();
+                }
+            }
+        }
+        wave_sync();
+    }
+}
+
+// Computes output row r.  Returns false (with nothing written) if the row
+// needs more workspace than max_words / cap provide.
+template <bool kGlobal>
+__device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8_t* bytes, uint32_t* bm,
+                                            uint32_t* pre, double* acc, int32_t* cols, WaveStage& st,
+                                            int64_t max_words, int64_t cap, int64_t* kept_out)
+{
+    const int l = lane();
+    *kept_out = 0;
+    const int64_t o = P.out.off[r];
+    const int32_t W = P.W[r];
+    if (W <= 0) {
+        if (l == 0) {
+            P.out.end[r] = o;
+            P.out.span[r] = make_int2(1, 0);
+            P.out.amax[r] = 0.0;
+        }
+        return true;
+    }
+    const int32_t lo = P.lo[r];
+    const int64_t words = ((int64_t)W + 31) >> 5;
+    if (words > max_words) return false;
+
+    // 1. structure of the row inside its window
+    if (kGlobal) {
+        uint32_t* b4 = reinterpret_cast<uint32_t*>(bytes);
+        for (int64_t i = l; i < words * 8; i += kWave) b4[i] = 0u;
+    } else {
+        for (int64_t w = l; w < words; w += kWave) bm[w] = 0u;
+    }
+    wave_sync();
+    term_pass<false, kGlobal>(P, r, lo, (uint32_t)W, bytes, bm, pre, acc, st);
+    if (P.has_e) {
+        for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave) {
+            const uint32_t d = (uint32_t)(P.E.col[p] - lo);
+            if (d >= (uint32_t)W) {
+                flag_error(P, kErrColumnOutsideWindow);
+                continue;
+            }
+            if (kGlobal)
+                bytes[d] = 1;
+            else
+                atomicOr(&bm[d >> 5], 1u << (d & 31u));
+        }
+    }
+    wave_sync();
+    if (kGlobal) {  // pack the byte map into bits
+        const uint32_t* b4 = reinterpret_cast<const uint32_t*>(bytes);
+        for (int64_t w = l; w < words; w += kWave) {
+            uint32_t bits = 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t v = b4[w * 8 + j];
+                bits |= ((v & 1u) | ((v >> 7) & 2u) | ((v >> 14) & 4u) | ((v >> 21) & 8u)) << (4 * j);
+            }
+            bm[w] = bits;
+        }
+        wave_sync();
+    }
+
+    // 2. prefix counts of the bitmap words: rank(column) = slot
+    uint32_t running = 0;
+    for (int64_t w0 = 0; w0 < words; w0 += kWave) {
+        const int64_t w = w0 + l;
+        const uint32_t cnt = (w < words) ? (uint32_t)__popc(bm[w]) : 0u;
+        const uint32_t inc = wave_incl_sum(cnt);
+        if (w < words) pre[w] = running + inc - cnt;
+        running += __shfl(inc, kWave - 1, kWave);
+    }
+    const int64_t ns = running;
+    if (ns > cap) return false;
+    if (o + ns > P.out.cap) {
+        flag_error(P, kErrCapacity);
+        if (l == 0) {
+            P.out.end[r] = o;
+            P.out.span[r] = make_int2(1, 0);
+            P.out.amax[r] = 0.0;
+        }
+        return true;
+    }
+
+    // 3. zero the accumulator, list the columns in slot order
+    for (int64_t i = l; i < ns; i += kWave) acc[i] = 0.0;
+    for (int64_t w = l; w < words; w += kWave) {
+        uint32_t bits = bm[w];
+        uint32_t base = pre[w];
+        while (bits) {
+            const int b = __ffs((int)bits) - 1;
+            cols[base++] = lo + (int32_t)(w * 32 + b);
+            bits &= bits - 1u;
+        }
+    }
+    wave_sync();
+
+    // 4. ordered accumulation, then the extra row enters with one addition
+    term_pass<true, kGlobal>(P, r, lo, (uint32_t)W, bytes, bm, pre, acc, st);
+    if (P.has_e) {
+        for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave) {
+            const uint32_t d = (uint32_t)(P.E.col[p] - lo);
+            if (d >= (uint32_t)W) continue;
+            const uint32_t slot = rank_of(bm, pre, d);
+            acc[slot] = P.E.val[p] + acc[slot];
+        }
+        wave_sync();
+    }
+
+    // 5. drop test and sorted write-out
+    int64_t kept = 0;
+    double amx = 0.0;
+    int32_t first = INT_MAX, last = -1;
+    for (int64_t i0 = 0; i0 < ns; i0 += kWave) {
+        const int64_t i = i0 + l;
+        double x = 0.0;
+        int32_t c = 0;
+        bool keep = false;
+        if (i < ns) {
+            x = acc[i];
+            c = cols[i];
+            keep = (x != 0.0) && !(fabs(x) < P.tau);
+        }
+        const unsigned long long m = __ballot(keep);
+        if (keep) {
+            const int64_t pos = o + kept + (int64_t)lanes_below(m);
+            P.out.col[pos] = c;
+            P.out.val[pos] = x;
+            amx = fmax(amx, fabs(x));
+            first = min(first, c);
+            last = max(last, c);
+        }
+        kept += __popcll(m);
+    }
+    amx = group_max<kWave>(amx);
+    first = group_min<kWave>(first);
+    last = group_max<kWave>(last);
+    if (l == 0) {
+        P.out.end[r] = o + kept;
+        P.out.span[r] = kept ? make_int2(first, last) : make_int2(1, 0);
+        P.out.amax[r] = amx;
+    }
+    wave_sync();
+    *kept_out = kept;
+    return true;
+}
+
+// One row per wavefront, four rows per block, blocks in XCD-aware order.
+__global__ void __launch_bounds__(kBlock) k_numeric_lds(StageArgs P)
+{
+    __shared__ LdsWave lds[kWavesPerBlock];
+    __shared__ unsigned long long kept_sh[kWavesPerBlock];
+    const int wv = threadIdx.x / kWave;
+    LdsWave& me = lds[wv];
+    const int l = lane();
+    const int64_t blk = xcd_logical_block();
+    const int64_t r = blk * kWavesPerBlock + wv;
+    int64_t kept = 0;
+    if (r < P.n) {
+        bool done = false;
+        if (!P.force_global)
+            done = process_row<false>(P, r, nullptr, me.bm, me.pre, me.acc, me.cols, me.st, kLdsWords, kLdsCap,
+                                      &kept);
+        if (!done && l == 0) {
+            const unsigned long long i = atomicAdd(&P.ctr->fb_count, 1ull);
+            P.fb_list[i] = r;
+            if (!P.global_planned) flag_error(P, kErrNeedsGlobal);
+        }
+    }
+    if (l == 0) kept_sh[wv] = (unsigned long long)kept;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kWavesPerBlock; ++i) t += kept_sh[i];
+        P.part[kPartKept * P.part_stride + blk] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
+{
+    __shared__ WaveStage st[kWavesPerBlock];
+    const int wv = threadIdx.x / kWave;
+    const int l = lane();
+    const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    if (slot >= P.g_slots) return;
+    // per-slot layout (4-byte units): bytes[words*8] | bm[words] | pre[words] | acc[2*cap] | cols[cap]
+    const int64_t words = P.g_slot_words;
+    const int64_t cap = P.g_slot_cap;
+    uint32_t* base = P.g_scratch + slot * P.g_slot_stride;
+    uint8_t* bytes = reinterpret_cast<uint8_t*>(base);
+    uint32_t* bm = base + words * 8;
+    uint32_t* pre = bm + words;
+    double* acc = reinterpret_cast<double*>(pre + words);
+    int32_t* cols = reinterpret_cast<int32_t*>(acc + cap);
+    const unsigned long long count = __hip_atomic_load(&P.ctr->fb_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long kept = 0;
+    while (true) {
+        unsigned long long i = 0;
+        if (l == 0) i = atomicAdd(&P.ctr->fb_next, 1ull);
+        i = __shfl(i, 0, kWave);
+        if (i >= count) break;
+        const int64_t r = P.fb_list[i];
+        int64_t k = 0;
+        if (!process_row<true>(P, r, bytes, bm, pre, acc, cols, st[wv], words, cap, &k)) flag_error(P, kErrCapacity);
+        kept += (unsigned long long)k;
+    }
+    if (l == 0 && kept) atomicAdd(&P.ctr->kept_global, kept);
+}
+
+// ---------------------------------------------------------------------------
+// Compaction of a slack matrix into canonical CSR.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_row_lengths(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
+                                                        int64_t n, int64_t* len)
+{
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r < n) len[r] = end[r] - beg[r];
+}
+
+__global__ void __launch_bounds__(kBlock) k_compact(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
+                                                    const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                    int64_t n, const int64_t* __restrict__ rp, int32_t* ocol,
+                                                    double* oval)
+{
+    const int64_t r = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+    if (r >= n) return;
+    const int64_t b = beg[r], e = end[r], d = rp[r];
+    for (int64_t p = b + lane(); p < e; p += kWave) {
+        ocol[d + (p - b)] = col[p];
+        oval[d + (p - b)] = val[p];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_u64(unsigned long long* p, int64_t count, unsigned long long v)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+inline unsigned blocks_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+// ---- launch wrappers -------------------------------------------------------
+
+hipError_t launch_rowinfo_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n, int2* span,
+                              double* amax, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rowinfo_csr, dim3(blocks_for(n * 16)), dim3(kBlock), 0, s, row_ptr, col, val, n, span, amax);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n, int64_t nnz,
+                               unsigned long long* err, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_validate_csr, dim3(blocks_for(n > 0 ? n : 1)), dim3(kBlock), 0, s, row_ptr, col, val, n, nnz,
+                       err);
+    return hipGetLastError();
+}
+
+hipError_t launch_analyze(const StageArgs& a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    if (a.mode == kModeProduct)
+        hipLaunchKernelGGL(k_analyze_product, dim3(blocks_for(a.n * 16)), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_analyze_sum, dim3(blocks_for(a.n)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+size_t scan_tmp_elems(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
+
+hipError_t launch_scan(const int64_t* x, int64_t* y, int64_t n, int64_t* tmp, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned tiles = (unsigned)((n + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kBlock), 0, s, x, n, tmp);
+    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kBlock), 0, s, x, n, (const int64_t*)tmp, y);
+    return hipGetLastError();
+}
+
+int64_t analyze_blocks(int32_t mode, int64_t n) { return mode == kModeProduct ? (n * 16 + kBlock - 1) / kBlock : (n + kBlock - 1) / kBlock; }
+
+int64_t numeric_blocks(int64_t n) { return (n + kWavesPerBlock - 1) / kWavesPerBlock; }
+
+hipError_t launch_numeric_lds(const StageArgs& a, int grid, hipStream_t s)
+{
+    (void)grid;
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_numeric_lds, dim3((unsigned)numeric_blocks(a.n)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_numeric_global(const StageArgs& a, int grid, hipStream_t s)
+{
+    if (a.n <= 0 || grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_numeric_global, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_lengths(const int64_t* beg, const int64_t* end, int64_t n, int64_t* len, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_row_lengths, dim3(blocks_for(n)), dim3(kBlock), 0, s, beg, end, n, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const int64_t* beg, const int64_t* end, const int32_t* col, const double* val, int64_t n,
+                          const int64_t* row_ptr, int32_t* ocol, double* oval, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n * kWave)), dim3(kBlock), 0, s, beg, end, col, val, n, row_ptr,
+                       ocol, oval);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(count)), dim3(kBlock), 0, s, p, count, v);
+    return hipGetLastError();
+}
+
+int numeric_waves_per_block() { return kWavesPerBlock; }
+
+int numeric_global_blocks(int slots) { return slots / kWavesPerBlock; }
+
+}  // namespace fps
