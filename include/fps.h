@@ -99,10 +99,12 @@ typedef struct {
     int64_t rows_skipped;         /* output rows proven empty by the bound test */
     int64_t rows_global;          /* rows handled by the global-memory kernel */
     int64_t resizes;              /* evaluations that had to re-size a buffer */
-    double bytes_algorithmic;     /* sum over products of 12 (nnz A + nnz B + nnz E + nnz kept) + 8 (n+1) * operands */
-    double numeric_ms;            /* FPS_FLAG_TIMING: numeric-kernel time of the product stages per
-                                     evaluation, averaged over the last (up to 64) evaluations */
-    int32_t numeric_launches;     /* FPS_FLAG_TIMING: product-stage numeric launches per evaluation */
+    double bytes_algorithmic;     /* per evaluation, summed over stages: every operand entry read once and
+                                     every kept entry written once at 12 bytes (8 value + 4 column), plus
+                                     8 (n+1) bytes of row offsets per operand and output */
+    double numeric_ms;            /* FPS_FLAG_TIMING: shared-memory numeric-kernel time per evaluation
+                                     (all stages), averaged over the last (up to 64) evaluations */
+    int32_t numeric_launches;     /* FPS_FLAG_TIMING: shared-memory numeric launches per evaluation */
     int32_t kind[FPS_MAX_STAGES];
     int32_t index[FPS_MAX_STAGES];
     int64_t stage_products[FPS_MAX_STAGES];

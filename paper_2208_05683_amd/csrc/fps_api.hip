@@ -127,8 +127,8 @@ struct CanonMatrix {
 // Per-row workspace shared by the stages of one engine.
 struct Workspace {
     int64_t n = 0;
-    DevBuf W, lo, ub, fb, scan_tmp, zspan, zamax, gscratch, counters, part;
-    int64_t g_words = 0, g_cap = 0, g_stride = 0;
+    DevBuf W, lo, ub, fb, scan_tmp, zspan, zamax, gscratch, counters, part, dummy;
+    int64_t g_words = 0, g_cap = 0, g_stride = 0, g_off_acc = 0, g_off_ebuf = 0, g_off_cols = 0;
     int64_t part_stride = 0;
     int32_t g_slots = 0;
     int max_stages = 0;
@@ -146,12 +146,25 @@ struct Workspace {
         FPS_TRY(zspan.ensure(sizeof(int2) * rows));
         FPS_TRY(zamax.ensure(sizeof(double) * rows));
         FPS_TRY(counters.ensure(sizeof(StageCounters) * (size_t)stages));
+        FPS_TRY(dummy.ensure(128 * (sizeof(int32_t) + sizeof(double))));
+        {
+            hipError_t e = hipMemset(dummy.p, 0, 128 * (sizeof(int32_t) + sizeof(double)));
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return set_error(FPS_ERR_HIP, "hipMemset: %s", hipGetErrorString(e));
+            }
+        }
         part_stride = std::max({analyze_blocks(kModeProduct, nn), analyze_blocks(kModeSum, nn), numeric_blocks(nn)}) + 1;
         FPS_TRY(part.ensure(sizeof(unsigned long long) * (size_t)(kPartCount * part_stride * stages)));
         // global-memory kernel: per slot byte map + bitmap + prefix + accumulator for a full row
         g_words = (nn + 31) / 32;
         g_cap = std::max<int64_t>(nn, 1);
-        const int64_t per_slot_u32 = (g_words * 8 + 2 * g_words + 3 * g_cap + 63) / 64 * 64;
+        // per slot (4-byte units): byte map [8 words] | bitmap words as uint2 [2 words] | accumulator
+        // [2 cap] | parked extra values [2 cap] | column list [cap]
+        g_off_acc = g_words * 10;
+        g_off_ebuf = g_off_acc + 2 * g_cap;
+        g_off_cols = g_off_ebuf + 2 * g_cap;
+        const int64_t per_slot_u32 = (g_off_cols + g_cap + 63) / 64 * 64;
         g_stride = per_slot_u32;
         const int64_t budget = int64_t(1) << 31;  // 2 GiB of workspace at most
         int64_t slots = std::min<int64_t>(256, std::max<int64_t>(4, budget / (4 * per_slot_u32)));
@@ -171,6 +184,7 @@ struct StageRecord {
     int kind = 0, index = 0;
     int a_src = -1, b_src = -1, e_src = -1;  // stage that produced the operand (-1: Z or none)
     bool a_is_z = false, b_is_z = false;
+    std::vector<int> term_src;  // coefficient sums: per matrix term, -1 = Z, else producing stage
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // events of the current evaluation (ring slot)
 };
 
@@ -242,12 +256,17 @@ struct Engine {
         a.ub = ws.ub.as<int64_t>();
         a.ctr = ctr(idx);
         a.part = part(idx);
+        a.dummy_val = ws.dummy.as<double>();
+        a.dummy_col = reinterpret_cast<const int32_t*>(ws.dummy.as<double>() + 128);
         a.part_stride = ws.part_stride;
         a.fb_list = ws.fb.as<int64_t>();
         a.g_scratch = ws.gscratch.as<uint32_t>();
         a.g_slot_words = ws.g_words;
         a.g_slot_cap = ws.g_cap;
         a.g_slot_stride = ws.g_stride;
+        a.g_off_acc = ws.g_off_acc;
+        a.g_off_ebuf = ws.g_off_ebuf;
+        a.g_off_cols = ws.g_off_cols;
         a.g_slots = ws.g_slots;
         a.force_global = (flags & FPS_FLAG_FORCE_GLOBAL) ? 1 : 0;
         FPS_TRY(out.ensure_rows(n));
@@ -347,9 +366,8 @@ struct fps_plan_s {
     Schedule sc;
     Engine eng;
     std::vector<std::unique_ptr<SlackMatrix>> P;  // P[j], j >= 2
-    SlackMatrix S[2], Bh;
+    SlackMatrix S[2];
     CanonMatrix result;
-    int final_idx = -1;  // which slack matrix holds F (0/1 = S, 2 = Bh not used)
     const SlackMatrix* final_m = nullptr;
     std::vector<StageRecord> rec;
     std::vector<hipEvent_t> ring;  // [slot][stage][2] when timing
@@ -362,8 +380,8 @@ struct fps_plan_s {
 
     int stage_count() const
     {
-        // powers + at most (b blocks + b-1 products + 1 shortcut)
-        return (sc.J > 1 ? sc.J - 1 : 0) + 2 * sc.b + 2;
+        // powers + the first Horner state + the Horner steps
+        return (sc.J > 1 ? sc.J - 1 : 0) + sc.b + 2;
     }
 
     // Terms of block i over series indices i*q + j, j = 0..jmax (eq. 13).
@@ -382,6 +400,7 @@ struct fps_plan_s {
                 T->col[t] = nullptr;
                 T->val[t] = nullptr;
                 T->span[t] = nullptr;
+                T->amax[t] = nullptr;
             } else {
                 const MatView v = (j == 1) ? zv : P[(size_t)j]->view();
                 T->beg[t] = v.beg;
@@ -389,7 +408,20 @@ struct fps_plan_s {
                 T->col[t] = v.col;
                 T->val[t] = v.val;
                 T->span[t] = v.span;
+                T->amax[t] = v.amax;
             }
+        }
+    }
+
+    // Matrix terms of block `block` (eq. 13) for the byte accounting: -1 = Z,
+    // otherwise the stage that produced P_j.
+    void add_term_sources(StageRecord* r, int block, int jmax, const std::vector<int>& pow_stage) const
+    {
+        for (int j = 1; j <= jmax; ++j) {
+            const int kk = block * sc.q + j;
+            if (kk > m) break;
+            if (c[(size_t)kk] == 0.0) continue;
+            r->term_src.push_back(j == 1 ? -1 : pow_stage[(size_t)j]);
         }
     }
 
@@ -413,6 +445,7 @@ struct fps_plan_s {
             r->index = index;
             r->a_src = r->b_src = r->e_src = -1;
             r->a_is_z = r->b_is_z = false;
+            r->term_src.clear();
             if (!ring.empty()) {
                 r->ev0 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2];
                 r->ev1 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2 + 1];
@@ -446,6 +479,7 @@ struct fps_plan_s {
             block_terms(block, jmax, &a.T, zv);
             a.has_e = 0;
             StageRecord* r = begin_stage(k, index);
+            add_term_sources(r, block, jmax, pow_stage);
             FPS_TRY(eng.run(n_stages, a, out, s, size, r));
             n_stages++;
             return FPS_OK;
@@ -463,21 +497,21 @@ struct fps_plan_s {
             }
             int s_stage = n_stages - 1;
             for (int i = sc.start; i <= sc.b - 1; ++i) {
-                FPS_TRY(run_sum(Kind::Block, sc.b - 1 - i, sc.b - 1 - i, sc.q - 1, Bh));
-                const int bh_stage = n_stages - 1;
+                // S_i = D_tau(Bhat_{b-1-i} + P_q (x) S_{i-1}) with the block summed inside the step
                 StageArgs a{};
                 a.mode = kModeProduct;
                 a.tau = tau;
                 a.skip_tau = skip_tau;
                 a.A = (sc.q == 1) ? zv : P[(size_t)sc.q]->view();
                 a.B = S[cur].view();
-                a.E = Bh.view();
-                a.has_e = 1;
+                a.has_e = 0;
+                block_terms(sc.b - 1 - i, sc.q - 1, &a.T, zv);
+                a.has_blk = a.T.n > 0 ? 1 : 0;
                 StageRecord* r = begin_stage(Kind::Horner, i);
                 r->a_is_z = (sc.q == 1);
                 r->a_src = (sc.q == 1) ? -1 : pow_stage[(size_t)sc.q];
                 r->b_src = s_stage;
-                r->e_src = bh_stage;
+                add_term_sources(r, sc.b - 1 - i, sc.q - 1, pow_stage);
                 FPS_TRY(eng.run(n_stages, a, S[1 - cur], s, size, r));
                 s_stage = n_stages++;
                 cur = 1 - cur;
@@ -674,13 +708,20 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
         st->products_skipped += (int64_t)tot[(size_t)i][kPartProductsSkipped];
         st->rows_skipped += (int64_t)tot[(size_t)i][kPartRowsSkipped];
         st->rows_global += (int64_t)c[(size_t)i].fb_count;
+        const double za = (double)p->Z.nnz;
         if (r.kind == FPS_STAGE_POWER || r.kind == FPS_STAGE_HORNER) {
-            const double za = (double)p->Z.nnz;
             const double na = r.a_is_z ? za : (r.a_src >= 0 ? kept(r.a_src) : 0.0);
             const double nb = r.b_is_z ? za : (r.b_src >= 0 ? kept(r.b_src) : 0.0);
             const double ne = r.e_src >= 0 ? kept(r.e_src) : 0.0;
-            const int operands = (r.e_src >= 0) ? 4 : 3;
-            bytes += 12.0 * (na + nb + ne + kept(i)) + 8.0 * n1 * operands;
+            double nt = 0.0;  // fused block terms
+            for (int src : r.term_src) nt += (src < 0) ? za : kept(src);
+            const double operands = 3.0 + (r.e_src >= 0 ? 1.0 : 0.0) + (double)r.term_src.size();
+            bytes += 12.0 * (na + nb + ne + nt + kept(i)) + 8.0 * n1 * operands;
+        } else {
+            // coefficient sum: every stored term matrix read once, the sum written once
+            double in = 0.0;
+            for (int src : r.term_src) in += (src < 0) ? za : kept(src);
+            bytes += 12.0 * (in + kept(i)) + 8.0 * n1 * (double)(r.term_src.size() + 1);
         }
         if (!p->ring.empty()) {
             // average over the evaluations still held in the event ring
@@ -696,10 +737,8 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
             }
             const double avg = held > 0 ? sum / (double)held : 0.0;
             st->stage_ms[i] = avg;
-            if (r.kind == FPS_STAGE_POWER || r.kind == FPS_STAGE_HORNER) {
-                ms_total += avg;
-                launches++;
-            }
+            ms_total += avg;
+            launches++;
         }
     }
     st->bytes_algorithmic = bytes;
@@ -817,6 +856,7 @@ fps_status fps_axpy(fps_matrix* out, int64_t n, int32_t nterms, const double* co
             a.T.col[t] = nullptr;
             a.T.val[t] = nullptr;
             a.T.span[t] = nullptr;
+            a.T.amax[t] = nullptr;
             continue;
         }
         int2* sp = reinterpret_cast<int2*>(static_cast<char*>(info.p) + t * per);
@@ -827,6 +867,7 @@ fps_status fps_axpy(fps_matrix* out, int64_t n, int32_t nterms, const double* co
         a.T.col[t] = terms[t].col;
         a.T.val[t] = terms[t].val;
         a.T.span[t] = sp;
+        a.T.amax[t] = am;
     }
     HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(eng.ws.counters.p), sizeof(StageCounters) / 8, 0ull, s));
     SlackMatrix res;

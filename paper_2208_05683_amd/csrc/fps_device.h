@@ -33,6 +33,7 @@ struct Terms {
     const int32_t* col[kMaxTerms];
     const double* val[kMaxTerms];
     const int2* span[kMaxTerms];
+    const double* amax[kMaxTerms];
 };
 
 // Output of a stage in slack layout: row r may use [off[r], off[r+1]) and
@@ -69,9 +70,17 @@ constexpr unsigned long long kErrNeedsGlobal = 8;          // a row needed the g
 
 enum StageMode : int32_t { kModeProduct = 0, kModeSum = 1 };
 
+// A stage computes, for every row r,
+//     out_r = D_tau( extra_r + main_r )
+// where main_r accumulates the terms of the stage (products A_rk B_k,: in
+// product mode, c_t M_t[r,:] in coefficient-sum mode) and extra_r is either
+// row r of E (has_e) or, in product mode with has_blk, the coefficient sum
+// over T accumulated on its own (a coefficient block fused into a Horner
+// step); without extra, out_r = D_tau(main_r).
 struct StageArgs {
     int32_t mode;
     int32_t has_e;
+    int32_t has_blk;
     int64_t n;
     double tau;
     double skip_tau;  // rows whose bound is below this are empty (0 disables the test)
@@ -83,6 +92,8 @@ struct StageArgs {
     int64_t* ub;  // upper bound of the row's stored entries (scanned in place into OutView::off)
     OutView out;
     StageCounters* ctr;
+    const int32_t* dummy_col;  // 128 zeroed entries read by inactive lanes
+    const double* dummy_val;
     unsigned long long* part;  // this stage's partial sums
     int64_t part_stride;
     int64_t* fb_list;       // n entries
@@ -90,6 +101,9 @@ struct StageArgs {
     int64_t g_slot_words;   // bitmap words per slot
     int64_t g_slot_cap;     // accumulator entries per slot
     int64_t g_slot_stride;  // 4-byte units between slots (multiple of 64)
+    int64_t g_off_acc;      // 4-byte offsets of the slot's arrays: bytes at 0, then bitmap words (uint2),
+    int64_t g_off_ebuf;     //   then accumulator, parked extra values and column list
+    int64_t g_off_cols;
     int32_t g_slots;
     int32_t force_global;
     int32_t global_planned;  // 0: the global-memory kernel will not run for this stage

@@ -212,6 +212,25 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
                 emax = P.E.amax[r];
             }
         }
+        if (P.has_blk) {  // fused coefficient block: |block entries| <= sum_t |c_t| max|M_t[r,:]|
+            for (int t = 0; t < P.T.n; ++t) {
+                if (P.T.beg[t] == nullptr) {
+                    lo = min(lo, (int32_t)r);
+                    hi = max(hi, (int32_t)r);
+                    elen += 1;
+                    emax += fabs(P.T.coef[t]);
+                } else {
+                    const int64_t len = P.T.end[t][r] - P.T.beg[t][r];
+                    if (len > 0) {
+                        const int2 sp = P.T.span[t][r];
+                        lo = min(lo, sp.x);
+                        hi = max(hi, sp.y);
+                        elen += len;
+                        emax += fabs(P.T.coef[t]) * P.T.amax[t][r];
+                    }
+                }
+            }
+        }
         if (gl == 0) {
             const bool empty = (prod == 0 && elen == 0);
             const bool skip = !empty && P.skip_tau > 0.0 && (emax + bnd) < P.skip_tau;
@@ -224,11 +243,13 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
             P.W[r] = W;
             P.lo[r] = lo;
             P.ub[r] = ub;
+            // products counted as multiply-adds: the B rows plus, when fused, the block terms
+            const int64_t work = prod + (P.has_blk ? elen : 0);
             if (skip) {
-                prod_skip = (unsigned long long)prod;
+                prod_skip = (unsigned long long)work;
                 row_skip = 1;
             } else {
-                prod_done = (unsigned long long)prod;
+                prod_done = (unsigned long long)work;
             }
         }
     }
@@ -347,131 +368,367 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const int64_t* __restrict
 // Numeric stage.
 // ---------------------------------------------------------------------------
 struct WaveStage {
-    int32_t excl[kWave];  // exclusive prefix of term lengths in the current chunk
+    int32_t excl[kWave];  // exclusive prefix of the term row lengths in the current chunk
+    int32_t len[kWave];   // row length of each term
     int64_t beg[kWave];   // first entry of the term's row (-1: identity row)
     double a[kWave];      // term weight
 };
 
 struct LdsWave {
-    uint32_t bm[kLdsWords];
-    uint32_t pre[kLdsWords];
+    uint2 bmp[kLdsWords];  // per 32 window columns: .x structure bits, .y set bits in earlier words
     double acc[kLdsCap];
     int32_t cols[kLdsCap];
     WaveStage st;
 };
 
-__device__ __forceinline__ uint32_t rank_of(const uint32_t* bm, const uint32_t* pre, uint32_t d)
+constexpr int kParked = kLdsCap / kWave;  // parked values per lane (shared-memory kernel)
+constexpr int kU = 4;                     // flattened batch: kU sub-batches of 64 products
+constexpr int kStep = 2 * kWave;          // per-term step: 128 entries of one term row
+
+__device__ __forceinline__ uint32_t rank_of(const uint2* bmp, uint32_t d)
 {
-    const uint32_t w = d >> 5;
-    return pre[w] + (uint32_t)__popc(bm[w] & ((1u << (d & 31u)) - 1u));
+    const uint2 w = bmp[d >> 5];
+    return w.y + (uint32_t)__popc(w.x & ((1u << (d & 31u)) - 1u));
 }
 
-// One pass over the ordered terms of row r.  kAccum = false marks the
-// structure (bitmap in shared memory, byte map in device memory);
-// kAccum = true performs acc[rank(c)] = fma(a, v, acc[rank(c)]) with the
-// terms applied strictly in order: a chunk of 64 consecutive products is
-// loaded at once, and the read-modify-writes are issued one term at a time
-// (the products of one term have distinct columns, so they never collide).
-template <bool kAccum, bool kGlobal>
-__device__ __forceinline__ void term_pass(const StageArgs& P, int64_t r, int32_t lo, uint32_t W, uint8_t* bytes,
-                                          uint32_t* bm, const uint32_t* pre, double* acc, WaveStage& st)
+__device__ __forceinline__ int32_t sgpr(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t sgpr64(int64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double sgprd(double x) { return __longlong_as_double(sgpr64(__double_as_longlong(x))); }
+
+enum TermSource : int { kSrcProducts = 0, kSrcCoefs = 1 };
+
+// Terms of row r: entries [tb, te) of row r of A (products) or the
+// coefficient terms 0..T.n-1.
+__device__ __forceinline__ void term_range(const StageArgs& P, int src, int64_t r, int64_t* tb, int64_t* te)
+{
+    if (src == kSrcProducts) {
+        *tb = P.A.beg[r];
+        *te = P.A.end[r];
+    } else {
+        *tb = 0;
+        *te = P.T.n;
+    }
+}
+
+// Loads the next <= 64 terms starting at t0 into the staging area and
+// returns the number of products of the chunk.
+__device__ __forceinline__ int32_t load_chunk(const StageArgs& P, int src, int64_t r, int64_t t0, int64_t te,
+                                              WaveStage& st)
 {
     const int l = lane();
-    int64_t tb, te;
-    if (P.mode == kModeProduct) {
-        tb = P.A.beg[r];
-        te = P.A.end[r];
-    } else {
-        tb = 0;
-        te = P.T.n;
+    const int64_t t = t0 + l;
+    int32_t len = 0;
+    int64_t bb = 0;
+    double a = 0.0;
+    if (t < te) {
+        if (src == kSrcProducts) {
+            const int32_t k = P.A.col[t];
+            a = P.A.val[t];
+            bb = P.B.beg[k];
+            len = (int32_t)(P.B.end[k] - bb);
+        } else {
+            const int ti = (int)t;
+            a = P.T.coef[ti];
+            if (P.T.beg[ti] == nullptr) {
+                bb = -1;
+                len = 1;
+            } else {
+                bb = P.T.beg[ti][r];
+                len = (int32_t)(P.T.end[ti][r] - bb);
+            }
+        }
     }
-    for (int64_t t0 = tb; t0 < te; t0 += kWave) {
-        const int64_t t = t0 + l;
-        int32_t len = 0;
-        int64_t bb = 0;
-        double a = 0.0;
-        if (t < te) {
-            if (P.mode == kModeProduct) {
-                const int32_t k = P.A.col[t];
-                a = P.A.val[t];
-                bb = P.B.beg[k];
-                len = (int32_t)(P.B.end[k] - bb);
-            } else {
-                const int ti = (int)t;
-                a = P.T.coef[ti];
-                if (P.T.beg[ti] == nullptr) {
-                    bb = -1;
-                    len = 1;
-                } else {
-                    bb = P.T.beg[ti][r];
-                    len = (int32_t)(P.T.end[ti][r] - bb);
-                }
-            }
-        }
-        const int32_t inc = wave_incl_sum(len);
-        const int32_t total = __shfl(inc, kWave - 1, kWave);
-        st.excl[l] = inc - len;
-        st.beg[l] = bb;
-        st.a[l] = a;
-        wave_sync();
-        for (int32_t q0 = 0; q0 < total; q0 += kWave) {
-            const int32_t qq = q0 + l;
-            bool valid = qq < total;
-            int kidx = 0;
+    const int32_t inc = wave_incl_sum(len);
+    wave_sync();  // earlier readers of the staging area are done
+    st.excl[l] = inc - len;
+    st.len[l] = len;
+    st.beg[l] = bb;
+    st.a[l] = a;
+    wave_sync();
+    return __shfl(inc, kWave - 1, kWave);
+}
+
+// Largest term index i of the chunk with excl[i] <= q.
+__device__ __forceinline__ int find_term(const WaveStage& st, int32_t q)
+{
+    int k = 0;
 #pragma unroll
-            for (int step = 32; step >= 1; step >>= 1)
-                if (st.excl[kidx + step] <= qq) kidx += step;
-            int32_t c = 0;
-            double v = 0.0, av = 0.0;
-            if (valid) {
-                const int64_t b0 = st.beg[kidx];
-                const int32_t o = qq - st.excl[kidx];
-                av = st.a[kidx];
-                if (b0 < 0) {
-                    c = (int32_t)r;
-                    v = 1.0;
-                } else if (P.mode == kModeProduct) {
-                    c = P.B.col[b0 + o];
-                    v = P.B.val[b0 + o];
-                } else {
-                    const int ti = (int)(t0 + kidx);
-                    c = P.T.col[ti][b0 + o];
-                    v = P.T.val[ti][b0 + o];
-                }
-            }
-            const uint32_t d = (uint32_t)(c - lo);
-            if (valid && d >= W) {
-                flag_error(P, kErrColumnOutsideWindow);
-                valid = false;
-            }
-            if (!kAccum) {
-                if (valid) {
-                    if (kGlobal)
-                        bytes[d] = 1;
-                    else
-                        atomicOr(&bm[d >> 5], 1u << (d & 31u));
-                }
+    for (int step = 32; step >= 1; step >>= 1)
+        if (st.excl[k + step] <= q) k += step;
+    return k;
+}
+
+template <bool kGlobal>
+__device__ __forceinline__ void mark_d(uint32_t d, uint8_t* bytes, uint2* bmp)
+{
+    if (kGlobal)
+        bytes[d] = 1;
+    else
+        atomicOr(&bmp[d >> 5].x, 1u << (d & 31u));
+}
+
+// Window offset of a loaded column; out-of-window columns (impossible when
+// the row information is consistent) are recorded in `bad` and ignored.
+__device__ __forceinline__ uint32_t window_d(int32_t c, int32_t lo, uint32_t W, bool& ok, uint32_t& bad)
+{
+    const uint32_t d = (uint32_t)(c - lo);
+    const bool in = d < W;
+    bad |= (ok && !in) ? 1u : 0u;
+    ok = ok && in;
+    return ok ? d : 0u;
+}
+
+// ---- flattened batches (short term rows) ------------------------------------
+// Products q0 + j*64 + lane of the chunk.  Every lane issues its loads (lanes
+// without a product read a zeroed dummy row), so loads stay in flight until
+// the values are used.
+
+struct Batch {
+    int32_t c[kU];
+    double v[kU];
+    int kidx[kU];
+    bool ok[kU];
+};
+
+// Products only: coefficient terms always take the per-term path, whose term
+// index is uniform across the wavefront.
+template <bool kNeedV>
+__device__ __forceinline__ void gather(const StageArgs& P, const WaveStage& st, int32_t q0, int32_t total, Batch& b)
+{
+    const int l = lane();
+#pragma unroll
+    for (int j = 0; j < kU; ++j) {
+        const int32_t q = q0 + j * kWave + l;
+        b.ok[j] = q < total;
+        const int k = find_term(st, b.ok[j] ? q : total - 1);
+        b.kidx[j] = k;
+        const int64_t b0 = st.beg[k];
+        const int32_t* cp = P.dummy_col;
+        const double* vp = P.dummy_val;
+        int64_t e = l;
+        if (b.ok[j]) {
+            cp = P.B.col;
+            vp = P.B.val;
+            e = b0 + (q - st.excl[k]);
+        }
+        b.c[j] = cp[e];
+        b.v[j] = kNeedV ? vp[e] : 0.0;
+    }
+}
+
+template <bool kGlobal>
+__device__ __forceinline__ void mark_batch(int32_t lo, uint32_t W, Batch& b, uint8_t* bytes, uint2* bmp, uint32_t& bad)
+{
+#pragma unroll
+    for (int j = 0; j < kU; ++j) {
+        bool ok = b.ok[j];
+        const uint32_t d = window_d(b.c[j], lo, W, ok, bad);
+        if (ok) mark_d<kGlobal>(d, bytes, bmp);
+    }
+}
+
+// acc[rank] = fma(a, v, acc[rank]) in term order: each 64-product sub-batch
+// is applied one term at a time (the products of one term have distinct
+// columns, so a term's read-modify-writes never collide).
+__device__ __forceinline__ void accumulate_batch(const WaveStage& st, int32_t q0, int32_t total, int32_t lo, uint32_t W,
+                                                 Batch& b, const uint2* bmp, double* acc, uint32_t& bad)
+{
+#pragma unroll
+    for (int j = 0; j < kU; ++j) {
+        const int32_t qj = q0 + j * kWave;
+        if (qj >= total) break;
+        const double v = b.v[j];
+        bool ok = b.ok[j];
+        const uint32_t d = window_d(b.c[j], lo, W, ok, bad);
+        const uint32_t slot = rank_of(bmp, d);
+        const int last = min(kWave - 1, total - qj - 1);
+        const int kf = __builtin_amdgcn_readlane(b.kidx[j], 0);
+        const int kl = __builtin_amdgcn_readlane(b.kidx[j], last);
+        for (int kk = kf; kk <= kl; ++kk) {
+            if (ok && b.kidx[j] == kk) acc[slot] = fma(st.a[kk], v, acc[slot]);
+            wave_sync();
+        }
+    }
+}
+
+// ---- per-term groups (long term rows) ------------------------------------------
+// kGroup terms at a time: the first kStep entries of each of the group's rows
+// are loaded together (two per lane, clamped in-row indices, or a zeroed dummy
+// row), then the terms are applied one after the other.  Entries beyond kStep
+// (rows longer than 128) are handled right after their term's first part.
+
+constexpr int kGroup = 4;
+
+struct TermHead {
+    int32_t len;  // uniform
+    int64_t b0;   // uniform; < 0: identity row (coefficient terms) or no term
+    const int32_t* cp;
+    const double* vp;
+};
+
+template <int SRC>
+__device__ __forceinline__ TermHead term_head(const StageArgs& P, int64_t t0, const WaveStage& st, int i, int nterms)
+{
+    TermHead h{0, -1, P.dummy_col, P.dummy_val};
+    if (i < nterms) {
+        h.len = sgpr(st.len[i]);
+        h.b0 = sgpr64(st.beg[i]);
+        if (h.b0 >= 0 && h.len > 0) {
+            if (SRC == kSrcProducts) {
+                h.cp = P.B.col + h.b0;
+                h.vp = P.B.val + h.b0;
             } else {
-                const uint32_t slot = valid ? rank_of(bm, pre, d) : 0u;
-                const int kf = __shfl(kidx, 0, kWave);
-                const int last_lane = min(kWave - 1, total - q0 - 1);
-                const int kl = __shfl(kidx, last_lane, kWave);
-                for (int kk = kf; kk <= kl; ++kk) {
-                    if (valid && kidx == kk) acc[slot] = fma(av, v, acc[slot]);
-                    wave_sync();
-                }
+                h.cp = P.T.col[t0 + i] + h.b0;
+                h.vp = P.T.val[t0 + i] + h.b0;
             }
         }
+    }
+    return h;
+}
+
+template <bool kNeedV>
+__device__ __forceinline__ void load_part(const TermHead& h, int32_t e0, int32_t& c0, int32_t& c1, double& v0,
+                                          double& v1)
+{
+    const int l = lane();
+    // real rows: in-row index clamped to the last entry; otherwise the
+    // 128-entry dummy row at lane and lane + 64
+    const bool real = h.b0 >= 0 && h.len > 0;
+    const int32_t* cp = h.cp;
+    const double* vp = h.vp;
+    uint32_t i0 = (uint32_t)l, i1 = (uint32_t)(l + kWave);
+    if (real) {
+        const uint32_t last = (uint32_t)(h.len - 1);
+        i0 = min((uint32_t)(e0 + l), last);
+        i1 = min((uint32_t)(e0 + kWave + l), last);
+    }
+    c0 = cp[i0];
+    c1 = cp[i1];
+    if (kNeedV) {
+        v0 = vp[i0];
+        v1 = vp[i1];
+    } else {
+        v0 = v1 = 0.0;
+    }
+}
+
+template <int SRC, bool kAccum, bool kGlobal>
+__device__ __forceinline__ void use_part(const TermHead& h, int32_t e0, double a, int64_t r, int32_t lo, uint32_t W,
+                                         int32_t c0, int32_t c1, double v0, double v1, uint8_t* bytes, uint2* bmp,
+                                         double* acc, uint32_t& bad)
+{
+    const int l = lane();
+    bool ok0 = e0 + l < h.len, ok1 = e0 + kWave + l < h.len;
+    if (SRC == kSrcCoefs && h.b0 < 0) {  // identity row: the single entry (r, 1)
+        c0 = (int32_t)r;
+        v0 = 1.0;
+        ok1 = false;
+    }
+    const uint32_t d0 = window_d(c0, lo, W, ok0, bad);
+    const uint32_t d1 = window_d(c1, lo, W, ok1, bad);
+    if (!kAccum) {
+        if (ok0) mark_d<kGlobal>(d0, bytes, bmp);
+        if (ok1) mark_d<kGlobal>(d1, bytes, bmp);
+    } else {
+        // the two entries of a lane belong to one term: distinct columns, and
+        // no collision with any other lane
+        const uint32_t s0 = rank_of(bmp, d0);
+        const uint32_t s1 = rank_of(bmp, d1);
+        const double x0 = fma(a, v0, acc[s0]);
+        const double x1 = fma(a, v1, acc[s1]);
+        if (ok0) acc[s0] = x0;
+        if (ok1) acc[s1] = x1;
         wave_sync();
+    }
+}
+
+template <int SRC, bool kAccum, bool kGlobal>
+__device__ __forceinline__ void per_term_pass(const StageArgs& P, int64_t r, int64_t t0, int nterms,
+                                              const WaveStage& st, int32_t lo, uint32_t W, uint8_t* bytes,
+                                              uint2* bmp, double* acc, uint32_t& bad)
+{
+    for (int i0 = 0; i0 < nterms; i0 += kGroup) {
+        TermHead h[kGroup];
+        int32_t c0[kGroup], c1[kGroup];
+        double v0[kGroup], v1[kGroup];
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+            h[g] = term_head<SRC>(P, t0, st, i0 + g, nterms);
+            load_part<kAccum>(h[g], 0, c0[g], c1[g], v0[g], v1[g]);
+        }
+#pragma unroll
+        for (int g = 0; g < kGroup; ++g) {
+            if (h[g].len == 0) continue;
+            const double a = kAccum ? sgprd(st.a[i0 + g]) : 0.0;
+            use_part<SRC, kAccum, kGlobal>(h[g], 0, a, r, lo, W, c0[g], c1[g], v0[g], v1[g], bytes, bmp, acc, bad);
+            for (int32_t e0 = kStep; e0 < h[g].len; e0 += kStep) {
+                int32_t d0, d1;
+                double w0, w1;
+                load_part<kAccum>(h[g], e0, d0, d1, w0, w1);
+                use_part<SRC, kAccum, kGlobal>(h[g], e0, a, r, lo, W, d0, d1, w0, w1, bytes, bmp, acc, bad);
+            }
+        }
+    }
+}
+
+// Long term rows go step by step, short ones in flattened batches
+// (coefficient terms always step by step).
+__device__ __forceinline__ bool use_per_term(int src, int32_t total, int nterms)
+{
+    return src == kSrcCoefs || total >= 16 * nterms;
+}
+
+// One pass over all terms of a source.  kAccum = false marks the structure,
+// kAccum = true accumulates in term order.  If `first_loaded`, the staging
+// area already holds the chunk at tb with `total0` products.
+template <bool kAccum, bool kGlobal>
+__device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t r, int32_t lo, uint32_t W,
+                                           uint8_t* bytes, uint2* bmp, double* acc, WaveStage& st, bool first_loaded,
+                                           int32_t total0, uint32_t& bad)
+{
+    int64_t tb, te;
+    term_range(P, src, r, &tb, &te);
+    for (int64_t t0 = tb; t0 < te; t0 += kWave) {
+        const int32_t total = (first_loaded && t0 == tb) ? total0 : load_chunk(P, src, r, t0, te, st);
+        const int nterms = (int)min<int64_t>(kWave, te - t0);
+        if (use_per_term(src, total, nterms)) {
+            if (src == kSrcProducts)
+                per_term_pass<kSrcProducts, kAccum, kGlobal>(P, r, t0, nterms, st, lo, W, bytes, bmp, acc, bad);
+            else
+                per_term_pass<kSrcCoefs, kAccum, kGlobal>(P, r, t0, nterms, st, lo, W, bytes, bmp, acc, bad);
+        } else {
+            for (int32_t q0 = 0; q0 < total; q0 += kWave * kU) {
+                Batch b;
+                gather<kAccum>(P, st, q0, total, b);
+                if (kAccum)
+                    accumulate_batch(st, q0, total, lo, W, b, bmp, acc, bad);
+                else
+                    mark_batch<kGlobal>(lo, W, b, bytes, bmp, bad);
+            }
+        }
     }
 }
 
 // Computes output row r.  Returns false (with nothing written) if the row
 // needs more workspace than max_words / cap provide.
+//
+// Phases: structure bitmap of the row's column window; prefix counts so that
+// rank(column) is the column's slot in a dense accumulator kept in column
+// order; the main terms accumulated in order and parked (registers in the
+// shared-memory kernel, `ebuf` in the device-memory kernel); the extra part
+// (fused block terms or E) accumulated on its own; x = extra + main; the drop
+// test and a sorted, coalesced write-out.  Rows whose main terms fit one
+// flattened batch keep their products in registers from the structure pass to
+// the accumulation.
 template <bool kGlobal>
-__device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8_t* bytes, uint32_t* bm,
-                                            uint32_t* pre, double* acc, int32_t* cols, WaveStage& st,
-                                            int64_t max_words, int64_t cap, int64_t* kept_out)
+__device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8_t* bytes, uint2* bmp, double* acc,
+                                            int32_t* cols, double* ebuf, WaveStage& st, int64_t max_words,
+                                            int64_t cap, int64_t* kept_out)
 {
     const int l = lane();
     *kept_out = 0;
@@ -488,28 +745,41 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
     const int32_t lo = P.lo[r];
     const int64_t words = ((int64_t)W + 31) >> 5;
     if (words > max_words) return false;
+    const int main_src = (P.mode == kModeProduct) ? kSrcProducts : kSrcCoefs;
+    const bool has_extra = P.has_e || P.has_blk;
+    uint32_t bad = 0;
 
-    // 1. structure of the row inside its window
+    // 1. structure of the row inside its window (extra part first, main last,
+    //    so that the staging area ends up holding the main terms)
     if (kGlobal) {
         uint32_t* b4 = reinterpret_cast<uint32_t*>(bytes);
         for (int64_t i = l; i < words * 8; i += kWave) b4[i] = 0u;
     } else {
-        for (int64_t w = l; w < words; w += kWave) bm[w] = 0u;
+        for (int64_t w = l; w < words; w += kWave) bmp[w].x = 0u;
     }
     wave_sync();
-    term_pass<false, kGlobal>(P, r, lo, (uint32_t)W, bytes, bm, pre, acc, st);
+    if (P.has_blk)
+        terms_pass<false, kGlobal>(P, kSrcCoefs, r, lo, (uint32_t)W, bytes, bmp, nullptr, st, false, 0, bad);
     if (P.has_e) {
         for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave) {
-            const uint32_t d = (uint32_t)(P.E.col[p] - lo);
-            if (d >= (uint32_t)W) {
-                flag_error(P, kErrColumnOutsideWindow);
-                continue;
-            }
-            if (kGlobal)
-                bytes[d] = 1;
-            else
-                atomicOr(&bm[d >> 5], 1u << (d & 31u));
+            bool ok = true;
+            const uint32_t d = window_d(P.E.col[p], lo, (uint32_t)W, ok, bad);
+            if (ok) mark_d<kGlobal>(d, bytes, bmp);
         }
+    }
+    int64_t tb, te;
+    term_range(P, main_src, r, &tb, &te);
+    const int32_t total0 = load_chunk(P, main_src, r, tb, te, st);
+    const bool one_chunk = (te - tb <= kWave);
+    const bool single = one_chunk && (total0 <= kWave * kU) && !use_per_term(main_src, total0, (int)(te - tb));
+    Batch b1;
+    if (single) {
+        if (total0 > 0) {
+            gather<true>(P, st, 0, total0, b1);
+            mark_batch<kGlobal>(lo, (uint32_t)W, b1, bytes, bmp, bad);
+        }
+    } else {
+        terms_pass<false, kGlobal>(P, main_src, r, lo, (uint32_t)W, bytes, bmp, nullptr, st, true, total0, bad);
     }
     wave_sync();
     if (kGlobal) {  // pack the byte map into bits
@@ -521,7 +791,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
                 const uint32_t v = b4[w * 8 + j];
                 bits |= ((v & 1u) | ((v >> 7) & 2u) | ((v >> 14) & 4u) | ((v >> 21) & 8u)) << (4 * j);
             }
-            bm[w] = bits;
+            bmp[w].x = bits;
         }
         wave_sync();
     }
@@ -530,9 +800,9 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
     uint32_t running = 0;
     for (int64_t w0 = 0; w0 < words; w0 += kWave) {
         const int64_t w = w0 + l;
-        const uint32_t cnt = (w < words) ? (uint32_t)__popc(bm[w]) : 0u;
+        const uint32_t cnt = (w < words) ? (uint32_t)__popc(bmp[w].x) : 0u;
         const uint32_t inc = wave_incl_sum(cnt);
-        if (w < words) pre[w] = running + inc - cnt;
+        if (w < words) bmp[w].y = running + inc - cnt;
         running += __shfl(inc, kWave - 1, kWave);
     }
     const int64_t ns = running;
@@ -550,39 +820,67 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
     // 3. zero the accumulator, list the columns in slot order
     for (int64_t i = l; i < ns; i += kWave) acc[i] = 0.0;
     for (int64_t w = l; w < words; w += kWave) {
-        uint32_t bits = bm[w];
-        uint32_t base = pre[w];
+        const uint2 wd = bmp[w];
+        uint32_t bits = wd.x;
+        uint32_t base = wd.y;
         while (bits) {
-            const int b = __ffs((int)bits) - 1;
-            cols[base++] = lo + (int32_t)(w * 32 + b);
+            const int bt = __ffs((int)bits) - 1;
+            cols[base++] = lo + (int32_t)(w * 32 + bt);
             bits &= bits - 1u;
         }
     }
     wave_sync();
 
-    // 4. ordered accumulation, then the extra row enters with one addition
-    term_pass<true, kGlobal>(P, r, lo, (uint32_t)W, bytes, bm, pre, acc, st);
-    if (P.has_e) {
-        for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave) {
-            const uint32_t d = (uint32_t)(P.E.col[p] - lo);
-            if (d >= (uint32_t)W) continue;
-            const uint32_t slot = rank_of(bm, pre, d);
-            acc[slot] = P.E.val[p] + acc[slot];
+    // 4. main terms in order, parked; then the extra part on its own
+    if (single) {
+        if (total0 > 0) accumulate_batch(st, 0, total0, lo, (uint32_t)W, b1, bmp, acc, bad);
+    } else {
+        terms_pass<true, kGlobal>(P, main_src, r, lo, (uint32_t)W, nullptr, bmp, acc, st, one_chunk, total0, bad);
+    }
+    wave_sync();
+    double preg[kParked];
+#pragma unroll
+    for (int t = 0; t < kParked; ++t) preg[t] = 0.0;
+    if (has_extra) {
+        if (kGlobal) {
+            for (int64_t i = l; i < ns; i += kWave) {
+                ebuf[i] = acc[i];
+                acc[i] = 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < kParked; ++t) {
+                const int64_t i = (int64_t)t * kWave + l;
+                if (i < ns) {
+                    preg[t] = acc[i];
+                    acc[i] = 0.0;
+                }
+            }
+        }
+        wave_sync();
+        if (P.has_blk)
+            terms_pass<true, kGlobal>(P, kSrcCoefs, r, lo, (uint32_t)W, nullptr, bmp, acc, st, false, 0, bad);
+        if (P.has_e) {
+            for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave) {
+                bool ok = true;
+                const uint32_t d = window_d(P.E.col[p], lo, (uint32_t)W, ok, bad);
+                if (ok) acc[rank_of(bmp, d)] = P.E.val[p];
+            }
         }
         wave_sync();
     }
+    if (__ballot(bad != 0u)) flag_error(P, kErrColumnOutsideWindow);
 
-    // 5. drop test and sorted write-out
+    // 5. x = extra + main, drop test, sorted write-out
     int64_t kept = 0;
     double amx = 0.0;
     int32_t first = INT_MAX, last = -1;
-    for (int64_t i0 = 0; i0 < ns; i0 += kWave) {
-        const int64_t i = i0 + l;
+    auto emit = [&](int64_t i, double parked) {
         double x = 0.0;
         int32_t c = 0;
         bool keep = false;
         if (i < ns) {
-            x = acc[i];
+            x = has_extra ? acc[i] + parked : acc[i];
             c = cols[i];
             keep = (x != 0.0) && !(fabs(x) < P.tau);
         }
@@ -596,6 +894,16 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
             last = max(last, c);
         }
         kept += __popcll(m);
+    };
+    if (kGlobal) {
+        for (int64_t i0 = 0; i0 < ns; i0 += kWave) {
+            const int64_t i = i0 + l;
+            emit(i, (has_extra && i < ns) ? ebuf[i] : 0.0);
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < kParked; ++t)
+            if ((int64_t)t * kWave < ns) emit((int64_t)t * kWave + l, preg[t]);
     }
     amx = group_max<kWave>(amx);
     first = group_min<kWave>(first);
@@ -624,7 +932,7 @@ __global__ void __launch_bounds__(kBlock) k_numeric_lds(StageArgs P)
     if (r < P.n) {
         bool done = false;
         if (!P.force_global)
-            done = process_row<false>(P, r, nullptr, me.bm, me.pre, me.acc, me.cols, me.st, kLdsWords, kLdsCap,
+            done = process_row<false>(P, r, nullptr, me.bmp, me.acc, me.cols, nullptr, me.st, kLdsWords, kLdsCap,
                                       &kept);
         if (!done && l == 0) {
             const unsigned long long i = atomicAdd(&P.ctr->fb_count, 1ull);
@@ -641,6 +949,8 @@ __global__ void __launch_bounds__(kBlock) k_numeric_lds(StageArgs P)
     }
 }
 
+// Rows that did not fit the shared-memory workspace: per-wave workspace in
+// device memory sized for a full row, rows fetched from the fallback list.
 __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
 {
     __shared__ WaveStage st[kWavesPerBlock];
@@ -648,15 +958,12 @@ __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
     const int l = lane();
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wv;
     if (slot >= P.g_slots) return;
-    // per-slot layout (4-byte units): bytes[words*8] | bm[words] | pre[words] | acc[2*cap] | cols[cap]
-    const int64_t words = P.g_slot_words;
-    const int64_t cap = P.g_slot_cap;
     uint32_t* base = P.g_scratch + slot * P.g_slot_stride;
     uint8_t* bytes = reinterpret_cast<uint8_t*>(base);
-    uint32_t* bm = base + words * 8;
-    uint32_t* pre = bm + words;
-    double* acc = reinterpret_cast<double*>(pre + words);
-    int32_t* cols = reinterpret_cast<int32_t*>(acc + cap);
+    uint2* bmp = reinterpret_cast<uint2*>(base + P.g_slot_words * 8);
+    double* acc = reinterpret_cast<double*>(base + P.g_off_acc);
+    double* ebuf = reinterpret_cast<double*>(base + P.g_off_ebuf);
+    int32_t* cols = reinterpret_cast<int32_t*>(base + P.g_off_cols);
     const unsigned long long count = __hip_atomic_load(&P.ctr->fb_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned long long kept = 0;
     while (true) {
@@ -666,7 +973,8 @@ __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
         if (i >= count) break;
         const int64_t r = P.fb_list[i];
         int64_t k = 0;
-        if (!process_row<true>(P, r, bytes, bm, pre, acc, cols, st[wv], words, cap, &k)) flag_error(P, kErrCapacity);
+        if (!process_row<true>(P, r, bytes, bmp, acc, cols, ebuf, st[wv], P.g_slot_words, P.g_slot_cap, &k))
+            flag_error(P, kErrCapacity);
         kept += (unsigned long long)k;
     }
     if (l == 0 && kept) atomicAdd(&P.ctr->kept_global, kept);

@@ -150,7 +150,7 @@ def test_flags_do_not_change_results():
         if flags == B.FPS_FLAG_FORCE_GLOBAL:
             assert gst["rows_global"] > 0
         if flags == B.FPS_FLAG_TIMING:
-            assert gst["numeric_ms"] > 0 and gst["numeric_launches"] == gst["n_spgemm"]
+            assert gst["numeric_ms"] > 0 and gst["numeric_launches"] == gst["n_stages"]
 
 
 def test_result_within_eq23_bound():
