@@ -21,6 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+KERNEL_SRC = os.path.join(ROOT, "paper_2208_05683_amd", "csrc", "fps_kernels.hip")
 
 
 def log(*a):
@@ -35,6 +36,27 @@ def workload(name):
     if name == "lap1d":
         return G.config1()
     raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_source_sha256() -> str:
+    import hashlib
+
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(workload_name: str):
+    """HBM bytes per launch of the numeric kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None if there is none or the kernel
+    source changed since it was taken."""
+    p = os.path.join(ROOT, "profiles", f"traffic_k_numeric_lds_{workload_name}.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("source_sha256") != kernel_source_sha256():
+        return None
+    return d.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(cfg, budget_s: float):
@@ -64,6 +86,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="lap2d")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle timing (0 skips)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -80,6 +104,14 @@ def main():
     log(f"workload {cfg['name']}: n={Z.n} nnz={Z.nnz}")
     Zd = api.to_device(Z.row_ptr, Z.col, Z.val)
     stream = torch.cuda.current_stream()
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_mib} MiB device to device")
+        del src, dst
     plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"], flags=B.FPS_FLAG_TIMING)
 
     for i in range(args.warmup):
@@ -125,7 +157,9 @@ def main():
         "config": {"workload": cfg["name"], "n": Z.n, "nnz_Z": Z.nnz, "m": cfg["m"], "s": cfg["s"],
                    "tau": cfg["tau"], "series": "exp", "nnz_F": st["nnz_out"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg["name"]),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes_per_launch": bytes_eval / launches if launches else None,
                      "kernel": "k_numeric_lds",
                      "launches_per_step": launches,
                      "avg_launch_ms": kern_ms / launches if launches else None,
