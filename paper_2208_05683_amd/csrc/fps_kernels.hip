@@ -367,17 +367,20 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const int64_t* __restrict
 // ---------------------------------------------------------------------------
 // Numeric stage.
 // ---------------------------------------------------------------------------
+constexpr int kChunk = 32;  // terms staged at a time
+
 struct WaveStage {
-    int32_t excl[kWave];  // exclusive prefix of the term row lengths in the current chunk
-    int32_t len[kWave];   // row length of each term
-    int64_t beg[kWave];   // first entry of the term's row (-1: identity row)
-    double a[kWave];      // term weight
+    int32_t excl[kChunk];  // exclusive prefix of the term row lengths in the current chunk
+    int32_t len[kChunk];   // row length of each term
+    int64_t beg[kChunk];   // first entry of the term's row (-1: identity row)
+    double a[kChunk];      // term weight
 };
 
+// The structural column list of a row is kept in the row's own output slot
+// (P.out.col[off..off+ns)), which the write-out then compacts in place.
 struct LdsWave {
     uint2 bmp[kLdsWords];  // per 32 window columns: .x structure bits, .y set bits in earlier words
     double acc[kLdsCap];
-    int32_t cols[kLdsCap];
     WaveStage st;
 };
 
@@ -415,7 +418,7 @@ __device__ __forceinline__ void term_range(const StageArgs& P, int src, int64_t 
     }
 }
 
-// Loads the next <= 64 terms starting at t0 into the staging area and
+// Loads the next <= kChunk terms starting at t0 into the staging area and
 // returns the number of products of the chunk.
 __device__ __forceinline__ int32_t load_chunk(const StageArgs& P, int src, int64_t r, int64_t t0, int64_t te,
                                               WaveStage& st)
@@ -425,7 +428,7 @@ __device__ __forceinline__ int32_t load_chunk(const StageArgs& P, int src, int64
     int32_t len = 0;
     int64_t bb = 0;
     double a = 0.0;
-    if (t < te) {
+    if (l < kChunk && t < te) {
         if (src == kSrcProducts) {
             const int32_t k = P.A.col[t];
             a = P.A.val[t];
@@ -445,10 +448,12 @@ __device__ __forceinline__ int32_t load_chunk(const StageArgs& P, int src, int64
     }
     const int32_t inc = wave_incl_sum(len);
     wave_sync();  // earlier readers of the staging area are done
-    st.excl[l] = inc - len;
-    st.len[l] = len;
-    st.beg[l] = bb;
-    st.a[l] = a;
+    if (l < kChunk) {
+        st.excl[l] = inc - len;
+        st.len[l] = len;
+        st.beg[l] = bb;
+        st.a[l] = a;
+    }
     wave_sync();
     return __shfl(inc, kWave - 1, kWave);
 }
@@ -458,7 +463,7 @@ __device__ __forceinline__ int find_term(const WaveStage& st, int32_t q)
 {
     int k = 0;
 #pragma unroll
-    for (int step = 32; step >= 1; step >>= 1)
+    for (int step = kChunk / 2; step >= 1; step >>= 1)
         if (st.excl[k + step] <= q) k += step;
     return k;
 }
@@ -693,9 +698,9 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
 {
     int64_t tb, te;
     term_range(P, src, r, &tb, &te);
-    for (int64_t t0 = tb; t0 < te; t0 += kWave) {
+    for (int64_t t0 = tb; t0 < te; t0 += kChunk) {
         const int32_t total = (first_loaded && t0 == tb) ? total0 : load_chunk(P, src, r, t0, te, st);
-        const int nterms = (int)min<int64_t>(kWave, te - t0);
+        const int nterms = (int)min<int64_t>(kChunk, te - t0);
         if (use_per_term(src, total, nterms)) {
             if (src == kSrcProducts)
                 per_term_pass<kSrcProducts, kAccum, kGlobal>(P, r, t0, nterms, st, lo, W, bytes, bmp, acc, bad);
@@ -727,8 +732,8 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
 // the accumulation.
 template <bool kGlobal>
 __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8_t* bytes, uint2* bmp, double* acc,
-                                            int32_t* cols, double* ebuf, WaveStage& st, int64_t max_words,
-                                            int64_t cap, int64_t* kept_out)
+                                            double* ebuf, WaveStage& st, int64_t max_words, int64_t cap,
+                                            int64_t* kept_out)
 {
     const int l = lane();
     *kept_out = 0;
@@ -770,7 +775,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
     int64_t tb, te;
     term_range(P, main_src, r, &tb, &te);
     const int32_t total0 = load_chunk(P, main_src, r, tb, te, st);
-    const bool one_chunk = (te - tb <= kWave);
+    const bool one_chunk = (te - tb <= kChunk);
     const bool single = one_chunk && (total0 <= kWave * kU) && !use_per_term(main_src, total0, (int)(te - tb));
     Batch b1;
     if (single) {
@@ -817,7 +822,9 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
         return true;
     }
 
-    // 3. zero the accumulator, list the columns in slot order
+    // 3. zero the accumulator, list the columns in slot order (in the row's
+    //    output slot, compacted in place by the write-out)
+    int32_t* cols = P.out.col + o;
     for (int64_t i = l; i < ns; i += kWave) acc[i] = 0.0;
     for (int64_t w = l; w < words; w += kWave) {
         const uint2 wd = bmp[w];
@@ -871,7 +878,10 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
     }
     if (__ballot(bad != 0u)) flag_error(P, kErrColumnOutsideWindow);
 
-    // 5. x = extra + main, drop test, sorted write-out
+    // 5. x = extra + main, drop test, sorted write-out.  Entry i moves to
+    //    position kept-before-i <= i of the same slot: a batch reads its
+    //    columns before any of its writes (they depend on the loaded values)
+    //    and writes only below the next batch's reads.
     int64_t kept = 0;
     double amx = 0.0;
     int32_t first = INT_MAX, last = -1;
@@ -932,8 +942,7 @@ __global__ void __launch_bounds__(kBlock) k_numeric_lds(StageArgs P)
     if (r < P.n) {
         bool done = false;
         if (!P.force_global)
-            done = process_row<false>(P, r, nullptr, me.bmp, me.acc, me.cols, nullptr, me.st, kLdsWords, kLdsCap,
-                                      &kept);
+            done = process_row<false>(P, r, nullptr, me.bmp, me.acc, nullptr, me.st, kLdsWords, kLdsCap, &kept);
         if (!done && l == 0) {
             const unsigned long long i = atomicAdd(&P.ctr->fb_count, 1ull);
             P.fb_list[i] = r;
@@ -963,7 +972,6 @@ __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
     uint2* bmp = reinterpret_cast<uint2*>(base + P.g_slot_words * 8);
     double* acc = reinterpret_cast<double*>(base + P.g_off_acc);
     double* ebuf = reinterpret_cast<double*>(base + P.g_off_ebuf);
-    int32_t* cols = reinterpret_cast<int32_t*>(base + P.g_off_cols);
     const unsigned long long count = __hip_atomic_load(&P.ctr->fb_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned long long kept = 0;
     while (true) {
@@ -973,7 +981,7 @@ __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
         if (i >= count) break;
         const int64_t r = P.fb_list[i];
         int64_t k = 0;
-        if (!process_row<true>(P, r, bytes, bmp, acc, cols, ebuf, st[wv], P.g_slot_words, P.g_slot_cap, &k))
+        if (!process_row<true>(P, r, bytes, bmp, acc, ebuf, st[wv], P.g_slot_words, P.g_slot_cap, &k))
             flag_error(P, kErrCapacity);
         kept += (unsigned long long)k;
     }
