@@ -27,5 +27,8 @@ from .oracle import (  # noqa: F401
     spgemm,
     unfiltered_ps,
     lib_path,
+    alg1_filter,
+    fnt_thresholds,
+    filtered_ps_adaptive,
 )
 from .bound import filtering_bound, power_norms  # noqa: F401

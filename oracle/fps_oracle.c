@@ -523,3 +523,221 @@ int orc_dense_horner_ld(int64_t n, const double *Zd, const double *c, int m, lon
     free(Zl);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* Adaptive filter (Algorithm 1) and the thresholds of eqs. 21-28       */
+/* ------------------------------------------------------------------ */
+
+/*
+ * 1-norm of the candidate matrix {entries with 0 < |x| <= t} of C, with the
+ * column sums taken exactly in integers: every |x| contributes
+ * ceil(|x| * 2^40 / eps_g), and the largest column sum is returned divided
+ * by the same scale.  This is an upper bound of the exact 1-norm (up to one
+ * rounding per entry) and does not depend on the summation order.
+ */
+static double candidate_norm1(const orc_csr *C, double t, double eps_g)
+{
+    const double s = ldexp(1.0, 40) / eps_g;
+    uint64_t *cs = calloc((size_t)(C->n > 0 ? C->n : 1), sizeof(uint64_t));
+    if (!cs) return INFINITY;
+    for (int64_t r = 0; r < C->n; ++r)
+        for (int64_t p = C->row_ptr[r]; p < C->row_ptr[r + 1]; ++p) {
+            const double a = fabs(C->val[p]);
+            if (a > 0.0 && a <= t) cs[C->col[p]] += (uint64_t)ceil(a * s);
+        }
+    uint64_t mx = 0;
+    for (int64_t c = 0; c < C->n; ++c)
+        if (cs[c] > mx) mx = cs[c];
+    free(cs);
+    return (double)mx / s;
+}
+
+typedef struct {
+    double eps_g;      /* filtering-norm threshold of this stage */
+    double threshold;  /* final entry threshold: entries with |x| <= threshold dropped */
+    double dropped;    /* 1-norm of the dropped entries (integer column sums, as above) */
+    int32_t iters;     /* Algorithm 1 iterations */
+    int32_t pad;
+} orc_alg1_stats;
+
+/*
+ * Algorithm 1 on C in place: eps_f = eps_g / m_i, candidates are the entries
+ * with |x| <= eps_f (the entries above it are "found" and protected), the
+ * candidate norm c_{i+1} and m_{i+1} = c_{i+1} / eps_f follow, until
+ * c <= eps_g (1 + e_r); the final candidates are dropped.  m_0 = 1; the
+ * sentinel c_0 = 1 is taken as "enter the loop" (at least one iteration).
+ * eps_g = +inf drops nothing (no bound applies).
+ */
+int orc_alg1_filter(orc_csr *C, double eps_g, double e_r, int max_iter, orc_alg1_stats *st)
+{
+    if (!C || !(eps_g > 0.0) || !(e_r >= 0.0) || max_iter < 1) return ORC_EINVAL;
+    orc_alg1_stats s0 = {eps_g, 0.0, 0.0, 0, 0};
+    if (isinf(eps_g)) {
+        if (st) *st = s0;
+        return ORC_OK;
+    }
+    const double target = eps_g * (1.0 + e_r);
+    double m = 1.0, t = 0.0, c = 0.0;
+    int it = 0;
+    do {
+        t = eps_g / m;
+        c = candidate_norm1(C, t, eps_g);
+        m = c / t;
+        ++it;
+    } while (c > target && it < max_iter);
+    if (c > target) return ORC_EINVAL; /* did not converge */
+    /* drop the candidates */
+    int64_t w = 0;
+    int64_t *rp = C->row_ptr;
+    int64_t start = 0;
+    for (int64_t r = 0; r < C->n; ++r) {
+        const int64_t b = start, e = rp[r + 1];
+        start = e;
+        rp[r] = w;
+        for (int64_t p = b; p < e; ++p) {
+            if (fabs(C->val[p]) <= t) continue;
+            C->col[w] = C->col[p];
+            C->val[w] = C->val[p];
+            ++w;
+        }
+    }
+    rp[C->n] = w;
+    C->nnz = w;
+    s0.threshold = t;
+    s0.dropped = c;
+    s0.iters = it;
+    if (st) *st = s0;
+    return ORC_OK;
+}
+
+/*
+ * Filtering-norm thresholds for the polynomial case (eq. 28): zeta_k for the
+ * powers k = 2..q and sigma_j for the Horner steps, from d_k (eq. 24),
+ * beta (eq. 21) and the norm bounds of eqs. 25-26.  z[t] >= ||Z^t|| for
+ * t = 0..q(b-1).  Sums run in ascending index order with separate
+ * multiplications and additions.  M = the number of filtered stages of the
+ * schedule (q + b - 2 - g when b >= 2).  A zero d_k is replaced by 1.
+ * zeta[0..q] (entries 0, 1 unused) and sigma[0..b-1] are written.
+ */
+int orc_fnt_thresholds(const double *coef, int m, int s, double eps, const double *z, double *zeta,
+                       double *sigma)
+{
+    int N, q, b, g, J, start, nsp;
+    if (orc_schedule(m, s, &N, &q, &b, &g, &J, &start, &nsp)) return ORC_EINVAL;
+#define A_(k) (((k) >= 0 && (k) <= m) ? fabs(coef[(k)]) : 0.0)
+    double *nb = calloc((size_t)b, sizeof(double));
+    double *ns = calloc((size_t)b, sizeof(double));
+    if (!nb || !ns) { free(nb); free(ns); return ORC_ENOMEM; }
+    for (int i = 0; i < b; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < q; ++j) acc = acc + A_(i * q + j) * z[j];
+        nb[i] = acc;
+    }
+    ns[0] = nb[b - 1];
+    for (int i = 1; i < b; ++i) ns[i] = nb[b - 1 - i] + z[q] * ns[i - 1];
+    const double M = (double)(nsp > 0 ? nsp : 1);
+    for (int k = 0; k <= q; ++k) zeta[k] = INFINITY;
+    for (int k = 2; k <= q; ++k) {
+        double d = 0.0;
+        for (int j = 0; j < b; ++j) {
+            const int i = b - 1 - j;
+            double beta = 0.0;
+            if (k < q)
+                for (int kk = k; kk < q; ++kk) beta = beta + A_(i * q + kk) * z[kk - k];
+            const double sprev = (j >= 1) ? ns[j - 1] : 0.0;
+            d = d + z[q * (b - 1 - j)] * (beta + z[q - k] * sprev);
+        }
+        if (d == 0.0) d = 1.0;
+        zeta[k] = eps / (d * M);
+    }
+    for (int j = 0; j < b; ++j) sigma[j] = eps / (z[q * (b - 1 - j)] * M);
+#undef A_
+    free(nb);
+    free(ns);
+    return ORC_OK;
+}
+
+/*
+ * Filtered PS with the adaptive filter (Algorithm 2 for a polynomial of
+ * known degree, eq. 28 thresholds): every sparse product is formed without
+ * filtering (exact zeros dropped) and then filtered by Algorithm 1 with
+ * eps_g = zeta_{j+1} (powers) or sigma_i (Horner steps).  Stage records as
+ * in orc_filtered_ps; alg1[] receives one record per filtered stage.
+ */
+int orc_filtered_ps_adaptive(const orc_csr *Z, const double *c, int m, int s, double eps, double e_r,
+                             const double *z, orc_csr *F, orc_stage_stats *stats, int max_stats, int *n_stats,
+                             orc_alg1_stats *alg1, int max_alg1, int *n_alg1, int nthreads)
+{
+    int N, q, b, g, J, start, nsp;
+    if (!Z || !c || !F || !z || !(eps > 0.0) || orc_schedule(m, s, &N, &q, &b, &g, &J, &start, &nsp))
+        return ORC_EINVAL;
+    if (q > 255) return ORC_EINVAL;
+    double *zeta = malloc((size_t)(q + 1) * sizeof(double));
+    double *sigma = malloc((size_t)(b + 1) * sizeof(double));
+    if (!zeta || !sigma) { free(zeta); free(sigma); return ORC_ENOMEM; }
+    int rc = orc_fnt_thresholds(c, m, s, eps, z, zeta, sigma);
+    const int64_t n = Z->n;
+    int ns = 0, na = 0;
+    orc_stage_stats st;
+    orc_alg1_stats a1;
+    orc_csr *P = calloc((size_t)(J + 2), sizeof(orc_csr));
+    const orc_csr **Pp = calloc((size_t)(J + 2), sizeof(orc_csr *));
+    if (!P || !Pp) rc = ORC_ENOMEM;
+    if (rc == ORC_OK) {
+        Pp[0] = NULL;
+        if (J >= 1) Pp[1] = Z;
+    }
+    for (int j = 1; j + 1 <= J && rc == ORC_OK; ++j) {
+        rc = orc_spgemm(Z, Pp[j], NULL, 0.0, &P[j + 1], &st, nthreads);
+        if (rc == ORC_OK) rc = orc_alg1_filter(&P[j + 1], zeta[j + 1], e_r, 200, &a1);
+        if (rc == ORC_OK) {
+            Pp[j + 1] = &P[j + 1];
+            st.nnz_kept = P[j + 1].nnz;
+            record(stats, max_stats, &ns, &st, 0, j + 1);
+            if (na < max_alg1) alg1[na] = a1;
+            na++;
+        }
+    }
+    orc_csr S = {0}, T = {0}, Bh = {0};
+    if (rc == ORC_OK && b == 1) {
+        rc = coefficient_block(Pp, c, m, q, 0, q - 1, n, &S, &st, nthreads);
+        if (rc == ORC_OK) record(stats, max_stats, &ns, &st, 1, 0);
+    } else if (rc == ORC_OK) {
+        if (g) {
+            rc = coefficient_block(Pp, c, m, q, b - 2, q, n, &S, &st, nthreads);
+            if (rc == ORC_OK) record(stats, max_stats, &ns, &st, 2, 1);
+        } else {
+            rc = coefficient_block(Pp, c, m, q, b - 1, q - 1, n, &S, &st, nthreads);
+            if (rc == ORC_OK) record(stats, max_stats, &ns, &st, 1, b - 1);
+        }
+        for (int i = start; i <= b - 1 && rc == ORC_OK; ++i) {
+            rc = coefficient_block(Pp, c, m, q, b - 1 - i, q - 1, n, &Bh, &st, nthreads);
+            if (rc != ORC_OK) break;
+            record(stats, max_stats, &ns, &st, 1, b - 1 - i);
+            rc = orc_spgemm(Pp[q], &S, &Bh, 0.0, &T, &st, nthreads);
+            orc_csr_free(&Bh);
+            if (rc == ORC_OK) rc = orc_alg1_filter(&T, sigma[i], e_r, 200, &a1);
+            if (rc != ORC_OK) break;
+            st.nnz_kept = T.nnz;
+            record(stats, max_stats, &ns, &st, 3, i);
+            if (na < max_alg1) alg1[na] = a1;
+            na++;
+            orc_csr_free(&S);
+            S = T;
+            memset(&T, 0, sizeof(T));
+        }
+    }
+    for (int j = 2; j <= J && P; ++j) orc_csr_free(&P[j]);
+    free(P);
+    free(Pp);
+    free(zeta);
+    free(sigma);
+    if (rc != ORC_OK) {
+        orc_csr_free(&S);
+        return rc;
+    }
+    *F = S;
+    if (n_stats) *n_stats = ns;
+    if (n_alg1) *n_alg1 = na;
+    return ORC_OK;
+}

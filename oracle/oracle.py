@@ -45,6 +45,16 @@ class _Stats(C.Structure):
     ]
 
 
+class _Alg1(C.Structure):
+    _fields_ = [
+        ("eps_g", C.c_double),
+        ("threshold", C.c_double),
+        ("dropped", C.c_double),
+        ("iters", C.c_int32),
+        ("pad", C.c_int32),
+    ]
+
+
 STAGE_KINDS = {0: "power", 1: "block", 2: "gstep", 3: "horner"}
 
 
@@ -76,6 +86,15 @@ def _load():
             lib.orc_dense_horner_ld.restype = C.c_int
             lib.orc_csr_free.argtypes = [P(_Csr)]
             lib.orc_csr_free.restype = None
+            lib.orc_alg1_filter.argtypes = [P(_Csr), C.c_double, C.c_double, C.c_int, P(_Alg1)]
+            lib.orc_alg1_filter.restype = C.c_int
+            lib.orc_fnt_thresholds.argtypes = [P(C.c_double), C.c_int, C.c_int, C.c_double, P(C.c_double),
+                                               P(C.c_double), P(C.c_double)]
+            lib.orc_fnt_thresholds.restype = C.c_int
+            lib.orc_filtered_ps_adaptive.argtypes = [P(_Csr), P(C.c_double), C.c_int, C.c_int, C.c_double,
+                                                     C.c_double, P(C.c_double), P(_Csr), P(_Stats), C.c_int,
+                                                     P(C.c_int), P(_Alg1), C.c_int, P(C.c_int), C.c_int]
+            lib.orc_filtered_ps_adaptive.restype = C.c_int
             _lib = lib
     return _lib
 
@@ -217,3 +236,66 @@ def fro_norm(M) -> float:
     if isinstance(M, np.ndarray):
         return float(np.sqrt(np.sum(np.abs(M) ** 2)))
     return float(np.sqrt(np.sum(M.val ** 2)))
+
+
+# ---------------------------------------------------------------------------
+# Adaptive filter (Algorithm 1) and the eq. 28 thresholds
+# ---------------------------------------------------------------------------
+
+def _alg1_dict(a: _Alg1) -> dict:
+    return {"eps_g": a.eps_g, "threshold": a.threshold, "dropped": a.dropped, "iters": a.iters}
+
+
+def alg1_filter(M, eps_g: float, e_r: float, max_iter: int = 200):
+    """Algorithm 1 on a copy of M: returns (filtered matrix, record)."""
+    lib = _load()
+    rp = np.array(M.row_ptr, dtype=np.int64)
+    cl = np.array(M.col, dtype=np.int32)
+    vl = np.array(M.val, dtype=np.float64)
+    s = _Csr()
+    s.n, s.nnz = int(M.n), int(rp[-1])
+    s.row_ptr = rp.ctypes.data_as(C.POINTER(C.c_int64))
+    s.col = cl.ctypes.data_as(C.POINTER(C.c_int32))
+    s.val = vl.ctypes.data_as(C.POINTER(C.c_double))
+    st = _Alg1()
+    _check(lib.orc_alg1_filter(C.byref(s), float(eps_g), float(e_r), int(max_iter), C.byref(st)), "alg1_filter")
+    nnz = int(s.nnz)
+    return CSR(int(M.n), rp.copy(), cl[:nnz].copy(), vl[:nnz].copy()), _alg1_dict(st)
+
+
+def fnt_thresholds(coeffs, m: int, s: int, eps: float, z):
+    """zeta_k (k = 0..q, entries < 2 unused) and sigma_j (j = 0..b-1) of eq. 28."""
+    lib = _load()
+    sc = schedule(m, s)
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    zz = np.ascontiguousarray(z, dtype=np.float64)
+    if zz.size < sc["q"] * (sc["b"] - 1) + 1 or zz.size < sc["q"] + 1:
+        raise ValueError("need z[t] for t = 0..max(q, q(b-1))")
+    zeta = np.zeros(sc["q"] + 1)
+    sigma = np.zeros(sc["b"] + 1)
+    _check(lib.orc_fnt_thresholds(c.ctypes.data_as(C.POINTER(C.c_double)), int(m), int(s), float(eps),
+                                  zz.ctypes.data_as(C.POINTER(C.c_double)),
+                                  zeta.ctypes.data_as(C.POINTER(C.c_double)),
+                                  sigma.ctypes.data_as(C.POINTER(C.c_double))), "fnt_thresholds")
+    return zeta, sigma[: sc["b"]]
+
+
+def filtered_ps_adaptive(Z, coeffs, m: int, s: int, eps: float, e_r: float, z, nthreads: int = 0):
+    """Filtered PS with Algorithm 1 and the eq. 28 thresholds.  Returns
+    (F, stage records, Algorithm 1 records of the filtered stages)."""
+    lib = _load()
+    keep = []
+    zv = _view(Z, keep)
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    zz = np.ascontiguousarray(z, dtype=np.float64)
+    max_stats = 4 * (m + 4) + 8
+    stats = (_Stats * max_stats)()
+    a1 = (_Alg1 * max_stats)()
+    ns, na = C.c_int(), C.c_int()
+    out = _Csr()
+    _check(lib.orc_filtered_ps_adaptive(C.byref(zv), c.ctypes.data_as(C.POINTER(C.c_double)), int(m), int(s),
+                                        float(eps), float(e_r), zz.ctypes.data_as(C.POINTER(C.c_double)),
+                                        C.byref(out), stats, max_stats, C.byref(ns), a1, max_stats, C.byref(na),
+                                        int(nthreads)), "filtered_ps_adaptive")
+    return (_take(out), [_stats_dict(stats[i]) for i in range(min(ns.value, max_stats))],
+            [_alg1_dict(a1[i]) for i in range(min(na.value, max_stats))])

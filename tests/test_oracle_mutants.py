@@ -32,7 +32,19 @@ MUTANTS = {
     "product_weight_dropped": ("w->acc[c] = fma(a, B->val[t], w->acc[c]);",
                                "w->acc[c] = fma(1.0, B->val[t], w->acc[c]);"),
     "dropped_norm_not_recorded": ("w->drop_colsum[c] += fabs(x);", "w->drop_colsum[c] += 0.0;"),
+    "alg1_candidate_tie": ("if (a > 0.0 && a <= t) cs[C->col[p]]", "if (a > 0.0 && a < t) cs[C->col[p]]"),
+    "alg1_drop_tie": ("if (fabs(C->val[p]) <= t) continue;", "if (fabs(C->val[p]) < t) continue;"),
+    "alg1_single_iteration": ("} while (c > target && it < max_iter);", "} while (0);"),
+    "alg1_threshold_update": ("        m = c / t;\n", "        m = c * t;\n"),
+    "fnt_wrong_power_norm": ("d = d + z[q * (b - 1 - j)] * (beta + z[q - k] * sprev);",
+                             "d = d + z[q * (b - 1 - j)] * (beta + z[q - k + 1] * sprev);"),
+    "fnt_budget_not_shared": ("zeta[k] = eps / (d * M);", "zeta[k] = eps / d;"),
+    "adaptive_horner_unfiltered": ("if (rc == ORC_OK) rc = orc_alg1_filter(&T, sigma[i], e_r, 200, &a1);",
+                                   "if (rc == ORC_OK) rc = orc_alg1_filter(&T, INFINITY, e_r, 200, &a1);"),
 }
+
+
+MULTI = {"shortcut_ignored", "horner_step_missing"}
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -50,7 +62,11 @@ def test_planted_mistake_is_caught(name, tmp_path):
                "            if (A->col[p] != r) continue;\n"
                "            const int64_t k = kk;\n"
                "            const double a = A->val[p];\n")
-    assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+    # the schedule logic appears in both drivers (fixed and adaptive filter); a
+    # mistake there is planted in every copy
+    assert src.count(old) >= 1, f"mutation anchor for {name} not found"
+    if name not in MULTI:
+        assert src.count(old) == 1, f"mutation anchor for {name} not unique"
     mut = tmp_path / "mut.c"
     mut.write_text(src.replace(old, new))
     lib = tmp_path / "libmut.so"

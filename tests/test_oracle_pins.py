@@ -426,3 +426,147 @@ def test_against_scipy_implementation(case):
     F, _ = O.filtered_ps(Z, c, m, s, tau)
     R = _scipy_filtered_ps(Z, c, m, s, tau).toarray()
     assert rel_fro(F.to_dense(), R) <= (1e-14 if tau == 0 else 1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Adaptive filter (Algorithm 1) and the eq. 28 thresholds
+# ---------------------------------------------------------------------------
+
+def _exact_col_norm1(M, mask):
+    """max over columns of the exactly rounded sum of |x| over masked entries."""
+    rows_cols = {}
+    for r in range(M.n):
+        for p in range(M.row_ptr[r], M.row_ptr[r + 1]):
+            if mask[p]:
+                rows_cols.setdefault(int(M.col[p]), []).append(abs(float(M.val[p])))
+    return max((math.fsum(v) for v in rows_cols.values()), default=0.0)
+
+
+def _dropped_mask(before, after):
+    kept = set()
+    for r in range(after.n):
+        for p in range(after.row_ptr[r], after.row_ptr[r + 1]):
+            kept.add((r, int(after.col[p])))
+    mask = np.zeros(before.nnz, dtype=bool)
+    for r in range(before.n):
+        for p in range(before.row_ptr[r], before.row_ptr[r + 1]):
+            mask[p] = (r, int(before.col[p])) not in kept
+    return mask
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_alg1_postconditions(seed):
+    rng = np.random.default_rng(40 + seed)
+    n = int(rng.integers(5, 60))
+    d = np.where(rng.random((n, n)) < 0.3, 10.0 ** rng.uniform(-16, -9, (n, n)), 0.0)
+    d *= np.where(rng.random((n, n)) < 0.5, -1.0, 1.0)
+    M = G.from_dense(d)
+    eps_g = float(10.0 ** rng.uniform(-13, -10))
+    e_r = 0.1
+    F, st = O.alg1_filter(M, eps_g, e_r)
+    check_canonical(F)
+    drop = _dropped_mask(M, F)
+    t = st["threshold"]
+    assert 0 < t <= eps_g
+    # exactly the entries with |x| <= t are dropped
+    np.testing.assert_array_equal(drop, np.abs(M.val) <= t)
+    # the dropped norm satisfies Algorithm 1's postcondition, and the reported
+    # (integer-summed) norm bounds the exact one from above
+    exact = _exact_col_norm1(M, drop)
+    assert exact <= eps_g * (1 + e_r)
+    assert exact <= st["dropped"] * (1 + 1e-12) + 1e-300
+    assert st["dropped"] <= eps_g * (1 + e_r)
+    # the loop did not stop earlier
+    if st["iters"] > 1:
+        with pytest.raises(RuntimeError):
+            O.alg1_filter(M, eps_g, e_r, max_iter=st["iters"] - 1)
+
+
+def test_alg1_closed_forms():
+    eps = 1e-10
+    # one column with 10 entries of 0.5 eps: the first candidate set has norm
+    # 5 eps > 1.1 eps, the next threshold eps / 5 protects every entry
+    d = np.zeros((12, 12))
+    d[:10, 3] = 0.5 * eps
+    d[11, 11] = 1.0
+    F, st = O.alg1_filter(G.from_dense(d), eps, 0.1)
+    assert st["iters"] == 2 and st["dropped"] == 0.0 and F.nnz == 11
+    assert abs(st["threshold"] - eps / 5) <= 1e-15 * eps
+    # geometric column eps 2^-i: norm < eps, all dropped in one iteration
+    d = np.zeros((25, 25))
+    d[:20, 0] = eps * 2.0 ** -np.arange(1, 21)
+    d[24, 24] = 1.0
+    F, st = O.alg1_filter(G.from_dense(d), eps, 0.1)
+    assert st["iters"] == 1 and F.nnz == 1
+    # a diagonal candidate matrix has norm max|x| <= eps: one iteration
+    F, st = O.alg1_filter(G.diagonal([0.3 * eps, 0.9 * eps, 2 * eps]), eps, 0.0)
+    assert st["iters"] == 1 and F.nnz == 1 and F.val[0] == 2 * eps
+    # ties: |x| == eps_f is a candidate (Algorithm 1 protects |x| > eps_f only)
+    F, st = O.alg1_filter(G.diagonal([eps, 1.0]), eps, 0.0)
+    assert F.nnz == 1
+    # ... also in the candidate norm: a column {eps, 0.2 eps} has norm 1.2 eps >
+    # 1.1 eps at eps_f = eps, so the next threshold eps/1.2 keeps the tie entry
+    d = np.zeros((3, 3))
+    d[0, 1], d[1, 1], d[2, 2] = eps, 0.2 * eps, 1.0
+    F, st = O.alg1_filter(G.from_dense(d), eps, 0.1)
+    assert st["iters"] == 2 and F.nnz == 2 and eps in F.val
+
+
+@pytest.mark.parametrize("m,s", [(16, 4), (30, 6), (24, 5), (9, 3), (20, 4), (7, 8)])
+def test_fnt_thresholds_share_eps_equally(m, s):
+    # eq. 28: each filtered stage gets the same share eps / M of the eq. 27
+    # budget, so the eq. 23 bound evaluated at the thresholds equals eps
+    Z = G.random_banded(80, 2, 0.6, 1.3, seed=7)
+    c = G.exp_coeffs(m) if m != 24 else G.cos_coeffs(24)
+    sc = O.schedule(m, s)
+    z = power_norms(Z, max(sc["q"], sc["q"] * (sc["b"] - 1)))
+    eps = 1e-11
+    zeta, sigma = O.fnt_thresholds(c, m, s, eps, z)
+    stats = [{"kind": 0, "index": k, "dropped_1norm": zeta[k]} for k in range(2, sc["J"] + 1)]
+    stats += [{"kind": 3, "index": j, "dropped_1norm": sigma[j]} for j in range(sc["start"], sc["b"])]
+    bd = filtering_bound(c, m, s, stats, z)
+    assert abs(bd["bound"] - eps) <= 1e-12 * eps, (bd["bound"], eps)
+
+
+@pytest.mark.parametrize("case", ["c1", "lap2d", "band", "rand", "cos3d"])
+def test_adaptive_error_within_eps(case):
+    # the paper's guarantee (eq. 27): with the eq. 28 thresholds the filtering
+    # error is at most eps (1 + e_r) to first order
+    if case == "c1":
+        Z, c, m, s = G.laplacian_1d(400, 1.0), G.exp_coeffs(16), 16, 4
+    elif case == "lap2d":
+        Z, c, m, s = G.laplacian_2d(25, 2.0), G.exp_coeffs(30), 30, 6
+    elif case == "band":
+        Z, c, m, s = G.random_banded(300, 3, 0.6, 1.5, seed=5), G.exp_coeffs(20), 20, 4
+    elif case == "rand":
+        Z, c, m, s = G.random_sparse(50, 0.08, 3, 0.4), G.exp_coeffs(18), 18, 3
+    else:
+        Z, c, m, s = G.laplacian_3d_perturbed(6, seed=3), G.cos_coeffs(24), 24, 5
+    sc = O.schedule(m, s)
+    z = power_norms(Z, max(sc["q"], sc["q"] * (sc["b"] - 1)))
+    for eps in (1e-12, 1e-8):
+        e_r = 0.1
+        F, st, a1 = O.filtered_ps_adaptive(Z, c, m, s, eps, e_r, z)
+        check_canonical(F)
+        assert len(a1) == sc["n_spgemm"]
+        for a in a1:
+            assert a["dropped"] <= a["eps_g"] * (1 + e_r)
+        if Z.n <= 64:
+            P = O.dense_horner_ld(Z.to_dense(), c).astype(np.float64)
+        else:
+            P = O.dense_horner(Z.to_dense(), c)
+        err = O.norm1(F.to_dense() - P)
+        assert err <= eps * (1 + e_r) * (1 + 1e-3) + rounding_slack(c, m, O.norm1(Z)), (case, eps, err)
+        # every filtered stage ran Algorithm 1 with its eq. 28 threshold
+        zeta, sigma = O.fnt_thresholds(c, m, s, eps, z)
+        want = [zeta[k] for k in range(2, sc["J"] + 1)] + [sigma[j] for j in range(sc["start"], sc["b"])]
+        np.testing.assert_array_equal([a["eps_g"] for a in a1], want)
+        if case in ("lap2d", "band") and eps == 1e-8:
+            # and the Horner steps do filter: the result is much sparser
+            F0, _ = O.unfiltered_ps(Z, c, m, s)
+            assert F.nnz < 0.8 * F0.nnz
+            assert any(a["dropped"] > 0 for a in a1[sc["J"] - 1:])
+    # a tiny budget drops (almost) nothing beyond exact zeros
+    F, _, _ = O.filtered_ps_adaptive(Z, c, m, s, 1e-300, 0.1, z)
+    F0, _ = O.unfiltered_ps(Z, c, m, s)
+    assert F.nnz == F0.nnz
