@@ -86,6 +86,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="lap2d")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle timing (0 skips)")
+    ap.add_argument("--filter", choices=["fixed", "adaptive"], default="fixed",
+                    help="fixed: the workload's tau; adaptive: Algorithm 1 with the eq. 28 thresholds")
+    ap.add_argument("--eps", type=float, default=1e-12, help="adaptive: filtering error budget")
+    ap.add_argument("--e-r", type=float, default=0.1, help="adaptive: Algorithm 1 tolerance")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM counters)")
     args = ap.parse_args()
@@ -112,7 +116,19 @@ def main():
         torch.cuda.synchronize()
         log(f"copied {args.copy_mib} MiB device to device")
         del src, dst
-    plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"], flags=B.FPS_FLAG_TIMING)
+    if args.filter == "adaptive":
+        # ||Z^t||_1 <= ||Z||_1^t (the column-sum norm of the generated matrix)
+        import numpy as np
+
+        cs = np.zeros(Z.n)
+        np.add.at(cs, Z.col, np.abs(Z.val))
+        sc = api.schedule(cfg["m"], cfg["s"])
+        znorm = float(cs.max()) ** np.arange(max(sc["q"], sc["q"] * (sc["b"] - 1)) + 1)
+        plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], adaptive=True, eps=args.eps, e_r=args.e_r,
+                        znorm=znorm, flags=B.FPS_FLAG_TIMING)
+        cfg = dict(cfg, name=cfg["name"] + f"_adaptive_eps{args.eps:g}")
+    else:
+        plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"], flags=B.FPS_FLAG_TIMING)
 
     for i in range(args.warmup):
         plan.eval(stream)
@@ -155,7 +171,9 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "n": Z.n, "nnz_Z": Z.nnz, "m": cfg["m"], "s": cfg["s"],
-                   "tau": cfg["tau"], "series": "exp", "nnz_F": st["nnz_out"]},
+                   "filter": args.filter,
+                   **({"tau": cfg["tau"]} if args.filter == "fixed" else {"eps": args.eps, "e_r": args.e_r}),
+                   "series": "exp", "nnz_F": st["nnz_out"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg["name"]),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -170,7 +188,9 @@ def main():
         "stage_ms": {f"{['power', 'block', 'gstep', 'horner'][k]}{i}": round(ms, 4)
                      for k, i, ms in zip(st["kind"], st["index"], st["stage_ms"])},
     }
-    if args.cpu_budget > 0:
+    if args.filter == "adaptive":
+        res["alg1_iters_per_step"] = int(sum(st["stage_alg1_iters"]))
+    if args.cpu_budget > 0 and args.filter == "fixed":
         log("timing the CPU oracle ...")
         res["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
     plan.close()

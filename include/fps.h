@@ -82,6 +82,20 @@ typedef struct {
 typedef struct fps_plan_s *fps_plan;
 typedef struct fps_matrix_s *fps_matrix;
 
+/* filters (fps_filter_opts.filter) */
+#define FPS_FILTER_FIXED 0    /* drop |x| < tau after every sparse product (Section 3.1.1) */
+#define FPS_FILTER_ADAPTIVE 1 /* Algorithm 1 after every sparse product, thresholds of eq. 28 */
+
+typedef struct {
+    int32_t filter;         /* FPS_FILTER_FIXED or FPS_FILTER_ADAPTIVE */
+    int32_t max_alg1_iters; /* adaptive: iteration limit of Algorithm 1 (0: 200) */
+    double tau;             /* fixed: entry threshold (finite, >= 0) */
+    double eps;             /* adaptive: filtering error budget epsilon of eq. 27 (> 0) */
+    double e_r;             /* adaptive: Algorithm 1 tolerance e_r (>= 0) */
+    const double *znorm;    /* adaptive: HOST array, znorm[t] >= ||Z^t||_1 for t = 0..max(s, s(b-1)),
+                               b = ceil((m+1)/s); copied at plan time; required */
+} fps_filter_opts;
+
 /* stage kinds in fps_stats */
 #define FPS_STAGE_POWER 0  /* P_{index} = D_tau(Z (x) P_{index-1})            (eq. 11) */
 #define FPS_STAGE_BLOCK 1  /* Bhat_{index}, coefficient sum                     (eq. 13) */
@@ -110,6 +124,11 @@ typedef struct {
     int64_t stage_products[FPS_MAX_STAGES];
     int64_t stage_nnz[FPS_MAX_STAGES]; /* kept entries of the stage output */
     double stage_ms[FPS_MAX_STAGES];   /* FPS_FLAG_TIMING: numeric-kernel time per stage, same average */
+    /* adaptive filter, per stage (0 for stages without a sparse product) */
+    double stage_eps_g[FPS_MAX_STAGES];     /* filtering-norm threshold of the stage (eq. 28) */
+    double stage_threshold[FPS_MAX_STAGES]; /* final entry threshold of Algorithm 1 (|x| <= it dropped) */
+    double stage_dropped[FPS_MAX_STAGES];   /* 1-norm of the dropped entries (integer column sums) */
+    int32_t stage_alg1_iters[FPS_MAX_STAGES];
 } fps_stats;
 
 /* ---------------------------------------------------------------------- */
@@ -142,6 +161,20 @@ fps_status fps_schedule(int32_t m, int32_t s, int32_t *N, int32_t *q, int32_t *b
  */
 fps_status fps_plan_create(fps_plan *out, const fps_csr_view *Z, const double *coeffs, int32_t m, int32_t s,
                            double tau, uint64_t flags, fps_stream stream);
+
+/*
+ * Same as fps_plan_create with the filter chosen by `opts`.  With
+ * FPS_FILTER_ADAPTIVE every sparse product (powers, eq. 11; Horner steps,
+ * eq. 14) is formed without filtering and then filtered by Algorithm 1 with
+ * eps_g = zeta_k or sigma_j of eq. 28 (computed from eqs. 21-26 with the given
+ * norm bounds), so that the filtering error is at most eps (1 + e_r) to first
+ * order (eq. 27).  Algorithm 1 measures the candidate norm as the largest
+ * column sum of ceil(|x| 2^40 / eps_g) taken exactly in integers (an upper
+ * bound of the 1-norm, independent of summation order).  Adaptive
+ * evaluations synchronise the stream once per Algorithm 1 iteration.
+ */
+fps_status fps_plan_create_ex(fps_plan *out, const fps_csr_view *Z, const double *coeffs, int32_t m, int32_t s,
+                              const fps_filter_opts *opts, uint64_t flags, fps_stream stream);
 
 /*
  * Evaluate F(Z) on `stream`.  Once the plan has learned its buffer sizes

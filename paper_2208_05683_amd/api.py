@@ -31,12 +31,22 @@ def _alloc_csr(n, nnz, device):
 class Plan:
     """A plan for F(Z) = sum_k c_k Z^k by filtered PS (fps_plan_create)."""
 
-    def __init__(self, Z, coeffs, m: int, s: int, tau: float, flags: int = 0, stream=None):
+    def __init__(self, Z, coeffs, m: int, s: int, tau: float = 0.0, flags: int = 0, stream=None,
+                 adaptive: bool = False, eps: float = 0.0, e_r: float = 0.1, znorm=None, max_alg1_iters: int = 0):
+        """Fixed filter (drop |x| < tau) by default; adaptive=True runs
+        Algorithm 1 with the eq. 28 thresholds for budget eps (znorm[t] >=
+        ||Z^t||_1 required)."""
         self.Z = tuple(Z)  # keep the borrowed device arrays alive
         self.n = self.Z[0].numel() - 1
         self.device = self.Z[0].device
         self.view = B.csr_view(*self.Z)
-        self.handle = B.fps_plan_create(self.view, list(coeffs), m, s, tau, flags, stream)
+        self.handle = None
+        if adaptive:
+            self.handle = B.fps_plan_create_ex(self.view, list(coeffs), m, s, filter=B.FPS_FILTER_ADAPTIVE,
+                                               eps=eps, e_r=e_r, znorm=list(znorm) if znorm is not None else None,
+                                               max_alg1_iters=max_alg1_iters, flags=flags, stream=stream)
+        else:
+            self.handle = B.fps_plan_create(self.view, list(coeffs), m, s, tau, flags, stream)
 
     def eval(self, stream=None):
         B.fps_eval(self.handle, stream)

@@ -61,6 +61,21 @@ class fps_stats(C.Structure):
         ("kind", C.c_int32 * FPS_MAX_STAGES), ("index", C.c_int32 * FPS_MAX_STAGES),
         ("stage_products", C.c_int64 * FPS_MAX_STAGES), ("stage_nnz", C.c_int64 * FPS_MAX_STAGES),
         ("stage_ms", C.c_double * FPS_MAX_STAGES),
+        ("stage_eps_g", C.c_double * FPS_MAX_STAGES),
+        ("stage_threshold", C.c_double * FPS_MAX_STAGES),
+        ("stage_dropped", C.c_double * FPS_MAX_STAGES),
+        ("stage_alg1_iters", C.c_int32 * FPS_MAX_STAGES),
+    ]
+
+
+class fps_filter_opts(C.Structure):
+    _fields_ = [
+        ("filter", C.c_int32),
+        ("max_alg1_iters", C.c_int32),
+        ("tau", C.c_double),
+        ("eps", C.c_double),
+        ("e_r", C.c_double),
+        ("znorm", C.POINTER(C.c_double)),
     ]
 
 
@@ -73,6 +88,8 @@ _SIGS = {
     "fps_schedule": (C.c_int32, [C.c_int32, C.c_int32] + [_P(C.c_int32)] * 7),
     "fps_plan_create": (C.c_int32, [_P(_vp), _P(fps_csr_view), _P(C.c_double), C.c_int32, C.c_int32,
                                     C.c_double, C.c_uint64, _vp]),
+    "fps_plan_create_ex": (C.c_int32, [_P(_vp), _P(fps_csr_view), _P(C.c_double), C.c_int32, C.c_int32,
+                                       _P(fps_filter_opts), C.c_uint64, _vp]),
     "fps_eval": (C.c_int32, [_vp, _vp]),
     "fps_result_nnz": (C.c_int32, [_vp, _P(C.c_int64)]),
     "fps_result_copy": (C.c_int32, [_vp, _vp, _vp, _vp, _vp]),
@@ -143,6 +160,26 @@ def fps_plan_create(Z: fps_csr_view, coeffs, m: int, s: int, tau: float, flags: 
     h = C.c_void_p()
     _check(_lib.fps_plan_create(C.byref(h), C.byref(Z), arr, m, s, float(tau), C.c_uint64(flags),
                                 _stream_handle(stream)), "fps_plan_create")
+    return h
+
+
+def fps_plan_create_ex(Z: fps_csr_view, coeffs, m: int, s: int, filter: int = 0, tau: float = 0.0,
+                       eps: float = 0.0, e_r: float = 0.0, znorm=None, max_alg1_iters: int = 0, flags: int = 0,
+                       stream=None):
+    arr = (C.c_double * (m + 1))(*[float(x) for x in coeffs[: m + 1]])
+    o = fps_filter_opts()
+    o.filter = int(filter)
+    o.max_alg1_iters = int(max_alg1_iters)
+    o.tau = float(tau)
+    o.eps = float(eps)
+    o.e_r = float(e_r)
+    zarr = None
+    if znorm is not None:
+        zarr = (C.c_double * len(znorm))(*[float(x) for x in znorm])
+        o.znorm = C.cast(zarr, C.POINTER(C.c_double))
+    h = C.c_void_p()
+    _check(_lib.fps_plan_create_ex(C.byref(h), C.byref(Z), arr, m, s, C.byref(o), C.c_uint64(flags),
+                                   _stream_handle(stream)), "fps_plan_create_ex")
     return h
 
 

@@ -186,6 +186,9 @@ struct StageRecord {
     bool a_is_z = false, b_is_z = false;
     std::vector<int> term_src;  // coefficient sums: per matrix term, -1 = Z, else producing stage
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // events of the current evaluation (ring slot)
+    // adaptive filter (Algorithm 1) of this stage
+    double eps_g = 0.0, threshold = 0.0, dropped = 0.0;
+    int alg1_iters = 0;
 };
 
 struct Schedule {
@@ -205,9 +208,47 @@ bool make_schedule(int m, int s, Schedule* sc)
     return true;
 }
 
+// Filtering-norm thresholds of eq. 28 for a polynomial of known degree: zeta_k
+// for the powers (k = 2..q) and sigma_j for the Horner steps, from d_k
+// (eq. 24), beta (eq. 21) and the norm bounds of eqs. 25-26, with z[t] >=
+// ||Z^t||.  Sums run in ascending index order with separate multiplications
+// and additions; M = number of filtered stages; a zero d_k is replaced by 1.
+void fnt_thresholds(const std::vector<double>& c, int m, const Schedule& sc, double eps, const std::vector<double>& z,
+                    std::vector<double>& zeta, std::vector<double>& sigma)
+{
+    const int q = sc.q, b = sc.b;
+    auto A = [&](int k) { return (k >= 0 && k <= m) ? std::fabs(c[(size_t)k]) : 0.0; };
+    std::vector<double> nb((size_t)b), ns((size_t)b);
+    for (int i = 0; i < b; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < q; ++j) acc = acc + A(i * q + j) * z[(size_t)j];
+        nb[(size_t)i] = acc;
+    }
+    ns[0] = nb[(size_t)(b - 1)];
+    for (int i = 1; i < b; ++i) ns[(size_t)i] = nb[(size_t)(b - 1 - i)] + z[(size_t)q] * ns[(size_t)(i - 1)];
+    const double M = (double)(sc.nsp > 0 ? sc.nsp : 1);
+    zeta.assign((size_t)q + 1, INFINITY);
+    for (int k = 2; k <= q; ++k) {
+        double d = 0.0;
+        for (int j = 0; j < b; ++j) {
+            const int i = b - 1 - j;
+            double beta = 0.0;
+            if (k < q)
+                for (int kk = k; kk < q; ++kk) beta = beta + A(i * q + kk) * z[(size_t)(kk - k)];
+            const double sprev = (j >= 1) ? ns[(size_t)(j - 1)] : 0.0;
+            d = d + z[(size_t)(q * (b - 1 - j))] * (beta + z[(size_t)(q - k)] * sprev);
+        }
+        if (d == 0.0) d = 1.0;
+        zeta[(size_t)k] = eps / (d * M);
+    }
+    sigma.assign((size_t)b, 0.0);
+    for (int j = 0; j < b; ++j) sigma[(size_t)j] = eps / (z[(size_t)(q * (b - 1 - j))] * M);
+}
+
 // Runs row-accumulation stages with one workspace.
 struct Engine {
     Workspace ws;
+    DevBuf colsum;  // Algorithm 1 column sums
     uint64_t flags = 0;
     std::vector<int64_t> learned;  // per stage index: output capacity learned by a sizing run
     std::vector<bool> learned_global;
@@ -299,6 +340,47 @@ struct Engine {
         return FPS_OK;
     }
 
+    // Algorithm 1 on a stage output in place (see fps_plan_create_ex).
+    fps_status alg1(int idx, SlackMatrix& out, double eps_g, double e_r, int max_iter, hipStream_t s,
+                    StageRecord* rec)
+    {
+        const int64_t n = ws.n;
+        FPS_TRY(colsum.ensure(sizeof(unsigned long long) * (size_t)(n + 1)));
+        unsigned long long* cs = colsum.as<unsigned long long>();
+        unsigned long long* mx = cs + n;
+        const double target = eps_g * (1.0 + e_r);
+        const double scale = std::ldexp(1.0, 40) / eps_g;
+        double m = 1.0, t = 0.0, c = 0.0;
+        int it = 0;
+        do {
+            t = eps_g / m;
+            HIP_TRY(launch_fill_u64(cs, n + 1, 0ull, s));
+            HIP_TRY(launch_alg1_colsum(out.off.as<int64_t>(), out.end.as<int64_t>(), out.col.as<int32_t>(),
+                                       out.val.as<double>(), n, t, scale, cs, s));
+            HIP_TRY(launch_max_u64(cs, n, mx, s));
+            unsigned long long h = 0;
+            HIP_TRY(hipMemcpyAsync(&h, mx, sizeof(h), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            c = (double)h / scale;
+            m = c / t;
+            ++it;
+        } while (c > target && it < max_iter);
+        if (c > target)
+            return set_error(FPS_ERR_CAPACITY, "Algorithm 1 did not reach its target within %d iterations", max_iter);
+        HIP_TRY(launch_alg1_drop(out.off.as<int64_t>(), out.end.as<int64_t>(), out.col.as<int32_t>(),
+                                 out.val.as<double>(), out.span.as<int2>(), out.amax.as<double>(), n, t,
+                                 part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, s));
+        // the drop pass recounted every row, including those of the device-memory kernel
+        HIP_TRY(launch_fill_u64(&ctr(idx)->kept_global, 1, 0ull, s));
+        if (rec) {
+            rec->eps_g = eps_g;
+            rec->threshold = t;
+            rec->dropped = c;
+            rec->alg1_iters = it;
+        }
+        return FPS_OK;
+    }
+
     // Canonical compaction of a slack matrix.
     fps_status compact(const SlackMatrix& m, CanonMatrix& c, hipStream_t s)
     {
@@ -362,6 +444,11 @@ struct fps_plan_s {
     std::vector<double> c;
     int m = 0, s = 0;
     double tau = 0.0;
+    // adaptive filter
+    bool adaptive = false;
+    double eps = 0.0, e_r = 0.0;
+    int max_alg1 = 200;
+    std::vector<double> znorm, zeta, sigma;
     uint64_t flags = 0;
     Schedule sc;
     Engine eng;
@@ -446,6 +533,8 @@ struct fps_plan_s {
             r->a_src = r->b_src = r->e_src = -1;
             r->a_is_z = r->b_is_z = false;
             r->term_src.clear();
+            r->eps_g = r->threshold = r->dropped = 0.0;
+            r->alg1_iters = 0;
             if (!ring.empty()) {
                 r->ev0 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2];
                 r->ev1 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2 + 1];
@@ -458,8 +547,8 @@ struct fps_plan_s {
         for (int j = 1; j + 1 <= sc.J; ++j) {
             StageArgs a{};
             a.mode = kModeProduct;
-            a.tau = tau;
-            a.skip_tau = skip_tau;
+            a.tau = adaptive ? 0.0 : tau;
+            a.skip_tau = adaptive ? 0.0 : skip_tau;
             a.A = zv;
             a.B = (j == 1) ? zv : P[(size_t)j]->view();
             a.has_e = 0;
@@ -468,6 +557,7 @@ struct fps_plan_s {
             r->b_is_z = (j == 1);
             r->b_src = (j == 1) ? -1 : pow_stage[(size_t)j];
             FPS_TRY(eng.run(n_stages, a, *P[(size_t)j + 1], s, size, r));
+            if (adaptive) FPS_TRY(eng.alg1(n_stages, *P[(size_t)j + 1], zeta[(size_t)j + 1], e_r, max_alg1, s, r));
             pow_stage[(size_t)j + 1] = n_stages++;
         }
 
@@ -500,8 +590,8 @@ struct fps_plan_s {
                 // S_i = D_tau(Bhat_{b-1-i} + P_q (x) S_{i-1}) with the block summed inside the step
                 StageArgs a{};
                 a.mode = kModeProduct;
-                a.tau = tau;
-                a.skip_tau = skip_tau;
+                a.tau = adaptive ? 0.0 : tau;
+                a.skip_tau = adaptive ? 0.0 : skip_tau;
                 a.A = (sc.q == 1) ? zv : P[(size_t)sc.q]->view();
                 a.B = S[cur].view();
                 a.has_e = 0;
@@ -513,6 +603,7 @@ struct fps_plan_s {
                 r->b_src = s_stage;
                 add_term_sources(r, sc.b - 1 - i, sc.q - 1, pow_stage);
                 FPS_TRY(eng.run(n_stages, a, S[1 - cur], s, size, r));
+                if (adaptive) FPS_TRY(eng.alg1(n_stages, S[1 - cur], sigma[(size_t)i], e_r, max_alg1, s, r));
                 s_stage = n_stages++;
                 cur = 1 - cur;
             }
@@ -558,19 +649,35 @@ fps_status fps_schedule(int32_t m, int32_t s, int32_t* N, int32_t* q, int32_t* b
     return FPS_OK;
 }
 
-fps_status fps_plan_create(fps_plan* out, const fps_csr_view* Z, const double* coeffs, int32_t m, int32_t s,
-                           double tau, uint64_t flags, fps_stream stream)
+fps_status fps_plan_create_ex(fps_plan* out, const fps_csr_view* Z, const double* coeffs, int32_t m, int32_t s,
+                              const fps_filter_opts* opts, uint64_t flags, fps_stream stream)
 {
     g_last_error.clear();
     if (!out) return set_error(FPS_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
+    if (!opts) return set_error(FPS_ERR_INVALID_ARG, "opts is NULL");
     FPS_TRY(check_view(Z, "Z", -1));
     if (!coeffs) return set_error(FPS_ERR_INVALID_ARG, "coeffs is NULL");
     if (m < 0) return set_error(FPS_ERR_INVALID_ARG, "m must be >= 0");
     if (s < 1 || s > FPS_MAX_S) return set_error(FPS_ERR_INVALID_ARG, "s must be in [1, %d]", FPS_MAX_S);
-    if (!std::isfinite(tau) || tau < 0.0) return set_error(FPS_ERR_INVALID_ARG, "tau must be finite and >= 0");
     for (int k = 0; k <= m; ++k)
         if (!std::isfinite(coeffs[k])) return set_error(FPS_ERR_INVALID_ARG, "coefficient %d is not finite", k);
+    Schedule sc;
+    make_schedule(m, s, &sc);
+    const bool adaptive = opts->filter == FPS_FILTER_ADAPTIVE;
+    if (opts->filter == FPS_FILTER_FIXED) {
+        if (!std::isfinite(opts->tau) || opts->tau < 0.0)
+            return set_error(FPS_ERR_INVALID_ARG, "tau must be finite and >= 0");
+    } else if (adaptive) {
+        if (!std::isfinite(opts->eps) || !(opts->eps > 0.0))
+            return set_error(FPS_ERR_INVALID_ARG, "eps must be finite and > 0");
+        if (!std::isfinite(opts->e_r) || opts->e_r < 0.0)
+            return set_error(FPS_ERR_INVALID_ARG, "e_r must be finite and >= 0");
+        if (!opts->znorm) return set_error(FPS_ERR_INVALID_ARG, "the adaptive filter needs znorm");
+        if (opts->max_alg1_iters < 0) return set_error(FPS_ERR_INVALID_ARG, "max_alg1_iters must be >= 0");
+    } else {
+        return set_error(FPS_ERR_INVALID_ARG, "unknown filter %d", opts->filter);
+    }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (!(flags & FPS_FLAG_NO_VALIDATE)) FPS_TRY(validate_on_device(Z, "Z", st));
 
@@ -580,9 +687,20 @@ fps_status fps_plan_create(fps_plan* out, const fps_csr_view* Z, const double* c
     p->c.assign(coeffs, coeffs + m + 1);
     p->m = m;
     p->s = s;
-    p->tau = tau;
+    p->tau = adaptive ? 0.0 : opts->tau;
     p->flags = flags;
-    make_schedule(m, s, &p->sc);
+    p->sc = sc;
+    p->adaptive = adaptive;
+    if (adaptive) {
+        p->eps = opts->eps;
+        p->e_r = opts->e_r;
+        p->max_alg1 = opts->max_alg1_iters > 0 ? opts->max_alg1_iters : 200;
+        const int tmax = std::max(sc.q, sc.q * (sc.b - 1));
+        p->znorm.assign(opts->znorm, opts->znorm + tmax + 1);
+        for (double v : p->znorm)
+            if (!std::isfinite(v) || v < 0.0) return set_error(FPS_ERR_INVALID_ARG, "znorm values must be finite and >= 0");
+        fnt_thresholds(p->c, m, sc, p->eps, p->znorm, p->zeta, p->sigma);
+    }
     const int stages = p->stage_count();
     if (stages > FPS_MAX_STAGES)
         return set_error(FPS_ERR_CAPACITY, "schedule needs %d stages, at most %d supported", stages, FPS_MAX_STAGES);
@@ -598,11 +716,20 @@ fps_status fps_plan_create(fps_plan* out, const fps_csr_view* Z, const double* c
     return FPS_OK;
 }
 
+fps_status fps_plan_create(fps_plan* out, const fps_csr_view* Z, const double* coeffs, int32_t m, int32_t s,
+                           double tau, uint64_t flags, fps_stream stream)
+{
+    fps_filter_opts o{};
+    o.filter = FPS_FILTER_FIXED;
+    o.tau = tau;
+    return fps_plan_create_ex(out, Z, coeffs, m, s, &o, flags, stream);
+}
+
 fps_status fps_eval(fps_plan p, fps_stream stream)
 {
     if (!p) return set_error(FPS_ERR_INVALID_ARG, "plan is NULL");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const bool size = (p->flags & FPS_FLAG_SYNC_SIZES) || !p->sized_once;
+    const bool size = (p->flags & FPS_FLAG_SYNC_SIZES) || !p->sized_once || p->adaptive;
     p->last_stream = s;
     fps_status st = p->run_eval(s, size);
     if (st != FPS_OK) return st;
@@ -703,6 +830,10 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
         st->kind[i] = r.kind;
         st->index[i] = r.index;
         st->stage_products[i] = (int64_t)tot[(size_t)i][kPartProducts];
+        st->stage_eps_g[i] = r.eps_g;
+        st->stage_threshold[i] = r.threshold;
+        st->stage_dropped[i] = r.dropped;
+        st->stage_alg1_iters[i] = r.alg1_iters;
         st->stage_nnz[i] = (int64_t)tot[(size_t)i][kPartKept];
         st->products += (int64_t)tot[(size_t)i][kPartProducts];
         st->products_skipped += (int64_t)tot[(size_t)i][kPartProductsSkipped];

@@ -126,6 +126,12 @@ hipError_t launch_compact(const int64_t* beg, const int64_t* end, const int32_t*
                           int64_t n, const int64_t* row_ptr, int32_t* ocol, double* oval, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, hipStream_t s);
 int numeric_waves_per_block();
+// Algorithm 1 helpers (adaptive filter)
+hipError_t launch_alg1_colsum(const int64_t* beg, const int64_t* end, const int32_t* col, const double* val, int64_t n,
+                              double t, double scale, unsigned long long* colsum, hipStream_t s);
+hipError_t launch_max_u64(const unsigned long long* x, int64_t n, unsigned long long* out, hipStream_t s);
+hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
+                            int64_t n, double t, unsigned long long* part_kept, hipStream_t s);
 int numeric_global_blocks(int slots);
 // number of blocks each kernel writes partials for (host-side reduction)
 int64_t analyze_blocks(int32_t mode, int64_t n);

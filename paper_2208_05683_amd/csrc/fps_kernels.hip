@@ -26,6 +26,7 @@
 // are finished by a second kernel with per-wave workspace in device memory.
 #include "fps_device.h"
 
+#include <algorithm>
 #include <climits>
 
 namespace fps {
@@ -1018,6 +1019,100 @@ __global__ void __launch_bounds__(kBlock) k_fill_u64(unsigned long long* p, int6
     if (i < count) p[i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Adaptive filter (Algorithm 1) on a stage output in slack layout.
+//
+// The candidate norm at entry threshold t is the largest column sum of
+// ceil(|x| * scale) over the entries with 0 < |x| <= t, summed exactly in
+// 64-bit integers (so the result does not depend on the order of the atomic
+// additions), scale = 2^40 / eps_g.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock) k_alg1_colsum(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
+                                                        const int32_t* __restrict__ col,
+                                                        const double* __restrict__ val, int64_t n, double t,
+                                                        double scale, unsigned long long* colsum)
+{
+    const int64_t r = xcd_logical_block() * kWavesPerBlock + threadIdx.x / kWave;
+    if (r >= n) return;
+    for (int64_t p = beg[r] + lane(); p < end[r]; p += kWave) {
+        const double a = fabs(val[p]);
+        if (a > 0.0 && a <= t) atomicAdd(&colsum[col[p]], (unsigned long long)ceil(a * scale));
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_max_u64(const unsigned long long* __restrict__ x, int64_t n,
+                                                    unsigned long long* out)
+{
+    __shared__ unsigned long long sh[kBlock / kWave];
+    unsigned long long m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        m = max(m, x[i]);
+    m = group_max<kWave>(m);
+    if (lane() == 0) sh[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kBlock / kWave; ++i) t = max(t, sh[i]);
+        atomicMax(out, t);
+    }
+}
+
+// Drops the entries with |x| <= t of every row in place (the kept entries
+// keep their order), updates end, span and amax, and writes per-block kept
+// counts into `part_kept` (same block layout as the numeric kernel).
+__global__ void __launch_bounds__(kBlock) k_alg1_drop(const int64_t* __restrict__ beg, int64_t* end, int32_t* col,
+                                                      double* val, int2* span, double* amax, int64_t n, double t,
+                                                      unsigned long long* part_kept)
+{
+    __shared__ unsigned long long kept_sh[kWavesPerBlock];
+    const int wv = threadIdx.x / kWave;
+    const int l = lane();
+    const int64_t blk = xcd_logical_block();
+    const int64_t r = blk * kWavesPerBlock + wv;
+    int64_t kept = 0;
+    if (r < n) {
+        const int64_t b = beg[r], e = end[r];
+        double amx = 0.0;
+        int32_t first = INT_MAX, last = -1;
+        for (int64_t p0 = b; p0 < e; p0 += kWave) {
+            const int64_t p = p0 + l;
+            int32_t c = 0;
+            double x = 0.0;
+            bool keep = false;
+            if (p < e) {
+                c = col[p];
+                x = val[p];
+                keep = fabs(x) > t;
+            }
+            const unsigned long long m = __ballot(keep);
+            if (keep) {
+                const int64_t q = b + kept + (int64_t)lanes_below(m);
+                col[q] = c;
+                val[q] = x;
+                amx = fmax(amx, fabs(x));
+                first = min(first, c);
+                last = max(last, c);
+            }
+            kept += __popcll(m);
+        }
+        amx = group_max<kWave>(amx);
+        first = group_min<kWave>(first);
+        last = group_max<kWave>(last);
+        if (l == 0) {
+            end[r] = b + kept;
+            span[r] = kept ? make_int2(first, last) : make_int2(1, 0);
+            amax[r] = amx;
+        }
+    }
+    if (l == 0) kept_sh[wv] = (unsigned long long)kept;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+        for (int i = 0; i < kWavesPerBlock; ++i) s += kept_sh[i];
+        part_kept[blk] = s;
+    }
+}
+
 inline unsigned blocks_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -1104,6 +1199,32 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long l
 }
 
 int numeric_waves_per_block() { return kWavesPerBlock; }
+
+hipError_t launch_alg1_colsum(const int64_t* beg, const int64_t* end, const int32_t* col, const double* val, int64_t n,
+                              double t, double scale, unsigned long long* colsum, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_alg1_colsum, dim3((unsigned)numeric_blocks(n)), dim3(kBlock), 0, s, beg, end, col, val, n, t,
+                       scale, colsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_u64(const unsigned long long* x, int64_t n, unsigned long long* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_max_u64, dim3(blocks), dim3(kBlock), 0, s, x, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
+                            int64_t n, double t, unsigned long long* part_kept, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_alg1_drop, dim3((unsigned)numeric_blocks(n)), dim3(kBlock), 0, s, beg, end, col, val, span,
+                       amax, n, t, part_kept);
+    return hipGetLastError();
+}
 
 int numeric_global_blocks(int slots) { return slots / kWavesPerBlock; }
 

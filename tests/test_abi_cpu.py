@@ -105,3 +105,24 @@ def test_product_path_has_no_oracle_dependency():
                 assert "oracle" not in text.lower(), f
     with open(LIB, "rb") as f:
         assert b"orc_" not in f.read()
+
+
+def test_plan_create_ex_rejects_bad_filter_options(B):
+    lib = B.library()
+    h = C.c_void_p()
+    coeffs = (C.c_double * 5)(1.0, 1.0, 0.5, 1.0 / 6, 1.0 / 24)
+    v = B.fps_csr_view()
+    v.n, v.nnz, v.row_ptr, v.col, v.val = 4, 0, 0x1000, None, None  # never dereferenced on these paths
+    o = B.fps_filter_opts()
+    assert lib.fps_plan_create_ex(C.byref(h), C.byref(v), coeffs, 4, 2, None, 0, None) == B.FPS_ERR_INVALID_ARG
+    o.filter = 7
+    assert lib.fps_plan_create_ex(C.byref(h), C.byref(v), coeffs, 4, 2, C.byref(o), 0, None) == B.FPS_ERR_INVALID_ARG
+    o.filter = B.FPS_FILTER_ADAPTIVE
+    o.eps, o.e_r = 0.0, 0.1
+    assert lib.fps_plan_create_ex(C.byref(h), C.byref(v), coeffs, 4, 2, C.byref(o), 0, None) == B.FPS_ERR_INVALID_ARG
+    o.eps = 1e-12
+    assert lib.fps_plan_create_ex(C.byref(h), C.byref(v), coeffs, 4, 2, C.byref(o), 0, None) == B.FPS_ERR_INVALID_ARG
+    assert b"znorm" in lib.fps_last_error()
+    o.e_r = -1.0
+    assert lib.fps_plan_create_ex(C.byref(h), C.byref(v), coeffs, 4, 2, C.byref(o), 0, None) == B.FPS_ERR_INVALID_ARG
+    assert h.value is None

@@ -1,0 +1,103 @@
+"""Parity of the adaptive filter (Algorithm 1 with the eq. 28 thresholds) on
+the GPU with the CPU oracle: results, per-stage thresholds and Algorithm 1
+iteration counts must agree bit for bit."""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from fps_inputs import generators as G
+
+from gpu_helpers import assert_same_csr, check_canonical, download, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _progress(request):
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "gpu_test_progress.log"), "a") as f:
+        f.write(f"START {request.node.nodeid}\n")
+        f.flush()
+        os.fsync(f.fileno())
+    yield
+
+
+def znorms(Z, m, s):
+    """z[t] = ||Z^t||_1 from dense powers (small n) or ||Z||_1^t."""
+    sc = O.schedule(m, s)
+    tmax = max(sc["q"], sc["q"] * (sc["b"] - 1))
+    z = np.ones(tmax + 1)
+    if Z.n <= 1500:
+        d = Z.to_dense()
+        p = np.eye(Z.n)
+        for t in range(1, tmax + 1):
+            p = p @ d
+            z[t] = np.abs(p).sum(axis=0).max()
+    else:
+        cs = np.zeros(Z.n)
+        np.add.at(cs, Z.col, np.abs(Z.val))
+        z1 = cs.max()
+        z = z1 ** np.arange(tmax + 1)
+    return z
+
+
+def compare_adaptive(Z, c, m, s, eps, e_r=0.1, flags=0, what=""):
+    from paper_2208_05683_amd import api
+
+    z = znorms(Z, m, s)
+    want, st, a1 = O.filtered_ps_adaptive(Z, c, m, s, eps, e_r, z)
+    plan = api.Plan(upload(Z), c, m, s, adaptive=True, eps=eps, e_r=e_r, znorm=z, flags=flags)
+    try:
+        plan.eval()
+        got = download(plan.result())
+        gst = plan.stats()
+    finally:
+        plan.close()
+    check_canonical(got)
+    assert_same_csr(got, want, what)
+    prod = [i for i, k in enumerate(gst["kind"]) if k in (0, 3)]
+    assert [gst["stage_eps_g"][i] for i in prod] == [x["eps_g"] for x in a1]
+    assert [gst["stage_threshold"][i] for i in prod] == [x["threshold"] for x in a1]
+    assert [gst["stage_alg1_iters"][i] for i in prod] == [x["iters"] for x in a1]
+    assert [gst["stage_dropped"][i] for i in prod] == [x["dropped"] for x in a1]
+    return got, want, a1, gst
+
+
+@pytest.mark.parametrize("eps", [1e-12, 1e-8])
+def test_adaptive_lap1d(eps):
+    compare_adaptive(G.laplacian_1d(1000, 1.0), G.exp_coeffs(16), 16, 4, eps, what="lap1d")
+
+
+@pytest.mark.parametrize("side,eps", [(40, 1e-12), (60, 1e-9), (120, 1e-12)])
+def test_adaptive_lap2d(side, eps):
+    got, want, a1, gst = compare_adaptive(G.laplacian_2d(side, 2.0), G.exp_coeffs(30), 30, 6, eps, what="lap2d")
+    assert any(x["iters"] > 1 for x in a1)
+
+
+def test_adaptive_banded_and_random():
+    compare_adaptive(G.random_banded(3000, 4, 0.6, 1.7, seed=9), G.exp_coeffs(20), 20, 4, 1e-10, what="banded")
+    rng = np.random.default_rng(3)
+    compare_adaptive(G.random_sparse(300, 0.02, 5, 0.6), G.random_series_coeffs(18, rng), 18, 3, 1e-9,
+                     what="random")
+
+
+@pytest.mark.parametrize("side", [6, 8])
+def test_adaptive_lap3d_downscaled(side):
+    cfg = G.config3(side=side)
+    compare_adaptive(cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], 1e-10, what=f"3d {side}")
+
+
+def test_adaptive_flags_and_degenerate():
+    from paper_2208_05683_amd import binding as B
+
+    Z = G.laplacian_2d(50, 2.0)
+    compare_adaptive(Z, G.exp_coeffs(30), 30, 6, 1e-10, flags=B.FPS_FLAG_FORCE_GLOBAL, what="force global")
+    # a vanishing budget drops nothing beyond exact zeros
+    got, want, a1, gst = compare_adaptive(Z, G.exp_coeffs(30), 30, 6, 1e-300, what="tiny eps")
+    F0, _ = O.unfiltered_ps(Z, G.exp_coeffs(30), 30, 6)
+    assert got.nnz == F0.nnz
+    # b = 1: nothing but powers
+    compare_adaptive(G.laplacian_1d(200, 1.0), G.exp_coeffs(5), 5, 8, 1e-10, what="b=1")
