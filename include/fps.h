@@ -26,6 +26,8 @@
  * bit for bit, independent of launch configuration.
  *
  * Conventions for every entry point:
+ *   - Matrices are square with 1 <= n <= FPS_MAX_N (a term row is
+ *     addressed with 32-bit byte offsets).
  *   - CSR views hold DEVICE pointers: row_ptr int64[n+1] with row_ptr[0] = 0,
  *     col int32[nnz] strictly increasing within each row, val double[nnz]
  *     finite.  Views are borrowed: the library never frees them.
@@ -59,6 +61,8 @@ typedef int32_t fps_status;
 
 /* largest PS block size s accepted (the g = 1 sum has s+1 terms) */
 #define FPS_MAX_S 31
+/* Largest supported matrix dimension n. */
+#define FPS_MAX_N 268435456
 /* number of per-stage records kept in fps_stats */
 #define FPS_MAX_STAGES 96
 

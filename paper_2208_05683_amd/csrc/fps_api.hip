@@ -159,10 +159,11 @@ struct Workspace {
         // global-memory kernel: per slot byte map + bitmap + prefix + accumulator for a full row
         g_words = (nn + 31) / 32;
         g_cap = std::max<int64_t>(nn, 1);
-        // per slot (4-byte units): byte map [8 words] | bitmap words as uint2 [2 words] | accumulator
-        // [2 cap] | parked extra values [2 cap] | column list [cap]
-        g_off_acc = g_words * 10;
-        g_off_ebuf = g_off_acc + 2 * g_cap;
+        // per slot (4-byte units): byte map [8 words] | bitmap words as uint2 and the guard word
+        // [2 (words + 1)] | accumulator and the spare slot [2 (cap + 1)] | parked extra values [2 cap] |
+        // column list [cap]
+        g_off_acc = g_words * 8 + 2 * (g_words + 1);
+        g_off_ebuf = g_off_acc + 2 * (g_cap + 1);
         g_off_cols = g_off_ebuf + 2 * g_cap;
         const int64_t per_slot_u32 = (g_off_cols + g_cap + 63) / 64 * 64;
         g_stride = per_slot_u32;
@@ -406,7 +407,7 @@ struct Engine {
 fps_status check_view(const fps_csr_view* v, const char* what, int64_t n_expect)
 {
     if (!v) return set_error(FPS_ERR_INVALID_ARG, "%s is NULL", what);
-    if (v->n < 1 || v->n > INT32_MAX - 1) return set_error(FPS_ERR_INVALID_ARG, "%s: n = %lld out of range", what, (long long)v->n);
+    if (v->n < 1 || v->n > FPS_MAX_N) return set_error(FPS_ERR_INVALID_ARG, "%s: n = %lld out of range", what, (long long)v->n);
     if (n_expect >= 0 && v->n != n_expect) return set_error(FPS_ERR_INVALID_ARG, "%s: dimension mismatch", what);
     if (v->nnz < 0) return set_error(FPS_ERR_INVALID_ARG, "%s: negative nnz", what);
     if (!v->row_ptr || (v->nnz > 0 && (!v->col || !v->val)))
@@ -959,7 +960,7 @@ fps_status fps_axpy(fps_matrix* out, int64_t n, int32_t nterms, const double* co
     g_last_error.clear();
     if (!out) return set_error(FPS_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (n < 1 || n > INT32_MAX - 1) return set_error(FPS_ERR_INVALID_ARG, "n out of range");
+    if (n < 1 || n > FPS_MAX_N) return set_error(FPS_ERR_INVALID_ARG, "n out of range");
     if (nterms < 1 || nterms > kMaxTerms) return set_error(FPS_ERR_INVALID_ARG, "nterms must be in [1, %d]", kMaxTerms);
     if (!coefs || !terms) return set_error(FPS_ERR_INVALID_ARG, "null coefs/terms");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);

@@ -380,8 +380,9 @@ struct WaveStage {
 // The structural column list of a row is kept in the row's own output slot
 // (P.out.col[off..off+ns)), which the write-out then compacts in place.
 struct LdsWave {
-    uint2 bmp[kLdsWords];  // per 32 window columns: .x structure bits, .y set bits in earlier words
-    double acc[kLdsCap];
+    uint2 bmp[kLdsWords + 1];  // per 32 window columns: .x structure bits, .y set bits in earlier words;
+                               // then the guard word
+    double acc[kLdsCap + 1];   // then the spare slot
     WaveStage st;
 };
 
@@ -402,7 +403,6 @@ __device__ __forceinline__ int64_t sgpr64(int64_t x)
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
-__device__ __forceinline__ double sgprd(double x) { return __longlong_as_double(sgpr64(__double_as_longlong(x))); }
 
 enum TermSource : int { kSrcProducts = 0, kSrcCoefs = 1 };
 
@@ -563,123 +563,216 @@ __device__ __forceinline__ void accumulate_batch(const WaveStage& st, int32_t q0
 }
 
 // ---- per-term groups (long term rows) ------------------------------------------
-// kGroup terms at a time: the first kStep entries of each of the group's rows
-// are loaded together (two per lane, clamped in-row indices, or a zeroed dummy
-// row), then the terms are applied one after the other.  Entries beyond kStep
-// (rows longer than 128) are handled right after their term's first part.
+// kGroup terms at a time.  Each term row is addressed through a buffer
+// resource whose size is the row's length, so the loads of lanes past the end
+// of the row return zeros without touching memory; the first kStep entries of
+// each of the group's rows are loaded together (two per lane), then the terms
+// are applied one after the other.  Entries beyond kStep (rows longer than
+// 128) are handled right after their term's first part.
 
 constexpr int kGroup = 4;
+constexpr int kRsrcWord3 = 0x00020000;  // raw (unswizzled, stride 0) buffer of 32-bit elements
 
-struct TermHead {
-    int32_t len;  // uniform
-    int64_t b0;   // uniform; < 0: identity row (coefficient terms) or no term
-    const int32_t* cp;
-    const double* vp;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* base, int32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kRsrcWord3);
+}
+
+// Lane t < nterms holds term t of the staged chunk.
+struct ChunkRegs {
+    int32_t len;
+    int64_t beg;
+    double a;
 };
 
-template <int SRC>
-__device__ __forceinline__ TermHead term_head(const StageArgs& P, int64_t t0, const WaveStage& st, int i, int nterms)
+__device__ __forceinline__ ChunkRegs chunk_regs(const WaveStage& st, int nterms)
 {
-    TermHead h{0, -1, P.dummy_col, P.dummy_val};
+    const int l = lane();
+    ChunkRegs c{0, -1, 0.0};
+    if (l < nterms) {
+        c.len = st.len[l];
+        c.beg = st.beg[l];
+        c.a = st.a[l];
+    }
+    return c;
+}
+
+__device__ __forceinline__ int64_t readlane64(int64_t x, int i)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(uint64_t)x, i);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)x >> 32), i);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Uniform description of one term.
+struct TermDesc {
+    int32_t len;  // entries of the term row; 0: no term
+    bool ident;   // identity row (coefficient term of P_0): the single entry (r, 1)
+    double a;     // weight
+    __amdgpu_buffer_rsrc_t rc, rv;
+};
+
+template <int SRC, bool kNeedV>
+__device__ __forceinline__ TermDesc term_desc(const StageArgs& P, int64_t t0, const ChunkRegs& cr, int i, int nterms)
+{
+    TermDesc h;
+    h.len = 0;
+    h.ident = false;
+    h.a = 0.0;
+    const int32_t* cb = P.dummy_col;
+    const double* vb = P.dummy_val;
+    int32_t real = 0;
     if (i < nterms) {
-        h.len = sgpr(st.len[i]);
-        h.b0 = sgpr64(st.beg[i]);
-        if (h.b0 >= 0 && h.len > 0) {
+        const int32_t len = __builtin_amdgcn_readlane(cr.len, i);
+        const int64_t beg = readlane64(cr.beg, i);
+        if (kNeedV) h.a = __longlong_as_double(readlane64(__double_as_longlong(cr.a), i));
+        if (SRC == kSrcCoefs && beg < 0) {
+            h.ident = true;
+            h.len = 1;
+        } else if (len > 0) {
+            h.len = len;
+            real = len;
             if (SRC == kSrcProducts) {
-                h.cp = P.B.col + h.b0;
-                h.vp = P.B.val + h.b0;
+                cb = P.B.col + beg;
+                vb = P.B.val + beg;
             } else {
-                h.cp = P.T.col[t0 + i] + h.b0;
-                h.vp = P.T.val[t0 + i] + h.b0;
+                cb = P.T.col[t0 + i] + beg;
+                vb = P.T.val[t0 + i] + beg;
             }
         }
     }
+    h.rc = row_rsrc(cb, real * 4);
+    h.rv = row_rsrc(vb, real * 8);
     return h;
 }
 
+// Entries e0 + lane and e0 + 64 + lane of a term row (zeros past its end).
+struct Part {
+    int32_t c0, c1;
+    double v0, v1;
+};
+
 template <bool kNeedV>
-__device__ __forceinline__ void load_part(const TermHead& h, int32_t e0, int32_t& c0, int32_t& c1, double& v0,
-                                          double& v1)
+__device__ __forceinline__ Part load_part(const TermDesc& h, int32_t e0)
+{
+    const int32_t i = e0 + lane();
+    Part p;
+    p.c0 = __builtin_amdgcn_raw_buffer_load_b32(h.rc, i * 4, 0, 0);
+    p.c1 = __builtin_amdgcn_raw_buffer_load_b32(h.rc, i * 4 + kWave * 4, 0, 0);
+    if (kNeedV) {
+        p.v0 = __longlong_as_double((long long)__builtin_amdgcn_raw_buffer_load_b64(h.rv, i * 8, 0, 0));
+        p.v1 = __longlong_as_double((long long)__builtin_amdgcn_raw_buffer_load_b64(h.rv, i * 8 + kWave * 8, 0, 0));
+    } else {
+        p.v0 = p.v1 = 0.0;
+    }
+    return p;
+}
+
+// Structure pass over one part: marks the in-window columns and records
+// out-of-window ones in the wave-uniform mask `badm`.
+template <bool kGlobal>
+__device__ __forceinline__ void mark_part(const TermDesc& h, int32_t e0, const Part& p, int64_t r, int32_t lo,
+                                          uint32_t W, uint8_t* bytes, uint2* bmp, unsigned long long& badm)
 {
     const int l = lane();
-    // real rows: in-row index clamped to the last entry; otherwise the
-    // 128-entry dummy row at lane and lane + 64
-    const bool real = h.b0 >= 0 && h.len > 0;
-    const int32_t* cp = h.cp;
-    const double* vp = h.vp;
-    uint32_t i0 = (uint32_t)l, i1 = (uint32_t)(l + kWave);
-    if (real) {
-        const uint32_t last = (uint32_t)(h.len - 1);
-        i0 = min((uint32_t)(e0 + l), last);
-        i1 = min((uint32_t)(e0 + kWave + l), last);
-    }
-    c0 = cp[i0];
-    c1 = cp[i1];
-    if (kNeedV) {
-        v0 = vp[i0];
-        v1 = vp[i1];
-    } else {
-        v0 = v1 = 0.0;
+    const int32_t c0 = h.ident ? (int32_t)r : p.c0;
+    const bool ok0 = e0 + l < h.len;
+    const uint32_t d0 = (uint32_t)(c0 - lo);
+    badm |= __ballot(ok0 && !(d0 < W));
+    if (ok0 && d0 < W) mark_d<kGlobal>(d0, bytes, bmp);
+    if (h.len > e0 + kWave) {
+        const bool ok1 = e0 + kWave + l < h.len;
+        const uint32_t d1 = (uint32_t)(p.c1 - lo);
+        badm |= __ballot(ok1 && !(d1 < W));
+        if (ok1 && d1 < W) mark_d<kGlobal>(d1, bytes, bmp);
     }
 }
 
-template <int SRC, bool kAccum, bool kGlobal>
-__device__ __forceinline__ void use_part(const TermHead& h, int32_t e0, double a, int64_t r, int32_t lo, uint32_t W,
-                                         int32_t c0, int32_t c1, double v0, double v1, uint8_t* bytes, uint2* bmp,
-                                         double* acc, uint32_t& bad)
+// Accumulator slot of window offset d (the guard offset maps to the spare
+// slot behind the row's entries).
+__device__ __forceinline__ uint32_t slot_of(const uint2* bmp, uint32_t d)
+{
+    const uint2 w = bmp[d >> 5];
+    return w.y + (uint32_t)__popc(__builtin_amdgcn_ubfe(w.x, 0u, d));
+}
+
+struct Slots {
+    uint32_t s0, s1;
+};
+
+// Slots of a part's entries; lanes without an entry get the spare slot.  All
+// columns of the row lie in the window (checked by the structure pass).
+__device__ __forceinline__ Slots part_slots(const TermDesc& h, int32_t e0, const Part& p, int64_t r, int32_t lo,
+                                            uint32_t guard, const uint2* bmp)
 {
     const int l = lane();
-    bool ok0 = e0 + l < h.len, ok1 = e0 + kWave + l < h.len;
-    if (SRC == kSrcCoefs && h.b0 < 0) {  // identity row: the single entry (r, 1)
-        c0 = (int32_t)r;
-        v0 = 1.0;
-        ok1 = false;
-    }
-    const uint32_t d0 = window_d(c0, lo, W, ok0, bad);
-    const uint32_t d1 = window_d(c1, lo, W, ok1, bad);
-    if (!kAccum) {
-        if (ok0) mark_d<kGlobal>(d0, bytes, bmp);
-        if (ok1) mark_d<kGlobal>(d1, bytes, bmp);
+    const int32_t c0 = h.ident ? (int32_t)r : p.c0;
+    Slots s;
+    s.s0 = slot_of(bmp, (e0 + l < h.len) ? (uint32_t)(c0 - lo) : guard);
+    s.s1 = 0;
+    if (h.len > e0 + kWave) s.s1 = slot_of(bmp, (e0 + kWave + l < h.len) ? (uint32_t)(p.c1 - lo) : guard);
+    return s;
+}
+
+// acc[slot] = fma(a, v, acc[slot]) for a part's entries (one term: distinct
+// columns, so no two lanes touch one slot other than the spare).
+__device__ __forceinline__ void accumulate_part(const TermDesc& h, int32_t e0, const Part& p, const Slots& s,
+                                                double* acc)
+{
+    const double v0 = h.ident ? 1.0 : p.v0;
+    if (h.len > e0 + kWave) {
+        const double x0 = fma(h.a, v0, acc[s.s0]);
+        const double x1 = fma(h.a, p.v1, acc[s.s1]);
+        acc[s.s0] = x0;
+        acc[s.s1] = x1;
     } else {
-        // the two entries of a lane belong to one term: distinct columns, and
-        // no collision with any other lane
-        const uint32_t s0 = rank_of(bmp, d0);
-        const uint32_t s1 = rank_of(bmp, d1);
-        const double x0 = fma(a, v0, acc[s0]);
-        const double x1 = fma(a, v1, acc[s1]);
-        if (ok0) acc[s0] = x0;
-        if (ok1) acc[s1] = x1;
-        wave_sync();
+        acc[s.s0] = fma(h.a, v0, acc[s.s0]);
     }
 }
 
 template <int SRC, bool kAccum, bool kGlobal>
 __device__ __forceinline__ void per_term_pass(const StageArgs& P, int64_t r, int64_t t0, int nterms,
-                                              const WaveStage& st, int32_t lo, uint32_t W, uint8_t* bytes,
-                                              uint2* bmp, double* acc, uint32_t& bad)
+                                              const WaveStage& st, int32_t lo, uint32_t W, uint32_t guard,
+                                              uint8_t* bytes, uint2* bmp, double* acc, uint32_t& bad)
 {
+    const ChunkRegs cr = chunk_regs(st, nterms);
+    unsigned long long badm = 0;
     for (int i0 = 0; i0 < nterms; i0 += kGroup) {
-        TermHead h[kGroup];
-        int32_t c0[kGroup], c1[kGroup];
-        double v0[kGroup], v1[kGroup];
+        TermDesc h[kGroup];
+        Part p[kGroup];
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) {
-            h[g] = term_head<SRC>(P, t0, st, i0 + g, nterms);
-            load_part<kAccum>(h[g], 0, c0[g], c1[g], v0[g], v1[g]);
+            h[g] = term_desc<SRC, kAccum>(P, t0, cr, i0 + g, nterms);
+            p[g] = load_part<kAccum>(h[g], 0);
         }
+        if (!kAccum) {
 #pragma unroll
-        for (int g = 0; g < kGroup; ++g) {
-            if (h[g].len == 0) continue;
-            const double a = kAccum ? sgprd(st.a[i0 + g]) : 0.0;
-            use_part<SRC, kAccum, kGlobal>(h[g], 0, a, r, lo, W, c0[g], c1[g], v0[g], v1[g], bytes, bmp, acc, bad);
-            for (int32_t e0 = kStep; e0 < h[g].len; e0 += kStep) {
-                int32_t d0, d1;
-                double w0, w1;
-                load_part<kAccum>(h[g], e0, d0, d1, w0, w1);
-                use_part<SRC, kAccum, kGlobal>(h[g], e0, a, r, lo, W, d0, d1, w0, w1, bytes, bmp, acc, bad);
+            for (int g = 0; g < kGroup; ++g) {
+                if (h[g].len == 0) continue;
+                mark_part<kGlobal>(h[g], 0, p[g], r, lo, W, bytes, bmp, badm);
+                for (int32_t e0 = kStep; e0 < h[g].len; e0 += kStep)
+                    mark_part<kGlobal>(h[g], e0, load_part<false>(h[g], e0), r, lo, W, bytes, bmp, badm);
+            }
+        } else {
+            // the ranks of the whole group first (the bitmap is read-only
+            // here), then the read-modify-writes strictly term by term
+            Slots s[kGroup];
+#pragma unroll
+            for (int g = 0; g < kGroup; ++g) s[g] = part_slots(h[g], 0, p[g], r, lo, guard, bmp);
+#pragma unroll
+            for (int g = 0; g < kGroup; ++g) {
+                if (h[g].len == 0) continue;
+                accumulate_part(h[g], 0, p[g], s[g], acc);
+                wave_sync();
+                for (int32_t e0 = kStep; e0 < h[g].len; e0 += kStep) {
+                    const Part q = load_part<true>(h[g], e0);
+                    accumulate_part(h[g], e0, q, part_slots(h[g], e0, q, r, lo, guard, bmp), acc);
+                    wave_sync();
+                }
             }
         }
     }
+    if (badm) bad = 1u;
 }
 
 // Long term rows go step by step, short ones in flattened batches
@@ -694,8 +787,8 @@ __device__ __forceinline__ bool use_per_term(int src, int32_t total, int nterms)
 // area already holds the chunk at tb with `total0` products.
 template <bool kAccum, bool kGlobal>
 __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t r, int32_t lo, uint32_t W,
-                                           uint8_t* bytes, uint2* bmp, double* acc, WaveStage& st, bool first_loaded,
-                                           int32_t total0, uint32_t& bad)
+                                           uint32_t guard, uint8_t* bytes, uint2* bmp, double* acc, WaveStage& st,
+                                           bool first_loaded, int32_t total0, uint32_t& bad)
 {
     int64_t tb, te;
     term_range(P, src, r, &tb, &te);
@@ -704,9 +797,9 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
         const int nterms = (int)min<int64_t>(kChunk, te - t0);
         if (use_per_term(src, total, nterms)) {
             if (src == kSrcProducts)
-                per_term_pass<kSrcProducts, kAccum, kGlobal>(P, r, t0, nterms, st, lo, W, bytes, bmp, acc, bad);
+                per_term_pass<kSrcProducts, kAccum, kGlobal>(P, r, t0, nterms, st, lo, W, guard, bytes, bmp, acc, bad);
             else
-                per_term_pass<kSrcCoefs, kAccum, kGlobal>(P, r, t0, nterms, st, lo, W, bytes, bmp, acc, bad);
+                per_term_pass<kSrcCoefs, kAccum, kGlobal>(P, r, t0, nterms, st, lo, W, guard, bytes, bmp, acc, bad);
         } else {
             for (int32_t q0 = 0; q0 < total; q0 += kWave * kU) {
                 Batch b;
@@ -765,7 +858,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
     }
     wave_sync();
     if (P.has_blk)
-        terms_pass<false, kGlobal>(P, kSrcCoefs, r, lo, (uint32_t)W, bytes, bmp, nullptr, st, false, 0, bad);
+        terms_pass<false, kGlobal>(P, kSrcCoefs, r, lo, (uint32_t)W, 0u, bytes, bmp, nullptr, st, false, 0, bad);
     if (P.has_e) {
         for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave) {
             bool ok = true;
@@ -785,7 +878,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
             mark_batch<kGlobal>(lo, (uint32_t)W, b1, bytes, bmp, bad);
         }
     } else {
-        terms_pass<false, kGlobal>(P, main_src, r, lo, (uint32_t)W, bytes, bmp, nullptr, st, true, total0, bad);
+        terms_pass<false, kGlobal>(P, main_src, r, lo, (uint32_t)W, 0u, bytes, bmp, nullptr, st, true, total0, bad);
     }
     wave_sync();
     if (kGlobal) {  // pack the byte map into bits
@@ -802,7 +895,20 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
         wave_sync();
     }
 
-    // 2. prefix counts of the bitmap words: rank(column) = slot
+    // a column outside the row's window means the row information of an
+    // operand was inconsistent: the stage reports an error, the row stays empty
+    if (__ballot(bad != 0u)) {
+        flag_error(P, kErrColumnOutsideWindow);
+        if (l == 0) {
+            P.out.end[r] = o;
+            P.out.span[r] = make_int2(1, 0);
+            P.out.amax[r] = 0.0;
+        }
+        return true;
+    }
+
+    // 2. prefix counts of the bitmap words: rank(column) = slot; the guard
+    //    word behind the window maps to the spare accumulator slot `cap`
     uint32_t running = 0;
     for (int64_t w0 = 0; w0 < words; w0 += kWave) {
         const int64_t w = w0 + l;
@@ -812,6 +918,8 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
         running += __shfl(inc, kWave - 1, kWave);
     }
     const int64_t ns = running;
+    const uint32_t guard = (uint32_t)(words * 32);
+    if (l == 0) bmp[words] = make_uint2(0u, (uint32_t)cap);
     if (ns > cap) return false;
     if (o + ns > P.out.cap) {
         flag_error(P, kErrCapacity);
@@ -843,7 +951,8 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
     if (single) {
         if (total0 > 0) accumulate_batch(st, 0, total0, lo, (uint32_t)W, b1, bmp, acc, bad);
     } else {
-        terms_pass<true, kGlobal>(P, main_src, r, lo, (uint32_t)W, nullptr, bmp, acc, st, one_chunk, total0, bad);
+        terms_pass<true, kGlobal>(P, main_src, r, lo, (uint32_t)W, guard, nullptr, bmp, acc, st, one_chunk, total0,
+                                  bad);
     }
     wave_sync();
     double preg[kParked];
@@ -867,7 +976,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
         }
         wave_sync();
         if (P.has_blk)
-            terms_pass<true, kGlobal>(P, kSrcCoefs, r, lo, (uint32_t)W, nullptr, bmp, acc, st, false, 0, bad);
+            terms_pass<true, kGlobal>(P, kSrcCoefs, r, lo, (uint32_t)W, guard, nullptr, bmp, acc, st, false, 0, bad);
         if (P.has_e) {
             for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave) {
                 bool ok = true;
@@ -877,8 +986,6 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
         }
         wave_sync();
     }
-    if (__ballot(bad != 0u)) flag_error(P, kErrColumnOutsideWindow);
-
     // 5. x = extra + main, drop test, sorted write-out.  Entry i moves to
     //    position kept-before-i <= i of the same slot: a batch reads its
     //    columns before any of its writes (they depend on the loaded values)
@@ -934,7 +1041,7 @@ __global__ void __launch_bounds__(kBlock) k_numeric_lds(StageArgs P)
 {
     __shared__ LdsWave lds[kWavesPerBlock];
     __shared__ unsigned long long kept_sh[kWavesPerBlock];
-    const int wv = threadIdx.x / kWave;
+    const int wv = sgpr((int32_t)(threadIdx.x / kWave));  // wave-uniform: row-level values live in scalar registers
     LdsWave& me = lds[wv];
     const int l = lane();
     const int64_t blk = xcd_logical_block();
@@ -964,7 +1071,7 @@ __global__ void __launch_bounds__(kBlock) k_numeric_lds(StageArgs P)
 __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
 {
     __shared__ WaveStage st[kWavesPerBlock];
-    const int wv = threadIdx.x / kWave;
+    const int wv = sgpr((int32_t)(threadIdx.x / kWave));
     const int l = lane();
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wv;
     if (slot >= P.g_slots) return;
@@ -980,7 +1087,7 @@ __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
         if (l == 0) i = atomicAdd(&P.ctr->fb_next, 1ull);
         i = __shfl(i, 0, kWave);
         if (i >= count) break;
-        const int64_t r = P.fb_list[i];
+        const int64_t r = sgpr64(P.fb_list[i]);
         int64_t k = 0;
         if (!process_row<true>(P, r, bytes, bmp, acc, ebuf, st[wv], P.g_slot_words, P.g_slot_cap, &k))
             flag_error(P, kErrCapacity);
