@@ -159,10 +159,10 @@ struct Workspace {
         // global-memory kernel: per slot byte map + bitmap + prefix + accumulator for a full row
         g_words = (nn + 31) / 32;
         g_cap = std::max<int64_t>(nn, 1);
-        // per slot (4-byte units): byte map [8 words] | bitmap words as uint2 and the guard word
-        // [2 (words + 1)] | accumulator and the spare slot [2 (cap + 1)] | parked extra values [2 cap] |
-        // column list [cap]
-        g_off_acc = g_words * 8 + 2 * (g_words + 1);
+        // per slot (4-byte units): byte map and guard word [8 (words + 1)] | bitmap words as uint2 and
+        // the guard word [2 (words + 1)] | accumulator and the spare slot [2 (cap + 1)] | parked extra
+        // values [2 cap] | column list [cap]
+        g_off_acc = 10 * (g_words + 1);
         g_off_ebuf = g_off_acc + 2 * (g_cap + 1);
         g_off_cols = g_off_ebuf + 2 * g_cap;
         const int64_t per_slot_u32 = (g_off_cols + g_cap + 63) / 64 * 64;

@@ -98,11 +98,11 @@ struct StageArgs {
     int64_t part_stride;
     int64_t* fb_list;       // n entries
     uint32_t* g_scratch;    // global-memory kernel workspace
-    int64_t g_slot_words;   // bitmap words per slot
+    int64_t g_slot_words;   // bitmap words per slot (each array has room for one guard word / spare slot more)
     int64_t g_slot_cap;     // accumulator entries per slot
     int64_t g_slot_stride;  // 4-byte units between slots (multiple of 64)
-    int64_t g_off_acc;      // 4-byte offsets of the slot's arrays: bytes at 0, then bitmap words (uint2),
-    int64_t g_off_ebuf;     //   then accumulator, parked extra values and column list
+    int64_t g_off_acc;      // 4-byte offsets of the slot's arrays: byte map at 0, bitmap words (uint2) at
+    int64_t g_off_ebuf;     //   8 (words + 1), then accumulator, parked extra values and column list
     int64_t g_off_cols;
     int32_t g_slots;
     int32_t force_global;

@@ -33,7 +33,7 @@ namespace fps {
 namespace {
 
 constexpr int kLdsWords = 256;  // window of up to 8192 columns in shared memory
-constexpr int kLdsCap = 512;    // up to 512 structural entries per row in shared memory
+constexpr int kLdsCap = 448;    // up to 448 structural entries per row in shared memory
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 
@@ -368,13 +368,13 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const int64_t* __restrict
 // ---------------------------------------------------------------------------
 // Numeric stage.
 // ---------------------------------------------------------------------------
-constexpr int kChunk = 32;  // terms staged at a time
+constexpr int kChunk = kWave;  // terms handled per chunk: lane t holds term t
 
+// Short-row batches look up the term of each product in the staged prefix
+// counts of the chunk.
 struct WaveStage {
-    int32_t excl[kChunk];  // exclusive prefix of the term row lengths in the current chunk
-    int32_t len[kChunk];   // row length of each term
-    int64_t beg[kChunk];   // first entry of the term's row (-1: identity row)
-    double a[kChunk];      // term weight
+    int32_t excl[kChunk];  // exclusive prefix of the term row lengths
+    int64_t beg[kChunk];   // first entry of the term's row
 };
 
 // The structural column list of a row is kept in the row's own output slot
@@ -387,13 +387,14 @@ struct LdsWave {
 };
 
 constexpr int kParked = kLdsCap / kWave;  // parked values per lane (shared-memory kernel)
+static_assert(kLdsCap % kWave == 0, "the parked values cover the accumulator exactly");
 constexpr int kU = 4;                     // flattened batch: kU sub-batches of 64 products
 constexpr int kStep = 2 * kWave;          // per-term step: 128 entries of one term row
 
 __device__ __forceinline__ uint32_t rank_of(const uint2* bmp, uint32_t d)
 {
     const uint2 w = bmp[d >> 5];
-    return w.y + (uint32_t)__popc(w.x & ((1u << (d & 31u)) - 1u));
+    return w.y + (uint32_t)__popc(__builtin_amdgcn_ubfe(w.x, 0u, d));
 }
 
 __device__ __forceinline__ int32_t sgpr(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -402,6 +403,16 @@ __device__ __forceinline__ int64_t sgpr64(int64_t x)
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)x);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
     return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ int64_t readlane64(int64_t x, int i)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(uint64_t)x, i);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)x >> 32), i);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double readlaned(double x, int i)
+{
+    return __longlong_as_double(readlane64(__double_as_longlong(x), i));
 }
 
 enum TermSource : int { kSrcProducts = 0, kSrcCoefs = 1 };
@@ -419,44 +430,56 @@ __device__ __forceinline__ void term_range(const StageArgs& P, int src, int64_t 
     }
 }
 
-// Loads the next <= kChunk terms starting at t0 into the staging area and
-// returns the number of products of the chunk.
-__device__ __forceinline__ int32_t load_chunk(const StageArgs& P, int src, int64_t r, int64_t t0, int64_t te,
-                                              WaveStage& st)
+// One chunk of terms in registers: lane t holds term t0 + t (zero-length
+// padding past the last term).
+struct Chunk {
+    int32_t len;     // entries of the term row
+    int32_t incl;    // inclusive prefix of len over the lanes
+    int64_t beg;     // first entry of the term row; -1: identity row (P_0)
+    double a;        // weight
+    int32_t total;   // uniform: products of the chunk
+    int32_t nterms;  // uniform
+};
+
+__device__ __forceinline__ Chunk load_chunk(const StageArgs& P, int src, int64_t r, int64_t t0, int64_t te)
 {
     const int l = lane();
     const int64_t t = t0 + l;
-    int32_t len = 0;
-    int64_t bb = 0;
-    double a = 0.0;
-    if (l < kChunk && t < te) {
+    Chunk c;
+    c.len = 0;
+    c.beg = 0;
+    c.a = 0.0;
+    if (t < te) {
         if (src == kSrcProducts) {
             const int32_t k = P.A.col[t];
-            a = P.A.val[t];
-            bb = P.B.beg[k];
-            len = (int32_t)(P.B.end[k] - bb);
+            c.a = P.A.val[t];
+            c.beg = P.B.beg[k];
+            c.len = (int32_t)(P.B.end[k] - c.beg);
         } else {
             const int ti = (int)t;
-            a = P.T.coef[ti];
+            c.a = P.T.coef[ti];
             if (P.T.beg[ti] == nullptr) {
-                bb = -1;
-                len = 1;
+                c.beg = -1;
+                c.len = 1;
             } else {
-                bb = P.T.beg[ti][r];
-                len = (int32_t)(P.T.end[ti][r] - bb);
+                c.beg = P.T.beg[ti][r];
+                c.len = (int32_t)(P.T.end[ti][r] - c.beg);
             }
         }
     }
-    const int32_t inc = wave_incl_sum(len);
+    c.incl = wave_incl_sum(c.len);
+    c.total = __builtin_amdgcn_readlane(c.incl, kWave - 1);
+    c.nterms = (int32_t)min<int64_t>(kChunk, te - t0);
+    return c;
+}
+
+__device__ __forceinline__ void stage_chunk(const Chunk& c, WaveStage& st)
+{
+    const int l = lane();
     wave_sync();  // earlier readers of the staging area are done
-    if (l < kChunk) {
-        st.excl[l] = inc - len;
-        st.len[l] = len;
-        st.beg[l] = bb;
-        st.a[l] = a;
-    }
+    st.excl[l] = c.incl - c.len;
+    st.beg[l] = c.beg;
     wave_sync();
-    return __shfl(inc, kWave - 1, kWave);
 }
 
 // Largest term index i of the chunk with excl[i] <= q.
@@ -469,24 +492,17 @@ __device__ __forceinline__ int find_term(const WaveStage& st, int32_t q)
     return k;
 }
 
+// Marks window offset d (clamped to the guard offset: bit 0 of the guard word
+// records a column outside the window, which the row information of
+// consistent operands excludes).
 template <bool kGlobal>
-__device__ __forceinline__ void mark_d(uint32_t d, uint8_t* bytes, uint2* bmp)
+__device__ __forceinline__ void mark_d(uint32_t d, uint32_t guard, uint8_t* bytes, uint2* bmp)
 {
+    d = min(d, guard);
     if (kGlobal)
         bytes[d] = 1;
     else
         atomicOr(&bmp[d >> 5].x, 1u << (d & 31u));
-}
-
-// Window offset of a loaded column; out-of-window columns (impossible when
-// the row information is consistent) are recorded in `bad` and ignored.
-__device__ __forceinline__ uint32_t window_d(int32_t c, int32_t lo, uint32_t W, bool& ok, uint32_t& bad)
-{
-    const uint32_t d = (uint32_t)(c - lo);
-    const bool in = d < W;
-    bad |= (ok && !in) ? 1u : 0u;
-    ok = ok && in;
-    return ok ? d : 0u;
 }
 
 // ---- flattened batches (short term rows) ------------------------------------
@@ -528,35 +544,32 @@ __device__ __forceinline__ void gather(const StageArgs& P, const WaveStage& st, 
 }
 
 template <bool kGlobal>
-__device__ __forceinline__ void mark_batch(int32_t lo, uint32_t W, Batch& b, uint8_t* bytes, uint2* bmp, uint32_t& bad)
+__device__ __forceinline__ void mark_batch(int32_t lo, uint32_t guard, const Batch& b, uint8_t* bytes, uint2* bmp)
 {
 #pragma unroll
-    for (int j = 0; j < kU; ++j) {
-        bool ok = b.ok[j];
-        const uint32_t d = window_d(b.c[j], lo, W, ok, bad);
-        if (ok) mark_d<kGlobal>(d, bytes, bmp);
-    }
+    for (int j = 0; j < kU; ++j)
+        if (b.ok[j]) mark_d<kGlobal>((uint32_t)(b.c[j] - lo), guard, bytes, bmp);
 }
 
 // acc[rank] = fma(a, v, acc[rank]) in term order: each 64-product sub-batch
 // is applied one term at a time (the products of one term have distinct
 // columns, so a term's read-modify-writes never collide).
-__device__ __forceinline__ void accumulate_batch(const WaveStage& st, int32_t q0, int32_t total, int32_t lo, uint32_t W,
-                                                 Batch& b, const uint2* bmp, double* acc, uint32_t& bad)
+__device__ __forceinline__ void accumulate_batch(const Chunk& c, int32_t q0, int32_t lo, uint32_t guard,
+                                                 const Batch& b, const uint2* bmp, double* acc)
 {
 #pragma unroll
     for (int j = 0; j < kU; ++j) {
         const int32_t qj = q0 + j * kWave;
-        if (qj >= total) break;
+        if (qj >= c.total) break;
         const double v = b.v[j];
-        bool ok = b.ok[j];
-        const uint32_t d = window_d(b.c[j], lo, W, ok, bad);
-        const uint32_t slot = rank_of(bmp, d);
-        const int last = min(kWave - 1, total - qj - 1);
+        const bool ok = b.ok[j];
+        const uint32_t slot = rank_of(bmp, ok ? (uint32_t)(b.c[j] - lo) : guard);
+        const int last = min(kWave - 1, c.total - qj - 1);
         const int kf = __builtin_amdgcn_readlane(b.kidx[j], 0);
         const int kl = __builtin_amdgcn_readlane(b.kidx[j], last);
         for (int kk = kf; kk <= kl; ++kk) {
-            if (ok && b.kidx[j] == kk) acc[slot] = fma(st.a[kk], v, acc[slot]);
+            const double a = readlaned(c.a, kk);
+            if (ok && b.kidx[j] == kk) acc[slot] = fma(a, v, acc[slot]);
             wave_sync();
         }
     }
@@ -578,67 +591,38 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* base, int
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes, kRsrcWord3);
 }
 
-// Lane t < nterms holds term t of the staged chunk.
-struct ChunkRegs {
-    int32_t len;
-    int64_t beg;
-    double a;
-};
-
-__device__ __forceinline__ ChunkRegs chunk_regs(const WaveStage& st, int nterms)
-{
-    const int l = lane();
-    ChunkRegs c{0, -1, 0.0};
-    if (l < nterms) {
-        c.len = st.len[l];
-        c.beg = st.beg[l];
-        c.a = st.a[l];
-    }
-    return c;
-}
-
-__device__ __forceinline__ int64_t readlane64(int64_t x, int i)
-{
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(uint64_t)x, i);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)x >> 32), i);
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
 // Uniform description of one term.
-struct TermDesc {
+struct TermInfo {
     int32_t len;  // entries of the term row; 0: no term
     bool ident;   // identity row (coefficient term of P_0): the single entry (r, 1)
     double a;     // weight
+};
+struct TermDesc {
+    TermInfo t;
     __amdgpu_buffer_rsrc_t rc, rv;
 };
 
+// Term i of the chunk (i may point past the chunk's terms: no term).
 template <int SRC, bool kNeedV>
-__device__ __forceinline__ TermDesc term_desc(const StageArgs& P, int64_t t0, const ChunkRegs& cr, int i, int nterms)
+__device__ __forceinline__ TermDesc term_desc(const StageArgs& P, int64_t t0, const Chunk& c, int i)
 {
     TermDesc h;
-    h.len = 0;
-    h.ident = false;
-    h.a = 0.0;
+    const int il = min(i, kChunk - 1);
+    h.t.len = (i < c.nterms) ? __builtin_amdgcn_readlane(c.len, il) : 0;
+    const int64_t beg = readlane64(c.beg, il);
+    h.t.a = kNeedV ? readlaned(c.a, il) : 0.0;
+    h.t.ident = SRC == kSrcCoefs && h.t.len > 0 && beg < 0;
     const int32_t* cb = P.dummy_col;
     const double* vb = P.dummy_val;
     int32_t real = 0;
-    if (i < nterms) {
-        const int32_t len = __builtin_amdgcn_readlane(cr.len, i);
-        const int64_t beg = readlane64(cr.beg, i);
-        if (kNeedV) h.a = __longlong_as_double(readlane64(__double_as_longlong(cr.a), i));
-        if (SRC == kSrcCoefs && beg < 0) {
-            h.ident = true;
-            h.len = 1;
-        } else if (len > 0) {
-            h.len = len;
-            real = len;
-            if (SRC == kSrcProducts) {
-                cb = P.B.col + beg;
-                vb = P.B.val + beg;
-            } else {
-                cb = P.T.col[t0 + i] + beg;
-                vb = P.T.val[t0 + i] + beg;
-            }
+    if (!h.t.ident && h.t.len > 0) {
+        real = h.t.len;
+        if (SRC == kSrcProducts) {
+            cb = P.B.col + beg;
+            vb = P.B.val + beg;
+        } else {
+            cb = P.T.col[t0 + il] + beg;
+            vb = P.T.val[t0 + il] + beg;
         }
     }
     h.rc = row_rsrc(cb, real * 4);
@@ -668,55 +652,39 @@ __device__ __forceinline__ Part load_part(const TermDesc& h, int32_t e0)
     return p;
 }
 
-// Structure pass over one part: marks the in-window columns and records
-// out-of-window ones in the wave-uniform mask `badm`.
+// Structure pass over one part.
 template <bool kGlobal>
-__device__ __forceinline__ void mark_part(const TermDesc& h, int32_t e0, const Part& p, int64_t r, int32_t lo,
-                                          uint32_t W, uint8_t* bytes, uint2* bmp, unsigned long long& badm)
+__device__ __forceinline__ void mark_part(const TermInfo& h, int32_t e0, const Part& p, int64_t r, int32_t lo,
+                                          uint32_t guard, uint8_t* bytes, uint2* bmp)
 {
     const int l = lane();
     const int32_t c0 = h.ident ? (int32_t)r : p.c0;
-    const bool ok0 = e0 + l < h.len;
-    const uint32_t d0 = (uint32_t)(c0 - lo);
-    badm |= __ballot(ok0 && !(d0 < W));
-    if (ok0 && d0 < W) mark_d<kGlobal>(d0, bytes, bmp);
-    if (h.len > e0 + kWave) {
-        const bool ok1 = e0 + kWave + l < h.len;
-        const uint32_t d1 = (uint32_t)(p.c1 - lo);
-        badm |= __ballot(ok1 && !(d1 < W));
-        if (ok1 && d1 < W) mark_d<kGlobal>(d1, bytes, bmp);
-    }
-}
-
-// Accumulator slot of window offset d (the guard offset maps to the spare
-// slot behind the row's entries).
-__device__ __forceinline__ uint32_t slot_of(const uint2* bmp, uint32_t d)
-{
-    const uint2 w = bmp[d >> 5];
-    return w.y + (uint32_t)__popc(__builtin_amdgcn_ubfe(w.x, 0u, d));
+    if (e0 + l < h.len) mark_d<kGlobal>((uint32_t)(c0 - lo), guard, bytes, bmp);
+    if (h.len > e0 + kWave && e0 + kWave + l < h.len) mark_d<kGlobal>((uint32_t)(p.c1 - lo), guard, bytes, bmp);
 }
 
 struct Slots {
     uint32_t s0, s1;
 };
 
-// Slots of a part's entries; lanes without an entry get the spare slot.  All
-// columns of the row lie in the window (checked by the structure pass).
-__device__ __forceinline__ Slots part_slots(const TermDesc& h, int32_t e0, const Part& p, int64_t r, int32_t lo,
+// Accumulator slots of a part's entries; lanes without an entry get the spare
+// slot.  Every column of the row lies in the window (checked after the
+// structure pass).
+__device__ __forceinline__ Slots part_slots(const TermInfo& h, int32_t e0, const Part& p, int64_t r, int32_t lo,
                                             uint32_t guard, const uint2* bmp)
 {
     const int l = lane();
     const int32_t c0 = h.ident ? (int32_t)r : p.c0;
     Slots s;
-    s.s0 = slot_of(bmp, (e0 + l < h.len) ? (uint32_t)(c0 - lo) : guard);
+    s.s0 = rank_of(bmp, (e0 + l < h.len) ? (uint32_t)(c0 - lo) : guard);
     s.s1 = 0;
-    if (h.len > e0 + kWave) s.s1 = slot_of(bmp, (e0 + kWave + l < h.len) ? (uint32_t)(p.c1 - lo) : guard);
+    if (h.len > e0 + kWave) s.s1 = rank_of(bmp, (e0 + kWave + l < h.len) ? (uint32_t)(p.c1 - lo) : guard);
     return s;
 }
 
 // acc[slot] = fma(a, v, acc[slot]) for a part's entries (one term: distinct
 // columns, so no two lanes touch one slot other than the spare).
-__device__ __forceinline__ void accumulate_part(const TermDesc& h, int32_t e0, const Part& p, const Slots& s,
+__device__ __forceinline__ void accumulate_part(const TermInfo& h, int32_t e0, const Part& p, const Slots& s,
                                                 double* acc)
 {
     const double v0 = h.ident ? 1.0 : p.v0;
@@ -730,84 +698,108 @@ __device__ __forceinline__ void accumulate_part(const TermDesc& h, int32_t e0, c
     }
 }
 
-template <int SRC, bool kAccum, bool kGlobal>
-__device__ __forceinline__ void per_term_pass(const StageArgs& P, int64_t r, int64_t t0, int nterms,
-                                              const WaveStage& st, int32_t lo, uint32_t W, uint32_t guard,
-                                              uint8_t* bytes, uint2* bmp, double* acc, uint32_t& bad)
+// Issues the loads of the first part of the group's term rows.
+template <int SRC, bool kNeedV>
+__device__ __forceinline__ void issue_group(const StageArgs& P, int64_t t0, const Chunk& c, int i0, TermInfo* h,
+                                            Part* p)
 {
-    const ChunkRegs cr = chunk_regs(st, nterms);
-    unsigned long long badm = 0;
-    for (int i0 = 0; i0 < nterms; i0 += kGroup) {
-        TermDesc h[kGroup];
-        Part p[kGroup];
+#pragma unroll
+    for (int g = 0; g < kGroup; ++g) {
+        const TermDesc d = term_desc<SRC, kNeedV>(P, t0, c, i0 + g);
+        h[g] = d.t;
+        p[g] = load_part<kNeedV>(d, 0);
+    }
+}
+
+// Applies a loaded group: structure marks, or the ranks of the whole group
+// first (the bitmap is read-only then) and the read-modify-writes strictly
+// term by term.  Rows longer than kStep continue right after their first part.
+template <int SRC, bool kAccum, bool kGlobal>
+__device__ __forceinline__ void run_group(const StageArgs& P, int64_t r, int64_t t0, const Chunk& c, int i0,
+                                          const TermInfo* h, const Part* p, int32_t lo, uint32_t guard,
+                                          uint8_t* bytes, uint2* bmp, double* acc)
+{
+    if (!kAccum) {
 #pragma unroll
         for (int g = 0; g < kGroup; ++g) {
-            h[g] = term_desc<SRC, kAccum>(P, t0, cr, i0 + g, nterms);
-            p[g] = load_part<kAccum>(h[g], 0);
-        }
-        if (!kAccum) {
-#pragma unroll
-            for (int g = 0; g < kGroup; ++g) {
-                if (h[g].len == 0) continue;
-                mark_part<kGlobal>(h[g], 0, p[g], r, lo, W, bytes, bmp, badm);
+            if (h[g].len == 0) continue;
+            mark_part<kGlobal>(h[g], 0, p[g], r, lo, guard, bytes, bmp);
+            if (h[g].len > kStep) {
+                const TermDesc d = term_desc<SRC, false>(P, t0, c, i0 + g);
                 for (int32_t e0 = kStep; e0 < h[g].len; e0 += kStep)
-                    mark_part<kGlobal>(h[g], e0, load_part<false>(h[g], e0), r, lo, W, bytes, bmp, badm);
+                    mark_part<kGlobal>(h[g], e0, load_part<false>(d, e0), r, lo, guard, bytes, bmp);
             }
-        } else {
-            // the ranks of the whole group first (the bitmap is read-only
-            // here), then the read-modify-writes strictly term by term
-            Slots s[kGroup];
+        }
+    } else {
+        Slots s[kGroup];
 #pragma unroll
-            for (int g = 0; g < kGroup; ++g) s[g] = part_slots(h[g], 0, p[g], r, lo, guard, bmp);
+        for (int g = 0; g < kGroup; ++g) s[g] = part_slots(h[g], 0, p[g], r, lo, guard, bmp);
 #pragma unroll
-            for (int g = 0; g < kGroup; ++g) {
-                if (h[g].len == 0) continue;
-                accumulate_part(h[g], 0, p[g], s[g], acc);
-                wave_sync();
+        for (int g = 0; g < kGroup; ++g) {
+            if (h[g].len == 0) continue;
+            accumulate_part(h[g], 0, p[g], s[g], acc);
+            wave_sync();
+            if (h[g].len > kStep) {
+                const TermDesc d = term_desc<SRC, true>(P, t0, c, i0 + g);
                 for (int32_t e0 = kStep; e0 < h[g].len; e0 += kStep) {
-                    const Part q = load_part<true>(h[g], e0);
+                    const Part q = load_part<true>(d, e0);
                     accumulate_part(h[g], e0, q, part_slots(h[g], e0, q, r, lo, guard, bmp), acc);
                     wave_sync();
                 }
             }
         }
     }
-    if (badm) bad = 1u;
+}
+
+// The terms of one chunk, kGroup at a time.  (Keeping the next group's loads
+// in flight as well costs more in occupancy than it saves.)
+template <int SRC, bool kAccum, bool kGlobal>
+__device__ __forceinline__ void per_term_pass(const StageArgs& P, int64_t r, int64_t t0, const Chunk& c, int32_t lo,
+                                              uint32_t guard, uint8_t* bytes, uint2* bmp, double* acc)
+{
+    for (int i0 = 0; i0 < c.nterms; i0 += kGroup) {
+        TermInfo h[kGroup];
+        Part p[kGroup];
+        issue_group<SRC, kAccum>(P, t0, c, i0, h, p);
+        run_group<SRC, kAccum, kGlobal>(P, r, t0, c, i0, h, p, lo, guard, bytes, bmp, acc);
+    }
 }
 
 // Long term rows go step by step, short ones in flattened batches
 // (coefficient terms always step by step).
-__device__ __forceinline__ bool use_per_term(int src, int32_t total, int nterms)
+__device__ __forceinline__ bool use_per_term(int src, const Chunk& c)
 {
-    return src == kSrcCoefs || total >= 16 * nterms;
+    return src == kSrcCoefs || c.total >= 16 * c.nterms;
 }
 
 // One pass over all terms of a source.  kAccum = false marks the structure,
-// kAccum = true accumulates in term order.  If `first_loaded`, the staging
-// area already holds the chunk at tb with `total0` products.
+// kAccum = true accumulates in term order.  If `have_first`, `first` is the
+// chunk at the first term, already loaded (and staged if it takes the
+// flattened path).
 template <bool kAccum, bool kGlobal>
-__device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t r, int32_t lo, uint32_t W,
-                                           uint32_t guard, uint8_t* bytes, uint2* bmp, double* acc, WaveStage& st,
-                                           bool first_loaded, int32_t total0, uint32_t& bad)
+__device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t r, int32_t lo, uint32_t guard,
+                                           uint8_t* bytes, uint2* bmp, double* acc, WaveStage& st,
+                                           bool have_first, const Chunk& first)
 {
     int64_t tb, te;
     term_range(P, src, r, &tb, &te);
     for (int64_t t0 = tb; t0 < te; t0 += kChunk) {
-        const int32_t total = (first_loaded && t0 == tb) ? total0 : load_chunk(P, src, r, t0, te, st);
-        const int nterms = (int)min<int64_t>(kChunk, te - t0);
-        if (use_per_term(src, total, nterms)) {
+        const bool pre = have_first && t0 == tb;
+        const Chunk c = pre ? first : load_chunk(P, src, r, t0, te);
+        if (use_per_term(src, c)) {
             if (src == kSrcProducts)
-                per_term_pass<kSrcProducts, kAccum, kGlobal>(P, r, t0, nterms, st, lo, W, guard, bytes, bmp, acc, bad);
+                per_term_pass<kSrcProducts, kAccum, kGlobal>(P, r, t0, c, lo, guard, bytes, bmp, acc);
             else
-                per_term_pass<kSrcCoefs, kAccum, kGlobal>(P, r, t0, nterms, st, lo, W, guard, bytes, bmp, acc, bad);
+                per_term_pass<kSrcCoefs, kAccum, kGlobal>(P, r, t0, c, lo, guard, bytes, bmp, acc);
         } else {
-            for (int32_t q0 = 0; q0 < total; q0 += kWave * kU) {
+            if (!pre) stage_chunk(c, st);
+            for (int32_t q0 = 0; q0 < c.total; q0 += kWave * kU) {
                 Batch b;
-                gather<kAccum>(P, st, q0, total, b);
+                gather<kAccum>(P, st, q0, c.total, b);
                 if (kAccum)
-                    accumulate_batch(st, q0, total, lo, W, b, bmp, acc, bad);
+                    accumulate_batch(c, q0, lo, guard, b, bmp, acc);
                 else
-                    mark_batch<kGlobal>(lo, W, b, bytes, bmp, bad);
+                    mark_batch<kGlobal>(lo, guard, b, bytes, bmp);
             }
         }
     }
@@ -844,46 +836,44 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
     const int32_t lo = P.lo[r];
     const int64_t words = ((int64_t)W + 31) >> 5;
     if (words > max_words) return false;
+    const uint32_t guard = (uint32_t)(words * 32);
     const int main_src = (P.mode == kModeProduct) ? kSrcProducts : kSrcCoefs;
     const bool has_extra = P.has_e || P.has_blk;
-    uint32_t bad = 0;
 
-    // 1. structure of the row inside its window (extra part first, main last,
-    //    so that the staging area ends up holding the main terms)
+    // 1. structure of the row inside its window, guard word included
     if (kGlobal) {
         uint32_t* b4 = reinterpret_cast<uint32_t*>(bytes);
-        for (int64_t i = l; i < words * 8; i += kWave) b4[i] = 0u;
+        for (int64_t i = l; i < (words + 1) * 8; i += kWave) b4[i] = 0u;
     } else {
-        for (int64_t w = l; w < words; w += kWave) bmp[w].x = 0u;
+        for (int64_t w = l; w <= words; w += kWave) bmp[w].x = 0u;
     }
     wave_sync();
-    if (P.has_blk)
-        terms_pass<false, kGlobal>(P, kSrcCoefs, r, lo, (uint32_t)W, 0u, bytes, bmp, nullptr, st, false, 0, bad);
+    const Chunk none{};
+    if (P.has_blk) terms_pass<false, kGlobal>(P, kSrcCoefs, r, lo, guard, bytes, bmp, nullptr, st, false, none);
     if (P.has_e) {
-        for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave) {
-            bool ok = true;
-            const uint32_t d = window_d(P.E.col[p], lo, (uint32_t)W, ok, bad);
-            if (ok) mark_d<kGlobal>(d, bytes, bmp);
-        }
+        for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave)
+            mark_d<kGlobal>((uint32_t)(P.E.col[p] - lo), guard, bytes, bmp);
     }
     int64_t tb, te;
     term_range(P, main_src, r, &tb, &te);
-    const int32_t total0 = load_chunk(P, main_src, r, tb, te, st);
+    const Chunk c0 = load_chunk(P, main_src, r, tb, te);
     const bool one_chunk = (te - tb <= kChunk);
-    const bool single = one_chunk && (total0 <= kWave * kU) && !use_per_term(main_src, total0, (int)(te - tb));
+    const bool flat0 = !use_per_term(main_src, c0);
+    if (flat0) stage_chunk(c0, st);
+    const bool single = one_chunk && flat0 && (c0.total <= kWave * kU);
     Batch b1;
     if (single) {
-        if (total0 > 0) {
-            gather<true>(P, st, 0, total0, b1);
-            mark_batch<kGlobal>(lo, (uint32_t)W, b1, bytes, bmp, bad);
+        if (c0.total > 0) {
+            gather<true>(P, st, 0, c0.total, b1);
+            mark_batch<kGlobal>(lo, guard, b1, bytes, bmp);
         }
     } else {
-        terms_pass<false, kGlobal>(P, main_src, r, lo, (uint32_t)W, 0u, bytes, bmp, nullptr, st, true, total0, bad);
+        terms_pass<false, kGlobal>(P, main_src, r, lo, guard, bytes, bmp, nullptr, st, true, c0);
     }
     wave_sync();
-    if (kGlobal) {  // pack the byte map into bits
+    if (kGlobal) {  // pack the byte map into bits, guard word included
         const uint32_t* b4 = reinterpret_cast<const uint32_t*>(bytes);
-        for (int64_t w = l; w < words; w += kWave) {
+        for (int64_t w = l; w <= words; w += kWave) {
             uint32_t bits = 0;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
@@ -897,7 +887,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
 
     // a column outside the row's window means the row information of an
     // operand was inconsistent: the stage reports an error, the row stays empty
-    if (__ballot(bad != 0u)) {
+    if (bmp[words].x & 1u) {
         flag_error(P, kErrColumnOutsideWindow);
         if (l == 0) {
             P.out.end[r] = o;
@@ -908,7 +898,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
     }
 
     // 2. prefix counts of the bitmap words: rank(column) = slot; the guard
-    //    word behind the window maps to the spare accumulator slot `cap`
+    //    word maps to the spare accumulator slot `cap`
     uint32_t running = 0;
     for (int64_t w0 = 0; w0 < words; w0 += kWave) {
         const int64_t w = w0 + l;
@@ -918,7 +908,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
         running += __shfl(inc, kWave - 1, kWave);
     }
     const int64_t ns = running;
-    const uint32_t guard = (uint32_t)(words * 32);
+    wave_sync();
     if (l == 0) bmp[words] = make_uint2(0u, (uint32_t)cap);
     if (ns > cap) return false;
     if (o + ns > P.out.cap) {
@@ -949,10 +939,9 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
 
     // 4. main terms in order, parked; then the extra part on its own
     if (single) {
-        if (total0 > 0) accumulate_batch(st, 0, total0, lo, (uint32_t)W, b1, bmp, acc, bad);
+        if (c0.total > 0) accumulate_batch(c0, 0, lo, guard, b1, bmp, acc);
     } else {
-        terms_pass<true, kGlobal>(P, main_src, r, lo, (uint32_t)W, guard, nullptr, bmp, acc, st, one_chunk, total0,
-                                  bad);
+        terms_pass<true, kGlobal>(P, main_src, r, lo, guard, nullptr, bmp, acc, st, one_chunk, c0);
     }
     wave_sync();
     double preg[kParked];
@@ -975,14 +964,10 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
             }
         }
         wave_sync();
-        if (P.has_blk)
-            terms_pass<true, kGlobal>(P, kSrcCoefs, r, lo, (uint32_t)W, guard, nullptr, bmp, acc, st, false, 0, bad);
+        if (P.has_blk) terms_pass<true, kGlobal>(P, kSrcCoefs, r, lo, guard, nullptr, bmp, acc, st, false, none);
         if (P.has_e) {
-            for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave) {
-                bool ok = true;
-                const uint32_t d = window_d(P.E.col[p], lo, (uint32_t)W, ok, bad);
-                if (ok) acc[rank_of(bmp, d)] = P.E.val[p];
-            }
+            for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave)
+                acc[rank_of(bmp, (uint32_t)(P.E.col[p] - lo))] = P.E.val[p];
         }
         wave_sync();
     }
@@ -1037,7 +1022,9 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
 }
 
 // One row per wavefront, four rows per block, blocks in XCD-aware order.
-__global__ void __launch_bounds__(kBlock) k_numeric_lds(StageArgs P)
+// The shared-memory workspace (25.7 KB per block) and the register budget
+// (80 per lane) are sized for six wavefronts per SIMD.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) k_numeric_lds(StageArgs P)
 {
     __shared__ LdsWave lds[kWavesPerBlock];
     __shared__ unsigned long long kept_sh[kWavesPerBlock];
@@ -1077,7 +1064,7 @@ __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
     if (slot >= P.g_slots) return;
     uint32_t* base = P.g_scratch + slot * P.g_slot_stride;
     uint8_t* bytes = reinterpret_cast<uint8_t*>(base);
-    uint2* bmp = reinterpret_cast<uint2*>(base + P.g_slot_words * 8);
+    uint2* bmp = reinterpret_cast<uint2*>(base + (P.g_slot_words + 1) * 8);
     double* acc = reinterpret_cast<double*>(base + P.g_off_acc);
     double* ebuf = reinterpret_cast<double*>(base + P.g_off_ebuf);
     const unsigned long long count = __hip_atomic_load(&P.ctr->fb_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
