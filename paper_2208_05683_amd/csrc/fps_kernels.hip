@@ -510,21 +510,22 @@ __device__ __forceinline__ void mark_d(uint32_t d, uint32_t guard, uint8_t* byte
 // without a product read a zeroed dummy row), so loads stay in flight until
 // the values are used.
 
+template <int U>
 struct Batch {
-    int32_t c[kU];
-    double v[kU];
-    int kidx[kU];
-    bool ok[kU];
+    int32_t c[U];
+    double v[U];
+    int kidx[U];
+    bool ok[U];
 };
 
 // Products only: coefficient terms always take the per-term path, whose term
 // index is uniform across the wavefront.
-template <bool kNeedV>
-__device__ __forceinline__ void gather(const StageArgs& P, const WaveStage& st, int32_t q0, int32_t total, Batch& b)
+template <bool kNeedV, int U>
+__device__ __forceinline__ void gather(const StageArgs& P, const WaveStage& st, int32_t q0, int32_t total, Batch<U>& b)
 {
     const int l = lane();
 #pragma unroll
-    for (int j = 0; j < kU; ++j) {
+    for (int j = 0; j < U; ++j) {
         const int32_t q = q0 + j * kWave + l;
         b.ok[j] = q < total;
         const int k = find_term(st, b.ok[j] ? q : total - 1);
@@ -543,22 +544,23 @@ __device__ __forceinline__ void gather(const StageArgs& P, const WaveStage& st, 
     }
 }
 
-template <bool kGlobal>
-__device__ __forceinline__ void mark_batch(int32_t lo, uint32_t guard, const Batch& b, uint8_t* bytes, uint2* bmp)
+template <bool kGlobal, int U>
+__device__ __forceinline__ void mark_batch(int32_t lo, uint32_t guard, const Batch<U>& b, uint8_t* bytes, uint2* bmp)
 {
 #pragma unroll
-    for (int j = 0; j < kU; ++j)
+    for (int j = 0; j < U; ++j)
         if (b.ok[j]) mark_d<kGlobal>((uint32_t)(b.c[j] - lo), guard, bytes, bmp);
 }
 
 // acc[rank] = fma(a, v, acc[rank]) in term order: each 64-product sub-batch
 // is applied one term at a time (the products of one term have distinct
 // columns, so a term's read-modify-writes never collide).
+template <int U>
 __device__ __forceinline__ void accumulate_batch(const Chunk& c, int32_t q0, int32_t lo, uint32_t guard,
-                                                 const Batch& b, const uint2* bmp, double* acc)
+                                                 const Batch<U>& b, const uint2* bmp, double* acc)
 {
 #pragma unroll
-    for (int j = 0; j < kU; ++j) {
+    for (int j = 0; j < U; ++j) {
         const int32_t qj = q0 + j * kWave;
         if (qj >= c.total) break;
         const double v = b.v[j];
@@ -583,7 +585,9 @@ __device__ __forceinline__ void accumulate_batch(const Chunk& c, int32_t q0, int
 // are applied one after the other.  Entries beyond kStep (rows longer than
 // 128) are handled right after their term's first part.
 
-constexpr int kGroup = 4;
+constexpr int kGroup = 4;  // terms per group (products; coefficient terms go two at a time, which keeps
+                           // the register budget while the main part is parked in registers)
+__host__ __device__ constexpr int group_size(int src) { return src == 0 ? kGroup : 2; }
 constexpr int kRsrcWord3 = 0x00020000;  // raw (unswizzled, stride 0) buffer of 32-bit elements
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* base, int32_t bytes)
@@ -704,7 +708,7 @@ __device__ __forceinline__ void issue_group(const StageArgs& P, int64_t t0, cons
                                             Part* p)
 {
 #pragma unroll
-    for (int g = 0; g < kGroup; ++g) {
+    for (int g = 0; g < group_size(SRC); ++g) {
         const TermDesc d = term_desc<SRC, kNeedV>(P, t0, c, i0 + g);
         h[g] = d.t;
         p[g] = load_part<kNeedV>(d, 0);
@@ -721,7 +725,7 @@ __device__ __forceinline__ void run_group(const StageArgs& P, int64_t r, int64_t
 {
     if (!kAccum) {
 #pragma unroll
-        for (int g = 0; g < kGroup; ++g) {
+        for (int g = 0; g < group_size(SRC); ++g) {
             if (h[g].len == 0) continue;
             mark_part<kGlobal>(h[g], 0, p[g], r, lo, guard, bytes, bmp);
             if (h[g].len > kStep) {
@@ -733,9 +737,9 @@ __device__ __forceinline__ void run_group(const StageArgs& P, int64_t r, int64_t
     } else {
         Slots s[kGroup];
 #pragma unroll
-        for (int g = 0; g < kGroup; ++g) s[g] = part_slots(h[g], 0, p[g], r, lo, guard, bmp);
+        for (int g = 0; g < group_size(SRC); ++g) s[g] = part_slots(h[g], 0, p[g], r, lo, guard, bmp);
 #pragma unroll
-        for (int g = 0; g < kGroup; ++g) {
+        for (int g = 0; g < group_size(SRC); ++g) {
             if (h[g].len == 0) continue;
             accumulate_part(h[g], 0, p[g], s[g], acc);
             wave_sync();
@@ -757,7 +761,7 @@ template <int SRC, bool kAccum, bool kGlobal>
 __device__ __forceinline__ void per_term_pass(const StageArgs& P, int64_t r, int64_t t0, const Chunk& c, int32_t lo,
                                               uint32_t guard, uint8_t* bytes, uint2* bmp, double* acc)
 {
-    for (int i0 = 0; i0 < c.nterms; i0 += kGroup) {
+    for (int i0 = 0; i0 < c.nterms; i0 += group_size(SRC)) {
         TermInfo h[kGroup];
         Part p[kGroup];
         issue_group<SRC, kAccum>(P, t0, c, i0, h, p);
@@ -794,7 +798,7 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
         } else {
             if (!pre) stage_chunk(c, st);
             for (int32_t q0 = 0; q0 < c.total; q0 += kWave * kU) {
-                Batch b;
+                Batch<kU> b;
                 gather<kAccum>(P, st, q0, c.total, b);
                 if (kAccum)
                     accumulate_batch(c, q0, lo, guard, b, bmp, acc);
@@ -813,8 +817,8 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
 // order; the main terms accumulated in order and parked (registers in the
 // shared-memory kernel, `ebuf` in the device-memory kernel); the extra part
 // (fused block terms or E) accumulated on its own; x = extra + main; the drop
-// test and a sorted, coalesced write-out.  Rows whose main terms fit one
-// flattened batch keep their products in registers from the structure pass to
+// test and a sorted, coalesced write-out.  Rows whose main terms are at most
+// 64 short-row products keep them in registers from the structure pass to
 // the accumulation.
 template <bool kGlobal>
 __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8_t* bytes, uint2* bmp, double* acc,
@@ -860,8 +864,8 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8
     const bool one_chunk = (te - tb <= kChunk);
     const bool flat0 = !use_per_term(main_src, c0);
     if (flat0) stage_chunk(c0, st);
-    const bool single = one_chunk && flat0 && (c0.total <= kWave * kU);
-    Batch b1;
+    const bool single = one_chunk && flat0 && (c0.total <= kWave);
+    Batch<1> b1;
     if (single) {
         if (c0.total > 0) {
             gather<true>(P, st, 0, c0.total, b1);
