@@ -121,13 +121,13 @@ struct SlackMatrix {
 struct CanonMatrix {
     int64_t n = 0;
     int64_t cap = 0;
-    DevBuf rp, col, val, len_tmp, scan_tmp;
+    DevBuf rp, col, val;
 };
 
 // Per-row workspace shared by the stages of one engine.
 struct Workspace {
     int64_t n = 0;
-    DevBuf W, lo, ub, fb, scan_tmp, zspan, zamax, gscratch, counters, part, dummy;
+    DevBuf W, lo, ub, fb, blk_pre, zspan, zamax, gscratch, counters, part, dummy;
     int64_t g_words = 0, g_cap = 0, g_stride = 0, g_off_acc = 0, g_off_ebuf = 0, g_off_cols = 0;
     int64_t part_stride = 0;
     int32_t g_slots = 0;
@@ -142,7 +142,9 @@ struct Workspace {
         FPS_TRY(lo.ensure(sizeof(int32_t) * rows));
         FPS_TRY(ub.ensure(sizeof(int64_t) * rows));
         FPS_TRY(fb.ensure(sizeof(int64_t) * rows));
-        FPS_TRY(scan_tmp.ensure(sizeof(int64_t) * scan_tmp_elems(nn)));
+        FPS_TRY(blk_pre.ensure(sizeof(int64_t) * (size_t)(std::max({analyze_blocks(kModeProduct, nn),
+                                                                    analyze_blocks(kModeSum, nn),
+                                                                    offset_blocks(nn)}) + 1)));
         FPS_TRY(zspan.ensure(sizeof(int2) * rows));
         FPS_TRY(zamax.ensure(sizeof(double) * rows));
         FPS_TRY(counters.ensure(sizeof(StageCounters) * (size_t)stages));
@@ -312,8 +314,10 @@ struct Engine {
         a.g_slots = ws.g_slots;
         a.force_global = (flags & FPS_FLAG_FORCE_GLOBAL) ? 1 : 0;
         FPS_TRY(out.ensure_rows(n));
+        a.blk_pre = ws.blk_pre.as<int64_t>();
+        a.scan_shift = analyze_shift(a.mode);
+        a.out = out.out();  // the analysis writes the row offsets (out.off)
         HIP_TRY(launch_analyze(a, s));
-        HIP_TRY(launch_scan(ws.ub.as<int64_t>(), out.off.as<int64_t>(), n, ws.scan_tmp.as<int64_t>(), s));
         bool run_global = true;
         if (size || learned[(size_t)idx] < 0) {
             int64_t total = 0;
@@ -388,18 +392,17 @@ struct Engine {
         const int64_t n = m.n;
         c.n = n;
         FPS_TRY(c.rp.ensure(sizeof(int64_t) * (size_t)(n + 1)));
-        FPS_TRY(c.len_tmp.ensure(sizeof(int64_t) * (size_t)std::max<int64_t>(n, 1)));
-        FPS_TRY(c.scan_tmp.ensure(sizeof(int64_t) * scan_tmp_elems(n)));
         const int64_t want = std::max<int64_t>(m.cap, 1);
         if (want > c.cap) {
             FPS_TRY(c.col.ensure(sizeof(int32_t) * (size_t)want));
             FPS_TRY(c.val.ensure(sizeof(double) * (size_t)want));
             c.cap = want;
         }
-        HIP_TRY(launch_row_lengths(m.off.as<int64_t>(), m.end.as<int64_t>(), n, c.len_tmp.as<int64_t>(), s));
-        HIP_TRY(launch_scan(c.len_tmp.as<int64_t>(), c.rp.as<int64_t>(), n, c.scan_tmp.as<int64_t>(), s));
+        HIP_TRY(launch_row_offsets(m.off.as<int64_t>(), m.end.as<int64_t>(), n, c.rp.as<int64_t>(),
+                                   ws.blk_pre.as<int64_t>(), s));
         HIP_TRY(launch_compact(m.off.as<int64_t>(), m.end.as<int64_t>(), m.col.as<int32_t>(), m.val.as<double>(), n,
-                               c.rp.as<int64_t>(), c.col.as<int32_t>(), c.val.as<double>(), s));
+                               c.rp.as<int64_t>(), ws.blk_pre.as<int64_t>(), c.col.as<int32_t>(),
+                               c.val.as<double>(), s));
         return FPS_OK;
     }
 };
@@ -711,7 +714,8 @@ fps_status fps_plan_create_ex(fps_plan* out, const fps_csr_view* Z, const double
     p->rec.assign((size_t)stages, StageRecord{});
     if (flags & FPS_FLAG_TIMING) {
         p->ring.assign((size_t)kTimingRing * (size_t)stages * 2, nullptr);
-        for (auto& e : p->ring) HIP_TRY(hipEventCreate(&e));
+        // timestamps only: no system-scope fence (which would flush caches at every record)
+        for (auto& e : p->ring) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     }
     *out = p.release();
     return FPS_OK;

@@ -39,7 +39,7 @@ struct Terms {
 // Output of a stage in slack layout: row r may use [off[r], off[r+1]) and
 // the kernel writes end[r] = off[r] + kept entries.
 struct OutView {
-    const int64_t* off;  // n+1 (exclusive scan of the per-row upper bounds)
+    int64_t* off;  // n+1: row offsets (exclusive scan of the per-row upper bounds)
     int64_t* end;        // n
     int32_t* col;
     double* val;
@@ -89,7 +89,15 @@ struct StageArgs {
     // analysis outputs
     int32_t* W;   // window width (0 = empty row)
     int32_t* lo;  // first column of the window
-    int64_t* ub;  // upper bound of the row's stored entries (scanned in place into OutView::off)
+    int64_t* ub;  // upper bound of the row's stored entries
+    // Row offsets of the output: the analysis writes each row's offset within
+    // its block of 2^scan_shift rows into out.off and the block totals into
+    // blk_pre; a one-block scan turns blk_pre into the exclusive prefix of the
+    // totals and writes out.off[n]; the numeric kernel adds
+    // blk_pre[r >> scan_shift] to out.off[r] when it starts row r.
+    int64_t* blk_pre;
+    int32_t scan_shift;  // log2 of the rows per analysis block
+    int32_t scan_pad;
     OutView out;
     StageCounters* ctr;
     const int32_t* dummy_col;  // 128 zeroed entries read by inactive lanes
@@ -115,15 +123,21 @@ hipError_t launch_rowinfo_csr(const int64_t* row_ptr, const int32_t* col, const 
 hipError_t launch_validate_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n,
                                int64_t nnz, unsigned long long* err, hipStream_t s);
 hipError_t launch_analyze(const StageArgs& a, hipStream_t s);
-// exclusive scan of x[0..n) into y[0..n], y[n] = total; tmp needs scan_tmp_elems(n)
-size_t scan_tmp_elems(int64_t n);
-hipError_t launch_scan(const int64_t* x, int64_t* y, int64_t n, int64_t* tmp, hipStream_t s);
+// log2 of the rows per analysis block (the numeric kernel's offset fix-up)
+int analyze_shift(int32_t mode);
 hipError_t launch_numeric_lds(const StageArgs& a, int grid, hipStream_t s);
 hipError_t launch_numeric_global(const StageArgs& a, int grid, hipStream_t s);
-// row lengths end[r]-beg[r] into len[r]
-hipError_t launch_row_lengths(const int64_t* beg, const int64_t* end, int64_t n, int64_t* len, hipStream_t s);
+// Canonical row pointers of a slack matrix: rp[r] gets the row's offset
+// within its block of 256 rows, blk_pre the exclusive prefix of the block
+// totals, rp[n] the total.  launch_compact adds the block prefix to rp[r]
+// while it copies the rows.
+hipError_t launch_row_offsets(const int64_t* beg, const int64_t* end, int64_t n, int64_t* rp, int64_t* blk_pre,
+                              hipStream_t s);
+// exclusive scan in place of nblk block totals, total to *grand (one block)
+hipError_t launch_block_scan(int64_t* x, int64_t nblk, int64_t* grand, hipStream_t s);
 hipError_t launch_compact(const int64_t* beg, const int64_t* end, const int32_t* col, const double* val,
-                          int64_t n, const int64_t* row_ptr, int32_t* ocol, double* oval, hipStream_t s);
+                          int64_t n, int64_t* rp, const int64_t* blk_pre, int32_t* ocol, double* oval, hipStream_t s);
+int64_t offset_blocks(int64_t n);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, hipStream_t s);
 int numeric_waves_per_block();
 // Algorithm 1 helpers (adaptive filter)

@@ -115,6 +115,44 @@ __device__ __forceinline__ T block_sum_256(T x, T* sh)
     return t;
 }
 
+// Inclusive scan over the threads of a block; *total gets the block's sum.
+__device__ __forceinline__ int64_t block_incl_scan(int64_t x, int64_t* sh, int64_t* total)
+{
+    const int64_t inc = wave_incl_sum(x);
+    const int w = threadIdx.x / kWave;
+    if (lane() == kWave - 1) sh[w] = inc;
+    __syncthreads();
+    int64_t pre = 0, tot = 0;
+    for (int i = 0; i < kBlock / kWave; ++i) {
+        const int64_t v = sh[i];
+        pre += (i < w) ? v : 0;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + inc;
+}
+
+// Exclusive scan, in place, of the per-block totals x[0..nblk) written by a
+// row kernel; the grand total goes to *grand.  One block.
+__global__ void __launch_bounds__(kBlock) k_block_scan(int64_t* x, int64_t nblk, int64_t* grand)
+{
+    __shared__ int64_t sh[kBlock / kWave];
+    // thread t owns the contiguous range [t * per, (t + 1) * per)
+    const int64_t per = (nblk + kBlock - 1) / kBlock;
+    const int64_t b = min<int64_t>((int64_t)threadIdx.x * per, nblk), e = min<int64_t>(b + per, nblk);
+    int64_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += x[i];
+    int64_t tot = 0;
+    int64_t run = block_incl_scan(sum, sh, &tot) - sum;
+    for (int64_t i = b; i < e; ++i) {
+        const int64_t v = x[i];
+        x[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) *grand = tot;
+}
+
 // ---------------------------------------------------------------------------
 // Row information of a canonical CSR: (first, last) column and max |value|.
 // ---------------------------------------------------------------------------
@@ -173,10 +211,18 @@ __global__ void __launch_bounds__(kBlock) k_validate_csr(const int64_t* __restri
 // row whose bound is below skip_tau would be dropped entirely by D_tau and is
 // marked empty without computing it.
 // ---------------------------------------------------------------------------
+constexpr int kAnalyzeLanes = 16;  // lanes per row in the product analysis
+constexpr int kAnalyzeShiftProduct = 4;  // log2(kBlock / kAnalyzeLanes) rows per block
+constexpr int kAnalyzeShiftSum = 8;      // log2(kBlock) rows per block
+static_assert(kBlock / kAnalyzeLanes == (1 << kAnalyzeShiftProduct) && kBlock == (1 << kAnalyzeShiftSum),
+              "analysis block geometry");
+
 __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
 {
-    constexpr int G = 16;
+    constexpr int G = kAnalyzeLanes;
     __shared__ unsigned long long sh[3][kBlock / G];
+    __shared__ int64_t ubs[kBlock / G];
+    __shared__ int64_t blk_total;
     const int64_t blk = xcd_logical_block();
     const int64_t r = (blk * kBlock + threadIdx.x) / G;
     const int gl = threadIdx.x % G;
@@ -244,6 +290,7 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
             P.W[r] = W;
             P.lo[r] = lo;
             P.ub[r] = ub;
+            ubs[grp] = ub;
             // products counted as multiply-adds: the B rows plus, when fused, the block terms
             const int64_t work = prod + (P.has_blk ? elen : 0);
             if (skip) {
@@ -258,6 +305,7 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
         sh[0][grp] = prod_done;
         sh[1][grp] = prod_skip;
         sh[2][grp] = row_skip;
+        if (r >= P.n) ubs[grp] = 0;
     }
     __syncthreads();
     if (threadIdx.x < 3) {
@@ -265,14 +313,28 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
         for (int i = 0; i < kBlock / G; ++i) t += sh[threadIdx.x][i];
         P.part[threadIdx.x * P.part_stride + blk] = t;  // kPartProducts, kPartProductsSkipped, kPartRowsSkipped
     }
+    if (threadIdx.x == kBlock - 1) {  // offsets of the block's rows within the block
+        int64_t run = 0;
+        for (int i = 0; i < kBlock / G; ++i) {
+            const int64_t t = ubs[i];
+            ubs[i] = run;
+            run += t;
+        }
+        blk_total = run;
+    }
+    __syncthreads();
+    if (gl == 0 && r < P.n) P.out.off[r] = ubs[grp];
+    if (threadIdx.x == 0) P.blk_pre[blk] = blk_total;
 }
 
 __global__ void __launch_bounds__(kBlock) k_analyze_sum(StageArgs P)
 {
     __shared__ unsigned long long sh[kBlock / kWave];
+    __shared__ int64_t osh[kBlock / kWave];
     const int64_t blk = xcd_logical_block();
     const int64_t r = blk * kBlock + threadIdx.x;
     unsigned long long prod_done = 0;
+    int64_t ubv = 0;
     if (r < P.n) {
         int32_t lo = INT_MAX, hi = -1;
         int64_t prod = 0;
@@ -300,6 +362,7 @@ __global__ void __launch_bounds__(kBlock) k_analyze_sum(StageArgs P)
         P.W[r] = W;
         P.lo[r] = lo;
         P.ub[r] = ub;
+        ubv = ub;
         prod_done = (unsigned long long)prod;
     }
     const unsigned long long t = block_sum_256(prod_done, sh);
@@ -308,61 +371,10 @@ __global__ void __launch_bounds__(kBlock) k_analyze_sum(StageArgs P)
         P.part[kPartProductsSkipped * P.part_stride + blk] = 0;
         P.part[kPartRowsSkipped * P.part_stride + blk] = 0;
     }
-}
-
-// ---------------------------------------------------------------------------
-// Exclusive scan of int64 (two passes: tile sums, then tile scans with the
-// tile offset reduced from the preceding tile sums).
-// ---------------------------------------------------------------------------
-constexpr int kScanPer = 8;
-constexpr int kScanTile = kBlock * kScanPer;
-
-__global__ void __launch_bounds__(kBlock) k_scan_tiles(const int64_t* __restrict__ x, int64_t n, int64_t* tile_sum)
-{
-    __shared__ int64_t sh[kBlock / kWave];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile;
-    int64_t s = 0;
-    for (int i = 0; i < kScanPer; ++i) {
-        const int64_t j = base + (int64_t)i * kBlock + threadIdx.x;
-        if (j < n) s += x[j];
-    }
-    const int64_t t = block_sum_256(s, sh);
-    if (threadIdx.x == 0) tile_sum[blockIdx.x] = t;
-}
-
-__global__ void __launch_bounds__(kBlock) k_scan_apply(const int64_t* __restrict__ x, int64_t n,
-                                                      const int64_t* __restrict__ tile_sum, int64_t* y)
-{
-    __shared__ int64_t sh[kBlock / kWave];
-    __shared__ int64_t wsum[kBlock / kWave];
-    __shared__ int64_t base_off;
-    // offset of this tile
-    int64_t s = 0;
-    for (int64_t i = threadIdx.x; i < (int64_t)blockIdx.x; i += kBlock) s += tile_sum[i];
-    const int64_t off = block_sum_256(s, sh);
-    if (threadIdx.x == 0) base_off = off;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
-    int64_t v[kScanPer];
-    int64_t local = 0;
-    for (int i = 0; i < kScanPer; ++i) {
-        const int64_t j = base + i;
-        v[i] = (j < n) ? x[j] : 0;
-        local += v[i];
-    }
-    const int64_t inc = wave_incl_sum(local);
-    const int w = threadIdx.x / kWave;
-    if (lane() == kWave - 1) wsum[w] = inc;
-    __syncthreads();
-    int64_t wpre = 0;
-    for (int i = 0; i < w; ++i) wpre += wsum[i];
-    int64_t run = base_off + wpre + inc - local;
-    for (int i = 0; i < kScanPer; ++i) {
-        const int64_t j = base + i;
-        if (j < n) y[j] = run;
-        run += v[i];
-    }
-    if (base < n && base + kScanPer >= n) y[n] = run;  // the thread holding the last element
+    int64_t total = 0;
+    const int64_t inc = block_incl_scan(ubv, osh, &total);
+    if (r < P.n) P.out.off[r] = inc - ubv;
+    if (threadIdx.x == 0) P.blk_pre[blk] = total;
 }
 
 // ---------------------------------------------------------------------------
@@ -821,13 +833,12 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
 // 64 short-row products keep them in registers from the structure pass to
 // the accumulation.
 template <bool kGlobal>
-__device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, uint8_t* bytes, uint2* bmp, double* acc,
-                                            double* ebuf, WaveStage& st, int64_t max_words, int64_t cap,
+__device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64_t o, uint8_t* bytes, uint2* bmp,
+                                            double* acc, double* ebuf, WaveStage& st, int64_t max_words, int64_t cap,
                                             int64_t* kept_out)
 {
     const int l = lane();
     *kept_out = 0;
-    const int64_t o = P.out.off[r];
     const int32_t W = P.W[r];
     if (W <= 0) {
         if (l == 0) {
@@ -1039,9 +1050,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 
     const int64_t r = blk * kWavesPerBlock + wv;
     int64_t kept = 0;
     if (r < P.n) {
+        // the row's output offset: its block prefix plus its offset in the block
+        const int64_t o = P.blk_pre[r >> P.scan_shift] + P.out.off[r];
+        if (l == 0) P.out.off[r] = o;
         bool done = false;
         if (!P.force_global)
-            done = process_row<false>(P, r, nullptr, me.bmp, me.acc, nullptr, me.st, kLdsWords, kLdsCap, &kept);
+            done = process_row<false>(P, r, o, nullptr, me.bmp, me.acc, nullptr, me.st, kLdsWords, kLdsCap, &kept);
         if (!done && l == 0) {
             const unsigned long long i = atomicAdd(&P.ctr->fb_count, 1ull);
             P.fb_list[i] = r;
@@ -1080,7 +1094,7 @@ __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
         if (i >= count) break;
         const int64_t r = sgpr64(P.fb_list[i]);
         int64_t k = 0;
-        if (!process_row<true>(P, r, bytes, bmp, acc, ebuf, st[wv], P.g_slot_words, P.g_slot_cap, &k))
+        if (!process_row<true>(P, r, P.out.off[r], bytes, bmp, acc, ebuf, st[wv], P.g_slot_words, P.g_slot_cap, &k))
             flag_error(P, kErrCapacity);
         kept += (unsigned long long)k;
     }
@@ -1090,21 +1104,27 @@ __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
 // ---------------------------------------------------------------------------
 // Compaction of a slack matrix into canonical CSR.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_row_lengths(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
-                                                        int64_t n, int64_t* len)
+__global__ void __launch_bounds__(kBlock) k_row_offsets(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
+                                                        int64_t n, int64_t* rp, int64_t* blk_pre)
 {
+    __shared__ int64_t sh[kBlock / kWave];
     const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (r < n) len[r] = end[r] - beg[r];
+    const int64_t len = (r < n) ? end[r] - beg[r] : 0;
+    int64_t total = 0;
+    const int64_t inc = block_incl_scan(len, sh, &total);
+    if (r < n) rp[r] = inc - len;
+    if (threadIdx.x == 0) blk_pre[blockIdx.x] = total;
 }
 
 __global__ void __launch_bounds__(kBlock) k_compact(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
                                                     const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                    int64_t n, const int64_t* __restrict__ rp, int32_t* ocol,
-                                                    double* oval)
+                                                    int64_t n, int64_t* rp, const int64_t* __restrict__ blk_pre,
+                                                    int32_t* ocol, double* oval)
 {
     const int64_t r = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
     if (r >= n) return;
-    const int64_t b = beg[r], e = end[r], d = rp[r];
+    const int64_t b = beg[r], e = end[r], d = blk_pre[r >> 8] + rp[r];
+    if (lane() == 0) rp[r] = d;
     for (int64_t p = b + lane(); p < e; p += kWave) {
         ocol[d + (p - b)] = col[p];
         oval[d + (p - b)] = val[p];
@@ -1233,28 +1253,30 @@ hipError_t launch_validate_csr(const int64_t* row_ptr, const int32_t* col, const
     return hipGetLastError();
 }
 
+hipError_t launch_block_scan(int64_t* x, int64_t nblk, int64_t* grand, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(kBlock), 0, s, x, nblk, grand);
+    return hipGetLastError();
+}
+
 hipError_t launch_analyze(const StageArgs& a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
     if (a.mode == kModeProduct)
-        hipLaunchKernelGGL(k_analyze_product, dim3(blocks_for(a.n * 16)), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(k_analyze_product, dim3((unsigned)analyze_blocks(a.mode, a.n)), dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL(k_analyze_sum, dim3(blocks_for(a.n)), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+        hipLaunchKernelGGL(k_analyze_sum, dim3((unsigned)analyze_blocks(a.mode, a.n)), dim3(kBlock), 0, s, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_block_scan(a.blk_pre, analyze_blocks(a.mode, a.n), a.out.off + a.n, s);
 }
 
-size_t scan_tmp_elems(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
+int analyze_shift(int32_t mode) { return mode == kModeProduct ? kAnalyzeShiftProduct : kAnalyzeShiftSum; }
 
-hipError_t launch_scan(const int64_t* x, int64_t* y, int64_t n, int64_t* tmp, hipStream_t s)
+int64_t analyze_blocks(int32_t mode, int64_t n)
 {
-    if (n <= 0) return hipSuccess;
-    const unsigned tiles = (unsigned)((n + kScanTile - 1) / kScanTile);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(tiles), dim3(kBlock), 0, s, x, n, tmp);
-    hipLaunchKernelGGL(k_scan_apply, dim3(tiles), dim3(kBlock), 0, s, x, n, (const int64_t*)tmp, y);
-    return hipGetLastError();
+    return mode == kModeProduct ? (n * kAnalyzeLanes + kBlock - 1) / kBlock : (n + kBlock - 1) / kBlock;
 }
-
-int64_t analyze_blocks(int32_t mode, int64_t n) { return mode == kModeProduct ? (n * 16 + kBlock - 1) / kBlock : (n + kBlock - 1) / kBlock; }
 
 int64_t numeric_blocks(int64_t n) { return (n + kWavesPerBlock - 1) / kWavesPerBlock; }
 
@@ -1273,19 +1295,22 @@ hipError_t launch_numeric_global(const StageArgs& a, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_row_lengths(const int64_t* beg, const int64_t* end, int64_t n, int64_t* len, hipStream_t s)
+int64_t offset_blocks(int64_t n) { return (n + kBlock - 1) / kBlock; }
+
+hipError_t launch_row_offsets(const int64_t* beg, const int64_t* end, int64_t n, int64_t* rp, int64_t* blk_pre,
+                              hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_row_lengths, dim3(blocks_for(n)), dim3(kBlock), 0, s, beg, end, n, len);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_row_offsets, dim3(blocks_for(n)), dim3(kBlock), 0, s, beg, end, n, rp, blk_pre);
+    return launch_block_scan(blk_pre, offset_blocks(n), rp + n, s);
 }
 
 hipError_t launch_compact(const int64_t* beg, const int64_t* end, const int32_t* col, const double* val, int64_t n,
-                          const int64_t* row_ptr, int32_t* ocol, double* oval, hipStream_t s)
+                          int64_t* rp, const int64_t* blk_pre, int32_t* ocol, double* oval, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n * kWave)), dim3(kBlock), 0, s, beg, end, col, val, n, row_ptr,
-                       ocol, oval);
+    hipLaunchKernelGGL(k_compact, dim3(blocks_for(n * kWave)), dim3(kBlock), 0, s, beg, end, col, val, n, rp,
+                       blk_pre, ocol, oval);
     return hipGetLastError();
 }
 
