@@ -12,6 +12,8 @@ Contents:
     and a long-double dense Horner evaluation of the plain polynomial (eq. 1).
   * ``oracle.py``: ctypes wrapper, dense double Horner (eq. 1 by the Qin
     scheme, numpy matmul as the product step), norms.
+  * series mode (Algorithm 2 steps 1-3): the 1-norm estimator on Z^p,
+    the norm bounds of eq. 37 (Lemma 1), the degree N of eq. 34.
   * ``bound.py``: the paper's a-posteriori filtering error bound
     (eqs. 21-26 combined in eq. 23).
 """
@@ -30,5 +32,9 @@ from .oracle import (  # noqa: F401
     alg1_filter,
     fnt_thresholds,
     filtered_ps_adaptive,
+    normest1_power,
+    power_norm_bounds,
+    series_degree,
+    series,
 )
 from .bound import filtering_bound, power_norms  # noqa: F401

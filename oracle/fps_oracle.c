@@ -741,3 +741,175 @@ int orc_filtered_ps_adaptive(const orc_csr *Z, const double *c, int m, int s, do
     if (n_alg1) *n_alg1 = na;
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* Series mode (Section 3.2; Algorithm 2 steps 1-3; eqs. 33-37)         */
+/* ------------------------------------------------------------------ */
+
+/* y = Z x: y_r accumulates Z_rk x_k over the stored k of row r in
+ * ascending order, one fused multiply-add each, from +0. */
+static void spmv(const orc_csr *Z, const double *x, double *y)
+{
+    for (int64_t r = 0; r < Z->n; ++r) {
+        double acc = 0.0;
+        for (int64_t p = Z->row_ptr[r]; p < Z->row_ptr[r + 1]; ++p) acc = fma(Z->val[p], x[Z->col[p]], acc);
+        y[r] = acc;
+    }
+}
+
+/* y = Z^T x: y_c accumulates Z_rc x_r over the rows r holding column c in
+ * ascending r, one fused multiply-add each, from +0. */
+static void spmv_t(const orc_csr *Z, const double *x, double *y)
+{
+    for (int64_t c = 0; c < Z->n; ++c) y[c] = 0.0;
+    for (int64_t r = 0; r < Z->n; ++r)
+        for (int64_t p = Z->row_ptr[r]; p < Z->row_ptr[r + 1]; ++p) y[Z->col[p]] = fma(Z->val[p], x[r], y[Z->col[p]]);
+}
+
+/* ||y||_1 with the terms added in ascending index order. */
+static double vec_norm1(const double *y, int64_t n)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s = s + fabs(y[i]);
+    return s;
+}
+
+/* y = A x with A = Z^p (p products with Z), or A^T x = (Z^T)^p x. */
+static void apply_power(const orc_csr *Z, int p, int transpose, const double *x, double *y, double *tmp)
+{
+    const int64_t n = Z->n;
+    memcpy(y, x, (size_t)n * sizeof(double));
+    for (int i = 0; i < p; ++i) {
+        if (transpose)
+            spmv_t(Z, y, tmp);
+        else
+            spmv(Z, y, tmp);
+        memcpy(y, tmp, (size_t)n * sizeof(double));
+    }
+}
+
+/*
+ * The block 1-norm estimator of Higham and Tisseur (the algorithm behind
+ * normest1, the paper's refs. [16, 17]) with one column (t = 1) and at most
+ * itmax = 5 iterations, on A = Z^p applied implicitly.  The start vector is
+ * ones/n; sign(0) = +1; among equal largest |(A^T s)_i| the smallest i is
+ * taken.  The result est satisfies est <= ||A||_1 and equals ||A v||_1 for
+ * the returned unit vector v = e_ind (ind = -1 when the first iterate won).
+ * *iters counts the products with A.
+ */
+int orc_normest1_power(const orc_csr *Z, int p, double *est_out, int64_t *ind_out, int *iters)
+{
+    if (!Z || p < 0 || !est_out) return ORC_EINVAL;
+    const int64_t n = Z->n;
+    const int itmax = 5;
+    double *x = malloc((size_t)n * sizeof(double));
+    double *y = malloc((size_t)n * sizeof(double));
+    double *s = malloc((size_t)n * sizeof(double));
+    double *s_old = malloc((size_t)n * sizeof(double));
+    double *zt = malloc((size_t)n * sizeof(double));
+    double *tmp = malloc((size_t)n * sizeof(double));
+    if (!x || !y || !s || !s_old || !zt || !tmp) {
+        free(x); free(y); free(s); free(s_old); free(zt); free(tmp);
+        return ORC_ENOMEM;
+    }
+    for (int64_t i = 0; i < n; ++i) x[i] = 1.0 / (double)n;
+    double est = 0.0, est_old = 0.0;
+    int64_t ind = -1, ind_best = -1;
+    int k = 0;
+    for (k = 1;; ++k) {
+        apply_power(Z, p, 0, x, y, tmp);
+        est = vec_norm1(y, n);
+        if (est > est_old || k == 2) ind_best = ind;
+        if (k >= 2 && est <= est_old) {
+            est = est_old;
+            break;
+        }
+        est_old = est;
+        if (k > itmax) break;
+        for (int64_t i = 0; i < n; ++i) s[i] = (y[i] >= 0.0) ? 1.0 : -1.0;
+        if (k >= 2) { /* s parallel to s_old: equal up to sign */
+            int same = 1, opposite = 1;
+            for (int64_t i = 0; i < n; ++i) {
+                if (s[i] != s_old[i]) same = 0;
+                if (s[i] != -s_old[i]) opposite = 0;
+            }
+            if (same || opposite) break;
+        }
+        memcpy(s_old, s, (size_t)n * sizeof(double));
+        apply_power(Z, p, 1, s, zt, tmp);
+        double hmax = -1.0;
+        int64_t imax = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (fabs(zt[i]) > hmax) {
+                hmax = fabs(zt[i]);
+                imax = i;
+            }
+        if (k >= 2 && hmax == fabs(zt[ind_best])) break;
+        ind = imax;
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        x[ind] = 1.0;
+    }
+    *est_out = est;
+    if (ind_out) *ind_out = ind_best;
+    if (iters) *iters = k;
+    free(x); free(y); free(s); free(s_old); free(zt); free(tmp);
+    return ORC_OK;
+}
+
+/*
+ * Norm bounds of eq. 37: z[0] = 1, z[i] = the estimate of ||Z^i||_1 for
+ * 1 <= i <= K (K = 10 in the paper), and z[i] = alpha^i for i > K with
+ * alpha = max_{k = ceil(K/2)..K} z[k]^(1/k) (Lemma 1).  z[0..tmax].
+ */
+int orc_power_norm_bounds(const orc_csr *Z, int K, int tmax, double *z)
+{
+    if (!Z || K < 2 || (K % 2) != 0 || tmax < 0 || !z) return ORC_EINVAL;
+    z[0] = 1.0;
+    const int top = tmax < K ? tmax : K;
+    for (int i = 1; i <= top; ++i) {
+        const int rc = orc_normest1_power(Z, i, &z[i], NULL, NULL);
+        if (rc) return rc;
+    }
+    if (tmax > K) {
+        double alpha = 0.0;
+        for (int k = (K + 1) / 2; k <= K; ++k) {
+            const double r = pow(z[k], 1.0 / (double)k);
+            if (r > alpha) alpha = r;
+        }
+        for (int i = K + 1; i <= tmax; ++i) z[i] = pow(alpha, (double)i);
+    }
+    return ORC_OK;
+}
+
+/*
+ * Eq. 34: N = the smallest m with T_m = sum_{i >= m} |a_i| z_i <= eps_tol/2,
+ * the series given by its first L coefficients (terms beyond are taken as
+ * zero; N = L means they were not enough and is reported as an error).
+ * T_m is accumulated from the end: T_L = 0, T_m = T_{m+1} + |a_m| z_m.
+ * Algorithm 2 step 3: q = floor(sqrt(N - 1)) (at least 1).  *tail = T_N.
+ */
+int orc_series_degree(const double *a, int L, const double *z, double eps_tol, int *N_out, int *q_out,
+                      double *tail)
+{
+    if (!a || L < 1 || !z || !(eps_tol > 0.0) || !N_out || !q_out) return ORC_EINVAL;
+    double *T = malloc((size_t)(L + 1) * sizeof(double));
+    if (!T) return ORC_ENOMEM;
+    T[L] = 0.0;
+    for (int m = L - 1; m >= 0; --m) T[m] = T[m + 1] + fabs(a[m]) * z[m];
+    int N = L;
+    for (int m = 1; m <= L; ++m)
+        if (T[m] <= 0.5 * eps_tol) {
+            N = m;
+            break;
+        }
+    const double tN = T[N];
+    free(T);
+    if (N >= L) return ORC_EINVAL;
+    int q = 0;
+    while ((int64_t)(q + 1) * (q + 1) <= (int64_t)(N - 1)) ++q;
+    if (q < 1) q = 1;
+    *N_out = N;
+    *q_out = q;
+    if (tail) *tail = tN;
+    return ORC_OK;
+}

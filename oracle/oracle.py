@@ -95,6 +95,13 @@ def _load():
                                                      C.c_double, P(C.c_double), P(_Csr), P(_Stats), C.c_int,
                                                      P(C.c_int), P(_Alg1), C.c_int, P(C.c_int), C.c_int]
             lib.orc_filtered_ps_adaptive.restype = C.c_int
+            lib.orc_normest1_power.argtypes = [P(_Csr), C.c_int, P(C.c_double), P(C.c_int64), P(C.c_int)]
+            lib.orc_normest1_power.restype = C.c_int
+            lib.orc_power_norm_bounds.argtypes = [P(_Csr), C.c_int, C.c_int, P(C.c_double)]
+            lib.orc_power_norm_bounds.restype = C.c_int
+            lib.orc_series_degree.argtypes = [P(C.c_double), C.c_int, P(C.c_double), C.c_double, P(C.c_int),
+                                              P(C.c_int), P(C.c_double)]
+            lib.orc_series_degree.restype = C.c_int
             _lib = lib
     return _lib
 
@@ -299,3 +306,58 @@ def filtered_ps_adaptive(Z, coeffs, m: int, s: int, eps: float, e_r: float, z, n
                                         int(nthreads)), "filtered_ps_adaptive")
     return (_take(out), [_stats_dict(stats[i]) for i in range(min(ns.value, max_stats))],
             [_alg1_dict(a1[i]) for i in range(min(na.value, max_stats))])
+
+
+# ---- series mode (Section 3.2, Algorithm 2 steps 1-3) ------------------------
+
+def normest1_power(Z, p: int) -> dict:
+    """Estimate of ||Z^p||_1 (Higham-Tisseur estimator, one column, itmax 5):
+    {"est", "ind" (unit vector attaining it, -1: the start vector), "iters"}."""
+    lib = _load()
+    keep = []
+    zv = _view(Z, keep)
+    est, ind, it = C.c_double(), C.c_int64(), C.c_int()
+    _check(lib.orc_normest1_power(C.byref(zv), int(p), C.byref(est), C.byref(ind), C.byref(it)), "normest1_power")
+    return {"est": est.value, "ind": ind.value, "iters": it.value}
+
+
+def power_norm_bounds(Z, tmax: int, K: int = 10) -> np.ndarray:
+    """z[0..tmax] of eq. 37 (estimates up to K, Lemma 1 beyond)."""
+    lib = _load()
+    keep = []
+    zv = _view(Z, keep)
+    z = np.zeros(tmax + 1)
+    _check(lib.orc_power_norm_bounds(C.byref(zv), int(K), int(tmax), z.ctypes.data_as(C.POINTER(C.c_double))),
+           "power_norm_bounds")
+    return z
+
+
+def series_degree(a, z, eps_tol: float) -> dict:
+    """N of eq. 34, q of Algorithm 2 step 3 and the tail T_N, for the series
+    given by its coefficients a[0..L-1] and the bounds z[0..L-1]."""
+    lib = _load()
+    aa = np.ascontiguousarray(a, dtype=np.float64)
+    zz = np.ascontiguousarray(z, dtype=np.float64)
+    if zz.size < aa.size:
+        raise ValueError("need z[i] for every coefficient")
+    N, q, tail = C.c_int(), C.c_int(), C.c_double()
+    _check(lib.orc_series_degree(aa.ctypes.data_as(C.POINTER(C.c_double)), int(aa.size),
+                                 zz.ctypes.data_as(C.POINTER(C.c_double)), float(eps_tol), C.byref(N), C.byref(q),
+                                 C.byref(tail)), "series_degree")
+    return {"N": N.value, "q": q.value, "tail": tail.value}
+
+
+def series(Z, a, eps_tol: float, e_r: float, K: int = 10, nthreads: int = 0):
+    """Algorithm 2 for a power series: z by eq. 37, N by eq. 34, q by step 3,
+    then the filtered PS of P_N with Algorithm 1 and the thresholds of eq. 36
+    (those of eq. 28 with the budget eps_tol - T_N).  Returns
+    (F, info, stage records, Algorithm 1 records)."""
+    L = len(a)
+    z = power_norm_bounds(Z, L - 1, K)
+    d = series_degree(a, z, eps_tol)
+    N, q = d["N"], d["q"]
+    budget = eps_tol - d["tail"]
+    F, stats, a1 = filtered_ps_adaptive(Z, np.asarray(a[:N], dtype=np.float64), N - 1, q, budget, e_r, z,
+                                        nthreads)
+    info = dict(d, z=z, budget=budget, m=N - 1, s=q)
+    return F, info, stats, a1

@@ -41,6 +41,16 @@ MUTANTS = {
     "fnt_budget_not_shared": ("zeta[k] = eps / (d * M);", "zeta[k] = eps / d;"),
     "adaptive_horner_unfiltered": ("if (rc == ORC_OK) rc = orc_alg1_filter(&T, sigma[i], e_r, 200, &a1);",
                                    "if (rc == ORC_OK) rc = orc_alg1_filter(&T, INFINITY, e_r, 200, &a1);"),
+    "normest_no_transpose": ("apply_power(Z, p, 1, s, zt, tmp);", "apply_power(Z, p, 0, s, zt, tmp);"),
+    "normest_first_iterate_only": ("if (k > itmax) break;", "if (k > 0) break;"),
+    "normest_argmax_is_min": ("if (fabs(zt[i]) > hmax) {", "if (hmax < 0.0 || fabs(zt[i]) < hmax) {"),
+    "lemma1_alpha_min": ("if (r > alpha) alpha = r;", "if (alpha == 0.0 || r < alpha) alpha = r;"),
+    "lemma1_no_root": ("const double r = pow(z[k], 1.0 / (double)k);", "const double r = z[k];"),
+    "theta_off_by_one": ("if (T[m] <= 0.5 * eps_tol) {", "if (T[m + 1] <= 0.5 * eps_tol) {"),
+    "theta_full_budget": ("if (T[m] <= 0.5 * eps_tol) {", "if (T[m] <= eps_tol) {"),
+    "theta_tail_index": ("T[m] = T[m + 1] + fabs(a[m]) * z[m];", "T[m] = T[m + 1] + fabs(a[m]) * z[m + 1];"),
+    "q_ceil_sqrt": ("while ((int64_t)(q + 1) * (q + 1) <= (int64_t)(N - 1)) ++q;",
+                    "while ((int64_t)q * q < (int64_t)(N - 1)) ++q;"),
 }
 
 

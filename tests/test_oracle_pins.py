@@ -570,3 +570,157 @@ def test_adaptive_error_within_eps(case):
     F, _, _ = O.filtered_ps_adaptive(Z, c, m, s, 1e-300, 0.1, z)
     F0, _ = O.unfiltered_ps(Z, c, m, s)
     assert F.nnz == F0.nnz
+
+
+# ---------------------------------------------------------------------------
+# Series mode (Section 3.2, Algorithm 2 steps 1-3): the 1-norm estimator on
+# Z^p, the bounds of eq. 37 (Lemma 1) and the degree N of eq. 34
+# ---------------------------------------------------------------------------
+
+def _nonneg_random(n, density, seed):
+    rng = np.random.default_rng(seed)
+    d = (rng.random((n, n)) < density) * rng.random((n, n))
+    np.fill_diagonal(d, 0.0)
+    d[np.arange(n - 1), np.arange(1, n)] += 0.25  # a path so that powers stay nonzero
+    return G.from_dense(d)
+
+
+def _exact_power_norm1(Zd, p):
+    """||Z^p||_1 in exact rational arithmetic (tiny matrices only)."""
+    n = Zd.shape[0]
+    A = [[Fraction(float(Zd[i, j])) for j in range(n)] for i in range(n)]
+    P = [[Fraction(int(i == j)) for j in range(n)] for i in range(n)]
+    for _ in range(p):
+        P = [[sum((P[i][k] * A[k][j] for k in range(n) if A[k][j] != 0), Fraction(0)) for j in range(n)]
+             for i in range(n)]
+    return max(sum(abs(P[i][j]) for i in range(n)) for j in range(n))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_normest1_exact_for_nonnegative_matrices(seed):
+    # For a nonnegative A the estimator's first sign vector is all ones, so
+    # A^T s is the vector of column sums and the second iterate is the column
+    # of largest sum: the estimate is ||A||_1 itself.
+    n = 9 + seed
+    Z = _nonneg_random(n, 0.3, seed)
+    Zd = Z.to_dense()
+    for p in (1, 2, 3, 5):
+        r = O.normest1_power(Z, p)
+        exact = float(_exact_power_norm1(Zd, p))
+        assert abs(r["est"] - exact) <= 1e-14 * exact, (p, r, exact)
+        assert r["ind"] >= 0
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_normest1_is_an_attained_lower_bound(seed):
+    # est <= ||A||_1 always; est is the 1-norm of A v for the returned unit
+    # vector v = e_ind (or of the start vector ones/n); the iteration never
+    # returns less than its first iterate
+    Z = G.random_sparse(40, 0.12, seed + 11, 0.5)
+    Zd = Z.to_dense()
+    for p in (1, 2, 4):
+        A = np.linalg.matrix_power(Zd, p)
+        r = O.normest1_power(Z, p)
+        colsums = np.abs(A).sum(0)
+        first = np.abs(A @ np.full(Z.n, 1.0 / Z.n)).sum()
+        assert r["est"] <= colsums.max() * (1 + 1e-12)
+        assert r["est"] >= first * (1 - 1e-12)
+        attained = colsums[r["ind"]] if r["ind"] >= 0 else first
+        assert abs(r["est"] - attained) <= 1e-12 * max(attained, 1e-300), (p, r, attained)
+        assert 1 <= r["iters"] <= 6
+
+
+def test_normest1_closed_forms():
+    # diagonal: ||D^p||_1 = max |d|^p; shift J: ||J^p||_1 = 1 for p < n, 0 after
+    d = np.array([0.5, -1.25, 0.75, -0.3, 1.0])
+    Z = G.diagonal(d)
+    for p in range(1, 6):
+        assert O.normest1_power(Z, p)["est"] == 1.25 ** p
+    J = G.shift_matrix(6)
+    for p in range(1, 9):
+        assert O.normest1_power(J, p)["est"] == (1.0 if p < 6 else 0.0)
+    assert O.normest1_power(G.diagonal([-3.0]), 3)["est"] == 27.0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_power_norm_bounds_eq37_and_lemma1(seed):
+    # z[0] = 1, z[i] the estimates up to K = 10; beyond K, Lemma 1 gives
+    # ||Z^i|| <= alpha^i with alpha = max_{k=5..10} ||Z^k||^(1/k), so with the
+    # exact norms of a nonnegative matrix every z[i] bounds ||Z^i||_1
+    n = 10
+    Z = _nonneg_random(n, 0.35, 20 + seed)
+    Zd = Z.to_dense()
+    z = O.power_norm_bounds(Z, 20)
+    assert z[0] == 1.0
+    for i in range(1, 11):
+        assert z[i] == O.normest1_power(Z, i)["est"]
+    for i in range(11, 21):
+        exact = float(_exact_power_norm1(Zd, i))
+        assert z[i] >= exact * (1 - 1e-12), (i, z[i], exact)
+    # a 2-cycle with weights 4 and 1/4: ||Z^k||_1 is 4 for odd k and 1 for even
+    # k, so only the maximum over k = 5..10 (alpha = 4^(1/5)) bounds the odd powers
+    C2 = G.from_dense(np.array([[0.0, 4.0], [0.25, 0.0]]))
+    zc = O.power_norm_bounds(C2, 21)
+    for i in range(1, 22):
+        assert zc[i] >= (4.0 if i % 2 else 1.0) * (1 - 1e-12), (i, zc[i])
+    # diagonal closed form: every ||D^k||^(1/k) = max |d|, so z[i] = max|d|^i
+    zd = O.power_norm_bounds(G.diagonal([0.25, -1.5, 1.0]), 16)
+    for i in range(17):
+        assert abs(zd[i] - 1.5 ** i) <= 1e-14 * 1.5 ** i
+
+
+@pytest.mark.parametrize("eps", [1e-4, 3e-7, 1e-10, 2e-13, 1e-15])
+def test_series_degree_eq34_in_exact_arithmetic(eps):
+    # N = min m with sum_{i>=m} |a_i| z_i <= eps/2 (eq. 34), recomputed with
+    # exact rationals from the same double inputs; q = floor(sqrt(N - 1))
+    L = 60
+    a = G.exp_coeffs(L - 1)
+    z = np.array([1.5 ** i for i in range(L)])
+    T = [Fraction(0)] * (L + 1)
+    for m in range(L - 1, -1, -1):
+        T[m] = T[m + 1] + Fraction(float(a[m])) * Fraction(float(z[m]))
+    half = Fraction(eps) / 2
+    N = next(m for m in range(1, L + 1) if T[m] <= half)
+    # stay away from inputs whose decision rounding could flip
+    assert abs(T[N] - half) > half * Fraction(1, 10 ** 9) and abs(T[N - 1] - half) > half * Fraction(1, 10 ** 9)
+    d = O.series_degree(a, z, eps)
+    assert d["N"] == N
+    assert d["q"] == max(1, math.isqrt(N - 1))
+    assert abs(Fraction(d["tail"]) - T[N]) <= T[N] * Fraction(1, 10 ** 13)
+    with pytest.raises(RuntimeError):
+        O.series_degree(a[:N], z[:N], eps)  # too few coefficients: the tail is not below eps/2
+
+
+@pytest.mark.parametrize("case", ["exp_lap2d", "exp_band", "cos_lap1d", "exp_rand"])
+def test_series_mode_error_within_tol(case):
+    # Algorithm 2: ||f(Z) - F|| <= eps_tol, with f computed by scipy's dense
+    # expm / cosm; the truncation tail and the filtering budget of eq. 36
+    # add up to eps_tol
+    import scipy.linalg as sl
+
+    if case == "exp_lap2d":
+        Z, a, f = G.laplacian_2d(10, 2.0), G.exp_coeffs(60), sl.expm
+    elif case == "exp_band":
+        Z, a, f = G.random_banded(120, 3, 0.6, 1.5, seed=9), G.exp_coeffs(60), sl.expm
+    elif case == "cos_lap1d":
+        Z, a, f = G.laplacian_1d(150, 2.5), G.cos_coeffs(70), sl.cosm
+    else:
+        Z, a, f = G.random_sparse(60, 0.1, 4, 0.5), G.exp_coeffs(60), sl.expm
+    ref = f(Z.to_dense())
+    for eps_tol in (1e-6, 1e-11):
+        e_r = 0.1
+        F, info, st, a1 = O.series(Z, a, eps_tol, e_r)
+        check_canonical(F)
+        sc = O.schedule(info["m"], info["s"])
+        assert info["m"] == info["N"] - 1 and info["s"] == info["q"]
+        assert info["budget"] + info["tail"] == pytest.approx(eps_tol, rel=1e-15)
+        assert info["tail"] <= 0.5 * eps_tol
+        assert len(a1) == sc["n_spgemm"]
+        # the thresholds of eq. 36 share the budget eps_tol - T_N equally
+        zeta, sigma = O.fnt_thresholds(a[: info["N"]], info["m"], info["s"], info["budget"], info["z"])
+        stats = [{"kind": 0, "index": k, "dropped_1norm": zeta[k]} for k in range(2, sc["J"] + 1)]
+        stats += [{"kind": 3, "index": j, "dropped_1norm": sigma[j]} for j in range(sc["start"], sc["b"])]
+        bd = filtering_bound(a[: info["N"]], info["m"], info["s"], stats, info["z"])
+        assert abs(bd["bound"] - info["budget"]) <= 1e-12 * info["budget"]
+        err = O.norm1(F.to_dense() - ref)
+        assert err <= eps_tol * (1 + e_r), (case, eps_tol, err, info["N"])
