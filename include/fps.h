@@ -97,7 +97,8 @@ typedef struct {
     double eps;             /* adaptive: filtering error budget epsilon of eq. 27 (> 0) */
     double e_r;             /* adaptive: Algorithm 1 tolerance e_r (>= 0) */
     const double *znorm;    /* adaptive: HOST array, znorm[t] >= ||Z^t||_1 for t = 0..max(s, s(b-1)),
-                               b = ceil((m+1)/s); copied at plan time; required */
+                               b = ceil((m+1)/s); copied at plan time; NULL: the bounds of eq. 37
+                               from fps_power_norm_bounds with K = 10 (synchronises at creation) */
 } fps_filter_opts;
 
 /* stage kinds in fps_stats */
@@ -179,6 +180,61 @@ fps_status fps_plan_create(fps_plan *out, const fps_csr_view *Z, const double *c
  */
 fps_status fps_plan_create_ex(fps_plan *out, const fps_csr_view *Z, const double *coeffs, int32_t m, int32_t s,
                               const fps_filter_opts *opts, uint64_t flags, fps_stream stream);
+
+/* ---- Series mode (Section 3.2; Algorithm 2 steps 1-3; eqs. 33-37) ------- */
+
+/*
+ * Estimate of ||Z^p||_1 by the block 1-norm estimator of Higham and Tisseur
+ * (the estimator behind normest1, which the paper uses for eq. 37) with one
+ * column and at most 5 iterations, A = Z^p applied as p products with Z (A x)
+ * or Z^T (A^T s): start vector ones/n, sign(0) = +1, among equal largest
+ * |(A^T s)_i| the smallest i.  Every product accumulates in ascending index
+ * order with fused multiply-adds from +0 and ||y||_1 adds in ascending order,
+ * so the result is reproducible bit for bit.  *est <= ||Z^p||_1 and *est =
+ * ||Z^p v||_1 for v = e_{*ind} (*ind = -1: the start vector won).  Z: device
+ * CSR view, checked unless FPS_FLAG_NO_VALIDATE; est, ind, iters: HOST
+ * pointers (ind, iters may be NULL).  p >= 0.  Synchronises `stream`.
+ */
+fps_status fps_normest1(const fps_csr_view *Z, int32_t p, double *est, int64_t *ind, int32_t *iters, uint64_t flags,
+                        fps_stream stream);
+
+/*
+ * Norm bounds of eq. 37 into the HOST array z[0..tmax]: z[0] = 1,
+ * z[i] = fps_normest1(Z, i) for 1 <= i <= K, z[i] = alpha^i for i > K with
+ * alpha = max over k = K/2..K of z[k]^(1/k) (Lemma 1).  K even and >= 2 (the
+ * paper takes K = 10).  Synchronises `stream`.
+ */
+fps_status fps_power_norm_bounds(const fps_csr_view *Z, int32_t K, int32_t tmax, double *z, uint64_t flags,
+                                 fps_stream stream);
+
+typedef struct {
+    double eps_tol;          /* error tolerance of Algorithm 2 (> 0) */
+    double e_r;              /* Algorithm 1 tolerance (>= 0) */
+    int32_t K;               /* eq. 37 estimate depth, even (0: 10) */
+    int32_t max_alg1_iters;  /* Algorithm 1 iteration limit (0: 200) */
+} fps_series_opts;
+
+/*
+ * A plan for the power series f(Z) = sum_i a_i Z^i given by its first L
+ * coefficients a[0..L-1] (HOST; terms beyond are taken as zero), evaluated so
+ * that ||f(Z) - F||_1 <= eps_tol (Algorithm 2): z[0..L-1] by eq. 37; N = the
+ * smallest m >= 1 with T_m = sum_{i >= m} |a_i| z_i <= eps_tol / 2 (eq. 34;
+ * T accumulated from the end, T_L = 0); q = floor(sqrt(N - 1)), at least 1
+ * (Algorithm 2 step 3); then the plan of fps_plan_create_ex for the degree
+ * N - 1 polynomial with block size q, FPS_FILTER_ADAPTIVE and the budget
+ * eps_tol - T_N, which makes its eq. 28 thresholds those of eq. 36.
+ * FPS_ERR_INVALID_ARG if N would reach L (more coefficients are needed),
+ * FPS_ERR_CAPACITY if q > FPS_MAX_S.  The estimation runs here and
+ * synchronises `stream`; evaluation as for any plan.
+ */
+fps_status fps_plan_create_series(fps_plan *out, const fps_csr_view *Z, const double *a, int32_t L,
+                                  const fps_series_opts *opts, uint64_t flags, fps_stream stream);
+
+/* The quantities of a series plan: N (eq. 34), q (Algorithm 2 step 3), the
+ * tail T_N (eq. 33), the filtering budget eps_tol - T_N and, into the optional
+ * HOST array z[0..L-1], the eq. 37 bounds.  FPS_ERR_INVALID_ARG for a plan not
+ * made by fps_plan_create_series.  Host only. */
+fps_status fps_plan_series_info(fps_plan p, int32_t *N, int32_t *q, double *tail, double *budget, double *z);
 
 /*
  * Evaluate F(Z) on `stream`.  Once the plan has learned its buffer sizes

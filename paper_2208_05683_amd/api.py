@@ -48,6 +48,25 @@ class Plan:
         else:
             self.handle = B.fps_plan_create(self.view, list(coeffs), m, s, tau, flags, stream)
 
+    @classmethod
+    def series(cls, Z, a, eps_tol: float, e_r: float = 0.1, K: int = 10, max_alg1_iters: int = 0, flags: int = 0,
+               stream=None):
+        """Series mode (Algorithm 2): the plan picks N, q and the eq. 36
+        thresholds from the norm estimates of eq. 37 so that
+        ||f(Z) - F||_1 <= eps_tol; a holds the first coefficients of f."""
+        self = cls.__new__(cls)
+        self.Z = tuple(Z)
+        self.n = self.Z[0].numel() - 1
+        self.device = self.Z[0].device
+        self.view = B.csr_view(*self.Z)
+        self.handle = None
+        self.L = len(a)
+        self.handle = B.fps_plan_create_series(self.view, list(a), eps_tol, e_r, K, max_alg1_iters, flags, stream)
+        return self
+
+    def series_info(self) -> dict:
+        return B.fps_plan_series_info(self.handle, self.L)
+
     def eval(self, stream=None):
         B.fps_eval(self.handle, stream)
 
@@ -99,6 +118,16 @@ def axpy(n: int, coefs, terms, device="cuda"):
     views = [None if t is None else B.csr_view(*t) for t in terms]
     h = B.fps_axpy(n, coefs, views)
     return _take_matrix(h, n, device)
+
+
+def normest1(Z, p: int) -> dict:
+    """Estimate of ||Z^p||_1 (device CSR triple); see fps_normest1."""
+    return B.fps_normest1(B.csr_view(*Z), p)
+
+
+def power_norm_bounds(Z, tmax: int, K: int = 10) -> list:
+    """z[0..tmax] of eq. 37 (device CSR triple)."""
+    return B.fps_power_norm_bounds(B.csr_view(*Z), K, tmax)
 
 
 def schedule(m: int, s: int) -> dict:

@@ -79,6 +79,15 @@ class fps_filter_opts(C.Structure):
     ]
 
 
+class fps_series_opts(C.Structure):
+    _fields_ = [
+        ("eps_tol", C.c_double),
+        ("e_r", C.c_double),
+        ("K", C.c_int32),
+        ("max_alg1_iters", C.c_int32),
+    ]
+
+
 _P = C.POINTER
 _vp = C.c_void_p
 _SIGS = {
@@ -100,6 +109,13 @@ _SIGS = {
     "fps_matrix_nnz": (C.c_int32, [_vp, _P(C.c_int64)]),
     "fps_matrix_copy": (C.c_int32, [_vp, _vp, _vp, _vp, _vp]),
     "fps_matrix_destroy": (None, [_vp]),
+    "fps_normest1": (C.c_int32, [_P(fps_csr_view), C.c_int32, _P(C.c_double), _P(C.c_int64), _P(C.c_int32),
+                                 C.c_uint64, _vp]),
+    "fps_power_norm_bounds": (C.c_int32, [_P(fps_csr_view), C.c_int32, C.c_int32, _P(C.c_double), C.c_uint64, _vp]),
+    "fps_plan_create_series": (C.c_int32, [_P(_vp), _P(fps_csr_view), _P(C.c_double), C.c_int32,
+                                           _P(fps_series_opts), C.c_uint64, _vp]),
+    "fps_plan_series_info": (C.c_int32, [_vp, _P(C.c_int32), _P(C.c_int32), _P(C.c_double), _P(C.c_double),
+                                         _P(C.c_double)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -253,6 +269,39 @@ def fps_matrix_copy(m, row_ptr, col, val, stream=None):
 
 def fps_matrix_destroy(m):
     _lib.fps_matrix_destroy(m)
+
+
+def fps_normest1(Z: fps_csr_view, p: int, flags: int = 0, stream=None) -> dict:
+    est, ind, it = C.c_double(), C.c_int64(), C.c_int32()
+    _check(_lib.fps_normest1(C.byref(Z), int(p), C.byref(est), C.byref(ind), C.byref(it), C.c_uint64(flags),
+                             _stream_handle(stream)), "fps_normest1")
+    return {"est": est.value, "ind": ind.value, "iters": it.value}
+
+
+def fps_power_norm_bounds(Z: fps_csr_view, K: int, tmax: int, flags: int = 0, stream=None):
+    z = (C.c_double * (tmax + 1))()
+    _check(_lib.fps_power_norm_bounds(C.byref(Z), int(K), int(tmax), z, C.c_uint64(flags), _stream_handle(stream)),
+           "fps_power_norm_bounds")
+    return list(z)
+
+
+def fps_plan_create_series(Z: fps_csr_view, a, eps_tol: float, e_r: float = 0.1, K: int = 0,
+                           max_alg1_iters: int = 0, flags: int = 0, stream=None):
+    arr = (C.c_double * len(a))(*[float(x) for x in a])
+    o = fps_series_opts()
+    o.eps_tol, o.e_r, o.K, o.max_alg1_iters = float(eps_tol), float(e_r), int(K), int(max_alg1_iters)
+    h = C.c_void_p()
+    _check(_lib.fps_plan_create_series(C.byref(h), C.byref(Z), arr, len(a), C.byref(o), C.c_uint64(flags),
+                                       _stream_handle(stream)), "fps_plan_create_series")
+    return h
+
+
+def fps_plan_series_info(plan, L: int) -> dict:
+    N, q, tail, budget = C.c_int32(), C.c_int32(), C.c_double(), C.c_double()
+    z = (C.c_double * L)()
+    _check(_lib.fps_plan_series_info(plan, C.byref(N), C.byref(q), C.byref(tail), C.byref(budget), z),
+           "fps_plan_series_info")
+    return {"N": N.value, "q": q.value, "tail": tail.value, "budget": budget.value, "z": list(z)}
 
 
 def exported_symbols():

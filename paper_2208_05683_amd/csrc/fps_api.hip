@@ -431,6 +431,153 @@ fps_status validate_on_device(const fps_csr_view* v, const char* what, hipStream
     return FPS_OK;
 }
 
+// ---- 1-norm estimator and norm bounds (series mode, Section 3.2.2) --------------
+
+// Device workspace of the estimator on Z: Z^T as a CSR whose rows list the
+// rows of Z in ascending order, and the vectors of the iteration.
+struct EstWork {
+    int64_t n = 0;
+    DevBuf trp, trow, tval, trow_tmp, tval_tmp, cnt, x, y, t0, t1, s, s_old, zt, small;
+
+    fps_status init(const fps_csr_view* Z, hipStream_t st)
+    {
+        n = Z->n;
+        const size_t nn = (size_t)n, nz = (size_t)std::max<int64_t>(Z->nnz, 1);
+        FPS_TRY(trp.ensure(sizeof(int64_t) * (nn + 1)));
+        FPS_TRY(trow.ensure(sizeof(int32_t) * nz));
+        FPS_TRY(tval.ensure(sizeof(double) * nz));
+        FPS_TRY(trow_tmp.ensure(sizeof(int32_t) * nz));
+        FPS_TRY(tval_tmp.ensure(sizeof(double) * nz));
+        FPS_TRY(cnt.ensure(sizeof(unsigned long long) * nn));
+        for (DevBuf* b : {&x, &y, &t0, &t1, &s, &s_old, &zt}) FPS_TRY(b->ensure(sizeof(double) * nn));
+        FPS_TRY(small.ensure(64));
+        HIP_TRY(launch_transpose(Z->row_ptr, Z->col, Z->val, n, Z->nnz, cnt.as<unsigned long long>(),
+                                 trp.as<int64_t>(), trow_tmp.as<int32_t>(), tval_tmp.as<double>(), trow.as<int32_t>(),
+                                 tval.as<double>(), st));
+        return FPS_OK;
+    }
+
+    // out = Z^p in (or (Z^T)^p in); in and out are distinct from t0/t1
+    fps_status apply(const fps_csr_view* Z, int p, bool transpose, const double* in, double* out, hipStream_t st)
+    {
+        if (p == 0) {
+            HIP_TRY(hipMemcpyAsync(out, in, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st));
+            return FPS_OK;
+        }
+        const int64_t* rp = transpose ? trp.as<int64_t>() : Z->row_ptr;
+        const int32_t* cl = transpose ? trow.as<int32_t>() : Z->col;
+        const double* vl = transpose ? tval.as<double>() : Z->val;
+        const double* cur = in;
+        for (int i = 0; i < p; ++i) {
+            double* dst = (i == p - 1) ? out : ((i % 2) ? t1.as<double>() : t0.as<double>());
+            HIP_TRY(launch_spmv(rp, cl, vl, n, cur, dst, st));
+            cur = dst;
+        }
+        return FPS_OK;
+    }
+
+    // The estimator on A = Z^p (the same steps as the block 1-norm estimator
+    // of Higham and Tisseur with one column and itmax = 5).
+    fps_status normest1(const fps_csr_view* Z, int p, double* est_out, int64_t* ind_out, int* iters, hipStream_t st)
+    {
+        const int itmax = 5;
+        double* xv = x.as<double>();
+        double* yv = y.as<double>();
+        double* sv = s.as<double>();
+        double* sov = s_old.as<double>();
+        double* hv = zt.as<double>();
+        double* est_d = small.as<double>();
+        unsigned int* flags = reinterpret_cast<unsigned int*>(small.as<char>() + 8);
+        unsigned long long* res = reinterpret_cast<unsigned long long*>(small.as<char>() + 16);
+        HIP_TRY(launch_fill_f64(xv, n, 1.0 / (double)n, st));
+        double est = 0.0, est_old = 0.0;
+        int64_t ind = -1, ind_best = -1;
+        int k = 0;
+        for (k = 1;; ++k) {
+            FPS_TRY(apply(Z, p, false, xv, yv, st));
+            HIP_TRY(launch_abs_sum_ordered(yv, n, est_d, st));
+            HIP_TRY(hipMemcpyAsync(&est, est_d, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (est > est_old || k == 2) ind_best = ind;
+            if (k >= 2 && est <= est_old) {
+                est = est_old;
+                break;
+            }
+            est_old = est;
+            if (k > itmax) break;
+            const unsigned int ones[2] = {1u, 1u};
+            HIP_TRY(hipMemcpyAsync(flags, ones, sizeof(ones), hipMemcpyHostToDevice, st));
+            HIP_TRY(launch_sign(yv, n, sov, k >= 2 ? 1 : 0, sv, flags, st));
+            if (k >= 2) {  // the new sign vector parallel to the previous one
+                unsigned int f[2] = {0u, 0u};
+                HIP_TRY(hipMemcpyAsync(f, flags, sizeof(f), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                if (f[0] || f[1]) break;
+            }
+            std::swap(sv, sov);  // sov: the current sign vector
+            FPS_TRY(apply(Z, p, true, sov, hv, st));
+            const unsigned long long init[2] = {0ull, ~0ull};
+            HIP_TRY(hipMemcpyAsync(res, init, sizeof(init), hipMemcpyHostToDevice, st));
+            HIP_TRY(launch_absmax(hv, n, res, st));
+            unsigned long long r[2] = {0ull, 0ull};
+            double hbest = 0.0;
+            HIP_TRY(hipMemcpyAsync(r, res, sizeof(r), hipMemcpyDeviceToHost, st));
+            if (k >= 2) HIP_TRY(hipMemcpyAsync(&hbest, hv + ind_best, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            double hmax = 0.0;
+            std::memcpy(&hmax, &r[0], sizeof(double));
+            if (k >= 2 && hmax == std::fabs(hbest)) break;
+            ind = (int64_t)r[1];
+            HIP_TRY(launch_unit_vector(xv, n, ind, st));
+        }
+        *est_out = est;
+        if (ind_out) *ind_out = ind_best;
+        if (iters) *iters = k;
+        return FPS_OK;
+    }
+};
+
+// Eq. 37: z[0] = 1, z[i] estimates for 1 <= i <= K, alpha^i beyond (Lemma 1).
+fps_status power_norm_bounds(EstWork& w, const fps_csr_view* Z, int K, int tmax, double* z, hipStream_t st)
+{
+    z[0] = 1.0;
+    const int top = std::min(tmax, K);
+    for (int i = 1; i <= top; ++i) FPS_TRY(w.normest1(Z, i, &z[i], nullptr, nullptr, st));
+    if (tmax > K) {
+        double alpha = 0.0;
+        for (int k = (K + 1) / 2; k <= K; ++k) {
+            const double r = std::pow(z[k], 1.0 / (double)k);
+            if (r > alpha) alpha = r;
+        }
+        for (int i = K + 1; i <= tmax; ++i) z[i] = std::pow(alpha, (double)i);
+    }
+    return FPS_OK;
+}
+
+// Eq. 34 and Algorithm 2 step 3: N, q and the tail T_N.
+fps_status series_degree(const double* a, int L, const double* z, double eps_tol, int* N_out, int* q_out,
+                         double* tail)
+{
+    std::vector<double> T((size_t)L + 1);
+    T[(size_t)L] = 0.0;
+    for (int m = L - 1; m >= 0; --m) T[(size_t)m] = T[(size_t)m + 1] + std::fabs(a[m]) * z[m];
+    int N = L;
+    for (int m = 1; m <= L; ++m)
+        if (T[(size_t)m] <= 0.5 * eps_tol) {
+            N = m;
+            break;
+        }
+    if (N >= L)
+        return set_error(FPS_ERR_INVALID_ARG, "the %d coefficients given do not reach the tolerance (eq. 34 needs more)", L);
+    int q = 0;
+    while ((int64_t)(q + 1) * (q + 1) <= (int64_t)(N - 1)) ++q;
+    if (q < 1) q = 1;
+    *N_out = N;
+    *q_out = q;
+    *tail = T[(size_t)N];
+    return FPS_OK;
+}
+
 // View of a canonical CSR for the kernels, with row info in (span, amax).
 MatView canon_view(const fps_csr_view* v, const int2* span, const double* amax)
 {
@@ -454,6 +601,11 @@ struct fps_plan_s {
     int max_alg1 = 200;
     std::vector<double> znorm, zeta, sigma;
     uint64_t flags = 0;
+    // series mode (fps_plan_create_series)
+    bool series = false;
+    int series_N = 0, series_q = 0;
+    double series_tail = 0.0, series_budget = 0.0;
+    std::vector<double> series_z;
     Schedule sc;
     Engine eng;
     std::vector<std::unique_ptr<SlackMatrix>> P;  // P[j], j >= 2
@@ -677,7 +829,6 @@ fps_status fps_plan_create_ex(fps_plan* out, const fps_csr_view* Z, const double
             return set_error(FPS_ERR_INVALID_ARG, "eps must be finite and > 0");
         if (!std::isfinite(opts->e_r) || opts->e_r < 0.0)
             return set_error(FPS_ERR_INVALID_ARG, "e_r must be finite and >= 0");
-        if (!opts->znorm) return set_error(FPS_ERR_INVALID_ARG, "the adaptive filter needs znorm");
         if (opts->max_alg1_iters < 0) return set_error(FPS_ERR_INVALID_ARG, "max_alg1_iters must be >= 0");
     } else {
         return set_error(FPS_ERR_INVALID_ARG, "unknown filter %d", opts->filter);
@@ -700,7 +851,14 @@ fps_status fps_plan_create_ex(fps_plan* out, const fps_csr_view* Z, const double
         p->e_r = opts->e_r;
         p->max_alg1 = opts->max_alg1_iters > 0 ? opts->max_alg1_iters : 200;
         const int tmax = std::max(sc.q, sc.q * (sc.b - 1));
-        p->znorm.assign(opts->znorm, opts->znorm + tmax + 1);
+        if (opts->znorm) {
+            p->znorm.assign(opts->znorm, opts->znorm + tmax + 1);
+        } else {  // the bounds of eq. 37 from the 1-norm estimator
+            p->znorm.assign((size_t)tmax + 1, 0.0);
+            EstWork w;
+            FPS_TRY(w.init(Z, st));
+            FPS_TRY(power_norm_bounds(w, Z, 10, tmax, p->znorm.data(), st));
+        }
         for (double v : p->znorm)
             if (!std::isfinite(v) || v < 0.0) return set_error(FPS_ERR_INVALID_ARG, "znorm values must be finite and >= 0");
         fnt_thresholds(p->c, m, sc, p->eps, p->znorm, p->zeta, p->sigma);
@@ -1032,5 +1190,98 @@ fps_status fps_matrix_copy(fps_matrix m, int64_t* row_ptr, int32_t* col, double*
 }
 
 void fps_matrix_destroy(fps_matrix m) { delete m; }
+
+fps_status fps_normest1(const fps_csr_view* Z, int32_t p, double* est, int64_t* ind, int32_t* iters, uint64_t flags,
+                        fps_stream stream)
+{
+    g_last_error.clear();
+    if (!est) return set_error(FPS_ERR_INVALID_ARG, "est is NULL");
+    if (p < 0) return set_error(FPS_ERR_INVALID_ARG, "p must be >= 0");
+    FPS_TRY(check_view(Z, "Z", -1));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (!(flags & FPS_FLAG_NO_VALIDATE)) FPS_TRY(validate_on_device(Z, "Z", st));
+    EstWork w;
+    FPS_TRY(w.init(Z, st));
+    int it = 0;
+    FPS_TRY(w.normest1(Z, p, est, ind, &it, st));
+    if (iters) *iters = it;
+    return FPS_OK;
+}
+
+fps_status fps_power_norm_bounds(const fps_csr_view* Z, int32_t K, int32_t tmax, double* z, uint64_t flags,
+                                 fps_stream stream)
+{
+    g_last_error.clear();
+    if (!z) return set_error(FPS_ERR_INVALID_ARG, "z is NULL");
+    if (K < 2 || (K % 2) != 0) return set_error(FPS_ERR_INVALID_ARG, "K must be even and >= 2");
+    if (tmax < 0) return set_error(FPS_ERR_INVALID_ARG, "tmax must be >= 0");
+    FPS_TRY(check_view(Z, "Z", -1));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (!(flags & FPS_FLAG_NO_VALIDATE)) FPS_TRY(validate_on_device(Z, "Z", st));
+    EstWork w;
+    FPS_TRY(w.init(Z, st));
+    return power_norm_bounds(w, Z, K, tmax, z, st);
+}
+
+fps_status fps_plan_create_series(fps_plan* out, const fps_csr_view* Z, const double* a, int32_t L,
+                                  const fps_series_opts* opts, uint64_t flags, fps_stream stream)
+{
+    g_last_error.clear();
+    if (!out) return set_error(FPS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!opts || !a) return set_error(FPS_ERR_INVALID_ARG, "null a/opts");
+    if (L < 2) return set_error(FPS_ERR_INVALID_ARG, "L must be >= 2");
+    if (!std::isfinite(opts->eps_tol) || !(opts->eps_tol > 0.0))
+        return set_error(FPS_ERR_INVALID_ARG, "eps_tol must be finite and > 0");
+    if (!std::isfinite(opts->e_r) || opts->e_r < 0.0) return set_error(FPS_ERR_INVALID_ARG, "e_r must be finite and >= 0");
+    const int K = opts->K > 0 ? opts->K : 10;
+    if ((K % 2) != 0 || K < 2) return set_error(FPS_ERR_INVALID_ARG, "K must be even and >= 2");
+    if (opts->max_alg1_iters < 0) return set_error(FPS_ERR_INVALID_ARG, "max_alg1_iters must be >= 0");
+    for (int i = 0; i < L; ++i)
+        if (!std::isfinite(a[i])) return set_error(FPS_ERR_INVALID_ARG, "coefficient %d is not finite", i);
+    FPS_TRY(check_view(Z, "Z", -1));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (!(flags & FPS_FLAG_NO_VALIDATE)) FPS_TRY(validate_on_device(Z, "Z", st));
+    // Algorithm 2 steps 1-3
+    std::vector<double> z((size_t)L);
+    {
+        EstWork w;
+        FPS_TRY(w.init(Z, st));
+        FPS_TRY(power_norm_bounds(w, Z, K, L - 1, z.data(), st));
+    }
+    int N = 0, q = 0;
+    double tail = 0.0;
+    FPS_TRY(series_degree(a, L, z.data(), opts->eps_tol, &N, &q, &tail));
+    if (q > FPS_MAX_S) return set_error(FPS_ERR_CAPACITY, "q = %d exceeds FPS_MAX_S", q);
+    const double budget = opts->eps_tol - tail;
+    fps_filter_opts fo{};
+    fo.filter = FPS_FILTER_ADAPTIVE;
+    fo.max_alg1_iters = opts->max_alg1_iters;
+    fo.eps = budget;
+    fo.e_r = opts->e_r;
+    fo.znorm = z.data();
+    fps_plan pl = nullptr;
+    FPS_TRY(fps_plan_create_ex(&pl, Z, a, N - 1, q, &fo, flags | FPS_FLAG_NO_VALIDATE, stream));
+    pl->series = true;
+    pl->series_N = N;
+    pl->series_q = q;
+    pl->series_tail = tail;
+    pl->series_budget = budget;
+    pl->series_z = std::move(z);
+    *out = pl;
+    return FPS_OK;
+}
+
+fps_status fps_plan_series_info(fps_plan p, int32_t* N, int32_t* q, double* tail, double* budget, double* z)
+{
+    if (!p) return set_error(FPS_ERR_INVALID_ARG, "plan is NULL");
+    if (!p->series) return set_error(FPS_ERR_INVALID_ARG, "not a series plan");
+    if (N) *N = p->series_N;
+    if (q) *q = p->series_q;
+    if (tail) *tail = p->series_tail;
+    if (budget) *budget = p->series_budget;
+    if (z) std::memcpy(z, p->series_z.data(), sizeof(double) * p->series_z.size());
+    return FPS_OK;
+}
 
 }  // extern "C"

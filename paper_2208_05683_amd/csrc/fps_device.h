@@ -147,6 +147,18 @@ hipError_t launch_max_u64(const unsigned long long* x, int64_t n, unsigned long 
 hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
                             int64_t n, double t, unsigned long long* part_kept, hipStream_t s);
 int numeric_global_blocks(int slots);
+// 1-norm estimator (fps_normest.hip)
+hipError_t launch_transpose(const int64_t* rp, const int32_t* col, const double* val, int64_t n, int64_t nnz,
+                            unsigned long long* cnt, int64_t* trp, int32_t* trow_tmp, double* tval_tmp, int32_t* trow,
+                            double* tval, hipStream_t s);
+hipError_t launch_spmv(const int64_t* rp, const int32_t* col, const double* val, int64_t n, const double* x, double* y,
+                       hipStream_t s);
+hipError_t launch_abs_sum_ordered(const double* y, int64_t n, double* out, hipStream_t s);
+hipError_t launch_sign(const double* y, int64_t n, const double* s_old, int check, double* sv, unsigned int* flags,
+                       hipStream_t s);
+hipError_t launch_absmax(const double* h, int64_t n, unsigned long long* res, hipStream_t s);
+hipError_t launch_fill_f64(double* x, int64_t n, double v, hipStream_t s);
+hipError_t launch_unit_vector(double* x, int64_t n, int64_t i, hipStream_t s);
 // number of blocks each kernel writes partials for (host-side reduction)
 int64_t analyze_blocks(int32_t mode, int64_t n);
 int64_t numeric_blocks(int64_t n);
