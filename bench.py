@@ -86,9 +86,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="lap2d")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle timing (0 skips)")
-    ap.add_argument("--filter", choices=["fixed", "adaptive"], default="fixed",
-                    help="fixed: the workload's tau; adaptive: Algorithm 1 with the eq. 28 thresholds")
+    ap.add_argument("--filter", choices=["fixed", "adaptive", "series"], default="fixed",
+                    help="fixed: the workload's tau; adaptive: Algorithm 1 with the eq. 28 thresholds and the "
+                         "eq. 37 bounds; series: Algorithm 2 (N, q and the eq. 36 thresholds from --eps-tol)")
     ap.add_argument("--eps", type=float, default=1e-12, help="adaptive: filtering error budget")
+    ap.add_argument("--eps-tol", type=float, default=1e-12, help="series: error tolerance of Algorithm 2")
     ap.add_argument("--e-r", type=float, default=0.1, help="adaptive: Algorithm 1 tolerance")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM counters)")
@@ -116,17 +118,20 @@ def main():
         torch.cuda.synchronize()
         log(f"copied {args.copy_mib} MiB device to device")
         del src, dst
+    series_info = None
     if args.filter == "adaptive":
-        # ||Z^t||_1 <= ||Z||_1^t (the column-sum norm of the generated matrix)
-        import numpy as np
-
-        cs = np.zeros(Z.n)
-        np.add.at(cs, Z.col, np.abs(Z.val))
-        sc = api.schedule(cfg["m"], cfg["s"])
-        znorm = float(cs.max()) ** np.arange(max(sc["q"], sc["q"] * (sc["b"] - 1)) + 1)
+        # norm bounds of eq. 37 computed by the library on the device
         plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], adaptive=True, eps=args.eps, e_r=args.e_r,
-                        znorm=znorm, flags=B.FPS_FLAG_TIMING)
+                        znorm=None, flags=B.FPS_FLAG_TIMING)
         cfg = dict(cfg, name=cfg["name"] + f"_adaptive_eps{args.eps:g}")
+    elif args.filter == "series":
+        from fps_inputs import generators as G
+
+        plan = api.Plan.series(Zd, G.exp_coeffs(59), args.eps_tol, args.e_r, flags=B.FPS_FLAG_TIMING)
+        series_info = plan.series_info()
+        cfg = dict(cfg, name=cfg["name"].split("_m")[0] + f"_exp_series_tol{args.eps_tol:g}",
+                   m=series_info["N"] - 1, s=series_info["q"])
+        log(f"series mode: N = {series_info['N']}, q = {series_info['q']}, tail = {series_info['tail']:.3g}")
     else:
         plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"], flags=B.FPS_FLAG_TIMING)
 
@@ -172,7 +177,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": cfg["name"], "n": Z.n, "nnz_Z": Z.nnz, "m": cfg["m"], "s": cfg["s"],
                    "filter": args.filter,
-                   **({"tau": cfg["tau"]} if args.filter == "fixed" else {"eps": args.eps, "e_r": args.e_r}),
+                   **({"tau": cfg["tau"]} if args.filter == "fixed" else
+                      {"eps": args.eps, "e_r": args.e_r} if args.filter == "adaptive" else
+                      {"eps_tol": args.eps_tol, "e_r": args.e_r, "N": series_info["N"]}),
                    "series": "exp", "nnz_F": st["nnz_out"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg["name"]),
@@ -188,7 +195,7 @@ def main():
         "stage_ms": {f"{['power', 'block', 'gstep', 'horner'][k]}{i}": round(ms, 4)
                      for k, i, ms in zip(st["kind"], st["index"], st["stage_ms"])},
     }
-    if args.filter == "adaptive":
+    if args.filter != "fixed":
         res["alg1_iters_per_step"] = int(sum(st["stage_alg1_iters"]))
     if args.cpu_budget > 0 and args.filter == "fixed":
         log("timing the CPU oracle ...")

@@ -169,8 +169,9 @@ struct Workspace {
         g_off_cols = g_off_ebuf + 2 * g_cap;
         const int64_t per_slot_u32 = (g_off_cols + g_cap + 63) / 64 * 64;
         g_stride = per_slot_u32;
-        const int64_t budget = int64_t(1) << 31;  // 2 GiB of workspace at most
-        int64_t slots = std::min<int64_t>(256, std::max<int64_t>(4, budget / (4 * per_slot_u32)));
+        // up to 2048 wavefronts (eight per CU) with a workspace each, 4 GiB at most
+        const int64_t budget = int64_t(1) << 32;
+        int64_t slots = std::min<int64_t>(2048, std::max<int64_t>(4, budget / (4 * per_slot_u32)));
         slots = std::min<int64_t>(slots, std::max<int64_t>(4, ((nn + 3) / 4) * 4));
         slots = (slots + numeric_waves_per_block() - 1) / numeric_waves_per_block() * numeric_waves_per_block();
         g_slots = (int32_t)slots;

@@ -109,15 +109,22 @@ __global__ void __launch_bounds__(kB) k_spmv(const int64_t* __restrict__ rp, con
 }
 
 // sum of |y_i| in ascending i by one wavefront: 64 values loaded at a time,
-// added one after the other by lane 0
+// then added one after the other (each read from its lane into scalar
+// registers); the padding past n adds +0, which leaves a sum of nonnegative
+// terms unchanged
 __global__ void __launch_bounds__(kWave) k_abs_sum_ordered(const double* __restrict__ y, int64_t n, double* out)
 {
     const int l = threadIdx.x;
     double acc = 0.0;
     for (int64_t b = 0; b < n; b += kWave) {
         const double v = (b + l < n) ? fabs(y[b + l]) : 0.0;
-        const int cnt = (int)min<int64_t>(kWave, n - b);
-        for (int j = 0; j < cnt; ++j) acc = acc + __shfl(v, j, kWave);
+        const long long bits = __double_as_longlong(v);
+        const uint32_t lo = (uint32_t)bits, hi = (uint32_t)((unsigned long long)bits >> 32);
+#pragma unroll
+        for (int j = 0; j < kWave; ++j) {
+            const uint32_t a = __builtin_amdgcn_readlane(lo, j), c = __builtin_amdgcn_readlane(hi, j);
+            acc = acc + __longlong_as_double((long long)(((unsigned long long)c << 32) | a));
+        }
     }
     if (l == 0) *out = acc;
 }
@@ -128,27 +135,45 @@ __global__ void __launch_bounds__(kB) k_sign(const double* __restrict__ y, int64
                                              int check, double* s, unsigned int* flags)
 {
     const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (i >= n) return;
-    const double v = (y[i] >= 0.0) ? 1.0 : -1.0;
-    s[i] = v;
-    if (check) {
-        if (v != s_old[i]) atomicAnd(&flags[0], 0u);
-        if (v != -s_old[i]) atomicAnd(&flags[1], 0u);
+    bool diff = false, notneg = false;
+    if (i < n) {
+        const double v = (y[i] >= 0.0) ? 1.0 : -1.0;
+        s[i] = v;
+        if (check) {
+            diff = v != s_old[i];
+            notneg = v != -s_old[i];
+        }
+    }
+    // one atomic per wavefront that saw a difference
+    const unsigned long long md = __ballot(diff), mn = __ballot(notneg);
+    if ((threadIdx.x % kWave) == 0) {
+        if (md) atomicAnd(&flags[0], 0u);
+        if (mn) atomicAnd(&flags[1], 0u);
     }
 }
 
 // res[0] = bit pattern of max |h_i| (nonnegative doubles order like their
 // bit patterns), then res[1] = smallest i attaining it
+// (both reduce within the wavefront first: one atomic per wavefront)
 __global__ void __launch_bounds__(kB) k_absmax_bits(const double* __restrict__ h, int64_t n, unsigned long long* res)
 {
     const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (i < n) atomicMax(&res[0], (unsigned long long)__double_as_longlong(fabs(h[i])));
+    unsigned long long v = (i < n) ? (unsigned long long)__double_as_longlong(fabs(h[i])) : 0ull;
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        const unsigned long long o = __shfl_xor(v, d, kWave);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x % kWave) == 0) atomicMax(&res[0], v);
 }
 
 __global__ void __launch_bounds__(kB) k_absmax_index(const double* __restrict__ h, int64_t n, unsigned long long* res)
 {
     const int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (i < n && (unsigned long long)__double_as_longlong(fabs(h[i])) == res[0]) atomicMin(&res[1], (unsigned long long)i);
+    const bool hit = i < n && (unsigned long long)__double_as_longlong(fabs(h[i])) == res[0];
+    const unsigned long long m = __ballot(hit);
+    if ((threadIdx.x % kWave) == 0 && m)
+        atomicMin(&res[1], (unsigned long long)(i + __builtin_ctzll(m)));
 }
 
 __global__ void __launch_bounds__(kB) k_fill_f64(double* x, int64_t n, double v)
