@@ -7,6 +7,11 @@ powers, coefficient blocks and Horner steps) of the 2D 5-point Laplacian on a
 tau = 1e-12, with Z resident in HBM.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload lap2d|lap1d]
+
+Other lines (not the headline): --filter adaptive|series time Algorithm 1 and
+Algorithm 2 on the same matrix; --sweep banded times the paper's second test
+set (random banded 1000 x 1000, bandwidth 1..15, exp and cos, eps_tol 1e-14)
+against the unfiltered scheme and a dense fp64 Horner.
 """
 
 from __future__ import annotations
@@ -79,6 +84,105 @@ def cpu_baseline(cfg, budget_s: float):
                       f"{threads} OpenMP threads"}
 
 
+def dense_ps(Zt, c, m, s):
+    """Plain PS (eqs. 2-6) on a dense fp64 device matrix: powers, blocks and the
+    Horner recurrence as GEMMs (the dense comparison of the banded sweep)."""
+    import torch
+
+    n = Zt.shape[0]
+    N, q = m + 1, s
+    b = -(-N // q)
+    eye = torch.eye(n, dtype=torch.float64, device=Zt.device)
+    J = q if b >= 2 else m
+    P = [eye, Zt]
+    for _ in range(2, J + 1):
+        P.append(Zt @ P[-1])
+
+    def block(i, jmax):
+        acc = torch.zeros_like(Zt)
+        for j in range(jmax + 1):
+            k = i * q + j
+            if k <= m and c[k] != 0.0:
+                acc = acc + float(c[k]) * P[j]
+        return acc
+
+    if b == 1:
+        return block(0, q - 1)
+    g = 1 if N - q * (b - 1) == 1 else 0
+    S = block(b - 2, q) if g else block(b - 1, q - 1)
+    for i in range(1 + g, b):
+        S = block(b - 1 - i, q - 1) + P[q] @ S
+    return S
+
+
+def banded_sweep(count: int, eps_tol: float, e_r: float, bands):
+    """The paper's second test set on the GPU: for each bandwidth, `count`
+    matrices; the series mode (Algorithm 2), the unfiltered scheme with the same
+    N and q, and the dense Horner, timed per matrix; sparsity of F; relative
+    Frobenius errors against the matrix exponential / cosine computed densely
+    (torch.linalg.matrix_exp, cos through the complex exponential)."""
+    import numpy as np
+    import torch
+    from fps_inputs import generators as G
+    from paper_2208_05683_amd import api
+
+    def dev_ms(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, 1e3 * (time.perf_counter() - t)
+
+    def dense(csr):
+        rp, cl, vl = (x.cpu().numpy() for x in csr)
+        rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+        d = torch.zeros((len(rp) - 1, len(rp) - 1), dtype=torch.float64)
+        d[rows, cl] = torch.from_numpy(vl)
+        return d.cuda()
+
+    out = []
+    for fname, coeffs in (("exp", G.exp_coeffs(199)), ("cos", G.cos_coeffs(199))):
+        rows = []
+        for bw in bands:
+            acc = {k: [] for k in ("psscf_setup_ms", "psscf_ms", "ps_ms", "dense_ms", "sparsity_psscf",
+                                   "sparsity_ps", "err_psscf", "err_ps", "N", "q")}
+            for k in range(count):
+                Z = G.banded_sweep_matrix(bw, 1000, seed=1000 * bw + k)
+                Zd = api.to_device(Z.row_ptr, Z.col, Z.val)
+                plan, t_setup = dev_ms(lambda: api.Plan.series(Zd, coeffs, eps_tol, e_r))
+                info = plan.series_info()
+                plan.eval()  # sizing run
+                _, t_eval = dev_ms(plan.eval)
+                F = plan.result()
+                plan.close()
+                m, s = info["N"] - 1, info["q"]
+                ps = api.Plan(Zd, coeffs, m, s, 0.0)
+                ps.eval()
+                _, t_ps = dev_ms(ps.eval)
+                Fps = ps.result()
+                ps.close()
+                Zt = dense((Zd[0], Zd[1], Zd[2]))
+                dense_ps(Zt, coeffs, m, s)  # warm-up
+                _, t_dense = dev_ms(lambda: dense_ps(Zt, coeffs, m, s))
+                if fname == "exp":
+                    ref = torch.linalg.matrix_exp(Zt)
+                else:
+                    ref = torch.linalg.matrix_exp(1j * Zt.to(torch.complex128)).real
+                nref = torch.linalg.norm(ref)
+                acc["err_psscf"].append(float(torch.linalg.norm(dense(F) - ref) / nref))
+                acc["err_ps"].append(float(torch.linalg.norm(dense(Fps) - ref) / nref))
+                acc["sparsity_psscf"].append(F[1].numel() / Z.n ** 2)
+                acc["sparsity_ps"].append(Fps[1].numel() / Z.n ** 2)
+                for key, v in (("psscf_setup_ms", t_setup), ("psscf_ms", t_eval), ("ps_ms", t_ps),
+                               ("dense_ms", t_dense), ("N", info["N"]), ("q", info["q"])):
+                    acc[key].append(v)
+            row = {"b": bw, **{k: float(np.mean(v)) for k, v in acc.items()}}
+            log(f"{fname} b={bw}: " + ", ".join(f"{k}={v:.3g}" for k, v in row.items() if k != "b"))
+            rows.append(row)
+        out.append({"function": fname, "rows": rows})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +196,10 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-12, help="adaptive: filtering error budget")
     ap.add_argument("--eps-tol", type=float, default=1e-12, help="series: error tolerance of Algorithm 2")
     ap.add_argument("--e-r", type=float, default=0.1, help="adaptive: Algorithm 1 tolerance")
+    ap.add_argument("--sweep", choices=["banded"], default=None,
+                    help="banded: the paper's second test set instead of the headline workload")
+    ap.add_argument("--sweep-count", type=int, default=30, help="sweep: matrices per bandwidth")
+    ap.add_argument("--sweep-bands", default="1-15", help="sweep: bandwidths, e.g. 1-15 or 1,5,11")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM counters)")
     args = ap.parse_args()
@@ -104,6 +212,19 @@ def main():
 
     import torch
     from paper_2208_05683_amd import api, binding as B
+
+    if args.sweep == "banded":
+        if "-" in args.sweep_bands:
+            lo, hi = (int(x) for x in args.sweep_bands.split("-"))
+            bands = list(range(lo, hi + 1))
+        else:
+            bands = [int(x) for x in args.sweep_bands.split(",")]
+        tol = args.eps_tol if args.eps_tol != 1e-12 else 1e-14
+        res = {"sweep": "banded", "n": 1000, "matrices_per_band": args.sweep_count, "eps_tol": tol,
+               "e_r": args.e_r, "data": "synthetic: every in-band entry N(0, 1), seed 1000 b + k",
+               "results": banded_sweep(args.sweep_count, tol, args.e_r, bands)}
+        print(json.dumps(res), flush=True)
+        return
 
     cfg = workload(args.workload)
     Z = cfg["Z"]

@@ -128,3 +128,12 @@ def test_adaptive_polynomial_with_computed_bounds():
     finally:
         plan.close()
     assert_same_csr(got, want, "computed bounds")
+
+
+@pytest.mark.parametrize("bw", [1, 4, 8, 12])
+def test_series_banded_test_set(bw):
+    # the paper's second test set: 1000 x 1000, full band of N(0, 1) entries,
+    # exp and cos series at eps_tol = 1e-14
+    Z = G.banded_sweep_matrix(bw, 1000, seed=1000 * bw)
+    compare_series(Z, G.exp_coeffs(199), 1e-14, what=f"band{bw} exp")
+    compare_series(Z, G.cos_coeffs(199), 1e-14, what=f"band{bw} cos")

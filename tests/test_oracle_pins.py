@@ -724,3 +724,15 @@ def test_series_mode_error_within_tol(case):
         assert abs(bd["bound"] - info["budget"]) <= 1e-12 * info["budget"]
         err = O.norm1(F.to_dense() - ref)
         assert err <= eps_tol * (1 + e_r), (case, eps_tol, err, info["N"])
+
+
+def test_banded_test_set_generator():
+    # test set 2: equal lower and upper bandwidth b, every in-band entry drawn
+    # from N(0, 1), 1000 x 1000
+    for bw in (1, 7, 15):
+        Z = G.banded_sweep_matrix(bw, 1000, seed=1000 * bw + 3)
+        d = Z.to_dense()
+        i, j = np.nonzero(d)
+        assert Z.n == 1000 and np.abs(i - j).max() == bw
+        assert Z.nnz == sum(1000 - abs(k) for k in range(-bw, bw + 1))
+        assert abs(Z.val.mean()) < 4.0 / np.sqrt(Z.nnz) and abs(Z.val.std() - 1.0) < 0.05
