@@ -99,6 +99,13 @@ typedef struct {
     const double *znorm;    /* adaptive: HOST array, znorm[t] >= ||Z^t||_1 for t = 0..max(s, s(b-1)),
                                b = ceil((m+1)/s); copied at plan time; NULL: the bounds of eq. 37
                                from fps_power_norm_bounds with K = 10 (synchronises at creation) */
+    int32_t alg1_device_iters; /* adaptive: Algorithm 1 iterations launched per stage on the device
+                                  without host synchronisation; 0: as many as the stage needed in
+                                  the last host-driven run (the first evaluation runs host-driven,
+                                  one synchronisation per iteration, and learns them); -1: always
+                                  host-driven.  A stage that needs more than were launched makes
+                                  the result query repeat the evaluation host-driven */
+    int32_t reserved;
 } fps_filter_opts;
 
 /* stage kinds in fps_stats */
@@ -175,8 +182,9 @@ fps_status fps_plan_create(fps_plan *out, const fps_csr_view *Z, const double *c
  * norm bounds), so that the filtering error is at most eps (1 + e_r) to first
  * order (eq. 27).  Algorithm 1 measures the candidate norm as the largest
  * column sum of ceil(|x| 2^40 / eps_g) taken exactly in integers (an upper
- * bound of the 1-norm, independent of summation order).  Adaptive
- * evaluations synchronise the stream once per Algorithm 1 iteration.
+ * bound of the 1-norm, independent of summation order).  The iterations of
+ * Algorithm 1 run on the device (opts->alg1_device_iters), so an evaluation
+ * only enqueues work once the plan has learned its sizes.
  */
 fps_status fps_plan_create_ex(fps_plan *out, const fps_csr_view *Z, const double *coeffs, int32_t m, int32_t s,
                               const fps_filter_opts *opts, uint64_t flags, fps_stream stream);
@@ -212,6 +220,8 @@ typedef struct {
     double e_r;              /* Algorithm 1 tolerance (>= 0) */
     int32_t K;               /* eq. 37 estimate depth, even (0: 10) */
     int32_t max_alg1_iters;  /* Algorithm 1 iteration limit (0: 200) */
+    int32_t alg1_device_iters; /* as in fps_filter_opts */
+    int32_t reserved;
 } fps_series_opts;
 
 /*

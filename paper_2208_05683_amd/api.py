@@ -32,7 +32,8 @@ class Plan:
     """A plan for F(Z) = sum_k c_k Z^k by filtered PS (fps_plan_create)."""
 
     def __init__(self, Z, coeffs, m: int, s: int, tau: float = 0.0, flags: int = 0, stream=None,
-                 adaptive: bool = False, eps: float = 0.0, e_r: float = 0.1, znorm=None, max_alg1_iters: int = 0):
+                 adaptive: bool = False, eps: float = 0.0, e_r: float = 0.1, znorm=None, max_alg1_iters: int = 0,
+                 alg1_device_iters: int = 0):
         """Fixed filter (drop |x| < tau) by default; adaptive=True runs
         Algorithm 1 with the eq. 28 thresholds for budget eps (znorm[t] >=
         ||Z^t||_1 required)."""
@@ -44,13 +45,14 @@ class Plan:
         if adaptive:
             self.handle = B.fps_plan_create_ex(self.view, list(coeffs), m, s, filter=B.FPS_FILTER_ADAPTIVE,
                                                eps=eps, e_r=e_r, znorm=list(znorm) if znorm is not None else None,
-                                               max_alg1_iters=max_alg1_iters, flags=flags, stream=stream)
+                                               max_alg1_iters=max_alg1_iters, flags=flags, stream=stream,
+                                               alg1_device_iters=alg1_device_iters)
         else:
             self.handle = B.fps_plan_create(self.view, list(coeffs), m, s, tau, flags, stream)
 
     @classmethod
     def series(cls, Z, a, eps_tol: float, e_r: float = 0.1, K: int = 10, max_alg1_iters: int = 0, flags: int = 0,
-               stream=None):
+               stream=None, alg1_device_iters: int = 0):
         """Series mode (Algorithm 2): the plan picks N, q and the eq. 36
         thresholds from the norm estimates of eq. 37 so that
         ||f(Z) - F||_1 <= eps_tol; a holds the first coefficients of f."""
@@ -61,7 +63,8 @@ class Plan:
         self.view = B.csr_view(*self.Z)
         self.handle = None
         self.L = len(a)
-        self.handle = B.fps_plan_create_series(self.view, list(a), eps_tol, e_r, K, max_alg1_iters, flags, stream)
+        self.handle = B.fps_plan_create_series(self.view, list(a), eps_tol, e_r, K, max_alg1_iters, flags, stream,
+                                               alg1_device_iters)
         return self
 
     def series_info(self) -> dict:

@@ -76,6 +76,8 @@ class fps_filter_opts(C.Structure):
         ("eps", C.c_double),
         ("e_r", C.c_double),
         ("znorm", C.POINTER(C.c_double)),
+        ("alg1_device_iters", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 
@@ -85,6 +87,8 @@ class fps_series_opts(C.Structure):
         ("e_r", C.c_double),
         ("K", C.c_int32),
         ("max_alg1_iters", C.c_int32),
+        ("alg1_device_iters", C.c_int32),
+        ("reserved", C.c_int32),
     ]
 
 
@@ -181,7 +185,7 @@ def fps_plan_create(Z: fps_csr_view, coeffs, m: int, s: int, tau: float, flags: 
 
 def fps_plan_create_ex(Z: fps_csr_view, coeffs, m: int, s: int, filter: int = 0, tau: float = 0.0,
                        eps: float = 0.0, e_r: float = 0.0, znorm=None, max_alg1_iters: int = 0, flags: int = 0,
-                       stream=None):
+                       stream=None, alg1_device_iters: int = 0):
     arr = (C.c_double * (m + 1))(*[float(x) for x in coeffs[: m + 1]])
     o = fps_filter_opts()
     o.filter = int(filter)
@@ -189,6 +193,7 @@ def fps_plan_create_ex(Z: fps_csr_view, coeffs, m: int, s: int, filter: int = 0,
     o.tau = float(tau)
     o.eps = float(eps)
     o.e_r = float(e_r)
+    o.alg1_device_iters = int(alg1_device_iters)
     zarr = None
     if znorm is not None:
         zarr = (C.c_double * len(znorm))(*[float(x) for x in znorm])
@@ -286,10 +291,11 @@ def fps_power_norm_bounds(Z: fps_csr_view, K: int, tmax: int, flags: int = 0, st
 
 
 def fps_plan_create_series(Z: fps_csr_view, a, eps_tol: float, e_r: float = 0.1, K: int = 0,
-                           max_alg1_iters: int = 0, flags: int = 0, stream=None):
+                           max_alg1_iters: int = 0, flags: int = 0, stream=None, alg1_device_iters: int = 0):
     arr = (C.c_double * len(a))(*[float(x) for x in a])
     o = fps_series_opts()
     o.eps_tol, o.e_r, o.K, o.max_alg1_iters = float(eps_tol), float(e_r), int(K), int(max_alg1_iters)
+    o.alg1_device_iters = int(alg1_device_iters)
     h = C.c_void_p()
     _check(_lib.fps_plan_create_series(C.byref(h), C.byref(Z), arr, len(a), C.byref(o), C.c_uint64(flags),
                                        _stream_handle(stream)), "fps_plan_create_series")

@@ -193,6 +193,7 @@ struct StageRecord {
     // adaptive filter (Algorithm 1) of this stage
     double eps_g = 0.0, threshold = 0.0, dropped = 0.0;
     int alg1_iters = 0;
+    bool alg1_device = false;  // the record is in the device state (Engine::alg1_state)
 };
 
 struct Schedule {
@@ -250,14 +251,18 @@ void fnt_thresholds(const std::vector<double>& c, int m, const Schedule& sc, dou
 }
 
 // Runs row-accumulation stages with one workspace.
+
 struct Engine {
     Workspace ws;
-    DevBuf colsum;  // Algorithm 1 column sums
+    DevBuf colsum;  // Algorithm 1 column sums (two buffers) and maxima
+    DevBuf alg1st;  // per stage: two Algorithm 1 iteration states and the final record
     uint64_t flags = 0;
     std::vector<int64_t> learned;  // per stage index: output capacity learned by a sizing run
     std::vector<bool> learned_global;
+    std::vector<int> alg1_learned;  // per stage: Algorithm 1 iterations of the last host-driven run
 
     StageCounters* ctr(int i) const { return ws.counters.as<StageCounters>() + i; }
+    Alg1State* alg1_state(int i) const { return alg1st.as<Alg1State>() + 3 * (size_t)i; }
     unsigned long long* part(int i) const
     {
         return ws.part.as<unsigned long long>() + (size_t)i * kPartCount * (size_t)ws.part_stride;
@@ -286,6 +291,8 @@ struct Engine {
         flags = fl;
         learned.assign((size_t)stages, -1);
         learned_global.assign((size_t)stages, false);
+        alg1_learned.assign((size_t)stages, 0);
+        FPS_TRY(alg1st.ensure(sizeof(Alg1State) * 3 * (size_t)std::max(stages, 1)));
         return ws.init(n, stages);
     }
 
@@ -347,15 +354,43 @@ struct Engine {
     }
 
     // Algorithm 1 on a stage output in place (see fps_plan_create_ex).
+    // device_iters > 0: that many iterations are launched as kernels (no host
+    // round trip; the record is read back with the statistics); a stage that
+    // needs more raises kErrAlg1Pending and the evaluation is repeated with the
+    // host loop.  device_iters == 0: the count learned by the last host-driven
+    // run of this stage, or the host loop (which learns it) if there is none.
+    // device_iters < 0: the host loop, one synchronisation per iteration.
     fps_status alg1(int idx, SlackMatrix& out, double eps_g, double e_r, int max_iter, hipStream_t s,
-                    StageRecord* rec)
+                    StageRecord* rec, int device_iters)
     {
+        if (device_iters == 0) device_iters = alg1_learned[(size_t)idx];  // 0 if none: host loop
+
         const int64_t n = ws.n;
-        FPS_TRY(colsum.ensure(sizeof(unsigned long long) * (size_t)(n + 1)));
+        if (rec) {
+            rec->eps_g = eps_g;
+            rec->threshold = 0.0;
+            rec->dropped = 0.0;
+            rec->alg1_iters = 0;
+            rec->alg1_device = false;
+        }
+        if (!std::isfinite(eps_g)) return FPS_OK;  // an unbounded budget filters nothing
+        FPS_TRY(colsum.ensure(sizeof(unsigned long long) * (size_t)(2 * n + 3)));
         unsigned long long* cs = colsum.as<unsigned long long>();
         unsigned long long* mx = cs + n;
         const double target = eps_g * (1.0 + e_r);
         const double scale = std::ldexp(1.0, 40) / eps_g;
+        if (device_iters > 0) {
+            device_iters = std::min(device_iters, max_iter);
+            HIP_TRY(launch_fill_u64(cs, 2 * n + 3, 0ull, s));
+            const Alg1Params pr{eps_g, target, scale, max_iter, 0};
+            HIP_TRY(launch_alg1_device(out.off.as<int64_t>(), out.end.as<int64_t>(), out.col.as<int32_t>(),
+                                       out.val.as<double>(), out.span.as<int2>(), out.amax.as<double>(), n, pr,
+                                       device_iters, alg1_state(idx),
+                                       cs, part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, ctr(idx), s));
+            HIP_TRY(launch_fill_u64(&ctr(idx)->kept_global, 1, 0ull, s));
+            if (rec) rec->alg1_device = true;
+            return FPS_OK;
+        }
         double m = 1.0, t = 0.0, c = 0.0;
         int it = 0;
         do {
@@ -379,11 +414,11 @@ struct Engine {
         // the drop pass recounted every row, including those of the device-memory kernel
         HIP_TRY(launch_fill_u64(&ctr(idx)->kept_global, 1, 0ull, s));
         if (rec) {
-            rec->eps_g = eps_g;
             rec->threshold = t;
             rec->dropped = c;
             rec->alg1_iters = it;
         }
+        alg1_learned[(size_t)idx] = it;
         return FPS_OK;
     }
 
@@ -600,6 +635,7 @@ struct fps_plan_s {
     bool adaptive = false;
     double eps = 0.0, e_r = 0.0;
     int max_alg1 = 200;
+    int alg1_dev_iters = 0;  // Algorithm 1 iterations on the device: 0 learned, < 0 host-driven
     std::vector<double> znorm, zeta, sigma;
     uint64_t flags = 0;
     // series mode (fps_plan_create_series)
@@ -669,7 +705,7 @@ struct fps_plan_s {
         }
     }
 
-    fps_status run_eval(hipStream_t s, bool size)
+    fps_status run_eval(hipStream_t s, bool size, bool host_alg1 = false)
     {
         const int64_t n = Z.n;
         n_stages = 0;
@@ -692,6 +728,7 @@ struct fps_plan_s {
             r->term_src.clear();
             r->eps_g = r->threshold = r->dropped = 0.0;
             r->alg1_iters = 0;
+            r->alg1_device = false;
             if (!ring.empty()) {
                 r->ev0 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2];
                 r->ev1 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2 + 1];
@@ -714,7 +751,9 @@ struct fps_plan_s {
             r->b_is_z = (j == 1);
             r->b_src = (j == 1) ? -1 : pow_stage[(size_t)j];
             FPS_TRY(eng.run(n_stages, a, *P[(size_t)j + 1], s, size, r));
-            if (adaptive) FPS_TRY(eng.alg1(n_stages, *P[(size_t)j + 1], zeta[(size_t)j + 1], e_r, max_alg1, s, r));
+            if (adaptive)
+                FPS_TRY(eng.alg1(n_stages, *P[(size_t)j + 1], zeta[(size_t)j + 1], e_r, max_alg1, s, r,
+                                 host_alg1 ? -1 : alg1_dev_iters));
             pow_stage[(size_t)j + 1] = n_stages++;
         }
 
@@ -760,7 +799,9 @@ struct fps_plan_s {
                 r->b_src = s_stage;
                 add_term_sources(r, sc.b - 1 - i, sc.q - 1, pow_stage);
                 FPS_TRY(eng.run(n_stages, a, S[1 - cur], s, size, r));
-                if (adaptive) FPS_TRY(eng.alg1(n_stages, S[1 - cur], sigma[(size_t)i], e_r, max_alg1, s, r));
+                if (adaptive)
+                    FPS_TRY(eng.alg1(n_stages, S[1 - cur], sigma[(size_t)i], e_r, max_alg1, s, r,
+                                     host_alg1 ? -1 : alg1_dev_iters));
                 s_stage = n_stages++;
                 cur = 1 - cur;
             }
@@ -831,6 +872,8 @@ fps_status fps_plan_create_ex(fps_plan* out, const fps_csr_view* Z, const double
         if (!std::isfinite(opts->e_r) || opts->e_r < 0.0)
             return set_error(FPS_ERR_INVALID_ARG, "e_r must be finite and >= 0");
         if (opts->max_alg1_iters < 0) return set_error(FPS_ERR_INVALID_ARG, "max_alg1_iters must be >= 0");
+        if (opts->alg1_device_iters < -1 || opts->alg1_device_iters > 64)
+            return set_error(FPS_ERR_INVALID_ARG, "alg1_device_iters must be in [-1, 64]");
     } else {
         return set_error(FPS_ERR_INVALID_ARG, "unknown filter %d", opts->filter);
     }
@@ -851,6 +894,7 @@ fps_status fps_plan_create_ex(fps_plan* out, const fps_csr_view* Z, const double
         p->eps = opts->eps;
         p->e_r = opts->e_r;
         p->max_alg1 = opts->max_alg1_iters > 0 ? opts->max_alg1_iters : 200;
+        p->alg1_dev_iters = opts->alg1_device_iters;
         const int tmax = std::max(sc.q, sc.q * (sc.b - 1));
         if (opts->znorm) {
             p->znorm.assign(opts->znorm, opts->znorm + tmax + 1);
@@ -893,7 +937,7 @@ fps_status fps_eval(fps_plan p, fps_stream stream)
 {
     if (!p) return set_error(FPS_ERR_INVALID_ARG, "plan is NULL");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const bool size = (p->flags & FPS_FLAG_SYNC_SIZES) || !p->sized_once || p->adaptive;
+    const bool size = (p->flags & FPS_FLAG_SYNC_SIZES) || !p->sized_once;
     p->last_stream = s;
     fps_status st = p->run_eval(s, size);
     if (st != FPS_OK) return st;
@@ -923,9 +967,11 @@ static fps_status finish(fps_plan p)
     unsigned long long err = 0;
     FPS_TRY(read_errors(p, &err));
     if (err & kErrColumnOutsideWindow) return set_error(FPS_ERR_HIP, "internal error: column outside its row window");
-    if (err & (kErrCapacity | kErrNeedsGlobal)) {
+    if (err & (kErrCapacity | kErrNeedsGlobal | kErrAlg1Pending)) {
+        // re-run with sizing (and, if Algorithm 1 needed more iterations than
+        // were launched on the device, with the host-driven loop)
         p->resizes++;
-        FPS_TRY(p->run_eval(p->last_stream, true));
+        FPS_TRY(p->run_eval(p->last_stream, true, (err & kErrAlg1Pending) != 0));
         HIP_TRY(hipStreamSynchronize(p->last_stream));
         FPS_TRY(read_errors(p, &err));
         if (err) return set_error(FPS_ERR_CAPACITY, "stage workspace exceeded after re-sizing (flags %llx)", err);
@@ -978,6 +1024,9 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
     std::vector<StageCounters> c((size_t)ns);
     HIP_TRY(hipMemcpy(c.data(), p->eng.ws.counters.p, sizeof(StageCounters) * (size_t)ns, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(&st->nnz_out, p->result.rp.as<int64_t>() + p->Z.n, sizeof(int64_t), hipMemcpyDeviceToHost));
+    std::vector<Alg1State> a1((size_t)ns * 3);
+    if (p->adaptive && ns > 0)
+        HIP_TRY(hipMemcpy(a1.data(), p->eng.alg1st.p, sizeof(Alg1State) * 3 * (size_t)ns, hipMemcpyDeviceToHost));
     std::vector<std::array<unsigned long long, kPartCount>> tot((size_t)ns);
     for (int i = 0; i < ns; ++i) {
         const int kind = p->rec[(size_t)i].kind;
@@ -998,6 +1047,12 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
         st->stage_threshold[i] = r.threshold;
         st->stage_dropped[i] = r.dropped;
         st->stage_alg1_iters[i] = r.alg1_iters;
+        if (r.alg1_device) {
+            const Alg1State& f = a1[(size_t)i * 3 + 2];
+            st->stage_threshold[i] = f.t;
+            st->stage_dropped[i] = f.c;
+            st->stage_alg1_iters[i] = f.it;
+        }
         st->stage_nnz[i] = (int64_t)tot[(size_t)i][kPartKept];
         st->products += (int64_t)tot[(size_t)i][kPartProducts];
         st->products_skipped += (int64_t)tot[(size_t)i][kPartProductsSkipped];
@@ -1258,6 +1313,7 @@ fps_status fps_plan_create_series(fps_plan* out, const fps_csr_view* Z, const do
     fps_filter_opts fo{};
     fo.filter = FPS_FILTER_ADAPTIVE;
     fo.max_alg1_iters = opts->max_alg1_iters;
+    fo.alg1_device_iters = opts->alg1_device_iters;
     fo.eps = budget;
     fo.e_r = opts->e_r;
     fo.znorm = z.data();

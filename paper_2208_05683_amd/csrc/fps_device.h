@@ -59,6 +59,25 @@ struct StageCounters {
     unsigned long long pad[4];
 };
 
+// Algorithm 1 on the device (one record per state slot; three per stage: two
+// alternating iteration states and the final record).
+struct Alg1State {
+    double t;      // threshold of the current iteration (the final one once done)
+    double c;      // candidate norm of the final iteration
+    int32_t it;    // iterations done
+    int32_t done;  // the stopping test held
+    int32_t ok;    // final record: 1 = converged within the launched iterations
+    int32_t pad;
+};
+
+struct Alg1Params {
+    double eps_g;   // filtering-norm threshold of the stage (finite, > 0)
+    double target;  // eps_g (1 + e_r)
+    double scale;   // 2^40 / eps_g
+    int32_t max_iter;
+    int32_t pad;
+};
+
 // Per-stage partial sums, one entry per block, layout [kPartCount][part_stride]:
 enum PartIndex : int { kPartProducts = 0, kPartProductsSkipped = 1, kPartRowsSkipped = 2, kPartKept = 3, kPartCount = 4 };
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
@@ -67,6 +86,7 @@ constexpr unsigned long long kErrColumnOutsideWindow = 1;  // span info inconsis
 constexpr unsigned long long kErrCapacity = 2;             // output total above capacity
 constexpr unsigned long long kErrBadCsr = 4;               // validation failure
 constexpr unsigned long long kErrNeedsGlobal = 8;          // a row needed the global-memory kernel that was not scheduled
+constexpr unsigned long long kErrAlg1Pending = 16;         // Algorithm 1 needs more iterations than were launched
 
 enum StageMode : int32_t { kModeProduct = 0, kModeSum = 1 };
 
@@ -146,6 +166,14 @@ hipError_t launch_alg1_colsum(const int64_t* beg, const int64_t* end, const int3
 hipError_t launch_max_u64(const unsigned long long* x, int64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
                             int64_t n, double t, unsigned long long* part_kept, hipStream_t s);
+// Algorithm 1 driven on the device: `iters` iteration kernels (state in
+// st[0..1], column sums in cs[0..2n), maxima in cs[2n..2n+3), all zero on
+// entry), then the final update and the drop; the final record goes to st[2];
+// a stage that has not converged by then keeps its entries and raises
+// kErrAlg1Pending in ctr->errors.
+hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
+                              int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
+                              unsigned long long* part_kept, StageCounters* ctr, hipStream_t s);
 int numeric_global_blocks(int slots);
 // 1-norm estimator (fps_normest.hip)
 hipError_t launch_transpose(const int64_t* rp, const int32_t* col, const double* val, int64_t n, int64_t nnz,

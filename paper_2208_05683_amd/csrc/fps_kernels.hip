@@ -1175,13 +1175,101 @@ __global__ void __launch_bounds__(kBlock) k_max_u64(const unsigned long long* __
     }
 }
 
+// ---- Algorithm 1 driven on the device -------------------------------------------
+// Iteration i uses the state left by iteration i - 1 (slot (i-1)&1) and the
+// candidate norm it measured (max slot (i-1)%3), applies the update of
+// Algorithm 1 (every thread computes the same values), stores its own state
+// in slot i&1 (block 0 thread 0), and, unless the stopping test held,
+// accumulates the integer candidate column sums at its threshold into the
+// column buffer i&1 while clearing the buffers of iteration i + 1; a second
+// kernel takes the largest column sum.  Both run grid-stride loops over a
+// bounded grid, so the launches of iterations that are not needed are cheap.
+
+__device__ __forceinline__ void alg1_update(Alg1State& st, const Alg1Params& pr, unsigned long long mx)
+{
+    const double c = (double)mx / pr.scale;
+    const double m = c / st.t;
+    st.it += 1;
+    if (c > pr.target && st.it < pr.max_iter) {
+        st.t = pr.eps_g / m;
+    } else {
+        st.done = 1;
+        st.c = c;
+    }
+}
+
+__device__ __forceinline__ Alg1State alg1_state(const Alg1Params& pr, int i, const Alg1State* st,
+                                                const unsigned long long* mxs)
+{
+    if (i == 0) return Alg1State{pr.eps_g, 0.0, 0, 0, 0, 0};  // m_0 = 1
+    Alg1State cur = st[(i - 1) & 1];
+    if (!cur.done) alg1_update(cur, pr, mxs[(i - 1) % 3]);
+    return cur;
+}
+
+__global__ void __launch_bounds__(kBlock) k_alg1_iter(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ val, int64_t n, Alg1Params pr, int i,
+                                                      Alg1State* st, unsigned long long* cs)
+{
+    unsigned long long* mxs = cs + 2 * n;
+    const Alg1State cur = alg1_state(pr, i, st, mxs);
+    if (blockIdx.x == 0 && threadIdx.x == 0) st[i & 1] = cur;
+    if (cur.done) return;
+    const int64_t nthreads = (int64_t)gridDim.x * kBlock;
+    unsigned long long* next = cs + (int64_t)((i + 1) & 1) * n;
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n; g += nthreads) next[g] = 0ull;
+    if (blockIdx.x == 0 && threadIdx.x == 0) mxs[(i + 1) % 3] = 0ull;
+    unsigned long long* sums = cs + (int64_t)(i & 1) * n;
+    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t r = xcd_logical_block() * kWavesPerBlock + threadIdx.x / kWave; r < n; r += waves) {
+        for (int64_t p = beg[r] + lane(); p < end[r]; p += kWave) {
+            const double a = fabs(val[p]);
+            if (a > 0.0 && a <= cur.t) atomicAdd(&sums[col[p]], (unsigned long long)ceil(a * pr.scale));
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_alg1_max(int64_t n, int i, const Alg1State* st, unsigned long long* cs)
+{
+    if (st[i & 1].done) return;
+    __shared__ unsigned long long sh[kBlock / kWave];
+    const unsigned long long* sums = cs + (int64_t)(i & 1) * n;
+    unsigned long long m = 0;
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n; g += (int64_t)gridDim.x * kBlock)
+        m = max(m, sums[g]);
+    m = group_max<kWave>(m);
+    if (lane() == 0) sh[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < kBlock / kWave; ++k) t = max(t, sh[k]);
+        if (t) atomicMax(&cs[2 * n + i % 3], t);
+    }
+}
+
 // Drops the entries with |x| <= t of every row in place (the kept entries
 // keep their order), updates end, span and amax, and writes per-block kept
 // counts into `part_kept` (same block layout as the numeric kernel).
-__global__ void __launch_bounds__(kBlock) k_alg1_drop(const int64_t* __restrict__ beg, int64_t* end, int32_t* col,
-                                                      double* val, int2* span, double* amax, int64_t n, double t,
-                                                      unsigned long long* part_kept)
+template <bool kDevice>
+__global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restrict__ beg, int64_t* end, int32_t* col,
+                                                        double* val, int2* span, double* amax, int64_t n, double t,
+                                                        unsigned long long* part_kept, Alg1Params pr, int iters,
+                                                        Alg1State* st, const unsigned long long* cs,
+                                                        StageCounters* ctr)
 {
+    if (kDevice) {  // the final update; the threshold is the last one used
+        const Alg1State fin = alg1_state(pr, iters, st, cs + 2 * n);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            Alg1State rec = fin;
+            rec.ok = fin.done;
+            st[2] = rec;
+            if (!fin.done) atomicOr(&ctr->errors, kErrAlg1Pending);
+            if (fin.done && fin.c > pr.target) atomicOr(&ctr->errors, kErrCapacity);  // iteration limit reached
+        }
+        if (!fin.done) return;
+        t = fin.t;
+    }
     __shared__ unsigned long long kept_sh[kWavesPerBlock];
     const int wv = threadIdx.x / kWave;
     const int l = lane();
@@ -1344,8 +1432,27 @@ hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, doub
                             int64_t n, double t, unsigned long long* part_kept, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_alg1_drop, dim3((unsigned)numeric_blocks(n)), dim3(kBlock), 0, s, beg, end, col, val, span,
-                       amax, n, t, part_kept);
+    hipLaunchKernelGGL(k_alg1_drop_t<false>, dim3((unsigned)numeric_blocks(n)), dim3(kBlock), 0, s, beg, end, col, val,
+                       span, amax, n, t, part_kept, Alg1Params{}, 0, (Alg1State*)nullptr,
+                       (const unsigned long long*)nullptr, (StageCounters*)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
+                              int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
+                              unsigned long long* part_kept, StageCounters* ctr, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)numeric_blocks(n);
+    const unsigned iter_blocks = (unsigned)std::min<int64_t>(2048, numeric_blocks(n));
+    const unsigned max_blocks = (unsigned)std::min<int64_t>(256, (n + kBlock - 1) / kBlock);
+    for (int i = 0; i < iters; ++i) {
+        hipLaunchKernelGGL(k_alg1_iter, dim3(iter_blocks), dim3(kBlock), 0, s, (const int64_t*)beg,
+                           (const int64_t*)end, (const int32_t*)col, (const double*)val, n, pr, i, st, cs);
+        hipLaunchKernelGGL(k_alg1_max, dim3(max_blocks), dim3(kBlock), 0, s, n, i, (const Alg1State*)st, cs);
+    }
+    hipLaunchKernelGGL(k_alg1_drop_t<true>, dim3(blocks), dim3(kBlock), 0, s, beg, end, col, val, span, amax, n, 0.0,
+                       part_kept, pr, iters, st, (const unsigned long long*)cs, ctr);
     return hipGetLastError();
 }
 

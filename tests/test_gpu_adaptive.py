@@ -44,12 +44,14 @@ def znorms(Z, m, s):
     return z
 
 
-def compare_adaptive(Z, c, m, s, eps, e_r=0.1, flags=0, what=""):
+def compare_adaptive(Z, c, m, s, eps, e_r=0.1, flags=0, what="", z=None, device_iters=0):
     from paper_2208_05683_amd import api
 
-    z = znorms(Z, m, s)
+    if z is None:
+        z = znorms(Z, m, s)
     want, st, a1 = O.filtered_ps_adaptive(Z, c, m, s, eps, e_r, z)
-    plan = api.Plan(upload(Z), c, m, s, adaptive=True, eps=eps, e_r=e_r, znorm=z, flags=flags)
+    plan = api.Plan(upload(Z), c, m, s, adaptive=True, eps=eps, e_r=e_r, znorm=z, flags=flags,
+                    alg1_device_iters=device_iters)
     try:
         plan.eval()
         got = download(plan.result())
@@ -101,3 +103,28 @@ def test_adaptive_flags_and_degenerate():
     assert got.nnz == F0.nnz
     # b = 1: nothing but powers
     compare_adaptive(G.laplacian_1d(200, 1.0), G.exp_coeffs(5), 5, 8, 1e-10, what="b=1")
+
+
+@pytest.mark.parametrize("device_iters", [-1, 0, 1, 2, 4])
+def test_adaptive_iteration_drivers_agree(device_iters):
+    # host-driven iterations, or 1, 2, 4 launched on the device (stages needing
+    # more are repeated host-driven by the result query): identical results
+    # and records
+    Z = G.laplacian_2d(60, 2.0)
+    got, want, a1, gst = compare_adaptive(Z, G.exp_coeffs(30), 30, 6, 1e-9, what=f"iters {device_iters}",
+                                          device_iters=device_iters)
+    if device_iters == 1 and max(x["iters"] for x in a1) > 1:
+        assert gst["resizes"] >= 1
+
+
+def test_adaptive_nilpotent_unbounded_thresholds():
+    # J^t = 0 for t >= n: the bounds vanish and the Horner steps whose
+    # threshold is eps / (0 M) = inf are not filtered (as in the oracle)
+    Z = G.shift_matrix(8, value=0.75)
+    m, s = 20, 4
+    sc = O.schedule(m, s)
+    z = O.power_norm_bounds(Z, max(sc["q"], sc["q"] * (sc["b"] - 1)))
+    assert (z == 0).any()
+    for eps in (1e-12, 1e-3):
+        got, want, a1, gst = compare_adaptive(Z, G.exp_coeffs(m), m, s, eps, what="nilpotent", z=z)
+        assert any(np.isinf(x["eps_g"]) for x in a1)
