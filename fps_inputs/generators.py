@@ -190,6 +190,27 @@ def cos_coeffs(m: int) -> np.ndarray:
     return c
 
 
+def sin_coeffs(m: int) -> np.ndarray:
+    """c_{2k+1} = (-1)^k/(2k+1)!, even coefficients 0 (sine series)."""
+    c = np.zeros(m + 1)
+    for k in range(1, m + 1, 2):
+        c[k] = float(Fraction((-1) ** (k // 2), math.factorial(k)))
+    return c
+
+
+def neumann_coeffs(m: int) -> np.ndarray:
+    """c_k = 1 (Neumann series of (I - Z)^{-1}, convergent for rho(Z) < 1)."""
+    return np.ones(m + 1)
+
+
+def log1p_coeffs(m: int) -> np.ndarray:
+    """c_0 = 0, c_k = (-1)^(k+1)/k (log(I + Z), convergent for rho(Z) < 1)."""
+    c = np.zeros(m + 1)
+    for k in range(1, m + 1):
+        c[k] = float(Fraction((-1) ** (k + 1), k))
+    return c
+
+
 def random_series_coeffs(m: int, rng: np.random.Generator) -> np.ndarray:
     """c_k = x_k / k! with x_k ~ N(0, 1), correctly rounded."""
     x = rng.standard_normal(m + 1)

@@ -137,3 +137,29 @@ def test_series_banded_test_set(bw):
     Z = G.banded_sweep_matrix(bw, 1000, seed=1000 * bw)
     compare_series(Z, G.exp_coeffs(199), 1e-14, what=f"band{bw} exp")
     compare_series(Z, G.cos_coeffs(199), 1e-14, what=f"band{bw} cos")
+
+
+def test_series_other_functions():
+    # sine, Neumann series of (I - Z)^{-1} and log(I + Z) in series mode
+    compare_series(G.laplacian_2d(40, 2.0), G.sin_coeffs(70), 1e-12, what="sin")
+    compare_series(G.random_banded(2000, 3, 0.6, 0.5, seed=2), G.neumann_coeffs(220), 1e-10, what="neumann")
+    compare_series(G.laplacian_1d(500, 0.6), G.log1p_coeffs(220), 1e-10, what="log1p")
+
+
+def test_polynomial_mode_sine_computed_bounds():
+    # known degree (eq. 28) with the bounds of eq. 37 taken by the plan
+    from paper_2208_05683_amd import api
+
+    Z = G.random_banded(3000, 4, 0.6, 1.8, seed=6)
+    c, m, s, eps = G.sin_coeffs(25), 25, 5, 1e-11
+    sc = O.schedule(m, s)
+    z = O.power_norm_bounds(Z, max(sc["q"], sc["q"] * (sc["b"] - 1)))
+    want, st, a1 = O.filtered_ps_adaptive(Z, c, m, s, eps, 0.1, z)
+    plan = api.Plan(upload(Z), c, m, s, adaptive=True, eps=eps, e_r=0.1, znorm=None)
+    try:
+        plan.eval()
+        plan.eval()
+        got = download(plan.result())
+    finally:
+        plan.close()
+    assert_same_csr(got, want, "sine polynomial")

@@ -736,3 +736,40 @@ def test_banded_test_set_generator():
         assert Z.n == 1000 and np.abs(i - j).max() == bw
         assert Z.nnz == sum(1000 - abs(k) for k in range(-bw, bw + 1))
         assert abs(Z.val.mean()) < 4.0 / np.sqrt(Z.nnz) and abs(Z.val.std() - 1.0) < 0.05
+
+
+def test_series_coefficient_generators_exact():
+    # sin, Neumann and log(I + Z) coefficients are the correctly rounded
+    # doubles of their rational values
+    s, nm, lg = G.sin_coeffs(21), G.neumann_coeffs(9), G.log1p_coeffs(12)
+    for k in range(22):
+        want = Fraction((-1) ** (k // 2), math.factorial(k)) if k % 2 else Fraction(0)
+        assert s[k] == float(want)
+    assert np.all(nm == 1.0)
+    assert lg[0] == 0.0 and all(lg[k] == float(Fraction((-1) ** (k + 1), k)) for k in range(1, 13))
+
+
+@pytest.mark.parametrize("case", ["sin_lap2d", "neumann_band", "log1p_lap1d", "sin_rand"])
+def test_series_mode_other_functions(case):
+    # Algorithm 2 on other power series: ||f(Z) - F||_1 <= eps_tol against
+    # scipy's dense sinm, inv(I - Z) and logm(I + Z)
+    import scipy.linalg as sl
+
+    if case == "sin_lap2d":
+        Z, a, ref = G.laplacian_2d(10, 2.0), G.sin_coeffs(70), None
+        ref = sl.sinm(Z.to_dense())
+    elif case == "neumann_band":
+        Z, a = G.random_banded(150, 3, 0.6, 0.5, seed=2), G.neumann_coeffs(220)
+        ref = np.linalg.inv(np.eye(Z.n) - Z.to_dense())
+    elif case == "log1p_lap1d":
+        Z, a = G.laplacian_1d(120, 0.6), G.log1p_coeffs(220)
+        ref = sl.logm(np.eye(Z.n) + Z.to_dense()).real
+    else:
+        Z, a = G.random_sparse(60, 0.1, 4, 0.5), G.sin_coeffs(70)
+        ref = sl.sinm(Z.to_dense())
+    for eps_tol in (1e-6, 1e-11):
+        F, info, st, a1 = O.series(Z, a, eps_tol, 0.1)
+        check_canonical(F)
+        assert info["tail"] <= 0.5 * eps_tol
+        err = O.norm1(F.to_dense() - ref)
+        assert err <= eps_tol * 1.1 + 1e-13 * O.norm1(ref), (case, eps_tol, err, info["N"])
