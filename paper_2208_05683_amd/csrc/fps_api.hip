@@ -305,7 +305,7 @@ struct Engine {
         a.n = n;
         a.W = ws.W.as<int32_t>();
         a.lo = ws.lo.as<int32_t>();
-        a.ub = ws.ub.as<int64_t>();
+        a.prod = ws.ub.as<int64_t>();
         a.ctr = ctr(idx);
         a.part = part(idx);
         a.dummy_val = ws.dummy.as<double>();

@@ -109,7 +109,7 @@ struct StageArgs {
     // analysis outputs
     int32_t* W;   // window width (0 = empty row)
     int32_t* lo;  // first column of the window
-    int64_t* ub;  // upper bound of the row's stored entries
+    int64_t* prod;  // entries of the row's main terms (0: the main part is empty)
     // Row offsets of the output: the analysis writes each row's offset within
     // its block of 2^scan_shift rows into out.off and the block totals into
     // blk_pre; a one-block scan turns blk_pre into the exclusive prefix of the

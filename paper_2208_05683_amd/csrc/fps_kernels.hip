@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
             }
             P.W[r] = W;
             P.lo[r] = lo;
-            P.ub[r] = ub;
+            P.prod[r] = prod;
             ubs[grp] = ub;
             // products counted as multiply-adds: the B rows plus, when fused, the block terms
             const int64_t work = prod + (P.has_blk ? elen : 0);
@@ -361,7 +361,7 @@ __global__ void __launch_bounds__(kBlock) k_analyze_sum(StageArgs P)
         }
         P.W[r] = W;
         P.lo[r] = lo;
-        P.ub[r] = ub;
+        P.prod[r] = prod;
         ubv = ub;
         prod_done = (unsigned long long)prod;
     }
@@ -869,21 +869,27 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
         for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave)
             mark_d<kGlobal>((uint32_t)(P.E.col[p] - lo), guard, bytes, bmp);
     }
+    // rows whose main terms have no entries (known from the analysis) skip them
+    const bool has_main = P.prod[r] > 0;
     int64_t tb, te;
     term_range(P, main_src, r, &tb, &te);
-    const Chunk c0 = load_chunk(P, main_src, r, tb, te);
-    const bool one_chunk = (te - tb <= kChunk);
-    const bool flat0 = !use_per_term(main_src, c0);
-    if (flat0) stage_chunk(c0, st);
-    const bool single = one_chunk && flat0 && (c0.total <= kWave);
+    Chunk c0{};
+    bool one_chunk = true, single = false;
     Batch<1> b1;
-    if (single) {
-        if (c0.total > 0) {
-            gather<true>(P, st, 0, c0.total, b1);
-            mark_batch<kGlobal>(lo, guard, b1, bytes, bmp);
+    if (has_main) {
+        c0 = load_chunk(P, main_src, r, tb, te);
+        one_chunk = (te - tb <= kChunk);
+        const bool flat0 = !use_per_term(main_src, c0);
+        if (flat0) stage_chunk(c0, st);
+        single = one_chunk && flat0 && (c0.total <= kWave);
+        if (single) {
+            if (c0.total > 0) {
+                gather<true>(P, st, 0, c0.total, b1);
+                mark_batch<kGlobal>(lo, guard, b1, bytes, bmp);
+            }
+        } else {
+            terms_pass<false, kGlobal>(P, main_src, r, lo, guard, bytes, bmp, nullptr, st, true, c0);
         }
-    } else {
-        terms_pass<false, kGlobal>(P, main_src, r, lo, guard, bytes, bmp, nullptr, st, true, c0);
     }
     wave_sync();
     if (kGlobal) {  // pack the byte map into bits, guard word included
@@ -953,7 +959,8 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     wave_sync();
 
     // 4. main terms in order, parked; then the extra part on its own
-    if (single) {
+    if (!has_main) {
+    } else if (single) {
         if (c0.total > 0) accumulate_batch(c0, 0, lo, guard, b1, bmp, acc);
     } else {
         terms_pass<true, kGlobal>(P, main_src, r, lo, guard, nullptr, bmp, acc, st, one_chunk, c0);
