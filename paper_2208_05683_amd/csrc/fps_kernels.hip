@@ -389,8 +389,8 @@ struct WaveStage {
     int64_t beg[kChunk];   // first entry of the term's row
 };
 
-// The structural column list of a row is kept in the row's own output slot
-// (P.out.col[off..off+ns)), which the write-out then compacts in place.
+// Once the row's values have moved to registers, the accumulator holds the
+// structural column list of the row (int32, slot order) for the write-out.
 struct LdsWave {
     uint2 bmp[kLdsWords + 1];  // per 32 window columns: .x structure bits, .y set bits in earlier words;
                                // then the guard word
@@ -942,20 +942,26 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
         return true;
     }
 
-    // 3. zero the accumulator, list the columns in slot order (in the row's
-    //    output slot, compacted in place by the write-out)
-    int32_t* cols = P.out.col + o;
-    for (int64_t i = l; i < ns; i += kWave) acc[i] = 0.0;
-    for (int64_t w = l; w < words; w += kWave) {
-        const uint2 wd = bmp[w];
-        uint32_t bits = wd.x;
-        uint32_t base = wd.y;
-        while (bits) {
-            const int bt = __ffs((int)bits) - 1;
-            cols[base++] = lo + (int32_t)(w * 32 + bt);
-            bits &= bits - 1u;
+    // the columns in slot order: lane w lists the set bits of word w
+    auto list_cols = [&](int32_t* cols) {
+        for (int64_t w = l; w < words; w += kWave) {
+            const uint2 wd = bmp[w];
+            uint32_t bits = wd.x;
+            uint32_t base = wd.y;
+            while (bits) {
+                const int bt = __ffs((int)bits) - 1;
+                cols[base++] = lo + (int32_t)(w * 32 + bt);
+                bits &= bits - 1u;
+            }
         }
-    }
+    };
+
+    // 3. zero the accumulator.  The device-memory kernel lists the columns
+    //    now, in the row's output slot (compacted in place by the write-out);
+    //    the shared-memory kernel lists them in shared memory after the
+    //    accumulation (step 5).
+    for (int64_t i = l; i < ns; i += kWave) acc[i] = 0.0;
+    if (kGlobal) list_cols(P.out.col + o);
     wave_sync();
 
     // 4. main terms in order, parked; then the extra part on its own
@@ -993,22 +999,17 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
         }
         wave_sync();
     }
-    // 5. x = extra + main, drop test, sorted write-out.  Entry i moves to
-    //    position kept-before-i <= i of the same slot: a batch reads its
-    //    columns before any of its writes (they depend on the loaded values)
-    //    and writes only below the next batch's reads.
+    // 5. x = extra + main, drop test, sorted write-out.  (Device-memory
+    //    kernel: entry i moves to position kept-before-i <= i of the same
+    //    slot; a batch reads its columns before any of its writes, which
+    //    depend on the loaded values, and writes only below the next batch's
+    //    reads.)
     int64_t kept = 0;
     double amx = 0.0;
     int32_t first = INT_MAX, last = -1;
-    auto emit = [&](int64_t i, double parked) {
-        double x = 0.0;
-        int32_t c = 0;
+    auto emit = [&](int64_t i, double x, int32_t c) {
         bool keep = false;
-        if (i < ns) {
-            x = has_extra ? acc[i] + parked : acc[i];
-            c = cols[i];
-            keep = (x != 0.0) && !(fabs(x) < P.tau);
-        }
+        if (i < ns) keep = (x != 0.0) && !(fabs(x) < P.tau);
         const unsigned long long m = __ballot(keep);
         if (keep) {
             const int64_t pos = o + kept + (int64_t)lanes_below(m);
@@ -1021,14 +1022,34 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
         kept += __popcll(m);
     };
     if (kGlobal) {
+        const int32_t* cols = P.out.col + o;
         for (int64_t i0 = 0; i0 < ns; i0 += kWave) {
             const int64_t i = i0 + l;
-            emit(i, (has_extra && i < ns) ? ebuf[i] : 0.0);
+            double x = 0.0;
+            int32_t c = 0;
+            if (i < ns) {
+                x = has_extra ? acc[i] + ebuf[i] : acc[i];
+                c = cols[i];
+            }
+            emit(i, x, c);
         }
     } else {
+        // the values move to registers (x = extra + parked main part), which
+        // frees the accumulator for the column list
 #pragma unroll
-        for (int t = 0; t < kParked; ++t)
-            if ((int64_t)t * kWave < ns) emit((int64_t)t * kWave + l, preg[t]);
+        for (int t = 0; t < kParked; ++t) {
+            const int64_t i = (int64_t)t * kWave + l;
+            if (i < ns) preg[t] = has_extra ? acc[i] + preg[t] : acc[i];
+        }
+        wave_sync();
+        int32_t* cols = reinterpret_cast<int32_t*>(acc);
+        list_cols(cols);
+        wave_sync();
+#pragma unroll
+        for (int t = 0; t < kParked; ++t) {
+            const int64_t i = (int64_t)t * kWave + l;
+            if ((int64_t)t * kWave < ns) emit(i, preg[t], i < ns ? cols[i] : 0);
+        }
     }
     amx = group_max<kWave>(amx);
     first = group_min<kWave>(first);
