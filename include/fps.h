@@ -123,7 +123,10 @@ typedef struct {
     int64_t products;             /* multiply-adds performed in the last evaluation */
     int64_t products_skipped;     /* multiply-adds avoided by the exact bound test */
     int64_t rows_skipped;         /* output rows proven empty by the bound test */
-    int64_t rows_global;          /* rows handled by the global-memory kernel */
+    int64_t rows_global;          /* rows handled by the device-memory kernel (more than 448 structural
+                                     entries or a window wider than 8192 columns) */
+    int64_t rows_wide;            /* rows handled by the wide shared-memory kernel (more than 320
+                                     entries or a window wider than 6144 columns) */
     int64_t resizes;              /* evaluations that had to re-size a buffer */
     double bytes_algorithmic;     /* per evaluation, summed over stages: every operand entry read once and
                                      every kept entry written once at 12 bytes (8 value + 4 column), plus

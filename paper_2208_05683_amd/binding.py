@@ -56,7 +56,7 @@ class fps_stats(C.Structure):
         ("start", C.c_int32), ("n_spgemm", C.c_int32), ("n_stages", C.c_int32),
         ("evals", C.c_int64), ("nnz_out", C.c_int64), ("products", C.c_int64),
         ("products_skipped", C.c_int64), ("rows_skipped", C.c_int64), ("rows_global", C.c_int64),
-        ("resizes", C.c_int64), ("bytes_algorithmic", C.c_double), ("numeric_ms", C.c_double),
+        ("rows_wide", C.c_int64), ("resizes", C.c_int64), ("bytes_algorithmic", C.c_double), ("numeric_ms", C.c_double),
         ("numeric_launches", C.c_int32),
         ("kind", C.c_int32 * FPS_MAX_STAGES), ("index", C.c_int32 * FPS_MAX_STAGES),
         ("stage_products", C.c_int64 * FPS_MAX_STAGES), ("stage_nnz", C.c_int64 * FPS_MAX_STAGES),

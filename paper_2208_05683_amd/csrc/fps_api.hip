@@ -127,8 +127,8 @@ struct CanonMatrix {
 // Per-row workspace shared by the stages of one engine.
 struct Workspace {
     int64_t n = 0;
-    DevBuf W, lo, ub, fb, blk_pre, zspan, zamax, gscratch, counters, part, dummy;
-    int64_t g_words = 0, g_cap = 0, g_stride = 0, g_off_acc = 0, g_off_ebuf = 0, g_off_cols = 0;
+    DevBuf W, lo, ub, fb, fb2, blk_pre, zspan, zamax, gscratch, counters, part, dummy;
+    int64_t g_words = 0, g_cap = 0, g_stride = 0, g_off_acc = 0, g_off_ebuf = 0;
     int64_t part_stride = 0;
     int32_t g_slots = 0;
     int max_stages = 0;
@@ -142,6 +142,7 @@ struct Workspace {
         FPS_TRY(lo.ensure(sizeof(int32_t) * rows));
         FPS_TRY(ub.ensure(sizeof(int64_t) * rows));
         FPS_TRY(fb.ensure(sizeof(int64_t) * rows));
+        FPS_TRY(fb2.ensure(sizeof(int64_t) * rows));
         FPS_TRY(blk_pre.ensure(sizeof(int64_t) * (size_t)(std::max({analyze_blocks(kModeProduct, nn),
                                                                     analyze_blocks(kModeSum, nn),
                                                                     offset_blocks(nn)}) + 1)));
@@ -162,12 +163,11 @@ struct Workspace {
         g_words = (nn + 31) / 32;
         g_cap = std::max<int64_t>(nn, 1);
         // per slot (4-byte units): byte map and guard word [8 (words + 1)] | bitmap words as uint2 and
-        // the guard word [2 (words + 1)] | accumulator and the spare slot [2 (cap + 1)] | parked extra
-        // values [2 cap] | column list [cap]
+        // the guard word [2 (words + 1)] | accumulator and the spare slot [2 (cap + 1)] | parked
+        // values [2 cap]
         g_off_acc = 10 * (g_words + 1);
         g_off_ebuf = g_off_acc + 2 * (g_cap + 1);
-        g_off_cols = g_off_ebuf + 2 * g_cap;
-        const int64_t per_slot_u32 = (g_off_cols + g_cap + 63) / 64 * 64;
+        const int64_t per_slot_u32 = (g_off_ebuf + 2 * g_cap + 63) / 64 * 64;
         g_stride = per_slot_u32;
         // up to 2048 wavefronts (eight per CU) with a workspace each, 4 GiB at most
         const int64_t budget = int64_t(1) << 32;
@@ -258,7 +258,8 @@ struct Engine {
     DevBuf alg1st;  // per stage: two Algorithm 1 iteration states and the final record
     uint64_t flags = 0;
     std::vector<int64_t> learned;  // per stage index: output capacity learned by a sizing run
-    std::vector<bool> learned_global;
+    std::vector<bool> learned_wide;    // per stage: some row needs the wide shared-memory tier
+    std::vector<bool> learned_global;  // per stage: some row needs the device-memory kernel
     std::vector<int> alg1_learned;  // per stage: Algorithm 1 iterations of the last host-driven run
 
     StageCounters* ctr(int i) const { return ws.counters.as<StageCounters>() + i; }
@@ -290,6 +291,7 @@ struct Engine {
     {
         flags = fl;
         learned.assign((size_t)stages, -1);
+        learned_wide.assign((size_t)stages, false);
         learned_global.assign((size_t)stages, false);
         alg1_learned.assign((size_t)stages, 0);
         FPS_TRY(alg1st.ensure(sizeof(Alg1State) * 3 * (size_t)std::max(stages, 1)));
@@ -312,13 +314,13 @@ struct Engine {
         a.dummy_col = reinterpret_cast<const int32_t*>(ws.dummy.as<double>() + 128);
         a.part_stride = ws.part_stride;
         a.fb_list = ws.fb.as<int64_t>();
+        a.fb2_list = ws.fb2.as<int64_t>();
         a.g_scratch = ws.gscratch.as<uint32_t>();
         a.g_slot_words = ws.g_words;
         a.g_slot_cap = ws.g_cap;
         a.g_slot_stride = ws.g_stride;
         a.g_off_acc = ws.g_off_acc;
         a.g_off_ebuf = ws.g_off_ebuf;
-        a.g_off_cols = ws.g_off_cols;
         a.g_slots = ws.g_slots;
         a.force_global = (flags & FPS_FLAG_FORCE_GLOBAL) ? 1 : 0;
         FPS_TRY(out.ensure_rows(n));
@@ -326,7 +328,7 @@ struct Engine {
         a.scan_shift = analyze_shift(a.mode);
         a.out = out.out();  // the analysis writes the row offsets (out.off)
         HIP_TRY(launch_analyze(a, s));
-        bool run_global = true;
+        bool run_wide = true, run_global = true;
         if (size || learned[(size_t)idx] < 0) {
             int64_t total = 0;
             HIP_TRY(hipMemcpyAsync(&total, out.off.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -335,20 +337,24 @@ struct Engine {
             learned[(size_t)idx] = std::max<int64_t>(learned[(size_t)idx], total);
         } else {
             FPS_TRY(out.ensure_cap(learned[(size_t)idx]));
+            run_wide = learned_wide[(size_t)idx] && !a.force_global;
             run_global = learned_global[(size_t)idx] || a.force_global;
         }
         a.out = out.out();
+        a.wide_planned = run_wide ? 1 : 0;
         a.global_planned = run_global ? 1 : 0;
         if (rec && rec->ev0) HIP_TRY(hipEventRecord(rec->ev0, s));
         HIP_TRY(launch_numeric_lds(a, 0, s));
         if (rec && rec->ev1) HIP_TRY(hipEventRecord(rec->ev1, s));
+        if (run_wide) HIP_TRY(launch_numeric_wide(a, numeric_wide_blocks(n), s));
         if (run_global) HIP_TRY(launch_numeric_global(a, numeric_global_blocks(ws.g_slots), s));
         if (size) {
-            // learn whether this stage needs the global-memory kernel
+            // learn which of the fallback kernels this stage needs
             StageCounters c{};
             HIP_TRY(hipMemcpyAsync(&c, ctr(idx), sizeof(c), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            if (c.fb_count > 0) learned_global[(size_t)idx] = true;
+            if (c.fb_count > 0) learned_wide[(size_t)idx] = true;
+            if (c.fb2_count > 0) learned_global[(size_t)idx] = true;
         }
         return FPS_OK;
     }
@@ -1057,7 +1063,8 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
         st->products += (int64_t)tot[(size_t)i][kPartProducts];
         st->products_skipped += (int64_t)tot[(size_t)i][kPartProductsSkipped];
         st->rows_skipped += (int64_t)tot[(size_t)i][kPartRowsSkipped];
-        st->rows_global += (int64_t)c[(size_t)i].fb_count;
+        st->rows_global += (int64_t)c[(size_t)i].fb2_count;
+        st->rows_wide += (int64_t)c[(size_t)i].rows_wide;
         const double za = (double)p->Z.nnz;
         if (r.kind == FPS_STAGE_POWER || r.kind == FPS_STAGE_HORNER) {
             const double na = r.a_is_z ? za : (r.a_src >= 0 ? kept(r.a_src) : 0.0);

@@ -52,11 +52,14 @@ struct OutView {
 // events use them; per-row statistics go to per-block partial sums (below)
 // so that no hot path contends on one address.
 struct StageCounters {
-    unsigned long long fb_count;     // rows appended to the fallback list
-    unsigned long long fb_next;      // dynamic fetch, global-memory kernel
+    unsigned long long fb_count;     // rows appended to the wide-tier list (fb_list)
+    unsigned long long fb_next;      // dynamic fetch from fb_list, wide-tier kernel
     unsigned long long errors;       // bit flags, see kErr*
-    unsigned long long kept_global;  // stored entries written by the global-memory kernel
-    unsigned long long pad[4];
+    unsigned long long kept_global;  // stored entries written by the wide-tier and device-memory kernels
+    unsigned long long fb2_count;    // rows appended to the device-memory list (fb2_list)
+    unsigned long long fb2_next;     // dynamic fetch from fb2_list, device-memory kernel
+    unsigned long long rows_wide;    // rows computed by the wide-tier kernel
+    unsigned long long pad;
 };
 
 // Algorithm 1 on the device (one record per state slot; three per stage: two
@@ -124,17 +127,19 @@ struct StageArgs {
     const double* dummy_val;
     unsigned long long* part;  // this stage's partial sums
     int64_t part_stride;
-    int64_t* fb_list;       // n entries
+    int64_t* fb_list;       // n entries: rows for the wide shared-memory tier
+    int64_t* fb2_list;      // n entries: rows for the device-memory kernel
     uint32_t* g_scratch;    // global-memory kernel workspace
     int64_t g_slot_words;   // bitmap words per slot (each array has room for one guard word / spare slot more)
     int64_t g_slot_cap;     // accumulator entries per slot
     int64_t g_slot_stride;  // 4-byte units between slots (multiple of 64)
     int64_t g_off_acc;      // 4-byte offsets of the slot's arrays: byte map at 0, bitmap words (uint2) at
-    int64_t g_off_ebuf;     //   8 (words + 1), then accumulator, parked extra values and column list
-    int64_t g_off_cols;
+    int64_t g_off_ebuf;     //   8 (words + 1), then accumulator and parked values
     int32_t g_slots;
     int32_t force_global;
-    int32_t global_planned;  // 0: the global-memory kernel will not run for this stage
+    int32_t global_planned;  // 0: the device-memory kernel will not run for this stage
+    int32_t wide_planned;    // 0: the wide-tier kernel will not run for this stage
+    int32_t plan_pad;
 };
 
 // ---- launch wrappers (fps_kernels.hip) ---------------------------------
@@ -146,6 +151,9 @@ hipError_t launch_analyze(const StageArgs& a, hipStream_t s);
 // log2 of the rows per analysis block (the numeric kernel's offset fix-up)
 int analyze_shift(int32_t mode);
 hipError_t launch_numeric_lds(const StageArgs& a, int grid, hipStream_t s);
+// rows of fb_list (persistent blocks: the grid size only sets the parallelism)
+hipError_t launch_numeric_wide(const StageArgs& a, int grid, hipStream_t s);
+// rows of fb2_list
 hipError_t launch_numeric_global(const StageArgs& a, int grid, hipStream_t s);
 // Canonical row pointers of a slack matrix: rp[r] gets the row's offset
 // within its block of 256 rows, blk_pre the exclusive prefix of the block
@@ -175,6 +183,8 @@ hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, do
                               int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
                               unsigned long long* part_kept, StageCounters* ctr, hipStream_t s);
 int numeric_global_blocks(int slots);
+// blocks of the wide-tier kernel (persistent: six per CU at most)
+int numeric_wide_blocks(int64_t n);
 // 1-norm estimator (fps_normest.hip)
 hipError_t launch_transpose(const int64_t* rp, const int32_t* col, const double* val, int64_t n, int64_t nnz,
                             unsigned long long* cnt, int64_t* trp, int32_t* trow_tmp, double* tval_tmp, int32_t* trow,

@@ -32,8 +32,13 @@
 namespace fps {
 namespace {
 
-constexpr int kLdsWords = 256;  // window of up to 8192 columns in shared memory
-constexpr int kLdsCap = 448;    // up to 448 structural entries per row in shared memory
+// Shared-memory tiers of the numeric kernel.  Narrow: windows of up to 6144
+// columns and 320 structural entries, 19.5 KB per four-wavefront block and at
+// most 64 VGPRs, so eight wavefronts per SIMD.  Wide (rows that do not fit
+// the narrow tier): 8192 columns and 448 entries.  Larger rows take the
+// device-memory kernel.
+constexpr int kNarrowWords = 192, kNarrowCap = 320;
+constexpr int kWideWords = 256, kWideCap = 448;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 
@@ -391,15 +396,15 @@ struct WaveStage {
 
 // Once the row's values have moved to registers, the accumulator holds the
 // structural column list of the row (int32, slot order) for the write-out.
+template <int kWords, int kCap>
 struct LdsWave {
-    uint2 bmp[kLdsWords + 1];  // per 32 window columns: .x structure bits, .y set bits in earlier words;
-                               // then the guard word
-    double acc[kLdsCap + 1];   // then the spare slot
+    static_assert(kCap % kWave == 0, "the parked values cover the accumulator exactly");
+    static constexpr int kPark = kCap / kWave;  // parked values per lane
+    uint2 bmp[kWords + 1];  // per 32 window columns: .x structure bits, .y set bits in earlier words;
+                            // then the guard word
+    double acc[kCap + 1];   // then the spare slot
     WaveStage st;
 };
-
-constexpr int kParked = kLdsCap / kWave;  // parked values per lane (shared-memory kernel)
-static_assert(kLdsCap % kWave == 0, "the parked values cover the accumulator exactly");
 constexpr int kU = 4;                     // flattened batch: kU sub-batches of 64 products
 constexpr int kStep = 2 * kWave;          // per-term step: 128 entries of one term row
 
@@ -597,7 +602,7 @@ __device__ __forceinline__ void accumulate_batch(const Chunk& c, int32_t q0, int
 // are applied one after the other.  Entries beyond kStep (rows longer than
 // 128) are handled right after their term's first part.
 
-constexpr int kGroup = 4;  // terms per group (products; coefficient terms go two at a time, which keeps
+constexpr int kGroup = 3;  // terms per group (products; coefficient terms go two at a time, which keeps
                            // the register budget while the main part is parked in registers)
 __host__ __device__ constexpr int group_size(int src) { return src == 0 ? kGroup : 2; }
 constexpr int kRsrcWord3 = 0x00020000;  // raw (unswizzled, stride 0) buffer of 32-bit elements
@@ -628,21 +633,21 @@ __device__ __forceinline__ TermDesc term_desc(const StageArgs& P, int64_t t0, co
     const int64_t beg = readlane64(c.beg, il);
     h.t.a = kNeedV ? readlaned(c.a, il) : 0.0;
     h.t.ident = SRC == kSrcCoefs && h.t.len > 0 && beg < 0;
-    const int32_t* cb = P.dummy_col;
-    const double* vb = P.dummy_val;
-    int32_t real = 0;
-    if (!h.t.ident && h.t.len > 0) {
-        real = h.t.len;
-        if (SRC == kSrcProducts) {
-            cb = P.B.col + beg;
-            vb = P.B.val + beg;
-        } else {
-            cb = P.T.col[t0 + il] + beg;
-            vb = P.T.val[t0 + il] + beg;
-        }
+    // no term, or the identity (whose entry is not read): an empty buffer,
+    // whose loads return zeros without touching memory, so the base address
+    // does not matter
+    const int32_t real = h.t.ident ? 0 : h.t.len;
+    uintptr_t cb, vb;
+    if (SRC == kSrcProducts) {
+        cb = reinterpret_cast<uintptr_t>(P.B.col);
+        vb = reinterpret_cast<uintptr_t>(P.B.val);
+    } else {
+        const int ti = min((int)t0 + il, kMaxTerms - 1);
+        cb = reinterpret_cast<uintptr_t>(P.T.col[ti]);
+        vb = reinterpret_cast<uintptr_t>(P.T.val[ti]);
     }
-    h.rc = row_rsrc(cb, real * 4);
-    h.rv = row_rsrc(vb, real * 8);
+    h.rc = row_rsrc(reinterpret_cast<const void*>(cb + (uintptr_t)beg * 4u), real * 4);
+    h.rv = row_rsrc(reinterpret_cast<const void*>(vb + (uintptr_t)beg * 8u), real * 8);
     return h;
 }
 
@@ -685,7 +690,9 @@ struct Slots {
 
 // Accumulator slots of a part's entries; lanes without an entry get the spare
 // slot.  Every column of the row lies in the window (checked after the
-// structure pass).
+// structure pass).  kBoth: the second half of the part as well (the spare
+// slot for every lane if the row ends in the first half).
+template <bool kBoth>
 __device__ __forceinline__ Slots part_slots(const TermInfo& h, int32_t e0, const Part& p, int64_t r, int32_t lo,
                                             uint32_t guard, const uint2* bmp)
 {
@@ -693,8 +700,7 @@ __device__ __forceinline__ Slots part_slots(const TermInfo& h, int32_t e0, const
     const int32_t c0 = h.ident ? (int32_t)r : p.c0;
     Slots s;
     s.s0 = rank_of(bmp, (e0 + l < h.len) ? (uint32_t)(c0 - lo) : guard);
-    s.s1 = 0;
-    if (h.len > e0 + kWave) s.s1 = rank_of(bmp, (e0 + kWave + l < h.len) ? (uint32_t)(p.c1 - lo) : guard);
+    s.s1 = kBoth ? rank_of(bmp, (e0 + kWave + l < h.len) ? (uint32_t)(p.c1 - lo) : guard) : 0u;
     return s;
 }
 
@@ -747,9 +753,19 @@ __device__ __forceinline__ void run_group(const StageArgs& P, int64_t r, int64_t
             }
         }
     } else {
+        // the ranks of the whole group first, without branches between the
+        // bitmap reads: second halves for every term if any term needs them
         Slots s[kGroup];
+        bool two = false;
 #pragma unroll
-        for (int g = 0; g < group_size(SRC); ++g) s[g] = part_slots(h[g], 0, p[g], r, lo, guard, bmp);
+        for (int g = 0; g < group_size(SRC); ++g) two = two || h[g].len > kWave;
+        if (two) {
+#pragma unroll
+            for (int g = 0; g < group_size(SRC); ++g) s[g] = part_slots<true>(h[g], 0, p[g], r, lo, guard, bmp);
+        } else {
+#pragma unroll
+            for (int g = 0; g < group_size(SRC); ++g) s[g] = part_slots<false>(h[g], 0, p[g], r, lo, guard, bmp);
+        }
 #pragma unroll
         for (int g = 0; g < group_size(SRC); ++g) {
             if (h[g].len == 0) continue;
@@ -759,7 +775,7 @@ __device__ __forceinline__ void run_group(const StageArgs& P, int64_t r, int64_t
                 const TermDesc d = term_desc<SRC, true>(P, t0, c, i0 + g);
                 for (int32_t e0 = kStep; e0 < h[g].len; e0 += kStep) {
                     const Part q = load_part<true>(d, e0);
-                    accumulate_part(h[g], e0, q, part_slots(h[g], e0, q, r, lo, guard, bmp), acc);
+                    accumulate_part(h[g], e0, q, part_slots<true>(h[g], e0, q, r, lo, guard, bmp), acc);
                     wave_sync();
                 }
             }
@@ -821,6 +837,16 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
     }
 }
 
+// Row r of the stage output left empty at offset o (one lane writes): every
+// row gets its end, span and maximum in every evaluation, so that later stages
+// and the compaction never read a previous evaluation's values.
+__device__ __forceinline__ void empty_row(const StageArgs& P, int64_t r, int64_t o)
+{
+    P.out.end[r] = o;
+    P.out.span[r] = make_int2(1, 0);
+    P.out.amax[r] = 0.0;
+}
+
 // Computes output row r.  Returns false (with nothing written) if the row
 // needs more workspace than max_words / cap provide.
 //
@@ -832,7 +858,7 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
 // test and a sorted, coalesced write-out.  Rows whose main terms are at most
 // 64 short-row products keep them in registers from the structure pass to
 // the accumulation.
-template <bool kGlobal>
+template <bool kGlobal, int kParked>
 __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64_t o, uint8_t* bytes, uint2* bmp,
                                             double* acc, double* ebuf, WaveStage& st, int64_t max_words, int64_t cap,
                                             int64_t* kept_out)
@@ -841,11 +867,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     *kept_out = 0;
     const int32_t W = P.W[r];
     if (W <= 0) {
-        if (l == 0) {
-            P.out.end[r] = o;
-            P.out.span[r] = make_int2(1, 0);
-            P.out.amax[r] = 0.0;
-        }
+        if (l == 0) empty_row(P, r, o);
         return true;
     }
     const int32_t lo = P.lo[r];
@@ -910,11 +932,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     // operand was inconsistent: the stage reports an error, the row stays empty
     if (bmp[words].x & 1u) {
         flag_error(P, kErrColumnOutsideWindow);
-        if (l == 0) {
-            P.out.end[r] = o;
-            P.out.span[r] = make_int2(1, 0);
-            P.out.amax[r] = 0.0;
-        }
+        if (l == 0) empty_row(P, r, o);
         return true;
     }
 
@@ -934,11 +952,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     if (ns > cap) return false;
     if (o + ns > P.out.cap) {
         flag_error(P, kErrCapacity);
-        if (l == 0) {
-            P.out.end[r] = o;
-            P.out.span[r] = make_int2(1, 0);
-            P.out.amax[r] = 0.0;
-        }
+        if (l == 0) empty_row(P, r, o);
         return true;
     }
 
@@ -1064,15 +1078,34 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     return true;
 }
 
-// One row per wavefront, four rows per block, blocks in XCD-aware order.
-// The shared-memory workspace (25.7 KB per block) and the register budget
-// (80 per lane) are sized for six wavefronts per SIMD.
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) k_numeric_lds(StageArgs P)
+// Appends row r (output offset o) to a fallback list, called by one lane.
+// If the kernel that serves the list does not run for this stage (`planned`
+// is 0), the row is left empty and flagged instead: the result query then
+// repeats the evaluation with sizing, which plans that kernel.
+__device__ __forceinline__ void defer_row(const StageArgs& P, int64_t r, int64_t o, unsigned long long* count,
+                                          int64_t* list, int32_t planned)
 {
-    __shared__ LdsWave lds[kWavesPerBlock];
+    if (planned) {
+        const unsigned long long i = atomicAdd(count, 1ull);
+        list[i] = r;
+    } else {
+        empty_row(P, r, o);
+        flag_error(P, kErrNeedsGlobal);
+    }
+}
+
+// One row per wavefront, four rows per block, blocks in XCD-aware order.
+// Narrow shared-memory tier: the workspace (19.5 KB per block) and the
+// register budget (64 per lane) are sized for eight wavefronts per SIMD.
+// Rows that do not fit go to the wide tier's list (with FPS_FLAG_FORCE_GLOBAL
+// every row goes straight to the device-memory kernel's list).
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_numeric_lds(StageArgs P)
+{
+    using Ws = LdsWave<kNarrowWords, kNarrowCap>;
+    __shared__ Ws lds[kWavesPerBlock];
     __shared__ unsigned long long kept_sh[kWavesPerBlock];
     const int wv = sgpr((int32_t)(threadIdx.x / kWave));  // wave-uniform: row-level values live in scalar registers
-    LdsWave& me = lds[wv];
+    Ws& me = lds[wv];
     const int l = lane();
     const int64_t blk = xcd_logical_block();
     const int64_t r = blk * kWavesPerBlock + wv;
@@ -1083,11 +1116,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 
         if (l == 0) P.out.off[r] = o;
         bool done = false;
         if (!P.force_global)
-            done = process_row<false>(P, r, o, nullptr, me.bmp, me.acc, nullptr, me.st, kLdsWords, kLdsCap, &kept);
+            done = process_row<false, Ws::kPark>(P, r, o, nullptr, me.bmp, me.acc, nullptr, me.st, kNarrowWords,
+                                                 kNarrowCap, &kept);
         if (!done && l == 0) {
-            const unsigned long long i = atomicAdd(&P.ctr->fb_count, 1ull);
-            P.fb_list[i] = r;
-            if (!P.global_planned) flag_error(P, kErrNeedsGlobal);
+            const bool direct = P.force_global != 0;
+            defer_row(P, r, o, direct ? &P.ctr->fb2_count : &P.ctr->fb_count, direct ? P.fb2_list : P.fb_list,
+                      direct ? P.global_planned : P.wide_planned);
         }
     }
     if (l == 0) kept_sh[wv] = (unsigned long long)kept;
@@ -1099,8 +1133,41 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 
     }
 }
 
-// Rows that did not fit the shared-memory workspace: per-wave workspace in
-// device memory sized for a full row, rows fetched from the fallback list.
+// Rows of the wide tier's list, fetched dynamically (few rows, usually): 25.7
+// KB of shared memory per block; the register budget of four wavefronts per
+// SIMD keeps the persistent loop free of spills.  Rows that do not fit
+// either go to the device-memory kernel's list.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 8))) k_numeric_wide(StageArgs P)
+{
+    using Ws = LdsWave<kWideWords, kWideCap>;
+    __shared__ Ws lds[kWavesPerBlock];
+    const int wv = sgpr((int32_t)(threadIdx.x / kWave));
+    Ws& me = lds[wv];
+    const int l = lane();
+    const unsigned long long count = __hip_atomic_load(&P.ctr->fb_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long kept = 0, rows = 0;
+    while (true) {
+        unsigned long long i = 0;
+        if (l == 0) i = atomicAdd(&P.ctr->fb_next, 1ull);
+        i = __shfl(i, 0, kWave);
+        if (i >= count) break;
+        const int64_t r = sgpr64(P.fb_list[i]);
+        const int64_t o = sgpr64(P.out.off[r]);
+        int64_t k = 0;
+        if (process_row<false, Ws::kPark>(P, r, o, nullptr, me.bmp, me.acc, nullptr, me.st, kWideWords, kWideCap,
+                                          &k)) {
+            kept += (unsigned long long)k;
+            ++rows;
+        } else if (l == 0) {
+            defer_row(P, r, o, &P.ctr->fb2_count, P.fb2_list, P.global_planned);
+        }
+    }
+    if (l == 0 && kept) atomicAdd(&P.ctr->kept_global, kept);
+    if (l == 0 && rows) atomicAdd(&P.ctr->rows_wide, rows);
+}
+
+// Rows that did not fit shared memory: per-wave workspace in device memory
+// sized for a full row, rows fetched dynamically from the device-memory list.
 __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
 {
     __shared__ WaveStage st[kWavesPerBlock];
@@ -1113,17 +1180,20 @@ __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
     uint2* bmp = reinterpret_cast<uint2*>(base + (P.g_slot_words + 1) * 8);
     double* acc = reinterpret_cast<double*>(base + P.g_off_acc);
     double* ebuf = reinterpret_cast<double*>(base + P.g_off_ebuf);
-    const unsigned long long count = __hip_atomic_load(&P.ctr->fb_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long count = __hip_atomic_load(&P.ctr->fb2_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned long long kept = 0;
     while (true) {
         unsigned long long i = 0;
-        if (l == 0) i = atomicAdd(&P.ctr->fb_next, 1ull);
+        if (l == 0) i = atomicAdd(&P.ctr->fb2_next, 1ull);
         i = __shfl(i, 0, kWave);
         if (i >= count) break;
-        const int64_t r = sgpr64(P.fb_list[i]);
+        const int64_t r = sgpr64(P.fb2_list[i]);
+        const int64_t o = sgpr64(P.out.off[r]);
         int64_t k = 0;
-        if (!process_row<true>(P, r, P.out.off[r], bytes, bmp, acc, ebuf, st[wv], P.g_slot_words, P.g_slot_cap, &k))
+        if (!process_row<true, 1>(P, r, o, bytes, bmp, acc, ebuf, st[wv], P.g_slot_words, P.g_slot_cap, &k)) {
             flag_error(P, kErrCapacity);
+            if (l == 0) empty_row(P, r, o);
+        }
         kept += (unsigned long long)k;
     }
     if (l == 0 && kept) atomicAdd(&P.ctr->kept_global, kept);
@@ -1404,6 +1474,13 @@ hipError_t launch_numeric_lds(const StageArgs& a, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_numeric_wide(const StageArgs& a, int grid, hipStream_t s)
+{
+    if (a.n <= 0 || grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_numeric_wide, dim3(grid), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_numeric_global(const StageArgs& a, int grid, hipStream_t s)
 {
     if (a.n <= 0 || grid <= 0) return hipSuccess;
@@ -1485,5 +1562,7 @@ hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, do
 }
 
 int numeric_global_blocks(int slots) { return slots / kWavesPerBlock; }
+
+int numeric_wide_blocks(int64_t n) { return (int)std::min<int64_t>(numeric_blocks(n), 1536); }
 
 }  // namespace fps

@@ -1,0 +1,98 @@
+"""The three row kernels of a numeric stage on the GPU: rows of up to 320
+structural entries (window up to 6144 columns) in the narrow shared-memory
+tier, up to 448 entries (8192 columns) in the wide tier, larger rows in device
+memory.  Every tier must give the oracle's result bit for bit, also when a
+plan sized for small rows meets larger ones."""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from fps_inputs import generators as G
+
+from gpu_helpers import assert_same_csr, check_canonical, download, gpu_filtered_ps, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _progress(request):
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "gpu_test_progress.log"), "a") as f:
+        f.write(f"START {request.node.nodeid}\n")
+        f.flush()
+        os.fsync(f.fileno())
+    yield
+
+
+def _band(n=1200, w=40, seed=12):
+    # half bandwidth 40: the powers P_2..P_6 have up to 161, 241, 321, 401 and
+    # 481 entries per row (band widths 2jw + 1)
+    return G.random_banded(n, w, 0.6, 1.0, seed=seed)
+
+
+def test_rows_in_all_three_tiers():
+    Z = _band()
+    c, m, s, tau = G.exp_coeffs(12), 12, 6, 1e-14
+    want, _ = O.filtered_ps(Z, c, m, s, tau)
+    got, gst = gpu_filtered_ps(Z, c, m, s, tau)
+    check_canonical(got)
+    assert_same_csr(got, want, "three tiers")
+    assert gst["rows_wide"] > 0 and gst["rows_global"] > 0
+
+
+def test_wide_tier_only_window():
+    # rows with few entries spread over a window wider than 6144 columns (but
+    # within 8192): two entries per row of Z, 3500 columns apart, so rows of
+    # P_2 span 7001 columns (rows near the end wrap around and span more)
+    n = 20000
+    rows = np.repeat(np.arange(n), 2)
+    cols = np.stack([np.arange(n), (np.arange(n) + 3500) % n], axis=1).ravel()
+    vals = np.random.default_rng(3).uniform(0.5, 1.0, rows.size)
+    import scipy.sparse as sp
+
+    Z = G._from_scipy(sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr())
+    c, m, s, tau = G.exp_coeffs(2), 2, 2, 0.0
+    want, _ = O.filtered_ps(Z, c, m, s, tau)
+    got, gst = gpu_filtered_ps(Z, c, m, s, tau)
+    assert_same_csr(got, want, "wide windows")
+    assert gst["rows_wide"] > 0
+
+
+def test_changed_operand_outgrows_the_sized_tiers():
+    # a plan sized for contiguous short rows, then the same row pointers with
+    # the columns spread over the band: rows now need the wide tier and
+    # device memory, which the evaluation detects and repeats with sizing
+    from paper_2208_05683_amd import api
+    import torch
+
+    Z2 = _band(w=38, seed=13)
+    n = Z2.n
+    cnt = np.diff(Z2.row_ptr)
+    start = np.clip(np.arange(n) - cnt // 2, 0, n - cnt)
+    col1 = np.concatenate([np.arange(a, a + k) for a, k in zip(start, cnt)]).astype(np.int32)
+    Z1 = G.CSR(n, Z2.row_ptr.copy(), col1, Z2.val.copy())
+    # m = 6, s = 3: P_2, P_3, S_1 = Bhat_1 + c_6 P_3 and S_2 = D(Bhat_0 + P_3 S_1),
+    # whose rows reach 304 entries for Z1 and 457 for Z2
+    c, m, s, tau = G.exp_coeffs(6), 6, 3, 1e-14
+    want1, _ = O.filtered_ps(Z1, c, m, s, tau)
+    want2, _ = O.filtered_ps(Z2, c, m, s, tau)
+    Zd = upload(Z1)
+    plan = api.Plan(Zd, c, m, s, tau)
+    try:
+        plan.eval()
+        assert_same_csr(download(plan.result()), want1, "sized on short rows")
+        st1 = plan.stats()
+        assert st1["rows_wide"] == 0 and st1["rows_global"] == 0
+        Zd[1].copy_(torch.from_numpy(Z2.col).to(Zd[1].device))
+        Zd[2].copy_(torch.from_numpy(Z2.val).to(Zd[2].device))
+        plan.eval()
+        assert_same_csr(download(plan.result()), want2, "after the change")
+        st2 = plan.stats()
+        assert st2["resizes"] >= 1 and st2["rows_wide"] > 0 and st2["rows_global"] > 0
+        plan.eval()
+        assert_same_csr(download(plan.result()), want2, "planned tiers")
+    finally:
+        plan.close()
