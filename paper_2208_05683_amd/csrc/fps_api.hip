@@ -258,6 +258,7 @@ struct Engine {
     DevBuf alg1st;  // per stage: two Algorithm 1 iteration states and the final record
     uint64_t flags = 0;
     std::vector<int64_t> learned;  // per stage index: output capacity learned by a sizing run
+    std::vector<int64_t> learned_ns;  // per stage index: largest structural row seen by a sizing run
     std::vector<bool> learned_wide;    // per stage: some row needs the wide shared-memory tier
     std::vector<bool> learned_global;  // per stage: some row needs the device-memory kernel
     std::vector<int> alg1_learned;  // per stage: Algorithm 1 iterations of the last host-driven run
@@ -276,14 +277,18 @@ struct Engine {
         std::vector<unsigned long long> h((size_t)(kPartCount * ws.part_stride));
         HIP_TRY(hipMemcpy(h.data(), part(i), sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
         for (int k = 0; k < kPartCount; ++k) {
-            const int64_t cnt = (k == kPartKept) ? nk : na;
+            const int64_t cnt = (k == kPartKept || k == kPartMaxNs) ? nk : na;
             unsigned long long t = 0;
-            for (int64_t b = 0; b < cnt; ++b) t += h[(size_t)(k * ws.part_stride + b)];
+            for (int64_t b = 0; b < cnt; ++b) {
+                const unsigned long long v = h[(size_t)(k * ws.part_stride + b)];
+                t = (k == kPartMaxNs) ? std::max(t, v) : t + v;
+            }
             out[k] = t;
         }
         StageCounters c{};
         HIP_TRY(hipMemcpy(&c, ctr(i), sizeof(c), hipMemcpyDeviceToHost));
         out[kPartKept] += c.kept_global;
+        out[kPartMaxNs] = std::max(out[kPartMaxNs], c.max_ns);
         return FPS_OK;
     }
 
@@ -291,6 +296,7 @@ struct Engine {
     {
         flags = fl;
         learned.assign((size_t)stages, -1);
+        learned_ns.assign((size_t)stages, 0);
         learned_wide.assign((size_t)stages, false);
         learned_global.assign((size_t)stages, false);
         alg1_learned.assign((size_t)stages, 0);
@@ -326,17 +332,26 @@ struct Engine {
         FPS_TRY(out.ensure_rows(n));
         a.blk_pre = ws.blk_pre.as<int64_t>();
         a.scan_shift = analyze_shift(a.mode);
+        const bool sizing = size || learned[(size_t)idx] < 0;
+        // After sizing, rows get a fixed stride (the largest structural row
+        // seen, rounded up to 16 entries) when that takes no more room than
+        // the scanned upper bounds: no scan, and the rows lie close together.
+        a.row_stride = 0;
+        if (!sizing) {
+            const int64_t stride = (learned_ns[(size_t)idx] + 15) / 16 * 16;
+            if (stride > 0 && stride <= learned[(size_t)idx] / std::max<int64_t>(n, 1)) a.row_stride = stride;
+        }
+        FPS_TRY(out.ensure_cap(a.row_stride > 0 ? a.row_stride * n : std::max<int64_t>(learned[(size_t)idx], 0)));
         a.out = out.out();  // the analysis writes the row offsets (out.off)
         HIP_TRY(launch_analyze(a, s));
         bool run_wide = true, run_global = true;
-        if (size || learned[(size_t)idx] < 0) {
+        if (sizing) {
             int64_t total = 0;
             HIP_TRY(hipMemcpyAsync(&total, out.off.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             FPS_TRY(out.ensure_cap(total));
             learned[(size_t)idx] = std::max<int64_t>(learned[(size_t)idx], total);
         } else {
-            FPS_TRY(out.ensure_cap(learned[(size_t)idx]));
             run_wide = learned_wide[(size_t)idx] && !a.force_global;
             run_global = learned_global[(size_t)idx] || a.force_global;
         }
@@ -348,13 +363,17 @@ struct Engine {
         if (rec && rec->ev1) HIP_TRY(hipEventRecord(rec->ev1, s));
         if (run_wide) HIP_TRY(launch_numeric_wide(a, numeric_wide_blocks(n), s));
         if (run_global) HIP_TRY(launch_numeric_global(a, numeric_global_blocks(ws.g_slots), s));
-        if (size) {
-            // learn which of the fallback kernels this stage needs
+        if (sizing) {
+            // learn which of the fallback kernels this stage needs and its
+            // largest structural row
             StageCounters c{};
             HIP_TRY(hipMemcpyAsync(&c, ctr(idx), sizeof(c), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             if (c.fb_count > 0) learned_wide[(size_t)idx] = true;
             if (c.fb2_count > 0) learned_global[(size_t)idx] = true;
+            unsigned long long tot[kPartCount];
+            FPS_TRY(stage_totals(idx, a.mode, tot));
+            learned_ns[(size_t)idx] = std::max<int64_t>(learned_ns[(size_t)idx], (int64_t)tot[kPartMaxNs]);
         }
         return FPS_OK;
     }

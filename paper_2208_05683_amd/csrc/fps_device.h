@@ -59,7 +59,7 @@ struct StageCounters {
     unsigned long long fb2_count;    // rows appended to the device-memory list (fb2_list)
     unsigned long long fb2_next;     // dynamic fetch from fb2_list, device-memory kernel
     unsigned long long rows_wide;    // rows computed by the wide-tier kernel
-    unsigned long long pad;
+    unsigned long long max_ns;       // largest structural row computed by the wide-tier and device-memory kernels
 };
 
 // Algorithm 1 on the device (one record per state slot; three per stage: two
@@ -82,7 +82,15 @@ struct Alg1Params {
 };
 
 // Per-stage partial sums, one entry per block, layout [kPartCount][part_stride]:
-enum PartIndex : int { kPartProducts = 0, kPartProductsSkipped = 1, kPartRowsSkipped = 2, kPartKept = 3, kPartCount = 4 };
+// kPartMaxNs holds the largest structural row of the block (a maximum, not a sum).
+enum PartIndex : int {
+    kPartProducts = 0,
+    kPartProductsSkipped = 1,
+    kPartRowsSkipped = 2,
+    kPartKept = 3,
+    kPartMaxNs = 4,
+    kPartCount = 5
+};
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 
 constexpr unsigned long long kErrColumnOutsideWindow = 1;  // span info inconsistent with data
@@ -121,6 +129,10 @@ struct StageArgs {
     int64_t* blk_pre;
     int32_t scan_shift;  // log2 of the rows per analysis block
     int32_t scan_pad;
+    // > 0: row r of the output owns [r * row_stride, (r + 1) * row_stride)
+    // instead (no scan of the analysis totals); the numeric kernel writes
+    // out.off[r]
+    int64_t row_stride;
     OutView out;
     StageCounters* ctr;
     const int32_t* dummy_col;  // 128 zeroed entries read by inactive lanes
@@ -147,6 +159,8 @@ hipError_t launch_rowinfo_csr(const int64_t* row_ptr, const int32_t* col, const 
                               int2* span, double* amax, hipStream_t s);
 hipError_t launch_validate_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n,
                                int64_t nnz, unsigned long long* err, hipStream_t s);
+// the analysis of a stage, then (unless a.row_stride > 0) the scan of its
+// block totals into row offsets
 hipError_t launch_analyze(const StageArgs& a, hipStream_t s);
 // log2 of the rows per analysis block (the numeric kernel's offset fix-up)
 int analyze_shift(int32_t mode);

@@ -861,10 +861,11 @@ __device__ __forceinline__ void empty_row(const StageArgs& P, int64_t r, int64_t
 template <bool kGlobal, int kParked>
 __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64_t o, uint8_t* bytes, uint2* bmp,
                                             double* acc, double* ebuf, WaveStage& st, int64_t max_words, int64_t cap,
-                                            int64_t* kept_out)
+                                            int64_t* kept_out, int64_t* ns_out)
 {
     const int l = lane();
     *kept_out = 0;
+    *ns_out = 0;
     const int32_t W = P.W[r];
     if (W <= 0) {
         if (l == 0) empty_row(P, r, o);
@@ -949,8 +950,10 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     const int64_t ns = running;
     wave_sync();
     if (l == 0) bmp[words] = make_uint2(0u, (uint32_t)cap);
+    *ns_out = ns;
     if (ns > cap) return false;
-    if (o + ns > P.out.cap) {
+    // room of the row in the output: its stride, or up to the capacity
+    if (ns > (P.row_stride > 0 ? P.row_stride : P.out.cap - o)) {
         flag_error(P, kErrCapacity);
         if (l == 0) empty_row(P, r, o);
         return true;
@@ -1103,33 +1106,41 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 
 {
     using Ws = LdsWave<kNarrowWords, kNarrowCap>;
     __shared__ Ws lds[kWavesPerBlock];
-    __shared__ unsigned long long kept_sh[kWavesPerBlock];
+    __shared__ unsigned long long kept_sh[kWavesPerBlock], ns_sh[kWavesPerBlock];
     const int wv = sgpr((int32_t)(threadIdx.x / kWave));  // wave-uniform: row-level values live in scalar registers
     Ws& me = lds[wv];
     const int l = lane();
     const int64_t blk = xcd_logical_block();
     const int64_t r = blk * kWavesPerBlock + wv;
-    int64_t kept = 0;
+    int64_t kept = 0, ns = 0;
     if (r < P.n) {
-        // the row's output offset: its block prefix plus its offset in the block
-        const int64_t o = P.blk_pre[r >> P.scan_shift] + P.out.off[r];
+        // the row's output offset: a fixed stride, or its block prefix plus
+        // its offset in the block
+        const int64_t o = P.row_stride > 0 ? r * P.row_stride : P.blk_pre[r >> P.scan_shift] + P.out.off[r];
         if (l == 0) P.out.off[r] = o;
         bool done = false;
         if (!P.force_global)
             done = process_row<false, Ws::kPark>(P, r, o, nullptr, me.bmp, me.acc, nullptr, me.st, kNarrowWords,
-                                                 kNarrowCap, &kept);
+                                                 kNarrowCap, &kept, &ns);
         if (!done && l == 0) {
             const bool direct = P.force_global != 0;
             defer_row(P, r, o, direct ? &P.ctr->fb2_count : &P.ctr->fb_count, direct ? P.fb2_list : P.fb_list,
                       direct ? P.global_planned : P.wide_planned);
         }
     }
-    if (l == 0) kept_sh[wv] = (unsigned long long)kept;
+    if (l == 0) {
+        kept_sh[wv] = (unsigned long long)kept;
+        ns_sh[wv] = (unsigned long long)ns;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int i = 0; i < kWavesPerBlock; ++i) t += kept_sh[i];
+        unsigned long long t = 0, mx = 0;
+        for (int i = 0; i < kWavesPerBlock; ++i) {
+            t += kept_sh[i];
+            mx = max(mx, ns_sh[i]);
+        }
         P.part[kPartKept * P.part_stride + blk] = t;
+        P.part[kPartMaxNs * P.part_stride + blk] = mx;
     }
 }
 
@@ -1145,7 +1156,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 
     Ws& me = lds[wv];
     const int l = lane();
     const unsigned long long count = __hip_atomic_load(&P.ctr->fb_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned long long kept = 0, rows = 0;
+    unsigned long long kept = 0, rows = 0, mx = 0;
     while (true) {
         unsigned long long i = 0;
         if (l == 0) i = atomicAdd(&P.ctr->fb_next, 1ull);
@@ -1153,10 +1164,11 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 
         if (i >= count) break;
         const int64_t r = sgpr64(P.fb_list[i]);
         const int64_t o = sgpr64(P.out.off[r]);
-        int64_t k = 0;
+        int64_t k = 0, ns = 0;
         if (process_row<false, Ws::kPark>(P, r, o, nullptr, me.bmp, me.acc, nullptr, me.st, kWideWords, kWideCap,
-                                          &k)) {
+                                          &k, &ns)) {
             kept += (unsigned long long)k;
+            mx = max(mx, (unsigned long long)ns);
             ++rows;
         } else if (l == 0) {
             defer_row(P, r, o, &P.ctr->fb2_count, P.fb2_list, P.global_planned);
@@ -1164,6 +1176,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 
     }
     if (l == 0 && kept) atomicAdd(&P.ctr->kept_global, kept);
     if (l == 0 && rows) atomicAdd(&P.ctr->rows_wide, rows);
+    if (l == 0 && mx) atomicMax(&P.ctr->max_ns, mx);
 }
 
 // Rows that did not fit shared memory: per-wave workspace in device memory
@@ -1181,7 +1194,7 @@ __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
     double* acc = reinterpret_cast<double*>(base + P.g_off_acc);
     double* ebuf = reinterpret_cast<double*>(base + P.g_off_ebuf);
     const unsigned long long count = __hip_atomic_load(&P.ctr->fb2_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned long long kept = 0;
+    unsigned long long kept = 0, mx = 0;
     while (true) {
         unsigned long long i = 0;
         if (l == 0) i = atomicAdd(&P.ctr->fb2_next, 1ull);
@@ -1189,14 +1202,16 @@ __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
         if (i >= count) break;
         const int64_t r = sgpr64(P.fb2_list[i]);
         const int64_t o = sgpr64(P.out.off[r]);
-        int64_t k = 0;
-        if (!process_row<true, 1>(P, r, o, bytes, bmp, acc, ebuf, st[wv], P.g_slot_words, P.g_slot_cap, &k)) {
+        int64_t k = 0, ns = 0;
+        if (!process_row<true, 1>(P, r, o, bytes, bmp, acc, ebuf, st[wv], P.g_slot_words, P.g_slot_cap, &k, &ns)) {
             flag_error(P, kErrCapacity);
             if (l == 0) empty_row(P, r, o);
         }
         kept += (unsigned long long)k;
+        mx = max(mx, (unsigned long long)ns);
     }
     if (l == 0 && kept) atomicAdd(&P.ctr->kept_global, kept);
+    if (l == 0 && mx) atomicMax(&P.ctr->max_ns, mx);
 }
 
 // ---------------------------------------------------------------------------
@@ -1453,7 +1468,7 @@ hipError_t launch_analyze(const StageArgs& a, hipStream_t s)
     else
         hipLaunchKernelGGL(k_analyze_sum, dim3((unsigned)analyze_blocks(a.mode, a.n)), dim3(kBlock), 0, s, a);
     const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || a.row_stride > 0) return e;
     return launch_block_scan(a.blk_pre, analyze_blocks(a.mode, a.n), a.out.off + a.n, s);
 }
 

@@ -96,3 +96,40 @@ def test_changed_operand_outgrows_the_sized_tiers():
         assert_same_csr(download(plan.result()), want2, "planned tiers")
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("case", ["random", "tiers", "lap3d", "lap2d_adaptive"])
+def test_repeated_evaluations_after_sizing(case):
+    # the first evaluation sizes the plan (scanned row offsets); later ones
+    # reuse the learned capacities with a fixed row stride and the learned
+    # tiers: every evaluation must give the oracle's result bit for bit
+    from paper_2208_05683_amd import api
+
+    adaptive = False
+    if case == "random":
+        Z, c, m, s, tau = G.random_sparse(300, 0.03, 7, 0.6), G.exp_coeffs(14), 14, 4, 1e-10
+    elif case == "tiers":
+        Z, c, m, s, tau = _band(), G.exp_coeffs(12), 12, 6, 1e-14
+    elif case == "lap3d":
+        cfg = G.config3(side=8)
+        Z, c, m, s, tau = cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"]
+    else:
+        Z, c, m, s, tau = G.laplacian_2d(60, 2.0), G.exp_coeffs(30), 30, 6, 1e-10
+        adaptive = True
+    if adaptive:
+        sc = O.schedule(m, s)
+        z = O.power_norm_bounds(Z, max(sc["q"], sc["q"] * (sc["b"] - 1)))
+        want, _, _ = O.filtered_ps_adaptive(Z, c, m, s, tau, 0.1, z)
+        plan = api.Plan(upload(Z), c, m, s, adaptive=True, eps=tau, e_r=0.1, znorm=list(z))
+    else:
+        want, _ = O.filtered_ps(Z, c, m, s, tau)
+        plan = api.Plan(upload(Z), c, m, s, tau)
+    try:
+        for k in range(3):
+            plan.eval()
+            got = download(plan.result())
+            check_canonical(got)
+            assert_same_csr(got, want, f"{case} evaluation {k}")
+        assert plan.stats()["resizes"] == 0
+    finally:
+        plan.close()
