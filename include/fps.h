@@ -69,7 +69,9 @@ typedef int32_t fps_status;
 /* plan flags */
 #define FPS_FLAG_NO_SKIP 0x1ull      /* disable the exact bound-based row skip */
 #define FPS_FLAG_FORCE_GLOBAL 0x2ull /* route every row through the global-memory kernel */
-#define FPS_FLAG_TIMING 0x4ull       /* record HIP events around every shared-memory numeric launch */
+#define FPS_FLAG_TIMING 0x4ull       /* record HIP events around the shared-memory numeric launches of
+                                        the first evaluation after a statistics query and every 8th
+                                        one after it */
 #define FPS_FLAG_NO_VALIDATE 0x8ull  /* skip the device-side CSR check of Z at plan time */
 #define FPS_FLAG_SYNC_SIZES 0x10ull  /* size every stage from a host read (no learned capacities) */
 
@@ -132,7 +134,9 @@ typedef struct {
                                      every kept entry written once at 12 bytes (8 value + 4 column), plus
                                      8 (n+1) bytes of row offsets per operand and output */
     double numeric_ms;            /* FPS_FLAG_TIMING: shared-memory numeric-kernel time per evaluation
-                                     (all stages), averaged over the last (up to 64) evaluations */
+                                     (all stages), averaged over the sampled evaluations since the
+                                     previous fps_get_stats call (up to 64; the latest sampled one if
+                                     none) */
     int32_t numeric_launches;     /* FPS_FLAG_TIMING: shared-memory numeric launches per evaluation */
     int32_t kind[FPS_MAX_STAGES];
     int32_t index[FPS_MAX_STAGES];

@@ -182,7 +182,8 @@ struct Workspace {
 
 enum class Kind { Power = FPS_STAGE_POWER, Block = FPS_STAGE_BLOCK, GStep = FPS_STAGE_GSTEP, Horner = FPS_STAGE_HORNER };
 
-constexpr int kTimingRing = 64;  // evaluations whose kernel times are kept
+constexpr int kTimingRing = 64;   // sampled evaluations whose kernel times are kept
+constexpr int kTimingEvery = 8;   // every 8th evaluation records events (each record costs a few microseconds)
 
 struct StageRecord {
     int kind = 0, index = 0;
@@ -259,8 +260,8 @@ struct Engine {
     uint64_t flags = 0;
     std::vector<int64_t> learned;  // per stage index: output capacity learned by a sizing run
     std::vector<int64_t> learned_ns;  // per stage index: largest structural row seen by a sizing run
-    std::vector<bool> learned_wide;    // per stage: some row needs the wide shared-memory tier
-    std::vector<bool> learned_global;  // per stage: some row needs the device-memory kernel
+    std::vector<int64_t> learned_wide;    // per stage: rows a sizing run sent to the wide shared-memory tier
+    std::vector<int64_t> learned_global;  // per stage: rows a sizing run sent to the device-memory kernel
     std::vector<int> alg1_learned;  // per stage: Algorithm 1 iterations of the last host-driven run
 
     StageCounters* ctr(int i) const { return ws.counters.as<StageCounters>() + i; }
@@ -297,8 +298,8 @@ struct Engine {
         flags = fl;
         learned.assign((size_t)stages, -1);
         learned_ns.assign((size_t)stages, 0);
-        learned_wide.assign((size_t)stages, false);
-        learned_global.assign((size_t)stages, false);
+        learned_wide.assign((size_t)stages, 0);
+        learned_global.assign((size_t)stages, 0);
         alg1_learned.assign((size_t)stages, 0);
         FPS_TRY(alg1st.ensure(sizeof(Alg1State) * 3 * (size_t)std::max(stages, 1)));
         return ws.init(n, stages);
@@ -344,6 +345,11 @@ struct Engine {
         FPS_TRY(out.ensure_cap(a.row_stride > 0 ? a.row_stride * n : std::max<int64_t>(learned[(size_t)idx], 0)));
         a.out = out.out();  // the analysis writes the row offsets (out.off)
         HIP_TRY(launch_analyze(a, s));
+        // fallback kernels: a sizing run launches each one when rows reached
+        // its list (read back after the kernel before it); later runs launch
+        // those that a sizing run needed, with grids for the rows seen then
+        // (their blocks fetch rows until the list is exhausted, so any grid
+        // is correct; every wavefront of the grid takes one fetch ticket)
         bool run_wide = true, run_global = true;
         if (sizing) {
             int64_t total = 0;
@@ -352,25 +358,41 @@ struct Engine {
             FPS_TRY(out.ensure_cap(total));
             learned[(size_t)idx] = std::max<int64_t>(learned[(size_t)idx], total);
         } else {
-            run_wide = learned_wide[(size_t)idx] && !a.force_global;
-            run_global = learned_global[(size_t)idx] || a.force_global;
+            run_wide = learned_wide[(size_t)idx] > 0 && !a.force_global;
+            run_global = learned_global[(size_t)idx] > 0 || a.force_global;
         }
         a.out = out.out();
         a.wide_planned = run_wide ? 1 : 0;
         a.global_planned = run_global ? 1 : 0;
+        const int64_t per_block = numeric_waves_per_block();
+        auto grid_for_rows = [&](int64_t rows, int64_t cap) {
+            return (int)std::max<int64_t>(1, std::min<int64_t>((rows + per_block - 1) / per_block, cap));
+        };
         if (rec && rec->ev0) HIP_TRY(hipEventRecord(rec->ev0, s));
         HIP_TRY(launch_numeric_lds(a, 0, s));
         if (rec && rec->ev1) HIP_TRY(hipEventRecord(rec->ev1, s));
-        if (run_wide) HIP_TRY(launch_numeric_wide(a, numeric_wide_blocks(n), s));
-        if (run_global) HIP_TRY(launch_numeric_global(a, numeric_global_blocks(ws.g_slots), s));
+        StageCounters c{};
         if (sizing) {
-            // learn which of the fallback kernels this stage needs and its
-            // largest structural row
-            StageCounters c{};
             HIP_TRY(hipMemcpyAsync(&c, ctr(idx), sizeof(c), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            if (c.fb_count > 0) learned_wide[(size_t)idx] = true;
-            if (c.fb2_count > 0) learned_global[(size_t)idx] = true;
+            learned_wide[(size_t)idx] = std::max<int64_t>(learned_wide[(size_t)idx], (int64_t)c.fb_count);
+            run_wide = c.fb_count > 0;
+        }
+        if (run_wide)
+            HIP_TRY(launch_numeric_wide(a, grid_for_rows(learned_wide[(size_t)idx], numeric_wide_blocks(n)), s));
+        if (sizing) {
+            HIP_TRY(hipMemcpyAsync(&c, ctr(idx), sizeof(c), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            learned_global[(size_t)idx] = std::max<int64_t>(learned_global[(size_t)idx], (int64_t)c.fb2_count);
+            run_global = c.fb2_count > 0;
+        }
+        if (run_global)
+            HIP_TRY(launch_numeric_global(
+                a, grid_for_rows(std::max<int64_t>(learned_global[(size_t)idx], a.force_global ? n : 0),
+                                 numeric_global_blocks(ws.g_slots)),
+                s));
+        if (sizing) {
+            // the stage's largest structural row
             unsigned long long tot[kPartCount];
             FPS_TRY(stage_totals(idx, a.mode, tot));
             learned_ns[(size_t)idx] = std::max<int64_t>(learned_ns[(size_t)idx], (int64_t)tot[kPartMaxNs]);
@@ -679,6 +701,10 @@ struct fps_plan_s {
     int n_stages = 0;
     hipStream_t last_stream = nullptr;
     int64_t evals = 0;
+    // FPS_FLAG_TIMING: evaluations sampled so far, and the sample and
+    // evaluation counts at the last statistics query
+    int64_t timed = 0, timed_seen = 0, evals_seen = 0;
+    bool timing_now = false;  // the evaluation being enqueued records events
     int64_t resizes = 0;
     bool evaluated = false;
     bool sized_once = false;
@@ -743,7 +769,7 @@ struct fps_plan_s {
         const double skip_tau = (flags & FPS_FLAG_NO_SKIP) || tau <= 0.0 ? 0.0 : tau * (1.0 - 1e-6);
 
         const int nst = stage_count();
-        const size_t slot = (size_t)(evals % kTimingRing);
+        const size_t slot = (size_t)(timed % kTimingRing);
         auto begin_stage = [&](Kind k, int index) -> StageRecord* {
             StageRecord* r = &rec[(size_t)n_stages];
             r->kind = (int)k;
@@ -754,7 +780,8 @@ struct fps_plan_s {
             r->eps_g = r->threshold = r->dropped = 0.0;
             r->alg1_iters = 0;
             r->alg1_device = false;
-            if (!ring.empty()) {
+            r->ev0 = r->ev1 = nullptr;
+            if (timing_now) {
                 r->ev0 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2];
                 r->ev1 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2 + 1];
             }
@@ -964,9 +991,12 @@ fps_status fps_eval(fps_plan p, fps_stream stream)
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const bool size = (p->flags & FPS_FLAG_SYNC_SIZES) || !p->sized_once;
     p->last_stream = s;
+    // sampled: the first evaluation after a statistics query, then every 8th
+    p->timing_now = !p->ring.empty() && ((p->evals - p->evals_seen) % kTimingEvery == 0);
     fps_status st = p->run_eval(s, size);
     if (st != FPS_OK) return st;
     if (size) p->sized_once = true;
+    if (p->timing_now) p->timed++;
     p->evals++;
     p->evaluated = true;
     return FPS_OK;
@@ -996,6 +1026,7 @@ static fps_status finish(fps_plan p)
         // re-run with sizing (and, if Algorithm 1 needed more iterations than
         // were launched on the device, with the host-driven loop)
         p->resizes++;
+        p->timing_now = false;
         FPS_TRY(p->run_eval(p->last_stream, true, (err & kErrAlg1Pending) != 0));
         HIP_TRY(hipStreamSynchronize(p->last_stream));
         FPS_TRY(read_errors(p, &err));
@@ -1100,11 +1131,13 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
             bytes += 12.0 * (in + kept(i)) + 8.0 * n1 * (double)(r.term_src.size() + 1);
         }
         if (!p->ring.empty()) {
-            // average over the evaluations still held in the event ring
-            const int64_t held = std::min<int64_t>(p->evals, kTimingRing);
+            // average over the sampled evaluations since the last query (the
+            // latest sampled one if none)
+            const int64_t fresh = p->timed - p->timed_seen;
+            const int64_t held = fresh > 0 ? std::min<int64_t>(fresh, kTimingRing) : std::min<int64_t>(p->timed, 1);
             const size_t nst = (size_t)p->stage_count();
             double sum = 0.0;
-            for (int64_t e = p->evals - held; e < p->evals; ++e) {
+            for (int64_t e = p->timed - held; e < p->timed; ++e) {
                 const size_t slot = (size_t)(e % kTimingRing);
                 float ms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&ms, p->ring[(slot * nst + (size_t)i) * 2],
@@ -1120,6 +1153,8 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
     st->bytes_algorithmic = bytes;
     st->numeric_ms = ms_total;
     st->numeric_launches = launches;
+    p->timed_seen = p->timed;
+    p->evals_seen = p->evals;
     return FPS_OK;
 }
 
