@@ -238,6 +238,7 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
         int64_t prod = 0;
         double bnd = 0.0;
         const int64_t pb = P.A.beg[r], pe = P.A.end[r];
+#pragma unroll 4
         for (int64_t p = pb + gl; p < pe; p += G) {
             const int32_t k = P.A.col[p];
             const int64_t len = P.B.end[k] - P.B.beg[k];
@@ -249,13 +250,9 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
                 bnd += fabs(P.A.val[p]) * P.B.amax[k];
             }
         }
-        lo = group_min<G>(lo);
-        hi = group_max<G>(hi);
-        prod = group_sum<G>(prod);
-        bnd = group_sum<G>(bnd);
         int64_t elen = 0;
         double emax = 0.0;
-        if (P.has_e) {
+        if (P.has_e && gl == 0) {
             elen = P.E.end[r] - P.E.beg[r];
             if (elen > 0) {
                 const int2 sp = P.E.span[r];
@@ -265,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
             }
         }
         if (P.has_blk) {  // fused coefficient block: |block entries| <= sum_t |c_t| max|M_t[r,:]|
-            for (int t = 0; t < P.T.n; ++t) {
+            for (int t = gl; t < P.T.n; t += G) {  // the group's lanes share the terms
                 if (P.T.beg[t] == nullptr) {
                     lo = min(lo, (int32_t)r);
                     hi = max(hi, (int32_t)r);
@@ -283,6 +280,12 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
                 }
             }
         }
+        lo = group_min<G>(lo);
+        hi = group_max<G>(hi);
+        prod = group_sum<G>(prod);
+        bnd = group_sum<G>(bnd);
+        elen = group_sum<G>(elen);
+        emax = group_sum<G>(emax);
         if (gl == 0) {
             const bool empty = (prod == 0 && elen == 0);
             const bool skip = !empty && P.skip_tau > 0.0 && (emax + bnd) < P.skip_tau;
