@@ -195,6 +195,7 @@ struct StageRecord {
     double eps_g = 0.0, threshold = 0.0, dropped = 0.0;
     int alg1_iters = 0;
     bool alg1_device = false;  // the record is in the device state (Engine::alg1_state)
+    bool wide_rows = false;    // every row of the stage ran in the wide shared-memory tier
 };
 
 struct Schedule {
@@ -361,6 +362,12 @@ struct Engine {
             run_wide = learned_wide[(size_t)idx] > 0 && !a.force_global;
             run_global = learned_global[(size_t)idx] > 0 || a.force_global;
         }
+        // a stage whose sizing run sent more than an eighth of its rows past the
+        // narrow tier runs every row in the wide tier (instead of building
+        // those rows' structure twice)
+        const bool wide_rows = !sizing && !a.force_global && learned_wide[(size_t)idx] * 8 > n;
+        if (wide_rows) run_wide = false;
+        if (rec) rec->wide_rows = wide_rows;
         a.out = out.out();
         a.wide_planned = run_wide ? 1 : 0;
         a.global_planned = run_global ? 1 : 0;
@@ -369,7 +376,10 @@ struct Engine {
             return (int)std::max<int64_t>(1, std::min<int64_t>((rows + per_block - 1) / per_block, cap));
         };
         if (rec && rec->ev0) HIP_TRY(hipEventRecord(rec->ev0, s));
-        HIP_TRY(launch_numeric_lds(a, 0, s));
+        if (wide_rows)
+            HIP_TRY(launch_numeric_wide_rows(a, s));
+        else
+            HIP_TRY(launch_numeric_lds(a, 0, s));
         if (rec && rec->ev1) HIP_TRY(hipEventRecord(rec->ev1, s));
         StageCounters c{};
         if (sizing) {
@@ -780,6 +790,7 @@ struct fps_plan_s {
             r->eps_g = r->threshold = r->dropped = 0.0;
             r->alg1_iters = 0;
             r->alg1_device = false;
+            r->wide_rows = false;
             r->ev0 = r->ev1 = nullptr;
             if (timing_now) {
                 r->ev0 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2];
@@ -1114,7 +1125,7 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
         st->products_skipped += (int64_t)tot[(size_t)i][kPartProductsSkipped];
         st->rows_skipped += (int64_t)tot[(size_t)i][kPartRowsSkipped];
         st->rows_global += (int64_t)c[(size_t)i].fb2_count;
-        st->rows_wide += (int64_t)c[(size_t)i].rows_wide;
+        st->rows_wide += r.wide_rows ? p->Z.n - (int64_t)c[(size_t)i].fb2_count : (int64_t)c[(size_t)i].rows_wide;
         const double za = (double)p->Z.nnz;
         if (r.kind == FPS_STAGE_POWER || r.kind == FPS_STAGE_HORNER) {
             const double na = r.a_is_z ? za : (r.a_src >= 0 ? kept(r.a_src) : 0.0);

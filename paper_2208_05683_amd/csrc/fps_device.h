@@ -165,6 +165,9 @@ hipError_t launch_analyze(const StageArgs& a, hipStream_t s);
 // log2 of the rows per analysis block (the numeric kernel's offset fix-up)
 int analyze_shift(int32_t mode);
 hipError_t launch_numeric_lds(const StageArgs& a, int grid, hipStream_t s);
+// every row of the stage in the wide shared-memory tier (instead of
+// launch_numeric_lds, for stages whose rows mostly exceed the narrow tier)
+hipError_t launch_numeric_wide_rows(const StageArgs& a, hipStream_t s);
 // rows of fb_list (persistent blocks: the grid size only sets the parallelism)
 hipError_t launch_numeric_wide(const StageArgs& a, int grid, hipStream_t s);
 // rows of fb2_list

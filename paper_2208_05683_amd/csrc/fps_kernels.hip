@@ -1100,14 +1100,15 @@ __device__ __forceinline__ void defer_row(const StageArgs& P, int64_t r, int64_t
     }
 }
 
-// One row per wavefront, four rows per block, blocks in XCD-aware order.
-// Narrow shared-memory tier: the workspace (19.5 KB per block) and the
-// register budget (64 per lane) are sized for eight wavefronts per SIMD.
-// Rows that do not fit go to the wide tier's list (with FPS_FLAG_FORCE_GLOBAL
-// every row goes straight to the device-memory kernel's list).
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_numeric_lds(StageArgs P)
+// One row per wavefront, four rows per block, blocks in XCD-aware order, in
+// the shared-memory tier kWords / kCap.  Rows that do not fit go to the next
+// kernel's list: from the narrow tier the wide tier's (with
+// FPS_FLAG_FORCE_GLOBAL every row the device-memory kernel's), from the wide
+// tier the device-memory kernel's.
+template <int kWords, int kCap, bool kNarrow>
+__device__ __forceinline__ void numeric_rows(const StageArgs& P)
 {
-    using Ws = LdsWave<kNarrowWords, kNarrowCap>;
+    using Ws = LdsWave<kWords, kCap>;
     __shared__ Ws lds[kWavesPerBlock];
     __shared__ unsigned long long kept_sh[kWavesPerBlock], ns_sh[kWavesPerBlock];
     const int wv = sgpr((int32_t)(threadIdx.x / kWave));  // wave-uniform: row-level values live in scalar registers
@@ -1123,10 +1124,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 
         if (l == 0) P.out.off[r] = o;
         bool done = false;
         if (!P.force_global)
-            done = process_row<false, Ws::kPark>(P, r, o, nullptr, me.bmp, me.acc, nullptr, me.st, kNarrowWords,
-                                                 kNarrowCap, &kept, &ns);
+            done = process_row<false, Ws::kPark>(P, r, o, nullptr, me.bmp, me.acc, nullptr, me.st, kWords, kCap,
+                                                 &kept, &ns);
         if (!done && l == 0) {
-            const bool direct = P.force_global != 0;
+            const bool direct = !kNarrow || P.force_global != 0;
             defer_row(P, r, o, direct ? &P.ctr->fb2_count : &P.ctr->fb_count, direct ? P.fb2_list : P.fb_list,
                       direct ? P.global_planned : P.wide_planned);
         }
@@ -1145,6 +1146,20 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 
         P.part[kPartKept * P.part_stride + blk] = t;
         P.part[kPartMaxNs * P.part_stride + blk] = mx;
     }
+}
+
+// Narrow tier, every row of a stage: the workspace (19.5 KB per block) and
+// the register budget (64 per lane) are sized for eight wavefronts per SIMD.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) k_numeric_lds(StageArgs P)
+{
+    numeric_rows<kNarrowWords, kNarrowCap, true>(P);
+}
+
+// Wide tier, every row of a stage whose rows mostly exceed the narrow tier
+// (25.7 KB per block, six wavefronts per SIMD).
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) k_numeric_wide_rows(StageArgs P)
+{
+    numeric_rows<kWideWords, kWideCap, false>(P);
 }
 
 // Rows of the wide tier's list, fetched dynamically (few rows, usually): 25.7
@@ -1489,6 +1504,13 @@ hipError_t launch_numeric_lds(const StageArgs& a, int grid, hipStream_t s)
     (void)grid;
     if (a.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_numeric_lds, dim3((unsigned)numeric_blocks(a.n)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_numeric_wide_rows(const StageArgs& a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_numeric_wide_rows, dim3((unsigned)numeric_blocks(a.n)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
