@@ -98,13 +98,29 @@ def test_changed_operand_outgrows_the_sized_tiers():
         plan.close()
 
 
-@pytest.mark.parametrize("case", ["random", "tiers", "lap3d", "lap2d_adaptive"])
+@pytest.mark.parametrize("case", ["random", "tiers", "lap3d", "lap2d_adaptive", "lap2d_series"])
 def test_repeated_evaluations_after_sizing(case):
     # the first evaluation sizes the plan (scanned row offsets); later ones
     # reuse the learned capacities with a fixed row stride and the learned
     # tiers: every evaluation must give the oracle's result bit for bit
     from paper_2208_05683_amd import api
 
+    if case == "lap2d_series":
+        # the last Horner steps average 281 and 378 structural entries per
+        # row: after sizing they run every row in the wide tier
+        Z = G.laplacian_2d(100, 2.0)
+        a = G.exp_coeffs(59)
+        want, info, _, _ = O.series(Z, a, 1e-12, 0.1)
+        plan = api.Plan.series(upload(Z), a, 1e-12, 0.1)
+        try:
+            for k in range(3):
+                plan.eval()
+                assert_same_csr(download(plan.result()), want, f"series evaluation {k}")
+            st = plan.stats()
+            assert st["resizes"] == 0 and st["rows_wide"] > 0
+        finally:
+            plan.close()
+        return
     adaptive = False
     if case == "random":
         Z, c, m, s, tau = G.random_sparse(300, 0.03, 7, 0.6), G.exp_coeffs(14), 14, 4, 1e-10
