@@ -39,6 +39,10 @@ namespace {
 // device-memory kernel.
 constexpr int kNarrowWords = 192, kNarrowCap = 320;
 constexpr int kWideWords = 256, kWideCap = 448;
+// Rows beyond the wide tier: in the device-memory kernel, with structure and
+// accumulator still in shared memory up to 8192 columns and 2048 entries
+// (77 KB per block, two blocks per CU), the parked values in device memory.
+constexpr int kDevWords = 256, kDevCap = 2048;
 constexpr int kWavesPerBlock = 4;
 constexpr int kBlock = kWave * kWavesPerBlock;
 
@@ -861,7 +865,10 @@ __device__ __forceinline__ void empty_row(const StageArgs& P, int64_t r, int64_t
 // test and a sorted, coalesced write-out.  Rows whose main terms are at most
 // 64 short-row products keep them in registers from the structure pass to
 // the accumulation.
-template <bool kGlobal, int kParked>
+// kGlobal: the structure in a device-memory byte map, bitmap and accumulator
+// in device memory.  kDevPark: the main part parked in `ebuf` (device memory)
+// rather than in kParked registers per lane.
+template <bool kGlobal, bool kDevPark, int kParked>
 __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64_t o, uint8_t* bytes, uint2* bmp,
                                             double* acc, double* ebuf, WaveStage& st, int64_t max_words, int64_t cap,
                                             int64_t* kept_out, int64_t* ns_out)
@@ -996,7 +1003,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
 #pragma unroll
     for (int t = 0; t < kParked; ++t) preg[t] = 0.0;
     if (has_extra) {
-        if (kGlobal) {
+        if (kDevPark) {
             for (int64_t i = l; i < ns; i += kWave) {
                 ebuf[i] = acc[i];
                 acc[i] = 0.0;
@@ -1052,6 +1059,18 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
                 c = cols[i];
             }
             emit(i, x, c);
+        }
+    } else if (kDevPark) {
+        // the values move to `ebuf` (x = extra + parked main part), which
+        // frees the accumulator for the column list
+        for (int64_t i = l; i < ns; i += kWave) ebuf[i] = has_extra ? acc[i] + ebuf[i] : acc[i];
+        wave_sync();
+        int32_t* cols = reinterpret_cast<int32_t*>(acc);
+        list_cols(cols);
+        wave_sync();
+        for (int64_t i0 = 0; i0 < ns; i0 += kWave) {
+            const int64_t i = i0 + l;
+            emit(i, i < ns ? ebuf[i] : 0.0, i < ns ? cols[i] : 0);
         }
     } else {
         // the values move to registers (x = extra + parked main part), which
@@ -1124,7 +1143,7 @@ __device__ __forceinline__ void numeric_rows(const StageArgs& P)
         if (l == 0) P.out.off[r] = o;
         bool done = false;
         if (!P.force_global)
-            done = process_row<false, Ws::kPark>(P, r, o, nullptr, me.bmp, me.acc, nullptr, me.st, kWords, kCap,
+            done = process_row<false, false, Ws::kPark>(P, r, o, nullptr, me.bmp, me.acc, nullptr, me.st, kWords, kCap,
                                                  &kept, &ns);
         if (!done && l == 0) {
             const bool direct = !kNarrow || P.force_global != 0;
@@ -1183,7 +1202,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 
         const int64_t r = sgpr64(P.fb_list[i]);
         const int64_t o = sgpr64(P.out.off[r]);
         int64_t k = 0, ns = 0;
-        if (process_row<false, Ws::kPark>(P, r, o, nullptr, me.bmp, me.acc, nullptr, me.st, kWideWords, kWideCap,
+        if (process_row<false, false, Ws::kPark>(P, r, o, nullptr, me.bmp, me.acc, nullptr, me.st, kWideWords, kWideCap,
                                           &k, &ns)) {
             kept += (unsigned long long)k;
             mx = max(mx, (unsigned long long)ns);
@@ -1201,8 +1220,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 
 // sized for a full row, rows fetched dynamically from the device-memory list.
 __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
 {
-    __shared__ WaveStage st[kWavesPerBlock];
+    using Ws = LdsWave<kDevWords, kDevCap>;
+    __shared__ Ws lds[kWavesPerBlock];
     const int wv = sgpr((int32_t)(threadIdx.x / kWave));
+    Ws& me = lds[wv];
     const int l = lane();
     const int64_t slot = (int64_t)blockIdx.x * kWavesPerBlock + wv;
     if (slot >= P.g_slots) return;
@@ -1221,7 +1242,12 @@ __global__ void __launch_bounds__(kBlock) k_numeric_global(StageArgs P)
         const int64_t r = sgpr64(P.fb2_list[i]);
         const int64_t o = sgpr64(P.out.off[r]);
         int64_t k = 0, ns = 0;
-        if (!process_row<true, 1>(P, r, o, bytes, bmp, acc, ebuf, st[wv], P.g_slot_words, P.g_slot_cap, &k, &ns)) {
+        // rows of up to 2048 entries in a window of up to 8192 columns keep
+        // their structure and accumulator in shared memory
+        if (!process_row<false, true, 1>(P, r, o, nullptr, me.bmp, me.acc, ebuf, me.st, kDevWords, kDevCap, &k,
+                                         &ns) &&
+            !process_row<true, true, 1>(P, r, o, bytes, bmp, acc, ebuf, me.st, P.g_slot_words, P.g_slot_cap, &k,
+                                        &ns)) {
             flag_error(P, kErrCapacity);
             if (l == 0) empty_row(P, r, o);
         }
