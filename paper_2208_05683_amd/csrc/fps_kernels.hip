@@ -350,6 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_analyze_sum(StageArgs P)
     if (r < P.n) {
         int32_t lo = INT_MAX, hi = -1;
         int64_t prod = 0;
+#pragma unroll 4
         for (int t = 0; t < P.T.n; ++t) {
             if (P.T.beg[t] == nullptr) {
                 lo = min(lo, (int32_t)r);
@@ -480,15 +481,19 @@ __device__ __forceinline__ Chunk load_chunk(const StageArgs& P, int src, int64_t
             c.beg = P.B.beg[k];
             c.len = (int32_t)(P.B.end[k] - c.beg);
         } else {
+            // both row pointers of the term are read at once, then both
+            // offsets of row r (the identity term reads zeros from the dummy
+            // entries): two round trips instead of three
             const int ti = (int)t;
             c.a = P.T.coef[ti];
-            if (P.T.beg[ti] == nullptr) {
-                c.beg = -1;
-                c.len = 1;
-            } else {
-                c.beg = P.T.beg[ti][r];
-                c.len = (int32_t)(P.T.end[ti][r] - c.beg);
-            }
+            const int64_t* bp = P.T.beg[ti];
+            const int64_t* ep = P.T.end[ti];
+            const bool ident = bp == nullptr;
+            const int64_t* zero = reinterpret_cast<const int64_t*>(P.dummy_val);
+            const int64_t b = *(ident ? zero : bp + r);
+            const int64_t e = *(ident ? zero : ep + r);
+            c.beg = ident ? -1 : b;
+            c.len = ident ? 1 : (int32_t)(e - b);
         }
     }
     c.incl = wave_incl_sum(c.len);
