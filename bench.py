@@ -204,11 +204,11 @@ def main():
                     help="run one device-to-device copy of this many MiB first (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(how the evaluation would shard is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the throughput reported is that of a single GPU)", file=sys.stderr)
         sys.exit(2)
-    if args.steps > 64:
-        log("note: kernel timings average the last 64 evaluations")
+    if args.steps > 8 * 64:
+        log("note: kernel timings average the last 64 sampled evaluations (every 8th one)")
 
     import torch
     from paper_2208_05683_amd import api, binding as B

@@ -56,7 +56,7 @@ typedef int32_t fps_status;
 #define FPS_ERR_BAD_CSR 2       /* input matrix fails validation */
 #define FPS_ERR_OUT_OF_MEMORY 3 /* device allocation failed */
 #define FPS_ERR_HIP 4           /* a HIP runtime call or kernel failed */
-#define FPS_ERR_CAPACITY 5      /* a size limit of this build was exceeded */
+#define FPS_ERR_CAPACITY 5      /* a size limit of the library was exceeded */
 #define FPS_ERR_NOT_READY 6     /* result requested before any evaluation */
 
 /* largest PS block size s accepted (the g = 1 sum has s+1 terms) */

@@ -2,8 +2,6 @@
 the GPU with the CPU oracle: results, per-stage thresholds and Algorithm 1
 iteration counts must agree bit for bit."""
 
-import os
-
 import numpy as np
 import pytest
 
@@ -13,16 +11,6 @@ from fps_inputs import generators as G
 from gpu_helpers import assert_same_csr, check_canonical, download, upload
 
 pytestmark = pytest.mark.gpu
-
-
-@pytest.fixture(autouse=True)
-def _progress(request):
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "gpu_test_progress.log"), "a") as f:
-        f.write(f"START {request.node.nodeid}\n")
-        f.flush()
-        os.fsync(f.fileno())
-    yield
 
 
 def znorms(Z, m, s):

@@ -6,8 +6,6 @@ element, and P_4 = D(Z P_3) on 1000 sampled rows, which the oracle computes
 from its own P_3 (rows of P_4 hold about 5,400 entries: the device-memory
 kernel at full scale)."""
 
-import os
-
 import numpy as np
 import pytest
 
@@ -17,16 +15,6 @@ from fps_inputs import generators as G
 from gpu_helpers import assert_same_csr, check_canonical, download
 
 pytestmark = pytest.mark.gpu
-
-
-@pytest.fixture(autouse=True)
-def _progress(request):
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "gpu_test_progress.log"), "a") as f:
-        f.write(f"START {request.node.nodeid}\n")
-        f.flush()
-        os.fsync(f.fileno())
-    yield
 
 
 def _rows_only(M, rows):

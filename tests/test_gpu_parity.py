@@ -6,8 +6,6 @@ pointers, columns and values); the relative Frobenius difference, which must
 be <= 1e-10 in any case, is then exactly 0.
 """
 
-import os
-
 import numpy as np
 import pytest
 
@@ -20,17 +18,6 @@ from gpu_helpers import (assert_same_csr, check_canonical, download, gpu_filtere
 pytestmark = pytest.mark.gpu
 
 REL_TOL = 1e-10
-
-
-@pytest.fixture(autouse=True)
-def _progress(request):
-    """Record each case before it touches the GPU (for post-mortem of a crash)."""
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "gpu_test_progress.log"), "a") as f:
-        f.write(f"START {request.node.nodeid}\n")
-        f.flush()
-        os.fsync(f.fileno())
-    yield
 
 
 def compare_eval(Z, c, m, s, tau, flags=0, what=""):

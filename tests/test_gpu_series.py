@@ -3,8 +3,6 @@
 (eq. 34), q, the tail and budget of eq. 36, and the evaluated F must agree
 bit for bit."""
 
-import os
-
 import numpy as np
 import pytest
 
@@ -14,16 +12,6 @@ from fps_inputs import generators as G
 from gpu_helpers import assert_same_csr, check_canonical, download, upload
 
 pytestmark = pytest.mark.gpu
-
-
-@pytest.fixture(autouse=True)
-def _progress(request):
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "gpu_test_progress.log"), "a") as f:
-        f.write(f"START {request.node.nodeid}\n")
-        f.flush()
-        os.fsync(f.fileno())
-    yield
 
 
 def _nonneg(n, seed):

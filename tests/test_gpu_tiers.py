@@ -4,8 +4,6 @@ tier, up to 448 entries (8192 columns) in the wide tier, larger rows in device
 memory.  Every tier must give the oracle's result bit for bit, also when a
 plan sized for small rows meets larger ones."""
 
-import os
-
 import numpy as np
 import pytest
 
@@ -15,16 +13,6 @@ from fps_inputs import generators as G
 from gpu_helpers import assert_same_csr, check_canonical, download, gpu_filtered_ps, upload
 
 pytestmark = pytest.mark.gpu
-
-
-@pytest.fixture(autouse=True)
-def _progress(request):
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open(os.path.join("gpurun_out", "gpu_test_progress.log"), "a") as f:
-        f.write(f"START {request.node.nodeid}\n")
-        f.flush()
-        os.fsync(f.fileno())
-    yield
 
 
 def _band(n=1200, w=40, seed=12):
