@@ -315,6 +315,8 @@ def main():
         "products_per_s": prod_per_s,
         "products_per_step": products,
         "products_skipped_per_step": st["products_skipped"],
+        "rows_wide_per_step": st["rows_wide"],
+        "rows_global_per_step": st["rows_global"],
         "stage_ms": {f"{['power', 'block', 'gstep', 'horner'][k]}{i}": round(ms, 4)
                      for k, i, ms in zip(st["kind"], st["index"], st["stage_ms"])},
     }

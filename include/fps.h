@@ -125,8 +125,8 @@ typedef struct {
     int64_t products;             /* multiply-adds performed in the last evaluation */
     int64_t products_skipped;     /* multiply-adds avoided by the exact bound test */
     int64_t rows_skipped;         /* output rows proven empty by the bound test */
-    int64_t rows_global;          /* rows handled by the device-memory kernel (more than 448 structural
-                                     entries or a window wider than 8192 columns) */
+    int64_t rows_global;          /* rows handled by the device-memory kernel (more than 512 structural
+                                     entries or a window wider than 6912 columns) */
     int64_t rows_wide;            /* rows handled by the wide shared-memory kernel (more than 320
                                      entries or a window wider than 6144 columns) */
     int64_t resizes;              /* evaluations that had to re-size a buffer */

@@ -35,10 +35,10 @@ namespace {
 // Shared-memory tiers of the numeric kernel.  Narrow: windows of up to 6144
 // columns and 320 structural entries, 19.5 KB per four-wavefront block and at
 // most 64 VGPRs, so eight wavefronts per SIMD.  Wide (rows that do not fit
-// the narrow tier): 8192 columns and 448 entries.  Larger rows take the
-// device-memory kernel.
+// the narrow tier): 6912 columns and 512 entries, 26.5 KB per block, six
+// blocks per CU.  Larger rows take the device-memory kernel.
 constexpr int kNarrowWords = 192, kNarrowCap = 320;
-constexpr int kWideWords = 256, kWideCap = 448;
+constexpr int kWideWords = 216, kWideCap = 512;
 // Rows beyond the wide tier: in the device-memory kernel, with structure and
 // accumulator still in shared memory up to 8192 columns and 2048 entries
 // (77 KB per block, two blocks per CU), the parked values in device memory.
@@ -1180,13 +1180,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 
 }
 
 // Wide tier, every row of a stage whose rows mostly exceed the narrow tier
-// (25.7 KB per block, six wavefronts per SIMD).
+// (26.5 KB per block, six wavefronts per SIMD).
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) k_numeric_wide_rows(StageArgs P)
 {
     numeric_rows<kWideWords, kWideCap, false>(P);
 }
 
-// Rows of the wide tier's list, fetched dynamically (few rows, usually): 25.7
+// Rows of the wide tier's list, fetched dynamically (few rows, usually): 26.5
 // KB of shared memory per block; the register budget of four wavefronts per
 // SIMD keeps the persistent loop free of spills.  Rows that do not fit
 // either go to the device-memory kernel's list.

@@ -1,6 +1,6 @@
 """The three row kernels of a numeric stage on the GPU: rows of up to 320
 structural entries (window up to 6144 columns) in the narrow shared-memory
-tier, up to 448 entries (8192 columns) in the wide tier, larger rows in device
+tier, up to 512 entries (6912 columns) in the wide tier, larger rows in device
 memory.  Every tier must give the oracle's result bit for bit, also when a
 plan sized for small rows meets larger ones."""
 
@@ -15,9 +15,9 @@ from gpu_helpers import assert_same_csr, check_canonical, download, gpu_filtered
 pytestmark = pytest.mark.gpu
 
 
-def _band(n=1200, w=40, seed=12):
-    # half bandwidth 40: the powers P_2..P_6 have up to 161, 241, 321, 401 and
-    # 481 entries per row (band widths 2jw + 1)
+def _band(n=1200, w=44, seed=12):
+    # half bandwidth 44: the powers P_2..P_6 have up to 177, 265, 353, 441 and
+    # 529 entries per row (band widths 2jw + 1)
     return G.random_banded(n, w, 0.6, 1.0, seed=seed)
 
 
@@ -33,11 +33,11 @@ def test_rows_in_all_three_tiers():
 
 def test_wide_tier_only_window():
     # rows with few entries spread over a window wider than 6144 columns (but
-    # within 8192): two entries per row of Z, 3500 columns apart, so rows of
-    # P_2 span 7001 columns (rows near the end wrap around and span more)
+    # within 6912): two entries per row of Z, 3200 columns apart, so rows of
+    # P_2 span 6401 columns (rows near the end wrap around and span more)
     n = 20000
     rows = np.repeat(np.arange(n), 2)
-    cols = np.stack([np.arange(n), (np.arange(n) + 3500) % n], axis=1).ravel()
+    cols = np.stack([np.arange(n), (np.arange(n) + 3200) % n], axis=1).ravel()
     vals = np.random.default_rng(3).uniform(0.5, 1.0, rows.size)
     import scipy.sparse as sp
 
@@ -51,8 +51,8 @@ def test_wide_tier_only_window():
 
 def test_changed_operand_outgrows_the_sized_tiers():
     # a plan sized for contiguous short rows, then the same row pointers with
-    # the columns spread over the band: rows now need the wide tier and
-    # device memory, which the evaluation detects and repeats with sizing
+    # the columns spread over the band: rows now need the wide tier, which the
+    # evaluation detects and repeats with sizing
     from paper_2208_05683_amd import api
     import torch
 
@@ -79,7 +79,7 @@ def test_changed_operand_outgrows_the_sized_tiers():
         plan.eval()
         assert_same_csr(download(plan.result()), want2, "after the change")
         st2 = plan.stats()
-        assert st2["resizes"] >= 1 and st2["rows_wide"] > 0 and st2["rows_global"] > 0
+        assert st2["resizes"] >= 1 and st2["rows_wide"] > 0
         plan.eval()
         assert_same_csr(download(plan.result()), want2, "planned tiers")
     finally:
