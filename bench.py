@@ -240,6 +240,8 @@ def main():
         log(f"copied {args.copy_mib} MiB device to device")
         del src, dst
     series_info = None
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
     if args.filter == "adaptive":
         # norm bounds of eq. 37 computed by the library on the device
         plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], adaptive=True, eps=args.eps, e_r=args.e_r,
@@ -255,6 +257,8 @@ def main():
         log(f"series mode: N = {series_info['N']}, q = {series_info['q']}, tail = {series_info['tail']:.3g}")
     else:
         plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"], flags=B.FPS_FLAG_TIMING)
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t_setup)  # plan creation (with the norm estimates of eq. 37)
 
     for i in range(args.warmup):
         plan.eval(stream)
@@ -315,6 +319,7 @@ def main():
         "products_per_s": prod_per_s,
         "products_per_step": products,
         "products_skipped_per_step": st["products_skipped"],
+        "plan_setup_ms": setup_ms,
         "rows_wide_per_step": st["rows_wide"],
         "rows_global_per_step": st["rows_global"],
         "stage_ms": {f"{['power', 'block', 'gstep', 'horner'][k]}{i}": round(ms, 4)

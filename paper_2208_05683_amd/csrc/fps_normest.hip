@@ -108,23 +108,26 @@ __global__ void __launch_bounds__(kB) k_spmv(const int64_t* __restrict__ rp, con
     y[r] = acc;
 }
 
-// sum of |y_i| in ascending i by one wavefront: 64 values loaded at a time,
-// then added one after the other (each read from its lane into scalar
-// registers); the padding past n adds +0, which leaves a sum of nonnegative
-// terms unchanged
+// sum of |y_i| in ascending i by one wavefront: 64 values at a time go
+// through shared memory (the next 64 already loading), and every lane runs the
+// same chain of additions on broadcast reads of them in order; the padding
+// past n adds +0, which leaves a sum of nonnegative terms unchanged
 __global__ void __launch_bounds__(kWave) k_abs_sum_ordered(const double* __restrict__ y, int64_t n, double* out)
 {
+    __shared__ double buf[kWave];
     const int l = threadIdx.x;
     double acc = 0.0;
+    double nxt = (l < n) ? fabs(y[l]) : 0.0;
     for (int64_t b = 0; b < n; b += kWave) {
-        const double v = (b + l < n) ? fabs(y[b + l]) : 0.0;
-        const long long bits = __double_as_longlong(v);
-        const uint32_t lo = (uint32_t)bits, hi = (uint32_t)((unsigned long long)bits >> 32);
+        buf[l] = nxt;
+        __syncthreads();
+        nxt = (b + kWave + l < n) ? fabs(y[b + kWave + l]) : 0.0;
+        double v[kWave];
 #pragma unroll
-        for (int j = 0; j < kWave; ++j) {
-            const uint32_t a = __builtin_amdgcn_readlane(lo, j), c = __builtin_amdgcn_readlane(hi, j);
-            acc = acc + __longlong_as_double((long long)(((unsigned long long)c << 32) | a));
-        }
+        for (int j = 0; j < kWave; ++j) v[j] = buf[j];
+#pragma unroll
+        for (int j = 0; j < kWave; ++j) acc = acc + v[j];
+        __syncthreads();
     }
     if (l == 0) *out = acc;
 }
