@@ -86,7 +86,7 @@ struct DevBuf {
 struct SlackMatrix {
     int64_t n = 0;
     int64_t cap = 0;
-    DevBuf off, end, span, amax, col, val;
+    DevBuf off, end, span, amax, col, val, sw, nw;
     fps_status ensure_rows(int64_t nn)
     {
         n = nn;
@@ -94,6 +94,7 @@ struct SlackMatrix {
         FPS_TRY(end.ensure(sizeof(int64_t) * (size_t)std::max<int64_t>(nn, 1)));
         FPS_TRY(span.ensure(sizeof(int2) * (size_t)std::max<int64_t>(nn, 1)));
         FPS_TRY(amax.ensure(sizeof(double) * (size_t)std::max<int64_t>(nn, 1)));
+        FPS_TRY(nw.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nn, 1)));
         return FPS_OK;
     }
     fps_status ensure_cap(int64_t c)
@@ -102,18 +103,19 @@ struct SlackMatrix {
         const int64_t want = std::max<int64_t>(c + c / 8, 64);
         FPS_TRY(col.ensure(sizeof(int32_t) * (size_t)want));
         FPS_TRY(val.ensure(sizeof(double) * (size_t)want));
+        FPS_TRY(sw.ensure(sizeof(uint2) * (size_t)want));
         cap = want;
         return FPS_OK;
     }
     MatView view() const
     {
         return MatView{off.as<int64_t>(), end.as<int64_t>(), col.as<int32_t>(), val.as<double>(), span.as<int2>(),
-                       amax.as<double>()};
+                       amax.as<double>(), sw.as<uint2>(), nw.as<int32_t>()};
     }
     OutView out() const
     {
         return OutView{off.as<int64_t>(), end.as<int64_t>(), col.as<int32_t>(), val.as<double>(), span.as<int2>(),
-                       amax.as<double>(), cap};
+                       amax.as<double>(), sw.as<uint2>(), nw.as<int32_t>(), cap};
     }
 };
 
@@ -127,7 +129,7 @@ struct CanonMatrix {
 // Per-row workspace shared by the stages of one engine.
 struct Workspace {
     int64_t n = 0;
-    DevBuf W, lo, ub, fb, fb2, blk_pre, zspan, zamax, gscratch, counters, part, dummy;
+    DevBuf W, lo, ub, fb, fb2, blk_pre, zspan, zamax, zsw, znw, gscratch, counters, part, dummy;
     int64_t g_words = 0, g_cap = 0, g_stride = 0, g_off_acc = 0, g_off_ebuf = 0;
     int64_t part_stride = 0;
     int32_t g_slots = 0;
@@ -148,6 +150,7 @@ struct Workspace {
                                                                     offset_blocks(nn)}) + 1)));
         FPS_TRY(zspan.ensure(sizeof(int2) * rows));
         FPS_TRY(zamax.ensure(sizeof(double) * rows));
+        FPS_TRY(znw.ensure(sizeof(int32_t) * rows));
         FPS_TRY(counters.ensure(sizeof(StageCounters) * (size_t)stages));
         FPS_TRY(dummy.ensure(128 * (sizeof(int32_t) + sizeof(double))));
         {
@@ -441,7 +444,8 @@ struct Engine {
             HIP_TRY(launch_fill_u64(cs, 2 * n + 3, 0ull, s));
             const Alg1Params pr{eps_g, target, scale, max_iter, 0};
             HIP_TRY(launch_alg1_device(out.off.as<int64_t>(), out.end.as<int64_t>(), out.col.as<int32_t>(),
-                                       out.val.as<double>(), out.span.as<int2>(), out.amax.as<double>(), n, pr,
+                                       out.val.as<double>(), out.span.as<int2>(), out.amax.as<double>(),
+                                       out.sw.as<uint2>(), out.nw.as<int32_t>(), n, pr,
                                        device_iters, alg1_state(idx),
                                        cs, part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, ctr(idx), s));
             HIP_TRY(launch_fill_u64(&ctr(idx)->kept_global, 1, 0ull, s));
@@ -466,7 +470,8 @@ struct Engine {
         if (c > target)
             return set_error(FPS_ERR_CAPACITY, "Algorithm 1 did not reach its target within %d iterations", max_iter);
         HIP_TRY(launch_alg1_drop(out.off.as<int64_t>(), out.end.as<int64_t>(), out.col.as<int32_t>(),
-                                 out.val.as<double>(), out.span.as<int2>(), out.amax.as<double>(), n, t,
+                                 out.val.as<double>(), out.span.as<int2>(), out.amax.as<double>(),
+                                 out.sw.as<uint2>(), out.nw.as<int32_t>(), n, t,
                                  part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, s));
         // the drop pass recounted every row, including those of the device-memory kernel
         HIP_TRY(launch_fill_u64(&ctr(idx)->kept_global, 1, 0ull, s));
@@ -671,10 +676,11 @@ fps_status series_degree(const double* a, int L, const double* z, double eps_tol
     return FPS_OK;
 }
 
-// View of a canonical CSR for the kernels, with row info in (span, amax).
-MatView canon_view(const fps_csr_view* v, const int2* span, const double* amax)
+// View of a canonical CSR for the kernels, with row info in (span, amax) and
+// its structure words in (sw, nw).
+MatView canon_view(const fps_csr_view* v, const int2* span, const double* amax, const uint2* sw, const int32_t* nw)
 {
-    return MatView{v->row_ptr, v->row_ptr + 1, v->col, v->val, span, amax};
+    return MatView{v->row_ptr, v->row_ptr + 1, v->col, v->val, span, amax, sw, nw};
 }
 
 }  // namespace
@@ -742,6 +748,8 @@ struct fps_plan_s {
                 T->val[t] = nullptr;
                 T->span[t] = nullptr;
                 T->amax[t] = nullptr;
+                T->sw[t] = nullptr;
+                T->nw[t] = nullptr;
             } else {
                 const MatView v = (j == 1) ? zv : P[(size_t)j]->view();
                 T->beg[t] = v.beg;
@@ -750,6 +758,8 @@ struct fps_plan_s {
                 T->val[t] = v.val;
                 T->span[t] = v.span;
                 T->amax[t] = v.amax;
+                T->sw[t] = v.sw;
+                T->nw[t] = v.nw;
             }
         }
     }
@@ -774,8 +784,11 @@ struct fps_plan_s {
                                 (int64_t)(sizeof(StageCounters) / 8) * eng.ws.max_stages, 0ull, s));
         int2* zspan = eng.ws.zspan.as<int2>();
         double* zamax = eng.ws.zamax.as<double>();
-        HIP_TRY(launch_rowinfo_csr(Z.row_ptr, Z.col, Z.val, n, zspan, zamax, s));
-        const MatView zv = canon_view(&Z, zspan, zamax);
+        FPS_TRY(eng.ws.zsw.ensure(sizeof(uint2) * (size_t)std::max<int64_t>(Z.nnz, 1)));
+        uint2* zsw = eng.ws.zsw.as<uint2>();
+        int32_t* znw = eng.ws.znw.as<int32_t>();
+        HIP_TRY(launch_rowinfo_csr(Z.row_ptr, Z.col, Z.val, n, zspan, zamax, zsw, znw, s));
+        const MatView zv = canon_view(&Z, zspan, zamax, zsw, znw);
         const double skip_tau = (flags & FPS_FLAG_NO_SKIP) || tau <= 0.0 ? 0.0 : tau * (1.0 - 1e-6);
 
         const int nst = stage_count();
@@ -1218,27 +1231,33 @@ fps_status fps_spgemm(fps_matrix* out, const fps_csr_view* A, const fps_csr_view
     const int64_t n = A->n;
     Engine eng;
     FPS_TRY(eng.init(n, 1, 0));
-    DevBuf info;
-    const size_t per = (sizeof(int2) + sizeof(double)) * (size_t)n;
-    FPS_TRY(info.ensure(3 * per));
-    int2* sp[3];
-    double* am[3];
+    // row info and structure words of each operand
+    const fps_csr_view* ops[3] = {A, B, E};
+    DevBuf info[3], words[3];
+    int2* sp[3] = {};
+    double* am[3] = {};
+    uint2* sw[3] = {};
+    int32_t* nw[3] = {};
+    const size_t per = (sizeof(int2) + sizeof(double) + sizeof(int32_t)) * (size_t)n;
     for (int i = 0; i < 3; ++i) {
-        sp[i] = reinterpret_cast<int2*>(static_cast<char*>(info.p) + i * per);
-        am[i] = reinterpret_cast<double*>(static_cast<char*>(info.p) + i * per + sizeof(int2) * (size_t)n);
+        if (!ops[i]) continue;
+        FPS_TRY(info[i].ensure(per));
+        FPS_TRY(words[i].ensure(sizeof(uint2) * (size_t)std::max<int64_t>(ops[i]->nnz, 1)));
+        sp[i] = info[i].as<int2>();
+        am[i] = reinterpret_cast<double*>(static_cast<char*>(info[i].p) + sizeof(int2) * (size_t)n);
+        nw[i] = reinterpret_cast<int32_t*>(static_cast<char*>(info[i].p) + (sizeof(int2) + sizeof(double)) * (size_t)n);
+        sw[i] = words[i].as<uint2>();
+        HIP_TRY(launch_rowinfo_csr(ops[i]->row_ptr, ops[i]->col, ops[i]->val, n, sp[i], am[i], sw[i], nw[i], s));
     }
-    HIP_TRY(launch_rowinfo_csr(A->row_ptr, A->col, A->val, n, sp[0], am[0], s));
-    HIP_TRY(launch_rowinfo_csr(B->row_ptr, B->col, B->val, n, sp[1], am[1], s));
-    if (E) HIP_TRY(launch_rowinfo_csr(E->row_ptr, E->col, E->val, n, sp[2], am[2], s));
     HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(eng.ws.counters.p), sizeof(StageCounters) / 8, 0ull, s));
     StageArgs a{};
     a.mode = kModeProduct;
     a.tau = tau;
     a.skip_tau = tau > 0.0 ? tau * (1.0 - 1e-6) : 0.0;
-    a.A = canon_view(A, sp[0], am[0]);
-    a.B = canon_view(B, sp[1], am[1]);
+    a.A = canon_view(A, sp[0], am[0], sw[0], nw[0]);
+    a.B = canon_view(B, sp[1], am[1], sw[1], nw[1]);
     a.has_e = E ? 1 : 0;
-    if (E) a.E = canon_view(E, sp[2], am[2]);
+    if (E) a.E = canon_view(E, sp[2], am[2], sw[2], nw[2]);
     SlackMatrix res;
     FPS_TRY(eng.run(0, a, res, s, true, nullptr));
     return finish_single(eng, res, s, out);
@@ -1264,7 +1283,8 @@ fps_status fps_axpy(fps_matrix* out, int64_t n, int32_t nterms, const double* co
     Engine eng;
     FPS_TRY(eng.init(n, 1, 0));
     DevBuf info;
-    const size_t per = (sizeof(int2) + sizeof(double)) * (size_t)n;
+    std::vector<DevBuf> words((size_t)nterms);
+    const size_t per = (sizeof(int2) + sizeof(double) + sizeof(int32_t)) * (size_t)n;
     FPS_TRY(info.ensure(per * (size_t)nterms));
     StageArgs a{};
     a.mode = kModeSum;
@@ -1279,17 +1299,25 @@ fps_status fps_axpy(fps_matrix* out, int64_t n, int32_t nterms, const double* co
             a.T.val[t] = nullptr;
             a.T.span[t] = nullptr;
             a.T.amax[t] = nullptr;
+            a.T.sw[t] = nullptr;
+            a.T.nw[t] = nullptr;
             continue;
         }
-        int2* sp = reinterpret_cast<int2*>(static_cast<char*>(info.p) + t * per);
-        double* am = reinterpret_cast<double*>(static_cast<char*>(info.p) + t * per + sizeof(int2) * (size_t)n);
-        HIP_TRY(launch_rowinfo_csr(terms[t].row_ptr, terms[t].col, terms[t].val, n, sp, am, s));
+        char* base = static_cast<char*>(info.p) + t * per;
+        int2* sp = reinterpret_cast<int2*>(base);
+        double* am = reinterpret_cast<double*>(base + sizeof(int2) * (size_t)n);
+        int32_t* nw = reinterpret_cast<int32_t*>(base + (sizeof(int2) + sizeof(double)) * (size_t)n);
+        FPS_TRY(words[(size_t)t].ensure(sizeof(uint2) * (size_t)std::max<int64_t>(terms[t].nnz, 1)));
+        uint2* sw = words[(size_t)t].as<uint2>();
+        HIP_TRY(launch_rowinfo_csr(terms[t].row_ptr, terms[t].col, terms[t].val, n, sp, am, sw, nw, s));
         a.T.beg[t] = terms[t].row_ptr;
         a.T.end[t] = terms[t].row_ptr + 1;
         a.T.col[t] = terms[t].col;
         a.T.val[t] = terms[t].val;
         a.T.span[t] = sp;
         a.T.amax[t] = am;
+        a.T.sw[t] = sw;
+        a.T.nw[t] = nw;
     }
     HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(eng.ws.counters.p), sizeof(StageCounters) / 8, 0ull, s));
     SlackMatrix res;

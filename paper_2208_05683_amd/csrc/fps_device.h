@@ -14,6 +14,9 @@ constexpr int kMaxTerms = 32;  // FPS_MAX_S + 1
 // [beg[r], end[r]) of col/val, columns strictly increasing.  A canonical CSR
 // is the special case end = row_ptr + 1.  span[r] = (first, last) column of
 // the row (first > last when empty); amax[r] = max |value| of the row.
+// Structure words: sw[beg[r] .. beg[r] + nw[r]) lists the row's columns by
+// 32-column word, (column >> 5, bit (column & 31) set for each column of
+// the row in that word), words ascending; nw[r] <= entries of the row.
 struct MatView {
     const int64_t* beg;
     const int64_t* end;
@@ -21,6 +24,8 @@ struct MatView {
     const double* val;
     const int2* span;
     const double* amax;
+    const uint2* sw;
+    const int32_t* nw;
 };
 
 // Coefficient-sum operands: term t contributes coef[t] * M_t, with M_t the
@@ -34,6 +39,8 @@ struct Terms {
     const double* val[kMaxTerms];
     const int2* span[kMaxTerms];
     const double* amax[kMaxTerms];
+    const uint2* sw[kMaxTerms];
+    const int32_t* nw[kMaxTerms];
 };
 
 // Output of a stage in slack layout: row r may use [off[r], off[r+1]) and
@@ -45,7 +52,9 @@ struct OutView {
     double* val;
     int2* span;
     double* amax;
-    int64_t cap;  // capacity of col/val
+    uint2* sw;    // structure words of row r at sw[off[r] ..]
+    int32_t* nw;  // n: structure words of each row
+    int64_t cap;  // capacity of col/val/sw
 };
 
 // Per-stage device counters (zeroed before each evaluation).  Only rare
@@ -155,8 +164,9 @@ struct StageArgs {
 };
 
 // ---- launch wrappers (fps_kernels.hip) ---------------------------------
+// span, amax and the structure words (sw: nnz entries, nw: n) of a canonical CSR
 hipError_t launch_rowinfo_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n,
-                              int2* span, double* amax, hipStream_t s);
+                              int2* span, double* amax, uint2* sw, int32_t* nw, hipStream_t s);
 hipError_t launch_validate_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n,
                                int64_t nnz, unsigned long long* err, hipStream_t s);
 // the analysis of a stage, then (unless a.row_stride > 0) the scan of its
@@ -190,14 +200,14 @@ hipError_t launch_alg1_colsum(const int64_t* beg, const int64_t* end, const int3
                               double t, double scale, unsigned long long* colsum, hipStream_t s);
 hipError_t launch_max_u64(const unsigned long long* x, int64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
-                            int64_t n, double t, unsigned long long* part_kept, hipStream_t s);
+                            uint2* sw, int32_t* nw, int64_t n, double t, unsigned long long* part_kept, hipStream_t s);
 // Algorithm 1 driven on the device: `iters` iteration kernels (state in
 // st[0..1], column sums in cs[0..2n), maxima in cs[2n..2n+3), all zero on
 // entry), then the final update and the drop; the final record goes to st[2];
 // a stage that has not converged by then keeps its entries and raises
 // kErrAlg1Pending in ctr->errors.
 hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
-                              int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
+                              uint2* sw, int32_t* nw, int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
                               unsigned long long* part_kept, StageCounters* ctr, hipStream_t s);
 int numeric_global_blocks(int slots);
 // blocks of the wide-tier kernel (persistent: six per CU at most)

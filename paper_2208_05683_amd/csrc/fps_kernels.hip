@@ -163,11 +163,79 @@ __global__ void __launch_bounds__(kBlock) k_block_scan(int64_t* x, int64_t nblk,
 }
 
 // ---------------------------------------------------------------------------
-// Row information of a canonical CSR: (first, last) column and max |value|.
+// Structure words of a row from its ascending columns, G lanes at a time (G a
+// power of two up to 64; a group is G consecutive lanes that all make the
+// same calls).  The columns of one word sit on consecutive lanes, so a
+// segmented OR over lane distances 1, 2, 4, ... leaves each word's bits on
+// its first lane.  The last word of a batch stays open, since the next batch
+// may continue it.
+// ---------------------------------------------------------------------------
+template <int G>
+struct WordBuilder {
+    uint2* out;       // first word of the row
+    int32_t n = 0;    // words written
+    uint32_t cw = 0;  // the open word
+    uint32_t cm = 0;  // its bits (0: no open word)
+
+    // Columns c of group lanes [0, cnt), ascending, above the previous batch's.
+    __device__ __forceinline__ void add(int32_t c, int32_t cnt)
+    {
+        if (cnt <= 0) return;
+        const int gl = lane() & (G - 1);
+        const int gb = lane() & (kWave - G);
+        const bool v = gl < cnt;
+        const uint32_t w = (uint32_t)c >> 5;
+        uint32_t m = v ? (1u << (c & 31)) : 0u;
+#pragma unroll
+        for (int d = 1; d < G; d <<= 1) {
+            const uint32_t ow = __shfl_down(w, d, G);
+            const uint32_t om = __shfl_down(m, d, G);
+            if (gl + d < cnt && ow == w) m |= om;
+        }
+        const uint32_t pw = __shfl_up(w, 1, G);
+        const bool lead = v && (gl == 0 || pw != w);
+        const unsigned long long bal = __ballot(lead);
+        const unsigned long long gm = (G == kWave) ? bal : (bal >> gb) & ((1ull << (G & 63)) - 1ull);
+        const int nseg = __popcll(gm);
+        const int seg = __popcll(gm & ((1ull << gl) - 1ull));
+        const uint32_t w0 = __shfl(w, 0, G), m0 = __shfl(m, 0, G);
+        const bool cont = cm != 0u && w0 == cw;  // the first word continues the open one
+        uint32_t om = cm;
+        if (cont) om |= m0;
+        const int first = cont ? 1 : 0;
+        if (nseg == first) {  // the batch only continued the open word
+            cm = om;
+            return;
+        }
+        if (om != 0u) {
+            if (gl == 0) out[n] = make_uint2(cw, om);
+            n += 1;
+        }
+        if (lead && seg >= first && seg < nseg - 1) out[n + seg - first] = make_uint2(w, m);
+        n += nseg - 1 - first;
+        const int lastl = 63 - __clzll(gm);
+        cw = __shfl(w, lastl, G);
+        cm = __shfl(m, lastl, G);
+    }
+    // Closes the open word; returns the number of words of the row.
+    __device__ __forceinline__ int32_t finish()
+    {
+        if (cm != 0u) {
+            if ((lane() & (G - 1)) == 0) out[n] = make_uint2(cw, cm);
+            n += 1;
+            cm = 0u;
+        }
+        return n;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Row information of a canonical CSR: (first, last) column, max |value| and
+// the structure words.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_rowinfo_csr(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                                         const double* __restrict__ val, int64_t n, int2* span,
-                                                        double* amax)
+                                                        double* amax, uint2* sw, int32_t* nw)
 {
     constexpr int G = 16;
     const int64_t r = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
@@ -175,11 +243,22 @@ __global__ void __launch_bounds__(kBlock) k_rowinfo_csr(const int64_t* __restric
     if (r >= n) return;
     const int64_t b = rp[r], e = rp[r + 1];
     double m = 0.0;
-    for (int64_t p = b + gl; p < e; p += G) m = fmax(m, fabs(val[p]));
+    WordBuilder<G> wb{sw + b};
+    for (int64_t p0 = b; p0 < e; p0 += G) {
+        const int64_t p = p0 + gl;
+        int32_t c = 0;
+        if (p < e) {
+            c = col[p];
+            m = fmax(m, fabs(val[p]));
+        }
+        wb.add(c, (int32_t)min<int64_t>(G, e - p0));
+    }
+    const int32_t words = wb.finish();
     m = group_max<G>(m);
     if (gl == 0) {
         span[r] = (e > b) ? make_int2(col[b], col[e - 1]) : make_int2(1, 0);
         amax[r] = m;
+        nw[r] = words;
     }
 }
 
@@ -296,8 +375,11 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
             int32_t W = 0;
             int64_t ub = 0;
             if (!empty && !skip) {
+                // the window starts on a 32-column boundary, so that its bitmap
+                // words are whole words of the column space
+                ub = min(prod + elen, (int64_t)(hi - lo + 1));
+                lo &= ~31;
                 W = hi - lo + 1;
-                ub = min(prod + elen, (int64_t)W);
             }
             P.W[r] = W;
             P.lo[r] = lo;
@@ -369,8 +451,9 @@ __global__ void __launch_bounds__(kBlock) k_analyze_sum(StageArgs P)
         int32_t W = 0;
         int64_t ub = 0;
         if (prod > 0) {
+            ub = min(prod, (int64_t)(hi - lo + 1));
+            lo &= ~31;  // whole words of the column space
             W = hi - lo + 1;
-            ub = min(prod, (int64_t)W);
         }
         P.W[r] = W;
         P.lo[r] = lo;
@@ -849,14 +932,98 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
     }
 }
 
+// ---- structure marks from structure words ------------------------------------
+// A term row marks the output row's bitmap with one OR per structure word
+// (the words of one row are distinct, so its ORs never meet on one address).
+// The chunk's terms are spread over the lanes, `per` terms per instruction
+// with `wd` lanes each, wd being the chunk's largest word count; term rows of
+// more than 64 words go 64 words per step.  A word outside the window lands
+// in the guard word.
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src)
+{
+    const uint32_t lo = __shfl((uint32_t)x, src, kWave);
+    const uint32_t hi = __shfl((uint32_t)(x >> 32), src, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int SRC>
+__device__ __forceinline__ void mark_words(const StageArgs& P, int64_t r, int32_t lo, uint32_t words, uint2* bmp)
+{
+    const int l = lane();
+    const uint32_t lo_w = (uint32_t)lo >> 5;
+    const uint2 ident = make_uint2((uint32_t)(r >> 5), 1u << (r & 31));
+    int64_t tb, te;
+    term_range(P, SRC, r, &tb, &te);
+    for (int64_t t0 = tb; t0 < te; t0 += kChunk) {
+        const int64_t t = t0 + l;
+        uint64_t wp = 0;  // address of the term row's first word; 0: the identity row
+        int32_t nw = 0;
+        if (t < te) {
+            if (SRC == kSrcProducts) {
+                const int32_t k = P.A.col[t];
+                wp = reinterpret_cast<uint64_t>(P.B.sw + P.B.beg[k]);
+                nw = P.B.nw[k];
+            } else {
+                const int ti = (int)t;
+                const int64_t* bp = P.T.beg[ti];
+                if (bp == nullptr) {
+                    nw = 1;
+                } else {
+                    wp = reinterpret_cast<uint64_t>(P.T.sw[ti] + bp[r]);
+                    nw = P.T.nw[ti][r];
+                }
+            }
+        }
+        const int32_t nterms = (int32_t)min<int64_t>(kChunk, te - t0);
+        const int32_t maxnw = sgpr(group_max<kWave>(nw));
+        if (maxnw == 0) continue;
+        const int32_t wd = min(maxnw, (int32_t)kWave);
+        const int32_t per = kWave / wd;
+        const int32_t sub = l / wd, idx = l - sub * wd;
+        const bool lane_on = sub < per;
+        // word e of the term held by lane ti of the chunk
+        auto fetch = [&](int32_t ti, int32_t e, bool* ok) -> uint2 {
+            const int src = min(ti, kChunk - 1);
+            const uint64_t p = shfl_u64(wp, src);
+            const int32_t n_t = __shfl(nw, src, kWave);
+            *ok = lane_on && ti < nterms && e < n_t;
+            if (!*ok) return make_uint2(0u, 0u);
+            if (SRC == kSrcCoefs && p == 0) return ident;
+            return reinterpret_cast<const uint2*>(p)[e];
+        };
+        auto mark = [&](bool ok, uint2 w) {
+            if (ok) atomicOr(&bmp[min(w.x - lo_w, words)].x, w.y);
+        };
+        if (maxnw <= kWave) {
+            for (int32_t i0 = 0; i0 < nterms; i0 += 2 * per) {
+                bool ok0, ok1;
+                const uint2 w0 = fetch(i0 + sub, idx, &ok0);
+                const uint2 w1 = fetch(i0 + per + sub, idx, &ok1);
+                mark(ok0, w0);
+                mark(ok1, w1);
+            }
+        } else {
+            for (int32_t i0 = 0; i0 < nterms; ++i0)
+                for (int32_t e0 = 0; e0 < maxnw; e0 += kWave) {
+                    bool ok;
+                    const uint2 w = fetch(i0, e0 + l, &ok);
+                    mark(ok, w);
+                }
+        }
+    }
+}
+
 // Row r of the stage output left empty at offset o (one lane writes): every
-// row gets its end, span and maximum in every evaluation, so that later stages
-// and the compaction never read a previous evaluation's values.
+// row gets its end, span, maximum and word count in every evaluation, so
+// that later stages and the compaction never read a previous evaluation's
+// values.
 __device__ __forceinline__ void empty_row(const StageArgs& P, int64_t r, int64_t o)
 {
     P.out.end[r] = o;
     P.out.span[r] = make_int2(1, 0);
     P.out.amax[r] = 0.0;
+    P.out.nw[r] = 0;
 }
 
 // Computes output row r.  Returns false (with nothing written) if the row
@@ -902,7 +1069,12 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     }
     wave_sync();
     const Chunk none{};
-    if (P.has_blk) terms_pass<false, kGlobal>(P, kSrcCoefs, r, lo, guard, bytes, bmp, nullptr, st, false, none);
+    if (P.has_blk) {
+        if (kGlobal)
+            terms_pass<false, true>(P, kSrcCoefs, r, lo, guard, bytes, bmp, nullptr, st, false, none);
+        else
+            mark_words<kSrcCoefs>(P, r, lo, (uint32_t)words, bmp);
+    }
     if (P.has_e) {
         for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave)
             mark_d<kGlobal>((uint32_t)(P.E.col[p] - lo), guard, bytes, bmp);
@@ -925,8 +1097,12 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
                 gather<true>(P, st, 0, c0.total, b1);
                 mark_batch<kGlobal>(lo, guard, b1, bytes, bmp);
             }
+        } else if (kGlobal) {
+            terms_pass<false, true>(P, main_src, r, lo, guard, bytes, bmp, nullptr, st, true, c0);
+        } else if (main_src == kSrcProducts) {
+            mark_words<kSrcProducts>(P, r, lo, (uint32_t)words, bmp);
         } else {
-            terms_pass<false, kGlobal>(P, main_src, r, lo, guard, bytes, bmp, nullptr, st, true, c0);
+            mark_words<kSrcCoefs>(P, r, lo, (uint32_t)words, bmp);
         }
     }
     wave_sync();
@@ -946,7 +1122,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
 
     // a column outside the row's window means the row information of an
     // operand was inconsistent: the stage reports an error, the row stays empty
-    if (bmp[words].x & 1u) {
+    if (bmp[words].x != 0u) {
         flag_error(P, kErrColumnOutsideWindow);
         if (l == 0) empty_row(P, r, o);
         return true;
@@ -1041,7 +1217,11 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     int32_t first = INT_MAX, last = -1;
     auto emit = [&](int64_t i, double x, int32_t c) {
         bool keep = false;
-        if (i < ns) keep = (x != 0.0) && !(fabs(x) < P.tau);
+        if (i < ns) {
+            keep = (x != 0.0) && !(fabs(x) < P.tau);
+            // the bitmap keeps the kept columns only, for the structure words
+            if (!keep) atomicAnd(&bmp[(uint32_t)(c - lo) >> 5].x, ~(1u << (c & 31)));
+        }
         const unsigned long long m = __ballot(keep);
         if (keep) {
             const int64_t pos = o + kept + (int64_t)lanes_below(m);
@@ -1098,10 +1278,21 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     amx = group_max<kWave>(amx);
     first = group_min<kWave>(first);
     last = group_max<kWave>(last);
+    // 6. structure words of the row: the nonzero bitmap words, in order
+    wave_sync();
+    int32_t nwd = 0;
+    for (int64_t w0 = 0; w0 < words; w0 += kWave) {
+        const int64_t w = w0 + l;
+        const uint32_t bits = (w < words) ? bmp[w].x : 0u;
+        const unsigned long long m = __ballot(bits != 0u);
+        if (bits != 0u) P.out.sw[o + nwd + (int64_t)lanes_below(m)] = make_uint2(((uint32_t)lo >> 5) + (uint32_t)w, bits);
+        nwd += __popcll(m);
+    }
     if (l == 0) {
         P.out.end[r] = o + kept;
         P.out.span[r] = kept ? make_int2(first, last) : make_int2(1, 0);
         P.out.amax[r] = amx;
+        P.out.nw[r] = nwd;
     }
     wave_sync();
     *kept_out = kept;
@@ -1411,11 +1602,13 @@ __global__ void __launch_bounds__(kBlock) k_alg1_max(int64_t n, int i, const Alg
 }
 
 // Drops the entries with |x| <= t of every row in place (the kept entries
-// keep their order), updates end, span and amax, and writes per-block kept
-// counts into `part_kept` (same block layout as the numeric kernel).
+// keep their order), updates end, span, amax and the structure words, and
+// writes per-block kept counts into `part_kept` (same block layout as the
+// numeric kernel).
 template <bool kDevice>
 __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restrict__ beg, int64_t* end, int32_t* col,
-                                                        double* val, int2* span, double* amax, int64_t n, double t,
+                                                        double* val, int2* span, double* amax, uint2* sw, int32_t* nw,
+                                                        int64_t n, double t,
                                                         unsigned long long* part_kept, Alg1Params pr, int iters,
                                                         Alg1State* st, const unsigned long long* cs,
                                                         StageCounters* ctr)
@@ -1466,10 +1659,19 @@ __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restric
         amx = group_max<kWave>(amx);
         first = group_min<kWave>(first);
         last = group_max<kWave>(last);
+        // structure words of the kept columns
+        wave_sync();
+        WordBuilder<kWave> wb{sw + b};
+        for (int64_t p0 = 0; p0 < kept; p0 += kWave) {
+            const int64_t p = p0 + l;
+            wb.add(p < kept ? col[b + p] : 0, (int32_t)min<int64_t>(kWave, kept - p0));
+        }
+        const int32_t words = wb.finish();
         if (l == 0) {
             end[r] = b + kept;
             span[r] = kept ? make_int2(first, last) : make_int2(1, 0);
             amax[r] = amx;
+            nw[r] = words;
         }
     }
     if (l == 0) kept_sh[wv] = (unsigned long long)kept;
@@ -1488,10 +1690,11 @@ inline unsigned blocks_for(int64_t threads) { return (unsigned)((threads + kBloc
 // ---- launch wrappers -------------------------------------------------------
 
 hipError_t launch_rowinfo_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n, int2* span,
-                              double* amax, hipStream_t s)
+                              double* amax, uint2* sw, int32_t* nw, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rowinfo_csr, dim3(blocks_for(n * 16)), dim3(kBlock), 0, s, row_ptr, col, val, n, span, amax);
+    hipLaunchKernelGGL(k_rowinfo_csr, dim3(blocks_for(n * 16)), dim3(kBlock), 0, s, row_ptr, col, val, n, span, amax,
+                       sw, nw);
     return hipGetLastError();
 }
 
@@ -1605,17 +1808,17 @@ hipError_t launch_max_u64(const unsigned long long* x, int64_t n, unsigned long 
 }
 
 hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
-                            int64_t n, double t, unsigned long long* part_kept, hipStream_t s)
+                            uint2* sw, int32_t* nw, int64_t n, double t, unsigned long long* part_kept, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_alg1_drop_t<false>, dim3((unsigned)numeric_blocks(n)), dim3(kBlock), 0, s, beg, end, col, val,
-                       span, amax, n, t, part_kept, Alg1Params{}, 0, (Alg1State*)nullptr,
+                       span, amax, sw, nw, n, t, part_kept, Alg1Params{}, 0, (Alg1State*)nullptr,
                        (const unsigned long long*)nullptr, (StageCounters*)nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
-                              int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
+                              uint2* sw, int32_t* nw, int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
                               unsigned long long* part_kept, StageCounters* ctr, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
@@ -1627,7 +1830,8 @@ hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, do
                            (const int64_t*)end, (const int32_t*)col, (const double*)val, n, pr, i, st, cs);
         hipLaunchKernelGGL(k_alg1_max, dim3(max_blocks), dim3(kBlock), 0, s, n, i, (const Alg1State*)st, cs);
     }
-    hipLaunchKernelGGL(k_alg1_drop_t<true>, dim3(blocks), dim3(kBlock), 0, s, beg, end, col, val, span, amax, n, 0.0,
+    hipLaunchKernelGGL(k_alg1_drop_t<true>, dim3(blocks), dim3(kBlock), 0, s, beg, end, col, val, span, amax, sw, nw,
+                       n, 0.0,
                        part_kept, pr, iters, st, (const unsigned long long*)cs, ctr);
     return hipGetLastError();
 }
