@@ -505,6 +505,15 @@ __device__ __forceinline__ uint32_t rank_of(const uint2* bmp, uint32_t d)
     return w.y + (uint32_t)__popc(__builtin_amdgcn_ubfe(w.x, 0u, d));
 }
 
+// The same by column: the window starts on a word boundary, so with
+// bw = bmp - (lo >> 5) the column's word is bw[c >> 5] and its bit c & 31.
+// The guard column lo + guard ranks to the spare slot.
+__device__ __forceinline__ uint32_t rank_col(const uint2* bw, int32_t c)
+{
+    const uint2 w = bw[(uint32_t)c >> 5];
+    return w.y + (uint32_t)__popc(__builtin_amdgcn_ubfe(w.x, 0u, (uint32_t)c));
+}
+
 __device__ __forceinline__ int32_t sgpr(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ int64_t sgpr64(int64_t x)
 {
@@ -542,6 +551,7 @@ __device__ __forceinline__ void term_range(const StageArgs& P, int src, int64_t 
 // padding past the last term).
 struct Chunk {
     int32_t len;     // entries of the term row
+    int32_t nw;      // structure words of the term row
     int32_t incl;    // inclusive prefix of len over the lanes
     int64_t beg;     // first entry of the term row; -1: identity row (P_0)
     double a;        // weight
@@ -555,6 +565,7 @@ __device__ __forceinline__ Chunk load_chunk(const StageArgs& P, int src, int64_t
     const int64_t t = t0 + l;
     Chunk c;
     c.len = 0;
+    c.nw = 0;
     c.beg = 0;
     c.a = 0.0;
     if (t < te) {
@@ -563,6 +574,7 @@ __device__ __forceinline__ Chunk load_chunk(const StageArgs& P, int src, int64_t
             c.a = P.A.val[t];
             c.beg = P.B.beg[k];
             c.len = (int32_t)(P.B.end[k] - c.beg);
+            c.nw = P.B.nw[k];
         } else {
             // both row pointers of the term are read at once, then both
             // offsets of row r (the identity term reads zeros from the dummy
@@ -575,8 +587,10 @@ __device__ __forceinline__ Chunk load_chunk(const StageArgs& P, int src, int64_t
             const int64_t* zero = reinterpret_cast<const int64_t*>(P.dummy_val);
             const int64_t b = *(ident ? zero : bp + r);
             const int64_t e = *(ident ? zero : ep + r);
+            const int32_t nwv = *(ident ? reinterpret_cast<const int32_t*>(zero) : P.T.nw[ti] + r);
             c.beg = ident ? -1 : b;
             c.len = ident ? 1 : (int32_t)(e - b);
+            c.nw = ident ? 1 : nwv;
         }
     }
     c.incl = wave_incl_sum(c.len);
@@ -671,13 +685,15 @@ template <int U>
 __device__ __forceinline__ void accumulate_batch(const Chunk& c, int32_t q0, int32_t lo, uint32_t guard,
                                                  const Batch<U>& b, const uint2* bmp, double* acc)
 {
+    const uint2* bw = bmp - (lo >> 5);
+    const int32_t gcol = lo + (int32_t)guard;
 #pragma unroll
     for (int j = 0; j < U; ++j) {
         const int32_t qj = q0 + j * kWave;
         if (qj >= c.total) break;
         const double v = b.v[j];
         const bool ok = b.ok[j];
-        const uint32_t slot = rank_of(bmp, ok ? (uint32_t)(b.c[j] - lo) : guard);
+        const uint32_t slot = rank_col(bw, ok ? b.c[j] : gcol);
         const int last = min(kWave - 1, c.total - qj - 1);
         const int kf = __builtin_amdgcn_readlane(b.kidx[j], 0);
         const int kl = __builtin_amdgcn_readlane(b.kidx[j], last);
@@ -793,9 +809,11 @@ __device__ __forceinline__ Slots part_slots(const TermInfo& h, int32_t e0, const
 {
     const int l = lane();
     const int32_t c0 = h.ident ? (int32_t)r : p.c0;
+    const uint2* bw = bmp - (lo >> 5);
+    const int32_t gcol = lo + (int32_t)guard;
     Slots s;
-    s.s0 = rank_of(bmp, (e0 + l < h.len) ? (uint32_t)(c0 - lo) : guard);
-    s.s1 = kBoth ? rank_of(bmp, (e0 + kWave + l < h.len) ? (uint32_t)(p.c1 - lo) : guard) : 0u;
+    s.s0 = rank_col(bw, (e0 + l < h.len) ? c0 : gcol);
+    s.s1 = kBoth ? rank_col(bw, (e0 + kWave + l < h.len) ? p.c1 : gcol) : 0u;
     return s;
 }
 
@@ -947,8 +965,10 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// `first`, if given, is the chunk at the first term, already loaded.
 template <int SRC>
-__device__ __forceinline__ void mark_words(const StageArgs& P, int64_t r, int32_t lo, uint32_t words, uint2* bmp)
+__device__ __forceinline__ void mark_words(const StageArgs& P, int64_t r, int32_t lo, uint32_t words, uint2* bmp,
+                                           const Chunk* first)
 {
     const int l = lane();
     const uint32_t lo_w = (uint32_t)lo >> 5;
@@ -959,7 +979,14 @@ __device__ __forceinline__ void mark_words(const StageArgs& P, int64_t r, int32_
         const int64_t t = t0 + l;
         uint64_t wp = 0;  // address of the term row's first word; 0: the identity row
         int32_t nw = 0;
-        if (t < te) {
+        if (first != nullptr && t0 == tb) {
+            nw = first->nw;
+            if (SRC == kSrcProducts) {
+                wp = reinterpret_cast<uint64_t>(P.B.sw + first->beg);
+            } else if (t < te && first->beg >= 0) {
+                wp = reinterpret_cast<uint64_t>(P.T.sw[(int)t] + first->beg);
+            }
+        } else if (t < te) {
             if (SRC == kSrcProducts) {
                 const int32_t k = P.A.col[t];
                 wp = reinterpret_cast<uint64_t>(P.B.sw + P.B.beg[k]);
@@ -1068,26 +1095,28 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
         for (int64_t w = l; w <= words; w += kWave) bmp[w].x = 0u;
     }
     wave_sync();
+    // rows whose main terms have no entries (known from the analysis) skip
+    // them.  The first chunk of main terms is loaded before the block's marks
+    // (its loads overlap theirs); the structure pass reuses it.
+    const bool has_main = P.prod[r] > 0;
+    int64_t tb, te;
+    term_range(P, main_src, r, &tb, &te);
+    Chunk c0{};
+    if (has_main) c0 = load_chunk(P, main_src, r, tb, te);
     const Chunk none{};
     if (P.has_blk) {
         if (kGlobal)
             terms_pass<false, true>(P, kSrcCoefs, r, lo, guard, bytes, bmp, nullptr, st, false, none);
         else
-            mark_words<kSrcCoefs>(P, r, lo, (uint32_t)words, bmp);
+            mark_words<kSrcCoefs>(P, r, lo, (uint32_t)words, bmp, nullptr);
     }
     if (P.has_e) {
         for (int64_t p = P.E.beg[r] + l; p < P.E.end[r]; p += kWave)
             mark_d<kGlobal>((uint32_t)(P.E.col[p] - lo), guard, bytes, bmp);
     }
-    // rows whose main terms have no entries (known from the analysis) skip them
-    const bool has_main = P.prod[r] > 0;
-    int64_t tb, te;
-    term_range(P, main_src, r, &tb, &te);
-    Chunk c0{};
     bool one_chunk = true, single = false;
     Batch<1> b1;
     if (has_main) {
-        c0 = load_chunk(P, main_src, r, tb, te);
         one_chunk = (te - tb <= kChunk);
         const bool flat0 = !use_per_term(main_src, c0);
         if (flat0) stage_chunk(c0, st);
@@ -1100,9 +1129,9 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
         } else if (kGlobal) {
             terms_pass<false, true>(P, main_src, r, lo, guard, bytes, bmp, nullptr, st, true, c0);
         } else if (main_src == kSrcProducts) {
-            mark_words<kSrcProducts>(P, r, lo, (uint32_t)words, bmp);
+            mark_words<kSrcProducts>(P, r, lo, (uint32_t)words, bmp, &c0);
         } else {
-            mark_words<kSrcCoefs>(P, r, lo, (uint32_t)words, bmp);
+            mark_words<kSrcCoefs>(P, r, lo, (uint32_t)words, bmp, &c0);
         }
     }
     wave_sync();
