@@ -91,6 +91,90 @@ __device__ __forceinline__ T group_max(T x)
     return x;
 }
 
+// ---- cross-lane operations on DPP (data-parallel primitives) ------------------
+// A DPP row is 16 lanes.  These replace shuffles through the LDS crossbar
+// (ds_bpermute, one LDS round trip per step) on the paths every row takes;
+// all lanes of the wavefront must be active.
+constexpr int kDppQuadSwap1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kDppQuadSwap2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kDppRowHalfMirror = 0x141;  // lane i <- lane 7 - i of its half row
+constexpr int kDppRowMirror = 0x140;     // lane i <- lane 15 - i of its row
+constexpr int kDppRowShr1 = 0x111;       // lane i <- lane i - n of its row (0 below)
+constexpr int kDppRowBcast15 = 0x142;    // lanes of row k+1 <- lane 15 of row k
+constexpr int kDppRowBcast31 = 0x143;    // lanes of rows 2, 3 <- lane 31
+
+template <int kCtrl, int kRowMask = 0xF>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kCtrl, kRowMask, 0xF, false);
+}
+template <int kCtrl, typename T>
+__device__ __forceinline__ T dpp_val(T x)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, dpp32<kCtrl>(__builtin_bit_cast(uint32_t, x)));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, x);
+        const uint64_t lo = dpp32<kCtrl>((uint32_t)u), hi = dpp32<kCtrl>((uint32_t)(u >> 32));
+        return __builtin_bit_cast(T, (hi << 32) | lo);
+    }
+}
+struct OpMax {
+    template <typename T>
+    __device__ T operator()(T a, T b) const { return a > b ? a : b; }
+};
+struct OpMin {
+    template <typename T>
+    __device__ T operator()(T a, T b) const { return a < b ? a : b; }
+};
+struct OpSum {
+    template <typename T>
+    __device__ T operator()(T a, T b) const { return a + b; }
+};
+// Every lane gets the reduction over its 16-lane row.
+template <typename Op, typename T>
+__device__ __forceinline__ T row_reduce(T x)
+{
+    const Op op;
+    x = op(x, dpp_val<kDppQuadSwap1>(x));
+    x = op(x, dpp_val<kDppQuadSwap2>(x));
+    x = op(x, dpp_val<kDppRowHalfMirror>(x));
+    x = op(x, dpp_val<kDppRowMirror>(x));
+    return x;
+}
+// The reduction over the wavefront (uniform).
+template <typename Op, typename T>
+__device__ __forceinline__ T wave_reduce(T x)
+{
+    x = row_reduce<Op>(x);
+    const Op op;
+    T r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if constexpr (sizeof(T) == 4) {
+            r[k] = __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 16 * k));
+        } else {
+            const uint64_t u = __builtin_bit_cast(uint64_t, x);
+            const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 16 * k);
+            const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 16 * k);
+            r[k] = __builtin_bit_cast(T, (hi << 32) | lo);
+        }
+    }
+    return op(op(r[0], r[1]), op(r[2], r[3]));
+}
+// Inclusive prefix sum over the wavefront.
+__device__ __forceinline__ uint32_t wave_scan_u32(uint32_t x)
+{
+    x += dpp32<kDppRowShr1>(x);
+    x += dpp32<kDppRowShr1 + 1>(x);
+    x += dpp32<kDppRowShr1 + 3>(x);
+    x += dpp32<kDppRowShr1 + 7>(x);
+    x += dpp32<kDppRowBcast15, 0xA>(x);
+    x += dpp32<kDppRowBcast31, 0xC>(x);
+    return x;
+}
+
 __device__ __forceinline__ unsigned lanes_below(unsigned long long mask)
 {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
@@ -254,7 +338,7 @@ __global__ void __launch_bounds__(kBlock) k_rowinfo_csr(const int64_t* __restric
         wb.add(c, (int32_t)min<int64_t>(G, e - p0));
     }
     const int32_t words = wb.finish();
-    m = group_max<G>(m);
+    m = row_reduce<OpMax>(m);
     if (gl == 0) {
         span[r] = (e > b) ? make_int2(col[b], col[e - 1]) : make_int2(1, 0);
         amax[r] = m;
@@ -363,12 +447,13 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
                 }
             }
         }
-        lo = group_min<G>(lo);
-        hi = group_max<G>(hi);
-        prod = group_sum<G>(prod);
-        bnd = group_sum<G>(bnd);
-        elen = group_sum<G>(elen);
-        emax = group_sum<G>(emax);
+        static_assert(G == 16, "a product row is one DPP row");
+        lo = row_reduce<OpMin>(lo);
+        hi = row_reduce<OpMax>(hi);
+        prod = row_reduce<OpSum>(prod);
+        bnd = row_reduce<OpSum>(bnd);
+        elen = row_reduce<OpSum>(elen);
+        emax = row_reduce<OpSum>(emax);
         if (gl == 0) {
             const bool empty = (prod == 0 && elen == 0);
             const bool skip = !empty && P.skip_tau > 0.0 && (emax + bnd) < P.skip_tau;
@@ -593,7 +678,7 @@ __device__ __forceinline__ Chunk load_chunk(const StageArgs& P, int src, int64_t
             c.nw = ident ? 1 : nwv;
         }
     }
-    c.incl = wave_incl_sum(c.len);
+    c.incl = (int32_t)wave_scan_u32((uint32_t)c.len);
     c.total = __builtin_amdgcn_readlane(c.incl, kWave - 1);
     c.nterms = (int32_t)min<int64_t>(kChunk, te - t0);
     return c;
@@ -1003,7 +1088,7 @@ __device__ __forceinline__ void mark_words(const StageArgs& P, int64_t r, int32_
             }
         }
         const int32_t nterms = (int32_t)min<int64_t>(kChunk, te - t0);
-        const int32_t maxnw = sgpr(group_max<kWave>(nw));
+        const int32_t maxnw = sgpr(wave_reduce<OpMax>(nw));
         if (maxnw == 0) continue;
         const int32_t wd = min(maxnw, (int32_t)kWave);
         const int32_t per = kWave / wd;
@@ -1163,9 +1248,9 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     for (int64_t w0 = 0; w0 < words; w0 += kWave) {
         const int64_t w = w0 + l;
         const uint32_t cnt = (w < words) ? (uint32_t)__popc(bmp[w].x) : 0u;
-        const uint32_t inc = wave_incl_sum(cnt);
+        const uint32_t inc = wave_scan_u32(cnt);
         if (w < words) bmp[w].y = running + inc - cnt;
-        running += __shfl(inc, kWave - 1, kWave);
+        running += (uint32_t)__builtin_amdgcn_readlane((int)inc, kWave - 1);
     }
     const int64_t ns = running;
     wave_sync();
@@ -1304,9 +1389,9 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
             if ((int64_t)t * kWave < ns) emit(i, preg[t], i < ns ? cols[i] : 0);
         }
     }
-    amx = group_max<kWave>(amx);
-    first = group_min<kWave>(first);
-    last = group_max<kWave>(last);
+    amx = wave_reduce<OpMax>(amx);
+    first = wave_reduce<OpMin>(first);
+    last = wave_reduce<OpMax>(last);
     // 6. structure words of the row: the nonzero bitmap words, in order
     wave_sync();
     int32_t nwd = 0;
@@ -1685,9 +1770,9 @@ __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restric
             }
             kept += __popcll(m);
         }
-        amx = group_max<kWave>(amx);
-        first = group_min<kWave>(first);
-        last = group_max<kWave>(last);
+        amx = wave_reduce<OpMax>(amx);
+        first = wave_reduce<OpMin>(first);
+        last = wave_reduce<OpMax>(last);
         // structure words of the kept columns
         wave_sync();
         WordBuilder<kWave> wb{sw + b};
