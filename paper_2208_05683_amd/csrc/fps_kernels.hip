@@ -642,6 +642,7 @@ struct Chunk {
     double a;        // weight
     int32_t total;   // uniform: products of the chunk
     int32_t nterms;  // uniform
+    int32_t maxlen;  // uniform: longest term row of the chunk
 };
 
 __device__ __forceinline__ Chunk load_chunk(const StageArgs& P, int src, int64_t r, int64_t t0, int64_t te)
@@ -680,6 +681,7 @@ __device__ __forceinline__ Chunk load_chunk(const StageArgs& P, int src, int64_t
     }
     c.incl = (int32_t)wave_scan_u32((uint32_t)c.len);
     c.total = __builtin_amdgcn_readlane(c.incl, kWave - 1);
+    c.maxlen = wave_reduce<OpMax>(c.len);
     c.nterms = (int32_t)min<int64_t>(kChunk, te - t0);
     return c;
 }
@@ -995,6 +997,46 @@ __device__ __forceinline__ void per_term_pass(const StageArgs& P, int64_t r, int
     }
 }
 
+// Chunks whose term rows all fit one wavefront (at most 64 entries)
+// accumulate kShortGroup terms at a time, one load per lane and term: the
+// same registers as a group of kGroup terms with two halves each, half the
+// dependent round trips.
+constexpr int kShortGroup = 6;
+
+template <int SRC>
+__device__ __forceinline__ void short_group_pass(const StageArgs& P, int64_t r, int64_t t0, const Chunk& c,
+                                                 int32_t lo, uint32_t guard, const uint2* bmp, double* acc)
+{
+    const int l = lane();
+    const uint2* bw = bmp - (lo >> 5);
+    const int32_t gcol = lo + (int32_t)guard;
+    for (int i0 = 0; i0 < c.nterms; i0 += kShortGroup) {
+        TermInfo h[kShortGroup];
+        int32_t cc[kShortGroup];
+        double vv[kShortGroup];
+#pragma unroll
+        for (int g = 0; g < kShortGroup; ++g) {
+            const TermDesc d = term_desc<SRC, true>(P, t0, c, i0 + g);
+            h[g] = d.t;
+            cc[g] = __builtin_amdgcn_raw_buffer_load_b32(d.rc, l * 4, 0, 0);
+            vv[g] = __longlong_as_double((long long)__builtin_amdgcn_raw_buffer_load_b64(d.rv, l * 8, 0, 0));
+        }
+        uint32_t sl[kShortGroup];
+#pragma unroll
+        for (int g = 0; g < kShortGroup; ++g) {
+            const int32_t col = h[g].ident ? (int32_t)r : cc[g];
+            sl[g] = rank_col(bw, (l < h[g].len) ? col : gcol);
+        }
+#pragma unroll
+        for (int g = 0; g < kShortGroup; ++g) {
+            if (h[g].len == 0) continue;
+            const double v = h[g].ident ? 1.0 : vv[g];
+            acc[sl[g]] = fma(h[g].a, v, acc[sl[g]]);
+            wave_sync();
+        }
+    }
+}
+
 // Long term rows go step by step, short ones in flattened batches
 // (coefficient terms always step by step).
 __device__ __forceinline__ bool use_per_term(int src, const Chunk& c)
@@ -1017,10 +1059,16 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
         const bool pre = have_first && t0 == tb;
         const Chunk c = pre ? first : load_chunk(P, src, r, t0, te);
         if (use_per_term(src, c)) {
-            if (src == kSrcProducts)
+            if (kAccum && c.maxlen <= kWave) {
+                if (src == kSrcProducts)
+                    short_group_pass<kSrcProducts>(P, r, t0, c, lo, guard, bmp, acc);
+                else
+                    short_group_pass<kSrcCoefs>(P, r, t0, c, lo, guard, bmp, acc);
+            } else if (src == kSrcProducts) {
                 per_term_pass<kSrcProducts, kAccum, kGlobal>(P, r, t0, c, lo, guard, bytes, bmp, acc);
-            else
+            } else {
                 per_term_pass<kSrcCoefs, kAccum, kGlobal>(P, r, t0, c, lo, guard, bytes, bmp, acc);
+            }
         } else {
             if (!pre) stage_chunk(c, st);
             for (int32_t q0 = 0; q0 < c.total; q0 += kWave * kU) {
