@@ -86,14 +86,13 @@ struct DevBuf {
 struct SlackMatrix {
     int64_t n = 0;
     int64_t cap = 0;
-    DevBuf off, end, span, amax, col, val, sw, nw;
+    DevBuf off, end, info, col, val, sw, nw;
     fps_status ensure_rows(int64_t nn)
     {
         n = nn;
         FPS_TRY(off.ensure(sizeof(int64_t) * (size_t)(nn + 1)));
         FPS_TRY(end.ensure(sizeof(int64_t) * (size_t)std::max<int64_t>(nn, 1)));
-        FPS_TRY(span.ensure(sizeof(int2) * (size_t)std::max<int64_t>(nn, 1)));
-        FPS_TRY(amax.ensure(sizeof(double) * (size_t)std::max<int64_t>(nn, 1)));
+        FPS_TRY(info.ensure(sizeof(RowInfo) * (size_t)std::max<int64_t>(nn, 1)));
         FPS_TRY(nw.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nn, 1)));
         return FPS_OK;
     }
@@ -109,13 +108,13 @@ struct SlackMatrix {
     }
     MatView view() const
     {
-        return MatView{off.as<int64_t>(), end.as<int64_t>(), col.as<int32_t>(), val.as<double>(), span.as<int2>(),
-                       amax.as<double>(), sw.as<uint2>(), nw.as<int32_t>()};
+        return MatView{off.as<int64_t>(), end.as<int64_t>(), col.as<int32_t>(), val.as<double>(), info.as<RowInfo>(),
+                       sw.as<uint2>(), nw.as<int32_t>()};
     }
     OutView out() const
     {
-        return OutView{off.as<int64_t>(), end.as<int64_t>(), col.as<int32_t>(), val.as<double>(), span.as<int2>(),
-                       amax.as<double>(), sw.as<uint2>(), nw.as<int32_t>(), cap};
+        return OutView{off.as<int64_t>(), end.as<int64_t>(), col.as<int32_t>(), val.as<double>(), info.as<RowInfo>(),
+                       sw.as<uint2>(), nw.as<int32_t>(), cap};
     }
 };
 
@@ -129,7 +128,7 @@ struct CanonMatrix {
 // Per-row workspace shared by the stages of one engine.
 struct Workspace {
     int64_t n = 0;
-    DevBuf W, lo, ub, fb, fb2, blk_pre, zspan, zamax, zsw, znw, gscratch, counters, part, dummy;
+    DevBuf W, lo, ub, fb, fb2, blk_pre, zinfo, zsw, znw, gscratch, counters, part, dummy;
     int64_t g_words = 0, g_cap = 0, g_stride = 0, g_off_acc = 0, g_off_ebuf = 0;
     int64_t part_stride = 0;
     int32_t g_slots = 0;
@@ -148,8 +147,7 @@ struct Workspace {
         FPS_TRY(blk_pre.ensure(sizeof(int64_t) * (size_t)(std::max({analyze_blocks(kModeProduct, nn),
                                                                     analyze_blocks(kModeSum, nn),
                                                                     offset_blocks(nn)}) + 1)));
-        FPS_TRY(zspan.ensure(sizeof(int2) * rows));
-        FPS_TRY(zamax.ensure(sizeof(double) * rows));
+        FPS_TRY(zinfo.ensure(sizeof(RowInfo) * rows));
         FPS_TRY(znw.ensure(sizeof(int32_t) * rows));
         FPS_TRY(counters.ensure(sizeof(StageCounters) * (size_t)stages));
         FPS_TRY(dummy.ensure(128 * (sizeof(int32_t) + sizeof(double))));
@@ -444,7 +442,7 @@ struct Engine {
             HIP_TRY(launch_fill_u64(cs, 2 * n + 3, 0ull, s));
             const Alg1Params pr{eps_g, target, scale, max_iter, 0};
             HIP_TRY(launch_alg1_device(out.off.as<int64_t>(), out.end.as<int64_t>(), out.col.as<int32_t>(),
-                                       out.val.as<double>(), out.span.as<int2>(), out.amax.as<double>(),
+                                       out.val.as<double>(), out.info.as<RowInfo>(),
                                        out.sw.as<uint2>(), out.nw.as<int32_t>(), n, pr,
                                        device_iters, alg1_state(idx),
                                        cs, part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, ctr(idx), s));
@@ -470,7 +468,7 @@ struct Engine {
         if (c > target)
             return set_error(FPS_ERR_CAPACITY, "Algorithm 1 did not reach its target within %d iterations", max_iter);
         HIP_TRY(launch_alg1_drop(out.off.as<int64_t>(), out.end.as<int64_t>(), out.col.as<int32_t>(),
-                                 out.val.as<double>(), out.span.as<int2>(), out.amax.as<double>(),
+                                 out.val.as<double>(), out.info.as<RowInfo>(),
                                  out.sw.as<uint2>(), out.nw.as<int32_t>(), n, t,
                                  part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, s));
         // the drop pass recounted every row, including those of the device-memory kernel
@@ -676,11 +674,11 @@ fps_status series_degree(const double* a, int L, const double* z, double eps_tol
     return FPS_OK;
 }
 
-// View of a canonical CSR for the kernels, with row info in (span, amax) and
-// its structure words in (sw, nw).
-MatView canon_view(const fps_csr_view* v, const int2* span, const double* amax, const uint2* sw, const int32_t* nw)
+// View of a canonical CSR for the kernels, with its row summaries and
+// structure words.
+MatView canon_view(const fps_csr_view* v, const RowInfo* info, const uint2* sw, const int32_t* nw)
 {
-    return MatView{v->row_ptr, v->row_ptr + 1, v->col, v->val, span, amax, sw, nw};
+    return MatView{v->row_ptr, v->row_ptr + 1, v->col, v->val, info, sw, nw};
 }
 
 }  // namespace
@@ -746,8 +744,7 @@ struct fps_plan_s {
                 T->end[t] = nullptr;
                 T->col[t] = nullptr;
                 T->val[t] = nullptr;
-                T->span[t] = nullptr;
-                T->amax[t] = nullptr;
+                T->info[t] = nullptr;
                 T->sw[t] = nullptr;
                 T->nw[t] = nullptr;
             } else {
@@ -756,8 +753,7 @@ struct fps_plan_s {
                 T->end[t] = v.end;
                 T->col[t] = v.col;
                 T->val[t] = v.val;
-                T->span[t] = v.span;
-                T->amax[t] = v.amax;
+                T->info[t] = v.info;
                 T->sw[t] = v.sw;
                 T->nw[t] = v.nw;
             }
@@ -782,13 +778,12 @@ struct fps_plan_s {
         n_stages = 0;
         HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(eng.ws.counters.p),
                                 (int64_t)(sizeof(StageCounters) / 8) * eng.ws.max_stages, 0ull, s));
-        int2* zspan = eng.ws.zspan.as<int2>();
-        double* zamax = eng.ws.zamax.as<double>();
+        RowInfo* zinfo = eng.ws.zinfo.as<RowInfo>();
         FPS_TRY(eng.ws.zsw.ensure(sizeof(uint2) * (size_t)std::max<int64_t>(Z.nnz, 1)));
         uint2* zsw = eng.ws.zsw.as<uint2>();
         int32_t* znw = eng.ws.znw.as<int32_t>();
-        HIP_TRY(launch_rowinfo_csr(Z.row_ptr, Z.col, Z.val, n, zspan, zamax, zsw, znw, s));
-        const MatView zv = canon_view(&Z, zspan, zamax, zsw, znw);
+        HIP_TRY(launch_rowinfo_csr(Z.row_ptr, Z.col, Z.val, n, zinfo, zsw, znw, s));
+        const MatView zv = canon_view(&Z, zinfo, zsw, znw);
         const double skip_tau = (flags & FPS_FLAG_NO_SKIP) || tau <= 0.0 ? 0.0 : tau * (1.0 - 1e-6);
 
         const int nst = stage_count();
@@ -1234,30 +1229,28 @@ fps_status fps_spgemm(fps_matrix* out, const fps_csr_view* A, const fps_csr_view
     // row info and structure words of each operand
     const fps_csr_view* ops[3] = {A, B, E};
     DevBuf info[3], words[3];
-    int2* sp[3] = {};
-    double* am[3] = {};
+    RowInfo* ri[3] = {};
     uint2* sw[3] = {};
     int32_t* nw[3] = {};
-    const size_t per = (sizeof(int2) + sizeof(double) + sizeof(int32_t)) * (size_t)n;
+    const size_t per = (sizeof(RowInfo) + sizeof(int32_t)) * (size_t)n;
     for (int i = 0; i < 3; ++i) {
         if (!ops[i]) continue;
         FPS_TRY(info[i].ensure(per));
         FPS_TRY(words[i].ensure(sizeof(uint2) * (size_t)std::max<int64_t>(ops[i]->nnz, 1)));
-        sp[i] = info[i].as<int2>();
-        am[i] = reinterpret_cast<double*>(static_cast<char*>(info[i].p) + sizeof(int2) * (size_t)n);
-        nw[i] = reinterpret_cast<int32_t*>(static_cast<char*>(info[i].p) + (sizeof(int2) + sizeof(double)) * (size_t)n);
+        ri[i] = info[i].as<RowInfo>();
+        nw[i] = reinterpret_cast<int32_t*>(static_cast<char*>(info[i].p) + sizeof(RowInfo) * (size_t)n);
         sw[i] = words[i].as<uint2>();
-        HIP_TRY(launch_rowinfo_csr(ops[i]->row_ptr, ops[i]->col, ops[i]->val, n, sp[i], am[i], sw[i], nw[i], s));
+        HIP_TRY(launch_rowinfo_csr(ops[i]->row_ptr, ops[i]->col, ops[i]->val, n, ri[i], sw[i], nw[i], s));
     }
     HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(eng.ws.counters.p), sizeof(StageCounters) / 8, 0ull, s));
     StageArgs a{};
     a.mode = kModeProduct;
     a.tau = tau;
     a.skip_tau = tau > 0.0 ? tau * (1.0 - 1e-6) : 0.0;
-    a.A = canon_view(A, sp[0], am[0], sw[0], nw[0]);
-    a.B = canon_view(B, sp[1], am[1], sw[1], nw[1]);
+    a.A = canon_view(A, ri[0], sw[0], nw[0]);
+    a.B = canon_view(B, ri[1], sw[1], nw[1]);
     a.has_e = E ? 1 : 0;
-    if (E) a.E = canon_view(E, sp[2], am[2], sw[2], nw[2]);
+    if (E) a.E = canon_view(E, ri[2], sw[2], nw[2]);
     SlackMatrix res;
     FPS_TRY(eng.run(0, a, res, s, true, nullptr));
     return finish_single(eng, res, s, out);
@@ -1284,7 +1277,8 @@ fps_status fps_axpy(fps_matrix* out, int64_t n, int32_t nterms, const double* co
     FPS_TRY(eng.init(n, 1, 0));
     DevBuf info;
     std::vector<DevBuf> words((size_t)nterms);
-    const size_t per = (sizeof(int2) + sizeof(double) + sizeof(int32_t)) * (size_t)n;
+    // per term: row summaries (16-byte aligned blocks), then word counts
+    const size_t per = ((sizeof(RowInfo) + sizeof(int32_t)) * (size_t)n + 255) / 256 * 256;
     FPS_TRY(info.ensure(per * (size_t)nterms));
     StageArgs a{};
     a.mode = kModeSum;
@@ -1297,25 +1291,22 @@ fps_status fps_axpy(fps_matrix* out, int64_t n, int32_t nterms, const double* co
             a.T.beg[t] = a.T.end[t] = nullptr;
             a.T.col[t] = nullptr;
             a.T.val[t] = nullptr;
-            a.T.span[t] = nullptr;
-            a.T.amax[t] = nullptr;
+            a.T.info[t] = nullptr;
             a.T.sw[t] = nullptr;
             a.T.nw[t] = nullptr;
             continue;
         }
         char* base = static_cast<char*>(info.p) + t * per;
-        int2* sp = reinterpret_cast<int2*>(base);
-        double* am = reinterpret_cast<double*>(base + sizeof(int2) * (size_t)n);
-        int32_t* nw = reinterpret_cast<int32_t*>(base + (sizeof(int2) + sizeof(double)) * (size_t)n);
+        RowInfo* ri = reinterpret_cast<RowInfo*>(base);
+        int32_t* nw = reinterpret_cast<int32_t*>(base + sizeof(RowInfo) * (size_t)n);
         FPS_TRY(words[(size_t)t].ensure(sizeof(uint2) * (size_t)std::max<int64_t>(terms[t].nnz, 1)));
         uint2* sw = words[(size_t)t].as<uint2>();
-        HIP_TRY(launch_rowinfo_csr(terms[t].row_ptr, terms[t].col, terms[t].val, n, sp, am, sw, nw, s));
+        HIP_TRY(launch_rowinfo_csr(terms[t].row_ptr, terms[t].col, terms[t].val, n, ri, sw, nw, s));
         a.T.beg[t] = terms[t].row_ptr;
         a.T.end[t] = terms[t].row_ptr + 1;
         a.T.col[t] = terms[t].col;
         a.T.val[t] = terms[t].val;
-        a.T.span[t] = sp;
-        a.T.amax[t] = am;
+        a.T.info[t] = ri;
         a.T.sw[t] = sw;
         a.T.nw[t] = nw;
     }

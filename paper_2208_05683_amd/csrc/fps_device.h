@@ -10,10 +10,19 @@ namespace fps {
 constexpr int kWave = 64;
 constexpr int kMaxTerms = 32;  // FPS_MAX_S + 1
 
+// Summary of a stored row for the analysis, one 16-byte load: its entries,
+// first and last column (first > last when empty), and its largest |value|
+// rounded up to float (an upper bound of every |entry|).
+struct __attribute__((aligned(16))) RowInfo {
+    int32_t len;
+    int32_t first;
+    int32_t last;
+    float amax;
+};
+
 // Row-range sparse matrix on the device.  Row r holds entries
 // [beg[r], end[r]) of col/val, columns strictly increasing.  A canonical CSR
-// is the special case end = row_ptr + 1.  span[r] = (first, last) column of
-// the row (first > last when empty); amax[r] = max |value| of the row.
+// is the special case end = row_ptr + 1.  info[r] summarises the row.
 // Structure words: sw[beg[r] .. beg[r] + nw[r]) lists the row's columns by
 // 32-column word, (column >> 5, bit (column & 31) set for each column of
 // the row in that word), words ascending; nw[r] <= entries of the row.
@@ -22,8 +31,7 @@ struct MatView {
     const int64_t* end;
     const int32_t* col;
     const double* val;
-    const int2* span;
-    const double* amax;
+    const RowInfo* info;
     const uint2* sw;
     const int32_t* nw;
 };
@@ -37,8 +45,7 @@ struct Terms {
     const int64_t* end[kMaxTerms];
     const int32_t* col[kMaxTerms];
     const double* val[kMaxTerms];
-    const int2* span[kMaxTerms];
-    const double* amax[kMaxTerms];
+    const RowInfo* info[kMaxTerms];
     const uint2* sw[kMaxTerms];
     const int32_t* nw[kMaxTerms];
 };
@@ -50,8 +57,7 @@ struct OutView {
     int64_t* end;        // n
     int32_t* col;
     double* val;
-    int2* span;
-    double* amax;
+    RowInfo* info;
     uint2* sw;    // structure words of row r at sw[off[r] ..]
     int32_t* nw;  // n: structure words of each row
     int64_t cap;  // capacity of col/val/sw
@@ -102,7 +108,7 @@ enum PartIndex : int {
 };
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 
-constexpr unsigned long long kErrColumnOutsideWindow = 1;  // span info inconsistent with data
+constexpr unsigned long long kErrColumnOutsideWindow = 1;  // row summary inconsistent with data
 constexpr unsigned long long kErrCapacity = 2;             // output total above capacity
 constexpr unsigned long long kErrBadCsr = 4;               // validation failure
 constexpr unsigned long long kErrNeedsGlobal = 8;          // a row needed the global-memory kernel that was not scheduled
@@ -164,9 +170,9 @@ struct StageArgs {
 };
 
 // ---- launch wrappers (fps_kernels.hip) ---------------------------------
-// span, amax and the structure words (sw: nnz entries, nw: n) of a canonical CSR
+// row summaries and the structure words (sw: nnz entries, nw: n) of a canonical CSR
 hipError_t launch_rowinfo_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n,
-                              int2* span, double* amax, uint2* sw, int32_t* nw, hipStream_t s);
+                              RowInfo* info, uint2* sw, int32_t* nw, hipStream_t s);
 hipError_t launch_validate_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n,
                                int64_t nnz, unsigned long long* err, hipStream_t s);
 // the analysis of a stage, then (unless a.row_stride > 0) the scan of its
@@ -199,14 +205,14 @@ int numeric_waves_per_block();
 hipError_t launch_alg1_colsum(const int64_t* beg, const int64_t* end, const int32_t* col, const double* val, int64_t n,
                               double t, double scale, unsigned long long* colsum, hipStream_t s);
 hipError_t launch_max_u64(const unsigned long long* x, int64_t n, unsigned long long* out, hipStream_t s);
-hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
+hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, RowInfo* info,
                             uint2* sw, int32_t* nw, int64_t n, double t, unsigned long long* part_kept, hipStream_t s);
 // Algorithm 1 driven on the device: `iters` iteration kernels (state in
 // st[0..1], column sums in cs[0..2n), maxima in cs[2n..2n+3), all zero on
 // entry), then the final update and the drop; the final record goes to st[2];
 // a stage that has not converged by then keeps its entries and raises
 // kErrAlg1Pending in ctr->errors.
-hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
+hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, RowInfo* info,
                               uint2* sw, int32_t* nw, int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
                               unsigned long long* part_kept, StageCounters* ctr, hipStream_t s);
 int numeric_global_blocks(int slots);

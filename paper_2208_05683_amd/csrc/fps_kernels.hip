@@ -313,13 +313,35 @@ struct WordBuilder {
     }
 };
 
+// Row summary (a rounded-up float keeps amax an upper bound).
+__device__ __forceinline__ RowInfo row_info(int64_t len, int32_t first, int32_t last, double amax)
+{
+    RowInfo q;
+    q.len = (int32_t)len;
+    q.first = len > 0 ? first : 1;
+    q.last = len > 0 ? last : 0;
+    q.amax = __double2float_ru(amax);
+    return q;
+}
+
+// One 16-byte load of a row summary.
+__device__ __forceinline__ RowInfo load_info(const RowInfo* p)
+{
+    const int4 v = *reinterpret_cast<const int4*>(p);
+    RowInfo q;
+    q.len = v.x;
+    q.first = v.y;
+    q.last = v.z;
+    q.amax = __int_as_float(v.w);
+    return q;
+}
+
 // ---------------------------------------------------------------------------
-// Row information of a canonical CSR: (first, last) column, max |value| and
-// the structure words.
+// Row summaries and structure words of a canonical CSR.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_rowinfo_csr(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
-                                                        const double* __restrict__ val, int64_t n, int2* span,
-                                                        double* amax, uint2* sw, int32_t* nw)
+                                                        const double* __restrict__ val, int64_t n, RowInfo* info,
+                                                        uint2* sw, int32_t* nw)
 {
     constexpr int G = 16;
     const int64_t r = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
@@ -340,8 +362,7 @@ __global__ void __launch_bounds__(kBlock) k_rowinfo_csr(const int64_t* __restric
     const int32_t words = wb.finish();
     m = row_reduce<OpMax>(m);
     if (gl == 0) {
-        span[r] = (e > b) ? make_int2(col[b], col[e - 1]) : make_int2(1, 0);
-        amax[r] = m;
+        info[r] = row_info(e - b, e > b ? col[b] : 1, e > b ? col[e - 1] : 0, m);
         nw[r] = words;
     }
 }
@@ -378,7 +399,8 @@ __global__ void __launch_bounds__(kBlock) k_validate_csr(const int64_t* __restri
 // Analysis: window, upper bound, exact empty-row test.
 //
 // For a product row, |e_r| + sum_k |A_rk| max|B_k,:| bounds every entry of
-// (*) in exact arithmetic; the computed values exceed it by at most a
+// (*) in exact arithmetic (the row maxima are stored rounded up to float,
+// which only enlarges the bound); the computed values exceed it by at most a
 // relative (terms+2) u, far below the 1e-6 margin folded into skip_tau, so a
 // row whose bound is below skip_tau would be dropped entirely by D_tau and is
 // marked empty without computing it.
@@ -407,25 +429,24 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
         const int64_t pb = P.A.beg[r], pe = P.A.end[r];
 #pragma unroll 4
         for (int64_t p = pb + gl; p < pe; p += G) {
+            // an empty row adds nothing (len 0, amax 0); every field is
+            // used unconditionally, so the summary is one 16-byte load
             const int32_t k = P.A.col[p];
-            const int64_t len = P.B.end[k] - P.B.beg[k];
-            if (len > 0) {
-                const int2 sp = P.B.span[k];
-                lo = min(lo, sp.x);
-                hi = max(hi, sp.y);
-                prod += len;
-                bnd += fabs(P.A.val[p]) * P.B.amax[k];
-            }
+            const RowInfo q = load_info(P.B.info + k);
+            lo = min(lo, q.len > 0 ? q.first : INT_MAX);
+            hi = max(hi, q.len > 0 ? q.last : -1);
+            prod += q.len;
+            bnd += fabs(P.A.val[p]) * (double)q.amax;
         }
         int64_t elen = 0;
         double emax = 0.0;
         if (P.has_e && gl == 0) {
-            elen = P.E.end[r] - P.E.beg[r];
+            const RowInfo q = load_info(P.E.info + r);
+            elen = q.len;
             if (elen > 0) {
-                const int2 sp = P.E.span[r];
-                lo = min(lo, sp.x);
-                hi = max(hi, sp.y);
-                emax = P.E.amax[r];
+                lo = min(lo, q.first);
+                hi = max(hi, q.last);
+                emax = (double)q.amax;
             }
         }
         if (P.has_blk) {  // fused coefficient block: |block entries| <= sum_t |c_t| max|M_t[r,:]|
@@ -436,13 +457,12 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
                     elen += 1;
                     emax += fabs(P.T.coef[t]);
                 } else {
-                    const int64_t len = P.T.end[t][r] - P.T.beg[t][r];
-                    if (len > 0) {
-                        const int2 sp = P.T.span[t][r];
-                        lo = min(lo, sp.x);
-                        hi = max(hi, sp.y);
-                        elen += len;
-                        emax += fabs(P.T.coef[t]) * P.T.amax[t][r];
+                    const RowInfo q = load_info(P.T.info[t] + r);
+                    if (q.len > 0) {
+                        lo = min(lo, q.first);
+                        hi = max(hi, q.last);
+                        elen += q.len;
+                        emax += fabs(P.T.coef[t]) * (double)q.amax;
                     }
                 }
             }
@@ -524,12 +544,11 @@ __global__ void __launch_bounds__(kBlock) k_analyze_sum(StageArgs P)
                 hi = max(hi, (int32_t)r);
                 prod += 1;
             } else {
-                const int64_t len = P.T.end[t][r] - P.T.beg[t][r];
-                if (len > 0) {
-                    const int2 sp = P.T.span[t][r];
-                    lo = min(lo, sp.x);
-                    hi = max(hi, sp.y);
-                    prod += len;
+                const RowInfo q = load_info(P.T.info[t] + r);
+                if (q.len > 0) {
+                    lo = min(lo, q.first);
+                    hi = max(hi, q.last);
+                    prod += q.len;
                 }
             }
         }
@@ -1181,8 +1200,7 @@ __device__ __forceinline__ void mark_words(const StageArgs& P, int64_t r, int32_
 __device__ __forceinline__ void empty_row(const StageArgs& P, int64_t r, int64_t o)
 {
     P.out.end[r] = o;
-    P.out.span[r] = make_int2(1, 0);
-    P.out.amax[r] = 0.0;
+    P.out.info[r] = row_info(0, 1, 0, 0.0);
     P.out.nw[r] = 0;
 }
 
@@ -1452,8 +1470,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     }
     if (l == 0) {
         P.out.end[r] = o + kept;
-        P.out.span[r] = kept ? make_int2(first, last) : make_int2(1, 0);
-        P.out.amax[r] = amx;
+        P.out.info[r] = row_info(kept, first, last, amx);
         P.out.nw[r] = nwd;
     }
     wave_sync();
@@ -1769,7 +1786,7 @@ __global__ void __launch_bounds__(kBlock) k_alg1_max(int64_t n, int i, const Alg
 // numeric kernel).
 template <bool kDevice>
 __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restrict__ beg, int64_t* end, int32_t* col,
-                                                        double* val, int2* span, double* amax, uint2* sw, int32_t* nw,
+                                                        double* val, RowInfo* info, uint2* sw, int32_t* nw,
                                                         int64_t n, double t,
                                                         unsigned long long* part_kept, Alg1Params pr, int iters,
                                                         Alg1State* st, const unsigned long long* cs,
@@ -1831,8 +1848,7 @@ __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restric
         const int32_t words = wb.finish();
         if (l == 0) {
             end[r] = b + kept;
-            span[r] = kept ? make_int2(first, last) : make_int2(1, 0);
-            amax[r] = amx;
+            info[r] = row_info(kept, first, last, amx);
             nw[r] = words;
         }
     }
@@ -1851,12 +1867,12 @@ inline unsigned blocks_for(int64_t threads) { return (unsigned)((threads + kBloc
 
 // ---- launch wrappers -------------------------------------------------------
 
-hipError_t launch_rowinfo_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n, int2* span,
-                              double* amax, uint2* sw, int32_t* nw, hipStream_t s)
+hipError_t launch_rowinfo_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n, RowInfo* info,
+                              uint2* sw, int32_t* nw, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rowinfo_csr, dim3(blocks_for(n * 16)), dim3(kBlock), 0, s, row_ptr, col, val, n, span, amax,
-                       sw, nw);
+    hipLaunchKernelGGL(k_rowinfo_csr, dim3(blocks_for(n * 16)), dim3(kBlock), 0, s, row_ptr, col, val, n, info, sw,
+                       nw);
     return hipGetLastError();
 }
 
@@ -1969,17 +1985,17 @@ hipError_t launch_max_u64(const unsigned long long* x, int64_t n, unsigned long 
     return hipGetLastError();
 }
 
-hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
-                            uint2* sw, int32_t* nw, int64_t n, double t, unsigned long long* part_kept, hipStream_t s)
+hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, RowInfo* info, uint2* sw,
+                            int32_t* nw, int64_t n, double t, unsigned long long* part_kept, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_alg1_drop_t<false>, dim3((unsigned)numeric_blocks(n)), dim3(kBlock), 0, s, beg, end, col, val,
-                       span, amax, sw, nw, n, t, part_kept, Alg1Params{}, 0, (Alg1State*)nullptr,
+                       info, sw, nw, n, t, part_kept, Alg1Params{}, 0, (Alg1State*)nullptr,
                        (const unsigned long long*)nullptr, (StageCounters*)nullptr);
     return hipGetLastError();
 }
 
-hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, int2* span, double* amax,
+hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, RowInfo* info,
                               uint2* sw, int32_t* nw, int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
                               unsigned long long* part_kept, StageCounters* ctr, hipStream_t s)
 {
@@ -1992,7 +2008,7 @@ hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, do
                            (const int64_t*)end, (const int32_t*)col, (const double*)val, n, pr, i, st, cs);
         hipLaunchKernelGGL(k_alg1_max, dim3(max_blocks), dim3(kBlock), 0, s, n, i, (const Alg1State*)st, cs);
     }
-    hipLaunchKernelGGL(k_alg1_drop_t<true>, dim3(blocks), dim3(kBlock), 0, s, beg, end, col, val, span, amax, sw, nw,
+    hipLaunchKernelGGL(k_alg1_drop_t<true>, dim3(blocks), dim3(kBlock), 0, s, beg, end, col, val, info, sw, nw,
                        n, 0.0,
                        part_kept, pr, iters, st, (const unsigned long long*)cs, ctr);
     return hipGetLastError();
