@@ -337,12 +337,14 @@ struct Engine {
         a.scan_shift = analyze_shift(a.mode);
         const bool sizing = size || learned[(size_t)idx] < 0;
         // After sizing, rows get a fixed stride (the largest structural row
-        // seen, rounded up to 16 entries) when that takes no more room than
-        // the scanned upper bounds: no scan, and the rows lie close together.
+        // seen, rounded up to 16 entries, at least 16) when that takes no more
+        // room than the scanned upper bounds, or when every row was empty: no
+        // scan, and the rows lie close together.
         a.row_stride = 0;
         if (!sizing) {
-            const int64_t stride = (learned_ns[(size_t)idx] + 15) / 16 * 16;
-            if (stride > 0 && stride <= learned[(size_t)idx] / std::max<int64_t>(n, 1)) a.row_stride = stride;
+            const int64_t ns_max = learned_ns[(size_t)idx];
+            const int64_t stride = std::max<int64_t>(16, (ns_max + 15) / 16 * 16);
+            if (ns_max == 0 || stride <= learned[(size_t)idx] / std::max<int64_t>(n, 1)) a.row_stride = stride;
         }
         FPS_TRY(out.ensure_cap(a.row_stride > 0 ? a.row_stride * n : std::max<int64_t>(learned[(size_t)idx], 0)));
         a.out = out.out();  // the analysis writes the row offsets (out.off)
