@@ -1056,6 +1056,66 @@ __device__ __forceinline__ void short_group_pass(const StageArgs& P, int64_t r, 
     }
 }
 
+// Short product term rows (at most kPackedMax entries) packed over the
+// lanes: `per` terms per instruction with `wd` = the chunk's longest row
+// lanes each, so each lane knows its term without a search.  The ranks of an
+// instruction's entries come first, then one read-modify-write round per
+// term, in term order (two terms may share a column).
+constexpr int kPackedMax = 32;
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src)
+{
+    const uint32_t lo = __shfl((uint32_t)x, src, kWave);
+    const uint32_t hi = __shfl((uint32_t)(x >> 32), src, kWave);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double shfl_f64(double x, int src)
+{
+    return __longlong_as_double((long long)shfl_u64((uint64_t)__double_as_longlong(x), src));
+}
+
+__device__ __forceinline__ void packed_pass(const StageArgs& P, const Chunk& c, int32_t lo, uint32_t guard,
+                                            const uint2* bmp, double* acc)
+{
+    const int l = lane();
+    const int32_t wd = max(c.maxlen, 1);
+    const int32_t per = kWave / wd;
+    const int32_t sub = l / wd, idx = l - sub * wd;
+    const bool lane_on = sub < per;
+    const uint2* bw = bmp - (lo >> 5);
+    const int32_t gcol = lo + (int32_t)guard;
+    // entry idx of the term held by lane ti of the chunk
+    auto fetch = [&](int32_t ti, bool* ok, double* a, int32_t* cl, double* v) {
+        const int src = min(ti, kChunk - 1);
+        const uint64_t beg = shfl_u64((uint64_t)c.beg, src);
+        const int32_t len = __shfl(c.len, src, kWave);
+        *a = shfl_f64(c.a, src);
+        *ok = lane_on && ti < c.nterms && idx < len;
+        const int64_t e = *ok ? (int64_t)beg + idx : 0;
+        *cl = *ok ? P.B.col[e] : gcol;
+        *v = *ok ? P.B.val[e] : 0.0;
+    };
+    for (int32_t i0 = 0; i0 < c.nterms; i0 += 2 * per) {
+        bool ok0, ok1;
+        double a0, a1, v0, v1;
+        int32_t c0, c1;
+        fetch(i0 + sub, &ok0, &a0, &c0, &v0);
+        fetch(i0 + per + sub, &ok1, &a1, &c1, &v1);
+        const uint32_t s0 = rank_col(bw, c0), s1 = rank_col(bw, c1);
+        const int32_t n0 = min(per, c.nterms - i0);
+        for (int32_t j = 0; j < n0; ++j) {
+            if (ok0 && sub == j) acc[s0] = fma(a0, v0, acc[s0]);
+            wave_sync();
+        }
+        const int32_t n1 = min(per, c.nterms - i0 - per);
+        for (int32_t j = 0; j < n1; ++j) {
+            if (ok1 && sub == j) acc[s1] = fma(a1, v1, acc[s1]);
+            wave_sync();
+        }
+    }
+}
+
 // Long term rows go step by step, short ones in flattened batches
 // (coefficient terms always step by step).
 __device__ __forceinline__ bool use_per_term(int src, const Chunk& c)
@@ -1088,6 +1148,8 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
             } else {
                 per_term_pass<kSrcCoefs, kAccum, kGlobal>(P, r, t0, c, lo, guard, bytes, bmp, acc);
             }
+        } else if (kAccum && src == kSrcProducts && c.maxlen <= kPackedMax) {
+            packed_pass(P, c, lo, guard, bmp, acc);
         } else {
             if (!pre) stage_chunk(c, st);
             for (int32_t q0 = 0; q0 < c.total; q0 += kWave * kU) {
@@ -1109,13 +1171,6 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
 // with `wd` lanes each, wd being the chunk's largest word count; term rows of
 // more than 64 words go 64 words per step.  A word outside the window lands
 // in the guard word.
-
-__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, int src)
-{
-    const uint32_t lo = __shfl((uint32_t)x, src, kWave);
-    const uint32_t hi = __shfl((uint32_t)(x >> 32), src, kWave);
-    return ((uint64_t)hi << 32) | lo;
-}
 
 // `first`, if given, is the chunk at the first term, already loaded.
 template <int SRC>
