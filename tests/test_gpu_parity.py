@@ -221,6 +221,73 @@ def test_stage_long_and_wide_rows():
         assert np.diff(want.row_ptr)[0] > 512 or tau > 0
 
 
+def _rows_with_lengths(n, lengths, rng, half_window):
+    """Row k holds lengths[k] distinct columns within k +- half_window, N(0, 1) values."""
+    import scipy.sparse as sp
+
+    rows, cols = [], []
+    for k, length in enumerate(lengths):
+        lo, hi = max(0, k - half_window), min(n, k + half_window + 1)
+        c = rng.choice(np.arange(lo, hi), min(length, hi - lo), replace=False)
+        rows += [k] * len(c)
+        cols += [int(x) for x in c]
+    return G._from_scipy(sp.coo_matrix((rng.standard_normal(len(rows)), (rows, cols)), shape=(n, n)))
+
+
+def test_stage_term_row_length_boundaries():
+    """Chunks whose term rows sit on the boundaries between the ways a chunk
+    is read: longest row 32 / 33 with short rows on average (packed over the
+    lanes / flattened batches), 64 / 65 (one load per term / two halves),
+    129 (a second 128-entry step), six / seven and seventy terms per row."""
+    import scipy.sparse as sp
+
+    n = 2400
+    rng = np.random.default_rng(77)
+    cycle = [1, 3, 8, 31, 32, 33, 16, 40, 63, 64, 65, 129]
+    Bm = _rows_with_lengths(n, [cycle[k % 12] for k in range(n)], rng, 600)
+
+    def near(r, length, count):
+        # rows k within r +- 300 whose B row has the given length
+        idx = cycle.index(length)
+        ks = [k for k in range(max(0, r - 300), min(n, r + 301)) if k % 12 == idx]
+        return [int(x) for x in rng.choice(ks, min(count, len(ks)), replace=False)]
+
+    plans = [
+        lambda r: near(r, 1, 4) + near(r, 3, 3) + near(r, 8, 3) + near(r, 32, 1),   # longest 32, short on average
+        lambda r: near(r, 1, 4) + near(r, 3, 3) + near(r, 8, 3) + near(r, 33, 1),   # longest 33
+        lambda r: near(r, 16, 2) + near(r, 40, 2) + near(r, 63, 2) + near(r, 64, 1),  # 7 terms, longest 64
+        lambda r: near(r, 16, 2) + near(r, 40, 2) + near(r, 64, 2) + near(r, 65, 1),  # longest 65
+        lambda r: near(r, 129, 5),                                                  # 128-entry steps
+        lambda r: near(r, 1, 25) + near(r, 3, 25) + near(r, 8, 20),                 # 70 terms: two chunks
+        lambda r: near(r, 31, 3) + near(r, 32, 3),                                  # two rows per instruction
+        lambda r: near(r, 1, 1),
+    ]
+    rows, cols = [], []
+    for r in range(n):
+        ks = sorted(set(plans[r % len(plans)](r)))
+        rows += [r] * len(ks)
+        cols += ks
+    A = G._from_scipy(sp.coo_matrix((rng.standard_normal(len(rows)), (rows, cols)), shape=(n, n)))
+    for tau in (0.0, 0.5):
+        _stage_spgemm(A, Bm, None, tau, f"length boundaries tau {tau}")
+
+
+def test_stage_coefficient_length_boundaries():
+    """Coefficient sums mixing the identity with rows of 1, 32, 64, 65 and 129
+    entries (one load per term, two halves, a second step)."""
+    from paper_2208_05683_amd import api
+
+    n = 1500
+    rng = np.random.default_rng(78)
+    mats = [None] + [_rows_with_lengths(n, [L] * n, rng, 400) for L in (1, 32, 64, 65, 129, 3)]
+    coefs = [float(x) for x in rng.standard_normal(len(mats))]
+    for sel in (slice(0, 4), slice(0, 7), slice(1, 7)):
+        want, _ = O.axpy(n, coefs[sel], mats[sel])
+        got = download(api.axpy(n, coefs[sel], [None if m is None else upload(m) for m in mats[sel]]))
+        check_canonical(got)
+        assert_same_csr(got, want, f"coefficient lengths {sel}")
+
+
 def test_stage_all_dropped_rows_and_empty_rows():
     Z = G.random_banded(3000, 4, 0.6, 1.0, seed=3)
     got, want, st = _stage_spgemm(Z, Z, None, 1e3, "all dropped")
