@@ -1262,14 +1262,16 @@ __device__ __forceinline__ void empty_row(const StageArgs& P, int64_t r, int64_t
 // Computes output row r.  Returns false (with nothing written) if the row
 // needs more workspace than max_words / cap provide.
 //
-// Phases: structure bitmap of the row's column window; prefix counts so that
-// rank(column) is the column's slot in a dense accumulator kept in column
-// order; the main terms accumulated in order and parked (registers in the
-// shared-memory kernel, `ebuf` in the device-memory kernel); the extra part
-// (fused block terms or E) accumulated on its own; x = extra + main; the drop
-// test and a sorted, coalesced write-out.  Rows whose main terms are at most
-// 64 short-row products keep them in registers from the structure pass to
-// the accumulation.
+// Phases: structure bitmap of the row's column window (the term rows'
+// structure words ORed in; the device-memory kernel marks entries in a byte
+// map); prefix counts so that rank(column) is the column's slot in a dense
+// accumulator kept in column order; the main terms accumulated in order and
+// parked (registers in the shared-memory kernel, `ebuf` in the device-memory
+// kernel); the extra part (fused block terms or E) accumulated on its own;
+// x = extra + main; the drop test and a sorted, coalesced write-out; the
+// row's summary and structure words.  Rows whose main terms are at most 64
+// short-row products keep them in registers from the structure pass to the
+// accumulation.
 // kGlobal: the structure in a device-memory byte map, bitmap and accumulator
 // in device memory.  kDevPark: the main part parked in `ebuf` (device memory)
 // rather than in kParked registers per lane.
