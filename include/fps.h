@@ -204,8 +204,9 @@ fps_status fps_plan_create_ex(fps_plan *out, const fps_csr_view *Z, const double
  * column and at most 5 iterations, A = Z^p applied as p products with Z (A x)
  * or Z^T (A^T s): start vector ones/n, sign(0) = +1, among equal largest
  * |(A^T s)_i| the smallest i.  Every product accumulates in ascending index
- * order with fused multiply-adds from +0 and ||y||_1 adds in ascending order,
- * so the result is reproducible bit for bit.  *est <= ||Z^p||_1 and *est =
+ * order with fused multiply-adds from +0, and ||y||_1 adds |y_i| in ascending
+ * order within blocks of 64 consecutive entries, then the block sums in
+ * ascending order, so the result is reproducible bit for bit.  *est <= ||Z^p||_1 and *est =
  * ||Z^p v||_1 for v = e_{*ind} (*ind = -1: the start vector won).  Z: device
  * CSR view, checked unless FPS_FLAG_NO_VALIDATE; est, ind, iters: HOST
  * pointers (ind, iters may be NULL).  p >= 0.  Synchronises `stream`.

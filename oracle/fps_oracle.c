@@ -766,11 +766,18 @@ static void spmv_t(const orc_csr *Z, const double *x, double *y)
         for (int64_t p = Z->row_ptr[r]; p < Z->row_ptr[r + 1]; ++p) y[Z->col[p]] = fma(Z->val[p], x[r], y[Z->col[p]]);
 }
 
-/* ||y||_1 with the terms added in ascending index order. */
+/* ||y||_1 in a fixed two-level order: |y_i| added in ascending index order
+ * within each block of 64 consecutive entries (the last block may be
+ * shorter), then the block sums added in ascending block order. */
 static double vec_norm1(const double *y, int64_t n)
 {
     double s = 0.0;
-    for (int64_t i = 0; i < n; ++i) s = s + fabs(y[i]);
+    for (int64_t b = 0; b < n; b += 64) {
+        double t = 0.0;
+        const int64_t e = (b + 64 < n) ? b + 64 : n;
+        for (int64_t i = b; i < e; ++i) t = t + fabs(y[i]);
+        s = s + t;
+    }
     return s;
 }
 

@@ -535,7 +535,7 @@ fps_status validate_on_device(const fps_csr_view* v, const char* what, hipStream
 // rows of Z in ascending order, and the vectors of the iteration.
 struct EstWork {
     int64_t n = 0;
-    DevBuf trp, trow, tval, trow_tmp, tval_tmp, cnt, x, y, t0, t1, s, s_old, zt, small;
+    DevBuf trp, trow, tval, trow_tmp, tval_tmp, cnt, x, y, t0, t1, s, s_old, zt, small, bsum;
 
     fps_status init(const fps_csr_view* Z, hipStream_t st)
     {
@@ -549,6 +549,7 @@ struct EstWork {
         FPS_TRY(cnt.ensure(sizeof(unsigned long long) * nn));
         for (DevBuf* b : {&x, &y, &t0, &t1, &s, &s_old, &zt}) FPS_TRY(b->ensure(sizeof(double) * nn));
         FPS_TRY(small.ensure(64));
+        FPS_TRY(bsum.ensure(sizeof(double) * (nn / 64 + 1)));
         HIP_TRY(launch_transpose(Z->row_ptr, Z->col, Z->val, n, Z->nnz, cnt.as<unsigned long long>(),
                                  trp.as<int64_t>(), trow_tmp.as<int32_t>(), tval_tmp.as<double>(), trow.as<int32_t>(),
                                  tval.as<double>(), st));
@@ -593,7 +594,7 @@ struct EstWork {
         int k = 0;
         for (k = 1;; ++k) {
             FPS_TRY(apply(Z, p, false, xv, yv, st));
-            HIP_TRY(launch_abs_sum_ordered(yv, n, est_d, st));
+            HIP_TRY(launch_abs_sum_ordered(yv, n, bsum.as<double>(), est_d, st));
             HIP_TRY(hipMemcpyAsync(&est, est_d, sizeof(double), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             if (est > est_old || k == 2) ind_best = ind;
