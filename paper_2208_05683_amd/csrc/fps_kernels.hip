@@ -1116,8 +1116,13 @@ __device__ __forceinline__ void packed_pass(const StageArgs& P, const Chunk& c, 
     }
 }
 
-// Long term rows go step by step, short ones in flattened batches
-// (coefficient terms always step by step).
+// How the accumulation reads a chunk: term rows of 16 entries or more on
+// average (coefficient terms always) go term by term, six at a time when they
+// all fit one wavefront, otherwise three at a time (coefficient terms two) in
+// steps of 128 entries; shorter product rows are packed over the lanes when
+// the longest has at most kPackedMax entries, else read in flattened batches.
+// The structure pass reads structure words instead (mark_words), except in
+// the device-memory kernel.
 __device__ __forceinline__ bool use_per_term(int src, const Chunk& c)
 {
     return src == kSrcCoefs || c.total >= 16 * c.nterms;
