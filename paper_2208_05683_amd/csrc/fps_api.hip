@@ -458,7 +458,7 @@ struct Engine {
             t = eps_g / m;
             HIP_TRY(launch_fill_u64(cs, n + 1, 0ull, s));
             HIP_TRY(launch_alg1_colsum(out.off.as<int64_t>(), out.end.as<int64_t>(), out.col.as<int32_t>(),
-                                       out.val.as<double>(), n, t, scale, cs, s));
+                                       out.val.as<double>(), out.info.as<RowInfo>(), n, t, scale, cs, s));
             HIP_TRY(launch_max_u64(cs, n, mx, s));
             unsigned long long h = 0;
             HIP_TRY(hipMemcpyAsync(&h, mx, sizeof(h), hipMemcpyDeviceToHost, s));

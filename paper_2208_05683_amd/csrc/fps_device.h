@@ -202,8 +202,9 @@ int64_t offset_blocks(int64_t n);
 hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long long v, hipStream_t s);
 int numeric_waves_per_block();
 // Algorithm 1 helpers (adaptive filter)
-hipError_t launch_alg1_colsum(const int64_t* beg, const int64_t* end, const int32_t* col, const double* val, int64_t n,
-                              double t, double scale, unsigned long long* colsum, hipStream_t s);
+hipError_t launch_alg1_colsum(const int64_t* beg, const int64_t* end, const int32_t* col, const double* val,
+                              const RowInfo* info, int64_t n, double t, double scale, unsigned long long* colsum,
+                              hipStream_t s);
 hipError_t launch_max_u64(const unsigned long long* x, int64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, RowInfo* info,
                             uint2* sw, int32_t* nw, int64_t n, double t, unsigned long long* part_kept, hipStream_t s);

@@ -1739,17 +1739,76 @@ __global__ void __launch_bounds__(kBlock) k_fill_u64(unsigned long long* p, int6
 // 64-bit integers (so the result does not depend on the order of the atomic
 // additions), scale = 2^40 / eps_g.
 // ---------------------------------------------------------------------------
+constexpr int kAlg1Rows = 64;    // rows per block of the candidate column sums
+constexpr int kAlg1Cols = 6144;  // widest column window summed in shared memory
+static_assert(kBlock >= kAlg1Rows, "one thread per row reads the row summaries");
+
+// Candidate column sums of rows [blockIdx.x * kAlg1Rows, ...): every entry
+// with 0 < |x| <= t adds ceil(|x| scale) to sums[col].  When the block's rows
+// span at most kAlg1Cols columns (from their summaries), the block sums in
+// shared memory first and adds each column to the device array once; the
+// integer sums do not depend on the order of the additions.
+__device__ __forceinline__ void alg1_block_colsums(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
+                                                   const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                   const RowInfo* __restrict__ info, int64_t n, double t,
+                                                   double scale, unsigned long long* sums)
+{
+    __shared__ unsigned long long sh[kAlg1Cols];
+    __shared__ int32_t wlo[kWavesPerBlock], whi[kWavesPerBlock];
+    const int wv = threadIdx.x / kWave;
+    const int64_t r0 = (int64_t)blockIdx.x * kAlg1Rows;
+    const int64_t r1 = min(r0 + (int64_t)kAlg1Rows, n);
+    int32_t f = INT_MAX, g = -1;
+    if (r0 + (int64_t)threadIdx.x < r1) {
+        const RowInfo q = load_info(info + r0 + threadIdx.x);
+        if (q.len > 0) {
+            f = q.first;
+            g = q.last;
+        }
+    }
+    f = wave_reduce<OpMin>(f);
+    g = wave_reduce<OpMax>(g);
+    if (lane() == 0) {
+        wlo[wv] = f;
+        whi[wv] = g;
+    }
+    __syncthreads();
+    int32_t lo = INT_MAX, hi = -1;
+    for (int k = 0; k < kWavesPerBlock; ++k) {
+        lo = min(lo, wlo[k]);
+        hi = max(hi, whi[k]);
+    }
+    const bool local = hi >= lo && hi - lo < kAlg1Cols;  // uniform over the block
+    if (local)
+        for (int j = threadIdx.x; j <= hi - lo; j += kBlock) sh[j] = 0ull;
+    __syncthreads();
+    for (int64_t r = r0 + wv; r < r1; r += kWavesPerBlock) {
+        for (int64_t p = beg[r] + lane(); p < end[r]; p += kWave) {
+            const double a = fabs(val[p]);
+            if (a > 0.0 && a <= t) {
+                const unsigned long long v = (unsigned long long)ceil(a * scale);
+                const int32_t c = col[p];
+                // (a column outside the summaries' window goes to the device array)
+                if (local && (uint32_t)(c - lo) <= (uint32_t)(hi - lo))
+                    atomicAdd(&sh[c - lo], v);
+                else
+                    atomicAdd(&sums[c], v);
+            }
+        }
+    }
+    if (local) {
+        __syncthreads();
+        for (int j = threadIdx.x; j <= hi - lo; j += kBlock)
+            if (sh[j] != 0ull) atomicAdd(&sums[lo + j], sh[j]);
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_alg1_colsum(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
                                                         const int32_t* __restrict__ col,
-                                                        const double* __restrict__ val, int64_t n, double t,
-                                                        double scale, unsigned long long* colsum)
+                                                        const double* __restrict__ val, const RowInfo* info,
+                                                        int64_t n, double t, double scale, unsigned long long* colsum)
 {
-    const int64_t r = xcd_logical_block() * kWavesPerBlock + threadIdx.x / kWave;
-    if (r >= n) return;
-    for (int64_t p = beg[r] + lane(); p < end[r]; p += kWave) {
-        const double a = fabs(val[p]);
-        if (a > 0.0 && a <= t) atomicAdd(&colsum[col[p]], (unsigned long long)ceil(a * scale));
-    }
+    alg1_block_colsums(beg, end, col, val, info, n, t, scale, colsum);
 }
 
 __global__ void __launch_bounds__(kBlock) k_max_u64(const unsigned long long* __restrict__ x, int64_t n,
@@ -1803,8 +1862,8 @@ __device__ __forceinline__ Alg1State alg1_state(const Alg1Params& pr, int i, con
 
 __global__ void __launch_bounds__(kBlock) k_alg1_iter(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
                                                       const int32_t* __restrict__ col,
-                                                      const double* __restrict__ val, int64_t n, Alg1Params pr, int i,
-                                                      Alg1State* st, unsigned long long* cs)
+                                                      const double* __restrict__ val, const RowInfo* info, int64_t n,
+                                                      Alg1Params pr, int i, Alg1State* st, unsigned long long* cs)
 {
     unsigned long long* mxs = cs + 2 * n;
     const Alg1State cur = alg1_state(pr, i, st, mxs);
@@ -1814,14 +1873,7 @@ __global__ void __launch_bounds__(kBlock) k_alg1_iter(const int64_t* __restrict_
     unsigned long long* next = cs + (int64_t)((i + 1) & 1) * n;
     for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n; g += nthreads) next[g] = 0ull;
     if (blockIdx.x == 0 && threadIdx.x == 0) mxs[(i + 1) % 3] = 0ull;
-    unsigned long long* sums = cs + (int64_t)(i & 1) * n;
-    const int64_t waves = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t r = xcd_logical_block() * kWavesPerBlock + threadIdx.x / kWave; r < n; r += waves) {
-        for (int64_t p = beg[r] + lane(); p < end[r]; p += kWave) {
-            const double a = fabs(val[p]);
-            if (a > 0.0 && a <= cur.t) atomicAdd(&sums[col[p]], (unsigned long long)ceil(a * pr.scale));
-        }
-    }
+    alg1_block_colsums(beg, end, col, val, info, n, cur.t, pr.scale, cs + (int64_t)(i & 1) * n);
 }
 
 __global__ void __launch_bounds__(kBlock) k_alg1_max(int64_t n, int i, const Alg1State* st, unsigned long long* cs)
@@ -2030,12 +2082,13 @@ hipError_t launch_fill_u64(unsigned long long* p, int64_t count, unsigned long l
 
 int numeric_waves_per_block() { return kWavesPerBlock; }
 
-hipError_t launch_alg1_colsum(const int64_t* beg, const int64_t* end, const int32_t* col, const double* val, int64_t n,
-                              double t, double scale, unsigned long long* colsum, hipStream_t s)
+hipError_t launch_alg1_colsum(const int64_t* beg, const int64_t* end, const int32_t* col, const double* val,
+                              const RowInfo* info, int64_t n, double t, double scale, unsigned long long* colsum,
+                              hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_alg1_colsum, dim3((unsigned)numeric_blocks(n)), dim3(kBlock), 0, s, beg, end, col, val, n, t,
-                       scale, colsum);
+    hipLaunchKernelGGL(k_alg1_colsum, dim3((unsigned)((n + kAlg1Rows - 1) / kAlg1Rows)), dim3(kBlock), 0, s, beg, end,
+                       col, val, info, n, t, scale, colsum);
     return hipGetLastError();
 }
 
@@ -2063,11 +2116,12 @@ hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, do
 {
     if (n <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)numeric_blocks(n);
-    const unsigned iter_blocks = (unsigned)std::min<int64_t>(2048, numeric_blocks(n));
+    const unsigned iter_blocks = (unsigned)((n + kAlg1Rows - 1) / kAlg1Rows);
     const unsigned max_blocks = (unsigned)std::min<int64_t>(256, (n + kBlock - 1) / kBlock);
     for (int i = 0; i < iters; ++i) {
         hipLaunchKernelGGL(k_alg1_iter, dim3(iter_blocks), dim3(kBlock), 0, s, (const int64_t*)beg,
-                           (const int64_t*)end, (const int32_t*)col, (const double*)val, n, pr, i, st, cs);
+                           (const int64_t*)end, (const int32_t*)col, (const double*)val, (const RowInfo*)info, n, pr,
+                           i, st, cs);
         hipLaunchKernelGGL(k_alg1_max, dim3(max_blocks), dim3(kBlock), 0, s, n, i, (const Alg1State*)st, cs);
     }
     hipLaunchKernelGGL(k_alg1_drop_t<true>, dim3(blocks), dim3(kBlock), 0, s, beg, end, col, val, info, sw, nw,
