@@ -313,6 +313,65 @@ struct WordBuilder {
     }
 };
 
+// The same for a whole wavefront, with the ORs of each word's bits done in
+// shared memory (`seg`: 64 words per wavefront) instead of by shuffles.
+struct WaveWordBuilder {
+    uint2* out;       // first word of the row
+    uint32_t* seg;    // this wavefront's 64 segment masks
+    int32_t n = 0;    // words written
+    uint32_t cw = 0;  // the open word
+    uint32_t cm = 0;  // its bits (0: no open word)
+
+    // Columns c of lanes [0, cnt), ascending, above the previous batch's.
+    __device__ __forceinline__ void add(int32_t c, int32_t cnt)
+    {
+        if (cnt <= 0) return;
+        const int l = lane();
+        const bool v = l < cnt;
+        const uint32_t w = (uint32_t)c >> 5;
+        const uint32_t pw = __shfl_up(w, 1, kWave);
+        const bool lead = v && (l == 0 || pw != w);
+        const unsigned long long L = __ballot(lead);
+        const int nseg = __popcll(L);
+        // segment of lane l: leaders at or below it, minus one
+        const int si = (int)lanes_below(L) + (lead ? 1 : 0) - 1;
+        if (l < nseg) seg[l] = 0u;
+        wave_sync();
+        if (v) atomicOr(&seg[si], 1u << (c & 31));
+        wave_sync();
+        const uint32_t m = lead ? seg[si] : 0u;
+        const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)w, 0);
+        const uint32_t m0 = (uint32_t)__builtin_amdgcn_readlane((int)m, 0);
+        const bool cont = cm != 0u && w0 == cw;  // the first word continues the open one
+        uint32_t om = cm;
+        if (cont) om |= m0;
+        const int first = cont ? 1 : 0;
+        if (nseg == first) {
+            cm = om;
+            return;
+        }
+        if (om != 0u) {
+            if (l == 0) out[n] = make_uint2(cw, om);
+            n += 1;
+        }
+        if (lead && si >= first && si < nseg - 1) out[n + si - first] = make_uint2(w, m);
+        n += nseg - 1 - first;
+        const int lastl = 63 - __clzll(L);
+        cw = (uint32_t)__builtin_amdgcn_readlane((int)w, lastl);
+        cm = (uint32_t)__builtin_amdgcn_readlane((int)m, lastl);
+        wave_sync();  // the next batch clears seg
+    }
+    __device__ __forceinline__ int32_t finish()
+    {
+        if (cm != 0u) {
+            if (lane() == 0) out[n] = make_uint2(cw, cm);
+            n += 1;
+            cm = 0u;
+        }
+        return n;
+    }
+};
+
 // Row summary (a rounded-up float keeps amax an upper bound).
 __device__ __forceinline__ RowInfo row_info(int64_t len, int32_t first, int32_t last, double amax)
 {
@@ -1919,6 +1978,7 @@ __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restric
         t = fin.t;
     }
     __shared__ unsigned long long kept_sh[kWavesPerBlock];
+    __shared__ uint32_t seg_sh[kWavesPerBlock][kWave];
     const int wv = threadIdx.x / kWave;
     const int l = lane();
     const int64_t blk = xcd_logical_block();
@@ -1954,7 +2014,7 @@ __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restric
         last = wave_reduce<OpMax>(last);
         // structure words of the kept columns
         wave_sync();
-        WordBuilder<kWave> wb{sw + b};
+        WaveWordBuilder wb{sw + b, seg_sh[wv]};
         for (int64_t p0 = 0; p0 < kept; p0 += kWave) {
             const int64_t p = p0 + l;
             wb.add(p < kept ? col[b + p] : 0, (int32_t)min<int64_t>(kWave, kept - p0));
