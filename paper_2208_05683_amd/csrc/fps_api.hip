@@ -448,7 +448,6 @@ struct Engine {
                                        out.sw.as<uint2>(), out.nw.as<int32_t>(), n, pr,
                                        device_iters, alg1_state(idx),
                                        cs, part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, ctr(idx), s));
-            HIP_TRY(launch_fill_u64(&ctr(idx)->kept_global, 1, 0ull, s));
             if (rec) rec->alg1_device = true;
             return FPS_OK;
         }
@@ -472,9 +471,7 @@ struct Engine {
         HIP_TRY(launch_alg1_drop(out.off.as<int64_t>(), out.end.as<int64_t>(), out.col.as<int32_t>(),
                                  out.val.as<double>(), out.info.as<RowInfo>(),
                                  out.sw.as<uint2>(), out.nw.as<int32_t>(), n, t,
-                                 part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, s));
-        // the drop pass recounted every row, including those of the device-memory kernel
-        HIP_TRY(launch_fill_u64(&ctr(idx)->kept_global, 1, 0ull, s));
+                                 part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, ctr(idx), s));
         if (rec) {
             rec->threshold = t;
             rec->dropped = c;

@@ -206,8 +206,10 @@ hipError_t launch_alg1_colsum(const int64_t* beg, const int64_t* end, const int3
                               const RowInfo* info, int64_t n, double t, double scale, unsigned long long* colsum,
                               hipStream_t s);
 hipError_t launch_max_u64(const unsigned long long* x, int64_t n, unsigned long long* out, hipStream_t s);
+// (both drops also clear ctr->kept_global: they recount every row)
 hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, RowInfo* info,
-                            uint2* sw, int32_t* nw, int64_t n, double t, unsigned long long* part_kept, hipStream_t s);
+                            uint2* sw, int32_t* nw, int64_t n, double t, unsigned long long* part_kept,
+                            StageCounters* ctr, hipStream_t s);
 // Algorithm 1 driven on the device: `iters` iteration kernels (state in
 // st[0..1], column sums in cs[0..2n), maxima in cs[2n..2n+3), all zero on
 // entry), then the final update and the drop; the final record goes to st[2];

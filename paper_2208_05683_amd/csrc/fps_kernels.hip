@@ -1977,6 +1977,9 @@ __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restric
         if (!fin.done) return;
         t = fin.t;
     }
+    // the drop recounts every row (per-block partials), including those of
+    // the fallback kernels, whose separate count is cleared
+    if (ctr != nullptr && blockIdx.x == 0 && threadIdx.x == 0) ctr->kept_global = 0ull;
     __shared__ unsigned long long kept_sh[kWavesPerBlock];
     __shared__ uint32_t seg_sh[kWavesPerBlock][kWave];
     const int wv = threadIdx.x / kWave;
@@ -2161,12 +2164,13 @@ hipError_t launch_max_u64(const unsigned long long* x, int64_t n, unsigned long 
 }
 
 hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, double* val, RowInfo* info, uint2* sw,
-                            int32_t* nw, int64_t n, double t, unsigned long long* part_kept, hipStream_t s)
+                            int32_t* nw, int64_t n, double t, unsigned long long* part_kept, StageCounters* ctr,
+                            hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_alg1_drop_t<false>, dim3((unsigned)numeric_blocks(n)), dim3(kBlock), 0, s, beg, end, col, val,
                        info, sw, nw, n, t, part_kept, Alg1Params{}, 0, (Alg1State*)nullptr,
-                       (const unsigned long long*)nullptr, (StageCounters*)nullptr);
+                       (const unsigned long long*)nullptr, ctr);
     return hipGetLastError();
 }
 
