@@ -1798,9 +1798,11 @@ __global__ void __launch_bounds__(kBlock) k_fill_u64(unsigned long long* p, int6
 // 64-bit integers (so the result does not depend on the order of the atomic
 // additions), scale = 2^40 / eps_g.
 // ---------------------------------------------------------------------------
-constexpr int kAlg1Rows = 64;    // rows per block of the candidate column sums
-constexpr int kAlg1Cols = 6144;  // widest column window summed in shared memory
-static_assert(kBlock >= kAlg1Rows, "one thread per row reads the row summaries");
+constexpr int kAlg1Rows = 32;       // rows per block of the candidate column sums
+constexpr int kAlg1Cols = 6144;     // widest column window summed in shared memory
+constexpr int kAlg1Threads = 1024;   // threads per block of the candidate column sums
+constexpr int kAlg1Waves = kAlg1Threads / kWave;
+static_assert(kAlg1Threads >= kAlg1Rows, "one thread per row reads the row summaries");
 
 // Candidate column sums of rows [blockIdx.x * kAlg1Rows, ...): every entry
 // with 0 < |x| <= t adds ceil(|x| scale) to sums[col].  When the block's rows
@@ -1813,7 +1815,7 @@ __device__ __forceinline__ void alg1_block_colsums(const int64_t* __restrict__ b
                                                    double scale, unsigned long long* sums)
 {
     __shared__ unsigned long long sh[kAlg1Cols];
-    __shared__ int32_t wlo[kWavesPerBlock], whi[kWavesPerBlock];
+    __shared__ int32_t wlo[kAlg1Waves], whi[kAlg1Waves];
     const int wv = threadIdx.x / kWave;
     const int64_t r0 = (int64_t)blockIdx.x * kAlg1Rows;
     const int64_t r1 = min(r0 + (int64_t)kAlg1Rows, n);
@@ -1833,36 +1835,43 @@ __device__ __forceinline__ void alg1_block_colsums(const int64_t* __restrict__ b
     }
     __syncthreads();
     int32_t lo = INT_MAX, hi = -1;
-    for (int k = 0; k < kWavesPerBlock; ++k) {
+    for (int k = 0; k < kAlg1Waves; ++k) {
         lo = min(lo, wlo[k]);
         hi = max(hi, whi[k]);
     }
     const bool local = hi >= lo && hi - lo < kAlg1Cols;  // uniform over the block
     if (local)
-        for (int j = threadIdx.x; j <= hi - lo; j += kBlock) sh[j] = 0ull;
+        for (int j = threadIdx.x; j <= hi - lo; j += kAlg1Threads) sh[j] = 0ull;
     __syncthreads();
-    for (int64_t r = r0 + wv; r < r1; r += kWavesPerBlock) {
-        for (int64_t p = beg[r] + lane(); p < end[r]; p += kWave) {
-            const double a = fabs(val[p]);
+    for (int64_t r = r0 + wv; r < r1; r += kAlg1Waves) {
+        auto add = [&](double a, int32_t c) {
             if (a > 0.0 && a <= t) {
                 const unsigned long long v = (unsigned long long)ceil(a * scale);
-                const int32_t c = col[p];
                 // (a column outside the summaries' window goes to the device array)
                 if (local && (uint32_t)(c - lo) <= (uint32_t)(hi - lo))
                     atomicAdd(&sh[c - lo], v);
                 else
                     atomicAdd(&sums[c], v);
             }
+        };
+        const int64_t pe = end[r];
+        int64_t p = beg[r] + lane();
+        for (; p + kWave < pe; p += 2 * kWave) {  // two entries per lane in flight
+            const double a0 = fabs(val[p]), a1 = fabs(val[p + kWave]);
+            const int32_t c0 = col[p], c1 = col[p + kWave];
+            add(a0, c0);
+            add(a1, c1);
         }
+        if (p < pe) add(fabs(val[p]), col[p]);
     }
     if (local) {
         __syncthreads();
-        for (int j = threadIdx.x; j <= hi - lo; j += kBlock)
+        for (int j = threadIdx.x; j <= hi - lo; j += kAlg1Threads)
             if (sh[j] != 0ull) atomicAdd(&sums[lo + j], sh[j]);
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_alg1_colsum(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
+__global__ void __launch_bounds__(kAlg1Threads) k_alg1_colsum(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
                                                         const int32_t* __restrict__ col,
                                                         const double* __restrict__ val, const RowInfo* info,
                                                         int64_t n, double t, double scale, unsigned long long* colsum)
@@ -1919,7 +1928,7 @@ __device__ __forceinline__ Alg1State alg1_state(const Alg1Params& pr, int i, con
     return cur;
 }
 
-__global__ void __launch_bounds__(kBlock) k_alg1_iter(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
+__global__ void __launch_bounds__(kAlg1Threads) k_alg1_iter(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
                                                       const int32_t* __restrict__ col,
                                                       const double* __restrict__ val, const RowInfo* info, int64_t n,
                                                       Alg1Params pr, int i, Alg1State* st, unsigned long long* cs)
@@ -1928,9 +1937,9 @@ __global__ void __launch_bounds__(kBlock) k_alg1_iter(const int64_t* __restrict_
     const Alg1State cur = alg1_state(pr, i, st, mxs);
     if (blockIdx.x == 0 && threadIdx.x == 0) st[i & 1] = cur;
     if (cur.done) return;
-    const int64_t nthreads = (int64_t)gridDim.x * kBlock;
+    const int64_t nthreads = (int64_t)gridDim.x * kAlg1Threads;
     unsigned long long* next = cs + (int64_t)((i + 1) & 1) * n;
-    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n; g += nthreads) next[g] = 0ull;
+    for (int64_t g = (int64_t)blockIdx.x * kAlg1Threads + threadIdx.x; g < n; g += nthreads) next[g] = 0ull;
     if (blockIdx.x == 0 && threadIdx.x == 0) mxs[(i + 1) % 3] = 0ull;
     alg1_block_colsums(beg, end, col, val, info, n, cur.t, pr.scale, cs + (int64_t)(i & 1) * n);
 }
@@ -2150,7 +2159,7 @@ hipError_t launch_alg1_colsum(const int64_t* beg, const int64_t* end, const int3
                               hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_alg1_colsum, dim3((unsigned)((n + kAlg1Rows - 1) / kAlg1Rows)), dim3(kBlock), 0, s, beg, end,
+    hipLaunchKernelGGL(k_alg1_colsum, dim3((unsigned)((n + kAlg1Rows - 1) / kAlg1Rows)), dim3(kAlg1Threads), 0, s, beg, end,
                        col, val, info, n, t, scale, colsum);
     return hipGetLastError();
 }
@@ -2183,7 +2192,7 @@ hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, do
     const unsigned iter_blocks = (unsigned)((n + kAlg1Rows - 1) / kAlg1Rows);
     const unsigned max_blocks = (unsigned)std::min<int64_t>(256, (n + kBlock - 1) / kBlock);
     for (int i = 0; i < iters; ++i) {
-        hipLaunchKernelGGL(k_alg1_iter, dim3(iter_blocks), dim3(kBlock), 0, s, (const int64_t*)beg,
+        hipLaunchKernelGGL(k_alg1_iter, dim3(iter_blocks), dim3(kAlg1Threads), 0, s, (const int64_t*)beg,
                            (const int64_t*)end, (const int32_t*)col, (const double*)val, (const RowInfo*)info, n, pr,
                            i, st, cs);
         hipLaunchKernelGGL(k_alg1_max, dim3(max_blocks), dim3(kBlock), 0, s, n, i, (const Alg1State*)st, cs);

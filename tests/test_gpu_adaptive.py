@@ -67,6 +67,26 @@ def test_adaptive_lap2d(side, eps):
     assert any(x["iters"] > 1 for x in a1)
 
 
+def test_adaptive_full_size_lap2d():
+    """The 2D Laplacian workload (200 x 200 grid, exp, m = 30, s = 6) under
+    Algorithm 1 at eps = 1e-12: the late products' rows span more columns than
+    a block's shared-memory column sums hold, so both ways of summing run."""
+    got, want, a1, gst = compare_adaptive(G.laplacian_2d(200, 2.0), G.exp_coeffs(30), 30, 6, 1e-12,
+                                          what="lap2d 200 x 200")
+    assert got.nnz == want.nnz > 10_000_000
+    assert max(x["iters"] for x in a1) >= 3
+
+
+def test_adaptive_wide_column_windows():
+    """Random columns over n = 7000: every block's rows span nearly all
+    columns, so the candidate sums go to the device array, and the late rows
+    (thousands of entries) take the device-memory kernel."""
+    Z = G.random_sparse(7000, 3.0 / 7000, 21, 0.6)
+    got, want, a1, gst = compare_adaptive(Z, G.exp_coeffs(8), 8, 3, 1e-8, what="random n=7000")
+    assert want.nnz / Z.n > 2048
+    assert any(x["iters"] > 1 for x in a1)
+
+
 def test_adaptive_banded_and_random():
     compare_adaptive(G.random_banded(3000, 4, 0.6, 1.7, seed=9), G.exp_coeffs(20), 20, 4, 1e-10, what="banded")
     rng = np.random.default_rng(3)
