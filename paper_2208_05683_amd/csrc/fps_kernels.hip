@@ -1991,6 +1991,7 @@ __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restric
     if (ctr != nullptr && blockIdx.x == 0 && threadIdx.x == 0) ctr->kept_global = 0ull;
     __shared__ unsigned long long kept_sh[kWavesPerBlock];
     __shared__ uint32_t seg_sh[kWavesPerBlock][kWave];
+    __shared__ uint32_t stage_sh[kWavesPerBlock][2 * kWave];
     const int wv = threadIdx.x / kWave;
     const int l = lane();
     const int64_t blk = xcd_logical_block();
@@ -2000,37 +2001,61 @@ __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restric
         const int64_t b = beg[r], e = end[r];
         double amx = 0.0;
         int32_t first = INT_MAX, last = -1;
+        // The kept columns are staged in order in shared memory and handed to
+        // the word builder 64 at a time.
+        WaveWordBuilder wb{sw + b, seg_sh[wv]};
+        uint32_t* stg = stage_sh[wv];
+        int32_t staged = 0;
+        int32_t c = 0;
+        double x = 0.0;
+        if (b + l < e) {
+            c = col[b + l];
+            x = val[b + l];
+        }
         for (int64_t p0 = b; p0 < e; p0 += kWave) {
             const int64_t p = p0 + l;
-            int32_t c = 0;
-            double x = 0.0;
-            bool keep = false;
-            if (p < e) {
-                c = col[p];
-                x = val[p];
-                keep = fabs(x) > t;
+            const bool keep = p < e && fabs(x) > t;
+            // The next 64 entries lie past every position this batch writes
+            // (kept <= p0 - b), so they are loaded before its stores.
+            int32_t cn = 0;
+            double xn = 0.0;
+            if (p + kWave < e) {
+                cn = col[p + kWave];
+                xn = val[p + kWave];
             }
             const unsigned long long m = __ballot(keep);
+            const int32_t below = (int32_t)lanes_below(m);
             if (keep) {
-                const int64_t q = b + kept + (int64_t)lanes_below(m);
+                const int64_t q = b + kept + below;
                 col[q] = c;
                 val[q] = x;
                 amx = fmax(amx, fabs(x));
                 first = min(first, c);
                 last = max(last, c);
+                stg[staged + below] = (uint32_t)c;
             }
             kept += __popcll(m);
+            staged += __popcll(m);
+            if (staged >= kWave) {  // staged <= 127
+                wave_sync();
+                const int32_t cc = (int32_t)stg[l];
+                const uint32_t rest = stg[kWave + l];
+                wave_sync();
+                if (l < staged - kWave) stg[l] = rest;
+                staged -= kWave;
+                wb.add(cc, kWave);
+            }
+            c = cn;
+            x = xn;
+        }
+        if (staged > 0) {
+            wave_sync();
+            const int32_t cc = l < staged ? (int32_t)stg[l] : 0;
+            wb.add(cc, staged);
         }
         amx = wave_reduce<OpMax>(amx);
         first = wave_reduce<OpMin>(first);
         last = wave_reduce<OpMax>(last);
-        // structure words of the kept columns
-        wave_sync();
-        WaveWordBuilder wb{sw + b, seg_sh[wv]};
-        for (int64_t p0 = 0; p0 < kept; p0 += kWave) {
-            const int64_t p = p0 + l;
-            wb.add(p < kept ? col[b + p] : 0, (int32_t)min<int64_t>(kWave, kept - p0));
-        }
         const int32_t words = wb.finish();
         if (l == 0) {
             end[r] = b + kept;
