@@ -74,6 +74,11 @@ typedef int32_t fps_status;
                                         one after it */
 #define FPS_FLAG_NO_VALIDATE 0x8ull  /* skip the device-side CSR check of Z at plan time */
 #define FPS_FLAG_SYNC_SIZES 0x10ull  /* size every stage from a host read (no learned capacities) */
+#define FPS_FLAG_DROP_STATS 0x20ull  /* fixed threshold: per filtered product, count the entries that D_tau
+                                        removes and take their largest magnitude and the 1-norm of the
+                                        removed part (the dropped matrices of eqs. 11 and 14, whose norms
+                                        enter the error bound of eq. 23); turns the row skip off, so that
+                                        every removed entry is computed */
 
 typedef struct ihipStream_t *fps_stream; /* same type as hipStream_t */
 
@@ -146,8 +151,14 @@ typedef struct {
     /* adaptive filter, per stage (0 for stages without a sparse product) */
     double stage_eps_g[FPS_MAX_STAGES];     /* filtering-norm threshold of the stage (eq. 28) */
     double stage_threshold[FPS_MAX_STAGES]; /* final entry threshold of Algorithm 1 (|x| <= it dropped) */
-    double stage_dropped[FPS_MAX_STAGES];   /* 1-norm of the dropped entries (integer column sums) */
+    double stage_dropped[FPS_MAX_STAGES];   /* 1-norm of the dropped entries (integer column sums); with a
+                                               fixed threshold and FPS_FLAG_DROP_STATS, the largest column
+                                               sum of ceil(|x| 2^40 / tau) 2^-40 tau over the entries
+                                               removed (an upper bound, within 2^-40 tau per entry) */
     int32_t stage_alg1_iters[FPS_MAX_STAGES];
+    /* FPS_FLAG_DROP_STATS with a fixed threshold, per filtered product (0 otherwise) */
+    int64_t stage_n_dropped[FPS_MAX_STAGES]; /* nonzero entries with |x| < tau removed */
+    double stage_dropped_max[FPS_MAX_STAGES]; /* their largest magnitude */
 } fps_stats;
 
 /* ---------------------------------------------------------------------- */

@@ -65,6 +65,8 @@ class fps_stats(C.Structure):
         ("stage_threshold", C.c_double * FPS_MAX_STAGES),
         ("stage_dropped", C.c_double * FPS_MAX_STAGES),
         ("stage_alg1_iters", C.c_int32 * FPS_MAX_STAGES),
+        ("stage_n_dropped", C.c_int64 * FPS_MAX_STAGES),
+        ("stage_dropped_max", C.c_double * FPS_MAX_STAGES),
     ]
 
 

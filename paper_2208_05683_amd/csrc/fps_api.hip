@@ -128,7 +128,7 @@ struct CanonMatrix {
 // Per-row workspace shared by the stages of one engine.
 struct Workspace {
     int64_t n = 0;
-    DevBuf W, lo, ub, fb, fb2, blk_pre, zinfo, zsw, znw, gscratch, counters, part, dummy;
+    DevBuf W, lo, ub, fb, fb2, blk_pre, zinfo, zsw, znw, gscratch, counters, part, dummy, dsum;
     int64_t g_words = 0, g_cap = 0, g_stride = 0, g_off_acc = 0, g_off_ebuf = 0;
     int64_t part_stride = 0;
     int32_t g_slots = 0;
@@ -784,7 +784,27 @@ struct fps_plan_s {
         int32_t* znw = eng.ws.znw.as<int32_t>();
         HIP_TRY(launch_rowinfo_csr(Z.row_ptr, Z.col, Z.val, n, zinfo, zsw, znw, s));
         const MatView zv = canon_view(&Z, zinfo, zsw, znw);
-        const double skip_tau = (flags & FPS_FLAG_NO_SKIP) || tau <= 0.0 ? 0.0 : tau * (1.0 - 1e-6);
+        // dropped-entry statistics (fixed threshold): every stage's removed
+        // entries are computed, so the row skip is off
+        const bool dstats = (flags & FPS_FLAG_DROP_STATS) && !adaptive && tau > 0.0;
+        const double skip_tau = (flags & FPS_FLAG_NO_SKIP) || dstats || tau <= 0.0 ? 0.0 : tau * (1.0 - 1e-6);
+        unsigned long long* dsum = nullptr;
+        if (dstats) {
+            FPS_TRY(eng.ws.dsum.ensure(sizeof(unsigned long long) * (size_t)std::max<int64_t>(n, 1)));
+            dsum = eng.ws.dsum.as<unsigned long long>();
+            HIP_TRY(launch_fill_u64(dsum, n, 0ull, s));
+        }
+        // after a filtered product: the largest column sum, then the sums cleared
+        auto drop_stats = [&](StageArgs& a) {
+            a.dsum = dsum;
+            a.dscale = dstats ? std::ldexp(1.0, 40) / tau : 0.0;
+        };
+        auto drop_norm = [&](int idx) -> fps_status {
+            if (!dstats) return FPS_OK;
+            HIP_TRY(launch_max_u64(dsum, n, &eng.ctr(idx)->dropped_colmax, s));
+            HIP_TRY(launch_fill_u64(dsum, n, 0ull, s));
+            return FPS_OK;
+        };
 
         const int nst = stage_count();
         const size_t slot = (size_t)(timed % kTimingRing);
@@ -817,11 +837,13 @@ struct fps_plan_s {
             a.A = zv;
             a.B = (j == 1) ? zv : P[(size_t)j]->view();
             a.has_e = 0;
+            drop_stats(a);
             StageRecord* r = begin_stage(Kind::Power, j + 1);
             r->a_is_z = true;
             r->b_is_z = (j == 1);
             r->b_src = (j == 1) ? -1 : pow_stage[(size_t)j];
             FPS_TRY(eng.run(n_stages, a, *P[(size_t)j + 1], s, size, r));
+            FPS_TRY(drop_norm(n_stages));
             if (adaptive)
                 FPS_TRY(eng.alg1(n_stages, *P[(size_t)j + 1], zeta[(size_t)j + 1], e_r, max_alg1, s, r,
                                  host_alg1 ? -1 : alg1_dev_iters));
@@ -864,12 +886,14 @@ struct fps_plan_s {
                 a.has_e = 0;
                 block_terms(sc.b - 1 - i, sc.q - 1, &a.T, zv);
                 a.has_blk = a.T.n > 0 ? 1 : 0;
+                drop_stats(a);
                 StageRecord* r = begin_stage(Kind::Horner, i);
                 r->a_is_z = (sc.q == 1);
                 r->a_src = (sc.q == 1) ? -1 : pow_stage[(size_t)sc.q];
                 r->b_src = s_stage;
                 add_term_sources(r, sc.b - 1 - i, sc.q - 1, pow_stage);
                 FPS_TRY(eng.run(n_stages, a, S[1 - cur], s, size, r));
+                FPS_TRY(drop_norm(n_stages));
                 if (adaptive)
                     FPS_TRY(eng.alg1(n_stages, S[1 - cur], sigma[(size_t)i], e_r, max_alg1, s, r,
                                      host_alg1 ? -1 : alg1_dev_iters));
@@ -1127,6 +1151,15 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
             st->stage_threshold[i] = f.t;
             st->stage_dropped[i] = f.c;
             st->stage_alg1_iters[i] = f.it;
+        }
+        if ((p->flags & FPS_FLAG_DROP_STATS) && !p->adaptive && p->tau > 0.0 &&
+            (r.kind == FPS_STAGE_POWER || r.kind == FPS_STAGE_HORNER)) {
+            const StageCounters& k = c[(size_t)i];
+            st->stage_n_dropped[i] = (int64_t)k.n_dropped;
+            double mx;
+            std::memcpy(&mx, &k.dropped_max, sizeof(mx));
+            st->stage_dropped_max[i] = mx;
+            st->stage_dropped[i] = std::ldexp((double)k.dropped_colmax, -40) * p->tau;
         }
         st->stage_nnz[i] = (int64_t)tot[(size_t)i][kPartKept];
         st->products += (int64_t)tot[(size_t)i][kPartProducts];

@@ -75,6 +75,10 @@ struct StageCounters {
     unsigned long long fb2_next;     // dynamic fetch from fb2_list, device-memory kernel
     unsigned long long rows_wide;    // rows computed by the wide-tier kernel
     unsigned long long max_ns;       // largest structural row computed by the wide-tier and device-memory kernels
+    // dropped-entry statistics (only when StageArgs::dsum is set)
+    unsigned long long n_dropped;       // nonzero entries removed by the tau test
+    unsigned long long dropped_max;     // bits of the largest |dropped| (non-negative doubles order as integers)
+    unsigned long long dropped_colmax;  // largest column sum of ceil(|dropped| * dscale)
 };
 
 // Algorithm 1 on the device (one record per state slot; three per stage: two
@@ -167,6 +171,11 @@ struct StageArgs {
     int32_t global_planned;  // 0: the device-memory kernel will not run for this stage
     int32_t wide_planned;    // 0: the wide-tier kernel will not run for this stage
     int32_t plan_pad;
+    // Dropped-entry statistics: when set, every entry removed by the tau
+    // test adds ceil(|x| * dscale) to dsum[col] (exact integer sums) and is
+    // counted in ctr->n_dropped / ctr->dropped_max.
+    unsigned long long* dsum;
+    double dscale;
 };
 
 // ---- launch wrappers (fps_kernels.hip) ---------------------------------

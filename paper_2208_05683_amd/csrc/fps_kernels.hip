@@ -1516,12 +1516,22 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     int64_t kept = 0;
     double amx = 0.0;
     int32_t first = INT_MAX, last = -1;
+    unsigned long long ndrop = 0;  // dropped-entry statistics
+    double dmx = 0.0;
     auto emit = [&](int64_t i, double x, int32_t c) {
         bool keep = false;
         if (i < ns) {
             keep = (x != 0.0) && !(fabs(x) < P.tau);
             // the bitmap keeps the kept columns only, for the structure words
             if (!keep) atomicAnd(&bmp[(uint32_t)(c - lo) >> 5].x, ~(1u << (c & 31)));
+        }
+        if (P.dsum != nullptr) {
+            const bool d = i < ns && !keep && x != 0.0;
+            if (d) {
+                atomicAdd(&P.dsum[c], (unsigned long long)ceil(fabs(x) * P.dscale));
+                dmx = fmax(dmx, fabs(x));
+            }
+            ndrop += __popcll(__ballot(d));
         }
         const unsigned long long m = __ballot(keep);
         if (keep) {
@@ -1579,6 +1589,13 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     amx = wave_reduce<OpMax>(amx);
     first = wave_reduce<OpMin>(first);
     last = wave_reduce<OpMax>(last);
+    if (P.dsum != nullptr) {
+        dmx = wave_reduce<OpMax>(dmx);
+        if (l == 0 && ndrop != 0) {
+            atomicAdd(&P.ctr->n_dropped, ndrop);
+            atomicMax(&P.ctr->dropped_max, (unsigned long long)__double_as_longlong(dmx));
+        }
+    }
     // 6. structure words of the row: the nonzero bitmap words, in order
     wave_sync();
     int32_t nwd = 0;

@@ -140,6 +140,45 @@ def test_flags_do_not_change_results():
             assert gst["numeric_ms"] > 0 and gst["numeric_launches"] == gst["n_stages"]
 
 
+@pytest.mark.parametrize("which", ["config1", "config2 side 70", "random banded"])
+def test_drop_statistics_match_oracle(which):
+    """FPS_FLAG_DROP_STATS: per filtered product, the count and largest
+    magnitude of the entries D_tau removes equal the oracle's exactly; the
+    1-norm of the removed part (integer column sums of ceil(|x| 2^40 / tau))
+    is the oracle's floating-point one up to 2^-40 tau per entry, from above."""
+    from paper_2208_05683_amd import binding as B
+
+    if which == "config1":
+        cfg = G.config1()
+        Z, c, m, s, tau = cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"]
+    elif which == "random banded":
+        Z, c, m, s, tau = G.random_banded(900, 4, 0.6, 1.5, seed=33), G.exp_coeffs(20), 20, 4, 1e-9
+    else:
+        cfg = G.config2(side=70)
+        Z, c, m, s, tau = cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"]
+    want, st = O.filtered_ps(Z, c, m, s, tau)
+    got, gst = gpu_filtered_ps(Z, c, m, s, tau, B.FPS_FLAG_DROP_STATS, evals=2)
+    for k, g in enumerate(got):
+        assert_same_csr(g, want, f"{which}, evaluation {k}")
+    assert gst["rows_skipped"] == 0
+    ora = {(x["kind"], x["index"]): x for x in st}
+    checked = dropped = 0
+    for i, kind in enumerate(gst["kind"]):
+        if kind not in (0, 3):  # coefficient sums are not filtered
+            assert gst["stage_n_dropped"][i] == 0 and gst["stage_dropped"][i] == 0.0
+            continue
+        o = ora[(kind, gst["index"][i])]
+        what = f"{which}, stage {i} ({o['kind_name']} {o['index']})"
+        assert gst["stage_n_dropped"][i] == o["n_dropped"], what
+        assert gst["stage_dropped_max"][i] == o["dropped_max"], what
+        lo = o["dropped_1norm"] * (1 - 1e-12)
+        hi = o["dropped_1norm"] * (1 + 1e-12) + o["n_dropped"] * tau * 2.0 ** -40
+        assert lo <= gst["stage_dropped"][i] <= hi, (what, gst["stage_dropped"][i], o["dropped_1norm"])
+        checked += 1
+        dropped += o["n_dropped"]
+    assert checked >= 3 and dropped > 0
+
+
 def test_result_within_eq23_bound():
     Z, c, m, s, tau = G.random_banded(400, 3, 0.6, 1.5, seed=21), G.exp_coeffs(20), 20, 4, 1e-7
     got, gst = gpu_filtered_ps(Z, c, m, s, tau)
