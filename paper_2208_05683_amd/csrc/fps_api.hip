@@ -125,6 +125,10 @@ struct CanonMatrix {
     DevBuf rp, col, val;
 };
 
+// Algorithm 1 on the device: the first iteration's column sums taken in the
+// numeric kernel's write-out.
+constexpr bool kAlg1FuseFirst = true;
+
 // Per-row workspace shared by the stages of one engine.
 struct Workspace {
     int64_t n = 0;
@@ -420,9 +424,32 @@ struct Engine {
     // host loop.  device_iters == 0: the count learned by the last host-driven
     // run of this stage, or the host loop (which learns it) if there is none.
     // device_iters < 0: the host loop, one synchronisation per iteration.
+    // Before a stage that Algorithm 1 will filter on the device: the numeric
+    // kernel's write-out sums the first iteration's candidates (0 < |x| <=
+    // eps_g, the first threshold) into the column sums, which saves that
+    // iteration's pass over the product.
+    bool alg1_fused = false;
+    fps_status alg1_fuse(int idx, double eps_g, int device_iters, StageArgs& a, hipStream_t s)
+    {
+        alg1_fused = false;
+        if (device_iters == 0) device_iters = alg1_learned[(size_t)idx];
+        if (device_iters <= 0 || !std::isfinite(eps_g) || !kAlg1FuseFirst) return FPS_OK;
+        const int64_t n = ws.n;
+        FPS_TRY(colsum.ensure(sizeof(unsigned long long) * (size_t)(2 * n + 3)));
+        HIP_TRY(launch_fill_u64(colsum.as<unsigned long long>(), 2 * n + 3, 0ull, s));
+        a.dsum = colsum.as<unsigned long long>();
+        a.dscale = std::ldexp(1.0, 40) / eps_g;
+        a.dthr = eps_g;
+        a.dcount = 0;
+        alg1_fused = true;
+        return FPS_OK;
+    }
+
     fps_status alg1(int idx, SlackMatrix& out, double eps_g, double e_r, int max_iter, hipStream_t s,
                     StageRecord* rec, int device_iters)
     {
+        const bool fused = alg1_fused;
+        alg1_fused = false;
         if (device_iters == 0) device_iters = alg1_learned[(size_t)idx];  // 0 if none: host loop
 
         const int64_t n = ws.n;
@@ -441,13 +468,14 @@ struct Engine {
         const double scale = std::ldexp(1.0, 40) / eps_g;
         if (device_iters > 0) {
             device_iters = std::min(device_iters, max_iter);
-            HIP_TRY(launch_fill_u64(cs, 2 * n + 3, 0ull, s));
+            if (!fused) HIP_TRY(launch_fill_u64(cs, 2 * n + 3, 0ull, s));
             const Alg1Params pr{eps_g, target, scale, max_iter, 0};
             HIP_TRY(launch_alg1_device(out.off.as<int64_t>(), out.end.as<int64_t>(), out.col.as<int32_t>(),
                                        out.val.as<double>(), out.info.as<RowInfo>(),
                                        out.sw.as<uint2>(), out.nw.as<int32_t>(), n, pr,
                                        device_iters, alg1_state(idx),
-                                       cs, part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, ctr(idx), s));
+                                       cs, part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, ctr(idx),
+                                       fused ? 1 : 0, s));
             if (rec) rec->alg1_device = true;
             return FPS_OK;
         }
@@ -798,6 +826,8 @@ struct fps_plan_s {
         auto drop_stats = [&](StageArgs& a) {
             a.dsum = dsum;
             a.dscale = dstats ? std::ldexp(1.0, 40) / tau : 0.0;
+            a.dthr = 0.0;
+            a.dcount = 1;
         };
         auto drop_norm = [&](int idx) -> fps_status {
             if (!dstats) return FPS_OK;
@@ -838,6 +868,8 @@ struct fps_plan_s {
             a.B = (j == 1) ? zv : P[(size_t)j]->view();
             a.has_e = 0;
             drop_stats(a);
+            if (adaptive)
+                FPS_TRY(eng.alg1_fuse(n_stages, zeta[(size_t)j + 1], host_alg1 ? -1 : alg1_dev_iters, a, s));
             StageRecord* r = begin_stage(Kind::Power, j + 1);
             r->a_is_z = true;
             r->b_is_z = (j == 1);
@@ -887,6 +919,8 @@ struct fps_plan_s {
                 block_terms(sc.b - 1 - i, sc.q - 1, &a.T, zv);
                 a.has_blk = a.T.n > 0 ? 1 : 0;
                 drop_stats(a);
+                if (adaptive)
+                    FPS_TRY(eng.alg1_fuse(n_stages, sigma[(size_t)i], host_alg1 ? -1 : alg1_dev_iters, a, s));
                 StageRecord* r = begin_stage(Kind::Horner, i);
                 r->a_is_z = (sc.q == 1);
                 r->a_src = (sc.q == 1) ? -1 : pow_stage[(size_t)sc.q];

@@ -171,11 +171,17 @@ struct StageArgs {
     int32_t global_planned;  // 0: the device-memory kernel will not run for this stage
     int32_t wide_planned;    // 0: the wide-tier kernel will not run for this stage
     int32_t plan_pad;
-    // Dropped-entry statistics: when set, every entry removed by the tau
-    // test adds ceil(|x| * dscale) to dsum[col] (exact integer sums) and is
-    // counted in ctr->n_dropped / ctr->dropped_max.
+    // Column sums at the write-out: when dsum is set, every nonzero entry
+    // removed by the tau test or with |x| <= dthr adds ceil(|x| * dscale) to
+    // dsum[col] (exact integer sums); with dcount it is also counted in
+    // ctr->n_dropped / ctr->dropped_max.  (Fixed threshold: the dropped-entry
+    // statistics, dthr = 0.  Algorithm 1: the candidate sums of its first
+    // iteration, dthr = eps_g.)
     unsigned long long* dsum;
     double dscale;
+    double dthr;
+    int32_t dcount;
+    int32_t dpad;
 };
 
 // ---- launch wrappers (fps_kernels.hip) ---------------------------------
@@ -224,9 +230,10 @@ hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, doub
 // entry), then the final update and the drop; the final record goes to st[2];
 // a stage that has not converged by then keeps its entries and raises
 // kErrAlg1Pending in ctr->errors.
+// (fused0: the numeric kernel already summed the first iteration's candidates into cs[0, n))
 hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, RowInfo* info,
                               uint2* sw, int32_t* nw, int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
-                              unsigned long long* part_kept, StageCounters* ctr, hipStream_t s);
+                              unsigned long long* part_kept, StageCounters* ctr, int fused0, hipStream_t s);
 int numeric_global_blocks(int slots);
 // blocks of the wide-tier kernel (persistent: six per CU at most)
 int numeric_wide_blocks(int64_t n);

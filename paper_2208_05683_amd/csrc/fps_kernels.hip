@@ -1526,12 +1526,12 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
             if (!keep) atomicAnd(&bmp[(uint32_t)(c - lo) >> 5].x, ~(1u << (c & 31)));
         }
         if (P.dsum != nullptr) {
-            const bool d = i < ns && !keep && x != 0.0;
-            if (d) {
-                atomicAdd(&P.dsum[c], (unsigned long long)ceil(fabs(x) * P.dscale));
-                dmx = fmax(dmx, fabs(x));
+            const bool d = i < ns && x != 0.0 && (!keep || fabs(x) <= P.dthr);
+            if (d) atomicAdd(&P.dsum[c], (unsigned long long)ceil(fabs(x) * P.dscale));
+            if (P.dcount) {
+                if (d) dmx = fmax(dmx, fabs(x));
+                ndrop += __popcll(__ballot(d));
             }
-            ndrop += __popcll(__ballot(d));
         }
         const unsigned long long m = __ballot(keep);
         if (keep) {
@@ -1589,7 +1589,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     amx = wave_reduce<OpMax>(amx);
     first = wave_reduce<OpMin>(first);
     last = wave_reduce<OpMax>(last);
-    if (P.dsum != nullptr) {
+    if (P.dsum != nullptr && P.dcount) {
         dmx = wave_reduce<OpMax>(dmx);
         if (l == 0 && ndrop != 0) {
             atomicAdd(&P.ctr->n_dropped, ndrop);
@@ -1948,7 +1948,8 @@ __device__ __forceinline__ Alg1State alg1_state(const Alg1Params& pr, int i, con
 __global__ void __launch_bounds__(kAlg1Threads) k_alg1_iter(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
                                                       const int32_t* __restrict__ col,
                                                       const double* __restrict__ val, const RowInfo* info, int64_t n,
-                                                      Alg1Params pr, int i, Alg1State* st, unsigned long long* cs)
+                                                      Alg1Params pr, int i, Alg1State* st, unsigned long long* cs,
+                                                      int fused0)
 {
     unsigned long long* mxs = cs + 2 * n;
     const Alg1State cur = alg1_state(pr, i, st, mxs);
@@ -1958,6 +1959,7 @@ __global__ void __launch_bounds__(kAlg1Threads) k_alg1_iter(const int64_t* __res
     unsigned long long* next = cs + (int64_t)((i + 1) & 1) * n;
     for (int64_t g = (int64_t)blockIdx.x * kAlg1Threads + threadIdx.x; g < n; g += nthreads) next[g] = 0ull;
     if (blockIdx.x == 0 && threadIdx.x == 0) mxs[(i + 1) % 3] = 0ull;
+    if (i == 0 && fused0) return;  // summed by the numeric kernel's write-out
     alg1_block_colsums(beg, end, col, val, info, n, cur.t, pr.scale, cs + (int64_t)(i & 1) * n);
 }
 
@@ -2227,7 +2229,7 @@ hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, doub
 
 hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, RowInfo* info,
                               uint2* sw, int32_t* nw, int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
-                              unsigned long long* part_kept, StageCounters* ctr, hipStream_t s)
+                              unsigned long long* part_kept, StageCounters* ctr, int fused0, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)numeric_blocks(n);
@@ -2236,7 +2238,7 @@ hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, do
     for (int i = 0; i < iters; ++i) {
         hipLaunchKernelGGL(k_alg1_iter, dim3(iter_blocks), dim3(kAlg1Threads), 0, s, (const int64_t*)beg,
                            (const int64_t*)end, (const int32_t*)col, (const double*)val, (const RowInfo*)info, n, pr,
-                           i, st, cs);
+                           i, st, cs, fused0);
         hipLaunchKernelGGL(k_alg1_max, dim3(max_blocks), dim3(kBlock), 0, s, n, i, (const Alg1State*)st, cs);
     }
     hipLaunchKernelGGL(k_alg1_drop_t<true>, dim3(blocks), dim3(kBlock), 0, s, beg, end, col, val, info, sw, nw,

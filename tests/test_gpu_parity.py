@@ -187,6 +187,16 @@ def test_result_within_eq23_bound():
     err = O.norm1(got.to_dense() - P)
     bd = filtering_bound(c, m, s, st, power_norms(Z, s * (-(-(m + 1) // s))))
     assert 0 < err <= bd["bound"] * (1 + 1e-3) + rounding_slack(c, m, O.norm1(Z))
+    # the same bound from the GPU's own dropped norms (FPS_FLAG_DROP_STATS)
+    from paper_2208_05683_amd import binding as B
+
+    got2, gst2 = gpu_filtered_ps(Z, c, m, s, tau, B.FPS_FLAG_DROP_STATS)
+    assert_same_csr(got2, got, "with drop statistics")
+    gpu_st = [{"kind": k, "index": i, "dropped_1norm": v}
+              for k, i, v in zip(gst2["kind"], gst2["index"], gst2["stage_dropped"])]
+    bd_gpu = filtering_bound(c, m, s, gpu_st, power_norms(Z, s * (-(-(m + 1) // s))))
+    assert bd_gpu["bound"] >= bd["bound"] * (1 - 1e-12)
+    assert err <= bd_gpu["bound"] * (1 + 1e-3) + rounding_slack(c, m, O.norm1(Z))
 
 
 # ---------------------------------------------------------------------------
