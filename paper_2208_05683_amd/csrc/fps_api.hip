@@ -128,6 +128,8 @@ struct CanonMatrix {
 // Algorithm 1 on the device: the first iteration's column sums taken in the
 // numeric kernel's write-out.
 constexpr bool kAlg1FuseFirst = true;
+// ... and, for stages that needed one iteration, the drop applied there too.
+constexpr bool kAlg1DropFirst = true;
 
 // Per-row workspace shared by the stages of one engine.
 struct Workspace {
@@ -428,28 +430,41 @@ struct Engine {
     // kernel's write-out sums the first iteration's candidates (0 < |x| <=
     // eps_g, the first threshold) into the column sums, which saves that
     // iteration's pass over the product.
-    bool alg1_fused = false;
+    // When the stage needed a single iteration before (the count learned by
+    // the host loop), the write-out also drops those candidates at once, as
+    // that iteration would if its candidate norm is within the target; the
+    // final state is then only checked on the device, and a miss raises
+    // kErrAlg1Pending like any other iteration count that falls short.
+    int alg1_fused = 0;  // 0: not fused, 1: first iteration's sums, 2: sums and drop
     fps_status alg1_fuse(int idx, double eps_g, int device_iters, StageArgs& a, hipStream_t s)
     {
-        alg1_fused = false;
+        alg1_fused = 0;
         if (device_iters == 0) device_iters = alg1_learned[(size_t)idx];
-        if (device_iters <= 0 || !std::isfinite(eps_g) || !kAlg1FuseFirst) return FPS_OK;
+        if (device_iters <= 0 || !std::isfinite(eps_g) || !(eps_g > 0.0) || !kAlg1FuseFirst) return FPS_OK;
         const int64_t n = ws.n;
         FPS_TRY(colsum.ensure(sizeof(unsigned long long) * (size_t)(2 * n + 3)));
         HIP_TRY(launch_fill_u64(colsum.as<unsigned long long>(), 2 * n + 3, 0ull, s));
         a.dsum = colsum.as<unsigned long long>();
         a.dscale = std::ldexp(1.0, 40) / eps_g;
-        a.dthr = eps_g;
         a.dcount = 0;
-        alg1_fused = true;
+        if (device_iters == 1 && kAlg1DropFirst) {
+            // keep |x| > eps_g: !(|x| < tau) with tau the next double above eps_g
+            a.tau = std::nextafter(eps_g, HUGE_VAL);
+            a.skip_tau = 0.0;
+            a.dthr = 0.0;  // the summed entries are exactly the removed ones
+            alg1_fused = 2;
+        } else {
+            a.dthr = eps_g;
+            alg1_fused = 1;
+        }
         return FPS_OK;
     }
 
     fps_status alg1(int idx, SlackMatrix& out, double eps_g, double e_r, int max_iter, hipStream_t s,
                     StageRecord* rec, int device_iters)
     {
-        const bool fused = alg1_fused;
-        alg1_fused = false;
+        const int fused = alg1_fused;
+        alg1_fused = 0;
         if (device_iters == 0) device_iters = alg1_learned[(size_t)idx];  // 0 if none: host loop
 
         const int64_t n = ws.n;
@@ -468,6 +483,7 @@ struct Engine {
         const double scale = std::ldexp(1.0, 40) / eps_g;
         if (device_iters > 0) {
             device_iters = std::min(device_iters, max_iter);
+            if (fused == 2) device_iters = 1;
             if (!fused) HIP_TRY(launch_fill_u64(cs, 2 * n + 3, 0ull, s));
             const Alg1Params pr{eps_g, target, scale, max_iter, 0};
             HIP_TRY(launch_alg1_device(out.off.as<int64_t>(), out.end.as<int64_t>(), out.col.as<int32_t>(),
@@ -475,7 +491,7 @@ struct Engine {
                                        out.sw.as<uint2>(), out.nw.as<int32_t>(), n, pr,
                                        device_iters, alg1_state(idx),
                                        cs, part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, ctr(idx),
-                                       fused ? 1 : 0, s));
+                                       fused ? 1 : 0, fused == 2 ? 1 : 0, s));
             if (rec) rec->alg1_device = true;
             return FPS_OK;
         }

@@ -1991,7 +1991,7 @@ __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restric
                                                         int64_t n, double t,
                                                         unsigned long long* part_kept, Alg1Params pr, int iters,
                                                         Alg1State* st, const unsigned long long* cs,
-                                                        StageCounters* ctr)
+                                                        StageCounters* ctr, int finalize_only)
 {
     if (kDevice) {  // the final update; the threshold is the last one used
         const Alg1State fin = alg1_state(pr, iters, st, cs + 2 * n);
@@ -2002,7 +2002,7 @@ __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restric
             if (!fin.done) atomicOr(&ctr->errors, kErrAlg1Pending);
             if (fin.done && fin.c > pr.target) atomicOr(&ctr->errors, kErrCapacity);  // iteration limit reached
         }
-        if (!fin.done) return;
+        if (!fin.done || finalize_only) return;
         t = fin.t;
     }
     // the drop recounts every row (per-block partials), including those of
@@ -2223,13 +2223,14 @@ hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, doub
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_alg1_drop_t<false>, dim3((unsigned)numeric_blocks(n)), dim3(kBlock), 0, s, beg, end, col, val,
                        info, sw, nw, n, t, part_kept, Alg1Params{}, 0, (Alg1State*)nullptr,
-                       (const unsigned long long*)nullptr, ctr);
+                       (const unsigned long long*)nullptr, ctr, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, RowInfo* info,
                               uint2* sw, int32_t* nw, int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
-                              unsigned long long* part_kept, StageCounters* ctr, int fused0, hipStream_t s)
+                              unsigned long long* part_kept, StageCounters* ctr, int fused0, int finalize_only,
+                              hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)numeric_blocks(n);
@@ -2241,9 +2242,11 @@ hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, do
                            i, st, cs, fused0);
         hipLaunchKernelGGL(k_alg1_max, dim3(max_blocks), dim3(kBlock), 0, s, n, i, (const Alg1State*)st, cs);
     }
-    hipLaunchKernelGGL(k_alg1_drop_t<true>, dim3(blocks), dim3(kBlock), 0, s, beg, end, col, val, info, sw, nw,
-                       n, 0.0,
-                       part_kept, pr, iters, st, (const unsigned long long*)cs, ctr);
+    // (finalize_only: the numeric write-out already applied the threshold; one
+    // block records the final state and raises the flags)
+    hipLaunchKernelGGL(k_alg1_drop_t<true>, dim3(finalize_only ? 1u : blocks), dim3(kBlock), 0, s, beg, end, col,
+                       val, info, sw, nw, n, 0.0,
+                       part_kept, pr, iters, st, (const unsigned long long*)cs, ctr, finalize_only);
     return hipGetLastError();
 }
 

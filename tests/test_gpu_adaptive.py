@@ -77,6 +77,49 @@ def test_adaptive_full_size_lap2d():
     assert max(x["iters"] for x in a1) >= 3
 
 
+def test_adaptive_operand_change_between_evaluations():
+    """Iteration counts learned on one operand, then its values scaled in
+    place by 1.5: a stage that needed one iteration now needs six (its
+    candidates were dropped at the write-out on the strength of the learned
+    count, so the device flags the miss and the evaluation is repeated with
+    the host loop); later stages need fewer or more.  Each evaluation must give
+    the oracle's result for the operand it saw."""
+    import torch
+    from paper_2208_05683_amd import api
+
+    m, s, eps = 30, 6, 1e-12
+    c = G.exp_coeffs(m)
+    Z1 = G.laplacian_2d(60, 2.0)
+    Z2 = G.laplacian_2d(60, 2.0)
+    Z2.val[:] = Z2.val * 1.5
+    z = znorms(Z1, m, s)
+    want1, _, a1 = O.filtered_ps_adaptive(Z1, c, m, s, eps, 0.1, z)
+    want2, _, a2 = O.filtered_ps_adaptive(Z2, c, m, s, eps, 0.1, z)
+    it1, it2 = [x["iters"] for x in a1], [x["iters"] for x in a2]
+    assert any(p == 1 and q > 1 for p, q in zip(it1, it2))
+    Zd = upload(Z1)
+    plan = api.Plan(Zd, c, m, s, adaptive=True, eps=eps, e_r=0.1, znorm=z)
+    try:
+        for k in range(2):
+            plan.eval()
+            assert_same_csr(download(plan.result()), want1, f"first operand, evaluation {k}")
+        Zd[2].copy_(torch.from_numpy(Z2.val).to(Zd[2].device))
+        for k in range(2):
+            plan.eval()
+            got = download(plan.result())
+            check_canonical(got)
+            assert_same_csr(got, want2, f"scaled operand, evaluation {k}")
+            gst = plan.stats()
+            prod = [i for i, kd in enumerate(gst["kind"]) if kd in (0, 3)]
+            assert [gst["stage_alg1_iters"][i] for i in prod] == it2
+            assert [gst["stage_threshold"][i] for i in prod] == [x["threshold"] for x in a2]
+        Zd[2].copy_(torch.from_numpy(Z1.val).to(Zd[2].device))
+        plan.eval()
+        assert_same_csr(download(plan.result()), want1, "first operand again")
+    finally:
+        plan.close()
+
+
 def test_adaptive_wide_column_windows():
     """Random columns over n = 7000: every block's rows span nearly all
     columns, so the candidate sums go to the device array, and the late rows
