@@ -1954,12 +1954,13 @@ __global__ void __launch_bounds__(kAlg1Threads) k_alg1_iter(const int64_t* __res
     unsigned long long* mxs = cs + 2 * n;
     const Alg1State cur = alg1_state(pr, i, st, mxs);
     if (blockIdx.x == 0 && threadIdx.x == 0) st[i & 1] = cur;
-    if (cur.done) return;
+    // (first iteration summed by the numeric kernel's write-out: the host
+    // cleared every buffer before it, and a single block records the state)
+    if (cur.done || (i == 0 && fused0)) return;
     const int64_t nthreads = (int64_t)gridDim.x * kAlg1Threads;
     unsigned long long* next = cs + (int64_t)((i + 1) & 1) * n;
     for (int64_t g = (int64_t)blockIdx.x * kAlg1Threads + threadIdx.x; g < n; g += nthreads) next[g] = 0ull;
     if (blockIdx.x == 0 && threadIdx.x == 0) mxs[(i + 1) % 3] = 0ull;
-    if (i == 0 && fused0) return;  // summed by the numeric kernel's write-out
     alg1_block_colsums(beg, end, col, val, info, n, cur.t, pr.scale, cs + (int64_t)(i & 1) * n);
 }
 
@@ -2237,7 +2238,8 @@ hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, do
     const unsigned iter_blocks = (unsigned)((n + kAlg1Rows - 1) / kAlg1Rows);
     const unsigned max_blocks = (unsigned)std::min<int64_t>(256, (n + kBlock - 1) / kBlock);
     for (int i = 0; i < iters; ++i) {
-        hipLaunchKernelGGL(k_alg1_iter, dim3(iter_blocks), dim3(kAlg1Threads), 0, s, (const int64_t*)beg,
+        hipLaunchKernelGGL(k_alg1_iter, dim3(i == 0 && fused0 ? 1u : iter_blocks), dim3(kAlg1Threads), 0, s,
+                           (const int64_t*)beg,
                            (const int64_t*)end, (const int32_t*)col, (const double*)val, (const RowInfo*)info, n, pr,
                            i, st, cs, fused0);
         hipLaunchKernelGGL(k_alg1_max, dim3(max_blocks), dim3(kBlock), 0, s, n, i, (const Alg1State*)st, cs);
