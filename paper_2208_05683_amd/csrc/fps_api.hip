@@ -130,6 +130,8 @@ struct CanonMatrix {
 constexpr bool kAlg1FuseFirst = true;
 // ... and, for stages that needed one iteration, the drop applied there too.
 constexpr bool kAlg1DropFirst = true;
+// ... and, for stages that needed more, the drop at the learned final threshold.
+constexpr bool kAlg1DropLearned = true;
 
 // Per-row workspace shared by the stages of one engine.
 struct Workspace {
@@ -271,6 +273,7 @@ struct Engine {
     std::vector<int64_t> learned_wide;    // per stage: rows a sizing run sent to the wide shared-memory tier
     std::vector<int64_t> learned_global;  // per stage: rows a sizing run sent to the device-memory kernel
     std::vector<int> alg1_learned;  // per stage: Algorithm 1 iterations of the last host-driven run
+    std::vector<double> alg1_learned_t;  // ... and its final threshold
 
     StageCounters* ctr(int i) const { return ws.counters.as<StageCounters>() + i; }
     Alg1State* alg1_state(int i) const { return alg1st.as<Alg1State>() + 3 * (size_t)i; }
@@ -309,6 +312,7 @@ struct Engine {
         learned_wide.assign((size_t)stages, 0);
         learned_global.assign((size_t)stages, 0);
         alg1_learned.assign((size_t)stages, 0);
+        alg1_learned_t.assign((size_t)stages, 0.0);
         FPS_TRY(alg1st.ensure(sizeof(Alg1State) * 3 * (size_t)std::max(stages, 1)));
         return ws.init(n, stages);
     }
@@ -435,25 +439,44 @@ struct Engine {
     // that iteration would if its candidate norm is within the target; the
     // final state is then only checked on the device, and a miss raises
     // kErrAlg1Pending like any other iteration count that falls short.
-    int alg1_fused = 0;  // 0: not fused, 1: first iteration's sums, 2: sums and drop
+    // With more iterations learned, the final threshold t* learned with them
+    // is applied at the write-out in the same way: the removed entries' column
+    // sums D go to a buffer of their own, every iteration sums the kept
+    // entries below its threshold on top of D (exact while its threshold is
+    // at least t*, which holds up to the first threshold below t*), and the
+    // evaluation is flagged for a repeat unless the iteration ends at t*.
+    int alg1_fused = 0;  // 0: not fused, 1: first iteration's sums, 2: sums and drop, 3: drop at t*
+    double alg1_spec_t = 0.0;
     fps_status alg1_fuse(int idx, double eps_g, int device_iters, StageArgs& a, hipStream_t s)
     {
         alg1_fused = 0;
         if (device_iters == 0) device_iters = alg1_learned[(size_t)idx];
         if (device_iters <= 0 || !std::isfinite(eps_g) || !(eps_g > 0.0) || !kAlg1FuseFirst) return FPS_OK;
         const int64_t n = ws.n;
-        FPS_TRY(colsum.ensure(sizeof(unsigned long long) * (size_t)(2 * n + 3)));
-        HIP_TRY(launch_fill_u64(colsum.as<unsigned long long>(), 2 * n + 3, 0ull, s));
-        a.dsum = colsum.as<unsigned long long>();
+        FPS_TRY(colsum.ensure(sizeof(unsigned long long) * (size_t)(3 * n + 3)));
+        unsigned long long* cs = colsum.as<unsigned long long>();
+        const double t_learned = alg1_learned_t[(size_t)idx];
+        const bool spec = device_iters >= 2 && kAlg1DropLearned && t_learned > 0.0 && t_learned < eps_g;
+        HIP_TRY(launch_fill_u64(cs, (spec ? 3 : 2) * n + 3, 0ull, s));
         a.dscale = std::ldexp(1.0, 40) / eps_g;
         a.dcount = 0;
         if (device_iters == 1 && kAlg1DropFirst) {
             // keep |x| > eps_g: !(|x| < tau) with tau the next double above eps_g
+            a.dsum = cs;
             a.tau = std::nextafter(eps_g, HUGE_VAL);
             a.skip_tau = 0.0;
             a.dthr = 0.0;  // the summed entries are exactly the removed ones
             alg1_fused = 2;
+            alg1_spec_t = eps_g;
+        } else if (spec) {
+            a.dsum = cs + 2 * n + 3;  // D
+            a.tau = std::nextafter(t_learned, HUGE_VAL);
+            a.skip_tau = 0.0;
+            a.dthr = 0.0;
+            alg1_fused = 3;
+            alg1_spec_t = t_learned;
         } else {
+            a.dsum = cs;
             a.dthr = eps_g;
             alg1_fused = 1;
         }
@@ -485,13 +508,19 @@ struct Engine {
             device_iters = std::min(device_iters, max_iter);
             if (fused == 2) device_iters = 1;
             if (!fused) HIP_TRY(launch_fill_u64(cs, 2 * n + 3, 0ull, s));
+            const unsigned long long* base = nullptr;
+            if (fused == 3) {  // the first iteration's sums start from D as well
+                base = cs + 2 * n + 3;
+                HIP_TRY(hipMemcpyAsync(cs, base, sizeof(unsigned long long) * (size_t)n, hipMemcpyDeviceToDevice, s));
+            }
             const Alg1Params pr{eps_g, target, scale, max_iter, 0};
             HIP_TRY(launch_alg1_device(out.off.as<int64_t>(), out.end.as<int64_t>(), out.col.as<int32_t>(),
                                        out.val.as<double>(), out.info.as<RowInfo>(),
                                        out.sw.as<uint2>(), out.nw.as<int32_t>(), n, pr,
                                        device_iters, alg1_state(idx),
                                        cs, part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, ctr(idx),
-                                       fused ? 1 : 0, fused == 2 ? 1 : 0, s));
+                                       (fused == 1 || fused == 2) ? 1 : 0, fused >= 2 ? 1 : 0, alg1_spec_t, base,
+                                       s));
             if (rec) rec->alg1_device = true;
             return FPS_OK;
         }
@@ -522,6 +551,7 @@ struct Engine {
             rec->alg1_iters = it;
         }
         alg1_learned[(size_t)idx] = it;
+        alg1_learned_t[(size_t)idx] = t;
         return FPS_OK;
     }
 

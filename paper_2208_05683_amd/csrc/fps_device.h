@@ -231,12 +231,15 @@ hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, doub
 // a stage that has not converged by then keeps its entries and raises
 // kErrAlg1Pending in ctr->errors.
 // (fused0: the numeric kernel already summed the first iteration's candidates
-// into cs[0, n); finalize_only: it also dropped them, iters is 1 and only the
-// final state and flags are written)
+// into cs[0, n); finalize_only: the numeric kernel already dropped |x| <=
+// t_dropped, and only the final state and flags are written, the evaluation
+// being flagged for a repeat unless the iteration ends at t_dropped; base:
+// column sums of those removed entries, with which every iteration's sums
+// start, or null)
 hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, RowInfo* info,
                               uint2* sw, int32_t* nw, int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
                               unsigned long long* part_kept, StageCounters* ctr, int fused0, int finalize_only,
-                              hipStream_t s);
+                              double t_dropped, const unsigned long long* base, hipStream_t s);
 int numeric_global_blocks(int slots);
 // blocks of the wide-tier kernel (persistent: six per CU at most)
 int numeric_wide_blocks(int64_t n);

@@ -1949,7 +1949,7 @@ __global__ void __launch_bounds__(kAlg1Threads) k_alg1_iter(const int64_t* __res
                                                       const int32_t* __restrict__ col,
                                                       const double* __restrict__ val, const RowInfo* info, int64_t n,
                                                       Alg1Params pr, int i, Alg1State* st, unsigned long long* cs,
-                                                      int fused0)
+                                                      int fused0, const unsigned long long* __restrict__ base)
 {
     unsigned long long* mxs = cs + 2 * n;
     const Alg1State cur = alg1_state(pr, i, st, mxs);
@@ -1959,7 +1959,10 @@ __global__ void __launch_bounds__(kAlg1Threads) k_alg1_iter(const int64_t* __res
     if (cur.done || (i == 0 && fused0)) return;
     const int64_t nthreads = (int64_t)gridDim.x * kAlg1Threads;
     unsigned long long* next = cs + (int64_t)((i + 1) & 1) * n;
-    for (int64_t g = (int64_t)blockIdx.x * kAlg1Threads + threadIdx.x; g < n; g += nthreads) next[g] = 0ull;
+    // (base: column sums of entries the numeric write-out already removed,
+    // all below every threshold tried, so every iteration's sums start there)
+    for (int64_t g = (int64_t)blockIdx.x * kAlg1Threads + threadIdx.x; g < n; g += nthreads)
+        next[g] = base != nullptr ? base[g] : 0ull;
     if (blockIdx.x == 0 && threadIdx.x == 0) mxs[(i + 1) % 3] = 0ull;
     alg1_block_colsums(beg, end, col, val, info, n, cur.t, pr.scale, cs + (int64_t)(i & 1) * n);
 }
@@ -1997,11 +2000,14 @@ __global__ void __launch_bounds__(kBlock) k_alg1_drop_t(const int64_t* __restric
     if (kDevice) {  // the final update; the threshold is the last one used
         const Alg1State fin = alg1_state(pr, iters, st, cs + 2 * n);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
+            // finalize_only: the write-out dropped at threshold t, which must
+            // be the one the iteration ends with
+            const bool miss = finalize_only && fin.done && fin.t != t;
             Alg1State rec = fin;
-            rec.ok = fin.done;
+            rec.ok = fin.done && !miss;
             st[2] = rec;
-            if (!fin.done) atomicOr(&ctr->errors, kErrAlg1Pending);
-            if (fin.done && fin.c > pr.target) atomicOr(&ctr->errors, kErrCapacity);  // iteration limit reached
+            if (!fin.done || miss) atomicOr(&ctr->errors, kErrAlg1Pending);
+            if (rec.ok && fin.c > pr.target) atomicOr(&ctr->errors, kErrCapacity);  // iteration limit reached
         }
         if (!fin.done || finalize_only) return;
         t = fin.t;
@@ -2231,7 +2237,7 @@ hipError_t launch_alg1_drop(const int64_t* beg, int64_t* end, int32_t* col, doub
 hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, double* val, RowInfo* info,
                               uint2* sw, int32_t* nw, int64_t n, const Alg1Params& pr, int iters, Alg1State* st, unsigned long long* cs,
                               unsigned long long* part_kept, StageCounters* ctr, int fused0, int finalize_only,
-                              hipStream_t s)
+                              double t_dropped, const unsigned long long* base, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)numeric_blocks(n);
@@ -2241,13 +2247,13 @@ hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, do
         hipLaunchKernelGGL(k_alg1_iter, dim3(i == 0 && fused0 ? 1u : iter_blocks), dim3(kAlg1Threads), 0, s,
                            (const int64_t*)beg,
                            (const int64_t*)end, (const int32_t*)col, (const double*)val, (const RowInfo*)info, n, pr,
-                           i, st, cs, fused0);
+                           i, st, cs, fused0, base);
         hipLaunchKernelGGL(k_alg1_max, dim3(max_blocks), dim3(kBlock), 0, s, n, i, (const Alg1State*)st, cs);
     }
     // (finalize_only: the numeric write-out already applied the threshold; one
     // block records the final state and raises the flags)
     hipLaunchKernelGGL(k_alg1_drop_t<true>, dim3(finalize_only ? 1u : blocks), dim3(kBlock), 0, s, beg, end, col,
-                       val, info, sw, nw, n, 0.0,
+                       val, info, sw, nw, n, finalize_only ? t_dropped : 0.0,
                        part_kept, pr, iters, st, (const unsigned long long*)cs, ctr, finalize_only);
     return hipGetLastError();
 }
