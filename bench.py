@@ -252,7 +252,7 @@ def main():
 
         plan = api.Plan.series(Zd, G.exp_coeffs(59), args.eps_tol, args.e_r, flags=B.FPS_FLAG_TIMING)
         series_info = plan.series_info()
-        cfg = dict(cfg, name=cfg["name"].split("_m")[0] + f"_exp_series_tol{args.eps_tol:g}",
+        cfg = dict(cfg, name=cfg["name"].split("_m")[0] + f"_series_tol{args.eps_tol:g}",
                    m=series_info["N"] - 1, s=series_info["q"])
         log(f"series mode: N = {series_info['N']}, q = {series_info['q']}, tail = {series_info['tail']:.3g}")
     else:
