@@ -1985,6 +1985,48 @@ __global__ void __launch_bounds__(kBlock) k_alg1_max(int64_t n, int i, const Alg
     }
 }
 
+// One-iteration check for a stage whose write-out already dropped |x| <=
+// eps_g and summed those entries into cs[0, n): the candidate norm (maximum
+// column sum) and, in the last block to finish, the final state of
+// Algorithm 1 and its flags, as the iteration, maximum and final-state
+// kernels would record them.  cs[2n + 1] counts finished blocks (cleared with
+// the sums; cleared again by the last block).
+__global__ void __launch_bounds__(kBlock) k_alg1_check1(int64_t n, Alg1Params pr, Alg1State* st,
+                                                        unsigned long long* cs, StageCounters* ctr)
+{
+    __shared__ unsigned long long sh[kBlock / kWave];
+    __shared__ int last;
+    unsigned long long* mxs = cs + 2 * n;
+    unsigned long long m = 0;
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < n; g += (int64_t)gridDim.x * kBlock)
+        m = max(m, cs[g]);
+    m = group_max<kWave>(m);
+    if (lane() == 0) sh[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < kBlock / kWave; ++k) t = max(t, sh[k]);
+        if (t) atomicMax(&mxs[0], t);
+        __threadfence();
+        last = atomicAdd(&mxs[1], 1ull) == (unsigned long long)(gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();
+    const unsigned long long mx = atomicAdd(&mxs[0], 0ull);
+    const Alg1State first{pr.eps_g, 0.0, 0, 0, 0, 0};  // m_0 = 1
+    Alg1State fin = first;
+    alg1_update(fin, pr, mx);
+    const bool miss = fin.done && fin.t != pr.eps_g;  // never: a stop keeps the first threshold
+    Alg1State rec = fin;
+    rec.ok = fin.done && !miss;
+    st[0] = first;
+    st[2] = rec;
+    if (!fin.done || miss) atomicOr(&ctr->errors, kErrAlg1Pending);
+    if (rec.ok && fin.c > pr.target) atomicOr(&ctr->errors, kErrCapacity);  // iteration limit reached
+    mxs[1] = 0ull;
+}
+
 // Drops the entries with |x| <= t of every row in place (the kept entries
 // keep their order), updates end, span, amax and the structure words, and
 // writes per-block kept counts into `part_kept` (same block layout as the
@@ -2243,6 +2285,10 @@ hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, do
     const unsigned blocks = (unsigned)numeric_blocks(n);
     const unsigned iter_blocks = (unsigned)((n + kAlg1Rows - 1) / kAlg1Rows);
     const unsigned max_blocks = (unsigned)std::min<int64_t>(256, (n + kBlock - 1) / kBlock);
+    if (finalize_only && iters == 1 && base == nullptr && t_dropped == pr.eps_g) {
+        hipLaunchKernelGGL(k_alg1_check1, dim3(max_blocks), dim3(kBlock), 0, s, n, pr, st, cs, ctr);
+        return hipGetLastError();
+    }
     for (int i = 0; i < iters; ++i) {
         hipLaunchKernelGGL(k_alg1_iter, dim3(i == 0 && fused0 ? 1u : iter_blocks), dim3(kAlg1Threads), 0, s,
                            (const int64_t*)beg,
