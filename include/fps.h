@@ -137,7 +137,13 @@ typedef struct {
     int64_t resizes;              /* evaluations that had to re-size a buffer */
     double bytes_algorithmic;     /* per evaluation, summed over stages: every operand entry read once and
                                      every kept entry written once at 12 bytes (8 value + 4 column), plus
-                                     8 (n+1) bytes of row offsets per operand and output */
+                                     8 (n+1) bytes of row offsets per operand and output.  Only rows that
+                                     are computed count: a product stage whose rows were all proven
+                                     empty counts what its analysis reads (12 bytes per left-operand
+                                     entry, the 16-byte summary of each referenced row and of each
+                                     block term's row, the left operand's offsets), and one
+                                     with some rows proven empty scales its right-operand and block
+                                     bytes by the fraction of rows computed */
     double numeric_ms;            /* FPS_FLAG_TIMING: shared-memory numeric-kernel time per evaluation
                                      (all stages), averaged over the sampled evaluations since the
                                      previous fps_get_stats call (up to 64; the latest sampled one if
@@ -159,6 +165,13 @@ typedef struct {
     /* FPS_FLAG_DROP_STATS with a fixed threshold, per filtered product (0 otherwise) */
     int64_t stage_n_dropped[FPS_MAX_STAGES]; /* nonzero entries with |x| < tau removed */
     double stage_dropped_max[FPS_MAX_STAGES]; /* their largest magnitude */
+    /* how Algorithm 1 ran on each stage in the last evaluation: 0 host-driven (or no Algorithm 1),
+       1 on the device with the first iteration's sums taken in the product's write-out, 2 on the
+       device with the drop of a one-iteration stage taken in the write-out, 3 on the device with
+       the drop at the learned final threshold taken in the write-out, 4 on the device unfused */
+    int32_t stage_alg1_mode[FPS_MAX_STAGES];
+    int64_t stage_rows_skipped[FPS_MAX_STAGES]; /* output rows proven empty by the bound test */
+    double stage_bytes[FPS_MAX_STAGES]; /* algorithmic bytes of the stage (see bytes_algorithmic) */
 } fps_stats;
 
 /* ---------------------------------------------------------------------- */
@@ -216,8 +229,8 @@ fps_status fps_plan_create_ex(fps_plan *out, const fps_csr_view *Z, const double
  * or Z^T (A^T s): start vector ones/n, sign(0) = +1, among equal largest
  * |(A^T s)_i| the smallest i.  Every product accumulates in ascending index
  * order with fused multiply-adds from +0, and ||y||_1 adds |y_i| in ascending
- * order within blocks of 64 consecutive entries, then the block sums in
- * ascending order, so the result is reproducible bit for bit.  *est <= ||Z^p||_1 and *est =
+ * index order from +0, so the result is reproducible bit for bit.
+ * *est <= ||Z^p||_1 and *est =
  * ||Z^p v||_1 for v = e_{*ind} (*ind = -1: the start vector won).  Z: device
  * CSR view, checked unless FPS_FLAG_NO_VALIDATE; est, ind, iters: HOST
  * pointers (ind, iters may be NULL).  p >= 0.  Synchronises `stream`.

@@ -12,7 +12,8 @@
  *
  * What is computed (paper Section 2.1 eqs. 2-6, Section 3.1.2 eqs. 11, 13,
  * 14, Algorithm 2 with a fixed entry threshold tau in place of the adaptive
- * filter of Algorithm 1; the "simple filtering method" of Section 3.1.1):
+ * filter of Algorithm 1; the plain fixed-threshold filter that Section
+ * 3.1.1 describes before it):
  *
  *   N = m+1, q = s, b = ceil(N/q), g = [N - q(b-1) == 1]          (eq. 6)
  *   P_1 = Z,  P_{j+1} = D_tau(Z (x) P_j)                            (eq. 11)
@@ -571,6 +572,9 @@ typedef struct {
 int orc_alg1_filter(orc_csr *C, double eps_g, double e_r, int max_iter, orc_alg1_stats *st)
 {
     if (!C || !(eps_g > 0.0) || !(e_r >= 0.0) || max_iter < 1) return ORC_EINVAL;
+    /* every candidate adds at most 2^40 + 1 (its |x| <= eps_f <= eps_g) to a
+     * 64-bit column sum: exact only while a column has fewer than 2^24 entries */
+    if (C->n >= ((int64_t)1 << 24)) return ORC_EINVAL;
     orc_alg1_stats s0 = {eps_g, 0.0, 0.0, 0, 0};
     if (isinf(eps_g)) {
         if (st) *st = s0;
@@ -766,18 +770,12 @@ static void spmv_t(const orc_csr *Z, const double *x, double *y)
         for (int64_t p = Z->row_ptr[r]; p < Z->row_ptr[r + 1]; ++p) y[Z->col[p]] = fma(Z->val[p], x[r], y[Z->col[p]]);
 }
 
-/* ||y||_1 in a fixed two-level order: |y_i| added in ascending index order
- * within each block of 64 consecutive entries (the last block may be
- * shorter), then the block sums added in ascending block order. */
+/* ||y||_1 = sum_i |y_i|, added in ascending index order from +0 (the plain
+ * definition of the vector 1-norm, one rounding per addition). */
 static double vec_norm1(const double *y, int64_t n)
 {
     double s = 0.0;
-    for (int64_t b = 0; b < n; b += 64) {
-        double t = 0.0;
-        const int64_t e = (b + 64 < n) ? b + 64 : n;
-        for (int64_t i = b; i < e; ++i) t = t + fabs(y[i]);
-        s = s + t;
-    }
+    for (int64_t i = 0; i < n; ++i) s = s + fabs(y[i]);
     return s;
 }
 

@@ -67,6 +67,9 @@ class fps_stats(C.Structure):
         ("stage_alg1_iters", C.c_int32 * FPS_MAX_STAGES),
         ("stage_n_dropped", C.c_int64 * FPS_MAX_STAGES),
         ("stage_dropped_max", C.c_double * FPS_MAX_STAGES),
+        ("stage_alg1_mode", C.c_int32 * FPS_MAX_STAGES),
+        ("stage_rows_skipped", C.c_int64 * FPS_MAX_STAGES),
+        ("stage_bytes", C.c_double * FPS_MAX_STAGES),
     ]
 
 

@@ -189,6 +189,9 @@ struct Workspace {
     }
 };
 
+// Largest n (exclusive) for the exact integer column sums of Algorithm 1.
+constexpr int64_t kColSumMaxN = int64_t(1) << 24;
+
 enum class Kind { Power = FPS_STAGE_POWER, Block = FPS_STAGE_BLOCK, GStep = FPS_STAGE_GSTEP, Horner = FPS_STAGE_HORNER };
 
 constexpr int kTimingRing = 64;   // sampled evaluations whose kernel times are kept
@@ -204,6 +207,7 @@ struct StageRecord {
     double eps_g = 0.0, threshold = 0.0, dropped = 0.0;
     int alg1_iters = 0;
     bool alg1_device = false;  // the record is in the device state (Engine::alg1_state)
+    int alg1_mode = 0;         // fps_stats.stage_alg1_mode
     bool wide_rows = false;    // every row of the stage ran in the wide shared-memory tier
 };
 
@@ -497,6 +501,7 @@ struct Engine {
             rec->dropped = 0.0;
             rec->alg1_iters = 0;
             rec->alg1_device = false;
+            rec->alg1_mode = 0;
         }
         if (!std::isfinite(eps_g)) return FPS_OK;  // an unbounded budget filters nothing
         FPS_TRY(colsum.ensure(sizeof(unsigned long long) * (size_t)(2 * n + 3)));
@@ -521,7 +526,10 @@ struct Engine {
                                        cs, part(idx) + (size_t)kPartKept * (size_t)ws.part_stride, ctr(idx),
                                        (fused == 1 || fused == 2) ? 1 : 0, fused >= 2 ? 1 : 0, alg1_spec_t, base,
                                        s));
-            if (rec) rec->alg1_device = true;
+            if (rec) {
+                rec->alg1_device = true;
+                rec->alg1_mode = fused ? fused : 4;
+            }
             return FPS_OK;
         }
         double m = 1.0, t = 0.0, c = 0.0;
@@ -606,7 +614,7 @@ fps_status validate_on_device(const fps_csr_view* v, const char* what, hipStream
 // rows of Z in ascending order, and the vectors of the iteration.
 struct EstWork {
     int64_t n = 0;
-    DevBuf trp, trow, tval, trow_tmp, tval_tmp, cnt, x, y, t0, t1, s, s_old, zt, small, bsum;
+    DevBuf trp, trow, tval, trow_tmp, tval_tmp, cnt, x, y, t0, t1, s, s_old, zt, small;
 
     fps_status init(const fps_csr_view* Z, hipStream_t st)
     {
@@ -620,7 +628,6 @@ struct EstWork {
         FPS_TRY(cnt.ensure(sizeof(unsigned long long) * nn));
         for (DevBuf* b : {&x, &y, &t0, &t1, &s, &s_old, &zt}) FPS_TRY(b->ensure(sizeof(double) * nn));
         FPS_TRY(small.ensure(64));
-        FPS_TRY(bsum.ensure(sizeof(double) * (nn / 64 + 1)));
         HIP_TRY(launch_transpose(Z->row_ptr, Z->col, Z->val, n, Z->nnz, cnt.as<unsigned long long>(),
                                  trp.as<int64_t>(), trow_tmp.as<int32_t>(), tval_tmp.as<double>(), trow.as<int32_t>(),
                                  tval.as<double>(), st));
@@ -665,7 +672,7 @@ struct EstWork {
         int k = 0;
         for (k = 1;; ++k) {
             FPS_TRY(apply(Z, p, false, xv, yv, st));
-            HIP_TRY(launch_abs_sum_ordered(yv, n, bsum.as<double>(), est_d, st));
+            HIP_TRY(launch_abs_sum_ordered(yv, n, est_d, st));
             HIP_TRY(hipMemcpyAsync(&est, est_d, sizeof(double), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             if (est > est_old || k == 2) ind_best = ind;
@@ -894,6 +901,7 @@ struct fps_plan_s {
             r->eps_g = r->threshold = r->dropped = 0.0;
             r->alg1_iters = 0;
             r->alg1_device = false;
+            r->alg1_mode = 0;
             r->wide_rows = false;
             r->ev0 = r->ev1 = nullptr;
             if (timing_now) {
@@ -1052,6 +1060,12 @@ fps_status fps_plan_create_ex(fps_plan* out, const fps_csr_view* Z, const double
     } else {
         return set_error(FPS_ERR_INVALID_ARG, "unknown filter %d", opts->filter);
     }
+    // The integer column sums of Algorithm 1 and of the dropped-entry
+    // statistics add at most 2^40 + 1 per entry into 64 bits: exact while a
+    // column holds fewer than 2^24 entries, which n < 2^24 guarantees.
+    if ((adaptive || (flags & FPS_FLAG_DROP_STATS)) && Z->n >= kColSumMaxN)
+        return set_error(FPS_ERR_CAPACITY, "n = %lld: Algorithm 1 and FPS_FLAG_DROP_STATS need n < 2^24",
+                         (long long)Z->n);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (!(flags & FPS_FLAG_NO_VALIDATE)) FPS_TRY(validate_on_device(Z, "Z", st));
 
@@ -1226,6 +1240,8 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
         st->stage_threshold[i] = r.threshold;
         st->stage_dropped[i] = r.dropped;
         st->stage_alg1_iters[i] = r.alg1_iters;
+        st->stage_alg1_mode[i] = r.alg1_mode;
+        st->stage_rows_skipped[i] = (int64_t)tot[(size_t)i][kPartRowsSkipped];
         if (r.alg1_device) {
             const Alg1State& f = a1[(size_t)i * 3 + 2];
             st->stage_threshold[i] = f.t;
@@ -1248,20 +1264,33 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
         st->rows_global += (int64_t)c[(size_t)i].fb2_count;
         st->rows_wide += r.wide_rows ? p->Z.n - (int64_t)c[(size_t)i].fb2_count : (int64_t)c[(size_t)i].rows_wide;
         const double za = (double)p->Z.nnz;
+        double sb = 0.0;
         if (r.kind == FPS_STAGE_POWER || r.kind == FPS_STAGE_HORNER) {
             const double na = r.a_is_z ? za : (r.a_src >= 0 ? kept(r.a_src) : 0.0);
             const double nb = r.b_is_z ? za : (r.b_src >= 0 ? kept(r.b_src) : 0.0);
             const double ne = r.e_src >= 0 ? kept(r.e_src) : 0.0;
             double nt = 0.0;  // fused block terms
             for (int src : r.term_src) nt += (src < 0) ? za : kept(src);
-            const double operands = 3.0 + (r.e_src >= 0 ? 1.0 : 0.0) + (double)r.term_src.size();
-            bytes += 12.0 * (na + nb + ne + nt + kept(i)) + 8.0 * n1 * operands;
+            const double skipped = (double)tot[(size_t)i][kPartRowsSkipped];
+            const double n0 = (double)p->Z.n;
+            if (n0 > 0.0 && skipped >= n0) {
+                // every row proven empty: the analysis reads the left operand,
+                // the 16-byte summary of each referenced row and of each block
+                // term's row, nothing else
+                sb = 12.0 * na + 16.0 * na + 16.0 * n0 * (double)r.term_src.size() + 8.0 * n1;
+            } else {
+                const double f = n0 > 0.0 ? (n0 - skipped) / n0 : 1.0;
+                const double operands = 3.0 + (r.e_src >= 0 ? 1.0 : 0.0) + (double)r.term_src.size();
+                sb = 12.0 * (na + f * (nb + ne + nt) + kept(i)) + 8.0 * n1 * operands;
+            }
         } else {
             // coefficient sum: every stored term matrix read once, the sum written once
             double in = 0.0;
             for (int src : r.term_src) in += (src < 0) ? za : kept(src);
-            bytes += 12.0 * (in + kept(i)) + 8.0 * n1 * (double)(r.term_src.size() + 1);
+            sb = 12.0 * (in + kept(i)) + 8.0 * n1 * (double)(r.term_src.size() + 1);
         }
+        st->stage_bytes[i] = sb;
+        bytes += sb;
         if (!p->ring.empty()) {
             // average over the sampled evaluations since the last query (the
             // latest sampled one if none)
@@ -1500,6 +1529,8 @@ fps_status fps_plan_create_series(fps_plan* out, const fps_csr_view* Z, const do
     for (int i = 0; i < L; ++i)
         if (!std::isfinite(a[i])) return set_error(FPS_ERR_INVALID_ARG, "coefficient %d is not finite", i);
     FPS_TRY(check_view(Z, "Z", -1));
+    if (Z->n >= kColSumMaxN)
+        return set_error(FPS_ERR_CAPACITY, "n = %lld: series mode (Algorithm 1) needs n < 2^24", (long long)Z->n);
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (!(flags & FPS_FLAG_NO_VALIDATE)) FPS_TRY(validate_on_device(Z, "Z", st));
     // Algorithm 2 steps 1-3

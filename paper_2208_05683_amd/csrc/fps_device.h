@@ -249,9 +249,8 @@ hipError_t launch_transpose(const int64_t* rp, const int32_t* col, const double*
                             double* tval, hipStream_t s);
 hipError_t launch_spmv(const int64_t* rp, const int32_t* col, const double* val, int64_t n, const double* x, double* y,
                        hipStream_t s);
-// ||y||_1: sums of |y_i| over blocks of 64 consecutive entries in ascending
-// order (block_sums: ceil(n / 64) entries), then those sums in ascending order
-hipError_t launch_abs_sum_ordered(const double* y, int64_t n, double* block_sums, double* out, hipStream_t s);
+// ||y||_1 = sum of |y_i| in ascending index order from +0 (one wavefront)
+hipError_t launch_abs_sum_ordered(const double* y, int64_t n, double* out, hipStream_t s);
 hipError_t launch_sign(const double* y, int64_t n, const double* s_old, int check, double* sv, unsigned int* flags,
                        hipStream_t s);
 hipError_t launch_absmax(const double* h, int64_t n, unsigned long long* res, hipStream_t s);

@@ -108,25 +108,11 @@ __global__ void __launch_bounds__(kB) k_spmv(const int64_t* __restrict__ rp, con
     y[r] = acc;
 }
 
-// ||y||_1 in two levels: bs[b] = sum of |y_i| over the block of 64
-// consecutive entries b, in ascending i (one thread per block)
-constexpr int kNormBlock = 64;
-__global__ void __launch_bounds__(kB) k_abs_block_sums(const double* __restrict__ y, int64_t n, double* bs)
-{
-    const int64_t b = (int64_t)blockIdx.x * kB + threadIdx.x;
-    const int64_t i0 = b * kNormBlock;
-    if (i0 >= n) return;
-    const int64_t i1 = min(i0 + (int64_t)kNormBlock, n);
-    double t = 0.0;
-    for (int64_t i = i0; i < i1; ++i) t = t + fabs(y[i]);
-    bs[b] = t;
-}
-
-// then the sum of the block sums in ascending order by one wavefront: 64
-// values at a time go through shared memory (the next 64 already loading),
-// and every lane runs the same chain of additions on broadcast reads of them
-// in order; the padding past n adds +0, which leaves a sum of nonnegative
-// terms unchanged
+// ||y||_1 = sum_i |y_i| added in ascending index order from +0, by one
+// wavefront: 64 values at a time go through shared memory (the next 64
+// already loading), and every lane runs the same chain of additions on
+// broadcast reads of them in order; the padding past n adds +0, which leaves
+// a sum of nonnegative terms unchanged
 __global__ void __launch_bounds__(kWave) k_abs_sum_ordered(const double* __restrict__ y, int64_t n, double* out)
 {
     __shared__ double buf[kWave];
@@ -230,11 +216,9 @@ hipError_t launch_spmv(const int64_t* rp, const int32_t* col, const double* val,
     return hipGetLastError();
 }
 
-hipError_t launch_abs_sum_ordered(const double* y, int64_t n, double* block_sums, double* out, hipStream_t s)
+hipError_t launch_abs_sum_ordered(const double* y, int64_t n, double* out, hipStream_t s)
 {
-    const int64_t nb = (n + kNormBlock - 1) / kNormBlock;
-    if (nb > 0) hipLaunchKernelGGL(k_abs_block_sums, dim3(grid_for(nb)), dim3(kB), 0, s, y, n, block_sums);
-    hipLaunchKernelGGL(k_abs_sum_ordered, dim3(1), dim3(kWave), 0, s, block_sums, nb, out);
+    hipLaunchKernelGGL(k_abs_sum_ordered, dim3(1), dim3(kWave), 0, s, y, n, out);
     return hipGetLastError();
 }
 

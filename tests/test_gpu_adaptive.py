@@ -32,7 +32,20 @@ def znorms(Z, m, s):
     return z
 
 
-def compare_adaptive(Z, c, m, s, eps, e_r=0.1, flags=0, what="", z=None, device_iters=0):
+def check_records(gst, a1):
+    prod = [i for i, k in enumerate(gst["kind"]) if k in (0, 3)]
+    assert [gst["stage_eps_g"][i] for i in prod] == [x["eps_g"] for x in a1]
+    assert [gst["stage_threshold"][i] for i in prod] == [x["threshold"] for x in a1]
+    assert [gst["stage_alg1_iters"][i] for i in prod] == [x["iters"] for x in a1]
+    assert [gst["stage_dropped"][i] for i in prod] == [x["dropped"] for x in a1]
+    return prod
+
+
+def compare_adaptive(Z, c, m, s, eps, e_r=0.1, flags=0, what="", z=None, device_iters=0, evals=1):
+    """Every evaluation on one plan must equal the oracle bit for bit; with
+    evals > 1 the later ones run Algorithm 1 on the device with the drops
+    taken in the write-out (the path the benchmark times), and must do so
+    without a repeated evaluation."""
     from paper_2208_05683_amd import api
 
     if z is None:
@@ -41,18 +54,20 @@ def compare_adaptive(Z, c, m, s, eps, e_r=0.1, flags=0, what="", z=None, device_
     plan = api.Plan(upload(Z), c, m, s, adaptive=True, eps=eps, e_r=e_r, znorm=z, flags=flags,
                     alg1_device_iters=device_iters)
     try:
-        plan.eval()
-        got = download(plan.result())
-        gst = plan.stats()
+        for e in range(evals):
+            plan.eval()
+            got = download(plan.result())
+            gst = plan.stats()
+            check_canonical(got)
+            assert_same_csr(got, want, f"{what} eval {e}")
+            prod = check_records(gst, a1)
+            if e >= 1 and device_iters == 0:
+                assert gst["resizes"] == 0, f"{what}: evaluation {e} was repeated"
+                modes = [gst["stage_alg1_mode"][i] for i in prod]
+                finite = [i for i, x in enumerate(a1) if np.isfinite(x["eps_g"])]
+                assert all(modes[i] in (1, 2, 3) for i in finite), (what, modes)
     finally:
         plan.close()
-    check_canonical(got)
-    assert_same_csr(got, want, what)
-    prod = [i for i, k in enumerate(gst["kind"]) if k in (0, 3)]
-    assert [gst["stage_eps_g"][i] for i in prod] == [x["eps_g"] for x in a1]
-    assert [gst["stage_threshold"][i] for i in prod] == [x["threshold"] for x in a1]
-    assert [gst["stage_alg1_iters"][i] for i in prod] == [x["iters"] for x in a1]
-    assert [gst["stage_dropped"][i] for i in prod] == [x["dropped"] for x in a1]
     return got, want, a1, gst
 
 
@@ -72,9 +87,13 @@ def test_adaptive_full_size_lap2d():
     Algorithm 1 at eps = 1e-12: the late products' rows span more columns than
     a block's shared-memory column sums hold, so both ways of summing run."""
     got, want, a1, gst = compare_adaptive(G.laplacian_2d(200, 2.0), G.exp_coeffs(30), 30, 6, 1e-12,
-                                          what="lap2d 200 x 200")
+                                          what="lap2d 200 x 200", evals=3)
     assert got.nnz == want.nnz > 10_000_000
     assert max(x["iters"] for x in a1) >= 3
+    # the third evaluation dropped one-iteration stages and the others at the
+    # learned final threshold in the write-out
+    modes = [gst["stage_alg1_mode"][i] for i, k in enumerate(gst["kind"]) if k in (0, 3)]
+    assert 2 in modes and 3 in modes, modes
 
 
 def test_adaptive_operand_change_between_evaluations():
@@ -97,6 +116,9 @@ def test_adaptive_operand_change_between_evaluations():
     want2, _, a2 = O.filtered_ps_adaptive(Z2, c, m, s, eps, 0.1, z)
     it1, it2 = [x["iters"] for x in a1], [x["iters"] for x in a2]
     assert any(p == 1 and q > 1 for p, q in zip(it1, it2))
+    # a stage learned at two or more iterations (dropped at its learned final
+    # threshold) ends at another threshold on the scaled operand
+    assert any(p >= 2 and x["threshold"] != y["threshold"] for p, x, y in zip(it1, a1, a2))
     Zd = upload(Z1)
     plan = api.Plan(Zd, c, m, s, adaptive=True, eps=eps, e_r=0.1, znorm=z)
     try:

@@ -1,10 +1,12 @@
-"""The 3D configuration at its full size (50^3 grid plus random long-range
+"""The 3D configuration: at its full size (50^3 grid plus random long-range
 links, n = 125,000) on the GPU, stage by stage: its Horner steps are beyond
 any CPU oracle (about 1e14 multiply-adds each), but its filtered powers are
 not.  P_2 = D(Z Z) and P_3 = D(Z P_2) are compared with the oracle element by
 element, and P_4 = D(Z P_3) on 1000 sampled rows, which the oracle computes
 from its own P_3 (rows of P_4 hold about 5,400 entries: the device-memory
-kernel at full scale)."""
+kernel at full scale).  End to end (every Horner step and F) it is compared
+bit for bit on 12^3 and 14^3 grids, with the oracle run inside the test, and
+on a 20^3 grid (n = 8000) against a stored digest of the oracle's result."""
 
 import numpy as np
 import pytest
@@ -68,3 +70,55 @@ def test_lap3d_full_size_powers():
     got4 = _device_rows(g4, rows)
     assert_same_csr(got4, P4s, "P_4 at 50^3, sampled rows")
     assert np.diff(P4s.row_ptr)[rows].mean() > 448  # beyond both shared-memory tiers
+
+
+# ---------------------------------------------------------------------------
+# the 3D workload end to end on smaller grids (its rows fill in to dense)
+# ---------------------------------------------------------------------------
+
+def _sparse_path_flags():
+    """Flags that keep every stage on the ordered sparse path (the bitwise one)."""
+    from paper_2208_05683_amd import binding as B
+
+    return getattr(B, "FPS_FLAG_NO_DENSE", 0)
+
+
+@pytest.mark.parametrize("side", [12, 14])
+def test_lap3d_end_to_end_bitwise(side):
+    # every Horner step and F, against the oracle computed here
+    from gpu_helpers import gpu_filtered_ps
+
+    cfg = G.config3(side=side)
+    Z, c, m, s, tau = cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"]
+    want, st = O.filtered_ps(Z, c, m, s, tau)
+    outs, gst = gpu_filtered_ps(Z, c, m, s, tau, flags=_sparse_path_flags(), evals=2)
+    for i, got in enumerate(outs):
+        check_canonical(got)
+        assert_same_csr(got, want, f"3d {side}^3 eval {i}")
+    assert want.nnz > 0.9 * Z.n * Z.n  # F is dense
+    assert gst["rows_global"] > 0
+
+
+def test_lap3d_side20_against_stored_digest():
+    # n = 8000: the oracle takes minutes, so its result is stored as a digest
+    # written by tests/golden/make_lap3d_digest.py (which calls only the oracle)
+    import hashlib
+    import json
+    import os
+
+    from gpu_helpers import gpu_filtered_ps
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "lap3d_side20_cos_m24_s5.json")
+    with open(path) as f:
+        ref = json.load(f)
+    cfg = G.config3(side=20)
+    Z, c, m, s, tau = cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"]
+    assert Z.n == ref["n"] == 8000
+    got, gst = gpu_filtered_ps(Z, c, m, s, tau, flags=_sparse_path_flags())
+    check_canonical(got)
+    assert got.nnz == ref["nnz"]
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(got.row_ptr, dtype="<i8").tobytes())
+    h.update(np.ascontiguousarray(got.col, dtype="<i4").tobytes())
+    h.update(np.ascontiguousarray(got.val, dtype="<f8").tobytes())
+    assert h.hexdigest() == ref["sha256"]

@@ -66,5 +66,10 @@ def test_random_modes_repeated(seed):
             got = download(plan.result())
             check_canonical(got)
             assert_same_csr(got, want, f"{what}, evaluation {k}")
+            if k == 0:
+                resizes0 = plan.stats()["resizes"]
+        # on a fixed operand no later evaluation is repeated (a speculative
+        # Algorithm 1 drop that always missed would double the cost silently)
+        assert plan.stats()["resizes"] == resizes0, what
     finally:
         plan.close()

@@ -39,6 +39,11 @@ MUTANTS = {
     "fnt_wrong_power_norm": ("d = d + z[q * (b - 1 - j)] * (beta + z[q - k] * sprev);",
                              "d = d + z[q * (b - 1 - j)] * (beta + z[q - k + 1] * sprev);"),
     "fnt_budget_not_shared": ("zeta[k] = eps / (d * M);", "zeta[k] = eps / d;"),
+    "fnt_beta_power_shift": ("beta = beta + A_(i * q + kk) * z[kk - k];", "beta = beta + A_(i * q + kk) * z[kk - k + 1];"),
+    "fnt_state_norm_no_power": ("ns[i] = nb[b - 1 - i] + z[q] * ns[i - 1];", "ns[i] = nb[b - 1 - i] + ns[i - 1];"),
+    "fnt_sigma_weight_shift": ("sigma[j] = eps / (z[q * (b - 1 - j)] * M);",
+                               "sigma[j] = eps / (z[q * (b - 1 - j) + (j > 0)] * M);"),
+    "alg1_norm_rounded_down": ("cs[C->col[p]] += (uint64_t)ceil(a * s);", "cs[C->col[p]] += (uint64_t)floor(a * s);"),
     "adaptive_horner_unfiltered": ("if (rc == ORC_OK) rc = orc_alg1_filter(&T, sigma[i], e_r, 200, &a1);",
                                    "if (rc == ORC_OK) rc = orc_alg1_filter(&T, INFINITY, e_r, 200, &a1);"),
     "normest_no_transpose": ("apply_power(Z, p, 1, s, zt, tmp);", "apply_power(Z, p, 0, s, zt, tmp);"),
@@ -84,6 +89,7 @@ def test_planted_mistake_is_caught(name, tmp_path):
                     "-o", str(lib), str(mut), "-lm"], check=True)
     env = dict(os.environ, ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_exact.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"
