@@ -21,6 +21,12 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python -m paper_2208_05683_amd.build` "
         "(hipcc, gfx950); there is no non-HIP implementation")
 
+# torch first: it loads its own HIP runtime, whose soname (libamdhip64.so.7)
+# then satisfies libfps.so's dependency, so the process holds one HIP runtime.
+# Loading libfps.so first would pull in the system runtime as well, and the
+# library's calls would then run on a second runtime that finds no device.
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 

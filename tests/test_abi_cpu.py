@@ -151,3 +151,18 @@ def test_series_entry_points_reject_bad_arguments_on_the_host(B):
     assert lib.fps_power_norm_bounds(C.byref(v), 3, 3, z, 0, None) == B.FPS_ERR_INVALID_ARG
     assert lib.fps_power_norm_bounds(C.byref(v), 10, -1, z, 0, None) == B.FPS_ERR_INVALID_ARG
     assert lib.fps_plan_series_info(None, None, None, None, None, None) == B.FPS_ERR_INVALID_ARG
+
+
+def test_binding_shares_torchs_hip_runtime():
+    # importing the binding before torch must still leave one HIP runtime in
+    # the process (libfps.so binds to the one torch loads)
+    import subprocess
+    import sys
+
+    code = ("from paper_2208_05683_amd import binding\n"
+            "import torch, re\n"
+            "m = open('/proc/self/maps').read()\n"
+            "print(len(set(re.findall(r'\\S*libamdhip64\\S*', m))))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
