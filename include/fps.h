@@ -239,6 +239,26 @@ fps_status fps_normest1(const fps_csr_view *Z, int32_t p, double *est, int64_t *
                         fps_stream stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * estimate as fps_normest1, bit for bit, with every piece of device workspace
+ * (the transpose of Z, the iteration vectors, the validation flag) in a
+ * static buffer of the library instead of allocations.  The buffer holds
+ * about 16.5 MiB per GPU (sized for FPS_NOALLOC_MAX_N rows and
+ * FPS_NOALLOC_MAX_NNZ entries), is set up on the first call on each device
+ * and kept until the process ends; no call allocates or frees device memory.
+ * FPS_ERR_CAPACITY if n > FPS_NOALLOC_MAX_N or nnz > FPS_NOALLOC_MAX_NNZ.
+ * Every call on one GPU uses the same buffer: calls that overlap on one GPU
+ * (from several host threads, or on several streams without ordering between
+ * them) race and give undefined results.  Arguments, synchronisation and
+ * errors as for fps_normest1.
+ */
+#define FPS_NOALLOC_MAX_N 65536
+#define FPS_NOALLOC_MAX_NNZ 524288
+fps_status fps_normest1_noalloc(const fps_csr_view *Z, int32_t p, double *est, int64_t *ind, int32_t *iters,
+                                uint64_t flags, fps_stream stream);
+
+/*
  * Norm bounds of eq. 37 into the HOST array z[0..tmax]: z[0] = 1,
  * z[i] = fps_normest1(Z, i) for 1 <= i <= K, z[i] = alpha^i for i > K with
  * alpha = max over k = K/2..K of z[k]^(1/k) (Lemma 1).  K even and >= 2 (the

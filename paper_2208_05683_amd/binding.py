@@ -126,6 +126,8 @@ _SIGS = {
     "fps_matrix_destroy": (None, [_vp]),
     "fps_normest1": (C.c_int32, [_P(fps_csr_view), C.c_int32, _P(C.c_double), _P(C.c_int64), _P(C.c_int32),
                                  C.c_uint64, _vp]),
+    "fps_normest1_noalloc": (C.c_int32, [_P(fps_csr_view), C.c_int32, _P(C.c_double), _P(C.c_int64),
+                                         _P(C.c_int32), C.c_uint64, _vp]),
     "fps_power_norm_bounds": (C.c_int32, [_P(fps_csr_view), C.c_int32, C.c_int32, _P(C.c_double), C.c_uint64, _vp]),
     "fps_plan_create_series": (C.c_int32, [_P(_vp), _P(fps_csr_view), _P(C.c_double), C.c_int32,
                                            _P(fps_series_opts), C.c_uint64, _vp]),
@@ -291,6 +293,13 @@ def fps_normest1(Z: fps_csr_view, p: int, flags: int = 0, stream=None) -> dict:
     est, ind, it = C.c_double(), C.c_int64(), C.c_int32()
     _check(_lib.fps_normest1(C.byref(Z), int(p), C.byref(est), C.byref(ind), C.byref(it), C.c_uint64(flags),
                              _stream_handle(stream)), "fps_normest1")
+    return {"est": est.value, "ind": ind.value, "iters": it.value}
+
+
+def fps_normest1_noalloc(Z: fps_csr_view, p: int, flags: int = 0, stream=None) -> dict:
+    est, ind, it = C.c_double(), C.c_int64(), C.c_int32()
+    _check(_lib.fps_normest1_noalloc(C.byref(Z), int(p), C.byref(est), C.byref(ind), C.byref(it),
+                                     C.c_uint64(flags), _stream_handle(stream)), "fps_normest1_noalloc")
     return {"est": est.value, "ind": ind.value, "iters": it.value}
 
 

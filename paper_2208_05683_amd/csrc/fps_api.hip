@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -595,14 +596,20 @@ fps_status check_view(const fps_csr_view* v, const char* what, int64_t n_expect)
     return FPS_OK;
 }
 
-fps_status validate_on_device(const fps_csr_view* v, const char* what, hipStream_t s)
+// Checks a CSR view on the device; the error flag lives in `flag` (8 bytes of
+// device memory) when given, else in a buffer allocated here.
+fps_status validate_on_device(const fps_csr_view* v, const char* what, hipStream_t s,
+                              unsigned long long* flag = nullptr)
 {
     DevBuf err;
-    FPS_TRY(err.ensure(sizeof(unsigned long long)));
-    HIP_TRY(hipMemsetAsync(err.p, 0, sizeof(unsigned long long), s));
-    HIP_TRY(launch_validate_csr(v->row_ptr, v->col, v->val, v->n, v->nnz, err.as<unsigned long long>(), s));
+    if (!flag) {
+        FPS_TRY(err.ensure(sizeof(unsigned long long)));
+        flag = err.as<unsigned long long>();
+    }
+    HIP_TRY(launch_fill_u64(flag, 1, 0ull, s));
+    HIP_TRY(launch_validate_csr(v->row_ptr, v->col, v->val, v->n, v->nnz, flag, s));
     unsigned long long h = 0;
-    HIP_TRY(hipMemcpyAsync(&h, err.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (h) return set_error(FPS_ERR_BAD_CSR, "%s is not a canonical CSR (row pointers, sorted in-range columns, finite values)", what);
     return FPS_OK;
@@ -611,26 +618,55 @@ fps_status validate_on_device(const fps_csr_view* v, const char* what, hipStream
 // ---- 1-norm estimator and norm bounds (series mode, Section 3.2.2) --------------
 
 // Device workspace of the estimator on Z: Z^T as a CSR whose rows list the
-// rows of Z in ascending order, and the vectors of the iteration.
+// rows of Z in ascending order, and the vectors of the iteration.  The pieces
+// are carved from one region, either owned by the workspace or given by the
+// caller (fps_normest1_noalloc), at 256-byte boundaries.
+constexpr size_t est_align(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t est_bytes(int64_t n, int64_t nnz)
+{
+    const size_t nn = (size_t)(n > 0 ? n : 1), nz = (size_t)(nnz > 0 ? nnz : 1);
+    return est_align(sizeof(int64_t) * (nn + 1)) + 2 * est_align(sizeof(int32_t) * nz) +
+           2 * est_align(sizeof(double) * nz) + est_align(sizeof(unsigned long long) * nn) +
+           7 * est_align(sizeof(double) * nn) + est_align(64);
+}
+
 struct EstWork {
     int64_t n = 0;
-    DevBuf trp, trow, tval, trow_tmp, tval_tmp, cnt, x, y, t0, t1, s, s_old, zt, small;
+    DevBuf own;
+    int64_t* trp = nullptr;
+    int32_t *trow = nullptr, *trow_tmp = nullptr;
+    double *tval = nullptr, *tval_tmp = nullptr;
+    unsigned long long* cnt = nullptr;
+    double *x = nullptr, *y = nullptr, *t0 = nullptr, *t1 = nullptr, *s = nullptr, *s_old = nullptr, *zt = nullptr;
+    char* small = nullptr;
 
     fps_status init(const fps_csr_view* Z, hipStream_t st)
     {
+        FPS_TRY(own.ensure(est_bytes(Z->n, Z->nnz)));
+        return init_at(Z, own.p, st);
+    }
+
+    // Carves the workspace from `base` (est_bytes(n, nnz) bytes of device
+    // memory) and builds Z^T there; allocates nothing.
+    fps_status init_at(const fps_csr_view* Z, void* base, hipStream_t st)
+    {
         n = Z->n;
         const size_t nn = (size_t)n, nz = (size_t)std::max<int64_t>(Z->nnz, 1);
-        FPS_TRY(trp.ensure(sizeof(int64_t) * (nn + 1)));
-        FPS_TRY(trow.ensure(sizeof(int32_t) * nz));
-        FPS_TRY(tval.ensure(sizeof(double) * nz));
-        FPS_TRY(trow_tmp.ensure(sizeof(int32_t) * nz));
-        FPS_TRY(tval_tmp.ensure(sizeof(double) * nz));
-        FPS_TRY(cnt.ensure(sizeof(unsigned long long) * nn));
-        for (DevBuf* b : {&x, &y, &t0, &t1, &s, &s_old, &zt}) FPS_TRY(b->ensure(sizeof(double) * nn));
-        FPS_TRY(small.ensure(64));
-        HIP_TRY(launch_transpose(Z->row_ptr, Z->col, Z->val, n, Z->nnz, cnt.as<unsigned long long>(),
-                                 trp.as<int64_t>(), trow_tmp.as<int32_t>(), tval_tmp.as<double>(), trow.as<int32_t>(),
-                                 tval.as<double>(), st));
+        char* c = static_cast<char*>(base);
+        auto take = [&](size_t bytes) {
+            char* r = c;
+            c += est_align(bytes);
+            return r;
+        };
+        trp = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (nn + 1)));
+        trow = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * nz));
+        trow_tmp = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * nz));
+        tval = reinterpret_cast<double*>(take(sizeof(double) * nz));
+        tval_tmp = reinterpret_cast<double*>(take(sizeof(double) * nz));
+        cnt = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long) * nn));
+        for (double** v : {&x, &y, &t0, &t1, &s, &s_old, &zt}) *v = reinterpret_cast<double*>(take(sizeof(double) * nn));
+        small = take(64);
+        HIP_TRY(launch_transpose(Z->row_ptr, Z->col, Z->val, n, Z->nnz, cnt, trp, trow_tmp, tval_tmp, trow, tval, st));
         return FPS_OK;
     }
 
@@ -641,12 +677,12 @@ struct EstWork {
             HIP_TRY(hipMemcpyAsync(out, in, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, st));
             return FPS_OK;
         }
-        const int64_t* rp = transpose ? trp.as<int64_t>() : Z->row_ptr;
-        const int32_t* cl = transpose ? trow.as<int32_t>() : Z->col;
-        const double* vl = transpose ? tval.as<double>() : Z->val;
+        const int64_t* rp = transpose ? trp : Z->row_ptr;
+        const int32_t* cl = transpose ? trow : Z->col;
+        const double* vl = transpose ? tval : Z->val;
         const double* cur = in;
         for (int i = 0; i < p; ++i) {
-            double* dst = (i == p - 1) ? out : ((i % 2) ? t1.as<double>() : t0.as<double>());
+            double* dst = (i == p - 1) ? out : ((i % 2) ? t1 : t0);
             HIP_TRY(launch_spmv(rp, cl, vl, n, cur, dst, st));
             cur = dst;
         }
@@ -658,14 +694,14 @@ struct EstWork {
     fps_status normest1(const fps_csr_view* Z, int p, double* est_out, int64_t* ind_out, int* iters, hipStream_t st)
     {
         const int itmax = 5;
-        double* xv = x.as<double>();
-        double* yv = y.as<double>();
-        double* sv = s.as<double>();
-        double* sov = s_old.as<double>();
-        double* hv = zt.as<double>();
-        double* est_d = small.as<double>();
-        unsigned int* flags = reinterpret_cast<unsigned int*>(small.as<char>() + 8);
-        unsigned long long* res = reinterpret_cast<unsigned long long*>(small.as<char>() + 16);
+        double* xv = x;
+        double* yv = y;
+        double* sv = s;
+        double* sov = s_old;
+        double* hv = zt;
+        double* est_d = reinterpret_cast<double*>(small);
+        unsigned int* flags = reinterpret_cast<unsigned int*>(small + 8);
+        unsigned long long* res = reinterpret_cast<unsigned long long*>(small + 16);
         HIP_TRY(launch_fill_f64(xv, n, 1.0 / (double)n, st));
         double est = 0.0, est_old = 0.0;
         int64_t ind = -1, ind_best = -1;
@@ -682,8 +718,8 @@ struct EstWork {
             }
             est_old = est;
             if (k > itmax) break;
-            const unsigned int ones[2] = {1u, 1u};
-            HIP_TRY(hipMemcpyAsync(flags, ones, sizeof(ones), hipMemcpyHostToDevice, st));
+            // both flags set (two 32-bit ones) by a fill kernel, no host copy
+            HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(flags), 1, 0x0000000100000001ull, st));
             HIP_TRY(launch_sign(yv, n, sov, k >= 2 ? 1 : 0, sv, flags, st));
             if (k >= 2) {  // the new sign vector parallel to the previous one
                 unsigned int f[2] = {0u, 0u};
@@ -693,8 +729,8 @@ struct EstWork {
             }
             std::swap(sv, sov);  // sov: the current sign vector
             FPS_TRY(apply(Z, p, true, sov, hv, st));
-            const unsigned long long init[2] = {0ull, ~0ull};
-            HIP_TRY(hipMemcpyAsync(res, init, sizeof(init), hipMemcpyHostToDevice, st));
+            HIP_TRY(launch_fill_u64(res, 1, 0ull, st));
+            HIP_TRY(launch_fill_u64(res + 1, 1, ~0ull, st));
             HIP_TRY(launch_absmax(hv, n, res, st));
             unsigned long long r[2] = {0ull, 0ull};
             double hbest = 0.0;
@@ -1491,6 +1527,70 @@ fps_status fps_normest1(const fps_csr_view* Z, int32_t p, double* est, int64_t* 
     if (!(flags & FPS_FLAG_NO_VALIDATE)) FPS_TRY(validate_on_device(Z, "Z", st));
     EstWork w;
     FPS_TRY(w.init(Z, st));
+    int it = 0;
+    FPS_TRY(w.normest1(Z, p, est, ind, &it, st));
+    if (iters) *iters = it;
+    return FPS_OK;
+}
+
+}  // extern "C"
+
+// ---- the estimator without allocation -----------------------------------------
+
+// Workspace of fps_normest1_noalloc: the estimator's pieces for the largest
+// accepted matrix, then the validation flag.  One copy per GPU, held until the
+// process ends; every call on that GPU shares it.
+constexpr size_t kNoAllocEstBytes = est_bytes(FPS_NOALLOC_MAX_N, FPS_NOALLOC_MAX_NNZ);
+constexpr size_t kScratchBytes = kNoAllocEstBytes + 256;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current (the host-side name of the array is not a
+// device address).
+fps_status scratch_address(void** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(FPS_ERR_CAPACITY, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return set_error(FPS_ERR_HIP, "hipGetSymbolAddress gave a null address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fps_status fps_normest1_noalloc(const fps_csr_view* Z, int32_t p, double* est, int64_t* ind, int32_t* iters,
+                                uint64_t flags, fps_stream stream)
+{
+    g_last_error.clear();
+    if (!est) return set_error(FPS_ERR_INVALID_ARG, "est is NULL");
+    if (p < 0) return set_error(FPS_ERR_INVALID_ARG, "p must be >= 0");
+    FPS_TRY(check_view(Z, "Z", -1));
+    if (Z->n > FPS_NOALLOC_MAX_N || Z->nnz > FPS_NOALLOC_MAX_NNZ)
+        return set_error(FPS_ERR_CAPACITY, "fps_normest1_noalloc: n = %lld, nnz = %lld beyond its limits (n <= %d, nnz <= %d)",
+                         (long long)Z->n, (long long)Z->nnz, FPS_NOALLOC_MAX_N, FPS_NOALLOC_MAX_NNZ);
+    void* base = nullptr;
+    FPS_TRY(scratch_address(&base));
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (!(flags & FPS_FLAG_NO_VALIDATE))
+        FPS_TRY(validate_on_device(Z, "Z", st,
+                                   reinterpret_cast<unsigned long long*>(static_cast<char*>(base) + kNoAllocEstBytes)));
+    EstWork w;
+    FPS_TRY(w.init_at(Z, base, st));
     int it = 0;
     FPS_TRY(w.normest1(Z, p, est, ind, &it, st));
     if (iters) *iters = it;
