@@ -350,6 +350,94 @@ fps_status fps_matrix_nnz(fps_matrix m, int64_t *nnz);
 fps_status fps_matrix_copy(fps_matrix m, int64_t *row_ptr, int32_t *col, double *val, fps_stream stream);
 void fps_matrix_destroy(fps_matrix m);
 
+/* ---------------------------------------------------------------------- */
+/* Batch: many evaluations in one launch sequence                          */
+/* ---------------------------------------------------------------------- */
+
+typedef struct fps_batch_s *fps_batch;
+
+typedef struct {
+    fps_csr_view Z;         /* device CSR, borrowed (as for fps_plan_create) */
+    const double *coeffs;   /* HOST, m+1 entries, copied */
+    int32_t m;              /* degree */
+    int32_t s;              /* PS block size; 0: chosen by fps_autotune_s in [s_lo, s_hi] */
+    double tau;             /* fixed threshold of this instance (finite, >= 0) */
+} fps_batch_item;
+
+#define FPS_BATCH_NO_GRAPH 0x100ull /* batch flag: evaluate with ordinary launches, no graph replay */
+
+/*
+ * A batch of `count` independent filtered PS evaluations (each as
+ * fps_plan_create would do it with its own Z, coefficients, m, s and tau).
+ * Instances with the same m, s and coefficients form a group whose matrices
+ * are joined into one block-diagonal CSR (rows of instance i after those of
+ * the instances before it, columns shifted alike) with a per-row threshold;
+ * every stage of the scheme is then one launch over all the group's rows,
+ * and since an output row only reads rows of its own block, each instance's
+ * result equals its own plan's bit for bit.
+ * Autotuner: items with s == 0 get the block size in [s_lo, s_hi] (s_lo =
+ * s_hi = 0: floor(sqrt(m)) - 1 .. floor(sqrt(m)) + 1, at least 1) whose
+ * evaluation takes the fewest multiply-adds, measured by one sizing
+ * evaluation per candidate of the instances with the same series joined
+ * (ties: the smaller s).  The paper's optimal q (eqs. 5-6) minimises the
+ * number of matrix products; for sparse operands the powers grow denser and
+ * the products differ in cost, so the count of scalar multiply-adds is what
+ * is minimised.  It is an exact integer of the instance alone, so the choice
+ * is deterministic and does not depend on the other items.  Each Z is
+ * validated on the device unless
+ * FPS_FLAG_NO_VALIDATE; FPS_FLAG_NO_SKIP and FPS_FLAG_FORCE_GLOBAL apply to
+ * every group, FPS_FLAG_DROP_STATS is not supported.  The joined copies are
+ * made here: the Z arrays need not stay valid afterwards.  The total number
+ * of rows of a group is at most FPS_MAX_N.  Synchronises `stream`.
+ */
+fps_status fps_batch_create(fps_batch *out, const fps_batch_item *items, int32_t count, int32_t s_lo, int32_t s_hi,
+                            uint64_t flags, fps_stream stream);
+
+/*
+ * Evaluate every instance on `stream`.  The first call sizes the groups'
+ * buffers (host reads, as a plan's first evaluation) and the second runs with
+ * ordinary launches (it may still grow a buffer); from the third on, calls
+ * replay one captured HIP graph in which the groups run as parallel branches
+ * (unless FPS_BATCH_NO_GRAPH), with no host synchronisation.  A capacity flag raised
+ * in a replay is handled by the next result query (the evaluation is
+ * repeated with sizing and the graph captured again).
+ */
+fps_status fps_batch_eval(fps_batch b, fps_stream stream);
+
+/* Stored entries of instance i's result (synchronises). */
+fps_status fps_batch_result_nnz(fps_batch b, int32_t i, int64_t *nnz);
+
+/* Copy instance i's result as canonical CSR into caller-owned DEVICE buffers
+ * (row_ptr int64[n_i + 1], col int32[nnz], val double[nnz]); enqueued on
+ * `stream`. */
+fps_status fps_batch_result_copy(fps_batch b, int32_t i, int64_t *row_ptr, int32_t *col, double *val,
+                                 fps_stream stream);
+
+typedef struct {
+    int32_t count;            /* instances */
+    int32_t groups;           /* groups (distinct m, s, coefficients) */
+    int32_t graph;            /* 1 if evaluations replay a captured graph */
+    int32_t reserved;
+    int64_t evals;            /* evaluations run */
+    int64_t graph_launches;   /* of which graph replays */
+    int64_t resizes;          /* evaluations repeated with sizing */
+    int64_t rows;             /* rows over all instances */
+    int64_t nnz_out;          /* stored entries over all results of the last evaluation */
+    int64_t products;         /* multiply-adds of the last evaluation over all groups */
+    double bytes_algorithmic; /* over all groups (see fps_stats) */
+} fps_batch_stats;
+
+/* Statistics of the batch (synchronises). */
+fps_status fps_batch_get_stats(fps_batch b, fps_batch_stats *st);
+
+/* Block size and group of instance i, and (if it was tuned) into the HOST
+ * array products[0 .. s_hi - s_lo] its measured multiply-adds for each
+ * candidate s (host only). */
+fps_status fps_batch_item_info(fps_batch b, int32_t i, int32_t *s, int32_t *group, int64_t *products);
+
+/* Release the batch (synchronises its last stream). */
+void fps_batch_destroy(fps_batch b);
+
 #ifdef __cplusplus
 }
 #endif

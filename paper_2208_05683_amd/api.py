@@ -135,3 +135,46 @@ def power_norm_bounds(Z, tmax: int, K: int = 10) -> list:
 
 def schedule(m: int, s: int) -> dict:
     return B.fps_schedule(m, s)
+
+
+class Batch:
+    """Many filtered PS evaluations in one launch sequence (see fps_batch_create).
+
+    items: list of dicts with Zd (device CSR triple), coeffs, m, tau and
+    optionally s (0 or absent: autotuned in [s_lo, s_hi])."""
+
+    def __init__(self, items, s_lo: int = 0, s_hi: int = 0, flags: int = 0, stream=None):
+        self.n = [int(it["Zd"][0].numel() - 1) for it in items]
+        self.device = items[0]["Zd"][0].device
+        spec = [(B.csr_view(*it["Zd"]), it["coeffs"], int(it["m"]), int(it.get("s", 0)), float(it["tau"]))
+                for it in items]
+        self.handle = B.fps_batch_create(spec, s_lo, s_hi, flags, stream)
+
+    def eval(self, stream=None):
+        B.fps_batch_eval(self.handle, stream)
+
+    def nnz(self, i: int) -> int:
+        return B.fps_batch_result_nnz(self.handle, i)
+
+    def result(self, i: int, stream=None):
+        out = _alloc_csr(self.n[i], self.nnz(i), self.device)
+        B.fps_batch_result_copy(self.handle, i, *out, stream=stream)
+        torch.cuda.current_stream(self.device).synchronize() if stream is None else stream.synchronize()
+        return out
+
+    def item_info(self, i: int, candidates: int = 0) -> dict:
+        return B.fps_batch_item_info(self.handle, i, candidates)
+
+    def stats(self) -> dict:
+        return B.fps_batch_get_stats(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            B.fps_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -103,6 +103,24 @@ class fps_series_opts(C.Structure):
     ]
 
 
+class fps_batch_item(C.Structure):
+    _fields_ = [
+        ("Z", fps_csr_view),
+        ("coeffs", C.POINTER(C.c_double)),
+        ("m", C.c_int32),
+        ("s", C.c_int32),
+        ("tau", C.c_double),
+    ]
+
+
+class fps_batch_stats(C.Structure):
+    _fields_ = [
+        ("count", C.c_int32), ("groups", C.c_int32), ("graph", C.c_int32), ("reserved", C.c_int32),
+        ("evals", C.c_int64), ("graph_launches", C.c_int64), ("resizes", C.c_int64), ("rows", C.c_int64),
+        ("nnz_out", C.c_int64), ("products", C.c_int64), ("bytes_algorithmic", C.c_double),
+    ]
+
+
 _P = C.POINTER
 _vp = C.c_void_p
 _SIGS = {
@@ -129,6 +147,14 @@ _SIGS = {
     "fps_normest1_noalloc": (C.c_int32, [_P(fps_csr_view), C.c_int32, _P(C.c_double), _P(C.c_int64),
                                          _P(C.c_int32), C.c_uint64, _vp]),
     "fps_power_norm_bounds": (C.c_int32, [_P(fps_csr_view), C.c_int32, C.c_int32, _P(C.c_double), C.c_uint64, _vp]),
+    "fps_batch_create": (C.c_int32, [_P(_vp), _P(fps_batch_item), C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                                     _vp]),
+    "fps_batch_eval": (C.c_int32, [_vp, _vp]),
+    "fps_batch_result_nnz": (C.c_int32, [_vp, C.c_int32, _P(C.c_int64)]),
+    "fps_batch_result_copy": (C.c_int32, [_vp, C.c_int32, _vp, _vp, _vp, _vp]),
+    "fps_batch_get_stats": (C.c_int32, [_vp, _P(fps_batch_stats)]),
+    "fps_batch_item_info": (C.c_int32, [_vp, C.c_int32, _P(C.c_int32), _P(C.c_int32), _P(C.c_int64)]),
+    "fps_batch_destroy": (None, [_vp]),
     "fps_plan_create_series": (C.c_int32, [_P(_vp), _P(fps_csr_view), _P(C.c_double), C.c_int32,
                                            _P(fps_series_opts), C.c_uint64, _vp]),
     "fps_plan_series_info": (C.c_int32, [_vp, _P(C.c_int32), _P(C.c_int32), _P(C.c_double), _P(C.c_double),
@@ -340,3 +366,58 @@ def exported_symbols():
 
 def library():
     return _lib
+
+
+# ---- autotuner and batch ---------------------------------------------------
+
+def fps_batch_create(items, s_lo: int = 0, s_hi: int = 0, flags: int = 0, stream=None):
+    """items: list of (fps_csr_view, coeffs, m, s, tau)."""
+    arr = (fps_batch_item * len(items))()
+    keep = []
+    for k, (Z, coeffs, m, s, tau) in enumerate(items):
+        c = (C.c_double * (m + 1))(*[float(x) for x in coeffs[: m + 1]])
+        keep.append(c)
+        arr[k].Z = Z
+        arr[k].coeffs = C.cast(c, C.POINTER(C.c_double))
+        arr[k].m = int(m)
+        arr[k].s = int(s)
+        arr[k].tau = float(tau)
+    h = C.c_void_p()
+    _check(_lib.fps_batch_create(C.byref(h), arr, len(items), int(s_lo), int(s_hi), C.c_uint64(flags),
+                                 _stream_handle(stream)), "fps_batch_create")
+    return h
+
+
+def fps_batch_eval(b, stream=None):
+    _check(_lib.fps_batch_eval(b, _stream_handle(stream)), "fps_batch_eval")
+
+
+def fps_batch_result_nnz(b, i: int) -> int:
+    v = C.c_int64()
+    _check(_lib.fps_batch_result_nnz(b, int(i), C.byref(v)), "fps_batch_result_nnz")
+    return v.value
+
+
+def fps_batch_result_copy(b, i: int, row_ptr, col, val, stream=None):
+    _check(_lib.fps_batch_result_copy(b, int(i), row_ptr.data_ptr(), col.data_ptr() if col.numel() else None,
+                                      val.data_ptr() if val.numel() else None, _stream_handle(stream)),
+           "fps_batch_result_copy")
+
+
+def fps_batch_get_stats(b) -> dict:
+    st = fps_batch_stats()
+    _check(_lib.fps_batch_get_stats(b, C.byref(st)), "fps_batch_get_stats")
+    return {name: getattr(st, name) for name, _ in fps_batch_stats._fields_}
+
+
+def fps_batch_item_info(b, i: int, candidates: int = 0) -> dict:
+    """candidates: s_hi - s_lo + 1 of a tuned batch (0: no product counts)."""
+    s, g = C.c_int32(), C.c_int32()
+    prod = (C.c_int64 * max(candidates, 1))()
+    _check(_lib.fps_batch_item_info(b, int(i), C.byref(s), C.byref(g), prod if candidates else None),
+           "fps_batch_item_info")
+    return {"s": s.value, "group": g.value, "products": list(prod)[:candidates]}
+
+
+def fps_batch_destroy(b):
+    _lib.fps_batch_destroy(b)

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -809,6 +810,10 @@ struct fps_plan_s {
     std::vector<double> c;
     int m = 0, s = 0;
     double tau = 0.0;
+    // per-row thresholds (device, n) of a batch group: row r drops |x| < tau_row[r]
+    const double* tau_row = nullptr;
+    // per-row multiply-add counters (device, n) added to by every stage's analysis
+    int64_t* prod_acc = nullptr;
     // adaptive filter
     bool adaptive = false;
     double eps = 0.0, e_r = 0.0;
@@ -905,6 +910,9 @@ struct fps_plan_s {
         // entries are computed, so the row skip is off
         const bool dstats = (flags & FPS_FLAG_DROP_STATS) && !adaptive && tau > 0.0;
         const double skip_tau = (flags & FPS_FLAG_NO_SKIP) || dstats || tau <= 0.0 ? 0.0 : tau * (1.0 - 1e-6);
+        // a batch group: per-row thresholds, the same 1e-6 margin for the skip
+        const double* tau_rows = adaptive ? nullptr : tau_row;
+        const double skip_rel = (flags & FPS_FLAG_NO_SKIP) ? 0.0 : 1.0 - 1e-6;
         unsigned long long* dsum = nullptr;
         if (dstats) {
             FPS_TRY(eng.ws.dsum.ensure(sizeof(unsigned long long) * (size_t)std::max<int64_t>(n, 1)));
@@ -951,9 +959,12 @@ struct fps_plan_s {
         // step 1: filtered powers P_{j+1} = D_tau(Z (x) P_j)   (eq. 11)
         for (int j = 1; j + 1 <= sc.J; ++j) {
             StageArgs a{};
+            a.prod_acc = prod_acc;
             a.mode = kModeProduct;
             a.tau = adaptive ? 0.0 : tau;
             a.skip_tau = adaptive ? 0.0 : skip_tau;
+            a.tau_row = tau_rows;
+            a.skip_rel = skip_rel;
             a.A = zv;
             a.B = (j == 1) ? zv : P[(size_t)j]->view();
             a.has_e = 0;
@@ -974,6 +985,7 @@ struct fps_plan_s {
 
         auto run_sum = [&](Kind k, int index, int block, int jmax, SlackMatrix& out) -> fps_status {
             StageArgs a{};
+            a.prod_acc = prod_acc;
             a.mode = kModeSum;
             a.tau = 0.0;
             a.skip_tau = 0.0;
@@ -1000,9 +1012,12 @@ struct fps_plan_s {
             for (int i = sc.start; i <= sc.b - 1; ++i) {
                 // S_i = D_tau(Bhat_{b-1-i} + P_q (x) S_{i-1}) with the block summed inside the step
                 StageArgs a{};
+                a.prod_acc = prod_acc;
                 a.mode = kModeProduct;
                 a.tau = adaptive ? 0.0 : tau;
                 a.skip_tau = adaptive ? 0.0 : skip_tau;
+                a.tau_row = tau_rows;
+                a.skip_rel = skip_rel;
                 a.A = (sc.q == 1) ? zv : P[(size_t)sc.q]->view();
                 a.B = S[cur].view();
                 a.has_e = 0;
@@ -1675,5 +1690,450 @@ fps_status fps_plan_series_info(fps_plan p, int32_t* N, int32_t* q, double* tail
     if (z) std::memcpy(z, p->series_z.data(), sizeof(double) * p->series_z.size());
     return FPS_OK;
 }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batch, and its autotuner of the block size
+// ===========================================================================
+
+namespace {
+
+// Instances joined into one block-diagonal CSR: instance j's rows follow
+// those of instances 0..j-1, its columns shifted alike, with its threshold
+// on each of its rows.
+struct Joined {
+    std::vector<int> members;   // item indices
+    std::vector<int64_t> base;  // first row of each member, and the total
+    int64_t rows = 0, nnz = 0;
+    DevBuf rp, col, val, tau_row, dbase;
+
+    fps_status build(const fps_batch_item* items, hipStream_t st)
+    {
+        const int cnt = (int)members.size();
+        base.assign(1, 0);
+        rows = nnz = 0;
+        std::vector<BatchSrc> src((size_t)cnt);
+        for (int j = 0; j < cnt; ++j) {
+            const fps_batch_item& it = items[members[(size_t)j]];
+            src[(size_t)j] = BatchSrc{it.Z.row_ptr, it.Z.col, it.Z.val, nnz, it.tau};
+            nnz += it.Z.nnz;
+            rows += it.Z.n;
+            base.push_back(rows);
+        }
+        if (rows > FPS_MAX_N) return set_error(FPS_ERR_CAPACITY, "a batch group has %lld rows", (long long)rows);
+        DevBuf dsrc;
+        FPS_TRY(dsrc.ensure(sizeof(BatchSrc) * (size_t)cnt));
+        FPS_TRY(dbase.ensure(sizeof(int64_t) * (size_t)(cnt + 1)));
+        FPS_TRY(rp.ensure(sizeof(int64_t) * (size_t)(rows + 1)));
+        FPS_TRY(col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1)));
+        FPS_TRY(val.ensure(sizeof(double) * (size_t)std::max<int64_t>(nnz, 1)));
+        FPS_TRY(tau_row.ensure(sizeof(double) * (size_t)rows));
+        HIP_TRY(hipMemcpyAsync(dsrc.p, src.data(), sizeof(BatchSrc) * (size_t)cnt, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(dbase.p, base.data(), sizeof(int64_t) * (size_t)(cnt + 1), hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_batch_join(dsrc.as<BatchSrc>(), dbase.as<int64_t>(), cnt, rows, rp.as<int64_t>(),
+                                  col.as<int32_t>(), val.as<double>(), tau_row.as<double>(), st));
+        HIP_TRY(hipStreamSynchronize(st));  // dsrc is released on return
+        return FPS_OK;
+    }
+
+    fps_csr_view view() const { return fps_csr_view{rows, nnz, rp.as<int64_t>(), col.as<int32_t>(), val.as<double>()}; }
+};
+
+// Multiply-adds of one sizing evaluation with block size s, per member of a
+// joined set (exact integers: each row's count is added by one thread, the
+// per-member sums are integer atomics).
+fps_status measure_products(Joined& J, const std::vector<double>& c, int m, int s, uint64_t flags, hipStream_t st,
+                            std::vector<int64_t>& out)
+{
+    const int cnt = (int)J.members.size();
+    fps_plan p = nullptr;
+    const fps_csr_view v = J.view();
+    FPS_TRY(fps_plan_create(&p, &v, c.data(), m, s, 0.0, flags | FPS_FLAG_NO_VALIDATE,
+                            reinterpret_cast<fps_stream>(st)));
+    std::unique_ptr<fps_plan_s, void (*)(fps_plan)> guard(p, fps_plan_destroy);
+    DevBuf acc, sums;
+    FPS_TRY(acc.ensure(sizeof(int64_t) * (size_t)J.rows));
+    FPS_TRY(sums.ensure(sizeof(unsigned long long) * (size_t)cnt));
+    HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(acc.p), J.rows, 0ull, st));
+    HIP_TRY(launch_fill_u64(sums.as<unsigned long long>(), cnt, 0ull, st));
+    p->tau_row = J.tau_row.as<double>();
+    p->prod_acc = acc.as<int64_t>();
+    FPS_TRY(fps_eval(p, reinterpret_cast<fps_stream>(st)));
+    FPS_TRY(finish(p));
+    HIP_TRY(launch_batch_instance_sum(acc.as<int64_t>(), J.dbase.as<int64_t>(), cnt, J.rows,
+                                      sums.as<unsigned long long>(), st));
+    std::vector<unsigned long long> h((size_t)cnt);
+    HIP_TRY(hipMemcpyAsync(h.data(), sums.p, sizeof(unsigned long long) * (size_t)cnt, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    out.assign(h.begin(), h.end());
+    return FPS_OK;
+}
+
+}  // namespace
+
+struct fps_batch_s {
+    struct Item {
+        int group = -1, member = -1;
+        int64_t n = 0, nnz = 0;
+        int m = 0, s = 0;
+        double tau = 0.0;
+        bool tuned = false;
+        std::vector<int64_t> products;  // tuned: multiply-adds measured for s = s_lo .. s_hi
+    };
+    struct Group {
+        int m = 0, s = 0;
+        std::vector<double> c;
+        Joined J;
+        DevBuf dbounds;
+        fps_plan plan = nullptr;
+        std::vector<int64_t> bounds;  // [2 j, 2 j + 1): member j's entries in the joined result
+        hipStream_t fork = nullptr;
+        hipEvent_t joined = nullptr;
+    };
+    std::vector<Item> items;
+    std::deque<Group> groups;  // stable addresses (DevBuf is not movable)
+    uint64_t flags = 0;
+    int s_lo = 0, s_hi = 0;
+    bool sized = false;
+    bool use_graph = true;
+    hipStream_t cap = nullptr;
+    hipEvent_t forked = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t last_stream = nullptr;
+    int64_t evals = 0, graph_launches = 0, collected = -1;
+
+    void drop_graph()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+
+    ~fps_batch_s()
+    {
+        if (evals) (void)hipStreamSynchronize(last_stream);
+        drop_graph();
+        for (Group& g : groups) {
+            if (g.plan) fps_plan_destroy(g.plan);
+            if (g.fork) (void)hipStreamDestroy(g.fork);
+            if (g.joined) (void)hipEventDestroy(g.joined);
+        }
+        if (cap) (void)hipStreamDestroy(cap);
+        if (forked) (void)hipEventDestroy(forked);
+    }
+
+    int64_t plan_resizes() const
+    {
+        int64_t t = 0;
+        for (const Group& g : groups) t += g.plan->resizes;
+        return t;
+    }
+
+    // Every group's evaluation (no sizing) on its own branch off `s`: fork on
+    // an event, join on the groups' events.  Every branch is joined even if a
+    // group fails, so that a capture on `s` always ends with no stream left
+    // capturing; the first failure is returned.
+    fps_status enqueue_groups(hipStream_t s)
+    {
+        HIP_TRY(hipEventRecord(forked, s));
+        fps_status first = FPS_OK;
+        for (Group& g : groups) {
+            HIP_TRY(hipStreamWaitEvent(g.fork, forked, 0));
+            if (first == FPS_OK) first = g.plan->run_eval(g.fork, false);
+            HIP_TRY(hipEventRecord(g.joined, g.fork));
+            HIP_TRY(hipStreamWaitEvent(s, g.joined, 0));
+        }
+        return first;
+    }
+
+    // Captures enqueue_groups into a graph; if capture or instantiation
+    // fails, the batch keeps using ordinary launches.
+    void capture()
+    {
+        drop_graph();
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            use_graph = false;
+            return;
+        }
+        const fps_status st = enqueue_groups(cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cap, &g);
+        if (st != FPS_OK || e != hipSuccess || !g) {
+            (void)hipGetLastError();
+            if (g) (void)hipGraphDestroy(g);
+            use_graph = false;
+            return;
+        }
+        graph = g;
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            drop_graph();
+            use_graph = false;
+        }
+    }
+
+    // After an evaluation: every group finished (a flagged group is run
+    // again with sizing, which invalidates the graph) and the members'
+    // bounds in the joined results read.
+    fps_status collect()
+    {
+        if (collected == evals) return FPS_OK;
+        const int64_t before = plan_resizes();
+        for (Group& g : groups) FPS_TRY(finish(g.plan));
+        if (plan_resizes() != before) drop_graph();
+        for (Group& g : groups) {
+            const int cnt = (int)g.J.members.size();
+            HIP_TRY(launch_batch_bounds(g.plan->result.rp.as<int64_t>(), g.J.dbase.as<int64_t>(), cnt,
+                                        g.dbounds.as<int64_t>(), g.plan->last_stream));
+            g.bounds.resize(2 * (size_t)cnt);
+            HIP_TRY(hipMemcpyAsync(g.bounds.data(), g.dbounds.p, sizeof(int64_t) * g.bounds.size(),
+                                   hipMemcpyDeviceToHost, g.plan->last_stream));
+            HIP_TRY(hipStreamSynchronize(g.plan->last_stream));
+        }
+        collected = evals;
+        return FPS_OK;
+    }
+};
+
+extern "C" {
+
+fps_status fps_batch_create(fps_batch* out, const fps_batch_item* items, int32_t count, int32_t s_lo, int32_t s_hi,
+                            uint64_t flags, fps_stream stream)
+{
+    g_last_error.clear();
+    if (!out) return set_error(FPS_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!items || count < 1) return set_error(FPS_ERR_INVALID_ARG, "need at least one item");
+    if (flags & FPS_FLAG_DROP_STATS) return set_error(FPS_ERR_INVALID_ARG, "FPS_FLAG_DROP_STATS is not supported by batches");
+    if (s_lo < 0 || s_hi < s_lo || s_hi > FPS_MAX_S || (s_lo == 0 && s_hi != 0))
+        return set_error(FPS_ERR_INVALID_ARG, "autotuner range [%d, %d] invalid", s_lo, s_hi);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    for (int i = 0; i < count; ++i) {
+        const fps_batch_item& it = items[i];
+        FPS_TRY(check_view(&it.Z, "batch item Z", -1));
+        if (!it.coeffs) return set_error(FPS_ERR_INVALID_ARG, "item %d: coeffs is NULL", i);
+        if (it.m < 0) return set_error(FPS_ERR_INVALID_ARG, "item %d: m must be >= 0", i);
+        if (it.s < 0 || it.s > FPS_MAX_S) return set_error(FPS_ERR_INVALID_ARG, "item %d: s out of range", i);
+        if (!std::isfinite(it.tau) || it.tau < 0.0) return set_error(FPS_ERR_INVALID_ARG, "item %d: bad tau", i);
+        for (int k = 0; k <= it.m; ++k)
+            if (!std::isfinite(it.coeffs[k])) return set_error(FPS_ERR_INVALID_ARG, "item %d: coefficient %d", i, k);
+    }
+    if (!(flags & FPS_FLAG_NO_VALIDATE)) {
+        DevBuf flag;
+        FPS_TRY(flag.ensure(sizeof(unsigned long long) * (size_t)count));
+        unsigned long long* fl = flag.as<unsigned long long>();
+        HIP_TRY(launch_fill_u64(fl, count, 0ull, st));
+        for (int i = 0; i < count; ++i)
+            HIP_TRY(launch_validate_csr(items[i].Z.row_ptr, items[i].Z.col, items[i].Z.val, items[i].Z.n,
+                                        items[i].Z.nnz, fl + i, st));
+        std::vector<unsigned long long> h((size_t)count);
+        HIP_TRY(hipMemcpyAsync(h.data(), fl, sizeof(unsigned long long) * (size_t)count, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int i = 0; i < count; ++i)
+            if (h[(size_t)i]) return set_error(FPS_ERR_BAD_CSR, "batch item %d is not a canonical CSR", i);
+    }
+    std::unique_ptr<fps_batch_s> b(new (std::nothrow) fps_batch_s());
+    if (!b) return set_error(FPS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    b->flags = flags & (FPS_FLAG_NO_SKIP | FPS_FLAG_FORCE_GLOBAL);
+    b->use_graph = !(flags & FPS_BATCH_NO_GRAPH);
+    b->s_lo = s_lo;
+    b->s_hi = s_hi;
+    b->items.resize((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        auto& x = b->items[(size_t)i];
+        x.n = items[i].Z.n;
+        x.nnz = items[i].Z.nnz;
+        x.m = items[i].m;
+        x.tau = items[i].tau;
+        x.s = items[i].s;
+    }
+    auto same_series = [&](int i, int j) {
+        return items[i].m == items[j].m &&
+               std::memcmp(items[i].coeffs, items[j].coeffs, sizeof(double) * (size_t)(items[i].m + 1)) == 0;
+    };
+    // Autotuner: items without s, by families of the same series, take the
+    // block size with the fewest multiply-adds in one sizing evaluation of
+    // the family per candidate (ties: the smaller s).
+    {
+        std::vector<int> family((size_t)count, -1);
+        std::vector<int> heads;
+        for (int i = 0; i < count; ++i) {
+            if (items[i].s != 0) continue;
+            for (int h : heads)
+                if (same_series(h, i)) {
+                    family[(size_t)i] = h;
+                    break;
+                }
+            if (family[(size_t)i] < 0) {
+                family[(size_t)i] = i;
+                heads.push_back(i);
+            }
+        }
+        for (int h : heads) {
+            Joined J;
+            for (int i = 0; i < count; ++i)
+                if (family[(size_t)i] == h) J.members.push_back(i);
+            FPS_TRY(J.build(items, st));
+            int lo = s_lo, hi = s_hi;
+            if (lo == 0) {
+                int r = 0;
+                while ((r + 1) * (r + 1) <= items[h].m) ++r;
+                lo = std::max(1, r - 1);
+                hi = std::min(FPS_MAX_S, std::max(lo, r + 1));
+            }
+            const std::vector<double> c(items[h].coeffs, items[h].coeffs + items[h].m + 1);
+            for (int s = lo; s <= hi; ++s) {
+                std::vector<int64_t> prod;
+                FPS_TRY(measure_products(J, c, items[h].m, s, b->flags, st, prod));
+                for (size_t j = 0; j < J.members.size(); ++j) {
+                    auto& x = b->items[(size_t)J.members[j]];
+                    x.products.push_back(prod[j]);
+                    if (s == lo || prod[j] < x.products[(size_t)(x.s - lo)]) x.s = s;
+                    x.tuned = true;
+                }
+            }
+        }
+    }
+    // groups: same m, s and coefficients
+    std::vector<int> head_of;  // first item of each group
+    for (int i = 0; i < count; ++i) {
+        auto& x = b->items[(size_t)i];
+        int gi = -1;
+        for (size_t k = 0; k < head_of.size(); ++k)
+            if (b->items[(size_t)head_of[k]].s == x.s && same_series(head_of[k], i)) {
+                gi = (int)k;
+                break;
+            }
+        if (gi < 0) {
+            b->groups.emplace_back();
+            auto& g = b->groups.back();
+            g.m = x.m;
+            g.s = x.s;
+            g.c.assign(items[i].coeffs, items[i].coeffs + x.m + 1);
+            head_of.push_back(i);
+            gi = (int)b->groups.size() - 1;
+        }
+        auto& g = b->groups[(size_t)gi];
+        x.group = gi;
+        x.member = (int)g.J.members.size();
+        g.J.members.push_back(i);
+    }
+    HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&b->forked, hipEventDisableTiming));
+    for (auto& g : b->groups) {
+        FPS_TRY(g.J.build(items, st));
+        FPS_TRY(g.dbounds.ensure(sizeof(int64_t) * 2 * g.J.members.size()));
+        const fps_csr_view v = g.J.view();
+        FPS_TRY(fps_plan_create(&g.plan, &v, g.c.data(), g.m, g.s, 0.0, b->flags | FPS_FLAG_NO_VALIDATE, stream));
+        g.plan->tau_row = g.J.tau_row.as<double>();
+        HIP_TRY(hipStreamCreateWithFlags(&g.fork, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&g.joined, hipEventDisableTiming));
+    }
+    *out = b.release();
+    return FPS_OK;
+}
+
+fps_status fps_batch_eval(fps_batch b, fps_stream stream)
+{
+    if (!b) return set_error(FPS_ERR_INVALID_ARG, "batch is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!b->sized) {
+        // sizing evaluation, group after group (host reads per stage)
+        for (auto& g : b->groups) FPS_TRY(fps_eval(g.plan, stream));
+        b->sized = true;
+    } else {
+        // the first evaluation after sizing runs with ordinary launches (it may
+        // still grow a buffer, e.g. the fixed stride of a stage whose rows were
+        // all empty, which a capture cannot do); later ones replay the graph
+        if (b->use_graph && !b->exec && b->evals >= 2) b->capture();
+        if (b->use_graph && b->exec) {
+            HIP_TRY(hipGraphLaunch(b->exec, s));
+            b->graph_launches++;
+        } else {
+            FPS_TRY(b->enqueue_groups(s));
+        }
+        for (auto& g : b->groups) {
+            g.plan->last_stream = s;
+            g.plan->evals++;
+            g.plan->evaluated = true;
+        }
+    }
+    b->last_stream = s;
+    b->evals++;
+    return FPS_OK;
+}
+
+fps_status fps_batch_result_nnz(fps_batch b, int32_t i, int64_t* nnz)
+{
+    if (!b || !nnz) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    if (i < 0 || i >= (int32_t)b->items.size()) return set_error(FPS_ERR_INVALID_ARG, "item index out of range");
+    if (!b->evals) return set_error(FPS_ERR_NOT_READY, "no evaluation has run on this batch");
+    FPS_TRY(b->collect());
+    const auto& x = b->items[(size_t)i];
+    const auto& g = b->groups[(size_t)x.group];
+    *nnz = g.bounds[2 * (size_t)x.member + 1] - g.bounds[2 * (size_t)x.member];
+    return FPS_OK;
+}
+
+fps_status fps_batch_result_copy(fps_batch b, int32_t i, int64_t* row_ptr, int32_t* col, double* val,
+                                 fps_stream stream)
+{
+    if (!b || !row_ptr) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    int64_t nnz = 0;
+    FPS_TRY(fps_batch_result_nnz(b, i, &nnz));
+    if (nnz > 0 && (!col || !val)) return set_error(FPS_ERR_INVALID_ARG, "null col/val with nnz > 0");
+    const auto& x = b->items[(size_t)i];
+    const auto& g = b->groups[(size_t)x.group];
+    const int64_t row0 = g.J.base[(size_t)x.member];
+    const int64_t p0 = g.bounds[2 * (size_t)x.member];
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(launch_batch_extract(g.plan->result.rp.as<int64_t>(), g.plan->result.col.as<int32_t>(), row0, x.n, p0,
+                                 nnz, (int32_t)row0, row_ptr, col, s));
+    if (nnz > 0)
+        HIP_TRY(hipMemcpyAsync(val, g.plan->result.val.as<double>() + p0, sizeof(double) * (size_t)nnz,
+                               hipMemcpyDeviceToDevice, s));
+    return FPS_OK;
+}
+
+fps_status fps_batch_get_stats(fps_batch b, fps_batch_stats* st)
+{
+    if (!b || !st) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    std::memset(st, 0, sizeof(*st));
+    st->count = (int32_t)b->items.size();
+    st->groups = (int32_t)b->groups.size();
+    st->graph = (b->use_graph && b->exec) ? 1 : 0;
+    st->evals = b->evals;
+    st->graph_launches = b->graph_launches;
+    for (const auto& g : b->groups) st->rows += g.J.rows;
+    if (!b->evals) return FPS_OK;
+    FPS_TRY(b->collect());
+    st->resizes = b->plan_resizes();
+    for (auto& g : b->groups) {
+        fps_stats ps;
+        FPS_TRY(fps_get_stats(g.plan, &ps));
+        st->nnz_out += ps.nnz_out;
+        st->products += ps.products;
+        st->bytes_algorithmic += ps.bytes_algorithmic;
+    }
+    return FPS_OK;
+}
+
+fps_status fps_batch_item_info(fps_batch b, int32_t i, int32_t* s, int32_t* group, int64_t* products)
+{
+    if (!b) return set_error(FPS_ERR_INVALID_ARG, "batch is NULL");
+    if (i < 0 || i >= (int32_t)b->items.size()) return set_error(FPS_ERR_INVALID_ARG, "item index out of range");
+    const auto& x = b->items[(size_t)i];
+    if (s) *s = x.s;
+    if (group) *group = x.group;
+    if (products)
+        for (size_t k = 0; k < x.products.size(); ++k) products[k] = x.products[k];
+    return FPS_OK;
+}
+
+void fps_batch_destroy(fps_batch b) { delete b; }
 
 }  // extern "C"

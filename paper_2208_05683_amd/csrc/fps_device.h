@@ -134,6 +134,14 @@ struct StageArgs {
     int64_t n;
     double tau;
     double skip_tau;  // rows whose bound is below this are empty (0 disables the test)
+    // Per-row thresholds (a batch of instances in one block-diagonal matrix):
+    // when set, row r drops |x| < tau_row[r] instead of tau, and its empty-row
+    // test uses tau_row[r] * skip_rel (skip_rel = 0 disables the test).
+    const double* tau_row;
+    double skip_rel;
+    // when set, the analysis adds each computed row's multiply-adds to
+    // prod_acc[r] (the batch autotuner's per-instance counts)
+    int64_t* prod_acc;
     MatView A, B, E;
     Terms T;
     // analysis outputs
@@ -183,6 +191,27 @@ struct StageArgs {
     int32_t dcount;
     int32_t dpad;
 };
+
+// One instance of a batch as the join kernels read it: its canonical CSR
+// (device), where its entries start in the joined matrix, and its threshold.
+struct BatchSrc {
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const double* val;
+    int64_t nnz_base;
+    double tau;
+};
+
+// ---- launch wrappers (fps_batch.hip) ------------------------------------
+// base[0..count]: first joined row of each instance (base[count] = total)
+hipError_t launch_batch_join(const BatchSrc* src, const int64_t* base, int count, int64_t total, int64_t* rp,
+                             int32_t* col, double* val, double* tau_row, hipStream_t s);
+hipError_t launch_batch_bounds(const int64_t* frp, const int64_t* base, int count, int64_t* bounds, hipStream_t s);
+// out[i] += sum of acc[r] over the rows of instance i (exact integer sums)
+hipError_t launch_batch_instance_sum(const int64_t* acc, const int64_t* base, int count, int64_t total,
+                                     unsigned long long* out, hipStream_t s);
+hipError_t launch_batch_extract(const int64_t* frp, const int32_t* fcol, int64_t row0, int64_t n, int64_t p0,
+                                int64_t cnt, int32_t shift, int64_t* rp, int32_t* col, hipStream_t s);
 
 // ---- launch wrappers (fps_kernels.hip) ---------------------------------
 // row summaries and the structure words (sw: nnz entries, nw: n) of a canonical CSR

@@ -535,7 +535,8 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
         emax = row_reduce<OpSum>(emax);
         if (gl == 0) {
             const bool empty = (prod == 0 && elen == 0);
-            const bool skip = !empty && P.skip_tau > 0.0 && (emax + bnd) < P.skip_tau;
+            const double skip_tau = P.tau_row ? P.tau_row[r] * P.skip_rel : P.skip_tau;
+            const bool skip = !empty && skip_tau > 0.0 && (emax + bnd) < skip_tau;
             int32_t W = 0;
             int64_t ub = 0;
             if (!empty && !skip) {
@@ -556,6 +557,7 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
                 row_skip = 1;
             } else {
                 prod_done = (unsigned long long)work;
+                if (P.prod_acc) P.prod_acc[r] += work;
             }
         }
     }
@@ -623,6 +625,7 @@ __global__ void __launch_bounds__(kBlock) k_analyze_sum(StageArgs P)
         P.prod[r] = prod;
         ubv = ub;
         prod_done = (unsigned long long)prod;
+        if (P.prod_acc) P.prod_acc[r] += prod;
     }
     const unsigned long long t = block_sum_256(prod_done, sh);
     if (threadIdx.x == 0) {
@@ -1518,10 +1521,11 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     int32_t first = INT_MAX, last = -1;
     unsigned long long ndrop = 0;  // dropped-entry statistics
     double dmx = 0.0;
+    const double tau = P.tau_row ? P.tau_row[r] : P.tau;
     auto emit = [&](int64_t i, double x, int32_t c) {
         bool keep = false;
         if (i < ns) {
-            keep = (x != 0.0) && !(fabs(x) < P.tau);
+            keep = (x != 0.0) && !(fabs(x) < tau);
             // the bitmap keeps the kept columns only, for the structure words
             if (!keep) atomicAnd(&bmp[(uint32_t)(c - lo) >> 5].x, ~(1u << (c & 31)));
         }
