@@ -8,6 +8,10 @@ tau = 1e-12, with Z resident in HBM.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload lap2d|lap1d]
 
+The headline line also carries the batched leg (512 seeded banded instances
+in one graph-replayed batch against 512 plain evaluations; --batch-count 0
+skips it) and the CPU oracle baseline (--cpu-budget 0 skips it).
+
 Other lines (not the headline): --filter adaptive|series time Algorithm 1 and
 Algorithm 2 on the same matrix; --sweep banded times the paper's second test
 set (random banded 1000 x 1000, bandwidth 1..15, exp and cos, eps_tol 1e-14)
@@ -64,24 +68,135 @@ def measured_traffic(workload_name: str):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(cfg, budget_s: float):
-    """The CPU oracle timed on this host's cores on whole evaluations."""
+def host_cpu():
+    """nproc and the CPU model of this host."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
+def cpu_baseline(cfg, reps: int = 5):
+    """The CPU oracle on this host's cores, whole evaluations of the same
+    workload: median of `reps` runs after one warm-up, with OpenMP on all the
+    cores the run may use and on one core."""
+    import statistics
+
     import oracle as O
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
+    nproc, model = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or nproc
     Z, c, m, s, tau = cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"]
-    O.filtered_ps(Z, c, m, s, tau, nthreads=threads)  # warm-up
+
+    def med(nt):
+        O.filtered_ps(Z, c, m, s, tau, nthreads=nt)  # warm-up
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            O.filtered_ps(Z, c, m, s, tau, nthreads=nt)
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts)
+
+    t_all = med(threads)
+    t_one = med(1)
+    return {"value": 1.0 / t_all, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"median of {reps} full evaluations of the same workload after 1 warm-up, "
+                      f"{threads} OpenMP threads",
+            "value_1core": 1.0 / t_one, "median_s": t_all, "median_s_1core": t_one,
+            "nproc": nproc, "cpu_model": model}
+
+
+def event_times(run, steps, stream):
+    """Per-step milliseconds from HIP events on `stream` around each call."""
+    import torch
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    k = 0
-    while True:
-        O.filtered_ps(Z, c, m, s, tau, nthreads=threads)
-        k += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or k >= 50:
-            break
-    return {"value": k / el, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{k} full evaluations of the same workload after 1 warm-up ({el:.1f} s), "
-                      f"{threads} OpenMP threads"}
+    for a, b in evs:
+        a.record(stream)
+        run()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [a.elapsed_time(b) for a, b in evs], wall
+
+
+def median(v):
+    import statistics
+
+    return statistics.median(v)
+
+
+def bench_batch(args, stream):
+    """The batched layer against the plain path on 512 seeded banded instances
+    (n log-uniform in [500, 20000], half-bandwidth 1..5, in-band density 0.6,
+    ||Z||_1 ~ U(0.5, 2), exp m = 20, tau = 1e-12 ||Z||_1, s in {4, 5} from the
+    autotuner): one batch evaluation (a graph replay) against 512 fps_eval
+    calls of plans with the same s, both after their sizing evaluations."""
+    import numpy as np
+    import torch
+    from fps_inputs import generators as G
+    from paper_2208_05683_amd import api
+
+    inst = G.batch_instances(count=args.batch_count)
+    dev = [api.to_device(x["Z"].row_ptr, x["Z"].col, x["Z"].val) for x in inst]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = api.Batch([dict(Zd=d, coeffs=x["coeffs"], m=x["m"], s=0, tau=x["tau"]) for d, x in zip(dev, inst)],
+                  s_lo=4, s_hi=5)
+    torch.cuda.synchronize()
+    create_ms = 1e3 * (time.perf_counter() - t0)
+    chosen = [b.item_info(i)["s"] for i in range(len(inst))]
+    for _ in range(3):  # sizing, the eager one, then the graph capture
+        b.eval(stream)
+    torch.cuda.synchronize()
+    bt, bwall = event_times(lambda: b.eval(stream), args.batch_steps, stream)
+    bst = b.stats()
+    plans = [api.Plan(d, x["coeffs"], x["m"], s, x["tau"]) for d, x, s in zip(dev, inst, chosen)]
+    for p in plans:
+        p.eval(stream)
+        p.eval(stream)
+    torch.cuda.synchronize()
+
+    def seq():
+        for p in plans:
+            p.eval(stream)
+
+    pt, pwall = event_times(seq, args.batch_steps, stream)
+    # spot check: the batch gives each instance's own result
+    same = 0
+    for i in range(0, len(inst), max(1, len(inst) // 16)):
+        g = [x.cpu().numpy() for x in b.result(i)]
+        h = [x.cpu().numpy() for x in plans[i].result()]
+        same += int(all(np.array_equal(u.view(np.uint8), v.view(np.uint8)) for u, v in zip(g, h)))
+    checked = len(range(0, len(inst), max(1, len(inst) // 16)))
+    products = bst["products"]
+    for p in plans:
+        p.close()
+    b.close()
+    bms, pms = median(bt), median(pt)
+    return {
+        "workload": f"batch{len(inst)}_banded_exp_m20",
+        "instances": len(inst), "rows": bst["rows"], "groups": bst["groups"],
+        "s_chosen": {"4": chosen.count(4), "5": chosen.count(5)},
+        "batch_ms": bms, "batch_evals_per_s": len(inst) / (bms * 1e-3),
+        "plain_ms": pms, "plain_evals_per_s": len(inst) / (pms * 1e-3),
+        "speedup_vs_plain": pms / bms,
+        "graph": bst["graph"], "steps": args.batch_steps,
+        "batch_wall_ms_per_step": 1e3 * bwall / args.batch_steps,
+        "plain_wall_ms_per_step": 1e3 * pwall / args.batch_steps,
+        "create_ms": create_ms, "products_per_step": products,
+        "bytes_algorithmic_per_step": bst["bytes_algorithmic"],
+        "hbm_frac_algorithmic": bst["bytes_algorithmic"] / (bms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "nnz_out": bst["nnz_out"], "results_checked_bitwise": f"{same}/{checked}",
+    }
 
 
 def dense_ps(Zt, c, m, s):
@@ -189,7 +304,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="lap2d")
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle timing (0 skips)")
+    ap.add_argument("--cpu-budget", type=float, default=1.0, help="0 skips the CPU oracle timing")
     ap.add_argument("--filter", choices=["fixed", "adaptive", "series"], default="fixed",
                     help="fixed: the workload's tau; adaptive: Algorithm 1 with the eq. 28 thresholds and the "
                          "eq. 37 bounds; series: Algorithm 2 (N, q and the eq. 36 thresholds from --eps-tol)")
@@ -202,6 +317,8 @@ def main():
     ap.add_argument("--sweep-bands", default="1-15", help="sweep: bandwidths, e.g. 1-15 or 1,5,11")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (calibrates HBM counters)")
+    ap.add_argument("--batch-count", type=int, default=512, help="instances of the batch leg (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=10, help="timed batch evaluations")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -266,28 +383,41 @@ def main():
     log(f"warm-up done ({args.warmup} evals), F nnz = {plan.nnz()}")
     plan.stats()  # the kernel times reported below are those of the timed evaluations
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.eval(stream)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    # each evaluation timed by HIP events on the stream it runs on; the value
+    # is the median (the bracketed wall time is reported beside it)
+    times, el = event_times(lambda: plan.eval(stream), args.steps, stream)
     st = plan.stats()
     if st["resizes"]:
         log(f"warning: {st['resizes']} evaluations re-sized buffers")
-    ms_per_step = 1e3 * el / args.steps
-    evals_per_s = args.steps / el
-    log(f"timed {args.steps} evals: {ms_per_step:.3f} ms/eval")
+    ms_per_step = median(times)
+    evals_per_s = 1e3 / ms_per_step
+    log(f"timed {args.steps} evals: median {ms_per_step:.3f} ms/eval (wall {1e3 * el / args.steps:.3f})")
 
     # roofline of the dominant kernel, the shared-memory numeric kernel (every
-    # stage launches it once; HIP events on the plan's stream around each launch
-    # of the first timed evaluation and every 8th one after it)
+    # stage launches it once; the library records HIP events on the plan's
+    # stream around each launch of the first timed evaluation and every 8th
+    # one after it).  Algorithmic bytes count the rows each stage computes
+    # (a stage whose rows were all proven empty counts its analysis reads).
     launches = st["numeric_launches"]
     kern_ms = st["numeric_ms"]
     bytes_eval = st["bytes_algorithmic"]
-    achieved = (bytes_eval / (kern_ms * 1e-3)) / 1e9 if kern_ms > 0 else 0.0
+    # the numeric kernel's own bytes: a stage whose rows were all proven empty
+    # by the analysis only writes each row's (empty) end in it, 8 bytes a row
+    n1 = Z.n + 1
+    kern_bytes = [8.0 * n1 if sk >= Z.n else by for by, sk in zip(st["stage_bytes"], st["stage_rows_skipped"])]
+    bytes_kernel = sum(kern_bytes)
+    achieved = (bytes_kernel / (kern_ms * 1e-3)) / 1e9 if kern_ms > 0 else 0.0
     products = st["products"]
     prod_per_s = products / (ms_per_step * 1e-3)
+    names = [f"{['power', 'block', 'gstep', 'horner'][k]}{i}" for k, i in zip(st["kind"], st["index"])]
+    stages = {}
+    for nm, ms, by, pr, sk in zip(names, st["stage_ms"], kern_bytes, st["stage_products"],
+                                  st["stage_rows_skipped"]):
+        gbs = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        stages[nm] = {"us": round(1e3 * ms, 2), "bytes": by, "GBps": round(gbs, 1),
+                      "frac": round(gbs / HBM_PEAK_GBS, 4), "products": pr, "rows_skipped": sk}
+    dom = max(stages, key=lambda k: stages[k]["us"]) if stages else None
+    traffic = measured_traffic(cfg["name"])
 
     res = {
         "metric": "series evals/s + SpGEMM HBM GB/s vs plain filtered PS; p50/p99 latency at QPS",
@@ -297,6 +427,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "wall_ms_per_step": 1e3 * el / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -309,28 +440,39 @@ def main():
                       {"eps_tol": args.eps_tol, "e_r": args.e_r, "N": series_info["N"]}),
                    "series": "exp", "nnz_F": st["nnz_out"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg["name"]),
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "algorithmic_bytes_per_launch": bytes_eval / launches if launches else None,
+                     "traffic_frac": (traffic / ((kern_ms / launches) * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                      if traffic and launches and kern_ms > 0 else None),
+                     "algorithmic_bytes_per_launch": bytes_kernel / launches if launches else None,
                      "kernel": "k_numeric_lds",
                      "launches_per_step": launches,
                      "avg_launch_ms": kern_ms / launches if launches else None,
-                     "algorithmic_bytes_per_step": bytes_eval},
+                     "algorithmic_bytes_per_step": bytes_kernel,
+                     "evaluation_bytes_per_step": bytes_eval,
+                     "evaluation_GBps": bytes_eval / (ms_per_step * 1e-3) / 1e9,
+                     "dominant_launch": dom,
+                     "dominant_launch_frac": stages[dom]["frac"] if dom else None},
+        "stages": stages,
         "products_per_s": prod_per_s,
         "products_per_step": products,
         "products_skipped_per_step": st["products_skipped"],
         "plan_setup_ms": setup_ms,
         "rows_wide_per_step": st["rows_wide"],
         "rows_global_per_step": st["rows_global"],
-        "stage_ms": {f"{['power', 'block', 'gstep', 'horner'][k]}{i}": round(ms, 4)
-                     for k, i, ms in zip(st["kind"], st["index"], st["stage_ms"])},
     }
     if args.filter != "fixed":
         res["alg1_iters_per_step"] = int(sum(st["stage_alg1_iters"]))
+    plan.close()
+    if args.batch_count > 0 and args.filter == "fixed" and args.workload == "lap2d":
+        log(f"batch leg: {args.batch_count} banded instances ...")
+        res["batch"] = bench_batch(args, stream)
+        log(f"batch: {res['batch']['batch_ms']:.2f} ms vs plain {res['batch']['plain_ms']:.2f} ms "
+            f"({res['batch']['speedup_vs_plain']:.2f}x)")
     if args.cpu_budget > 0 and args.filter == "fixed":
         log("timing the CPU oracle ...")
-        res["cpu_baseline"] = cpu_baseline(cfg, args.cpu_budget)
-    plan.close()
+        res["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(res), flush=True)
 
 

@@ -186,8 +186,14 @@ struct Workspace {
         slots = std::min<int64_t>(slots, std::max<int64_t>(4, ((nn + 3) / 4) * 4));
         slots = (slots + numeric_waves_per_block() - 1) / numeric_waves_per_block() * numeric_waves_per_block();
         g_slots = (int32_t)slots;
-        FPS_TRY(gscratch.ensure(sizeof(uint32_t) * (size_t)(per_slot_u32 * slots)));
-        return FPS_OK;
+        return FPS_OK;  // the device-memory kernel's workspace: ensure_global, when a stage needs it
+    }
+
+    // The device-memory kernel's per-wavefront workspace, allocated the
+    // first time a stage sends rows to that kernel (most plans never do).
+    fps_status ensure_global()
+    {
+        return gscratch.ensure(sizeof(uint32_t) * (size_t)g_stride * (size_t)g_slots);
     }
 };
 
@@ -414,6 +420,10 @@ struct Engine {
             HIP_TRY(hipStreamSynchronize(s));
             learned_global[(size_t)idx] = std::max<int64_t>(learned_global[(size_t)idx], (int64_t)c.fb2_count);
             run_global = c.fb2_count > 0;
+        }
+        if (run_global) {
+            FPS_TRY(ws.ensure_global());
+            a.g_scratch = ws.gscratch.as<uint32_t>();
         }
         if (run_global)
             HIP_TRY(launch_numeric_global(
