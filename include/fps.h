@@ -438,6 +438,102 @@ fps_status fps_batch_item_info(fps_batch b, int32_t i, int32_t *s, int32_t *grou
 /* Release the batch (synchronises its last stream). */
 void fps_batch_destroy(fps_batch b);
 
+/* ---------------------------------------------------------------------- */
+/* Server: continuous admission of evaluations by device-memory footprint  */
+/* ---------------------------------------------------------------------- */
+
+typedef struct fps_server_s *fps_server;
+
+typedef struct {
+    int32_t slots;        /* worker slots (1..64), each a host thread with its own stream: up to `slots`
+                             requests run at once and their kernels overlap on the device */
+    int32_t max_queue;    /* waiting requests accepted before fps_server_submit refuses (0: 4096) */
+    int64_t hbm_budget;   /* device bytes that the running requests may reserve and the finished,
+                             unreleased results may hold, in total (> 0) */
+    uint64_t flags;       /* plan flags applied to every request (FPS_FLAG_NO_VALIDATE, FPS_FLAG_NO_SKIP) */
+    int32_t fake_backend; /* 1: nothing is computed and no device call is made: a worker holds each request
+                             for n microseconds and charges 100 n bytes against its reservation (tests of
+                             the scheduler without a GPU) */
+    int32_t reserved;
+} fps_server_opts;
+
+/* request states */
+#define FPS_REQ_QUEUED 0
+#define FPS_REQ_RUNNING 1
+#define FPS_REQ_DONE 2
+#define FPS_REQ_FAILED 3
+
+/*
+ * A server of fixed-threshold filtered PS evaluations (each as
+ * fps_plan_create + fps_eval would run it).  Requests wait in one FIFO queue;
+ * the head is admitted when a slot is free and its reservation fits the
+ * budget beside the reservations of the running requests and the bytes of
+ * the finished results not yet released.  A request's plan may hold at most
+ * its reservation (an estimate from n, nnz, m and s, or the caller's hint);
+ * if it needs more, it goes back to the head of the queue with four times
+ * the reservation (up to the whole budget) and runs again when that fits.
+ * A finished request keeps only its result (canonical CSR) on the device
+ * until fps_server_release.  Results do not depend on what else runs: each
+ * request is its own plan, evaluated exactly as alone.
+ */
+fps_status fps_server_create(fps_server *out, const fps_server_opts *opts);
+
+/*
+ * Queue an evaluation: Z (device CSR, borrowed until the request is done or
+ * failed), coefficients c[0..m] (HOST, copied), block size s (0: floor(sqrt(m)),
+ * the q of eq. 6, at least 1), threshold tau; reserve_hint > 0 sets the first
+ * reservation in bytes.  *ticket identifies the request.  FPS_ERR_CAPACITY
+ * when max_queue requests are waiting (the caller retries later).
+ */
+fps_status fps_server_submit(fps_server sv, const fps_csr_view *Z, const double *coeffs, int32_t m, int32_t s,
+                             double tau, int64_t reserve_hint, int64_t *ticket);
+
+/* Wait until the request is done or failed, or timeout_ms passes (< 0: no
+ * limit); *state gets its state.  The request's own status is in
+ * fps_server_request_info. */
+fps_status fps_server_wait(fps_server sv, int64_t ticket, int64_t timeout_ms, int32_t *state);
+
+/* The result of a done request: entries, and a copy into caller-owned DEVICE
+ * buffers (row_ptr int64[n + 1], col int32[nnz], val double[nnz]) enqueued on
+ * `stream`.  FPS_ERR_NOT_READY unless done. */
+fps_status fps_server_result_nnz(fps_server sv, int64_t ticket, int64_t *nnz);
+fps_status fps_server_result_copy(fps_server sv, int64_t ticket, int64_t *row_ptr, int32_t *col, double *val,
+                                  fps_stream stream);
+
+/* Forget a done or failed request and free its result (after the copies
+ * out of it enqueued by fps_server_result_copy have finished). */
+fps_status fps_server_release(fps_server sv, int64_t ticket);
+
+typedef struct {
+    int32_t state;       /* FPS_REQ_* */
+    int32_t status;      /* fps_status of a finished request */
+    int32_t attempts;    /* runs (more than one after a reservation was too small) */
+    int32_t s;           /* block size used */
+    int64_t n;
+    int64_t reserve;     /* current reservation, bytes */
+    int64_t held;        /* bytes of the kept result (done requests) */
+    int64_t peak;        /* largest device bytes its plan held */
+    int64_t t_submit_ns; /* steady-clock times: submission, start of the last run, result ready */
+    int64_t t_start_ns;
+    int64_t t_done_ns;
+} fps_server_request;
+
+fps_status fps_server_request_info(fps_server sv, int64_t ticket, fps_server_request *out);
+
+typedef struct {
+    int64_t submitted, completed, failed, retries, refused;
+    int32_t running, queued, slots, peak_running;
+    int64_t reserved;      /* bytes reserved now (running) or held (finished, unreleased) */
+    int64_t peak_reserved; /* its largest value so far (never above the budget) */
+    int64_t budget;
+} fps_server_stats;
+
+fps_status fps_server_get_stats(fps_server sv, fps_server_stats *out);
+
+/* Stop the server: running requests finish, waiting ones fail; then free
+ * everything (results included). */
+void fps_server_destroy(fps_server sv);
+
 #ifdef __cplusplus
 }
 #endif

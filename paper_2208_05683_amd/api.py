@@ -178,3 +178,53 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+
+class Server:
+    """Continuous admission of evaluations by device-memory footprint (see
+    fps_server_create).  submit() returns a ticket; wait(), result() and
+    release() act on it."""
+
+    def __init__(self, slots: int, hbm_budget: int, max_queue: int = 0, flags: int = 0, fake_backend: bool = False):
+        self.handle = B.fps_server_create(slots, hbm_budget, max_queue, flags, fake_backend)
+        self._n = {}
+        self._dev = {}
+
+    def submit(self, Zd, coeffs, m: int, tau: float, s: int = 0, reserve_hint: int = 0) -> int:
+        t = B.fps_server_submit(self.handle, B.csr_view(*Zd), coeffs, m, s, tau, reserve_hint)
+        self._n[t] = int(Zd[0].numel() - 1)
+        self._dev[t] = Zd[0].device
+        return t
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> int:
+        return B.fps_server_wait(self.handle, ticket, timeout_ms)
+
+    def result(self, ticket: int, stream=None):
+        nnz = B.fps_server_result_nnz(self.handle, ticket)
+        out = _alloc_csr(self._n[ticket], nnz, self._dev[ticket])
+        B.fps_server_result_copy(self.handle, ticket, *out, stream=stream)
+        torch.cuda.current_stream(self._dev[ticket]).synchronize() if stream is None else stream.synchronize()
+        return out
+
+    def info(self, ticket: int) -> dict:
+        return B.fps_server_request_info(self.handle, ticket)
+
+    def release(self, ticket: int):
+        B.fps_server_release(self.handle, ticket)
+        self._n.pop(ticket, None)
+        self._dev.pop(ticket, None)
+
+    def stats(self) -> dict:
+        return B.fps_server_get_stats(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            B.fps_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -121,6 +121,24 @@ class fps_batch_stats(C.Structure):
     ]
 
 
+class fps_server_opts(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("max_queue", C.c_int32), ("hbm_budget", C.c_int64), ("flags", C.c_uint64),
+                ("fake_backend", C.c_int32), ("reserved", C.c_int32)]
+
+
+class fps_server_request(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("attempts", C.c_int32), ("s", C.c_int32),
+                ("n", C.c_int64), ("reserve", C.c_int64), ("held", C.c_int64), ("peak", C.c_int64),
+                ("t_submit_ns", C.c_int64), ("t_start_ns", C.c_int64), ("t_done_ns", C.c_int64)]
+
+
+class fps_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("retries", C.c_int64),
+                ("refused", C.c_int64), ("running", C.c_int32), ("queued", C.c_int32), ("slots", C.c_int32),
+                ("peak_running", C.c_int32), ("reserved", C.c_int64), ("peak_reserved", C.c_int64),
+                ("budget", C.c_int64)]
+
+
 _P = C.POINTER
 _vp = C.c_void_p
 _SIGS = {
@@ -155,6 +173,16 @@ _SIGS = {
     "fps_batch_get_stats": (C.c_int32, [_vp, _P(fps_batch_stats)]),
     "fps_batch_item_info": (C.c_int32, [_vp, C.c_int32, _P(C.c_int32), _P(C.c_int32), _P(C.c_int64)]),
     "fps_batch_destroy": (None, [_vp]),
+    "fps_server_create": (C.c_int32, [_P(_vp), _P(fps_server_opts)]),
+    "fps_server_submit": (C.c_int32, [_vp, _P(fps_csr_view), _P(C.c_double), C.c_int32, C.c_int32, C.c_double,
+                                      C.c_int64, _P(C.c_int64)]),
+    "fps_server_wait": (C.c_int32, [_vp, C.c_int64, C.c_int64, _P(C.c_int32)]),
+    "fps_server_result_nnz": (C.c_int32, [_vp, C.c_int64, _P(C.c_int64)]),
+    "fps_server_result_copy": (C.c_int32, [_vp, C.c_int64, _vp, _vp, _vp, _vp]),
+    "fps_server_release": (C.c_int32, [_vp, C.c_int64]),
+    "fps_server_request_info": (C.c_int32, [_vp, C.c_int64, _P(fps_server_request)]),
+    "fps_server_get_stats": (C.c_int32, [_vp, _P(fps_server_stats)]),
+    "fps_server_destroy": (None, [_vp]),
     "fps_plan_create_series": (C.c_int32, [_P(_vp), _P(fps_csr_view), _P(C.c_double), C.c_int32,
                                            _P(fps_series_opts), C.c_uint64, _vp]),
     "fps_plan_series_info": (C.c_int32, [_vp, _P(C.c_int32), _P(C.c_int32), _P(C.c_double), _P(C.c_double),
@@ -421,3 +449,58 @@ def fps_batch_item_info(b, i: int, candidates: int = 0) -> dict:
 
 def fps_batch_destroy(b):
     _lib.fps_batch_destroy(b)
+
+
+# ---- server -------------------------------------------------------------------
+
+def fps_server_create(slots: int, hbm_budget: int, max_queue: int = 0, flags: int = 0, fake_backend: bool = False):
+    o = fps_server_opts(int(slots), int(max_queue), int(hbm_budget), int(flags), 1 if fake_backend else 0, 0)
+    h = C.c_void_p()
+    _check(_lib.fps_server_create(C.byref(h), C.byref(o)), "fps_server_create")
+    return h
+
+
+def fps_server_submit(sv, Z: fps_csr_view, coeffs, m: int, s: int, tau: float, reserve_hint: int = 0) -> int:
+    arr = (C.c_double * (m + 1))(*[float(x) for x in coeffs[: m + 1]])
+    t = C.c_int64()
+    _check(_lib.fps_server_submit(sv, C.byref(Z), arr, int(m), int(s), float(tau), int(reserve_hint), C.byref(t)),
+           "fps_server_submit")
+    return t.value
+
+
+def fps_server_wait(sv, ticket: int, timeout_ms: int = -1) -> int:
+    st = C.c_int32()
+    _check(_lib.fps_server_wait(sv, int(ticket), int(timeout_ms), C.byref(st)), "fps_server_wait")
+    return st.value
+
+
+def fps_server_result_nnz(sv, ticket: int) -> int:
+    v = C.c_int64()
+    _check(_lib.fps_server_result_nnz(sv, int(ticket), C.byref(v)), "fps_server_result_nnz")
+    return v.value
+
+
+def fps_server_result_copy(sv, ticket: int, row_ptr, col, val, stream=None):
+    _check(_lib.fps_server_result_copy(sv, int(ticket), row_ptr.data_ptr(), col.data_ptr() if col.numel() else None,
+                                       val.data_ptr() if val.numel() else None, _stream_handle(stream)),
+           "fps_server_result_copy")
+
+
+def fps_server_release(sv, ticket: int):
+    _check(_lib.fps_server_release(sv, int(ticket)), "fps_server_release")
+
+
+def fps_server_request_info(sv, ticket: int) -> dict:
+    r = fps_server_request()
+    _check(_lib.fps_server_request_info(sv, int(ticket), C.byref(r)), "fps_server_request_info")
+    return {name: getattr(r, name) for name, _ in fps_server_request._fields_}
+
+
+def fps_server_get_stats(sv) -> dict:
+    st = fps_server_stats()
+    _check(_lib.fps_server_get_stats(sv, C.byref(st)), "fps_server_get_stats")
+    return {name: getattr(st, name) for name, _ in fps_server_stats._fields_}
+
+
+def fps_server_destroy(sv):
+    _lib.fps_server_destroy(sv)

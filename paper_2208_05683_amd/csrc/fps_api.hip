@@ -8,12 +8,16 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <chrono>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <memory>
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 using namespace fps;
@@ -49,25 +53,50 @@ fps_status set_error(fps_status st, const char* fmt, ...)
         if (s_ != FPS_OK) return s_;       \
     } while (0)
 
+// Device bytes held by one owner (a plan), with an optional limit.  The
+// owner makes its account current on the calling thread (AcctScope) for the
+// duration of each entry point; allocations made meanwhile are charged to
+// it and fail with FPS_ERR_CAPACITY past the limit.
+struct MemAcct {
+    size_t used = 0;
+    size_t peak = 0;
+    size_t cap = SIZE_MAX;
+};
+thread_local MemAcct* t_acct = nullptr;
+
+struct AcctScope {
+    MemAcct* prev;
+    explicit AcctScope(MemAcct* a) : prev(t_acct) { t_acct = a; }
+    ~AcctScope() { t_acct = prev; }
+};
+
 // Grow-only device allocation.
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    MemAcct* acct = nullptr;  // the account charged for p
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            (void)hipFree(p);
+            if (acct) acct->used -= bytes;
+        }
         p = nullptr;
         bytes = 0;
+        acct = nullptr;
     }
     fps_status ensure(size_t want)
     {
         if (want <= bytes && p) return FPS_OK;
         release();
         const size_t b = std::max<size_t>(want, 256);
+        if (t_acct && (b > t_acct->cap || t_acct->used > t_acct->cap - b))
+            return set_error(FPS_ERR_CAPACITY, "device memory limit of %zu bytes reached (%zu held, %zu more wanted)",
+                             t_acct->cap, t_acct->used, b);
         hipError_t e = hipMalloc(&p, b);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -75,6 +104,11 @@ struct DevBuf {
             return set_error(FPS_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
         }
         bytes = b;
+        acct = t_acct;
+        if (acct) {
+            acct->used += b;
+            acct->peak = std::max(acct->peak, acct->used);
+        }
         return FPS_OK;
     }
     template <typename T>
@@ -816,6 +850,7 @@ MatView canon_view(const fps_csr_view* v, const RowInfo* info, const uint2* sw, 
 // ===========================================================================
 
 struct fps_plan_s {
+    MemAcct acct;  // first member: it outlives every buffer of the plan
     fps_csr_view Z{};
     std::vector<double> c;
     int m = 0, s = 0;
@@ -1091,8 +1126,26 @@ fps_status fps_schedule(int32_t m, int32_t s, int32_t* N, int32_t* q, int32_t* b
     return FPS_OK;
 }
 
+}  // extern "C"
+
+// fps_plan_create_ex with a limit on the device bytes the plan may hold
+// (creation and every later evaluation); past it an allocation fails with
+// FPS_ERR_CAPACITY.
+static fps_status plan_create_limited(fps_plan* out, const fps_csr_view* Z, const double* coeffs, int32_t m, int32_t s,
+                                      const fps_filter_opts* opts, uint64_t flags, fps_stream stream, size_t mem_cap);
+
+extern "C" {
+
 fps_status fps_plan_create_ex(fps_plan* out, const fps_csr_view* Z, const double* coeffs, int32_t m, int32_t s,
                               const fps_filter_opts* opts, uint64_t flags, fps_stream stream)
+{
+    return plan_create_limited(out, Z, coeffs, m, s, opts, flags, stream, SIZE_MAX);
+}
+
+}  // extern "C"
+
+static fps_status plan_create_limited(fps_plan* out, const fps_csr_view* Z, const double* coeffs, int32_t m, int32_t s,
+                                      const fps_filter_opts* opts, uint64_t flags, fps_stream stream, size_t mem_cap)
 {
     g_last_error.clear();
     if (!out) return set_error(FPS_ERR_INVALID_ARG, "out is NULL");
@@ -1132,6 +1185,8 @@ fps_status fps_plan_create_ex(fps_plan* out, const fps_csr_view* Z, const double
 
     std::unique_ptr<fps_plan_s> p(new (std::nothrow) fps_plan_s());
     if (!p) return set_error(FPS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->acct.cap = mem_cap;
+    AcctScope scope(&p->acct);
     p->Z = *Z;
     p->c.assign(coeffs, coeffs + m + 1);
     p->m = m;
@@ -1174,6 +1229,8 @@ fps_status fps_plan_create_ex(fps_plan* out, const fps_csr_view* Z, const double
     return FPS_OK;
 }
 
+extern "C" {
+
 fps_status fps_plan_create(fps_plan* out, const fps_csr_view* Z, const double* coeffs, int32_t m, int32_t s,
                            double tau, uint64_t flags, fps_stream stream)
 {
@@ -1186,6 +1243,7 @@ fps_status fps_plan_create(fps_plan* out, const fps_csr_view* Z, const double* c
 fps_status fps_eval(fps_plan p, fps_stream stream)
 {
     if (!p) return set_error(FPS_ERR_INVALID_ARG, "plan is NULL");
+    AcctScope scope(&p->acct);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const bool size = (p->flags & FPS_FLAG_SYNC_SIZES) || !p->sized_once;
     p->last_stream = s;
@@ -1216,6 +1274,7 @@ static fps_status read_errors(fps_plan p, unsigned long long* err)
 // learned capacity turned out too small.
 static fps_status finish(fps_plan p)
 {
+    AcctScope scope(&p->acct);
     HIP_TRY(hipStreamSynchronize(p->last_stream));
     unsigned long long err = 0;
     FPS_TRY(read_errors(p, &err));
@@ -2145,5 +2204,394 @@ fps_status fps_batch_item_info(fps_batch b, int32_t i, int32_t* s, int32_t* grou
 }
 
 void fps_batch_destroy(fps_batch b) { delete b; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Server
+// ===========================================================================
+
+namespace {
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// First reservation of a request: the plan's per-row arrays and, per stage,
+// a slack matrix for rows of about (s + 1) times Z's entries per row, at
+// 24 bytes an entry (value, column, structure word).  A request that needs
+// more is run again with a larger reservation.
+size_t first_reservation(int64_t n, int64_t nnz, int m, int s)
+{
+    Schedule sc;
+    make_schedule(m, s, &sc);
+    const double stages = (double)(sc.J + sc.b + 2);
+    const double per_row = (double)nnz / (double)std::max<int64_t>(n, 1);
+    const double entries = (double)n * std::max(1.0, per_row) * (double)(s + 1);
+    const double bytes = (double)n * 160.0 + stages * (entries * 24.0 + (double)n * 40.0);
+    return (size_t)std::min(bytes, 1e18);
+}
+
+}  // namespace
+
+struct fps_server_s {
+    struct Req {
+        int64_t id = 0;
+        fps_csr_view Z{};
+        std::vector<double> c;
+        int m = 0, s = 0;
+        double tau = 0.0;
+        int state = FPS_REQ_QUEUED;
+        fps_status status = FPS_OK;
+        std::string error;
+        int attempts = 0;
+        size_t reserve = 0, held = 0, peak = 0;
+        int64_t nnz_out = 0;
+        DevBuf rp, col, val;  // the result, kept until release
+        hipEvent_t copied = nullptr;  // recorded after the last copy out of the result
+        int64_t t_submit = 0, t_start = 0, t_done = 0;
+        ~Req()
+        {
+            if (copied) {
+                (void)hipEventSynchronize(copied);
+                (void)hipEventDestroy(copied);
+            }
+        }
+    };
+
+    fps_server_opts o{};
+    int device = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req*> queue;
+    std::unordered_map<int64_t, std::unique_ptr<Req>> reqs;
+    int64_t next_id = 1;
+    size_t reserved = 0, peak_reserved = 0;
+    int running = 0, peak_running = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, retries = 0, refused = 0;
+    bool stopping = false;
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> streams;
+
+    // Runs one attempt of a request on `st` (no lock held).
+    void execute(Req* r, hipStream_t st)
+    {
+        r->status = FPS_OK;
+        r->error.clear();
+        if (o.fake_backend) {
+            std::this_thread::sleep_for(std::chrono::microseconds(r->Z.n));
+            r->peak = (size_t)r->Z.n * 100;
+            if (r->peak > r->reserve) {
+                r->status = FPS_ERR_CAPACITY;
+                r->error = "fake backend: reservation too small";
+            } else {
+                r->held = 0;
+                r->nnz_out = 0;
+            }
+            return;
+        }
+        fps_filter_opts fo{};
+        fo.filter = FPS_FILTER_FIXED;
+        fo.tau = r->tau;
+        fps_plan p = nullptr;
+        fps_status stt = plan_create_limited(&p, &r->Z, r->c.data(), r->m, r->s, &fo, o.flags,
+                                             reinterpret_cast<fps_stream>(st), r->reserve);
+        if (stt == FPS_OK) stt = fps_eval(p, reinterpret_cast<fps_stream>(st));
+        if (stt == FPS_OK) stt = finish(p);
+        if (stt == FPS_OK) {
+            // keep only the result, in buffers of the server's own
+            const int64_t n = r->Z.n;
+            int64_t nnz = 0;
+            stt = fps_result_nnz(p, &nnz);
+            // the copy exists beside the plan for a moment: it must fit the
+            // reservation too
+            const size_t copy = sizeof(int64_t) * (size_t)(n + 1) + 12 * (size_t)std::max<int64_t>(nnz, 1) + 768;
+            if (stt == FPS_OK && p->acct.used + copy > r->reserve)
+                stt = set_error(FPS_ERR_CAPACITY, "the result copy does not fit the reservation");
+            if (stt == FPS_OK) stt = r->rp.ensure(sizeof(int64_t) * (size_t)(n + 1));
+            if (stt == FPS_OK) stt = r->col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
+            if (stt == FPS_OK) stt = r->val.ensure(sizeof(double) * (size_t)std::max<int64_t>(nnz, 1));
+            if (stt == FPS_OK)
+                stt = fps_result_copy(p, r->rp.as<int64_t>(), r->col.as<int32_t>(), r->val.as<double>(),
+                                      reinterpret_cast<fps_stream>(st));
+            if (stt == FPS_OK && hipStreamSynchronize(st) != hipSuccess) {
+                (void)hipGetLastError();
+                stt = set_error(FPS_ERR_HIP, "stream synchronisation failed");
+            }
+            r->nnz_out = nnz;
+            r->held = r->rp.bytes + r->col.bytes + r->val.bytes;
+        }
+        if (p) r->peak = std::max(p->acct.peak, p->acct.used + r->rp.bytes + r->col.bytes + r->val.bytes);
+        if (stt != FPS_OK) {
+            r->error = g_last_error;
+            r->rp.release();
+            r->col.release();
+            r->val.release();
+            r->held = 0;
+        }
+        r->status = stt;
+        if (p) fps_plan_destroy(p);
+    }
+
+    void worker(int k)
+    {
+        if (!o.fake_backend) (void)hipSetDevice(device);
+        for (;;) {
+            Req* r = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] {
+                    return stopping || (!queue.empty() && reserved + queue.front()->reserve <= (size_t)o.hbm_budget);
+                });
+                if (stopping) return;
+                r = queue.front();
+                queue.pop_front();
+                reserved += r->reserve;
+                peak_reserved = std::max(peak_reserved, reserved);
+                running++;
+                peak_running = std::max(peak_running, running);
+                r->state = FPS_REQ_RUNNING;
+                r->attempts++;
+                r->t_start = now_ns();
+            }
+            execute(r, o.fake_backend ? nullptr : streams[(size_t)k]);
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                running--;
+                reserved -= r->reserve;
+                if (r->status == FPS_ERR_CAPACITY && r->reserve < (size_t)o.hbm_budget && r->attempts < 16) {
+                    // the reservation was too small: back to the head with more
+                    r->reserve = (size_t)std::min<double>((double)o.hbm_budget, 4.0 * (double)r->reserve);
+                    r->state = FPS_REQ_QUEUED;
+                    queue.push_front(r);
+                    retries++;
+                } else {
+                    r->t_done = now_ns();
+                    if (r->status == FPS_OK) {
+                        r->state = FPS_REQ_DONE;
+                        reserved += r->held;
+                        peak_reserved = std::max(peak_reserved, reserved);
+                        completed++;
+                    } else {
+                        r->state = FPS_REQ_FAILED;
+                        failed++;
+                    }
+                }
+            }
+            cv_work.notify_all();
+            cv_done.notify_all();
+        }
+    }
+
+    Req* find(int64_t id)
+    {
+        auto it = reqs.find(id);
+        return it == reqs.end() ? nullptr : it->second.get();
+    }
+
+    ~fps_server_s()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stopping = true;
+            for (Req* r : queue) {
+                r->state = FPS_REQ_FAILED;
+                r->status = FPS_ERR_NOT_READY;
+                r->t_done = now_ns();
+            }
+            queue.clear();
+        }
+        cv_work.notify_all();
+        cv_done.notify_all();
+        for (auto& t : workers)
+            if (t.joinable()) t.join();
+        if (!o.fake_backend) (void)hipDeviceSynchronize();
+        reqs.clear();
+        for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+    }
+};
+
+extern "C" {
+
+fps_status fps_server_create(fps_server* out, const fps_server_opts* opts)
+{
+    g_last_error.clear();
+    if (!out || !opts) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    if (opts->slots < 1 || opts->slots > 64) return set_error(FPS_ERR_INVALID_ARG, "slots must be in [1, 64]");
+    if (opts->hbm_budget <= 0) return set_error(FPS_ERR_INVALID_ARG, "hbm_budget must be > 0");
+    if (opts->max_queue < 0) return set_error(FPS_ERR_INVALID_ARG, "max_queue must be >= 0");
+    if (opts->flags & ~(uint64_t)(FPS_FLAG_NO_VALIDATE | FPS_FLAG_NO_SKIP))
+        return set_error(FPS_ERR_INVALID_ARG, "unsupported server flags");
+    std::unique_ptr<fps_server_s> sv(new (std::nothrow) fps_server_s());
+    if (!sv) return set_error(FPS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    sv->o = *opts;
+    if (sv->o.max_queue == 0) sv->o.max_queue = 4096;
+    if (!opts->fake_backend) {
+        HIP_TRY(hipGetDevice(&sv->device));
+        for (int k = 0; k < opts->slots; ++k) {
+            hipStream_t s = nullptr;
+            HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+            sv->streams.push_back(s);
+        }
+    }
+    fps_server_s* raw = sv.get();
+    for (int k = 0; k < opts->slots; ++k) sv->workers.emplace_back([raw, k] { raw->worker(k); });
+    *out = sv.release();
+    return FPS_OK;
+}
+
+fps_status fps_server_submit(fps_server sv, const fps_csr_view* Z, const double* coeffs, int32_t m, int32_t s,
+                             double tau, int64_t reserve_hint, int64_t* ticket)
+{
+    g_last_error.clear();
+    if (!sv || !ticket || !coeffs) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    FPS_TRY(check_view(Z, "Z", -1));
+    if (m < 0) return set_error(FPS_ERR_INVALID_ARG, "m must be >= 0");
+    if (s < 0 || s > FPS_MAX_S) return set_error(FPS_ERR_INVALID_ARG, "s out of range");
+    if (!std::isfinite(tau) || tau < 0.0) return set_error(FPS_ERR_INVALID_ARG, "tau must be finite and >= 0");
+    for (int k = 0; k <= m; ++k)
+        if (!std::isfinite(coeffs[k])) return set_error(FPS_ERR_INVALID_ARG, "coefficient %d is not finite", k);
+    std::unique_ptr<fps_server_s::Req> r(new (std::nothrow) fps_server_s::Req());
+    if (!r) return set_error(FPS_ERR_OUT_OF_MEMORY, "host allocation failed");
+    r->Z = *Z;
+    r->c.assign(coeffs, coeffs + m + 1);
+    r->m = m;
+    if (s == 0) {
+        s = 0;
+        while ((s + 1) * (s + 1) <= m) ++s;
+        s = std::min(std::max(s, 1), FPS_MAX_S);
+    }
+    r->s = s;
+    r->tau = tau;
+    r->reserve = reserve_hint > 0 ? (size_t)reserve_hint : first_reservation(Z->n, Z->nnz, m, s);
+    r->reserve = std::min(r->reserve, (size_t)sv->o.hbm_budget);
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->stopping) return set_error(FPS_ERR_INVALID_ARG, "server is stopping");
+        if ((int64_t)sv->queue.size() >= sv->o.max_queue) {
+            sv->refused++;
+            return set_error(FPS_ERR_CAPACITY, "server queue full (%d waiting)", sv->o.max_queue);
+        }
+        r->id = sv->next_id++;
+        r->t_submit = now_ns();
+        *ticket = r->id;
+        sv->queue.push_back(r.get());
+        sv->reqs.emplace(r->id, std::move(r));
+        sv->submitted++;
+    }
+    sv->cv_work.notify_all();
+    return FPS_OK;
+}
+
+fps_status fps_server_wait(fps_server sv, int64_t ticket, int64_t timeout_ms, int32_t* state)
+{
+    if (!sv) return set_error(FPS_ERR_INVALID_ARG, "server is NULL");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    fps_server_s::Req* r = sv->find(ticket);
+    if (!r) return set_error(FPS_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+    auto finished = [&] { return r->state == FPS_REQ_DONE || r->state == FPS_REQ_FAILED; };
+    if (timeout_ms < 0)
+        sv->cv_done.wait(lk, finished);
+    else
+        sv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), finished);
+    if (state) *state = r->state;
+    return FPS_OK;
+}
+
+fps_status fps_server_result_nnz(fps_server sv, int64_t ticket, int64_t* nnz)
+{
+    if (!sv || !nnz) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    fps_server_s::Req* r = sv->find(ticket);
+    if (!r) return set_error(FPS_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+    if (r->state != FPS_REQ_DONE) return set_error(FPS_ERR_NOT_READY, "request %lld is not done", (long long)ticket);
+    *nnz = r->nnz_out;
+    return FPS_OK;
+}
+
+fps_status fps_server_result_copy(fps_server sv, int64_t ticket, int64_t* row_ptr, int32_t* col, double* val,
+                                  fps_stream stream)
+{
+    if (!sv || !row_ptr) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    fps_server_s::Req* r = sv->find(ticket);
+    if (!r) return set_error(FPS_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+    if (r->state != FPS_REQ_DONE) return set_error(FPS_ERR_NOT_READY, "request %lld is not done", (long long)ticket);
+    if (sv->o.fake_backend) return set_error(FPS_ERR_INVALID_ARG, "the fake backend has no results");
+    if (r->nnz_out > 0 && (!col || !val)) return set_error(FPS_ERR_INVALID_ARG, "null col/val with nnz > 0");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(row_ptr, r->rp.p, sizeof(int64_t) * (size_t)(r->Z.n + 1), hipMemcpyDeviceToDevice, s));
+    if (r->nnz_out > 0) {
+        HIP_TRY(hipMemcpyAsync(col, r->col.p, sizeof(int32_t) * (size_t)r->nnz_out, hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(val, r->val.p, sizeof(double) * (size_t)r->nnz_out, hipMemcpyDeviceToDevice, s));
+    }
+    if (!r->copied) HIP_TRY(hipEventCreateWithFlags(&r->copied, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(r->copied, s));
+    return FPS_OK;
+}
+
+fps_status fps_server_release(fps_server sv, int64_t ticket)
+{
+    if (!sv) return set_error(FPS_ERR_INVALID_ARG, "server is NULL");
+    std::unique_ptr<fps_server_s::Req> gone;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        auto it = sv->reqs.find(ticket);
+        if (it == sv->reqs.end()) return set_error(FPS_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+        fps_server_s::Req* r = it->second.get();
+        if (r->state != FPS_REQ_DONE && r->state != FPS_REQ_FAILED)
+            return set_error(FPS_ERR_NOT_READY, "request %lld is still queued or running", (long long)ticket);
+        sv->reserved -= r->held;
+        gone = std::move(it->second);
+        sv->reqs.erase(it);
+    }
+    gone.reset();  // waits for the copies out of the result, then frees it
+    sv->cv_work.notify_all();
+    return FPS_OK;
+}
+
+fps_status fps_server_request_info(fps_server sv, int64_t ticket, fps_server_request* out)
+{
+    if (!sv || !out) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    fps_server_s::Req* r = sv->find(ticket);
+    if (!r) return set_error(FPS_ERR_INVALID_ARG, "unknown ticket %lld", (long long)ticket);
+    out->state = r->state;
+    out->status = r->status;
+    out->attempts = r->attempts;
+    out->s = r->s;
+    out->n = r->Z.n;
+    out->reserve = (int64_t)r->reserve;
+    out->held = (int64_t)r->held;
+    out->peak = (int64_t)r->peak;
+    out->t_submit_ns = r->t_submit;
+    out->t_start_ns = r->t_start;
+    out->t_done_ns = r->t_done;
+    return FPS_OK;
+}
+
+fps_status fps_server_get_stats(fps_server sv, fps_server_stats* out)
+{
+    if (!sv || !out) return set_error(FPS_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    out->submitted = sv->submitted;
+    out->completed = sv->completed;
+    out->failed = sv->failed;
+    out->retries = sv->retries;
+    out->refused = sv->refused;
+    out->running = sv->running;
+    out->queued = (int32_t)sv->queue.size();
+    out->slots = sv->o.slots;
+    out->peak_running = sv->peak_running;
+    out->reserved = (int64_t)sv->reserved;
+    out->peak_reserved = (int64_t)sv->peak_reserved;
+    out->budget = sv->o.hbm_budget;
+    return FPS_OK;
+}
+
+void fps_server_destroy(fps_server sv) { delete sv; }
 
 }  // extern "C"

@@ -1,0 +1,87 @@
+"""The server on the GPU: every request's result, computed while other
+requests of the mix run beside it, equals bit for bit the same request
+evaluated alone (its own plan) and the oracle; a reservation that is too
+small is retried larger; the budget bounds what is reserved."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from fps_inputs import generators as G
+
+from gpu_helpers import assert_same_csr, check_canonical, download, gpu_filtered_ps, upload
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix(count, max_n, seed=5):
+    return [r for r in G.serving_requests(count=count * 4, seed=seed) if r["Z"].n <= max_n][:count]
+
+
+def test_results_alone_and_in_the_mix_are_identical():
+    from paper_2208_05683_amd import api
+
+    reqs = _mix(16, 6000)
+    assert len(reqs) == 16 and len({r["fn"] for r in reqs}) == 3
+    dev = [upload(r["Z"]) for r in reqs]
+    sv = api.Server(slots=4, hbm_budget=32 << 30)
+    try:
+        tickets = [sv.submit(d, r["coeffs"], r["m"], r["tau"]) for d, r in zip(dev, reqs)]
+        for t in tickets:
+            assert sv.wait(t, 60000) == 2
+        st = sv.stats()
+        assert st["completed"] == 16 and st["peak_running"] >= 2  # requests overlapped
+        for t, r in zip(tickets, reqs):
+            info = sv.info(t)
+            s = info["s"]
+            assert s == max(1, int(np.floor(np.sqrt(r["m"]))))
+            got = download(sv.result(t))
+            check_canonical(got)
+            alone, _ = gpu_filtered_ps(r["Z"], r["coeffs"], r["m"], s, r["tau"])
+            assert_same_csr(got, alone, f"{r['name']} in the mix vs alone")
+            want, _ = O.filtered_ps(r["Z"], r["coeffs"], r["m"], s, r["tau"])
+            assert_same_csr(got, want, f"{r['name']} vs the oracle")
+            assert info["held"] > 0 and info["peak"] <= info["reserve"]
+            sv.release(t)
+        assert sv.stats()["reserved"] == 0
+    finally:
+        sv.close()
+
+
+def test_small_reservation_retried_and_budget_respected():
+    from paper_2208_05683_amd import api
+
+    reqs = _mix(6, 4000, seed=7)
+    dev = [upload(r["Z"]) for r in reqs]
+    budget = 2 << 30
+    sv = api.Server(slots=3, hbm_budget=budget)
+    try:
+        # far too small a first reservation: the plan's first allocation fails
+        tickets = [sv.submit(d, r["coeffs"], r["m"], r["tau"], reserve_hint=4096) for d, r in zip(dev, reqs)]
+        for t in tickets:
+            assert sv.wait(t, 60000) == 2
+        for t, r in zip(tickets, reqs):
+            info = sv.info(t)
+            assert info["attempts"] > 1 and info["status"] == 0
+            want, _ = O.filtered_ps(r["Z"], r["coeffs"], r["m"], info["s"], r["tau"])
+            assert_same_csr(download(sv.result(t)), want, r["name"])
+        st = sv.stats()
+        assert st["retries"] >= len(reqs) and st["peak_reserved"] <= budget
+    finally:
+        sv.close()
+
+
+def test_explicit_block_size_and_large_request():
+    from paper_2208_05683_amd import api
+
+    cfg = G.config2(side=120)
+    Zd = upload(cfg["Z"])
+    sv = api.Server(slots=2, hbm_budget=64 << 30)
+    try:
+        t = sv.submit(Zd, cfg["coeffs"], cfg["m"], cfg["tau"], s=cfg["s"])
+        assert sv.wait(t, 60000) == 2
+        want, _ = O.filtered_ps(cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"])
+        assert_same_csr(download(sv.result(t)), want, "lap2d 120")
+        assert sv.info(t)["s"] == cfg["s"]
+    finally:
+        sv.close()
