@@ -10,7 +10,10 @@ tau = 1e-12, with Z resident in HBM.  Prints one JSON line.
 
 The headline line also carries the batched leg (512 seeded banded instances
 in one graph-replayed batch against 512 plain evaluations; --batch-count 0
-skips it) and the CPU oracle baseline (--cpu-budget 0 skips it).
+skips it), the serving leg (the server against plain sequential evaluations
+on the mixed request stream, saturation and Poisson arrivals with p50/p99;
+--serve-requests 0 skips it) and the CPU oracle baseline (--cpu-budget 0
+skips it).
 
 Other lines (not the headline): --filter adaptive|series time Algorithm 1 and
 Algorithm 2 on the same matrix; --sweep banded times the paper's second test
@@ -132,6 +135,130 @@ def median(v):
     import statistics
 
     return statistics.median(v)
+
+
+def bench_serve(args, stream):
+    """The server on the serving mix (n log-uniform in [1000, 60000], half 2D
+    Laplacians and half random banded matrices, exp / cos / random series,
+    m in 12..30, tau = 1e-12; a pool of distinct requests kept on the device
+    and submitted in turn).  Throughputs: plain sequential evaluations (plan,
+    evaluation, result size, release, one request after the other, as the
+    plain API does them) and, at saturation, a one-slot server (the plain
+    path behind a queue, buffers reused) and the multi-slot server.  Then
+    Poisson arrivals at fractions of the plain rate and of the server's
+    saturation rate, with p50/p99 of arrival-to-result-ready latency.  Both
+    servers are long-lived and warmed on the request pool first."""
+    import threading
+
+    import numpy as np
+    import torch
+    from fps_inputs import generators as G
+    from paper_2208_05683_amd import api
+
+    pool = G.serving_requests(count=args.serve_pool, seed=5)
+    dev = [api.to_device(r["Z"].row_ptr, r["Z"].col, r["Z"].val) for r in pool]
+    q = [max(1, int(np.floor(np.sqrt(r["m"])))) for r in pool]
+    torch.cuda.synchronize()
+
+    def plain_one(k):
+        r = pool[k % len(pool)]
+        p = api.Plan(dev[k % len(pool)], r["coeffs"], r["m"], q[k % len(pool)], r["tau"])
+        p.eval(stream)
+        p.nnz()
+        p.close()
+
+    for k in range(min(8, len(pool))):  # warm-up
+        plain_one(k)
+    nplain = args.serve_requests
+    t0 = time.perf_counter()
+    for k in range(nplain):
+        plain_one(k)
+    x_plain = nplain / (time.perf_counter() - t0)
+
+    budget = int(args.serve_budget_gib * (1 << 30))
+    count = args.serve_requests
+
+    def run(sv, rate, n, offset, seed):
+        """n requests (rate None: all at once); returns throughput, latencies
+        (ms) and the number that failed."""
+        infos, tickets = [], []
+        done_evt = threading.Event()
+
+        def consumer():
+            for i in range(n):
+                while len(tickets) <= i:
+                    time.sleep(0.0002)
+                t = tickets[i]
+                sv.wait(t, -1)
+                infos.append(sv.info(t))
+                sv.release(t)
+            done_evt.set()
+
+        th = threading.Thread(target=consumer)
+        th.start()
+        rng = np.random.default_rng(seed)
+        arrivals = np.zeros(n) if rate is None else np.cumsum(rng.exponential(1.0 / rate, n))
+        start = time.perf_counter()
+        for i in range(n):
+            k = (offset + i) % len(pool)
+            wait = start + arrivals[i] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            r = pool[k]
+            tickets.append(sv.submit(dev[k], r["coeffs"], r["m"], r["tau"], s=q[k]))
+        done_evt.wait()
+        th.join()
+        t_first = min(x["t_submit_ns"] for x in infos)
+        t_last = max(x["t_done_ns"] for x in infos)
+        lat = [(x["t_done_ns"] - x["t_submit_ns"]) * 1e-6 for x in infos]
+        failed = sum(1 for x in infos if x["state"] != 2)
+        return n / ((t_last - t_first) * 1e-9), lat, failed
+
+    slots = args.serve_slots
+    servers = {"one_slot": api.Server(slots=1, hbm_budget=budget, max_queue=count + 8),
+               "server": api.Server(slots=slots, hbm_budget=budget, max_queue=count + 8)}
+    try:
+        for sv in servers.values():  # warm: threads, streams and the buffer pools
+            run(sv, None, len(pool), 0, 1)
+        sat = {}
+        for name, sv in servers.items():
+            x, lat, failed = run(sv, None, count, 0, 2)
+            sat[name] = {"evals_per_s": x, "p50_ms": float(np.percentile(lat, 50)),
+                         "p99_ms": float(np.percentile(lat, 99)), "failed": failed}
+        x_srv = sat["server"]["evals_per_s"]
+        levels = []
+        for base_name, base in (("plain", x_plain), ("server", x_srv)):
+            for frac in (0.25, 0.5, 0.75, 0.9):
+                rate = frac * base
+                row = {"fraction_of": f"{base_name} saturation", "fraction": frac, "qps": rate}
+                for name, sv in servers.items():
+                    if base_name == "server" and name == "one_slot" and rate > sat["one_slot"]["evals_per_s"]:
+                        row[name] = "overloaded: offered rate above its saturation throughput"
+                        continue
+                    x, lat, failed = run(sv, rate, count, 17, int(1000 * frac) + len(base_name))
+                    row[name] = {"evals_per_s": x, "p50_ms": float(np.percentile(lat, 50)),
+                                 "p99_ms": float(np.percentile(lat, 99)), "failed": failed}
+                log(f"serve {frac:.2f} x {base_name} ({rate:.0f} qps): " + "; ".join(
+                    f"{k} p50 {v['p50_ms']:.2f} p99 {v['p99_ms']:.2f} ms" for k, v in row.items()
+                    if isinstance(v, dict)))
+                levels.append(row)
+        stats = {name: sv.stats() for name, sv in servers.items()}
+    finally:
+        for sv in servers.values():
+            sv.close()
+    return {
+        "workload": "serving_mix_n1000-60000_lap2d-banded_exp-cos-rand_m12-30",
+        "distinct_requests": len(pool), "requests_per_run": count, "slots": slots,
+        "budget_GiB": args.serve_budget_gib,
+        "plain_sequential_evals_per_s": x_plain,
+        "saturation": sat,
+        "server_saturation_evals_per_s": x_srv,
+        "speedup_vs_plain": x_srv / x_plain,
+        "speedup_vs_one_slot": x_srv / sat["one_slot"]["evals_per_s"],
+        "poisson": levels,
+        "server_stats": {k: {kk: v[kk] for kk in ("completed", "failed", "retries", "peak_running",
+                                                   "peak_reserved")} for k, v in stats.items()},
+    }
 
 
 def bench_batch(args, stream):
@@ -319,6 +446,10 @@ def main():
                     help="run one device-to-device copy of this many MiB first (calibrates HBM counters)")
     ap.add_argument("--batch-count", type=int, default=512, help="instances of the batch leg (0 skips it)")
     ap.add_argument("--batch-steps", type=int, default=10, help="timed batch evaluations")
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests per serving run (0 skips the leg)")
+    ap.add_argument("--serve-pool", type=int, default=96, help="distinct serving requests kept on the device")
+    ap.add_argument("--serve-slots", type=int, default=8, help="server slots")
+    ap.add_argument("--serve-budget-gib", type=float, default=96.0, help="server device-memory budget")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -470,6 +601,11 @@ def main():
         res["batch"] = bench_batch(args, stream)
         log(f"batch: {res['batch']['batch_ms']:.2f} ms vs plain {res['batch']['plain_ms']:.2f} ms "
             f"({res['batch']['speedup_vs_plain']:.2f}x)")
+    if args.serve_requests > 0 and args.filter == "fixed" and args.workload == "lap2d":
+        log(f"serving leg: {args.serve_requests} requests per run ...")
+        res["serve"] = bench_serve(args, stream)
+        log(f"serve: plain {res['serve']['plain_sequential_evals_per_s']:.0f}/s, server saturation "
+            f"{res['serve']['server_saturation_evals_per_s']:.0f}/s ({res['serve']['speedup_vs_plain']:.2f}x)")
     if args.cpu_budget > 0 and args.filter == "fixed":
         log("timing the CPU oracle ...")
         res["cpu_baseline"] = cpu_baseline(cfg)

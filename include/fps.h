@@ -80,6 +80,15 @@ typedef int32_t fps_status;
                                         enter the error bound of eq. 23); turns the row skip off, so that
                                         every removed entry is computed */
 
+#define FPS_FLAG_DENSE 0x40ull       /* compute a sparse product densely on the FP64 matrix cores when its
+                                        multiply-adds reach 1/64 of the dense product's (n rounded up to 128,
+                                        cubed) and three dense n x n operands fit the free device memory;
+                                        the decision is taken per stage in the sizing evaluation.  The
+                                        product is then summed in the matrix cores' order: results agree
+                                        with the ordered sparse path to rounding (and entries within
+                                        rounding of tau may be kept or dropped differently), not bit for
+                                        bit.  Not with FPS_FLAG_DROP_STATS; not for batches */
+
 typedef struct ihipStream_t *fps_stream; /* same type as hipStream_t */
 
 typedef struct {
@@ -172,6 +181,8 @@ typedef struct {
     int32_t stage_alg1_mode[FPS_MAX_STAGES];
     int64_t stage_rows_skipped[FPS_MAX_STAGES]; /* output rows proven empty by the bound test */
     double stage_bytes[FPS_MAX_STAGES]; /* algorithmic bytes of the stage (see bytes_algorithmic) */
+    int32_t stage_dense[FPS_MAX_STAGES];  /* 1: the product ran on the dense path (FPS_FLAG_DENSE) */
+    int64_t dense_ld;                     /* leading dimension of the dense operands (0 if none ran) */
 } fps_stats;
 
 /* ---------------------------------------------------------------------- */
@@ -450,7 +461,8 @@ typedef struct {
     int32_t max_queue;    /* waiting requests accepted before fps_server_submit refuses (0: 4096) */
     int64_t hbm_budget;   /* device bytes that the running requests may reserve and the finished,
                              unreleased results may hold, in total (> 0) */
-    uint64_t flags;       /* plan flags applied to every request (FPS_FLAG_NO_VALIDATE, FPS_FLAG_NO_SKIP) */
+    uint64_t flags;       /* plan flags applied to every request (FPS_FLAG_NO_VALIDATE, FPS_FLAG_NO_SKIP,
+                             FPS_FLAG_DENSE) */
     int32_t fake_backend; /* 1: nothing is computed and no device call is made: a worker holds each request
                              for n microseconds and charges 100 n bytes against its reservation (tests of
                              the scheduler without a GPU) */

@@ -76,6 +76,8 @@ class fps_stats(C.Structure):
         ("stage_alg1_mode", C.c_int32 * FPS_MAX_STAGES),
         ("stage_rows_skipped", C.c_int64 * FPS_MAX_STAGES),
         ("stage_bytes", C.c_double * FPS_MAX_STAGES),
+        ("stage_dense", C.c_int32 * FPS_MAX_STAGES),
+        ("dense_ld", C.c_int64),
     ]
 
 

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfps.so")
-SOURCES = ["fps_kernels.hip", "fps_normest.hip", "fps_batch.hip", "fps_api.hip"]
+SOURCES = ["fps_kernels.hip", "fps_normest.hip", "fps_batch.hip", "fps_dense.hip", "fps_api.hip"]
 ARCH = "gfx950"
 
 

@@ -12,6 +12,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -70,11 +71,62 @@ struct AcctScope {
     ~AcctScope() { t_acct = prev; }
 };
 
-// Grow-only device allocation.
+// Device buffers recycled without hipMalloc / hipFree (a hipFree
+// synchronises the whole device, which would serialise concurrent requests).
+// Used by the server's worker threads, where every buffer is released only
+// after the stream that used it has been synchronised (and a result only
+// after the copies out of it have finished), so a block handed out again is
+// never still in use.  Sizes are rounded up to classes of 4 KiB below
+// 64 KiB, else to the next 2^k or 1.5 * 2^k.
+struct DevPool {
+    std::mutex mu;
+    std::multimap<size_t, void*> free_blocks;
+    size_t cached = 0;  // bytes of the free blocks
+
+    static size_t size_class(size_t b)
+    {
+        if (b <= (size_t(64) << 10)) return (b + 4095) / 4096 * 4096;
+        size_t p = size_t(1) << (63 - __builtin_clzll((unsigned long long)b));
+        if (p == b) return b;
+        return (b <= p + p / 2) ? p + p / 2 : 2 * p;
+    }
+    void* take(size_t cls)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = free_blocks.find(cls);
+        if (it == free_blocks.end()) return nullptr;
+        void* p = it->second;
+        free_blocks.erase(it);
+        cached -= cls;
+        return p;
+    }
+    void give(void* p, size_t cls)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        free_blocks.emplace(cls, p);
+        cached += cls;
+    }
+    // hipFree free blocks (largest first) until at most `keep` bytes are cached
+    void trim(size_t keep)
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        while (cached > keep && !free_blocks.empty()) {
+            auto it = std::prev(free_blocks.end());
+            (void)hipFree(it->second);
+            cached -= it->first;
+            free_blocks.erase(it);
+        }
+    }
+    ~DevPool() { trim(0); }
+};
+thread_local DevPool* t_pool = nullptr;
+
+// Grow-only device allocation (from the calling thread's pool if it has one).
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
     MemAcct* acct = nullptr;  // the account charged for p
+    DevPool* pool = nullptr;  // the pool p came from (it goes back there)
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
@@ -82,28 +134,37 @@ struct DevBuf {
     void release()
     {
         if (p) {
-            (void)hipFree(p);
+            if (pool)
+                pool->give(p, bytes);
+            else
+                (void)hipFree(p);
             if (acct) acct->used -= bytes;
         }
         p = nullptr;
         bytes = 0;
         acct = nullptr;
+        pool = nullptr;
     }
     fps_status ensure(size_t want)
     {
         if (want <= bytes && p) return FPS_OK;
         release();
-        const size_t b = std::max<size_t>(want, 256);
+        size_t b = std::max<size_t>(want, 256);
+        if (t_pool) b = DevPool::size_class(b);
         if (t_acct && (b > t_acct->cap || t_acct->used > t_acct->cap - b))
             return set_error(FPS_ERR_CAPACITY, "device memory limit of %zu bytes reached (%zu held, %zu more wanted)",
                              t_acct->cap, t_acct->used, b);
-        hipError_t e = hipMalloc(&p, b);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
-            return set_error(FPS_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
+        p = t_pool ? t_pool->take(b) : nullptr;
+        if (!p) {
+            hipError_t e = hipMalloc(&p, b);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                p = nullptr;
+                return set_error(FPS_ERR_OUT_OF_MEMORY, "hipMalloc(%zu) failed: %s", b, hipGetErrorString(e));
+            }
         }
         bytes = b;
+        pool = t_pool;
         acct = t_acct;
         if (acct) {
             acct->used += b;
@@ -178,7 +239,7 @@ struct Workspace {
     int32_t g_slots = 0;
     int max_stages = 0;
 
-    fps_status init(int64_t nn, int stages)
+    fps_status init(int64_t nn, int stages, hipStream_t st)
     {
         n = nn;
         max_stages = stages;
@@ -195,13 +256,7 @@ struct Workspace {
         FPS_TRY(znw.ensure(sizeof(int32_t) * rows));
         FPS_TRY(counters.ensure(sizeof(StageCounters) * (size_t)stages));
         FPS_TRY(dummy.ensure(128 * (sizeof(int32_t) + sizeof(double))));
-        {
-            hipError_t e = hipMemset(dummy.p, 0, 128 * (sizeof(int32_t) + sizeof(double)));
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                return set_error(FPS_ERR_HIP, "hipMemset: %s", hipGetErrorString(e));
-            }
-        }
+        HIP_TRY(launch_fill_u64(dummy.as<unsigned long long>(), 128 * (sizeof(int32_t) + sizeof(double)) / 8, 0ull, st));
         part_stride = std::max({analyze_blocks(kModeProduct, nn), analyze_blocks(kModeSum, nn), numeric_blocks(nn)}) + 1;
         FPS_TRY(part.ensure(sizeof(unsigned long long) * (size_t)(kPartCount * part_stride * stages)));
         // global-memory kernel: per slot byte map + bitmap + prefix + accumulator for a full row
@@ -251,6 +306,7 @@ struct StageRecord {
     bool alg1_device = false;  // the record is in the device state (Engine::alg1_state)
     int alg1_mode = 0;         // fps_stats.stage_alg1_mode
     bool wide_rows = false;    // every row of the stage ran in the wide shared-memory tier
+    bool dense = false;        // the product ran on the dense path
 };
 
 struct Schedule {
@@ -320,6 +376,15 @@ struct Engine {
     std::vector<int64_t> learned_global;  // per stage: rows a sizing run sent to the device-memory kernel
     std::vector<int> alg1_learned;  // per stage: Algorithm 1 iterations of the last host-driven run
     std::vector<double> alg1_learned_t;  // ... and its final threshold
+    // dense path (FPS_FLAG_DENSE): per stage the decision of the sizing run;
+    // three dense ld x ld operands; which left operand dA holds (its column
+    // array) and for which evaluation (P_q is the left operand of every
+    // Horner step of an evaluation, densified once)
+    std::vector<int> learned_dense;
+    DevBuf dA, dB, dE;
+    int64_t d_ld = 0;
+    const void* dA_key = nullptr;
+    int64_t dA_eval = -1, eval_id = 0;
 
     StageCounters* ctr(int i) const { return ws.counters.as<StageCounters>() + i; }
     Alg1State* alg1_state(int i) const { return alg1st.as<Alg1State>() + 3 * (size_t)i; }
@@ -350,7 +415,7 @@ struct Engine {
         return FPS_OK;
     }
 
-    fps_status init(int64_t n, int stages, uint64_t fl)
+    fps_status init(int64_t n, int stages, uint64_t fl, hipStream_t st)
     {
         flags = fl;
         learned.assign((size_t)stages, -1);
@@ -359,8 +424,71 @@ struct Engine {
         learned_global.assign((size_t)stages, 0);
         alg1_learned.assign((size_t)stages, 0);
         alg1_learned_t.assign((size_t)stages, 0.0);
+        learned_dense.assign((size_t)stages, 0);
         FPS_TRY(alg1st.ensure(sizeof(Alg1State) * 3 * (size_t)std::max(stages, 1)));
-        return ws.init(n, stages);
+        return ws.init(n, stages, st);
+    }
+
+    // Whether a product stage goes to the dense path: its multiply-adds (the
+    // analysis' count) reach 1/64 of the dense product's ld^3, and three
+    // dense operands fit the free device memory (and the plan's limit).
+    bool want_dense(int idx, hipStream_t s)
+    {
+        unsigned long long prods = 0;
+        {
+            const int64_t na = analyze_blocks(kModeProduct, ws.n);
+            std::vector<unsigned long long> h((size_t)na);
+            if (hipMemcpyAsync(h.data(), part(idx) + (size_t)kPartProducts * (size_t)ws.part_stride,
+                               sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                (void)hipGetLastError();
+                return false;
+            }
+            for (auto v : h) prods += v;
+        }
+        const double ld = (double)dense_ld(ws.n);
+        if ((double)prods * 64.0 < ld * ld * ld) return false;
+        const double need = 3.0 * ld * ld * 8.0 - (double)(dA.bytes + dB.bytes + dE.bytes);
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        if (need > 0.9 * (double)fr) return false;
+        if (t_acct && t_acct->used + (size_t)std::max(0.0, need) > t_acct->cap) return false;
+        return true;
+    }
+
+    // The product of stage `a` on the dense path into `out` (see
+    // launch_dgemm_mfma): operands densified, Bhat formed densely, the
+    // product with the block and the filter in its write-out, rows written
+    // back as slack CSR.
+    fps_status run_dense(StageArgs& a, hipStream_t s)
+    {
+        const int64_t n = ws.n, ld = dense_ld(n);
+        const size_t bytes = sizeof(double) * (size_t)ld * (size_t)ld;
+        FPS_TRY(dA.ensure(bytes));
+        FPS_TRY(dB.ensure(bytes));
+        FPS_TRY(dE.ensure(bytes));
+        if (ld != d_ld) dA_key = nullptr;
+        d_ld = ld;
+        const int64_t count = (int64_t)(bytes / 8);
+        if (!(dA_key == a.A.col && dA_eval == eval_id)) {
+            HIP_TRY(launch_fill_u64(dA.as<unsigned long long>(), count, 0ull, s));
+            HIP_TRY(launch_densify(a.A, n, ld, dA.as<double>(), s));
+            dA_key = a.A.col;
+            dA_eval = eval_id;
+        }
+        HIP_TRY(launch_fill_u64(dB.as<unsigned long long>(), count, 0ull, s));
+        HIP_TRY(launch_densify(a.B, n, ld, dB.as<double>(), s));
+        if (a.has_blk) {
+            HIP_TRY(launch_fill_u64(dE.as<unsigned long long>(), count, 0ull, s));
+            HIP_TRY(launch_dense_terms(a.T, n, ld, dE.as<double>(), s));
+        }
+        HIP_TRY(launch_dgemm_mfma(dA.as<double>(), dB.as<double>(), dE.as<double>(), ld, n, a.has_blk, a.tau,
+                                  a.tau_row, s));
+        HIP_TRY(launch_dense_to_slack(dE.as<double>(), ld, a, s));
+        return FPS_OK;
     }
 
     // Runs one stage into `out`.  With `size` true the stream is synchronised to
@@ -420,6 +548,25 @@ struct Engine {
         } else {
             run_wide = learned_wide[(size_t)idx] > 0 && !a.force_global;
             run_global = learned_global[(size_t)idx] > 0 || a.force_global;
+        }
+        // the dense path for a product stage whose work has gone dense
+        bool dense = false;
+        if (a.mode == kModeProduct && !a.has_e && (flags & FPS_FLAG_DENSE) && a.dsum == nullptr) {
+            if (sizing) learned_dense[(size_t)idx] = want_dense(idx, s) ? 1 : 0;
+            dense = learned_dense[(size_t)idx] != 0;
+        }
+        if (rec) rec->dense = dense;
+        if (dense) {
+            a.out = out.out();
+            if (rec && rec->ev0) HIP_TRY(hipEventRecord(rec->ev0, s));
+            FPS_TRY(run_dense(a, s));
+            if (rec && rec->ev1) HIP_TRY(hipEventRecord(rec->ev1, s));
+            if (sizing) {
+                unsigned long long tot[kPartCount];
+                FPS_TRY(stage_totals(idx, a.mode, tot));
+                learned_ns[(size_t)idx] = std::max<int64_t>(learned_ns[(size_t)idx], (int64_t)tot[kPartMaxNs]);
+            }
+            return FPS_OK;
         }
         // a stage whose sizing run sent more than an eighth of its rows past the
         // narrow tier runs every row in the wide tier (instead of building
@@ -502,6 +649,7 @@ struct Engine {
         alg1_fused = 0;
         if (device_iters == 0) device_iters = alg1_learned[(size_t)idx];
         if (device_iters <= 0 || !std::isfinite(eps_g) || !(eps_g > 0.0) || !kAlg1FuseFirst) return FPS_OK;
+        if (learned_dense[(size_t)idx]) return FPS_OK;  // the dense write-out takes no sums
         const int64_t n = ws.n;
         FPS_TRY(colsum.ensure(sizeof(unsigned long long) * (size_t)(3 * n + 3)));
         unsigned long long* cs = colsum.as<unsigned long long>();
@@ -943,6 +1091,7 @@ struct fps_plan_s {
     {
         const int64_t n = Z.n;
         n_stages = 0;
+        eng.eval_id++;
         HIP_TRY(launch_fill_u64(reinterpret_cast<unsigned long long*>(eng.ws.counters.p),
                                 (int64_t)(sizeof(StageCounters) / 8) * eng.ws.max_stages, 0ull, s));
         RowInfo* zinfo = eng.ws.zinfo.as<RowInfo>();
@@ -992,6 +1141,7 @@ struct fps_plan_s {
             r->alg1_device = false;
             r->alg1_mode = 0;
             r->wide_rows = false;
+            r->dense = false;
             r->ev0 = r->ev1 = nullptr;
             if (timing_now) {
                 r->ev0 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2];
@@ -1216,7 +1366,7 @@ static fps_status plan_create_limited(fps_plan* out, const fps_csr_view* Z, cons
     const int stages = p->stage_count();
     if (stages > FPS_MAX_STAGES)
         return set_error(FPS_ERR_CAPACITY, "schedule needs %d stages, at most %d supported", stages, FPS_MAX_STAGES);
-    FPS_TRY(p->eng.init(Z->n, stages, flags));
+    FPS_TRY(p->eng.init(Z->n, stages, flags, st));
     p->P.resize((size_t)std::max(p->sc.J, 1) + 2);
     for (auto& x : p->P) x.reset(new SlackMatrix());
     p->rec.assign((size_t)stages, StageRecord{});
@@ -1361,6 +1511,8 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
         st->stage_dropped[i] = r.dropped;
         st->stage_alg1_iters[i] = r.alg1_iters;
         st->stage_alg1_mode[i] = r.alg1_mode;
+        st->stage_dense[i] = r.dense ? 1 : 0;
+        if (r.dense) st->dense_ld = p->eng.d_ld;
         st->stage_rows_skipped[i] = (int64_t)tot[(size_t)i][kPartRowsSkipped];
         if (r.alg1_device) {
             const Alg1State& f = a1[(size_t)i * 3 + 2];
@@ -1487,7 +1639,7 @@ fps_status fps_spgemm(fps_matrix* out, const fps_csr_view* A, const fps_csr_view
     if (E) FPS_TRY(validate_on_device(E, "E", s));
     const int64_t n = A->n;
     Engine eng;
-    FPS_TRY(eng.init(n, 1, 0));
+    FPS_TRY(eng.init(n, 1, 0, s));
     // row info and structure words of each operand
     const fps_csr_view* ops[3] = {A, B, E};
     DevBuf info[3], words[3];
@@ -1536,7 +1688,7 @@ fps_status fps_axpy(fps_matrix* out, int64_t n, int32_t nterms, const double* co
         }
     }
     Engine eng;
-    FPS_TRY(eng.init(n, 1, 0));
+    FPS_TRY(eng.init(n, 1, 0, s));
     DevBuf info;
     std::vector<DevBuf> words((size_t)nterms);
     // per term: row summaries (16-byte aligned blocks), then word counts
@@ -2261,6 +2413,7 @@ struct fps_server_s {
         }
     };
 
+    DevPool pool;  // first member: it outlives every buffer handed out from it
     fps_server_opts o{};
     int device = 0;
     std::mutex mu;
@@ -2338,8 +2491,10 @@ struct fps_server_s {
     void worker(int k)
     {
         if (!o.fake_backend) (void)hipSetDevice(device);
+        t_pool = o.fake_backend ? nullptr : &pool;
         for (;;) {
             Req* r = nullptr;
+            size_t keep = SIZE_MAX;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 cv_work.wait(lk, [&] {
@@ -2355,7 +2510,10 @@ struct fps_server_s {
                 r->state = FPS_REQ_RUNNING;
                 r->attempts++;
                 r->t_start = now_ns();
+                // pooled free blocks count against the budget as well
+                keep = (size_t)o.hbm_budget - reserved;
             }
+            if (!o.fake_backend) pool.trim(keep);
             execute(r, o.fake_backend ? nullptr : streams[(size_t)k]);
             {
                 std::lock_guard<std::mutex> lk(mu);
@@ -2423,7 +2581,7 @@ fps_status fps_server_create(fps_server* out, const fps_server_opts* opts)
     if (opts->slots < 1 || opts->slots > 64) return set_error(FPS_ERR_INVALID_ARG, "slots must be in [1, 64]");
     if (opts->hbm_budget <= 0) return set_error(FPS_ERR_INVALID_ARG, "hbm_budget must be > 0");
     if (opts->max_queue < 0) return set_error(FPS_ERR_INVALID_ARG, "max_queue must be >= 0");
-    if (opts->flags & ~(uint64_t)(FPS_FLAG_NO_VALIDATE | FPS_FLAG_NO_SKIP))
+    if (opts->flags & ~(uint64_t)(FPS_FLAG_NO_VALIDATE | FPS_FLAG_NO_SKIP | FPS_FLAG_DENSE))
         return set_error(FPS_ERR_INVALID_ARG, "unsupported server flags");
     std::unique_ptr<fps_server_s> sv(new (std::nothrow) fps_server_s());
     if (!sv) return set_error(FPS_ERR_OUT_OF_MEMORY, "host allocation failed");

@@ -1,0 +1,297 @@
+// HIP kernels (gfx950) of the dense path: a sparse product whose work has
+// grown to a sizeable fraction of a dense one (the fill of the powers and of
+// the Horner states that the paper notes after eq. 9) is computed as a dense
+// FP64 matrix product on the matrix cores (v_mfma_f64_16x16x4f64), with the
+// coefficient block added and the filter applied in the product's write-out:
+//     C = D_tau(E + A B)            (eq. 11 with E = 0, eq. 14 with E = Bhat)
+// The operands are stored dense and row-major with a leading dimension ld
+// (n rounded up to 128, the padding zero), and the result is written back as
+// the same slack-CSR rows the sparse kernels write (entries in column order,
+// row summary, structure words, per-block counts), so later stages read it
+// as any other stage output.  The products are summed in the matrix cores'
+// order, not the ordered sparse one: results agree with the sparse path to
+// rounding, not bit for bit.  Bhat itself is formed in the sparse path's
+// order (ascending terms, one fused multiply-add each from +0), so it is
+// bit-identical.
+#include "fps_device.h"
+
+#include <climits>
+
+namespace fps {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kB = 256;
+constexpr int kRowsPerBlock = 4;  // write-out: one wavefront per row, as the numeric kernels
+
+inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kB - 1) / kB); }
+
+__device__ __forceinline__ unsigned lanes_below64(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// ---- densify --------------------------------------------------------------
+
+// D[r][col] = val for the stored entries of M (D zero beforehand); one
+// wavefront per row (the columns of a row are distinct).
+__global__ void __launch_bounds__(kB) k_densify(MatView M, int64_t n, int64_t ld, double* D)
+{
+    const int64_t r = ((int64_t)blockIdx.x * kB + threadIdx.x) / kWave;
+    const int l = threadIdx.x % kWave;
+    if (r >= n) return;
+    const int64_t b = M.beg[r], e = M.end[r];
+    double* row = D + r * ld;
+    for (int64_t p = b + l; p < e; p += kWave) row[M.col[p]] = M.val[p];
+}
+
+// E[r][.] = sum_t coef_t M_t[r][.] accumulated over ascending t with one
+// fused multiply-add per term from +0 (E zero beforehand; M_t the identity
+// when beg[t] is null).  One thread per row: the terms of a row are applied
+// in order by the one thread that owns it.
+__global__ void __launch_bounds__(kB) k_dense_terms(Terms T, int64_t n, int64_t ld, double* E)
+{
+    const int64_t r = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (r >= n) return;
+    double* row = E + r * ld;
+    for (int t = 0; t < T.n; ++t) {
+        const double c = T.coef[t];
+        if (T.beg[t] == nullptr) {
+            row[r] = fma(c, 1.0, row[r]);
+        } else {
+            const int64_t b = T.beg[t][r], e = T.end[t][r];
+            for (int64_t p = b; p < e; ++p) {
+                const int32_t k = T.col[t][p];
+                row[k] = fma(c, T.val[t][p], row[k]);
+            }
+        }
+    }
+}
+
+// ---- the product on the matrix cores ----------------------------------------
+//
+// Block tile BM x BM of C, four wavefronts in 2 x 2, each a (BM/2) x (BM/2)
+// tile made of 16 x 16 MFMA tiles.  K advances in chunks of 16 staged in
+// shared memory, A k-major and B row-major, so that the 16 lanes of a
+// quarter-wave read 16 consecutive doubles.  Lane layout of
+// v_mfma_f64_16x16x4f64 (wave64): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] of the 16 x 4 and 4 x 16 operands, and item v of its
+// result holds C[4 v + l / 16][l % 16].
+template <int BM>
+__global__ void __launch_bounds__(kB) k_dgemm_mfma(const double* __restrict__ A, const double* __restrict__ B,
+                                                   double* E, int64_t ld, int64_t n, int has_e, double tau,
+                                                   const double* __restrict__ tau_row)
+{
+    constexpr int KC = 16;
+    constexpr int WM = BM / 2;   // wave tile
+    constexpr int TM = WM / 16;  // MFMA tiles per wave dimension
+    constexpr int PAD = 2;
+    constexpr int PER = BM * KC / kB;  // doubles of each operand chunk per thread
+    __shared__ double As[KC][BM + PAD];
+    __shared__ double Bs[KC][BM + PAD];
+    const int t = threadIdx.x, l = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
+    const int64_t row0 = (int64_t)blockIdx.y * BM, col0 = (int64_t)blockIdx.x * BM;
+    v4d acc[TM][TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TM; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    // chunk loads: A rows (t / (KC / PER)), PER consecutive k; B row (t / (BM / PER)), PER consecutive columns
+    constexpr int AQ = KC / PER;  // threads per A row
+    constexpr int BQ = BM / PER;  // threads per B row
+    const int ar = t / AQ, ak = (t % AQ) * PER;
+    const int bk = t / BQ, bc = (t % BQ) * PER;
+    const double* pa = A + (row0 + ar) * ld + ak;
+    const double* pb = B + (int64_t)bk * ld + col0 + bc;
+    double ra[PER], rb[PER];
+#pragma unroll
+    for (int i = 0; i < PER; i += 2) {
+        const double2 x = *reinterpret_cast<const double2*>(pa + i);
+        const double2 y = *reinterpret_cast<const double2*>(pb + i);
+        ra[i] = x.x;
+        ra[i + 1] = x.y;
+        rb[i] = y.x;
+        rb[i + 1] = y.y;
+    }
+    for (int64_t k0 = 0; k0 < ld; k0 += KC) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            As[ak + i][ar] = ra[i];
+            Bs[bk][bc + i] = rb[i];
+        }
+        __syncthreads();
+        if (k0 + KC < ld) {  // the next chunk's loads overlap this chunk's products
+            const double* na = pa + (k0 + KC);
+            const double* nb = pb + (k0 + KC) * ld;
+#pragma unroll
+            for (int i = 0; i < PER; i += 2) {
+                const double2 x = *reinterpret_cast<const double2*>(na + i);
+                const double2 y = *reinterpret_cast<const double2*>(nb + i);
+                ra[i] = x.x;
+                ra[i + 1] = x.y;
+                rb[i] = y.x;
+                rb[i + 1] = y.y;
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            double a[TM], b[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[i] = As[kk + (l >> 4)][wr * WM + i * 16 + (l & 15)];
+#pragma unroll
+            for (int j = 0; j < TM; ++j) b[j] = Bs[kk + (l >> 4)][wc * WM + j * 16 + (l & 15)];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TM; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // write-out: x = E + product (one addition), then the filter
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TM; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t gi = row0 + wr * WM + i * 16 + 4 * v + (l >> 4);
+                const int64_t gj = col0 + wc * WM + j * 16 + (l & 15);
+                if (gi < n && gj < n) {
+                    double x = acc[i][j][v];
+                    double* pe = E + gi * ld + gj;
+                    if (has_e) x = *pe + x;
+                    const double tr = tau_row ? tau_row[gi] : tau;
+                    *pe = (x != 0.0 && !(fabs(x) < tr)) ? x : 0.0;
+                }
+            }
+}
+
+// ---- back to slack-CSR rows -----------------------------------------------------
+
+// Row r of the dense result C as a stage output row: placed as the numeric
+// kernels place it (a fixed stride, or the analysis' block prefix plus its
+// offset), its nonzero entries in column order, its summary and structure
+// words; a row that does not fit its room is left empty and flagged.  The
+// block's kept count and largest row go to the stage's partial sums.
+__global__ void __launch_bounds__(kB) k_dense_to_slack(const double* __restrict__ C, int64_t ld, StageArgs P)
+{
+    __shared__ unsigned long long kept_sh[kRowsPerBlock];
+    const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    const int64_t blk = blockIdx.x;
+    const int64_t r = blk * kRowsPerBlock + wv;
+    int64_t kept = 0;
+    if (r < P.n) {
+        const int64_t o = P.row_stride > 0 ? r * P.row_stride : P.blk_pre[r >> P.scan_shift] + P.out.off[r];
+        const int64_t room = P.row_stride > 0 ? P.row_stride : P.out.cap - o;
+        if (l == 0) P.out.off[r] = o;
+        const double* row = C + r * ld;
+        double amx = 0.0;
+        int32_t first = INT_MAX, last = -1, nwd = 0;
+        for (int64_t c0 = 0; c0 < P.n; c0 += kWave) {
+            const int64_t c = c0 + l;
+            const double x = c < P.n ? row[c] : 0.0;
+            const bool nz = x != 0.0;
+            const unsigned long long m = __ballot(nz);
+            if (nz) {
+                const int64_t pos = kept + (int64_t)lanes_below64(m);
+                if (pos < room) {
+                    P.out.col[o + pos] = (int32_t)c;
+                    P.out.val[o + pos] = x;
+                }
+                amx = fmax(amx, fabs(x));
+                first = min(first, (int32_t)c);
+                last = max(last, (int32_t)c);
+            }
+            kept += __popcll(m);
+            // structure words: the chunk's two 32-column words (c0 is a multiple of 64)
+            const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+            if (l == 0) {
+                if (lo && nwd < room) P.out.sw[o + nwd] = make_uint2((uint32_t)(c0 >> 5), lo);
+                nwd += lo ? 1 : 0;
+                if (hi && nwd < room) P.out.sw[o + nwd] = make_uint2((uint32_t)(c0 >> 5) + 1u, hi);
+                nwd += hi ? 1 : 0;
+            }
+        }
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) {
+            amx = fmax(amx, __shfl_xor(amx, d, kWave));
+            first = min(first, __shfl_xor(first, d, kWave));
+            last = max(last, __shfl_xor(last, d, kWave));
+        }
+        if (l == 0) {
+            RowInfo q;
+            if (kept > room) {  // the row does not fit: left empty, the evaluation is repeated with sizing
+                atomicOr(&P.ctr->errors, kErrCapacity);
+                P.out.end[r] = o;
+                q.len = 0;
+                q.first = 1;
+                q.last = 0;
+                q.amax = 0.0f;
+                P.out.nw[r] = 0;
+                kept = 0;
+            } else {
+                P.out.end[r] = o + kept;
+                q.len = (int32_t)kept;
+                q.first = kept > 0 ? first : 1;
+                q.last = kept > 0 ? last : 0;
+                q.amax = __double2float_ru(amx);
+                P.out.nw[r] = nwd;
+            }
+            P.out.info[r] = q;
+        }
+    }
+    if (l == 0) kept_sh[wv] = (unsigned long long)kept;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0, mx = 0;
+        for (int i = 0; i < kRowsPerBlock; ++i) {
+            s += kept_sh[i];
+            mx = max(mx, kept_sh[i]);
+        }
+        P.part[kPartKept * P.part_stride + blk] = s;
+        P.part[kPartMaxNs * P.part_stride + blk] = mx;
+    }
+}
+
+}  // namespace
+
+int64_t dense_ld(int64_t n) { return (n + 127) / 128 * 128; }
+
+hipError_t launch_densify(const MatView& M, int64_t n, int64_t ld, double* D, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_densify, dim3(grid_for(n * kWave)), dim3(kB), 0, s, M, n, ld, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_terms(const Terms& T, int64_t n, int64_t ld, double* E, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dense_terms, dim3(grid_for(n)), dim3(kB), 0, s, T, n, ld, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_dgemm_mfma(const double* A, const double* B, double* E, int64_t ld, int64_t n, int has_e, double tau,
+                             const double* tau_row, hipStream_t s)
+{
+    // 128 x 128 tiles when they give the chip enough blocks, else 64 x 64
+    const int64_t t128 = ld / 128;
+    if (t128 * t128 >= 512) {
+        hipLaunchKernelGGL(k_dgemm_mfma<128>, dim3((unsigned)t128, (unsigned)t128), dim3(kB), 0, s, A, B, E, ld, n,
+                           has_e, tau, tau_row);
+    } else {
+        const int64_t t64 = ld / 64;
+        hipLaunchKernelGGL(k_dgemm_mfma<64>, dim3((unsigned)t64, (unsigned)t64), dim3(kB), 0, s, A, B, E, ld, n, has_e,
+                           tau, tau_row);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_to_slack(const double* C, int64_t ld, const StageArgs& a, hipStream_t s)
+{
+    const int64_t blocks = (a.n + kRowsPerBlock - 1) / kRowsPerBlock;
+    hipLaunchKernelGGL(k_dense_to_slack, dim3((unsigned)blocks), dim3(kB), 0, s, C, ld, a);
+    return hipGetLastError();
+}
+
+}  // namespace fps

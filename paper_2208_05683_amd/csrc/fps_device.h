@@ -213,6 +213,20 @@ hipError_t launch_batch_instance_sum(const int64_t* acc, const int64_t* base, in
 hipError_t launch_batch_extract(const int64_t* frp, const int32_t* fcol, int64_t row0, int64_t n, int64_t p0,
                                 int64_t cnt, int32_t shift, int64_t* rp, int32_t* col, hipStream_t s);
 
+// ---- launch wrappers (fps_dense.hip) ------------------------------------
+// leading dimension of the dense operands: n rounded up to 128
+int64_t dense_ld(int64_t n);
+// D[r][col] = val over the stored entries of M (D zero beforehand)
+hipError_t launch_densify(const MatView& M, int64_t n, int64_t ld, double* D, hipStream_t s);
+// E += sum_t coef_t M_t row by row, terms in order, one fma each (E zero beforehand)
+hipError_t launch_dense_terms(const Terms& T, int64_t n, int64_t ld, double* E, hipStream_t s);
+// E = D_tau((has_e ? E : 0) + A B) on the matrix cores (tau per row if tau_row)
+hipError_t launch_dgemm_mfma(const double* A, const double* B, double* E, int64_t ld, int64_t n, int has_e, double tau,
+                             const double* tau_row, hipStream_t s);
+// rows of the dense C written as the stage output a.out (placement, summaries,
+// structure words, partial sums as the numeric kernels)
+hipError_t launch_dense_to_slack(const double* C, int64_t ld, const StageArgs& a, hipStream_t s);
+
 // ---- launch wrappers (fps_kernels.hip) ---------------------------------
 // row summaries and the structure words (sw: nnz entries, nw: n) of a canonical CSR
 hipError_t launch_rowinfo_csr(const int64_t* row_ptr, const int32_t* col, const double* val, int64_t n,
