@@ -40,13 +40,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def workload(name):
+def workload(name, side=None):
     from fps_inputs import generators as G
 
     if name == "lap2d":
         return G.config2()
     if name == "lap1d":
         return G.config1()
+    if name == "lap3d":
+        return G.config3(side=side or 20)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -386,8 +388,9 @@ def banded_sweep(count: int, eps_tol: float, e_r: float, bands):
     for fname, coeffs in (("exp", G.exp_coeffs(199)), ("cos", G.cos_coeffs(199))):
         rows = []
         for bw in bands:
-            acc = {k: [] for k in ("psscf_setup_ms", "psscf_ms", "ps_ms", "dense_ms", "sparsity_psscf",
-                                   "sparsity_ps", "err_psscf", "err_ps", "N", "q")}
+            acc = {k: [] for k in ("psscf_setup_ms", "psscf_ms", "psscf_mfma_ms", "ps_ms", "dense_ms",
+                                   "sparsity_psscf", "sparsity_ps", "err_psscf", "err_psscf_mfma", "err_ps",
+                                   "N", "q")}
             for k in range(count):
                 Z = G.banded_sweep_matrix(bw, 1000, seed=1000 * bw + k)
                 Zd = api.to_device(Z.row_ptr, Z.col, Z.val)
@@ -397,6 +400,14 @@ def banded_sweep(count: int, eps_tol: float, e_r: float, bands):
                 _, t_eval = dev_ms(plan.eval)
                 F = plan.result()
                 plan.close()
+                # the same with the dense products on the matrix cores
+                from paper_2208_05683_amd import binding as B
+
+                pm = api.Plan.series(Zd, coeffs, eps_tol, e_r, flags=B.FPS_FLAG_DENSE)
+                pm.eval()
+                _, t_mfma = dev_ms(pm.eval)
+                Fm = pm.result()
+                pm.close()
                 m, s = info["N"] - 1, info["q"]
                 ps = api.Plan(Zd, coeffs, m, s, 0.0)
                 ps.eval()
@@ -413,9 +424,11 @@ def banded_sweep(count: int, eps_tol: float, e_r: float, bands):
                 nref = torch.linalg.norm(ref)
                 acc["err_psscf"].append(float(torch.linalg.norm(dense(F) - ref) / nref))
                 acc["err_ps"].append(float(torch.linalg.norm(dense(Fps) - ref) / nref))
+                acc["err_psscf_mfma"].append(float(torch.linalg.norm(dense(Fm) - ref) / nref))
                 acc["sparsity_psscf"].append(F[1].numel() / Z.n ** 2)
                 acc["sparsity_ps"].append(Fps[1].numel() / Z.n ** 2)
-                for key, v in (("psscf_setup_ms", t_setup), ("psscf_ms", t_eval), ("ps_ms", t_ps),
+                for key, v in (("psscf_setup_ms", t_setup), ("psscf_ms", t_eval), ("psscf_mfma_ms", t_mfma),
+                               ("ps_ms", t_ps),
                                ("dense_ms", t_dense), ("N", info["N"]), ("q", info["q"])):
                     acc[key].append(v)
             row = {"b": bw, **{k: float(np.mean(v)) for k, v in acc.items()}}
@@ -430,7 +443,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="lap2d")
+    ap.add_argument("--workload", default="lap2d", help="lap2d (headline), lap1d, lap3d (with --side)")
+    ap.add_argument("--side", type=int, default=None, help="lap3d: grid side (default 20)")
+    ap.add_argument("--dense", action="store_true", help="FPS_FLAG_DENSE: dense products on the FP64 matrix cores")
     ap.add_argument("--cpu-budget", type=float, default=1.0, help="0 skips the CPU oracle timing")
     ap.add_argument("--filter", choices=["fixed", "adaptive", "series"], default="fixed",
                     help="fixed: the workload's tau; adaptive: Algorithm 1 with the eq. 28 thresholds and the "
@@ -474,7 +489,7 @@ def main():
         print(json.dumps(res), flush=True)
         return
 
-    cfg = workload(args.workload)
+    cfg = workload(args.workload, args.side)
     Z = cfg["Z"]
     log(f"workload {cfg['name']}: n={Z.n} nnz={Z.nnz}")
     Zd = api.to_device(Z.row_ptr, Z.col, Z.val)
@@ -504,7 +519,10 @@ def main():
                    m=series_info["N"] - 1, s=series_info["q"])
         log(f"series mode: N = {series_info['N']}, q = {series_info['q']}, tail = {series_info['tail']:.3g}")
     else:
-        plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"], flags=B.FPS_FLAG_TIMING)
+        plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"],
+                        flags=B.FPS_FLAG_TIMING | (B.FPS_FLAG_DENSE if args.dense else 0))
+        if args.dense:
+            cfg = dict(cfg, name=cfg["name"] + "_dense")
     torch.cuda.synchronize()
     setup_ms = 1e3 * (time.perf_counter() - t_setup)  # plan creation (with the norm estimates of eq. 37)
 
@@ -549,6 +567,14 @@ def main():
                       "frac": round(gbs / HBM_PEAK_GBS, 4), "products": pr, "rows_skipped": sk}
     dom = max(stages, key=lambda k: stages[k]["us"]) if stages else None
     traffic = measured_traffic(cfg["name"])
+    dense_ld = st.get("dense_ld", 0)
+    dense_stages = [nm for nm, d in zip(names, st["stage_dense"]) if d]
+    for nm in dense_stages:
+        fl = 2.0 * dense_ld ** 3
+        us = stages[nm]["us"]
+        stages[nm]["dense"] = True
+        stages[nm]["dense_flops"] = fl
+        stages[nm]["TFLOPs"] = round(fl / (us * 1e-6) / 1e12, 2) if us > 0 else None
 
     res = {
         "metric": "series evals/s + SpGEMM HBM GB/s vs plain filtered PS; p50/p99 latency at QPS",
@@ -586,6 +612,15 @@ def main():
                      "dominant_launch": dom,
                      "dominant_launch_frac": stages[dom]["frac"] if dom else None},
         "stages": stages,
+        **({"dense": {"ld": dense_ld, "stages": dense_stages,
+                      "flops_per_step": 2.0 * dense_ld ** 3 * len(dense_stages),
+                      "stage_us": sum(stages[nm]["us"] for nm in dense_stages),
+                      "TFLOPs": (2.0 * dense_ld ** 3 * len(dense_stages)
+                                 / (sum(stages[nm]["us"] for nm in dense_stages) * 1e-6) / 1e12)
+                      if dense_stages else None,
+                      "peak_TFLOPs": 78.6,
+                      "note": "stage time includes densifying the operands and the write-out"}}
+           if args.dense else {}),
         "products_per_s": prod_per_s,
         "products_per_step": products,
         "products_skipped_per_step": st["products_skipped"],
@@ -593,6 +628,16 @@ def main():
         "rows_wide_per_step": st["rows_wide"],
         "rows_global_per_step": st["rows_global"],
     }
+    if dense_stages:
+        # the dominant kernel is the matrix-core product: its roofline is the
+        # FP64 matrix peak (stage time, densifying and write-out included)
+        d = res["dense"]
+        res["roofline_sparse"] = res["roofline"]
+        res["roofline"] = {"bound": "mfma", "achieved": d["TFLOPs"], "peak": 78.6, "unit": "TFLOP/s",
+                           "frac": d["TFLOPs"] / 78.6, "traffic": None, "kernel": "k_dgemm_mfma",
+                           "flops_per_launch": 2.0 * dense_ld ** 3, "launches_per_step": len(dense_stages),
+                           "avg_stage_ms": d["stage_us"] / len(dense_stages) / 1e3,
+                           "note": "per dense stage: densify, block sum, product, write-out"}
     if args.filter != "fixed":
         res["alg1_iters_per_step"] = int(sum(st["stage_alg1_iters"]))
     plan.close()
@@ -606,7 +651,7 @@ def main():
         res["serve"] = bench_serve(args, stream)
         log(f"serve: plain {res['serve']['plain_sequential_evals_per_s']:.0f}/s, server saturation "
             f"{res['serve']['server_saturation_evals_per_s']:.0f}/s ({res['serve']['speedup_vs_plain']:.2f}x)")
-    if args.cpu_budget > 0 and args.filter == "fixed":
+    if args.cpu_budget > 0 and args.filter == "fixed" and args.workload != "lap3d":
         log("timing the CPU oracle ...")
         res["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(res), flush=True)

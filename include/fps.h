@@ -69,9 +69,10 @@ typedef int32_t fps_status;
 /* plan flags */
 #define FPS_FLAG_NO_SKIP 0x1ull      /* disable the exact bound-based row skip */
 #define FPS_FLAG_FORCE_GLOBAL 0x2ull /* route every row through the global-memory kernel */
-#define FPS_FLAG_TIMING 0x4ull       /* record HIP events around the shared-memory numeric launches of
-                                        the first evaluation after a statistics query and every 8th
-                                        one after it */
+#define FPS_FLAG_TIMING 0x4ull       /* record HIP events around the numeric kernels of every stage (the
+                                        shared-memory kernel and the fallback tiers after it, or the dense
+                                        path) of the first evaluation after a statistics query and every
+                                        8th one after it */
 #define FPS_FLAG_NO_VALIDATE 0x8ull  /* skip the device-side CSR check of Z at plan time */
 #define FPS_FLAG_SYNC_SIZES 0x10ull  /* size every stage from a host read (no learned capacities) */
 #define FPS_FLAG_DROP_STATS 0x20ull  /* fixed threshold: per filtered product, count the entries that D_tau
@@ -80,10 +81,12 @@ typedef int32_t fps_status;
                                         enter the error bound of eq. 23); turns the row skip off, so that
                                         every removed entry is computed */
 
-#define FPS_FLAG_DENSE 0x40ull       /* compute a sparse product densely on the FP64 matrix cores when its
-                                        multiply-adds reach 1/64 of the dense product's (n rounded up to 128,
-                                        cubed) and three dense n x n operands fit the free device memory;
-                                        the decision is taken per stage in the sizing evaluation.  The
+#define FPS_FLAG_DENSE 0x40ull       /* compute a sparse product densely on the FP64 matrix cores when the
+                                        modelled time of the dense product (n rounded up to 128) is below
+                                        that of the sparse one (its multiply-adds at the rate of the row
+                                        kernel its rows take) and three dense n x n operands fit the free
+                                        device memory; the decision is taken per stage in the sizing
+                                        evaluation.  The
                                         product is then summed in the matrix cores' order: results agree
                                         with the ordered sparse path to rounding (and entries within
                                         rounding of tau may be kept or dropped differently), not bit for
@@ -153,11 +156,11 @@ typedef struct {
                                      block term's row, the left operand's offsets), and one
                                      with some rows proven empty scales its right-operand and block
                                      bytes by the fraction of rows computed */
-    double numeric_ms;            /* FPS_FLAG_TIMING: shared-memory numeric-kernel time per evaluation
+    double numeric_ms;            /* FPS_FLAG_TIMING: numeric-kernel time per evaluation
                                      (all stages), averaged over the sampled evaluations since the
                                      previous fps_get_stats call (up to 64; the latest sampled one if
                                      none) */
-    int32_t numeric_launches;     /* FPS_FLAG_TIMING: shared-memory numeric launches per evaluation */
+    int32_t numeric_launches;     /* FPS_FLAG_TIMING: stages timed per evaluation */
     int32_t kind[FPS_MAX_STAGES];
     int32_t index[FPS_MAX_STAGES];
     int64_t stage_products[FPS_MAX_STAGES];

@@ -429,10 +429,15 @@ struct Engine {
         return ws.init(n, stages, st);
     }
 
-    // Whether a product stage goes to the dense path: its multiply-adds (the
-    // analysis' count) reach 1/64 of the dense product's ld^3, and three
-    // dense operands fit the free device memory (and the plan's limit).
-    bool want_dense(int idx, hipStream_t s)
+    // Whether a product stage goes to the dense path: the modelled time of
+    // the dense product is below that of the sparse one, and three dense
+    // operands fit the free device memory (and the plan's limit).  Sparse:
+    // the analysis' multiply-adds at the measured rate of the row kernel the
+    // rows will take (2.5e11 per second in shared memory, 5e10 in the
+    // device-memory kernel for rows beyond 512 entries on average); dense:
+    // 2 ld^3 flops at 4e13 per second on the matrix cores, five passes over
+    // ld^2 doubles at 3 TB/s (fills, densify, write-out) and 20 us of launches.
+    bool want_dense(int idx, int64_t bound_total, hipStream_t s)
     {
         unsigned long long prods = 0;
         {
@@ -447,7 +452,10 @@ struct Engine {
             for (auto v : h) prods += v;
         }
         const double ld = (double)dense_ld(ws.n);
-        if ((double)prods * 64.0 < ld * ld * ld) return false;
+        const double per_row = (double)bound_total / (double)std::max<int64_t>(ws.n, 1);
+        const double t_sparse = (double)prods / (per_row > 512.0 ? 5e10 : 2.5e11);
+        const double t_dense = 2.0 * ld * ld * ld / 4e13 + 5.0 * ld * ld * 8.0 / 3e12 + 20e-6;
+        if (t_dense >= t_sparse) return false;
         const double need = 3.0 * ld * ld * 8.0 - (double)(dA.bytes + dB.bytes + dE.bytes);
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
@@ -552,7 +560,7 @@ struct Engine {
         // the dense path for a product stage whose work has gone dense
         bool dense = false;
         if (a.mode == kModeProduct && !a.has_e && (flags & FPS_FLAG_DENSE) && a.dsum == nullptr) {
-            if (sizing) learned_dense[(size_t)idx] = want_dense(idx, s) ? 1 : 0;
+            if (sizing) learned_dense[(size_t)idx] = want_dense(idx, learned[(size_t)idx], s) ? 1 : 0;
             dense = learned_dense[(size_t)idx] != 0;
         }
         if (rec) rec->dense = dense;
@@ -586,7 +594,9 @@ struct Engine {
             HIP_TRY(launch_numeric_wide_rows(a, s));
         else
             HIP_TRY(launch_numeric_lds(a, 0, s));
-        if (rec && rec->ev1) HIP_TRY(hipEventRecord(rec->ev1, s));
+        // (without sizing the stage's numeric kernels are timed together: the
+        // end event follows the fallback tiers below)
+        if (sizing && rec && rec->ev1) HIP_TRY(hipEventRecord(rec->ev1, s));
         StageCounters c{};
         if (sizing) {
             HIP_TRY(hipMemcpyAsync(&c, ctr(idx), sizeof(c), hipMemcpyDeviceToHost, s));
@@ -611,6 +621,7 @@ struct Engine {
                 a, grid_for_rows(std::max<int64_t>(learned_global[(size_t)idx], a.force_global ? n : 0),
                                  numeric_global_blocks(ws.g_slots)),
                 s));
+        if (!sizing && rec && rec->ev1) HIP_TRY(hipEventRecord(rec->ev1, s));
         if (sizing) {
             // the stage's largest structural row
             unsigned long long tot[kPartCount];

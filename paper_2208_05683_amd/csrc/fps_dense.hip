@@ -48,23 +48,40 @@ __global__ void __launch_bounds__(kB) k_densify(MatView M, int64_t n, int64_t ld
 
 // E[r][.] = sum_t coef_t M_t[r][.] accumulated over ascending t with one
 // fused multiply-add per term from +0 (E zero beforehand; M_t the identity
-// when beg[t] is null).  One thread per row: the terms of a row are applied
-// in order by the one thread that owns it.
+// when beg[t] is null).  One thread per (row, chunk of kTermCols columns):
+// for each term in order it finds the chunk's entries in the term's sorted
+// row by binary search and applies them, so every entry of E is owned and
+// updated in term order by one thread.
+constexpr int kTermCols = 32;
+
 __global__ void __launch_bounds__(kB) k_dense_terms(Terms T, int64_t n, int64_t ld, double* E)
 {
-    const int64_t r = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (r >= n) return;
+    const int64_t chunks = (n + kTermCols - 1) / kTermCols;
+    const int64_t id = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if (id >= n * chunks) return;
+    const int64_t r = id / chunks;
+    const int32_t c0 = (int32_t)((id % chunks) * kTermCols), c1 = c0 + kTermCols;
     double* row = E + r * ld;
     for (int t = 0; t < T.n; ++t) {
         const double c = T.coef[t];
         if (T.beg[t] == nullptr) {
-            row[r] = fma(c, 1.0, row[r]);
-        } else {
-            const int64_t b = T.beg[t][r], e = T.end[t][r];
-            for (int64_t p = b; p < e; ++p) {
-                const int32_t k = T.col[t][p];
-                row[k] = fma(c, T.val[t][p], row[k]);
-            }
+            if (r >= c0 && r < c1) row[r] = fma(c, 1.0, row[r]);
+            continue;
+        }
+        const int32_t* cl = T.col[t];
+        int64_t lo = T.beg[t][r], hi = T.end[t][r];  // first entry with column >= c0
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (cl[mid] < c0)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        const int64_t e = T.end[t][r];
+        for (int64_t p = lo; p < e; ++p) {
+            const int32_t k = cl[p];
+            if (k >= c1) break;
+            row[k] = fma(c, T.val[t][p], row[k]);
         }
     }
 }
@@ -267,7 +284,8 @@ hipError_t launch_densify(const MatView& M, int64_t n, int64_t ld, double* D, hi
 
 hipError_t launch_dense_terms(const Terms& T, int64_t n, int64_t ld, double* E, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dense_terms, dim3(grid_for(n)), dim3(kB), 0, s, T, n, ld, E);
+    const int64_t chunks = (n + kTermCols - 1) / kTermCols;
+    hipLaunchKernelGGL(k_dense_terms, dim3(grid_for(n * chunks)), dim3(kB), 0, s, T, n, ld, E);
     return hipGetLastError();
 }
 
