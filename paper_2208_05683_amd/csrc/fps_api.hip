@@ -429,6 +429,30 @@ struct Engine {
         return ws.init(n, stages, st);
     }
 
+    // A stage's output bound (measured by its analysis in a sizing run) must
+    // fit the free device memory (either path writes its rows there); if it
+    // does not, the evaluation stops with FPS_ERR_CAPACITY and the footprint,
+    // the dense path's three operands included (the fill has outgrown the GPU).
+    fps_status fits_device(int idx, int64_t total, bool product)
+    {
+        const double per_entry = sizeof(int32_t) + sizeof(double) + sizeof(uint2);  // column, value, word
+        const double need = per_entry * (double)total;
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+            (void)hipGetLastError();
+            return FPS_OK;  // no information: let the allocation decide
+        }
+        const double ld = (double)dense_ld(ws.n);
+        const double dense_need = 3.0 * ld * ld * 8.0;
+        if (need <= 0.95 * (double)fr) return FPS_OK;
+        (void)product;
+        return set_error(FPS_ERR_CAPACITY,
+                         "stage %d: the output bound of %lld entries (%.0f per row, measured by the analysis) needs "
+                         "%.1f GB; the dense path needs %.1f GB; %.1f GB of %.1f GB are free",
+                         idx, (long long)total, (double)total / (double)std::max<int64_t>(ws.n, 1), need / 1e9,
+                         dense_need / 1e9, (double)fr / 1e9, (double)tot / 1e9);
+    }
+
     // Whether a product stage goes to the dense path: the modelled time of
     // the dense product is below that of the sparse one, and three dense
     // operands fit the free device memory (and the plan's limit).  Sparse:
@@ -551,6 +575,7 @@ struct Engine {
             int64_t total = 0;
             HIP_TRY(hipMemcpyAsync(&total, out.off.as<int64_t>() + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
+            FPS_TRY(fits_device(idx, total, a.mode == kModeProduct));
             FPS_TRY(out.ensure_cap(total));
             learned[(size_t)idx] = std::max<int64_t>(learned[(size_t)idx], total);
         } else {
