@@ -59,11 +59,11 @@ def kernel_source_sha256() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def measured_traffic(workload_name: str):
-    """HBM bytes per launch of the numeric kernel from the committed rocprofv3
+def measured_traffic(workload_name: str, kernel: str):
+    """HBM bytes per launch of a numeric kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None if there is none or the kernel
     source changed since it was taken."""
-    p = os.path.join(ROOT, "profiles", f"traffic_k_numeric_lds_{workload_name}.json")
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload_name}.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
@@ -446,6 +446,8 @@ def main():
     ap.add_argument("--workload", default="lap2d", help="lap2d (headline), lap1d, lap3d (with --side)")
     ap.add_argument("--side", type=int, default=None, help="lap3d: grid side (default 20)")
     ap.add_argument("--dense", action="store_true", help="FPS_FLAG_DENSE: dense products on the FP64 matrix cores")
+    ap.add_argument("--no-small", action="store_true",
+                    help="FPS_FLAG_NO_SMALL: every row on a 64-lane wavefront (no small-row tier)")
     ap.add_argument("--cpu-budget", type=float, default=1.0, help="0 skips the CPU oracle timing")
     ap.add_argument("--filter", choices=["fixed", "adaptive", "series"], default="fixed",
                     help="fixed: the workload's tau; adaptive: Algorithm 1 with the eq. 28 thresholds and the "
@@ -520,7 +522,8 @@ def main():
         log(f"series mode: N = {series_info['N']}, q = {series_info['q']}, tail = {series_info['tail']:.3g}")
     else:
         plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"],
-                        flags=B.FPS_FLAG_TIMING | (B.FPS_FLAG_DENSE if args.dense else 0))
+                        flags=B.FPS_FLAG_TIMING | (B.FPS_FLAG_DENSE if args.dense else 0)
+                        | (B.FPS_FLAG_NO_SMALL if args.no_small else 0))
         if args.dense:
             cfg = dict(cfg, name=cfg["name"] + "_dense")
     torch.cuda.synchronize()
@@ -575,9 +578,31 @@ def main():
         stages[nm] = {"us": round(1e3 * ms, 2), "bytes": by, "GBps": round(gbs, 1),
                       "frac": round(gbs / HBM_PEAK_GBS, 4), "products": pr, "rows_skipped": sk}
     dom = max(stages, key=lambda k: stages[k]["us"]) if stages else None
-    traffic = measured_traffic(cfg["name"])
     dense_ld = st.get("dense_ld", 0)
     dense_stages = [nm for nm, d in zip(names, st["stage_dense"]) if d]
+    # the stages by the kernel that ran them: the small-row tier, the dense
+    # path, or the 64-lane shared-memory kernel (with its fallback tiers)
+    kernels = {}
+    for i, nm in enumerate(names):
+        k = ("k_dgemm_mfma" if st["stage_dense"][i] else
+             "k_numeric_small" if st["stage_small"][i] else "k_numeric_lds")
+        stages[nm]["kernel"] = k
+        d = kernels.setdefault(k, {"launches": 0, "us": 0.0, "bytes": 0.0, "stages": []})
+        d["launches"] += 1
+        d["us"] += stages[nm]["us"]
+        d["bytes"] += kern_bytes[i]
+        d["stages"].append(nm)
+    for d in kernels.values():
+        d["us"] = round(d["us"], 2)
+        d["avg_launch_us"] = round(d["us"] / d["launches"], 2)
+        d["GBps"] = round(d["bytes"] / (d["us"] * 1e-6) / 1e9, 1) if d["us"] > 0 else 0.0
+        d["frac"] = round(d["GBps"] / HBM_PEAK_GBS, 4)
+    sparse_k = {k: d for k, d in kernels.items() if k != "k_dgemm_mfma"}
+    dom_k = max(sparse_k, key=lambda k: sparse_k[k]["us"]) if sparse_k else "k_numeric_lds"
+    dk = kernels.get(dom_k, {"launches": 0, "us": 0.0, "bytes": 0.0})
+    k_launches, k_ms, k_bytes = dk["launches"], dk["us"] / 1e3, dk["bytes"]
+    k_achieved = (k_bytes / (k_ms * 1e-3)) / 1e9 if k_ms > 0 else 0.0
+    traffic = measured_traffic(cfg["name"], dom_k)
     for nm in dense_stages:
         fl = 2.0 * dense_ld ** 3
         us = stages[nm]["us"]
@@ -605,21 +630,25 @@ def main():
                       {"eps": args.eps, "e_r": args.e_r} if args.filter == "adaptive" else
                       {"eps_tol": args.eps_tol, "e_r": args.e_r, "N": series_info["N"]}),
                    "series": "exp", "nnz_F": st["nnz_out"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "achieved": k_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": k_achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "traffic_frac": (traffic / ((kern_ms / launches) * 1e-3) / 1e9 / HBM_PEAK_GBS
-                                      if traffic and launches and kern_ms > 0 else None),
-                     "algorithmic_bytes_per_launch": bytes_kernel / launches if launches else None,
-                     "kernel": "k_numeric_lds",
-                     "launches_per_step": launches,
-                     "avg_launch_ms": kern_ms / launches if launches else None,
-                     "algorithmic_bytes_per_step": bytes_kernel,
+                     "traffic_frac": (traffic / ((k_ms / k_launches) * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                      if traffic and k_launches and k_ms > 0 else None),
+                     "algorithmic_bytes_per_launch": k_bytes / k_launches if k_launches else None,
+                     "kernel": dom_k,
+                     "launches_per_step": k_launches,
+                     "avg_launch_ms": k_ms / k_launches if k_launches else None,
+                     "algorithmic_bytes_per_step": k_bytes,
+                     "numeric_bytes_per_step": bytes_kernel,
+                     "numeric_GBps": achieved,
+                     "numeric_frac": achieved / HBM_PEAK_GBS,
                      "evaluation_bytes_per_step": bytes_eval,
                      "evaluation_GBps": bytes_eval / (ms_per_step * 1e-3) / 1e9,
                      "dominant_launch": dom,
                      "dominant_launch_frac": stages[dom]["frac"] if dom else None},
+        "kernels": kernels,
         "stages": stages,
         **({"dense": {"ld": dense_ld, "stages": dense_stages,
                       "flops_per_step": 2.0 * dense_ld ** 3 * len(dense_stages),

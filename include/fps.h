@@ -91,6 +91,11 @@ typedef int32_t fps_status;
                                         with the ordered sparse path to rounding (and entries within
                                         rounding of tau may be kept or dropped differently), not bit for
                                         bit.  Not with FPS_FLAG_DROP_STATS; not for batches */
+#define FPS_FLAG_NO_SMALL 0x80ull    /* keep every row on a 64-lane wavefront.  Without it, a stage whose
+                                        sizing evaluation found every row within 96 structural entries
+                                        and a 3072-column window runs later evaluations four rows per
+                                        wavefront (16 lanes per row), with the same order of operations
+                                        and so the same results bit for bit */
 
 typedef struct ihipStream_t *fps_stream; /* same type as hipStream_t */
 
@@ -186,6 +191,8 @@ typedef struct {
     double stage_bytes[FPS_MAX_STAGES]; /* algorithmic bytes of the stage (see bytes_algorithmic) */
     int32_t stage_dense[FPS_MAX_STAGES];  /* 1: the product ran on the dense path (FPS_FLAG_DENSE) */
     int64_t dense_ld;                     /* leading dimension of the dense operands (0 if none ran) */
+    int32_t stage_small[FPS_MAX_STAGES];  /* 1: every row of the stage ran in the small-row tier, four rows
+                                             per wavefront (see FPS_FLAG_NO_SMALL) */
 } fps_stats;
 
 /* ---------------------------------------------------------------------- */

@@ -78,6 +78,7 @@ class fps_stats(C.Structure):
         ("stage_bytes", C.c_double * FPS_MAX_STAGES),
         ("stage_dense", C.c_int32 * FPS_MAX_STAGES),
         ("dense_ld", C.c_int64),
+        ("stage_small", C.c_int32 * FPS_MAX_STAGES),
     ]
 
 

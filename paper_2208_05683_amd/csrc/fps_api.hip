@@ -306,6 +306,7 @@ struct StageRecord {
     bool alg1_device = false;  // the record is in the device state (Engine::alg1_state)
     int alg1_mode = 0;         // fps_stats.stage_alg1_mode
     bool wide_rows = false;    // every row of the stage ran in the wide shared-memory tier
+    bool small = false;        // every row of the stage ran in the small-row tier (four rows per wavefront)
     bool dense = false;        // the product ran on the dense path
 };
 
@@ -372,6 +373,7 @@ struct Engine {
     uint64_t flags = 0;
     std::vector<int64_t> learned;  // per stage index: output capacity learned by a sizing run
     std::vector<int64_t> learned_ns;  // per stage index: largest structural row seen by a sizing run
+    std::vector<int64_t> learned_words;  // per stage index: widest row window (32-column words) seen by a sizing run
     std::vector<int64_t> learned_wide;    // per stage: rows a sizing run sent to the wide shared-memory tier
     std::vector<int64_t> learned_global;  // per stage: rows a sizing run sent to the device-memory kernel
     std::vector<int> alg1_learned;  // per stage: Algorithm 1 iterations of the last host-driven run
@@ -400,11 +402,13 @@ struct Engine {
         std::vector<unsigned long long> h((size_t)(kPartCount * ws.part_stride));
         HIP_TRY(hipMemcpy(h.data(), part(i), sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
         for (int k = 0; k < kPartCount; ++k) {
-            const int64_t cnt = (k == kPartKept || k == kPartMaxNs) ? nk : na;
+            const bool per_row_block = k == kPartKept || k == kPartMaxNs || k == kPartMaxWords;
+            const bool maximum = k == kPartMaxNs || k == kPartMaxWords;
+            const int64_t cnt = per_row_block ? nk : na;
             unsigned long long t = 0;
             for (int64_t b = 0; b < cnt; ++b) {
                 const unsigned long long v = h[(size_t)(k * ws.part_stride + b)];
-                t = (k == kPartMaxNs) ? std::max(t, v) : t + v;
+                t = maximum ? std::max(t, v) : t + v;
             }
             out[k] = t;
         }
@@ -420,6 +424,7 @@ struct Engine {
         flags = fl;
         learned.assign((size_t)stages, -1);
         learned_ns.assign((size_t)stages, 0);
+        learned_words.assign((size_t)stages, 0);
         learned_wide.assign((size_t)stages, 0);
         learned_global.assign((size_t)stages, 0);
         alg1_learned.assign((size_t)stages, 0);
@@ -607,6 +612,12 @@ struct Engine {
         const bool wide_rows = !sizing && !a.force_global && learned_wide[(size_t)idx] * 8 > n;
         if (wide_rows) run_wide = false;
         if (rec) rec->wide_rows = wide_rows;
+        // a stage whose sizing run kept every row within the small-row tier
+        // runs four rows per wavefront
+        const bool small = !sizing && !wide_rows && !a.force_global && !a.has_e && !(flags & FPS_FLAG_NO_SMALL) &&
+                           learned_wide[(size_t)idx] == 0 && learned_global[(size_t)idx] == 0 &&
+                           small_tier_fits(learned_ns[(size_t)idx], learned_words[(size_t)idx]);
+        if (rec) rec->small = small;
         a.out = out.out();
         a.wide_planned = run_wide ? 1 : 0;
         a.global_planned = run_global ? 1 : 0;
@@ -615,7 +626,9 @@ struct Engine {
             return (int)std::max<int64_t>(1, std::min<int64_t>((rows + per_block - 1) / per_block, cap));
         };
         if (rec && rec->ev0) HIP_TRY(hipEventRecord(rec->ev0, s));
-        if (wide_rows)
+        if (small)
+            HIP_TRY(launch_numeric_small(a, s));
+        else if (wide_rows)
             HIP_TRY(launch_numeric_wide_rows(a, s));
         else
             HIP_TRY(launch_numeric_lds(a, 0, s));
@@ -652,6 +665,7 @@ struct Engine {
             unsigned long long tot[kPartCount];
             FPS_TRY(stage_totals(idx, a.mode, tot));
             learned_ns[(size_t)idx] = std::max<int64_t>(learned_ns[(size_t)idx], (int64_t)tot[kPartMaxNs]);
+            learned_words[(size_t)idx] = std::max<int64_t>(learned_words[(size_t)idx], (int64_t)tot[kPartMaxWords]);
         }
         return FPS_OK;
     }
@@ -1177,6 +1191,7 @@ struct fps_plan_s {
             r->alg1_device = false;
             r->alg1_mode = 0;
             r->wide_rows = false;
+            r->small = false;
             r->dense = false;
             r->ev0 = r->ev1 = nullptr;
             if (timing_now) {
@@ -1548,6 +1563,7 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
         st->stage_alg1_iters[i] = r.alg1_iters;
         st->stage_alg1_mode[i] = r.alg1_mode;
         st->stage_dense[i] = r.dense ? 1 : 0;
+        st->stage_small[i] = r.small ? 1 : 0;
         if (r.dense) st->dense_ld = p->eng.d_ld;
         st->stage_rows_skipped[i] = (int64_t)tot[(size_t)i][kPartRowsSkipped];
         if (r.alg1_device) {

@@ -101,14 +101,17 @@ struct Alg1Params {
 };
 
 // Per-stage partial sums, one entry per block, layout [kPartCount][part_stride]:
-// kPartMaxNs holds the largest structural row of the block (a maximum, not a sum).
+// kPartMaxNs holds the largest structural row of the block and kPartMaxWords
+// the widest window of its rows in 32-column words (maxima, not sums; the
+// window width is written by the shared-memory tiers only).
 enum PartIndex : int {
     kPartProducts = 0,
     kPartProductsSkipped = 1,
     kPartRowsSkipped = 2,
     kPartKept = 3,
     kPartMaxNs = 4,
-    kPartCount = 5
+    kPartMaxWords = 5,
+    kPartCount = 6
 };
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 
@@ -242,6 +245,12 @@ hipError_t launch_numeric_lds(const StageArgs& a, int grid, hipStream_t s);
 // every row of the stage in the wide shared-memory tier (instead of
 // launch_numeric_lds, for stages whose rows mostly exceed the narrow tier)
 hipError_t launch_numeric_wide_rows(const StageArgs& a, hipStream_t s);
+// Every row of a stage on a 16-lane DPP row (four rows per wavefront); rows
+// beyond the tier go to the wide tier's list.  small_tier_fits tells whether
+// a stage whose largest structural row and widest window (32-column words)
+// are these fits the tier.
+hipError_t launch_numeric_small(const StageArgs& a, hipStream_t s);
+bool small_tier_fits(int64_t max_ns, int64_t max_words);
 // rows of fb_list (persistent blocks: the grid size only sets the parallelism)
 hipError_t launch_numeric_wide(const StageArgs& a, int grid, hipStream_t s);
 // rows of fb2_list

@@ -1646,14 +1646,15 @@ __device__ __forceinline__ void numeric_rows(const StageArgs& P)
 {
     using Ws = LdsWave<kWords, kCap>;
     __shared__ Ws lds[kWavesPerBlock];
-    __shared__ unsigned long long kept_sh[kWavesPerBlock], ns_sh[kWavesPerBlock];
+    __shared__ unsigned long long kept_sh[kWavesPerBlock], ns_sh[kWavesPerBlock], words_sh[kWavesPerBlock];
     const int wv = sgpr((int32_t)(threadIdx.x / kWave));  // wave-uniform: row-level values live in scalar registers
     Ws& me = lds[wv];
     const int l = lane();
     const int64_t blk = xcd_logical_block();
     const int64_t r = blk * kWavesPerBlock + wv;
-    int64_t kept = 0, ns = 0;
+    int64_t kept = 0, ns = 0, words = 0;
     if (r < P.n) {
+        words = ((int64_t)max(P.W[r], 0) + 31) >> 5;
         // the row's output offset: a fixed stride, or its block prefix plus
         // its offset in the block
         const int64_t o = P.row_stride > 0 ? r * P.row_stride : P.blk_pre[r >> P.scan_shift] + P.out.off[r];
@@ -1671,16 +1672,19 @@ __device__ __forceinline__ void numeric_rows(const StageArgs& P)
     if (l == 0) {
         kept_sh[wv] = (unsigned long long)kept;
         ns_sh[wv] = (unsigned long long)ns;
+        words_sh[wv] = (unsigned long long)words;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long t = 0, mx = 0;
+        unsigned long long t = 0, mx = 0, mw = 0;
         for (int i = 0; i < kWavesPerBlock; ++i) {
             t += kept_sh[i];
             mx = max(mx, ns_sh[i]);
+            mw = max(mw, words_sh[i]);
         }
         P.part[kPartKept * P.part_stride + blk] = t;
         P.part[kPartMaxNs * P.part_stride + blk] = mx;
+        P.part[kPartMaxWords * P.part_stride + blk] = mw;
     }
 }
 
@@ -1696,6 +1700,463 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) k_numeric_wide_rows(StageArgs P)
 {
     numeric_rows<kWideWords, kWideCap, false>(P);
+}
+
+// ---- small rows: four rows per wavefront ---------------------------------------
+// Rows with a narrow window and few structural entries (powers of a stencil
+// operator, the start of the Horner recurrence) leave most lanes of a
+// wavefront idle, and such a stage is bound by the latency of each row's
+// chain of dependent loads.  Here each row is owned by one 16-lane DPP row
+// of a wavefront, so four rows share one chain.  The steps and the order of
+// every fma are those of process_row: structure bitmap of the window, ranks,
+// the main terms in term order, the block terms on their own, x = extra +
+// main, the drop test and a sorted write-out.  A stage runs in this tier
+// only when its sizing run found every row within kSmallWords / kSmallCap;
+// a row beyond them later goes to the wide tier's list.
+constexpr int kSmallLanes = 16;
+constexpr int kSmallRowsPerWave = kWave / kSmallLanes;
+constexpr int kSmallRowsPerBlock = kBlock / kSmallLanes;
+constexpr int kSmallWords = 96, kSmallCap = 96;
+constexpr int kSmallPark = kSmallCap / kSmallLanes;  // values per lane after the accumulation
+constexpr int kSmallU = 2;  // terms whose first 32 entries are loaded together
+
+struct SmallRow {
+    uint2 bmp[kSmallWords + 1];  // as in LdsWave: structure bits, earlier set bits; then the guard word
+    double acc[kSmallCap + 1];   // then the spare slot
+};
+
+__device__ __forceinline__ int small_lane() { return lane() & (kSmallLanes - 1); }
+
+// Inclusive prefix sum over the 16 lanes of a DPP row.
+__device__ __forceinline__ uint32_t row_scan_u32(uint32_t x)
+{
+    x += dpp32<kDppRowShr1>(x);
+    x += dpp32<kDppRowShr1 + 1>(x);
+    x += dpp32<kDppRowShr1 + 3>(x);
+    x += dpp32<kDppRowShr1 + 7>(x);
+    return x;
+}
+
+// This lane's DPP row's 16 bits of a wavefront ballot.
+__device__ __forceinline__ uint32_t row_bits(unsigned long long m)
+{
+    return (uint32_t)(m >> (lane() & (kWave - kSmallLanes))) & 0xFFFFu;
+}
+
+// Value of lane j of this lane's DPP row.
+__device__ __forceinline__ int32_t row_bcast(int32_t x, int j) { return __shfl(x, j, kSmallLanes); }
+__device__ __forceinline__ int64_t row_bcast64(int64_t x, int j)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)(uint64_t)x, j, kSmallLanes);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)((uint64_t)x >> 32), j, kSmallLanes);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double row_bcastd(double x, int j)
+{
+    return __longlong_as_double((long long)row_bcast64((int64_t)__double_as_longlong(x), j));
+}
+
+// One term of a chunk of up to 16, held by one lane of the row.
+struct SmallTerm {
+    int64_t beg;  // first entry of the term row; -1: the identity row (coefficient term of P_0)
+    int32_t len;  // entries of the term row (0: no term)
+    int32_t nw;   // structure words of the term row
+    double a;     // weight
+};
+
+template <int SRC>
+__device__ __forceinline__ SmallTerm small_term(const StageArgs& P, int64_t r, int64_t t, bool on)
+{
+    SmallTerm h{0, 0, 0, 0.0};
+    if (!on) return h;
+    if constexpr (SRC == kSrcProducts) {
+        const int32_t k = P.A.col[t];
+        h.a = P.A.val[t];
+        h.beg = P.B.beg[k];
+        h.len = (int32_t)(P.B.end[k] - h.beg);
+        h.nw = P.B.nw[k];
+    } else {
+        const int ti = (int)t;
+        h.a = P.T.coef[ti];
+        const int64_t* bp = P.T.beg[ti];
+        if (bp == nullptr) {
+            h.beg = -1;
+            h.len = 1;
+            h.nw = 1;
+        } else {
+            h.beg = bp[r];
+            h.len = (int32_t)(P.T.end[ti][r] - h.beg);
+            h.nw = P.T.nw[ti][r];
+        }
+    }
+    return h;
+}
+
+// Term j of the chunk starting at term t0: its row's columns, values and
+// structure words (coefficient terms index the same term on every row, so
+// their arrays are uniform).
+template <int SRC>
+__device__ __forceinline__ const uint2* small_sw(const StageArgs& P, int64_t t0, int j, int64_t beg)
+{
+    if constexpr (SRC == kSrcProducts)
+        return P.B.sw + beg;
+    else
+        return P.T.sw[min((int)t0 + j, kMaxTerms - 1)] + beg;
+}
+template <int SRC>
+__device__ __forceinline__ const int32_t* small_col(const StageArgs& P, int64_t t0, int j, int64_t beg)
+{
+    if constexpr (SRC == kSrcProducts)
+        return P.B.col + beg;
+    else
+        return P.T.col[min((int)t0 + j, kMaxTerms - 1)] + beg;
+}
+template <int SRC>
+__device__ __forceinline__ const double* small_val(const StageArgs& P, int64_t t0, int j, int64_t beg)
+{
+    if constexpr (SRC == kSrcProducts)
+        return P.B.val + beg;
+    else
+        return P.T.val[min((int)t0 + j, kMaxTerms - 1)] + beg;
+}
+
+// Structure marks of terms [0, nt) of a chunk: kSmallU terms at a time, the
+// first two words of each per lane loaded together, then the rest.
+template <int SRC>
+__device__ __forceinline__ void small_marks(const StageArgs& P, int64_t r, int64_t t0, int32_t nt, const SmallTerm& h,
+                                            uint32_t lo_w, uint32_t words, uint2* bmp)
+{
+    const int gl = small_lane();
+    const uint2 ident = make_uint2((uint32_t)(r >> 5), 1u << (r & 31));
+    for (int32_t j0 = 0; j0 < nt; j0 += kSmallU) {
+        uint2 w[kSmallU][2];
+        int32_t nw[kSmallU];
+        int64_t beg[kSmallU];
+#pragma unroll
+        for (int g = 0; g < kSmallU; ++g) {
+            const int j = min(j0 + g, kSmallLanes - 1);
+            beg[g] = row_bcast64(h.beg, j);
+            nw[g] = (j0 + g < nt) ? row_bcast(h.nw, j) : 0;
+            const bool id = SRC == kSrcCoefs && beg[g] < 0;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int e = gl + i * kSmallLanes;
+                w[g][i] = make_uint2(0u, 0u);
+                if (e < nw[g]) w[g][i] = id ? ident : small_sw<SRC>(P, t0, j, beg[g])[e];
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < kSmallU; ++g)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                if (gl + i * kSmallLanes < nw[g]) atomicOr(&bmp[min(w[g][i].x - lo_w, words)].x, w[g][i].y);
+#pragma unroll
+        for (int g = 0; g < kSmallU; ++g) {
+            for (int32_t e0 = 2 * kSmallLanes; e0 < nw[g]; e0 += kSmallLanes) {
+                const int32_t e = e0 + gl;
+                if (e < nw[g]) {
+                    const uint2 x = small_sw<SRC>(P, t0, min(j0 + g, kSmallLanes - 1), beg[g])[e];
+                    atomicOr(&bmp[min(x.x - lo_w, words)].x, x.y);
+                }
+            }
+        }
+    }
+}
+
+// acc[rank] = fma(a, v, acc[rank]) for terms [0, nt) of a chunk, strictly
+// term by term (the entries of one term have distinct columns); lanes
+// without an entry use the spare slot.
+template <int SRC>
+__device__ __forceinline__ void small_accumulate(const StageArgs& P, int64_t r, int64_t t0, int32_t nt,
+                                                 const SmallTerm& h, const uint2* bw, int32_t gcol, double* acc)
+{
+    const int gl = small_lane();
+    for (int32_t j0 = 0; j0 < nt; j0 += kSmallU) {
+        int32_t cc[kSmallU][2];
+        double vv[kSmallU][2];
+        double aa[kSmallU];
+        int32_t ln[kSmallU];
+#pragma unroll
+        for (int g = 0; g < kSmallU; ++g) {
+            const int j = min(j0 + g, kSmallLanes - 1);
+            const int64_t beg = row_bcast64(h.beg, j);
+            ln[g] = (j0 + g < nt) ? row_bcast(h.len, j) : 0;
+            aa[g] = row_bcastd(h.a, j);
+            const bool id = SRC == kSrcCoefs && beg < 0;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int e = gl + i * kSmallLanes;
+                cc[g][i] = gcol;
+                vv[g][i] = 0.0;
+                if (e < ln[g]) {
+                    cc[g][i] = id ? (int32_t)r : small_col<SRC>(P, t0, j, beg)[e];
+                    vv[g][i] = id ? 1.0 : small_val<SRC>(P, t0, j, beg)[e];
+                }
+            }
+        }
+        uint32_t sl[kSmallU][2];
+#pragma unroll
+        for (int g = 0; g < kSmallU; ++g)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) sl[g][i] = rank_col(bw, cc[g][i]);
+#pragma unroll
+        for (int g = 0; g < kSmallU; ++g) {
+            if (ln[g] == 0) continue;
+            acc[sl[g][0]] = fma(aa[g], vv[g][0], acc[sl[g][0]]);
+            if (ln[g] > kSmallLanes) acc[sl[g][1]] = fma(aa[g], vv[g][1], acc[sl[g][1]]);
+            if (ln[g] > 2 * kSmallLanes) {
+                const int j = min(j0 + g, kSmallLanes - 1);
+                const int64_t beg = row_bcast64(h.beg, j);
+                const int32_t* cp = small_col<SRC>(P, t0, j, beg);
+                const double* vp = small_val<SRC>(P, t0, j, beg);
+                for (int32_t e0 = 2 * kSmallLanes; e0 < ln[g]; e0 += kSmallLanes) {
+                    const int32_t e = e0 + gl;
+                    int32_t c = gcol;
+                    double v = 0.0;
+                    if (e < ln[g]) {
+                        c = cp[e];
+                        v = vp[e];
+                    }
+                    const uint32_t sv = rank_col(bw, c);
+                    acc[sv] = fma(aa[g], v, acc[sv]);
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
+// All terms of a source, chunk by chunk (16 terms per chunk, one per lane).
+// `first` is the first chunk, already loaded.
+template <int SRC, bool kAccum>
+__device__ __forceinline__ void small_pass(const StageArgs& P, int64_t r, const SmallTerm& first, uint32_t lo_w,
+                                           uint32_t words, uint2* bmp, const uint2* bw, int32_t gcol, double* acc)
+{
+    const int gl = small_lane();
+    int64_t tb, te;
+    term_range(P, SRC, r, &tb, &te);
+    for (int64_t t0 = tb; t0 < te; t0 += kSmallLanes) {
+        const int32_t nt = (int32_t)min<int64_t>(kSmallLanes, te - t0);
+        const SmallTerm h = (t0 == tb) ? first : small_term<SRC>(P, r, t0 + gl, gl < nt);
+        if (kAccum)
+            small_accumulate<SRC>(P, r, t0, nt, h, bw, gcol, acc);
+        else
+            small_marks<SRC>(P, r, t0, nt, h, lo_w, words, bmp);
+    }
+}
+
+// Row r (output offset o) on this lane's DPP row.  Returns false, with
+// nothing written, if the row does not fit the workspace.
+__device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t o, SmallRow& ws, int64_t* kept_out,
+                                          int64_t* ns_out)
+{
+    const int gl = small_lane();
+    *kept_out = 0;
+    *ns_out = 0;
+    const int32_t W = P.W[r];
+    if (W <= 0) {
+        if (gl == 0) empty_row(P, r, o);
+        return true;
+    }
+    const int32_t lo = P.lo[r];
+    const int32_t words = (W + 31) >> 5;
+    if (words > kSmallWords) return false;
+    uint2* bmp = ws.bmp;
+    double* acc = ws.acc;
+    const uint32_t lo_w = (uint32_t)lo >> 5;
+    const uint2* bw = bmp - (lo >> 5);
+    const int32_t gcol = lo + words * 32;
+
+    // 1. structure of the row inside its window, guard word included
+    for (int32_t w = gl; w <= words; w += kSmallLanes) bmp[w].x = 0u;
+    wave_sync();
+    const bool product = P.mode == kModeProduct;
+    const bool has_main = P.prod[r] > 0;
+    int64_t tb, te;
+    term_range(P, product ? kSrcProducts : kSrcCoefs, r, &tb, &te);
+    const int32_t nt0 = (int32_t)min<int64_t>(kSmallLanes, te - tb);
+    SmallTerm m0{0, 0, 0, 0.0}, b0{0, 0, 0, 0.0};
+    if (has_main)
+        m0 = product ? small_term<kSrcProducts>(P, r, tb + gl, gl < nt0) : small_term<kSrcCoefs>(P, r, tb + gl, gl < nt0);
+    if (P.has_blk) {
+        b0 = small_term<kSrcCoefs>(P, r, gl, gl < min(P.T.n, kSmallLanes));
+        small_pass<kSrcCoefs, false>(P, r, b0, lo_w, (uint32_t)words, bmp, bw, gcol, acc);
+    }
+    if (has_main) {
+        if (product)
+            small_pass<kSrcProducts, false>(P, r, m0, lo_w, (uint32_t)words, bmp, bw, gcol, acc);
+        else
+            small_pass<kSrcCoefs, false>(P, r, m0, lo_w, (uint32_t)words, bmp, bw, gcol, acc);
+    }
+    wave_sync();
+    if (bmp[words].x != 0u) {  // a column outside the window: inconsistent row information
+        flag_error(P, kErrColumnOutsideWindow);
+        if (gl == 0) empty_row(P, r, o);
+        return true;
+    }
+
+    // 2. ranks: prefix counts of the bitmap words; the guard word maps to the spare slot
+    uint32_t running = 0;
+    for (int32_t w0 = 0; w0 < words; w0 += kSmallLanes) {
+        const int32_t w = w0 + gl;
+        const uint32_t cnt = (w < words) ? (uint32_t)__popc(bmp[w].x) : 0u;
+        const uint32_t inc = row_scan_u32(cnt);
+        if (w < words) bmp[w].y = running + inc - cnt;
+        running += row_reduce<OpMax>(inc);
+    }
+    const int32_t ns = (int32_t)running;
+    wave_sync();
+    if (gl == 0) bmp[words] = make_uint2(0u, (uint32_t)kSmallCap);
+    *ns_out = ns;
+    if (ns > kSmallCap) return false;
+    if (ns > (P.row_stride > 0 ? P.row_stride : P.out.cap - o)) {
+        flag_error(P, kErrCapacity);
+        if (gl == 0) empty_row(P, r, o);
+        return true;
+    }
+
+    // 3. main terms in order, then the block terms on their own
+    for (int32_t i = gl; i < ns; i += kSmallLanes) acc[i] = 0.0;
+    wave_sync();
+    if (has_main) {
+        if (product)
+            small_pass<kSrcProducts, true>(P, r, m0, lo_w, (uint32_t)words, bmp, bw, gcol, acc);
+        else
+            small_pass<kSrcCoefs, true>(P, r, m0, lo_w, (uint32_t)words, bmp, bw, gcol, acc);
+    }
+    wave_sync();
+    double x[kSmallPark];
+#pragma unroll
+    for (int t = 0; t < kSmallPark; ++t) {
+        const int32_t i = t * kSmallLanes + gl;
+        x[t] = (i < ns) ? acc[i] : 0.0;
+    }
+    if (P.has_blk) {
+        wave_sync();
+        for (int32_t i = gl; i < ns; i += kSmallLanes) acc[i] = 0.0;
+        wave_sync();
+        small_pass<kSrcCoefs, true>(P, r, b0, lo_w, (uint32_t)words, bmp, bw, gcol, acc);
+        wave_sync();
+#pragma unroll
+        for (int t = 0; t < kSmallPark; ++t) {
+            const int32_t i = t * kSmallLanes + gl;
+            if (i < ns) x[t] = acc[i] + x[t];  // x = extra + main
+        }
+    }
+    wave_sync();
+
+    // 4. the columns in slot order, in the accumulator's place
+    int32_t* cols = reinterpret_cast<int32_t*>(acc);
+    for (int32_t w = gl; w < words; w += kSmallLanes) {
+        const uint2 wd = bmp[w];
+        uint32_t bits = wd.x, base = wd.y;
+        while (bits) {
+            const int bt = __ffs((int)bits) - 1;
+            cols[base++] = lo + w * 32 + bt;
+            bits &= bits - 1u;
+        }
+    }
+    wave_sync();
+
+    // 5. drop test and sorted write-out
+    const uint32_t below = (1u << gl) - 1u;
+    const double tau = P.tau_row ? P.tau_row[r] : P.tau;
+    int64_t kept = 0;
+    double amx = 0.0, dmx = 0.0;
+    int32_t first = INT_MAX, last = -1;
+    unsigned long long ndrop = 0;
+#pragma unroll
+    for (int t = 0; t < kSmallPark; ++t) {
+        if (t * kSmallLanes >= ns) break;
+        const int32_t i = t * kSmallLanes + gl;
+        const bool in = i < ns;
+        const int32_t c = in ? cols[i] : 0;
+        const double v = x[t];
+        const bool keep = in && (v != 0.0) && !(fabs(v) < tau);
+        // the bitmap keeps the kept columns only, for the structure words
+        if (in && !keep) atomicAnd(&bmp[(uint32_t)(c - lo) >> 5].x, ~(1u << (c & 31)));
+        if (P.dsum != nullptr) {
+            const bool d = in && v != 0.0 && (!keep || fabs(v) <= P.dthr);
+            if (d) atomicAdd(&P.dsum[c], (unsigned long long)ceil(fabs(v) * P.dscale));
+            if (P.dcount) {
+                if (d) dmx = fmax(dmx, fabs(v));
+                ndrop += (unsigned long long)__popc(row_bits(__ballot(d)));
+            }
+        }
+        const uint32_t m = row_bits(__ballot(keep));
+        if (keep) {
+            const int64_t pos = o + kept + (int64_t)__popc(m & below);
+            P.out.col[pos] = c;
+            P.out.val[pos] = v;
+            amx = fmax(amx, fabs(v));
+            first = min(first, c);
+            last = max(last, c);
+        }
+        kept += __popc(m);
+    }
+    amx = row_reduce<OpMax>(amx);
+    first = row_reduce<OpMin>(first);
+    last = row_reduce<OpMax>(last);
+    if (P.dsum != nullptr && P.dcount) {
+        dmx = row_reduce<OpMax>(dmx);
+        if (gl == 0 && ndrop != 0) {
+            atomicAdd(&P.ctr->n_dropped, ndrop);
+            atomicMax(&P.ctr->dropped_max, (unsigned long long)__double_as_longlong(dmx));
+        }
+    }
+
+    // 6. structure words of the row: the nonzero bitmap words, in order
+    wave_sync();
+    int32_t nwd = 0;
+    for (int32_t w0 = 0; w0 < words; w0 += kSmallLanes) {
+        const int32_t w = w0 + gl;
+        const uint32_t bits = (w < words) ? bmp[w].x : 0u;
+        const uint32_t m = row_bits(__ballot(bits != 0u));
+        if (bits != 0u) P.out.sw[o + nwd + (int64_t)__popc(m & below)] = make_uint2(lo_w + (uint32_t)w, bits);
+        nwd += __popc(m);
+    }
+    if (gl == 0) {
+        P.out.end[r] = o + kept;
+        P.out.info[r] = row_info(kept, first, last, amx);
+        P.out.nw[r] = nwd;
+    }
+    wave_sync();
+    *kept_out = kept;
+    return true;
+}
+
+// Four rows per wavefront, sixteen per block, blocks in XCD-aware order.  The
+// per-block partial sums are written per wavefront, at the index of the
+// four-row block of the other shared-memory tiers (same layout).
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) k_numeric_small(StageArgs P)
+{
+    __shared__ SmallRow rows[kSmallRowsPerBlock];
+    const int wv = sgpr((int32_t)(threadIdx.x / kWave));
+    const int l = lane();
+    const int grp = l / kSmallLanes;
+    const int64_t blk = xcd_logical_block();
+    const int64_t r0 = (blk * kWavesPerBlock + wv) * kSmallRowsPerWave;  // first row of the wavefront
+    const int64_t r = r0 + grp;
+    int64_t kept = 0, ns = 0;
+    if (r < P.n) {
+        const int64_t o = P.row_stride > 0 ? r * P.row_stride : P.blk_pre[r >> P.scan_shift] + P.out.off[r];
+        if (small_lane() == 0) P.out.off[r] = o;
+        const bool done = small_row(P, r, o, rows[wv * kSmallRowsPerWave + grp], &kept, &ns);
+        if (!done && small_lane() == 0) defer_row(P, r, o, &P.ctr->fb_count, P.fb_list, P.wide_planned);
+    }
+    if (r0 < P.n) {
+        unsigned long long t = 0, mx = 0;
+#pragma unroll
+        for (int k = 0; k < kSmallRowsPerWave; ++k) {
+            t += (unsigned long long)readlane64(kept, k * kSmallLanes);
+            mx = max(mx, (unsigned long long)readlane64(ns, k * kSmallLanes));
+        }
+        if (l == 0) {
+            const int64_t pi = r0 / kSmallRowsPerWave;
+            P.part[kPartKept * P.part_stride + pi] = t;
+            P.part[kPartMaxNs * P.part_stride + pi] = mx;
+        }
+    }
 }
 
 // Rows of the wide tier's list, fetched dynamically (few rows, usually): 26.5
@@ -2201,6 +2662,16 @@ hipError_t launch_numeric_lds(const StageArgs& a, int grid, hipStream_t s)
     hipLaunchKernelGGL(k_numeric_lds, dim3((unsigned)numeric_blocks(a.n)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
+
+hipError_t launch_numeric_small(const StageArgs& a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    const int64_t blocks = (a.n + kSmallRowsPerBlock - 1) / kSmallRowsPerBlock;
+    hipLaunchKernelGGL(k_numeric_small, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+bool small_tier_fits(int64_t max_ns, int64_t max_words) { return max_ns <= kSmallCap && max_words <= kSmallWords; }
 
 hipError_t launch_numeric_wide_rows(const StageArgs& a, hipStream_t s)
 {
