@@ -627,7 +627,7 @@ struct Engine {
         };
         if (rec && rec->ev0) HIP_TRY(hipEventRecord(rec->ev0, s));
         if (small)
-            HIP_TRY(launch_numeric_small(a, s));
+            HIP_TRY(launch_numeric_small(a, learned_ns[(size_t)idx], learned_words[(size_t)idx], s));
         else if (wide_rows)
             HIP_TRY(launch_numeric_wide_rows(a, s));
         else

@@ -1711,18 +1711,22 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 
 // every fma are those of process_row: structure bitmap of the window, ranks,
 // the main terms in term order, the block terms on their own, x = extra +
 // main, the drop test and a sorted write-out.  A stage runs in this tier
-// only when its sizing run found every row within kSmallWords / kSmallCap;
-// a row beyond them later goes to the wide tier's list.
+// only when its sizing run found every row within kSmallWords / kSmallCap
+// (24.3 KB per block, six wavefronts per SIMD: a smaller workspace for
+// eight measured no faster, the tier being bound by instruction issue); a
+// row beyond them later goes to the wide tier's list.
 constexpr int kSmallLanes = 16;
 constexpr int kSmallRowsPerWave = kWave / kSmallLanes;
 constexpr int kSmallRowsPerBlock = kBlock / kSmallLanes;
 constexpr int kSmallWords = 96, kSmallCap = 96;
-constexpr int kSmallPark = kSmallCap / kSmallLanes;  // values per lane after the accumulation
 constexpr int kSmallU = 2;  // terms whose first 32 entries are loaded together
 
+template <int kWords, int kCap>
 struct SmallRow {
-    uint2 bmp[kSmallWords + 1];  // as in LdsWave: structure bits, earlier set bits; then the guard word
-    double acc[kSmallCap + 1];   // then the spare slot
+    static_assert(kCap % kSmallLanes == 0, "the values per lane cover the accumulator exactly");
+    static constexpr int kPark = kCap / kSmallLanes;  // values per lane after the accumulation
+    uint2 bmp[kWords + 1];  // as in LdsWave: structure bits, earlier set bits; then the guard word
+    double acc[kCap + 1];   // then the spare slot
 };
 
 __device__ __forceinline__ int small_lane() { return lane() & (kSmallLanes - 1); }
@@ -1947,7 +1951,9 @@ __device__ __forceinline__ void small_pass(const StageArgs& P, int64_t r, const 
 
 // Row r (output offset o) on this lane's DPP row.  Returns false, with
 // nothing written, if the row does not fit the workspace.
-__device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t o, SmallRow& ws, int64_t* kept_out,
+// kBlk: the stage fuses a coefficient block (P.has_blk).
+template <int kWords, int kCap, bool kBlk>
+__device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t o, SmallRow<kWords, kCap>& ws, int64_t* kept_out,
                                           int64_t* ns_out)
 {
     const int gl = small_lane();
@@ -1960,7 +1966,7 @@ __device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t
     }
     const int32_t lo = P.lo[r];
     const int32_t words = (W + 31) >> 5;
-    if (words > kSmallWords) return false;
+    if (words > kWords) return false;
     uint2* bmp = ws.bmp;
     double* acc = ws.acc;
     const uint32_t lo_w = (uint32_t)lo >> 5;
@@ -1978,7 +1984,7 @@ __device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t
     SmallTerm m0{0, 0, 0, 0.0}, b0{0, 0, 0, 0.0};
     if (has_main)
         m0 = product ? small_term<kSrcProducts>(P, r, tb + gl, gl < nt0) : small_term<kSrcCoefs>(P, r, tb + gl, gl < nt0);
-    if (P.has_blk) {
+    if (kBlk) {
         b0 = small_term<kSrcCoefs>(P, r, gl, gl < min(P.T.n, kSmallLanes));
         small_pass<kSrcCoefs, false>(P, r, b0, lo_w, (uint32_t)words, bmp, bw, gcol, acc);
     }
@@ -2006,9 +2012,9 @@ __device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t
     }
     const int32_t ns = (int32_t)running;
     wave_sync();
-    if (gl == 0) bmp[words] = make_uint2(0u, (uint32_t)kSmallCap);
+    if (gl == 0) bmp[words] = make_uint2(0u, (uint32_t)kCap);
     *ns_out = ns;
-    if (ns > kSmallCap) return false;
+    if (ns > kCap) return false;
     if (ns > (P.row_stride > 0 ? P.row_stride : P.out.cap - o)) {
         flag_error(P, kErrCapacity);
         if (gl == 0) empty_row(P, r, o);
@@ -2025,20 +2031,20 @@ __device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t
             small_pass<kSrcCoefs, true>(P, r, m0, lo_w, (uint32_t)words, bmp, bw, gcol, acc);
     }
     wave_sync();
-    double x[kSmallPark];
+    double x[SmallRow<kWords, kCap>::kPark];
 #pragma unroll
-    for (int t = 0; t < kSmallPark; ++t) {
+    for (int t = 0; t < SmallRow<kWords, kCap>::kPark; ++t) {
         const int32_t i = t * kSmallLanes + gl;
         x[t] = (i < ns) ? acc[i] : 0.0;
     }
-    if (P.has_blk) {
+    if (kBlk) {
         wave_sync();
         for (int32_t i = gl; i < ns; i += kSmallLanes) acc[i] = 0.0;
         wave_sync();
         small_pass<kSrcCoefs, true>(P, r, b0, lo_w, (uint32_t)words, bmp, bw, gcol, acc);
         wave_sync();
 #pragma unroll
-        for (int t = 0; t < kSmallPark; ++t) {
+        for (int t = 0; t < SmallRow<kWords, kCap>::kPark; ++t) {
             const int32_t i = t * kSmallLanes + gl;
             if (i < ns) x[t] = acc[i] + x[t];  // x = extra + main
         }
@@ -2066,7 +2072,7 @@ __device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t
     int32_t first = INT_MAX, last = -1;
     unsigned long long ndrop = 0;
 #pragma unroll
-    for (int t = 0; t < kSmallPark; ++t) {
+    for (int t = 0; t < SmallRow<kWords, kCap>::kPark; ++t) {
         if (t * kSmallLanes >= ns) break;
         const int32_t i = t * kSmallLanes + gl;
         const bool in = i < ns;
@@ -2128,9 +2134,10 @@ __device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t
 // Four rows per wavefront, sixteen per block, blocks in XCD-aware order.  The
 // per-block partial sums are written per wavefront, at the index of the
 // four-row block of the other shared-memory tiers (same layout).
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) k_numeric_small(StageArgs P)
+template <int kWords, int kCap, int kWaves, bool kBlk>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 8))) k_numeric_small(StageArgs P)
 {
-    __shared__ SmallRow rows[kSmallRowsPerBlock];
+    __shared__ SmallRow<kWords, kCap> rows[kSmallRowsPerBlock];
     const int wv = sgpr((int32_t)(threadIdx.x / kWave));
     const int l = lane();
     const int grp = l / kSmallLanes;
@@ -2141,7 +2148,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 
     if (r < P.n) {
         const int64_t o = P.row_stride > 0 ? r * P.row_stride : P.blk_pre[r >> P.scan_shift] + P.out.off[r];
         if (small_lane() == 0) P.out.off[r] = o;
-        const bool done = small_row(P, r, o, rows[wv * kSmallRowsPerWave + grp], &kept, &ns);
+        const bool done = small_row<kWords, kCap, kBlk>(P, r, o, rows[wv * kSmallRowsPerWave + grp], &kept, &ns);
         if (!done && small_lane() == 0) defer_row(P, r, o, &P.ctr->fb_count, P.fb_list, P.wide_planned);
     }
     if (r0 < P.n) {
@@ -2663,11 +2670,17 @@ hipError_t launch_numeric_lds(const StageArgs& a, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_numeric_small(const StageArgs& a, hipStream_t s)
+hipError_t launch_numeric_small(const StageArgs& a, int64_t max_ns, int64_t max_words, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
     const int64_t blocks = (a.n + kSmallRowsPerBlock - 1) / kSmallRowsPerBlock;
-    hipLaunchKernelGGL(k_numeric_small, dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    (void)max_ns;
+    (void)max_words;
+    const dim3 g((unsigned)blocks), b(kBlock);
+    if (a.has_blk)
+        hipLaunchKernelGGL((k_numeric_small<kSmallWords, kSmallCap, 6, true>), g, b, 0, s, a);
+    else
+        hipLaunchKernelGGL((k_numeric_small<kSmallWords, kSmallCap, 6, false>), g, b, 0, s, a);
     return hipGetLastError();
 }
 
