@@ -374,6 +374,7 @@ struct Engine {
     std::vector<int64_t> learned;  // per stage index: output capacity learned by a sizing run
     std::vector<int64_t> learned_ns;  // per stage index: largest structural row seen by a sizing run
     std::vector<int64_t> learned_words;  // per stage index: widest row window (32-column words) seen by a sizing run
+    std::vector<int> fused;  // per stage index: the last run did the analysis in the small-row kernel
     std::vector<int64_t> learned_wide;    // per stage: rows a sizing run sent to the wide shared-memory tier
     std::vector<int64_t> learned_global;  // per stage: rows a sizing run sent to the device-memory kernel
     std::vector<int> alg1_learned;  // per stage: Algorithm 1 iterations of the last host-driven run
@@ -402,7 +403,7 @@ struct Engine {
         std::vector<unsigned long long> h((size_t)(kPartCount * ws.part_stride));
         HIP_TRY(hipMemcpy(h.data(), part(i), sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
         for (int k = 0; k < kPartCount; ++k) {
-            const bool per_row_block = k == kPartKept || k == kPartMaxNs || k == kPartMaxWords;
+            const bool per_row_block = k == kPartKept || k == kPartMaxNs || k == kPartMaxWords || fused[(size_t)i];
             const bool maximum = k == kPartMaxNs || k == kPartMaxWords;
             const int64_t cnt = per_row_block ? nk : na;
             unsigned long long t = 0;
@@ -425,6 +426,7 @@ struct Engine {
         learned.assign((size_t)stages, -1);
         learned_ns.assign((size_t)stages, 0);
         learned_words.assign((size_t)stages, 0);
+        fused.assign((size_t)stages, 0);
         learned_wide.assign((size_t)stages, 0);
         learned_global.assign((size_t)stages, 0);
         alg1_learned.assign((size_t)stages, 0);
@@ -569,7 +571,17 @@ struct Engine {
         }
         FPS_TRY(out.ensure_cap(a.row_stride > 0 ? a.row_stride * n : std::max<int64_t>(learned[(size_t)idx], 0)));
         a.out = out.out();  // the analysis writes the row offsets (out.off)
-        HIP_TRY(launch_analyze(a, s));
+        // a stage whose sizing run kept every row within the small-row tier
+        // runs four rows per wavefront; with fixed row strides that kernel
+        // also does each row's analysis (no analysis launch, no offsets scan)
+        const bool wide_rows = !sizing && !a.force_global && learned_wide[(size_t)idx] * 8 > n;
+        const bool small = !sizing && !wide_rows && !a.force_global && !a.has_e && !(flags & FPS_FLAG_NO_SMALL) &&
+                           !learned_dense[(size_t)idx] && learned_wide[(size_t)idx] == 0 &&
+                           learned_global[(size_t)idx] == 0 &&
+                           small_tier_fits(learned_ns[(size_t)idx], learned_words[(size_t)idx]);
+        a.fuse_analysis = (small && a.row_stride > 0 && a.prod_acc == nullptr) ? 1 : 0;
+        fused[(size_t)idx] = a.fuse_analysis;
+        if (!a.fuse_analysis) HIP_TRY(launch_analyze(a, s));
         // fallback kernels: a sizing run launches each one when rows reached
         // its list (read back after the kernel before it); later runs launch
         // those that a sizing run needed, with grids for the rows seen then
@@ -609,14 +621,8 @@ struct Engine {
         // a stage whose sizing run sent more than an eighth of its rows past the
         // narrow tier runs every row in the wide tier (instead of building
         // those rows' structure twice)
-        const bool wide_rows = !sizing && !a.force_global && learned_wide[(size_t)idx] * 8 > n;
         if (wide_rows) run_wide = false;
         if (rec) rec->wide_rows = wide_rows;
-        // a stage whose sizing run kept every row within the small-row tier
-        // runs four rows per wavefront
-        const bool small = !sizing && !wide_rows && !a.force_global && !a.has_e && !(flags & FPS_FLAG_NO_SMALL) &&
-                           learned_wide[(size_t)idx] == 0 && learned_global[(size_t)idx] == 0 &&
-                           small_tier_fits(learned_ns[(size_t)idx], learned_words[(size_t)idx]);
         if (rec) rec->small = small;
         a.out = out.out();
         a.wide_planned = run_wide ? 1 : 0;

@@ -181,7 +181,11 @@ struct StageArgs {
     int32_t force_global;
     int32_t global_planned;  // 0: the device-memory kernel will not run for this stage
     int32_t wide_planned;    // 0: the wide-tier kernel will not run for this stage
-    int32_t plan_pad;
+    // The small-row tier computes each row's window, product count and
+    // empty-row test itself (the analysis kernel is not launched; fixed row
+    // strides only); the product counts then go to the partial sums at the
+    // numeric kernel's four-row block index.
+    int32_t fuse_analysis;
     // Column sums at the write-out: when dsum is set, every nonzero entry
     // removed by the tau test or with |x| <= dthr adds ceil(|x| * dscale) to
     // dsum[col] (exact integer sums); with dcount it is also counted in

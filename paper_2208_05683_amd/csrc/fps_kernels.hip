@@ -1949,22 +1949,138 @@ __device__ __forceinline__ void small_pass(const StageArgs& P, int64_t r, const 
     }
 }
 
+// A row's analysis on its 16-lane DPP row, as the analysis kernels compute
+// it: the same lanes take the same terms in the same order and reduce over
+// the same DPP row, so the window, the product count and the empty-row test
+// (a floating-point bound) come out identical.  Writes W, lo and the product
+// count for the fallback tiers; also returns the row's multiply-adds and
+// whether the empty-row test skipped them.
+struct SmallAnalysis {
+    int32_t W, lo;
+    int64_t prod;
+    int64_t work;  // multiply-adds of the row (done, or skipped if `skip`)
+    bool skip;
+};
+
+template <bool kBlk>
+__device__ __forceinline__ SmallAnalysis small_analyze(const StageArgs& P, int64_t r)
+{
+    const int gl = small_lane();
+    static_assert(kSmallLanes == kAnalyzeLanes, "one DPP row per row, as in the analysis");
+    SmallAnalysis a{0, 0, 0, 0, false};
+    int32_t lo = INT_MAX, hi = -1;
+    int64_t prod = 0;
+    if (P.mode == kModeProduct) {
+        double bnd = 0.0;
+        const int64_t pb = P.A.beg[r], pe = P.A.end[r];
+#pragma unroll 4
+        for (int64_t p = pb + gl; p < pe; p += kSmallLanes) {
+            const int32_t k = P.A.col[p];
+            const RowInfo q = load_info(P.B.info + k);
+            lo = min(lo, q.len > 0 ? q.first : INT_MAX);
+            hi = max(hi, q.len > 0 ? q.last : -1);
+            prod += q.len;
+            bnd += fabs(P.A.val[p]) * (double)q.amax;
+        }
+        int64_t elen = 0;
+        double emax = 0.0;
+        if (kBlk) {
+            for (int t = gl; t < P.T.n; t += kSmallLanes) {
+                if (P.T.beg[t] == nullptr) {
+                    lo = min(lo, (int32_t)r);
+                    hi = max(hi, (int32_t)r);
+                    elen += 1;
+                    emax += fabs(P.T.coef[t]);
+                } else {
+                    const RowInfo q = load_info(P.T.info[t] + r);
+                    if (q.len > 0) {
+                        lo = min(lo, q.first);
+                        hi = max(hi, q.last);
+                        elen += q.len;
+                        emax += fabs(P.T.coef[t]) * (double)q.amax;
+                    }
+                }
+            }
+        }
+        lo = row_reduce<OpMin>(lo);
+        hi = row_reduce<OpMax>(hi);
+        prod = row_reduce<OpSum>(prod);
+        bnd = row_reduce<OpSum>(bnd);
+        elen = row_reduce<OpSum>(elen);
+        emax = row_reduce<OpSum>(emax);
+        const bool empty = (prod == 0 && elen == 0);
+        const double skip_tau = P.tau_row ? P.tau_row[r] * P.skip_rel : P.skip_tau;
+        const bool skip = !empty && skip_tau > 0.0 && (emax + bnd) < skip_tau;
+        if (!empty && !skip) {
+            lo &= ~31;
+            a.W = hi - lo + 1;
+        }
+        a.work = prod + (kBlk ? elen : 0);
+        a.skip = skip;
+    } else {
+        for (int t = gl; t < P.T.n; t += kSmallLanes) {
+            if (P.T.beg[t] == nullptr) {
+                lo = min(lo, (int32_t)r);
+                hi = max(hi, (int32_t)r);
+                prod += 1;
+            } else {
+                const RowInfo q = load_info(P.T.info[t] + r);
+                if (q.len > 0) {
+                    lo = min(lo, q.first);
+                    hi = max(hi, q.last);
+                    prod += q.len;
+                }
+            }
+        }
+        lo = row_reduce<OpMin>(lo);
+        hi = row_reduce<OpMax>(hi);
+        prod = row_reduce<OpSum>(prod);
+        if (prod > 0) {
+            lo &= ~31;
+            a.W = hi - lo + 1;
+        }
+        a.work = prod;
+    }
+    a.lo = lo;
+    a.prod = prod;
+    if (gl == 0) {
+        P.W[r] = a.W;
+        P.lo[r] = lo;
+        P.prod[r] = prod;
+    }
+    return a;
+}
+
 // Row r (output offset o) on this lane's DPP row.  Returns false, with
 // nothing written, if the row does not fit the workspace.
 // kBlk: the stage fuses a coefficient block (P.has_blk).
+// With P.fuse_analysis the row's analysis comes first; lane 0 stores the
+// row's multiply-adds in *work (their complement if the empty-row test
+// skipped them).
 template <int kWords, int kCap, bool kBlk>
 __device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t o, SmallRow<kWords, kCap>& ws, int64_t* kept_out,
-                                          int64_t* ns_out)
+                                          int64_t* ns_out, long long* work)
 {
     const int gl = small_lane();
     *kept_out = 0;
     *ns_out = 0;
-    const int32_t W = P.W[r];
+    int32_t W, lo;
+    int64_t prod;
+    if (P.fuse_analysis) {
+        const SmallAnalysis an = small_analyze<kBlk>(P, r);
+        W = an.W;
+        lo = an.lo;
+        prod = an.prod;
+        if (gl == 0) *work = an.skip ? ~(long long)an.work : (long long)an.work;
+    } else {
+        W = P.W[r];
+        lo = P.lo[r];
+        prod = P.prod[r];
+    }
     if (W <= 0) {
         if (gl == 0) empty_row(P, r, o);
         return true;
     }
-    const int32_t lo = P.lo[r];
     const int32_t words = (W + 31) >> 5;
     if (words > kWords) return false;
     uint2* bmp = ws.bmp;
@@ -1977,7 +2093,7 @@ __device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t
     for (int32_t w = gl; w <= words; w += kSmallLanes) bmp[w].x = 0u;
     wave_sync();
     const bool product = P.mode == kModeProduct;
-    const bool has_main = P.prod[r] > 0;
+    const bool has_main = prod > 0;
     int64_t tb, te;
     term_range(P, product ? kSrcProducts : kSrcCoefs, r, &tb, &te);
     const int32_t nt0 = (int32_t)min<int64_t>(kSmallLanes, te - tb);
@@ -2138,6 +2254,7 @@ template <int kWords, int kCap, int kWaves, bool kBlk>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWaves, 8))) k_numeric_small(StageArgs P)
 {
     __shared__ SmallRow<kWords, kCap> rows[kSmallRowsPerBlock];
+    __shared__ long long work_sh[kSmallRowsPerBlock];
     const int wv = sgpr((int32_t)(threadIdx.x / kWave));
     const int l = lane();
     const int grp = l / kSmallLanes;
@@ -2145,23 +2262,36 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kWa
     const int64_t r0 = (blk * kWavesPerBlock + wv) * kSmallRowsPerWave;  // first row of the wavefront
     const int64_t r = r0 + grp;
     int64_t kept = 0, ns = 0;
+    long long* work = &work_sh[wv * kSmallRowsPerWave + grp];
+    if (small_lane() == 0) *work = 0;
     if (r < P.n) {
         const int64_t o = P.row_stride > 0 ? r * P.row_stride : P.blk_pre[r >> P.scan_shift] + P.out.off[r];
         if (small_lane() == 0) P.out.off[r] = o;
-        const bool done = small_row<kWords, kCap, kBlk>(P, r, o, rows[wv * kSmallRowsPerWave + grp], &kept, &ns);
+        const bool done =
+            small_row<kWords, kCap, kBlk>(P, r, o, rows[wv * kSmallRowsPerWave + grp], &kept, &ns, work);
         if (!done && small_lane() == 0) defer_row(P, r, o, &P.ctr->fb_count, P.fb_list, P.wide_planned);
     }
+    wave_sync();
     if (r0 < P.n) {
-        unsigned long long t = 0, mx = 0;
+        unsigned long long t = 0, mx = 0, pd = 0, ps = 0, rs = 0;
 #pragma unroll
         for (int k = 0; k < kSmallRowsPerWave; ++k) {
             t += (unsigned long long)readlane64(kept, k * kSmallLanes);
             mx = max(mx, (unsigned long long)readlane64(ns, k * kSmallLanes));
+            const long long w = work_sh[wv * kSmallRowsPerWave + k];
+            pd += w >= 0 ? (unsigned long long)w : 0ull;
+            ps += w < 0 ? (unsigned long long)~w : 0ull;
+            rs += w < 0 ? 1ull : 0ull;
         }
         if (l == 0) {
             const int64_t pi = r0 / kSmallRowsPerWave;
             P.part[kPartKept * P.part_stride + pi] = t;
             P.part[kPartMaxNs * P.part_stride + pi] = mx;
+            if (P.fuse_analysis) {
+                P.part[kPartProducts * P.part_stride + pi] = pd;
+                P.part[kPartProductsSkipped * P.part_stride + pi] = ps;
+                P.part[kPartRowsSkipped * P.part_stride + pi] = rs;
+            }
         }
     }
 }
