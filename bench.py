@@ -574,11 +574,12 @@ def main():
     prod_per_s = products / (ms_per_step * 1e-3)
     names = [f"{['power', 'block', 'gstep', 'horner'][k]}{i}" for k, i in zip(st["kind"], st["index"])]
     stages = {}
-    for nm, ms, by, pr, sk in zip(names, st["stage_ms"], kern_bytes, st["stage_products"],
-                                  st["stage_rows_skipped"]):
+    for nm, ms, by, pr, sk, mn, mw in zip(names, st["stage_ms"], kern_bytes, st["stage_products"],
+                                          st["stage_rows_skipped"], st["stage_max_ns"], st["stage_max_words"]):
         gbs = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         stages[nm] = {"us": round(1e3 * ms, 2), "bytes": by, "GBps": round(gbs, 1),
-                      "frac": round(gbs / HBM_PEAK_GBS, 4), "products": pr, "rows_skipped": sk}
+                      "frac": round(gbs / HBM_PEAK_GBS, 4), "products": pr, "rows_skipped": sk,
+                      "max_row": mn, "max_window_words": mw}
     dom = max(stages, key=lambda k: stages[k]["us"]) if stages else None
     dense_ld = st.get("dense_ld", 0)
     dense_stages = [nm for nm, d in zip(names, st["stage_dense"]) if d]

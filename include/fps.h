@@ -193,6 +193,9 @@ typedef struct {
     int64_t dense_ld;                     /* leading dimension of the dense operands (0 if none ran) */
     int32_t stage_small[FPS_MAX_STAGES];  /* 1: every row of the stage ran in the small-row tier, four rows
                                              per wavefront (see FPS_FLAG_NO_SMALL) */
+    int64_t stage_max_ns[FPS_MAX_STAGES];    /* largest structural row (entries before the drop) seen by the
+                                                stage's sizing evaluations */
+    int64_t stage_max_words[FPS_MAX_STAGES]; /* widest row window, in 32-column words, seen by them */
 } fps_stats;
 
 /* ---------------------------------------------------------------------- */

@@ -79,6 +79,8 @@ class fps_stats(C.Structure):
         ("stage_dense", C.c_int32 * FPS_MAX_STAGES),
         ("dense_ld", C.c_int64),
         ("stage_small", C.c_int32 * FPS_MAX_STAGES),
+        ("stage_max_ns", C.c_int64 * FPS_MAX_STAGES),
+        ("stage_max_words", C.c_int64 * FPS_MAX_STAGES),
     ]
 
 

@@ -1570,6 +1570,8 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
         st->stage_alg1_mode[i] = r.alg1_mode;
         st->stage_dense[i] = r.dense ? 1 : 0;
         st->stage_small[i] = r.small ? 1 : 0;
+        st->stage_max_ns[i] = p->eng.learned_ns[(size_t)i];
+        st->stage_max_words[i] = p->eng.learned_words[(size_t)i];
         if (r.dense) st->dense_ld = p->eng.d_ld;
         st->stage_rows_skipped[i] = (int64_t)tot[(size_t)i][kPartRowsSkipped];
         if (r.alg1_device) {

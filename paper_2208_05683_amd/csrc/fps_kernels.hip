@@ -1713,8 +1713,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 
 // main, the drop test and a sorted write-out.  A stage runs in this tier
 // only when its sizing run found every row within kSmallWords / kSmallCap
 // (24.3 KB per block, six wavefronts per SIMD: a smaller workspace for
-// eight measured no faster, the tier being bound by instruction issue); a
-// row beyond them later goes to the wide tier's list.
+// eight measured no faster, the tier being bound by instruction issue; a
+// larger one, 192 entries in 5120 columns at three wavefronts per SIMD, took
+// rows of 85 terms of about 10 entries in 298 us against the 64-lane packed
+// path's 172); a row beyond them later goes to the wide tier's list.
 constexpr int kSmallLanes = 16;
 constexpr int kSmallRowsPerWave = kWave / kSmallLanes;
 constexpr int kSmallRowsPerBlock = kBlock / kSmallLanes;
