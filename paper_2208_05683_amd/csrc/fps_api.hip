@@ -573,7 +573,9 @@ struct Engine {
         a.out = out.out();  // the analysis writes the row offsets (out.off)
         // a stage whose sizing run kept every row within the small-row tier
         // runs four rows per wavefront; with fixed row strides that kernel
-        // also does each row's analysis (no analysis launch, no offsets scan)
+        // also does each row's analysis (no analysis launch, no offsets
+        // scan).  (Taking the analysis into the 64-lane kernel as well made
+        // its long rows slower than the separate launch costs.)
         const bool wide_rows = !sizing && !a.force_global && learned_wide[(size_t)idx] * 8 > n;
         const bool small = !sizing && !wide_rows && !a.force_global && !a.has_e && !(flags & FPS_FLAG_NO_SMALL) &&
                            !learned_dense[(size_t)idx] && learned_wide[(size_t)idx] == 0 &&

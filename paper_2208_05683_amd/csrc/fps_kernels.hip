@@ -1964,19 +1964,59 @@ struct SmallAnalysis {
     bool skip;
 };
 
+// The first chunk of terms (16, one per lane) of the main part and of the
+// block are read in the same pass: *mt and *bt are what small_term gives.
 template <bool kBlk>
-__device__ __forceinline__ SmallAnalysis small_analyze(const StageArgs& P, int64_t r)
+__device__ __forceinline__ SmallAnalysis small_analyze(const StageArgs& P, int64_t r, SmallTerm* mt, SmallTerm* bt)
 {
     const int gl = small_lane();
     static_assert(kSmallLanes == kAnalyzeLanes, "one DPP row per row, as in the analysis");
     SmallAnalysis a{0, 0, 0, 0, false};
     int32_t lo = INT_MAX, hi = -1;
     int64_t prod = 0;
+    *mt = SmallTerm{0, 0, 0, 0.0};
+    *bt = SmallTerm{0, 0, 0, 0.0};
+    // coefficient term t of row r: summary into the window and counts, and
+    // (first chunk) the term itself
+    auto coef_term = [&](int t, bool first, int64_t* len_sum, double* amax_sum, SmallTerm* h) {
+        const int64_t* bp = P.T.beg[t];
+        if (bp == nullptr) {
+            lo = min(lo, (int32_t)r);
+            hi = max(hi, (int32_t)r);
+            *len_sum += 1;
+            if (amax_sum) *amax_sum += fabs(P.T.coef[t]);
+            if (first) *h = SmallTerm{-1, 1, 1, P.T.coef[t]};
+        } else {
+            const RowInfo q = load_info(P.T.info[t] + r);
+            if (first) {
+                const int64_t b = bp[r];
+                *h = SmallTerm{b, (int32_t)(P.T.end[t][r] - b), P.T.nw[t][r], P.T.coef[t]};
+            }
+            if (q.len > 0) {
+                lo = min(lo, q.first);
+                hi = max(hi, q.last);
+                *len_sum += q.len;
+                if (amax_sum) *amax_sum += fabs(P.T.coef[t]) * (double)q.amax;
+            }
+        }
+    };
     if (P.mode == kModeProduct) {
         double bnd = 0.0;
         const int64_t pb = P.A.beg[r], pe = P.A.end[r];
+        int64_t p = pb + gl;
+        if (p < pe) {  // the first chunk: the term as well
+            const int32_t k = P.A.col[p];
+            const double av = P.A.val[p];
+            const RowInfo q = load_info(P.B.info + k);
+            const int64_t b = P.B.beg[k];
+            *mt = SmallTerm{b, (int32_t)(P.B.end[k] - b), P.B.nw[k], av};
+            lo = min(lo, q.len > 0 ? q.first : INT_MAX);
+            hi = max(hi, q.len > 0 ? q.last : -1);
+            prod += q.len;
+            bnd += fabs(av) * (double)q.amax;
+        }
 #pragma unroll 4
-        for (int64_t p = pb + gl; p < pe; p += kSmallLanes) {
+        for (p += kSmallLanes; p < pe; p += kSmallLanes) {
             const int32_t k = P.A.col[p];
             const RowInfo q = load_info(P.B.info + k);
             lo = min(lo, q.len > 0 ? q.first : INT_MAX);
@@ -1987,22 +2027,7 @@ __device__ __forceinline__ SmallAnalysis small_analyze(const StageArgs& P, int64
         int64_t elen = 0;
         double emax = 0.0;
         if (kBlk) {
-            for (int t = gl; t < P.T.n; t += kSmallLanes) {
-                if (P.T.beg[t] == nullptr) {
-                    lo = min(lo, (int32_t)r);
-                    hi = max(hi, (int32_t)r);
-                    elen += 1;
-                    emax += fabs(P.T.coef[t]);
-                } else {
-                    const RowInfo q = load_info(P.T.info[t] + r);
-                    if (q.len > 0) {
-                        lo = min(lo, q.first);
-                        hi = max(hi, q.last);
-                        elen += q.len;
-                        emax += fabs(P.T.coef[t]) * (double)q.amax;
-                    }
-                }
-            }
+            for (int t = gl; t < P.T.n; t += kSmallLanes) coef_term(t, t == gl, &elen, &emax, bt);
         }
         lo = row_reduce<OpMin>(lo);
         hi = row_reduce<OpMax>(hi);
@@ -2020,20 +2045,7 @@ __device__ __forceinline__ SmallAnalysis small_analyze(const StageArgs& P, int64
         a.work = prod + (kBlk ? elen : 0);
         a.skip = skip;
     } else {
-        for (int t = gl; t < P.T.n; t += kSmallLanes) {
-            if (P.T.beg[t] == nullptr) {
-                lo = min(lo, (int32_t)r);
-                hi = max(hi, (int32_t)r);
-                prod += 1;
-            } else {
-                const RowInfo q = load_info(P.T.info[t] + r);
-                if (q.len > 0) {
-                    lo = min(lo, q.first);
-                    hi = max(hi, q.last);
-                    prod += q.len;
-                }
-            }
-        }
+        for (int t = gl; t < P.T.n; t += kSmallLanes) coef_term(t, t == gl, &prod, nullptr, mt);
         lo = row_reduce<OpMin>(lo);
         hi = row_reduce<OpMax>(hi);
         prod = row_reduce<OpSum>(prod);
@@ -2068,8 +2080,9 @@ __device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t
     *ns_out = 0;
     int32_t W, lo;
     int64_t prod;
+    SmallTerm m0{0, 0, 0, 0.0}, b0{0, 0, 0, 0.0};  // first chunks of the main and block terms
     if (P.fuse_analysis) {
-        const SmallAnalysis an = small_analyze<kBlk>(P, r);
+        const SmallAnalysis an = small_analyze<kBlk>(P, r, &m0, &b0);
         W = an.W;
         lo = an.lo;
         prod = an.prod;
@@ -2099,11 +2112,10 @@ __device__ __forceinline__ bool small_row(const StageArgs& P, int64_t r, int64_t
     int64_t tb, te;
     term_range(P, product ? kSrcProducts : kSrcCoefs, r, &tb, &te);
     const int32_t nt0 = (int32_t)min<int64_t>(kSmallLanes, te - tb);
-    SmallTerm m0{0, 0, 0, 0.0}, b0{0, 0, 0, 0.0};
-    if (has_main)
+    if (has_main && !P.fuse_analysis)
         m0 = product ? small_term<kSrcProducts>(P, r, tb + gl, gl < nt0) : small_term<kSrcCoefs>(P, r, tb + gl, gl < nt0);
     if (kBlk) {
-        b0 = small_term<kSrcCoefs>(P, r, gl, gl < min(P.T.n, kSmallLanes));
+        if (!P.fuse_analysis) b0 = small_term<kSrcCoefs>(P, r, gl, gl < min(P.T.n, kSmallLanes));
         small_pass<kSrcCoefs, false>(P, r, b0, lo_w, (uint32_t)words, bmp, bw, gcol, acc);
     }
     if (has_main) {
@@ -2390,18 +2402,37 @@ __global__ void __launch_bounds__(kBlock) k_row_offsets(const int64_t* __restric
     if (threadIdx.x == 0) blk_pre[blockIdx.x] = total;
 }
 
+// One wavefront per row; the row's entries four per lane at a time, all
+// loads issued before the stores (input and output never overlap).
 __global__ void __launch_bounds__(kBlock) k_compact(const int64_t* __restrict__ beg, const int64_t* __restrict__ end,
                                                     const int32_t* __restrict__ col, const double* __restrict__ val,
                                                     int64_t n, int64_t* rp, const int64_t* __restrict__ blk_pre,
-                                                    int32_t* ocol, double* oval)
+                                                    int32_t* __restrict__ ocol, double* __restrict__ oval)
 {
+    constexpr int kU4 = 4;
     const int64_t r = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
     if (r >= n) return;
     const int64_t b = beg[r], e = end[r], d = blk_pre[r >> 8] + rp[r];
     if (lane() == 0) rp[r] = d;
-    for (int64_t p = b + lane(); p < e; p += kWave) {
-        ocol[d + (p - b)] = col[p];
-        oval[d + (p - b)] = val[p];
+    for (int64_t p0 = b; p0 < e; p0 += kU4 * kWave) {
+        int32_t c[kU4];
+        double v[kU4];
+#pragma unroll
+        for (int u = 0; u < kU4; ++u) {
+            const int64_t p = p0 + u * kWave + lane();
+            if (p < e) {
+                c[u] = col[p];
+                v[u] = val[p];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU4; ++u) {
+            const int64_t p = p0 + u * kWave + lane();
+            if (p < e) {
+                ocol[d + (p - b)] = c[u];
+                oval[d + (p - b)] = v[u];
+            }
+        }
     }
 }
 
