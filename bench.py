@@ -632,7 +632,7 @@ def main():
                    **({"tau": cfg["tau"]} if args.filter == "fixed" else
                       {"eps": args.eps, "e_r": args.e_r} if args.filter == "adaptive" else
                       {"eps_tol": args.eps_tol, "e_r": args.e_r, "N": series_info["N"]}),
-                   "series": "exp", "nnz_F": st["nnz_out"]},
+                   "series": "cos" if "_cos_" in cfg["name"] else "exp", "nnz_F": st["nnz_out"]},
         "roofline": {"bound": "hbm", "achieved": k_achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": k_achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
