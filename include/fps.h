@@ -91,11 +91,11 @@ typedef int32_t fps_status;
                                         with the ordered sparse path to rounding (and entries within
                                         rounding of tau may be kept or dropped differently), not bit for
                                         bit.  Not with FPS_FLAG_DROP_STATS; not for batches */
-#define FPS_FLAG_NO_SMALL 0x80ull    /* keep every row on a 64-lane wavefront.  Without it, a stage whose
-                                        sizing evaluation found every row within 96 structural entries
-                                        and a 3072-column window runs later evaluations four rows per
-                                        wavefront (16 lanes per row), with the same order of operations
-                                        and so the same results bit for bit */
+#define FPS_FLAG_NO_SMALL 0x80ull    /* keep every row on a 64-lane wavefront.  Without it, a stage of more
+                                        than 8192 rows whose sizing evaluation found every row within 96
+                                        structural entries and a 3072-column window runs later
+                                        evaluations four rows per wavefront (16 lanes per row), with the
+                                        same order of operations and so the same results bit for bit */
 
 typedef struct ihipStream_t *fps_stream; /* same type as hipStream_t */
 

@@ -580,7 +580,7 @@ struct Engine {
         const bool small = !sizing && !wide_rows && !a.force_global && !a.has_e && !(flags & FPS_FLAG_NO_SMALL) &&
                            !learned_dense[(size_t)idx] && learned_wide[(size_t)idx] == 0 &&
                            learned_global[(size_t)idx] == 0 &&
-                           small_tier_fits(learned_ns[(size_t)idx], learned_words[(size_t)idx]);
+                           small_tier_fits(n, learned_ns[(size_t)idx], learned_words[(size_t)idx]);
         a.fuse_analysis = (small && a.row_stride > 0 && a.prod_acc == nullptr) ? 1 : 0;
         fused[(size_t)idx] = a.fuse_analysis;
         if (!a.fuse_analysis) HIP_TRY(launch_analyze(a, s));

@@ -251,10 +251,10 @@ hipError_t launch_numeric_lds(const StageArgs& a, int grid, hipStream_t s);
 hipError_t launch_numeric_wide_rows(const StageArgs& a, hipStream_t s);
 // Every row of a stage on a 16-lane DPP row (four rows per wavefront); rows
 // beyond the tier go to the wide tier's list.  small_tier_fits tells
-// whether a stage whose largest structural row and widest window (32-column
-// words) are max_ns and max_words fits the tier.
+// whether a stage of n rows whose largest structural row and widest window
+// (32-column words) are max_ns and max_words should run in the tier.
 hipError_t launch_numeric_small(const StageArgs& a, int64_t max_ns, int64_t max_words, hipStream_t s);
-bool small_tier_fits(int64_t max_ns, int64_t max_words);
+bool small_tier_fits(int64_t n, int64_t max_ns, int64_t max_words);
 // rows of fb_list (persistent blocks: the grid size only sets the parallelism)
 hipError_t launch_numeric_wide(const StageArgs& a, int grid, hipStream_t s);
 // rows of fb2_list

@@ -1721,6 +1721,10 @@ constexpr int kSmallLanes = 16;
 constexpr int kSmallRowsPerWave = kWave / kSmallLanes;
 constexpr int kSmallRowsPerBlock = kBlock / kSmallLanes;
 constexpr int kSmallWords = 96, kSmallCap = 96;
+// The tier pays only when a stage has more rows than the 64-lane kernel holds
+// at once (eight wavefronts per SIMD on 256 CUs): with fewer, both finish in
+// one round and a row's own chain, shorter on 64 lanes, sets the time.
+constexpr int64_t kSmallMinRows = 256 * 4 * 8;
 constexpr int kSmallU = 2;  // terms whose first 32 entries are loaded together
 
 template <int kWords, int kCap>
@@ -2847,7 +2851,10 @@ hipError_t launch_numeric_small(const StageArgs& a, int64_t max_ns, int64_t max_
     return hipGetLastError();
 }
 
-bool small_tier_fits(int64_t max_ns, int64_t max_words) { return max_ns <= kSmallCap && max_words <= kSmallWords; }
+bool small_tier_fits(int64_t n, int64_t max_ns, int64_t max_words)
+{
+    return n > kSmallMinRows && max_ns <= kSmallCap && max_words <= kSmallWords;
+}
 
 hipError_t launch_numeric_wide_rows(const StageArgs& a, hipStream_t s)
 {
