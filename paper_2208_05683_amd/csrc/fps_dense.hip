@@ -95,8 +95,11 @@ __global__ void __launch_bounds__(kB) k_dense_terms(Terms T, int64_t n, int64_t 
 // v_mfma_f64_16x16x4f64 (wave64): lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16] of the 16 x 4 and 4 x 16 operands, and item v of its
 // result holds C[4 v + l / 16][l % 16].
+// Two wavefronts per SIMD for the 128 x 128 tile: its accumulators then live
+// in VGPRs (198 in all) instead of AGPRs next to 194 VGPRs, which left one.
 template <int BM>
-__global__ void __launch_bounds__(kB) k_dgemm_mfma(const double* __restrict__ A, const double* __restrict__ B,
+__global__ void __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(BM == 128 ? 2 : 4, 8)))
+k_dgemm_mfma(const double* __restrict__ A, const double* __restrict__ B,
                                                    double* E, int64_t ld, int64_t n, int has_e, double tau,
                                                    const double* __restrict__ tau_row)
 {
