@@ -446,6 +446,8 @@ def main():
     ap.add_argument("--workload", default="lap2d", help="lap2d (headline), lap1d, lap3d (with --side)")
     ap.add_argument("--side", type=int, default=None, help="lap3d: grid side (default 20)")
     ap.add_argument("--dense", action="store_true", help="FPS_FLAG_DENSE: dense products on the FP64 matrix cores")
+    ap.add_argument("--dense-exact", action="store_true",
+                    help="FPS_FLAG_DENSE_EXACT: filled-in products as sparse rows times dense rows (exact)")
     ap.add_argument("--no-small", action="store_true",
                     help="FPS_FLAG_NO_SMALL: every row on a 64-lane wavefront (no small-row tier)")
     ap.add_argument("--cpu-budget", type=float, default=1.0, help="0 skips the CPU oracle timing")
@@ -523,9 +525,12 @@ def main():
     else:
         plan = api.Plan(Zd, cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"],
                         flags=B.FPS_FLAG_TIMING | (B.FPS_FLAG_DENSE if args.dense else 0)
+                        | (B.FPS_FLAG_DENSE_EXACT if args.dense_exact else 0)
                         | (B.FPS_FLAG_NO_SMALL if args.no_small else 0))
         if args.dense:
             cfg = dict(cfg, name=cfg["name"] + "_dense")
+        elif args.dense_exact:
+            cfg = dict(cfg, name=cfg["name"] + "_dense_exact")
     torch.cuda.synchronize()
     setup_ms = 1e3 * (time.perf_counter() - t_setup)  # plan creation (with the norm estimates of eq. 37)
 
@@ -582,12 +587,12 @@ def main():
                       "max_row": mn, "max_window_words": mw}
     dom = max(stages, key=lambda k: stages[k]["us"]) if stages else None
     dense_ld = st.get("dense_ld", 0)
-    dense_stages = [nm for nm, d in zip(names, st["stage_dense"]) if d]
+    dense_stages = [nm for nm, d in zip(names, st["stage_dense"]) if d == 1]  # on the matrix cores
     # the stages by the kernel that ran them: the small-row tier, the dense
     # path, or the 64-lane shared-memory kernel (with its fallback tiers)
     kernels = {}
     for i, nm in enumerate(names):
-        k = ("k_dgemm_mfma" if st["stage_dense"][i] else
+        k = ("k_dgemm_mfma" if st["stage_dense"][i] == 1 else "k_spmm_rows" if st["stage_dense"][i] == 2 else
              "k_numeric_small" if st["stage_small"][i] else "k_numeric_lds")
         stages[nm]["kernel"] = k
         d = kernels.setdefault(k, {"launches": 0, "us": 0.0, "bytes": 0.0, "stages": []})
@@ -600,7 +605,7 @@ def main():
         d["avg_launch_us"] = round(d["us"] / d["launches"], 2)
         d["GBps"] = round(d["bytes"] / (d["us"] * 1e-6) / 1e9, 1) if d["us"] > 0 else 0.0
         d["frac"] = round(d["GBps"] / HBM_PEAK_GBS, 4)
-    sparse_k = {k: d for k, d in kernels.items() if k != "k_dgemm_mfma"}
+    sparse_k = {k: d for k, d in kernels.items() if k not in ("k_dgemm_mfma", "k_spmm_rows")}
     dom_k = max(sparse_k, key=lambda k: sparse_k[k]["us"]) if sparse_k else "k_numeric_lds"
     dk = kernels.get(dom_k, {"launches": 0, "us": 0.0, "bytes": 0.0})
     k_launches, k_ms, k_bytes = dk["launches"], dk["us"] / 1e3, dk["bytes"]

@@ -91,6 +91,14 @@ typedef int32_t fps_status;
                                         with the ordered sparse path to rounding (and entries within
                                         rounding of tau may be kept or dropped differently), not bit for
                                         bit.  Not with FPS_FLAG_DROP_STATS; not for batches */
+#define FPS_FLAG_DENSE_EXACT 0x200ull /* compute a sparse product as sparse rows times dense rows when its
+                                        modelled time (one dense row of the right operand streamed per
+                                        stored entry of the left) is below the sparse one's and two dense
+                                        n x n operands fit the free device memory; each entry is still the
+                                        fma chain over the left row's entries in order (the added terms are
+                                        exact zeros), so results are the sparse path's bit for bit.
+                                        FPS_FLAG_DENSE also considers this path.  Not with
+                                        FPS_FLAG_DROP_STATS; not for batches */
 #define FPS_FLAG_NO_SMALL 0x80ull    /* keep every row on a 64-lane wavefront.  Without it, a stage of more
                                         than 8192 rows whose sizing evaluation found every row within 96
                                         structural entries and a 3072-column window runs later
@@ -189,7 +197,9 @@ typedef struct {
     int32_t stage_alg1_mode[FPS_MAX_STAGES];
     int64_t stage_rows_skipped[FPS_MAX_STAGES]; /* output rows proven empty by the bound test */
     double stage_bytes[FPS_MAX_STAGES]; /* algorithmic bytes of the stage (see bytes_algorithmic) */
-    int32_t stage_dense[FPS_MAX_STAGES];  /* 1: the product ran on the dense path (FPS_FLAG_DENSE) */
+    int32_t stage_dense[FPS_MAX_STAGES];  /* the product ran on a dense path: 1 the matrix cores
+                                             (FPS_FLAG_DENSE), 2 sparse rows times dense rows
+                                             (FPS_FLAG_DENSE_EXACT or FPS_FLAG_DENSE) */
     int64_t dense_ld;                     /* leading dimension of the dense operands (0 if none ran) */
     int32_t stage_small[FPS_MAX_STAGES];  /* 1: every row of the stage ran in the small-row tier, four rows
                                              per wavefront (see FPS_FLAG_NO_SMALL) */
@@ -475,7 +485,7 @@ typedef struct {
     int64_t hbm_budget;   /* device bytes that the running requests may reserve and the finished,
                              unreleased results may hold, in total (> 0) */
     uint64_t flags;       /* plan flags applied to every request (FPS_FLAG_NO_VALIDATE, FPS_FLAG_NO_SKIP,
-                             FPS_FLAG_DENSE) */
+                             FPS_FLAG_DENSE, FPS_FLAG_DENSE_EXACT) */
     int32_t fake_backend; /* 1: nothing is computed and no device call is made: a worker holds each request
                              for n microseconds and charges 100 n bytes against its reservation (tests of
                              the scheduler without a GPU) */

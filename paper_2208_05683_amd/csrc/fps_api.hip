@@ -292,6 +292,9 @@ constexpr int64_t kColSumMaxN = int64_t(1) << 24;
 enum class Kind { Power = FPS_STAGE_POWER, Block = FPS_STAGE_BLOCK, GStep = FPS_STAGE_GSTEP, Horner = FPS_STAGE_HORNER };
 
 constexpr int kTimingRing = 64;   // sampled evaluations whose kernel times are kept
+// the dense path a product stage takes (fps_stats.stage_dense)
+constexpr int kDenseNone = 0, kDenseMfma = 1, kDenseRows = 2;
+
 constexpr int kTimingEvery = 8;   // every 8th evaluation records events (each record costs a few microseconds)
 
 struct StageRecord {
@@ -307,7 +310,7 @@ struct StageRecord {
     int alg1_mode = 0;         // fps_stats.stage_alg1_mode
     bool wide_rows = false;    // every row of the stage ran in the wide shared-memory tier
     bool small = false;        // every row of the stage ran in the small-row tier (four rows per wavefront)
-    bool dense = false;        // the product ran on the dense path
+    int dense = 0;             // the dense path the product ran on (kDenseNone, kDenseMfma, kDenseRows)
 };
 
 struct Schedule {
@@ -379,8 +382,9 @@ struct Engine {
     std::vector<int64_t> learned_global;  // per stage: rows a sizing run sent to the device-memory kernel
     std::vector<int> alg1_learned;  // per stage: Algorithm 1 iterations of the last host-driven run
     std::vector<double> alg1_learned_t;  // ... and its final threshold
-    // dense path (FPS_FLAG_DENSE): per stage the decision of the sizing run;
-    // three dense ld x ld operands; which left operand dA holds (its column
+    // dense paths (FPS_FLAG_DENSE, FPS_FLAG_DENSE_EXACT): per stage the decision
+    // of the sizing run (kDenseNone, kDenseMfma, kDenseRows); three dense
+    // ld x ld operands; which left operand dA holds (its column
     // array) and for which evaluation (P_q is the left operand of every
     // Horner step of an evaluation, densified once)
     std::vector<int> learned_dense;
@@ -403,7 +407,8 @@ struct Engine {
         std::vector<unsigned long long> h((size_t)(kPartCount * ws.part_stride));
         HIP_TRY(hipMemcpy(h.data(), part(i), sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
         for (int k = 0; k < kPartCount; ++k) {
-            const bool per_row_block = k == kPartKept || k == kPartMaxNs || k == kPartMaxWords || fused[(size_t)i];
+            const bool per_row_block = k == kPartKept || k == kPartMaxNs || k == kPartMaxWords ||
+                                       (fused[(size_t)i] && k <= kPartRowsSkipped);
             const bool maximum = k == kPartMaxNs || k == kPartMaxWords;
             const int64_t cnt = per_row_block ? nk : na;
             unsigned long long t = 0;
@@ -468,50 +473,77 @@ struct Engine {
     // device-memory kernel for rows beyond 512 entries on average); dense:
     // 2 ld^3 flops at 4e13 per second on the matrix cores, five passes over
     // ld^2 doubles at 3 TB/s (fills, densify, write-out) and 20 us of launches.
-    bool want_dense(int idx, int64_t bound_total, hipStream_t s)
+    // The path of a product stage by modelled time: sparse = the analysis'
+    // multiply-adds at the rate of the row kernel its rows take (2.5e11/s in
+    // shared memory, 5e10/s in the device-memory kernel, measured); matrix
+    // cores = 2 ld^3 at 4e13 flop/s plus five passes over ld^2 doubles;
+    // dense rows = one row of B (ld doubles) streamed per stored entry of A at
+    // 4 TB/s plus four passes.  The matrix cores only with FPS_FLAG_DENSE,
+    // the dense rows with either flag; both need their operands' memory.
+    int want_dense(int idx, int64_t bound_total, hipStream_t s)
     {
-        unsigned long long prods = 0;
+        unsigned long long prods = 0, a_nnz = 0;
         {
             const int64_t na = analyze_blocks(kModeProduct, ws.n);
-            std::vector<unsigned long long> h((size_t)na);
-            if (hipMemcpyAsync(h.data(), part(idx) + (size_t)kPartProducts * (size_t)ws.part_stride,
-                               sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            std::vector<unsigned long long> h((size_t)(kPartCount * ws.part_stride));
+            if (hipMemcpyAsync(h.data(), part(idx), sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
+                               s) != hipSuccess ||
                 hipStreamSynchronize(s) != hipSuccess) {
                 (void)hipGetLastError();
-                return false;
+                return kDenseNone;
             }
-            for (auto v : h) prods += v;
+            for (int64_t b = 0; b < na; ++b) {
+                prods += h[(size_t)(kPartProducts * ws.part_stride + b)];
+                a_nnz += h[(size_t)(kPartANnz * ws.part_stride + b)];
+            }
         }
         const double ld = (double)dense_ld(ws.n);
         const double per_row = (double)bound_total / (double)std::max<int64_t>(ws.n, 1);
         const double t_sparse = (double)prods / (per_row > 512.0 ? 5e10 : 2.5e11);
-        const double t_dense = 2.0 * ld * ld * ld / 4e13 + 5.0 * ld * ld * 8.0 / 3e12 + 20e-6;
-        if (t_dense >= t_sparse) return false;
-        const double need = 3.0 * ld * ld * 8.0 - (double)(dA.bytes + dB.bytes + dE.bytes);
+        const double t_mfma = (flags & FPS_FLAG_DENSE) ? 2.0 * ld * ld * ld / 4e13 + 5.0 * ld * ld * 8.0 / 3e12 + 20e-6
+                                                        : HUGE_VAL;
+        const double t_rows = (double)a_nnz * ld * 8.0 / 4e12 + 4.0 * ld * ld * 8.0 / 3e12 + 20e-6;
+        const int mode = (t_rows < t_mfma) ? kDenseRows : kDenseMfma;
+        if (std::min(t_rows, t_mfma) >= t_sparse) return kDenseNone;
+        // operands: B and E, and A for the matrix cores
+        const double ops = mode == kDenseMfma ? 3.0 : 2.0;
+        const double need = ops * ld * ld * 8.0 - (double)(dA.bytes + dB.bytes + dE.bytes);
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
             (void)hipGetLastError();
-            return false;
+            return kDenseNone;
         }
-        if (need > 0.9 * (double)fr) return false;
-        if (t_acct && t_acct->used + (size_t)std::max(0.0, need) > t_acct->cap) return false;
-        return true;
+        if (need > 0.9 * (double)fr) return kDenseNone;
+        if (t_acct && t_acct->used + (size_t)std::max(0.0, need) > t_acct->cap) return kDenseNone;
+        return mode;
     }
 
     // The product of stage `a` on the dense path into `out` (see
     // launch_dgemm_mfma): operands densified, Bhat formed densely, the
     // product with the block and the filter in its write-out, rows written
     // back as slack CSR.
-    fps_status run_dense(StageArgs& a, hipStream_t s)
+    fps_status run_dense(StageArgs& a, int mode, hipStream_t s)
     {
         const int64_t n = ws.n, ld = dense_ld(n);
         const size_t bytes = sizeof(double) * (size_t)ld * (size_t)ld;
-        FPS_TRY(dA.ensure(bytes));
         FPS_TRY(dB.ensure(bytes));
         FPS_TRY(dE.ensure(bytes));
         if (ld != d_ld) dA_key = nullptr;
         d_ld = ld;
         const int64_t count = (int64_t)(bytes / 8);
+        if (mode == kDenseRows) {
+            // A stays sparse: its rows stream B's dense rows in term order
+            HIP_TRY(launch_fill_u64(dB.as<unsigned long long>(), count, 0ull, s));
+            HIP_TRY(launch_densify(a.B, n, ld, dB.as<double>(), s));
+            if (a.has_blk) {
+                HIP_TRY(launch_fill_u64(dE.as<unsigned long long>(), count, 0ull, s));
+                HIP_TRY(launch_dense_terms(a.T, n, ld, dE.as<double>(), s));
+            }
+            HIP_TRY(launch_spmm_rows(a.A, dB.as<double>(), dE.as<double>(), ld, n, a.has_blk, a.tau, a.tau_row, s));
+            HIP_TRY(launch_dense_to_slack(dE.as<double>(), ld, a, s));
+            return FPS_OK;
+        }
+        FPS_TRY(dA.ensure(bytes));
         if (!(dA_key == a.A.col && dA_eval == eval_id)) {
             HIP_TRY(launch_fill_u64(dA.as<unsigned long long>(), count, 0ull, s));
             HIP_TRY(launch_densify(a.A, n, ld, dA.as<double>(), s));
@@ -601,17 +633,18 @@ struct Engine {
             run_wide = learned_wide[(size_t)idx] > 0 && !a.force_global;
             run_global = learned_global[(size_t)idx] > 0 || a.force_global;
         }
-        // the dense path for a product stage whose work has gone dense
-        bool dense = false;
-        if (a.mode == kModeProduct && !a.has_e && (flags & FPS_FLAG_DENSE) && a.dsum == nullptr) {
-            if (sizing) learned_dense[(size_t)idx] = want_dense(idx, learned[(size_t)idx], s) ? 1 : 0;
-            dense = learned_dense[(size_t)idx] != 0;
+        // a dense path for a product stage whose work has gone dense
+        int dense = kDenseNone;
+        if (a.mode == kModeProduct && !a.has_e && (flags & (FPS_FLAG_DENSE | FPS_FLAG_DENSE_EXACT)) &&
+            a.dsum == nullptr) {
+            if (sizing) learned_dense[(size_t)idx] = want_dense(idx, learned[(size_t)idx], s);
+            dense = learned_dense[(size_t)idx];
         }
         if (rec) rec->dense = dense;
-        if (dense) {
+        if (dense != kDenseNone) {
             a.out = out.out();
             if (rec && rec->ev0) HIP_TRY(hipEventRecord(rec->ev0, s));
-            FPS_TRY(run_dense(a, s));
+            FPS_TRY(run_dense(a, dense, s));
             if (rec && rec->ev1) HIP_TRY(hipEventRecord(rec->ev1, s));
             if (sizing) {
                 unsigned long long tot[kPartCount];
@@ -1200,7 +1233,7 @@ struct fps_plan_s {
             r->alg1_mode = 0;
             r->wide_rows = false;
             r->small = false;
-            r->dense = false;
+            r->dense = 0;
             r->ev0 = r->ev1 = nullptr;
             if (timing_now) {
                 r->ev0 = ring[(slot * (size_t)nst + (size_t)n_stages) * 2];
@@ -1570,7 +1603,7 @@ fps_status fps_get_stats(fps_plan p, fps_stats* st)
         st->stage_dropped[i] = r.dropped;
         st->stage_alg1_iters[i] = r.alg1_iters;
         st->stage_alg1_mode[i] = r.alg1_mode;
-        st->stage_dense[i] = r.dense ? 1 : 0;
+        st->stage_dense[i] = r.dense;
         st->stage_small[i] = r.small ? 1 : 0;
         st->stage_max_ns[i] = p->eng.learned_ns[(size_t)i];
         st->stage_max_words[i] = p->eng.learned_words[(size_t)i];
@@ -2643,7 +2676,7 @@ fps_status fps_server_create(fps_server* out, const fps_server_opts* opts)
     if (opts->slots < 1 || opts->slots > 64) return set_error(FPS_ERR_INVALID_ARG, "slots must be in [1, 64]");
     if (opts->hbm_budget <= 0) return set_error(FPS_ERR_INVALID_ARG, "hbm_budget must be > 0");
     if (opts->max_queue < 0) return set_error(FPS_ERR_INVALID_ARG, "max_queue must be >= 0");
-    if (opts->flags & ~(uint64_t)(FPS_FLAG_NO_VALIDATE | FPS_FLAG_NO_SKIP | FPS_FLAG_DENSE))
+    if (opts->flags & ~(uint64_t)(FPS_FLAG_NO_VALIDATE | FPS_FLAG_NO_SKIP | FPS_FLAG_DENSE | FPS_FLAG_DENSE_EXACT))
         return set_error(FPS_ERR_INVALID_ARG, "unsupported server flags");
     std::unique_ptr<fps_server_s> sv(new (std::nothrow) fps_server_s());
     if (!sv) return set_error(FPS_ERR_OUT_OF_MEMORY, "host allocation failed");

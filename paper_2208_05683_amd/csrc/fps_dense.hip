@@ -188,6 +188,50 @@ k_dgemm_mfma(const double* __restrict__ A, const double* __restrict__ B,
             }
 }
 
+// ---- sparse rows times dense rows -------------------------------------------------
+// C = D_tau(E + A B) with A sparse (row-range CSR, rows < n) and B dense (ld
+// columns).  Each output entry is the fma chain over row r's stored entries
+// of A in column order from +0, as in the sparse kernels.  Where B[k][c] is
+// zero (no stored entry) the fma adds an exact zero, which leaves the sum
+// unchanged (+0 stays +0: the sum is never -0, a stored product being
+// nonzero), so every entry the sparse path keeps has the same bits here,
+// and every column it never forms is 0 here and dropped.  One block per
+// (row, chunk of kRowsCols columns), kRowsPer columns per thread.
+constexpr int kRowsPer = 8;
+constexpr int kRowsCols = kB * kRowsPer;
+
+__global__ void __launch_bounds__(kB) k_spmm_rows(MatView A, const double* __restrict__ B, double* E, int64_t ld,
+                                                  int64_t n, int has_e, double tau, const double* __restrict__ tau_row)
+{
+    const int64_t r = blockIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.y * kRowsCols + threadIdx.x;
+    double acc[kRowsPer];
+#pragma unroll
+    for (int j = 0; j < kRowsPer; ++j) acc[j] = 0.0;
+    const int64_t pb = A.beg[r], pe = A.end[r];
+    for (int64_t p = pb; p < pe; ++p) {
+        const int64_t k = A.col[p];
+        const double a = A.val[p];
+        const double* bk = B + k * ld;
+#pragma unroll
+        for (int j = 0; j < kRowsPer; ++j) {
+            const int64_t c = c0 + (int64_t)j * kB;
+            if (c < n) acc[j] = fma(a, bk[c], acc[j]);
+        }
+    }
+    double* er = E + r * ld;
+    const double tr = tau_row ? tau_row[r] : tau;
+#pragma unroll
+    for (int j = 0; j < kRowsPer; ++j) {
+        const int64_t c = c0 + (int64_t)j * kB;
+        if (c < n) {
+            double x = acc[j];
+            if (has_e) x = er[c] + x;  // x = extra + main, one addition
+            er[c] = (x != 0.0 && !(fabs(x) < tr)) ? x : 0.0;
+        }
+    }
+}
+
 // ---- back to slack-CSR rows -----------------------------------------------------
 
 // Row r of the dense result C as a stage output row: placed as the numeric
@@ -305,6 +349,15 @@ hipError_t launch_dgemm_mfma(const double* A, const double* B, double* E, int64_
         hipLaunchKernelGGL(k_dgemm_mfma<64>, dim3((unsigned)t64, (unsigned)t64), dim3(kB), 0, s, A, B, E, ld, n, has_e,
                            tau, tau_row);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_spmm_rows(const MatView& A, const double* B, double* E, int64_t ld, int64_t n, int has_e, double tau,
+                            const double* tau_row, hipStream_t s)
+{
+    const int64_t chunks = (n + kRowsCols - 1) / kRowsCols;
+    hipLaunchKernelGGL(k_spmm_rows, dim3((unsigned)n, (unsigned)chunks), dim3(kB), 0, s, A, B, E, ld, n, has_e, tau,
+                       tau_row);
     return hipGetLastError();
 }
 

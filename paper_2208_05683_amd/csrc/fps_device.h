@@ -103,7 +103,9 @@ struct Alg1Params {
 // Per-stage partial sums, one entry per block, layout [kPartCount][part_stride]:
 // kPartMaxNs holds the largest structural row of the block and kPartMaxWords
 // the widest window of its rows in 32-column words (maxima, not sums; the
-// window width is written by the shared-memory tiers only).
+// window width is written by the shared-memory tiers only).  kPartANnz is the
+// product analysis' count of the left operand's stored entries in the block's
+// rows (the dense-rows cost model reads it).
 enum PartIndex : int {
     kPartProducts = 0,
     kPartProductsSkipped = 1,
@@ -111,7 +113,8 @@ enum PartIndex : int {
     kPartKept = 3,
     kPartMaxNs = 4,
     kPartMaxWords = 5,
-    kPartCount = 6
+    kPartANnz = 6,
+    kPartCount = 7
 };
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 
@@ -230,6 +233,10 @@ hipError_t launch_dense_terms(const Terms& T, int64_t n, int64_t ld, double* E, 
 // E = D_tau((has_e ? E : 0) + A B) on the matrix cores (tau per row if tau_row)
 hipError_t launch_dgemm_mfma(const double* A, const double* B, double* E, int64_t ld, int64_t n, int has_e, double tau,
                              const double* tau_row, hipStream_t s);
+// E = D_tau((has_e ? E : 0) + A B) with A sparse and B dense, each entry the
+// fma chain over A's row in order (the sparse path's bits)
+hipError_t launch_spmm_rows(const MatView& A, const double* B, double* E, int64_t ld, int64_t n, int has_e, double tau,
+                            const double* tau_row, hipStream_t s);
 // rows of the dense C written as the stage output a.out (placement, summaries,
 // structure words, partial sums as the numeric kernels)
 hipError_t launch_dense_to_slack(const double* C, int64_t ld, const StageArgs& a, hipStream_t s);

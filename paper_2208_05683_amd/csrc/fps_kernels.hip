@@ -473,19 +473,20 @@ static_assert(kBlock / kAnalyzeLanes == (1 << kAnalyzeShiftProduct) && kBlock ==
 __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
 {
     constexpr int G = kAnalyzeLanes;
-    __shared__ unsigned long long sh[3][kBlock / G];
+    __shared__ unsigned long long sh[4][kBlock / G];
     __shared__ int64_t ubs[kBlock / G];
     __shared__ int64_t blk_total;
     const int64_t blk = xcd_logical_block();
     const int64_t r = (blk * kBlock + threadIdx.x) / G;
     const int gl = threadIdx.x % G;
     const int grp = threadIdx.x / G;
-    unsigned long long prod_done = 0, prod_skip = 0, row_skip = 0;
+    unsigned long long prod_done = 0, prod_skip = 0, row_skip = 0, a_nnz = 0;
     if (r < P.n) {
         int32_t lo = INT_MAX, hi = -1;
         int64_t prod = 0;
         double bnd = 0.0;
         const int64_t pb = P.A.beg[r], pe = P.A.end[r];
+        a_nnz = (unsigned long long)(pe - pb);
 #pragma unroll 4
         for (int64_t p = pb + gl; p < pe; p += G) {
             // an empty row adds nothing (len 0, amax 0); every field is
@@ -565,13 +566,15 @@ __global__ void __launch_bounds__(kBlock) k_analyze_product(StageArgs P)
         sh[0][grp] = prod_done;
         sh[1][grp] = prod_skip;
         sh[2][grp] = row_skip;
+        sh[3][grp] = a_nnz;
         if (r >= P.n) ubs[grp] = 0;
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < 4) {
         unsigned long long t = 0;
         for (int i = 0; i < kBlock / G; ++i) t += sh[threadIdx.x][i];
-        P.part[threadIdx.x * P.part_stride + blk] = t;  // kPartProducts, kPartProductsSkipped, kPartRowsSkipped
+        // kPartProducts, kPartProductsSkipped, kPartRowsSkipped, then kPartANnz
+        P.part[(threadIdx.x < 3 ? threadIdx.x : kPartANnz) * P.part_stride + blk] = t;
     }
     if (threadIdx.x == kBlock - 1) {  // offsets of the block's rows within the block
         int64_t run = 0;
@@ -632,6 +635,7 @@ __global__ void __launch_bounds__(kBlock) k_analyze_sum(StageArgs P)
         P.part[kPartProducts * P.part_stride + blk] = t;
         P.part[kPartProductsSkipped * P.part_stride + blk] = 0;
         P.part[kPartRowsSkipped * P.part_stride + blk] = 0;
+        P.part[kPartANnz * P.part_stride + blk] = 0;
     }
     int64_t total = 0;
     const int64_t inc = block_incl_scan(ubv, osh, &total);

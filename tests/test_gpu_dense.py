@@ -1,9 +1,12 @@
-"""The dense path (FPS_FLAG_DENSE): products whose work has gone dense run
+"""The dense paths.  FPS_FLAG_DENSE: products whose work has gone dense run
 as FP64 matrix-core products with the block added and the filter applied in
 their write-out.  The sums run in the matrix cores' order, so results are
 compared with the oracle within the relative Frobenius tolerance 1e-10 (not
 bit for bit), and the eq. 23 bound must still hold; repeated evaluations of
-one plan are bit-identical to each other."""
+one plan are bit-identical to each other.  FPS_FLAG_DENSE_EXACT: products
+whose right operand's rows have filled in run as sparse rows times dense
+rows, each entry the sparse path's fma chain, so results are compared with
+the oracle bit for bit."""
 
 import numpy as np
 import pytest
@@ -95,3 +98,74 @@ def test_banded_series_mode_dense_within_tolerance(bw, fn):
             assert rel_fro_csr(got, want) <= REL_TOL
     finally:
         plan.close()
+
+
+# ---------------------------------------------------------------------------
+# sparse rows times dense rows (FPS_FLAG_DENSE_EXACT): exact, bit for bit
+# ---------------------------------------------------------------------------
+
+def _rows_plan_evals(Z, c, m, s, tau, evals=2):
+    from paper_2208_05683_amd import api, binding as B
+
+    plan = api.Plan(upload(Z), c, m, s, tau, B.FPS_FLAG_DENSE_EXACT)
+    try:
+        outs = []
+        for _ in range(evals):
+            plan.eval()
+            outs.append(download(plan.result()))
+        return outs, plan.stats()
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("side", [12, 14])
+def test_lap3d_dense_rows_bitwise(side):
+    # the powers whose rows have filled in run as Z times dense rows of
+    # P_j: every entry is the sparse path's fma chain (plus exact zeros)
+    from gpu_helpers import assert_same_csr
+
+    cfg = G.config3(side=side)
+    Z, c, m, s, tau = cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"]
+    want, _ = O.filtered_ps(Z, c, m, s, tau)
+    outs, gst = _rows_plan_evals(Z, c, m, s, tau)
+    assert 2 in gst["stage_dense"] and 1 not in gst["stage_dense"], gst["stage_dense"]
+    for i, got in enumerate(outs):
+        check_canonical(got, tau)
+        assert_same_csr(got, want, f"3d {side}^3 dense rows, evaluation {i}")
+
+
+def test_dense_rows_horner_with_block_bitwise():
+    # q = 2: P_2 stays sparse while S fills in, so the Horner steps (with
+    # their fused coefficient blocks) run as P_2 times dense rows of S
+    from gpu_helpers import assert_same_csr
+
+    cfg = G.config3(side=12)
+    Z, c, m, s, tau = cfg["Z"], G.cos_coeffs(12), 12, 2, 1e-12
+    want, _ = O.filtered_ps(Z, c, m, s, tau)
+    outs, gst = _rows_plan_evals(Z, c, m, s, tau)
+    horner = [d for d, k in zip(gst["stage_dense"], gst["kind"]) if k == 3]
+    assert 2 in horner, (gst["stage_dense"], gst["kind"])
+    for i, got in enumerate(outs):
+        check_canonical(got, tau)
+        assert_same_csr(got, want, f"q = 2 dense rows, evaluation {i}")
+
+
+def test_lap3d_side20_dense_rows_against_stored_digest():
+    # n = 8000 with the dense-rows path: the oracle's digest, bit for bit
+    import hashlib
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "lap3d_side20_cos_m24_s5.json")
+    with open(path) as f:
+        ref = json.load(f)
+    cfg = G.config3(side=20)
+    Z, c, m, s, tau = cfg["Z"], cfg["coeffs"], cfg["m"], cfg["s"], cfg["tau"]
+    (got,), gst = _rows_plan_evals(Z, c, m, s, tau, evals=1)
+    assert 2 in gst["stage_dense"], gst["stage_dense"]
+    assert got.nnz == ref["nnz"]
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(got.row_ptr, dtype="<i8").tobytes())
+    h.update(np.ascontiguousarray(got.col, dtype="<i4").tobytes())
+    h.update(np.ascontiguousarray(got.val, dtype="<f8").tobytes())
+    assert h.hexdigest() == ref["sha256"]
