@@ -447,7 +447,7 @@ def main():
     ap.add_argument("--side", type=int, default=None, help="lap3d: grid side (default 20)")
     ap.add_argument("--dense", action="store_true", help="FPS_FLAG_DENSE: dense products on the FP64 matrix cores")
     ap.add_argument("--dense-exact", action="store_true",
-                    help="FPS_FLAG_DENSE_EXACT: filled-in products as sparse rows times dense rows (exact)")
+                    help="FPS_FLAG_DENSE_EXACT: filled-in products on the exact dense paths (bitwise)")
     ap.add_argument("--no-small", action="store_true",
                     help="FPS_FLAG_NO_SMALL: every row on a 64-lane wavefront (no small-row tier)")
     ap.add_argument("--cpu-budget", type=float, default=1.0, help="0 skips the CPU oracle timing")
@@ -592,8 +592,8 @@ def main():
     # path, or the 64-lane shared-memory kernel (with its fallback tiers)
     kernels = {}
     for i, nm in enumerate(names):
-        k = ("k_dgemm_mfma" if st["stage_dense"][i] == 1 else "k_spmm_rows" if st["stage_dense"][i] == 2 else
-             "k_numeric_small" if st["stage_small"][i] else "k_numeric_lds")
+        k = {1: "k_dgemm_mfma", 2: "k_spmm_rows", 3: "k_dgemm_ordered"}.get(
+            st["stage_dense"][i], "k_numeric_small" if st["stage_small"][i] else "k_numeric_lds")
         stages[nm]["kernel"] = k
         d = kernels.setdefault(k, {"launches": 0, "us": 0.0, "bytes": 0.0, "stages": []})
         d["launches"] += 1
@@ -605,7 +605,7 @@ def main():
         d["avg_launch_us"] = round(d["us"] / d["launches"], 2)
         d["GBps"] = round(d["bytes"] / (d["us"] * 1e-6) / 1e9, 1) if d["us"] > 0 else 0.0
         d["frac"] = round(d["GBps"] / HBM_PEAK_GBS, 4)
-    sparse_k = {k: d for k, d in kernels.items() if k not in ("k_dgemm_mfma", "k_spmm_rows")}
+    sparse_k = {k: d for k, d in kernels.items() if k not in ("k_dgemm_mfma", "k_spmm_rows", "k_dgemm_ordered")}
     dom_k = max(sparse_k, key=lambda k: sparse_k[k]["us"]) if sparse_k else "k_numeric_lds"
     dk = kernels.get(dom_k, {"launches": 0, "us": 0.0, "bytes": 0.0})
     k_launches, k_ms, k_bytes = dk["launches"], dk["us"] / 1e3, dk["bytes"]

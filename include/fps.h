@@ -91,14 +91,16 @@ typedef int32_t fps_status;
                                         with the ordered sparse path to rounding (and entries within
                                         rounding of tau may be kept or dropped differently), not bit for
                                         bit.  Not with FPS_FLAG_DROP_STATS; not for batches */
-#define FPS_FLAG_DENSE_EXACT 0x200ull /* compute a sparse product as sparse rows times dense rows when its
-                                        modelled time (one dense row of the right operand streamed per
-                                        stored entry of the left) is below the sparse one's and two dense
-                                        n x n operands fit the free device memory; each entry is still the
-                                        fma chain over the left row's entries in order (the added terms are
-                                        exact zeros), so results are the sparse path's bit for bit.
-                                        FPS_FLAG_DENSE also considers this path.  Not with
-                                        FPS_FLAG_DROP_STATS; not for batches */
+#define FPS_FLAG_DENSE_EXACT 0x200ull /* dense paths that keep the sparse path's order of operations: a
+                                        product whose work has gone dense runs as sparse rows times dense
+                                        rows (one dense row of the right operand streamed per stored entry
+                                        of the left) or as a dense product on the vector units with every
+                                        entry's sum taken over k in order, whichever modelled time is
+                                        lowest, when it is below the sparse one's and the dense operands
+                                        fit the free device memory.  Each entry is the fma chain over the
+                                        left row's entries in order with exact zeros added, so results are
+                                        the sparse path's bit for bit.  FPS_FLAG_DENSE also considers
+                                        these paths.  Not with FPS_FLAG_DROP_STATS; not for batches */
 #define FPS_FLAG_NO_SMALL 0x80ull    /* keep every row on a 64-lane wavefront.  Without it, a stage of more
                                         than 8192 rows whose sizing evaluation found every row within 96
                                         structural entries and a 3072-column window runs later
@@ -198,8 +200,9 @@ typedef struct {
     int64_t stage_rows_skipped[FPS_MAX_STAGES]; /* output rows proven empty by the bound test */
     double stage_bytes[FPS_MAX_STAGES]; /* algorithmic bytes of the stage (see bytes_algorithmic) */
     int32_t stage_dense[FPS_MAX_STAGES];  /* the product ran on a dense path: 1 the matrix cores
-                                             (FPS_FLAG_DENSE), 2 sparse rows times dense rows
-                                             (FPS_FLAG_DENSE_EXACT or FPS_FLAG_DENSE) */
+                                             (FPS_FLAG_DENSE), 2 sparse rows times dense rows, 3 the
+                                             ordered dense product on the vector units (2 and 3 exact:
+                                             FPS_FLAG_DENSE_EXACT or FPS_FLAG_DENSE) */
     int64_t dense_ld;                     /* leading dimension of the dense operands (0 if none ran) */
     int32_t stage_small[FPS_MAX_STAGES];  /* 1: every row of the stage ran in the small-row tier, four rows
                                              per wavefront (see FPS_FLAG_NO_SMALL) */

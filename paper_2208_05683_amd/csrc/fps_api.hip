@@ -293,7 +293,7 @@ enum class Kind { Power = FPS_STAGE_POWER, Block = FPS_STAGE_BLOCK, GStep = FPS_
 
 constexpr int kTimingRing = 64;   // sampled evaluations whose kernel times are kept
 // the dense path a product stage takes (fps_stats.stage_dense)
-constexpr int kDenseNone = 0, kDenseMfma = 1, kDenseRows = 2;
+constexpr int kDenseNone = 0, kDenseMfma = 1, kDenseRows = 2, kDenseOrdered = 3;
 
 constexpr int kTimingEvery = 8;   // every 8th evaluation records events (each record costs a few microseconds)
 
@@ -383,7 +383,7 @@ struct Engine {
     std::vector<int> alg1_learned;  // per stage: Algorithm 1 iterations of the last host-driven run
     std::vector<double> alg1_learned_t;  // ... and its final threshold
     // dense paths (FPS_FLAG_DENSE, FPS_FLAG_DENSE_EXACT): per stage the decision
-    // of the sizing run (kDenseNone, kDenseMfma, kDenseRows); three dense
+    // of the sizing run (kDenseNone, kDenseMfma, kDenseRows, kDenseOrdered); three dense
     // ld x ld operands; which left operand dA holds (its column
     // array) and for which evaluation (P_q is the left operand of every
     // Horner step of an evaluation, densified once)
@@ -476,10 +476,12 @@ struct Engine {
     // The path of a product stage by modelled time: sparse = the analysis'
     // multiply-adds at the rate of the row kernel its rows take (2.5e11/s in
     // shared memory, 5e10/s in the device-memory kernel, measured); matrix
-    // cores = 2 ld^3 at 4e13 flop/s plus five passes over ld^2 doubles;
-    // dense rows = one row of B (ld doubles) streamed per stored entry of A at
-    // 4 TB/s plus four passes.  The matrix cores only with FPS_FLAG_DENSE,
-    // the dense rows with either flag; both need their operands' memory.
+    // cores = 2 ld^3 at 4e13 flop/s plus five passes over ld^2 doubles; the
+    // ordered product on the vector units = 2 ld^3 at 3e13 flop/s plus five
+    // passes; dense rows = one row of B (ld doubles) streamed per stored entry
+    // of A at 4 TB/s plus four passes.  The matrix cores only with
+    // FPS_FLAG_DENSE, the two exact paths with either flag; each needs its
+    // operands' memory.
     int want_dense(int idx, int64_t bound_total, hipStream_t s)
     {
         unsigned long long prods = 0, a_nnz = 0;
@@ -503,10 +505,20 @@ struct Engine {
         const double t_mfma = (flags & FPS_FLAG_DENSE) ? 2.0 * ld * ld * ld / 4e13 + 5.0 * ld * ld * 8.0 / 3e12 + 20e-6
                                                         : HUGE_VAL;
         const double t_rows = (double)a_nnz * ld * 8.0 / 4e12 + 4.0 * ld * ld * 8.0 / 3e12 + 20e-6;
-        const int mode = (t_rows < t_mfma) ? kDenseRows : kDenseMfma;
-        if (std::min(t_rows, t_mfma) >= t_sparse) return kDenseNone;
-        // operands: B and E, and A for the matrix cores
-        const double ops = mode == kDenseMfma ? 3.0 : 2.0;
+        const double t_ordered = 2.0 * ld * ld * ld / 3e13 + 5.0 * ld * ld * 8.0 / 3e12 + 20e-6;
+        int mode = kDenseMfma;
+        double t_best = t_mfma;
+        if (t_ordered < t_best) {
+            mode = kDenseOrdered;
+            t_best = t_ordered;
+        }
+        if (t_rows < t_best) {
+            mode = kDenseRows;
+            t_best = t_rows;
+        }
+        if (t_best >= t_sparse) return kDenseNone;
+        // operands: B and E, and A densified for the dense products
+        const double ops = mode == kDenseRows ? 2.0 : 3.0;
         const double need = ops * ld * ld * 8.0 - (double)(dA.bytes + dB.bytes + dE.bytes);
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
@@ -556,8 +568,12 @@ struct Engine {
             HIP_TRY(launch_fill_u64(dE.as<unsigned long long>(), count, 0ull, s));
             HIP_TRY(launch_dense_terms(a.T, n, ld, dE.as<double>(), s));
         }
-        HIP_TRY(launch_dgemm_mfma(dA.as<double>(), dB.as<double>(), dE.as<double>(), ld, n, a.has_blk, a.tau,
-                                  a.tau_row, s));
+        if (mode == kDenseOrdered)
+            HIP_TRY(launch_dgemm_ordered(dA.as<double>(), dB.as<double>(), dE.as<double>(), ld, n, a.has_blk, a.tau,
+                                         a.tau_row, s));
+        else
+            HIP_TRY(launch_dgemm_mfma(dA.as<double>(), dB.as<double>(), dE.as<double>(), ld, n, a.has_blk, a.tau,
+                                      a.tau_row, s));
         HIP_TRY(launch_dense_to_slack(dE.as<double>(), ld, a, s));
         return FPS_OK;
     }

@@ -188,6 +188,100 @@ k_dgemm_mfma(const double* __restrict__ A, const double* __restrict__ B,
             }
 }
 
+// ---- the dense product in k order on the vector units ---------------------------------
+// C = D_tau(E + A B) with every entry's sum taken over k = 0, 1, ..., ld - 1
+// in order, one fma per k from +0: the sparse path's fma chain over the
+// stored entries of A's row (ascending columns) with exact zeros added for
+// the others, so the sparse result bit for bit (as in k_spmm_rows below).
+// FP64 fma on the vector units has the matrix cores' FP64 peak on this chip.
+// Block tile 128 x 128, 256 threads as 16 x 16; thread (ty, tx) owns rows
+// ty + 16 i and columns tx + 16 j (i, j < 8), so that a wavefront's reads
+// of a k row of A are four broadcasts and of B sixteen consecutive doubles;
+// k in chunks of 16 staged in shared memory (A k-major), the next chunk's
+// global loads in flight during the current chunk's fmas.
+constexpr int kOT = 128, kOK = 16, kOR = 8;
+
+__global__ void __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_dgemm_ordered(const double* __restrict__ A, const double* __restrict__ B, double* E, int64_t ld, int64_t n,
+                int has_e, double tau, const double* __restrict__ tau_row)
+{
+    __shared__ double As[kOK][kOT];
+    __shared__ double Bs[kOK][kOT];
+    const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
+    const int64_t row0 = (int64_t)blockIdx.y * kOT, col0 = (int64_t)blockIdx.x * kOT;
+    double acc[kOR][kOR];
+#pragma unroll
+    for (int i = 0; i < kOR; ++i)
+#pragma unroll
+        for (int j = 0; j < kOR; ++j) acc[i][j] = 0.0;
+    // a chunk: A rows row0 + (t >> 1), k (t & 1) * 8 .. + 7; B k row t >> 4, columns (t & 15) * 8 .. + 7
+    const int ar = t >> 1, ak = (t & 1) * 8;
+    const int bk = t >> 4, bc = (t & 15) * 8;
+    const double* pa = A + (row0 + ar) * ld + ak;
+    const double* pb = B + (int64_t)bk * ld + col0 + bc;
+    double ra[8], rb[8];
+#pragma unroll
+    for (int i = 0; i < 8; i += 2) {
+        const double2 x = *reinterpret_cast<const double2*>(pa + i);
+        const double2 y = *reinterpret_cast<const double2*>(pb + i);
+        ra[i] = x.x;
+        ra[i + 1] = x.y;
+        rb[i] = y.x;
+        rb[i + 1] = y.y;
+    }
+    for (int64_t k0 = 0; k0 < ld; k0 += kOK) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            As[ak + i][ar] = ra[i];
+            Bs[bk][bc + i] = rb[i];
+        }
+        __syncthreads();
+        if (k0 + kOK < ld) {  // the next chunk's loads overlap this chunk's fmas
+            const double* na = pa + (k0 + kOK);
+            const double* nb = pb + (k0 + kOK) * ld;
+#pragma unroll
+            for (int i = 0; i < 8; i += 2) {
+                const double2 x = *reinterpret_cast<const double2*>(na + i);
+                const double2 y = *reinterpret_cast<const double2*>(nb + i);
+                ra[i] = x.x;
+                ra[i + 1] = x.y;
+                rb[i] = y.x;
+                rb[i + 1] = y.y;
+            }
+        }
+#pragma unroll 2
+        for (int kk = 0; kk < kOK; ++kk) {
+            double a[kOR], b[kOR];
+#pragma unroll
+            for (int i = 0; i < kOR; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < kOR; ++j) b[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < kOR; ++i)
+#pragma unroll
+                for (int j = 0; j < kOR; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+    // write-out: x = E + product (one addition), then the filter
+#pragma unroll
+    for (int i = 0; i < kOR; ++i) {
+        const int64_t gi = row0 + ty + 16 * i;
+        if (gi >= n) continue;
+        const double tr = tau_row ? tau_row[gi] : tau;
+#pragma unroll
+        for (int j = 0; j < kOR; ++j) {
+            const int64_t gj = col0 + tx + 16 * j;
+            if (gj < n) {
+                double x = acc[i][j];
+                double* pe = E + gi * ld + gj;
+                if (has_e) x = *pe + x;
+                *pe = (x != 0.0 && !(fabs(x) < tr)) ? x : 0.0;
+            }
+        }
+    }
+}
+
 // ---- sparse rows times dense rows -------------------------------------------------
 // C = D_tau(E + A B) with A sparse (row-range CSR, rows < n) and B dense (ld
 // columns).  Each output entry is the fma chain over row r's stored entries
@@ -349,6 +443,15 @@ hipError_t launch_dgemm_mfma(const double* A, const double* B, double* E, int64_
         hipLaunchKernelGGL(k_dgemm_mfma<64>, dim3((unsigned)t64, (unsigned)t64), dim3(kB), 0, s, A, B, E, ld, n, has_e,
                            tau, tau_row);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_dgemm_ordered(const double* A, const double* B, double* E, int64_t ld, int64_t n, int has_e,
+                               double tau, const double* tau_row, hipStream_t s)
+{
+    const int64_t t = ld / kOT;  // ld is a multiple of 128
+    hipLaunchKernelGGL(k_dgemm_ordered, dim3((unsigned)t, (unsigned)t), dim3(kB), 0, s, A, B, E, ld, n, has_e, tau,
+                       tau_row);
     return hipGetLastError();
 }
 

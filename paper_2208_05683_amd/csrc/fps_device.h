@@ -233,6 +233,10 @@ hipError_t launch_dense_terms(const Terms& T, int64_t n, int64_t ld, double* E, 
 // E = D_tau((has_e ? E : 0) + A B) on the matrix cores (tau per row if tau_row)
 hipError_t launch_dgemm_mfma(const double* A, const double* B, double* E, int64_t ld, int64_t n, int has_e, double tau,
                              const double* tau_row, hipStream_t s);
+// E = D_tau((has_e ? E : 0) + A B) on the vector units, each entry's sum over
+// k in order (the sparse path's bits; ld a multiple of 128)
+hipError_t launch_dgemm_ordered(const double* A, const double* B, double* E, int64_t ld, int64_t n, int has_e,
+                                double tau, const double* tau_row, hipStream_t s);
 // E = D_tau((has_e ? E : 0) + A B) with A sparse and B dense, each entry the
 // fma chain over A's row in order (the sparse path's bits)
 hipError_t launch_spmm_rows(const MatView& A, const double* B, double* E, int64_t ld, int64_t n, int has_e, double tau,
