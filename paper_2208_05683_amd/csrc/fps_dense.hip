@@ -194,22 +194,23 @@ k_dgemm_mfma(const double* __restrict__ A, const double* __restrict__ B,
 // stored entries of A's row (ascending columns) with exact zeros added for
 // the others, so the sparse result bit for bit (as in k_spmm_rows below).
 // FP64 fma on the vector units has the matrix cores' FP64 peak on this chip.
-// Block tile 128 x 128, 256 threads as 16 x 16; thread (ty, tx) owns rows
-// ty + 16 i and columns tx + 16 j (i, j < 8), so that a wavefront's reads
-// of a k row of A are four broadcasts and of B sixteen consecutive doubles;
-// k in chunks of 16 staged in shared memory (A k-major), the next chunk's
-// global loads in flight during the current chunk's fmas.
+// Block tile 128 x 128, 256 threads as 16 x 16; thread (ty, tx) owns the
+// row pairs 2 ty + 32 i + {0, 1} and column pairs 2 tx + 32 j + {0, 1}
+// (i, j < 4), so that each k row of A and of B is read with four 16-byte
+// loads per thread (a wavefront's reads of A are broadcasts, of B sixteen
+// consecutive pairs); k in chunks of 16 staged in shared memory (A k-major),
+// the next chunk's global loads in flight during the current chunk's fmas.
 constexpr int kOT = 128, kOK = 16, kOR = 8;
 
 __global__ void __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_dgemm_ordered(const double* __restrict__ A, const double* __restrict__ B, double* E, int64_t ld, int64_t n,
                 int has_e, double tau, const double* __restrict__ tau_row)
 {
-    __shared__ double As[kOK][kOT];
-    __shared__ double Bs[kOK][kOT];
+    __shared__ __align__(16) double As[kOK][kOT];
+    __shared__ __align__(16) double Bs[kOK][kOT];
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
     const int64_t row0 = (int64_t)blockIdx.y * kOT, col0 = (int64_t)blockIdx.x * kOT;
-    double acc[kOR][kOR];
+    double acc[kOR][kOR];  // [row 2 i + u][column 2 j + v] of the thread's pairs
 #pragma unroll
     for (int i = 0; i < kOR; ++i)
 #pragma unroll
@@ -253,9 +254,17 @@ k_dgemm_ordered(const double* __restrict__ A, const double* __restrict__ B, doub
         for (int kk = 0; kk < kOK; ++kk) {
             double a[kOR], b[kOR];
 #pragma unroll
-            for (int i = 0; i < kOR; ++i) a[i] = As[kk][ty + 16 * i];
+            for (int i = 0; i < kOR / 2; ++i) {
+                const double2 x = *reinterpret_cast<const double2*>(&As[kk][2 * ty + 32 * i]);
+                a[2 * i] = x.x;
+                a[2 * i + 1] = x.y;
+            }
 #pragma unroll
-            for (int j = 0; j < kOR; ++j) b[j] = Bs[kk][tx + 16 * j];
+            for (int j = 0; j < kOR / 2; ++j) {
+                const double2 y = *reinterpret_cast<const double2*>(&Bs[kk][2 * tx + 32 * j]);
+                b[2 * j] = y.x;
+                b[2 * j + 1] = y.y;
+            }
 #pragma unroll
             for (int i = 0; i < kOR; ++i)
 #pragma unroll
@@ -266,12 +275,12 @@ k_dgemm_ordered(const double* __restrict__ A, const double* __restrict__ B, doub
     // write-out: x = E + product (one addition), then the filter
 #pragma unroll
     for (int i = 0; i < kOR; ++i) {
-        const int64_t gi = row0 + ty + 16 * i;
+        const int64_t gi = row0 + 2 * ty + 32 * (i >> 1) + (i & 1);
         if (gi >= n) continue;
         const double tr = tau_row ? tau_row[gi] : tau;
 #pragma unroll
         for (int j = 0; j < kOR; ++j) {
-            const int64_t gj = col0 + tx + 16 * j;
+            const int64_t gj = col0 + 2 * tx + 32 * (j >> 1) + (j & 1);
             if (gj < n) {
                 double x = acc[i][j];
                 double* pe = E + gi * ld + gj;
