@@ -388,9 +388,9 @@ def banded_sweep(count: int, eps_tol: float, e_r: float, bands):
     for fname, coeffs in (("exp", G.exp_coeffs(199)), ("cos", G.cos_coeffs(199))):
         rows = []
         for bw in bands:
-            acc = {k: [] for k in ("psscf_setup_ms", "psscf_ms", "psscf_mfma_ms", "ps_ms", "dense_ms",
-                                   "sparsity_psscf", "sparsity_ps", "err_psscf", "err_psscf_mfma", "err_ps",
-                                   "N", "q")}
+            acc = {k: [] for k in ("psscf_setup_ms", "psscf_ms", "psscf_mfma_ms", "psscf_exact_ms", "ps_ms",
+                                   "dense_ms", "sparsity_psscf", "sparsity_ps", "err_psscf", "err_psscf_mfma",
+                                   "err_ps", "exact_bitwise", "N", "q")}
             for k in range(count):
                 Z = G.banded_sweep_matrix(bw, 1000, seed=1000 * bw + k)
                 Zd = api.to_device(Z.row_ptr, Z.col, Z.val)
@@ -408,6 +408,15 @@ def banded_sweep(count: int, eps_tol: float, e_r: float, bands):
                 _, t_mfma = dev_ms(pm.eval)
                 Fm = pm.result()
                 pm.close()
+                # the exact dense paths: the sparse result bit for bit
+                px = api.Plan.series(Zd, coeffs, eps_tol, e_r, flags=B.FPS_FLAG_DENSE_EXACT)
+                px.eval()
+                _, t_exact = dev_ms(px.eval)
+                Fx = px.result()
+                px.close()
+                same = all(a.shape == b.shape and torch.equal(a.view(torch.int64) if a.dtype == torch.float64 else a,
+                                                             b.view(torch.int64) if b.dtype == torch.float64 else b)
+                           for a, b in zip(F, Fx))
                 m, s = info["N"] - 1, info["q"]
                 ps = api.Plan(Zd, coeffs, m, s, 0.0)
                 ps.eval()
@@ -428,6 +437,7 @@ def banded_sweep(count: int, eps_tol: float, e_r: float, bands):
                 acc["sparsity_psscf"].append(F[1].numel() / Z.n ** 2)
                 acc["sparsity_ps"].append(Fps[1].numel() / Z.n ** 2)
                 for key, v in (("psscf_setup_ms", t_setup), ("psscf_ms", t_eval), ("psscf_mfma_ms", t_mfma),
+                               ("psscf_exact_ms", t_exact), ("exact_bitwise", 1.0 if same else 0.0),
                                ("ps_ms", t_ps),
                                ("dense_ms", t_dense), ("N", info["N"]), ("q", info["q"])):
                     acc[key].append(v)

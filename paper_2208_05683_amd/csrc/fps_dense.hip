@@ -194,35 +194,40 @@ k_dgemm_mfma(const double* __restrict__ A, const double* __restrict__ B,
 // stored entries of A's row (ascending columns) with exact zeros added for
 // the others, so the sparse result bit for bit (as in k_spmm_rows below).
 // FP64 fma on the vector units has the matrix cores' FP64 peak on this chip.
-// Block tile 128 x 128, 256 threads as 16 x 16; thread (ty, tx) owns the
-// row pairs 2 ty + 32 i + {0, 1} and column pairs 2 tx + 32 j + {0, 1}
-// (i, j < 4), so that each k row of A and of B is read with four 16-byte
-// loads per thread (a wavefront's reads of A are broadcasts, of B sixteen
-// consecutive pairs); k in chunks of 16 staged in shared memory (A k-major),
-// the next chunk's global loads in flight during the current chunk's fmas.
-constexpr int kOT = 128, kOK = 16, kOR = 8;
+// Block tile BT x BT (128, or 64 when that gives the chip too few blocks),
+// 256 threads as 16 x 16; thread (ty, tx) owns the row pairs
+// 2 ty + 32 i + {0, 1} and the column pairs 2 tx + 32 j + {0, 1}
+// (i, j < BT / 32), so that each k row of A and of B is read with 16-byte
+// loads (a wavefront's reads of A are broadcasts, of B sixteen consecutive
+// pairs); k in chunks of 16 staged in shared memory (A k-major), the next
+// chunk's global loads in flight during the current chunk's fmas.
+constexpr int kOK = 16;
 
-__global__ void __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(2, 8)))
+template <int BT>
+__global__ void __launch_bounds__(kB) __attribute__((amdgpu_waves_per_eu(BT == 128 ? 2 : 4, 8)))
 k_dgemm_ordered(const double* __restrict__ A, const double* __restrict__ B, double* E, int64_t ld, int64_t n,
                 int has_e, double tau, const double* __restrict__ tau_row)
 {
-    __shared__ __align__(16) double As[kOK][kOT];
-    __shared__ __align__(16) double Bs[kOK][kOT];
+    constexpr int R = BT / 16;          // rows (and columns) per thread
+    constexpr int PER = BT * kOK / kB;  // doubles of each operand chunk per thread
+    constexpr int AQ = kOK / PER;       // threads per A row of a chunk
+    constexpr int BQ = BT / PER;        // threads per B k row of a chunk
+    __shared__ __align__(16) double As[kOK][BT];
+    __shared__ __align__(16) double Bs[kOK][BT];
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
-    const int64_t row0 = (int64_t)blockIdx.y * kOT, col0 = (int64_t)blockIdx.x * kOT;
-    double acc[kOR][kOR];  // [row 2 i + u][column 2 j + v] of the thread's pairs
+    const int64_t row0 = (int64_t)blockIdx.y * BT, col0 = (int64_t)blockIdx.x * BT;
+    double acc[R][R];  // [row 2 i + u][column 2 j + v] of the thread's pairs
 #pragma unroll
-    for (int i = 0; i < kOR; ++i)
+    for (int i = 0; i < R; ++i)
 #pragma unroll
-        for (int j = 0; j < kOR; ++j) acc[i][j] = 0.0;
-    // a chunk: A rows row0 + (t >> 1), k (t & 1) * 8 .. + 7; B k row t >> 4, columns (t & 15) * 8 .. + 7
-    const int ar = t >> 1, ak = (t & 1) * 8;
-    const int bk = t >> 4, bc = (t & 15) * 8;
+        for (int j = 0; j < R; ++j) acc[i][j] = 0.0;
+    const int ar = t / AQ, ak = (t % AQ) * PER;
+    const int bk = t / BQ, bc = (t % BQ) * PER;
     const double* pa = A + (row0 + ar) * ld + ak;
     const double* pb = B + (int64_t)bk * ld + col0 + bc;
-    double ra[8], rb[8];
+    double ra[PER], rb[PER];
 #pragma unroll
-    for (int i = 0; i < 8; i += 2) {
+    for (int i = 0; i < PER; i += 2) {
         const double2 x = *reinterpret_cast<const double2*>(pa + i);
         const double2 y = *reinterpret_cast<const double2*>(pb + i);
         ra[i] = x.x;
@@ -232,7 +237,7 @@ k_dgemm_ordered(const double* __restrict__ A, const double* __restrict__ B, doub
     }
     for (int64_t k0 = 0; k0 < ld; k0 += kOK) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < PER; ++i) {
             As[ak + i][ar] = ra[i];
             Bs[bk][bc + i] = rb[i];
         }
@@ -241,7 +246,7 @@ k_dgemm_ordered(const double* __restrict__ A, const double* __restrict__ B, doub
             const double* na = pa + (k0 + kOK);
             const double* nb = pb + (k0 + kOK) * ld;
 #pragma unroll
-            for (int i = 0; i < 8; i += 2) {
+            for (int i = 0; i < PER; i += 2) {
                 const double2 x = *reinterpret_cast<const double2*>(na + i);
                 const double2 y = *reinterpret_cast<const double2*>(nb + i);
                 ra[i] = x.x;
@@ -252,34 +257,34 @@ k_dgemm_ordered(const double* __restrict__ A, const double* __restrict__ B, doub
         }
 #pragma unroll 2
         for (int kk = 0; kk < kOK; ++kk) {
-            double a[kOR], b[kOR];
+            double a[R], b[R];
 #pragma unroll
-            for (int i = 0; i < kOR / 2; ++i) {
+            for (int i = 0; i < R / 2; ++i) {
                 const double2 x = *reinterpret_cast<const double2*>(&As[kk][2 * ty + 32 * i]);
                 a[2 * i] = x.x;
                 a[2 * i + 1] = x.y;
             }
 #pragma unroll
-            for (int j = 0; j < kOR / 2; ++j) {
+            for (int j = 0; j < R / 2; ++j) {
                 const double2 y = *reinterpret_cast<const double2*>(&Bs[kk][2 * tx + 32 * j]);
                 b[2 * j] = y.x;
                 b[2 * j + 1] = y.y;
             }
 #pragma unroll
-            for (int i = 0; i < kOR; ++i)
+            for (int i = 0; i < R; ++i)
 #pragma unroll
-                for (int j = 0; j < kOR; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < R; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
         }
         __syncthreads();
     }
     // write-out: x = E + product (one addition), then the filter
 #pragma unroll
-    for (int i = 0; i < kOR; ++i) {
+    for (int i = 0; i < R; ++i) {
         const int64_t gi = row0 + 2 * ty + 32 * (i >> 1) + (i & 1);
         if (gi >= n) continue;
         const double tr = tau_row ? tau_row[gi] : tau;
 #pragma unroll
-        for (int j = 0; j < kOR; ++j) {
+        for (int j = 0; j < R; ++j) {
             const int64_t gj = col0 + 2 * tx + 32 * (j >> 1) + (j & 1);
             if (gj < n) {
                 double x = acc[i][j];
@@ -458,9 +463,16 @@ hipError_t launch_dgemm_mfma(const double* A, const double* B, double* E, int64_
 hipError_t launch_dgemm_ordered(const double* A, const double* B, double* E, int64_t ld, int64_t n, int has_e,
                                double tau, const double* tau_row, hipStream_t s)
 {
-    const int64_t t = ld / kOT;  // ld is a multiple of 128
-    hipLaunchKernelGGL(k_dgemm_ordered, dim3((unsigned)t, (unsigned)t), dim3(kB), 0, s, A, B, E, ld, n, has_e, tau,
-                       tau_row);
+    // 128 x 128 tiles when they give the chip enough blocks, else 64 x 64 (ld is a multiple of 128)
+    const int64_t t128 = ld / 128;
+    if (t128 * t128 >= 512) {
+        hipLaunchKernelGGL(k_dgemm_ordered<128>, dim3((unsigned)t128, (unsigned)t128), dim3(kB), 0, s, A, B, E, ld, n,
+                           has_e, tau, tau_row);
+    } else {
+        const int64_t t64 = ld / 64;
+        hipLaunchKernelGGL(k_dgemm_ordered<64>, dim3((unsigned)t64, (unsigned)t64), dim3(kB), 0, s, A, B, E, ld, n,
+                           has_e, tau, tau_row);
+    }
     return hipGetLastError();
 }
 
