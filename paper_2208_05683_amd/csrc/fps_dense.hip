@@ -212,8 +212,8 @@ k_dgemm_ordered(const double* __restrict__ A, const double* __restrict__ B, doub
     constexpr int PER = BT * kOK / kB;  // doubles of each operand chunk per thread
     constexpr int AQ = kOK / PER;       // threads per A row of a chunk
     constexpr int BQ = BT / PER;        // threads per B k row of a chunk
-    __shared__ __align__(16) double As[kOK][BT];
-    __shared__ __align__(16) double Bs[kOK][BT];
+    __shared__ __align__(16) double As[2][kOK][BT];
+    __shared__ __align__(16) double Bs[2][kOK][BT];
     const int t = threadIdx.x, tx = t & 15, ty = t >> 4;
     const int64_t row0 = (int64_t)blockIdx.y * BT, col0 = (int64_t)blockIdx.x * BT;
     double acc[R][R];  // [row 2 i + u][column 2 j + v] of the thread's pairs
@@ -226,47 +226,46 @@ k_dgemm_ordered(const double* __restrict__ A, const double* __restrict__ B, doub
     const double* pa = A + (row0 + ar) * ld + ak;
     const double* pb = B + (int64_t)bk * ld + col0 + bc;
     double ra[PER], rb[PER];
+    auto fetch = [&](int64_t k0) {
 #pragma unroll
-    for (int i = 0; i < PER; i += 2) {
-        const double2 x = *reinterpret_cast<const double2*>(pa + i);
-        const double2 y = *reinterpret_cast<const double2*>(pb + i);
-        ra[i] = x.x;
-        ra[i + 1] = x.y;
-        rb[i] = y.x;
-        rb[i + 1] = y.y;
-    }
-    for (int64_t k0 = 0; k0 < ld; k0 += kOK) {
+        for (int i = 0; i < PER; i += 2) {
+            const double2 x = *reinterpret_cast<const double2*>(pa + k0 + i);
+            const double2 y = *reinterpret_cast<const double2*>(pb + k0 * ld + i);
+            ra[i] = x.x;
+            ra[i + 1] = x.y;
+            rb[i] = y.x;
+            rb[i + 1] = y.y;
+        }
+    };
+    auto stash = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
-            As[ak + i][ar] = ra[i];
-            Bs[bk][bc + i] = rb[i];
+            As[buf][ak + i][ar] = ra[i];
+            Bs[buf][bk][bc + i] = rb[i];
         }
-        __syncthreads();
-        if (k0 + kOK < ld) {  // the next chunk's loads overlap this chunk's fmas
-            const double* na = pa + (k0 + kOK);
-            const double* nb = pb + (k0 + kOK) * ld;
-#pragma unroll
-            for (int i = 0; i < PER; i += 2) {
-                const double2 x = *reinterpret_cast<const double2*>(na + i);
-                const double2 y = *reinterpret_cast<const double2*>(nb + i);
-                ra[i] = x.x;
-                ra[i + 1] = x.y;
-                rb[i] = y.x;
-                rb[i + 1] = y.y;
-            }
-        }
+    };
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    // two buffers: chunk c is read from buffer c & 1 while chunk c + 1 goes
+    // to the other one, which every wavefront finished reading before the
+    // barrier that ended chunk c - 1; one barrier per chunk
+    for (int64_t k0 = 0, c = 0; k0 < ld; k0 += kOK, ++c) {
+        const int buf = (int)(c & 1);
+        const bool more = k0 + kOK < ld;
+        if (more) fetch(k0 + kOK);
 #pragma unroll 2
         for (int kk = 0; kk < kOK; ++kk) {
             double a[R], b[R];
 #pragma unroll
             for (int i = 0; i < R / 2; ++i) {
-                const double2 x = *reinterpret_cast<const double2*>(&As[kk][2 * ty + 32 * i]);
+                const double2 x = *reinterpret_cast<const double2*>(&As[buf][kk][2 * ty + 32 * i]);
                 a[2 * i] = x.x;
                 a[2 * i + 1] = x.y;
             }
 #pragma unroll
             for (int j = 0; j < R / 2; ++j) {
-                const double2 y = *reinterpret_cast<const double2*>(&Bs[kk][2 * tx + 32 * j]);
+                const double2 y = *reinterpret_cast<const double2*>(&Bs[buf][kk][2 * tx + 32 * j]);
                 b[2 * j] = y.x;
                 b[2 * j + 1] = y.y;
             }
@@ -275,6 +274,7 @@ k_dgemm_ordered(const double* __restrict__ A, const double* __restrict__ B, doub
 #pragma unroll
                 for (int j = 0; j < R; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
         }
+        if (more) stash(buf ^ 1);
         __syncthreads();
     }
     // write-out: x = E + product (one addition), then the filter
