@@ -117,3 +117,47 @@ def test_small_tier_adaptive():
         assert [gst["stage_alg1_iters"][i] for i in prod] == [x["iters"] for x in a1]
     finally:
         plan.close()
+
+
+def test_small_tier_operand_change():
+    """The operand's values scaled in place by 1.5 after the plan has learned
+    its tiers: the stages in the small-row tier stay there and keep giving the
+    oracle's bits (the stage whose rows were all proven empty stays so: its
+    coefficient block is too small for any scaling to matter), while the last
+    Horner step outgrows its learned row stride, so an evaluation is repeated
+    with sizing; every evaluation gives the oracle's result for the operand it
+    saw, and so does the first operand again afterwards."""
+    import torch
+    from paper_2208_05683_amd import api
+    from gpu_helpers import download, upload
+
+    c, m, s, tau = G.exp_coeffs(30), 30, 6, 1e-12
+    Z1 = G.laplacian_2d(100, 2.0)
+    Z2 = G.laplacian_2d(100, 2.0)
+    Z2.val[:] = Z2.val * 1.5
+    want1, _ = O.filtered_ps(Z1, c, m, s, tau)
+    want2, _ = O.filtered_ps(Z2, c, m, s, tau)
+    Zd = upload(Z1)
+    plan = api.Plan(Zd, c, m, s, tau)
+    try:
+        for k in range(2):
+            plan.eval()
+            assert_same_csr(download(plan.result()), want1, f"first operand, evaluation {k}")
+        g1 = plan.stats()
+        skipped = [i for i, v in enumerate(g1["stage_rows_skipped"]) if v == Z1.n]
+        assert skipped and all(g1["stage_small"][i] for i in skipped), (g1["stage_rows_skipped"], g1["stage_small"])
+        Zd[2].copy_(torch.from_numpy(Z2.val).to(Zd[2].device))
+        for k in range(3):
+            plan.eval()
+            got = download(plan.result())
+            check_canonical(got)
+            assert_same_csr(got, want2, f"scaled operand, evaluation {k}")
+        g2 = plan.stats()
+        assert g2["resizes"] >= 1, g2["resizes"]
+        assert g2["stage_small"] == g1["stage_small"], (g1["stage_small"], g2["stage_small"])
+        assert max(g2["stage_max_ns"]) > max(g1["stage_max_ns"])
+        Zd[2].copy_(torch.from_numpy(Z1.val).to(Zd[2].device))
+        plan.eval()
+        assert_same_csr(download(plan.result()), want1, "first operand again")
+    finally:
+        plan.close()
