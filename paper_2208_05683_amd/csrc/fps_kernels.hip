@@ -1141,8 +1141,14 @@ __device__ __forceinline__ double shfl_f64(double x, int src)
     return __longlong_as_double((long long)shfl_u64((uint64_t)__double_as_longlong(x), src));
 }
 
+// With `seen` (one zeroed word per accumulator slot, or null), an
+// instruction's entries are not applied one term per round: each lane ORs its
+// term's bit into its slot's word, and its round is the number of earlier
+// terms of the instruction on the same slot, so a round applies, for every
+// slot, its next term in term order, and an instruction takes as many rounds
+// as the most terms sharing one slot.
 __device__ __forceinline__ void packed_pass(const StageArgs& P, const Chunk& c, int32_t lo, uint32_t guard,
-                                            const uint2* bmp, double* acc)
+                                            const uint2* bmp, double* acc, uint32_t* seen)
 {
     const int l = lane();
     const int32_t wd = max(c.maxlen, 1);
@@ -1162,6 +1168,19 @@ __device__ __forceinline__ void packed_pass(const StageArgs& P, const Chunk& c, 
         *cl = *ok ? P.B.col[e] : gcol;
         *v = *ok ? P.B.val[e] : 0.0;
     };
+    // terms of an instruction by bit (sub < per <= 32)
+    const bool multi = seen != nullptr && per <= 32;
+    auto apply_rounds = [&](bool ok, uint32_t sl, double a, double v) {
+        if (ok) atomicOr(&seen[sl], 1u << sub);
+        wave_sync();
+        const uint32_t rk = ok ? (uint32_t)__popc(seen[sl] & ((1u << sub) - 1u)) : 0u;
+        for (uint32_t t = 0; __ballot(ok && rk >= t) != 0ull; ++t) {
+            if (ok && rk == t) acc[sl] = fma(a, v, acc[sl]);
+            wave_sync();
+        }
+        if (ok) seen[sl] = 0u;
+        wave_sync();
+    };
     for (int32_t i0 = 0; i0 < c.nterms; i0 += 2 * per) {
         bool ok0, ok1;
         double a0, a1, v0, v1;
@@ -1169,6 +1188,11 @@ __device__ __forceinline__ void packed_pass(const StageArgs& P, const Chunk& c, 
         fetch(i0 + sub, &ok0, &a0, &c0, &v0);
         fetch(i0 + per + sub, &ok1, &a1, &c1, &v1);
         const uint32_t s0 = rank_col(bw, c0), s1 = rank_col(bw, c1);
+        if (multi) {
+            apply_rounds(ok0, s0, a0, v0);
+            apply_rounds(ok1, s1, a1, v1);
+            continue;
+        }
         const int32_t n0 = min(per, c.nterms - i0);
         for (int32_t j = 0; j < n0; ++j) {
             if (ok0 && sub == j) acc[s0] = fma(a0, v0, acc[s0]);
@@ -1201,10 +1225,16 @@ __device__ __forceinline__ bool use_per_term(int src, const Chunk& c)
 template <bool kAccum, bool kGlobal>
 __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t r, int32_t lo, uint32_t guard,
                                            uint8_t* bytes, uint2* bmp, double* acc, WaveStage& st,
-                                           bool have_first, const Chunk& first)
+                                           bool have_first, const Chunk& first, uint32_t* seen = nullptr,
+                                           const int64_t* range = nullptr)
 {
     int64_t tb, te;
-    term_range(P, src, r, &tb, &te);
+    if (range != nullptr) {
+        tb = range[0];
+        te = range[1];
+    } else {
+        term_range(P, src, r, &tb, &te);
+    }
     for (int64_t t0 = tb; t0 < te; t0 += kChunk) {
         const bool pre = have_first && t0 == tb;
         const Chunk c = pre ? first : load_chunk(P, src, r, t0, te);
@@ -1220,7 +1250,7 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
                 per_term_pass<kSrcCoefs, kAccum, kGlobal>(P, r, t0, c, lo, guard, bytes, bmp, acc);
             }
         } else if (kAccum && src == kSrcProducts && c.maxlen <= kPackedMax) {
-            packed_pass(P, c, lo, guard, bmp, acc);
+            packed_pass(P, c, lo, guard, bmp, acc, seen);
         } else {
             if (!pre) stage_chunk(c, st);
             for (int32_t q0 = 0; q0 < c.total; q0 += kWave * kU) {
@@ -1246,13 +1276,18 @@ __device__ __forceinline__ void terms_pass(const StageArgs& P, int src, int64_t 
 // `first`, if given, is the chunk at the first term, already loaded.
 template <int SRC>
 __device__ __forceinline__ void mark_words(const StageArgs& P, int64_t r, int32_t lo, uint32_t words, uint2* bmp,
-                                           const Chunk* first)
+                                           const Chunk* first, const int64_t* range = nullptr)
 {
     const int l = lane();
     const uint32_t lo_w = (uint32_t)lo >> 5;
     const uint2 ident = make_uint2((uint32_t)(r >> 5), 1u << (r & 31));
     int64_t tb, te;
-    term_range(P, SRC, r, &tb, &te);
+    if (range != nullptr) {
+        tb = range[0];
+        te = range[1];
+    } else {
+        term_range(P, SRC, r, &tb, &te);
+    }
     for (int64_t t0 = tb; t0 < te; t0 += kChunk) {
         const int64_t t = t0 + l;
         uint64_t wp = 0;  // address of the term row's first word; 0: the identity row
@@ -1354,16 +1389,20 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     const int l = lane();
     *kept_out = 0;
     *ns_out = 0;
+    // the row's analysis results and its range of main terms in one round trip
+    const int main_src = (P.mode == kModeProduct) ? kSrcProducts : kSrcCoefs;
     const int32_t W = P.W[r];
+    const int32_t lo = P.lo[r];
+    const bool has_main = P.prod[r] > 0;
+    int64_t range[2];
+    term_range(P, main_src, r, &range[0], &range[1]);
     if (W <= 0) {
         if (l == 0) empty_row(P, r, o);
         return true;
     }
-    const int32_t lo = P.lo[r];
     const int64_t words = ((int64_t)W + 31) >> 5;
     if (words > max_words) return false;
     const uint32_t guard = (uint32_t)(words * 32);
-    const int main_src = (P.mode == kModeProduct) ? kSrcProducts : kSrcCoefs;
     const bool has_extra = P.has_e || P.has_blk;
 
     // 1. structure of the row inside its window, guard word included
@@ -1377,9 +1416,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     // rows whose main terms have no entries (known from the analysis) skip
     // them.  The first chunk of main terms is loaded before the block's marks
     // (its loads overlap theirs); the structure pass reuses it.
-    const bool has_main = P.prod[r] > 0;
-    int64_t tb, te;
-    term_range(P, main_src, r, &tb, &te);
+    const int64_t tb = range[0], te = range[1];
     Chunk c0{};
     if (has_main) c0 = load_chunk(P, main_src, r, tb, te);
     const Chunk none{};
@@ -1406,9 +1443,9 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
                 mark_batch<kGlobal>(lo, guard, b1, bytes, bmp);
             }
         } else if (kGlobal) {
-            terms_pass<false, true>(P, main_src, r, lo, guard, bytes, bmp, nullptr, st, true, c0);
+            terms_pass<false, true>(P, main_src, r, lo, guard, bytes, bmp, nullptr, st, true, c0, nullptr, range);
         } else if (main_src == kSrcProducts) {
-            mark_words<kSrcProducts>(P, r, lo, (uint32_t)words, bmp, &c0);
+            mark_words<kSrcProducts>(P, r, lo, (uint32_t)words, bmp, &c0, range);
         } else {
             mark_words<kSrcCoefs>(P, r, lo, (uint32_t)words, bmp, &c0);
         }
@@ -1477,6 +1514,14 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     //    the shared-memory kernel lists them in shared memory after the
     //    accumulation (step 5).
     for (int64_t i = l; i < ns; i += kWave) acc[i] = 0.0;
+    // the packed short-row path's slot words, zeroed, in the accumulator
+    // beyond the row's slots when they fit below the spare slot (that path
+    // leaves them zeroed)
+    uint32_t* seen = nullptr;
+    if (!kGlobal && ns + (ns + 1) / 2 <= cap) {
+        seen = reinterpret_cast<uint32_t*>(acc + ns);
+        for (int64_t i = l; i < ns; i += kWave) seen[i] = 0u;
+    }
     if (kGlobal) list_cols(P.out.col + o);
     wave_sync();
 
@@ -1485,7 +1530,7 @@ __device__ __forceinline__ bool process_row(const StageArgs& P, int64_t r, int64
     } else if (single) {
         if (c0.total > 0) accumulate_batch(c0, 0, lo, guard, b1, bmp, acc);
     } else {
-        terms_pass<true, kGlobal>(P, main_src, r, lo, guard, nullptr, bmp, acc, st, one_chunk, c0);
+        terms_pass<true, kGlobal>(P, main_src, r, lo, guard, nullptr, bmp, acc, st, one_chunk, c0, seen, range);
     }
     wave_sync();
     double preg[kParked];
