@@ -974,8 +974,9 @@ struct Slots {
 // Accumulator slots of a part's entries; lanes without an entry get the spare
 // slot.  Every column of the row lies in the window (checked after the
 // structure pass).  kBoth: the second half of the part as well (the spare
-// slot for every lane if the row ends in the first half).
-template <bool kBoth>
+// slot for every lane if the row ends in the first half).  kFull: the row
+// fills the first half (no lane of it needs the spare slot).
+template <bool kBoth, bool kFull = false>
 __device__ __forceinline__ Slots part_slots(const TermInfo& h, int32_t e0, const Part& p, int64_t r, int32_t lo,
                                             uint32_t guard, const uint2* bmp)
 {
@@ -984,7 +985,7 @@ __device__ __forceinline__ Slots part_slots(const TermInfo& h, int32_t e0, const
     const uint2* bw = bmp - (lo >> 5);
     const int32_t gcol = lo + (int32_t)guard;
     Slots s;
-    s.s0 = rank_col(bw, (e0 + l < h.len) ? c0 : gcol);
+    s.s0 = rank_col(bw, (kFull || e0 + l < h.len) ? c0 : gcol);
     s.s1 = kBoth ? rank_col(bw, (e0 + kWave + l < h.len) ? p.c1 : gcol) : 0u;
     return s;
 }
@@ -1041,10 +1042,17 @@ __device__ __forceinline__ void run_group(const StageArgs& P, int64_t r, int64_t
         // the ranks of the whole group first, without branches between the
         // bitmap reads: second halves for every term if any term needs them
         Slots s[kGroup];
-        bool two = false;
+        bool two = false, full = true;
 #pragma unroll
-        for (int g = 0; g < group_size(SRC); ++g) two = two || h[g].len > kWave;
-        if (two) {
+        for (int g = 0; g < group_size(SRC); ++g) {
+            two = two || h[g].len > kWave;
+            full = full && h[g].len >= kWave;
+        }
+        if (full) {  // every term row fills its first half (the usual case of long rows)
+#pragma unroll
+            for (int g = 0; g < group_size(SRC); ++g)
+                s[g] = part_slots<true, true>(h[g], 0, p[g], r, lo, guard, bmp);
+        } else if (two) {
 #pragma unroll
             for (int g = 0; g < group_size(SRC); ++g) s[g] = part_slots<true>(h[g], 0, p[g], r, lo, guard, bmp);
         } else {
