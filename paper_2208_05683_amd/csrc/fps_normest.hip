@@ -109,25 +109,38 @@ __global__ void __launch_bounds__(kB) k_spmv(const int64_t* __restrict__ rp, con
 }
 
 // ||y||_1 = sum_i |y_i| added in ascending index order from +0, by one
-// wavefront: 64 values at a time go through shared memory (the next 64
-// already loading), and every lane runs the same chain of additions on
-// broadcast reads of them in order; the padding past n adds +0, which leaves
-// a sum of nonnegative terms unchanged
+// wavefront: kSumBlock values at a time go through shared memory (the next
+// block already loading, kSumBlock / 64 per lane, so that a load's latency is
+// covered by a whole block of additions), and every lane runs the same chain
+// of additions on broadcast reads of them in order; the padding past n adds
+// +0, which leaves a sum of nonnegative terms unchanged
+constexpr int kSumBlock = 4 * kWave;
+
 __global__ void __launch_bounds__(kWave) k_abs_sum_ordered(const double* __restrict__ y, int64_t n, double* out)
 {
-    __shared__ double buf[kWave];
+    __shared__ double buf[kSumBlock];
+    constexpr int kPer = kSumBlock / kWave;
     const int l = threadIdx.x;
     double acc = 0.0;
-    double nxt = (l < n) ? fabs(y[l]) : 0.0;
-    for (int64_t b = 0; b < n; b += kWave) {
-        buf[l] = nxt;
+    double nxt[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) nxt[q] = (q * kWave + l < n) ? fabs(y[q * kWave + l]) : 0.0;
+    for (int64_t b = 0; b < n; b += kSumBlock) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) buf[q * kWave + l] = nxt[q];
         __syncthreads();
-        nxt = (b + kWave + l < n) ? fabs(y[b + kWave + l]) : 0.0;
-        double v[kWave];
 #pragma unroll
-        for (int j = 0; j < kWave; ++j) v[j] = buf[j];
+        for (int q = 0; q < kPer; ++q) {
+            const int64_t i = b + kSumBlock + q * kWave + l;
+            nxt[q] = (i < n) ? fabs(y[i]) : 0.0;
+        }
+        for (int j0 = 0; j0 < kSumBlock; j0 += kWave) {
+            double v[kWave];
 #pragma unroll
-        for (int j = 0; j < kWave; ++j) acc = acc + v[j];
+            for (int j = 0; j < kWave; ++j) v[j] = buf[j0 + j];
+#pragma unroll
+            for (int j = 0; j < kWave; ++j) acc = acc + v[j];
+        }
         __syncthreads();
     }
     if (l == 0) *out = acc;
