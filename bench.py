@@ -258,7 +258,7 @@ def bench_serve(args, stream):
         "speedup_vs_plain": x_srv / x_plain,
         "speedup_vs_one_slot": x_srv / sat["one_slot"]["evals_per_s"],
         "poisson": levels,
-        "server_stats": {k: {kk: v[kk] for kk in ("completed", "failed", "retries", "peak_running",
+        "server_stats": {k: {kk: v[kk] for kk in ("completed", "failed", "retries", "grows", "peak_running",
                                                    "peak_reserved")} for k, v in stats.items()},
     }
 

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define FPS_ABI_VERSION 1
+#define FPS_ABI_VERSION 2
 
 typedef int32_t fps_status;
 #define FPS_OK 0
@@ -492,7 +492,8 @@ typedef struct {
     int32_t fake_backend; /* 1: nothing is computed and no device call is made: a worker holds each request
                              for n microseconds and charges 100 n bytes against its reservation (tests of
                              the scheduler without a GPU) */
-    int32_t reserved;
+    int32_t no_grow;      /* 1: a request that needs more than its reservation always runs again with a
+                             larger one; 0: it first grows the reservation in place (see below) */
 } fps_server_opts;
 
 /* request states */
@@ -507,9 +508,12 @@ typedef struct {
  * the head is admitted when a slot is free and its reservation fits the
  * budget beside the reservations of the running requests and the bytes of
  * the finished results not yet released.  A request's plan may hold at most
- * its reservation (an estimate from n, nnz, m and s, or the caller's hint);
- * if it needs more, it goes back to the head of the queue with four times
- * the reservation (up to the whole budget) and runs again when that fits.
+ * its reservation (an estimate from n, nnz, m and s, or the caller's hint).
+ * If it needs more, the reservation grows in place, to a quarter more than
+ * needed, when the budget has room for that beside everything else reserved
+ * or held (unless opts->no_grow), and the run goes on; otherwise the request
+ * goes back to the head of the queue with four times the reservation (up to
+ * the whole budget) and runs again when that fits.
  * A finished request keeps only its result (canonical CSR) on the device
  * until fps_server_release.  Results do not depend on what else runs: each
  * request is its own plan, evaluated exactly as alone.
@@ -564,6 +568,7 @@ typedef struct {
     int64_t reserved;      /* bytes reserved now (running) or held (finished, unreleased) */
     int64_t peak_reserved; /* its largest value so far (never above the budget) */
     int64_t budget;
+    int64_t grows;         /* reservations grown in place */
 } fps_server_stats;
 
 fps_status fps_server_get_stats(fps_server sv, fps_server_stats *out);

@@ -186,8 +186,9 @@ class Server:
     fps_server_create).  submit() returns a ticket; wait(), result() and
     release() act on it."""
 
-    def __init__(self, slots: int, hbm_budget: int, max_queue: int = 0, flags: int = 0, fake_backend: bool = False):
-        self.handle = B.fps_server_create(slots, hbm_budget, max_queue, flags, fake_backend)
+    def __init__(self, slots: int, hbm_budget: int, max_queue: int = 0, flags: int = 0, fake_backend: bool = False,
+                 no_grow: bool = False):
+        self.handle = B.fps_server_create(slots, hbm_budget, max_queue, flags, fake_backend, no_grow)
         self._n = {}
         self._dev = {}
 

@@ -128,7 +128,7 @@ class fps_batch_stats(C.Structure):
 
 class fps_server_opts(C.Structure):
     _fields_ = [("slots", C.c_int32), ("max_queue", C.c_int32), ("hbm_budget", C.c_int64), ("flags", C.c_uint64),
-                ("fake_backend", C.c_int32), ("reserved", C.c_int32)]
+                ("fake_backend", C.c_int32), ("no_grow", C.c_int32)]
 
 
 class fps_server_request(C.Structure):
@@ -141,7 +141,7 @@ class fps_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("retries", C.c_int64),
                 ("refused", C.c_int64), ("running", C.c_int32), ("queued", C.c_int32), ("slots", C.c_int32),
                 ("peak_running", C.c_int32), ("reserved", C.c_int64), ("peak_reserved", C.c_int64),
-                ("budget", C.c_int64)]
+                ("budget", C.c_int64), ("grows", C.c_int64)]
 
 
 _P = C.POINTER
@@ -458,8 +458,10 @@ def fps_batch_destroy(b):
 
 # ---- server -------------------------------------------------------------------
 
-def fps_server_create(slots: int, hbm_budget: int, max_queue: int = 0, flags: int = 0, fake_backend: bool = False):
-    o = fps_server_opts(int(slots), int(max_queue), int(hbm_budget), int(flags), 1 if fake_backend else 0, 0)
+def fps_server_create(slots: int, hbm_budget: int, max_queue: int = 0, flags: int = 0, fake_backend: bool = False,
+                      no_grow: bool = False):
+    o = fps_server_opts(int(slots), int(max_queue), int(hbm_budget), int(flags), 1 if fake_backend else 0,
+                        1 if no_grow else 0)
     h = C.c_void_p()
     _check(_lib.fps_server_create(C.byref(h), C.byref(o)), "fps_server_create")
     return h

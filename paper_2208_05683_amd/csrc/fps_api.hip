@@ -62,6 +62,17 @@ struct MemAcct {
     size_t used = 0;
     size_t peak = 0;
     size_t cap = SIZE_MAX;
+    // optional: asked to raise `cap` to at least `need` before an allocation
+    // past it fails (true if it did)
+    bool (*extend)(void* ctx, MemAcct* a, size_t need) = nullptr;
+    void* ctx = nullptr;
+    // room for `more` bytes beside `used`, after asking for it if needed
+    bool admit(size_t more)
+    {
+        if (more <= cap && used <= cap - more) return true;
+        return extend != nullptr && used <= SIZE_MAX - more && extend(ctx, this, used + more) && more <= cap &&
+               used <= cap - more;
+    }
 };
 thread_local MemAcct* t_acct = nullptr;
 
@@ -151,7 +162,7 @@ struct DevBuf {
         release();
         size_t b = std::max<size_t>(want, 256);
         if (t_pool) b = DevPool::size_class(b);
-        if (t_acct && (b > t_acct->cap || t_acct->used > t_acct->cap - b))
+        if (t_acct && !t_acct->admit(b))
             return set_error(FPS_ERR_CAPACITY, "device memory limit of %zu bytes reached (%zu held, %zu more wanted)",
                              t_acct->cap, t_acct->used, b);
         p = t_pool ? t_pool->take(b) : nullptr;
@@ -1390,7 +1401,8 @@ fps_status fps_schedule(int32_t m, int32_t s, int32_t* N, int32_t* q, int32_t* b
 // (creation and every later evaluation); past it an allocation fails with
 // FPS_ERR_CAPACITY.
 static fps_status plan_create_limited(fps_plan* out, const fps_csr_view* Z, const double* coeffs, int32_t m, int32_t s,
-                                      const fps_filter_opts* opts, uint64_t flags, fps_stream stream, size_t mem_cap);
+                                      const fps_filter_opts* opts, uint64_t flags, fps_stream stream, size_t mem_cap,
+                                      bool (*extend)(void*, MemAcct*, size_t) = nullptr, void* extend_ctx = nullptr);
 
 extern "C" {
 
@@ -1403,7 +1415,8 @@ fps_status fps_plan_create_ex(fps_plan* out, const fps_csr_view* Z, const double
 }  // extern "C"
 
 static fps_status plan_create_limited(fps_plan* out, const fps_csr_view* Z, const double* coeffs, int32_t m, int32_t s,
-                                      const fps_filter_opts* opts, uint64_t flags, fps_stream stream, size_t mem_cap)
+                                      const fps_filter_opts* opts, uint64_t flags, fps_stream stream, size_t mem_cap,
+                                      bool (*extend)(void*, MemAcct*, size_t), void* extend_ctx)
 {
     g_last_error.clear();
     if (!out) return set_error(FPS_ERR_INVALID_ARG, "out is NULL");
@@ -1444,6 +1457,8 @@ static fps_status plan_create_limited(fps_plan* out, const fps_csr_view* Z, cons
     std::unique_ptr<fps_plan_s> p(new (std::nothrow) fps_plan_s());
     if (!p) return set_error(FPS_ERR_OUT_OF_MEMORY, "host allocation failed");
     p->acct.cap = mem_cap;
+    p->acct.extend = extend;
+    p->acct.ctx = extend_ctx;
     AcctScope scope(&p->acct);
     p->Z = *Z;
     p->c.assign(coeffs, coeffs + m + 1);
@@ -2510,6 +2525,7 @@ struct fps_server_s {
         fps_status status = FPS_OK;
         std::string error;
         int attempts = 0;
+        fps_server_s* sv = nullptr;  // the server (for growing the reservation in place)
         size_t reserve = 0, held = 0, peak = 0;
         int64_t nnz_out = 0;
         DevBuf rp, col, val;  // the result, kept until release
@@ -2534,10 +2550,42 @@ struct fps_server_s {
     int64_t next_id = 1;
     size_t reserved = 0, peak_reserved = 0;
     int running = 0, peak_running = 0;
-    int64_t submitted = 0, completed = 0, failed = 0, retries = 0, refused = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, retries = 0, refused = 0, grows = 0;
     bool stopping = false;
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
+
+    // Raises the reservation of running request r to at least `need` bytes
+    // (a quarter more where the budget allows, so that a plan grows in few
+    // steps) if the budget has room beside everything else reserved or held;
+    // the plan's account `a` (if any) follows.  Called by the request's own
+    // worker (no lock held).
+    bool grow(Req* r, size_t need, MemAcct* a)
+    {
+        size_t keep = 0;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            const size_t budget = (size_t)o.hbm_budget;
+            const size_t others = reserved - r->reserve;
+            if (need > budget || others > budget - need) return false;
+            const size_t want = std::min(budget - others, need + need / 4);
+            reserved = others + want;
+            peak_reserved = std::max(peak_reserved, reserved);
+            r->reserve = want;
+            if (a) a->cap = want;
+            grows++;
+            keep = budget - reserved;
+        }
+        // pooled free blocks count against the budget as well
+        if (!o.fake_backend) pool.trim(keep);
+        return true;
+    }
+
+    static bool extend_hook(void* ctx, MemAcct* a, size_t need)
+    {
+        Req* r = static_cast<Req*>(ctx);
+        return r->sv->grow(r, need, a);
+    }
 
     // Runs one attempt of a request on `st` (no lock held).
     void execute(Req* r, hipStream_t st)
@@ -2545,15 +2593,15 @@ struct fps_server_s {
         r->status = FPS_OK;
         r->error.clear();
         if (o.fake_backend) {
-            std::this_thread::sleep_for(std::chrono::microseconds(r->Z.n));
             r->peak = (size_t)r->Z.n * 100;
-            if (r->peak > r->reserve) {
+            if (r->peak > r->reserve && (o.no_grow || !grow(r, r->peak, nullptr))) {
                 r->status = FPS_ERR_CAPACITY;
                 r->error = "fake backend: reservation too small";
-            } else {
-                r->held = 0;
-                r->nnz_out = 0;
+                return;
             }
+            std::this_thread::sleep_for(std::chrono::microseconds(r->Z.n));
+            r->held = 0;
+            r->nnz_out = 0;
             return;
         }
         fps_filter_opts fo{};
@@ -2561,7 +2609,8 @@ struct fps_server_s {
         fo.tau = r->tau;
         fps_plan p = nullptr;
         fps_status stt = plan_create_limited(&p, &r->Z, r->c.data(), r->m, r->s, &fo, o.flags,
-                                             reinterpret_cast<fps_stream>(st), r->reserve);
+                                             reinterpret_cast<fps_stream>(st), r->reserve,
+                                             o.no_grow ? nullptr : &extend_hook, r);
         if (stt == FPS_OK) stt = fps_eval(p, reinterpret_cast<fps_stream>(st));
         if (stt == FPS_OK) stt = finish(p);
         if (stt == FPS_OK) {
@@ -2572,7 +2621,7 @@ struct fps_server_s {
             // the copy exists beside the plan for a moment: it must fit the
             // reservation too
             const size_t copy = sizeof(int64_t) * (size_t)(n + 1) + 12 * (size_t)std::max<int64_t>(nnz, 1) + 768;
-            if (stt == FPS_OK && p->acct.used + copy > r->reserve)
+            if (stt == FPS_OK && !p->acct.admit(copy))
                 stt = set_error(FPS_ERR_CAPACITY, "the result copy does not fit the reservation");
             if (stt == FPS_OK) stt = r->rp.ensure(sizeof(int64_t) * (size_t)(n + 1));
             if (stt == FPS_OK) stt = r->col.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
@@ -2728,6 +2777,7 @@ fps_status fps_server_submit(fps_server sv, const fps_csr_view* Z, const double*
     r->Z = *Z;
     r->c.assign(coeffs, coeffs + m + 1);
     r->m = m;
+    r->sv = sv;
     if (s == 0) {
         s = 0;
         while ((s + 1) * (s + 1) <= m) ++s;
@@ -2858,6 +2908,7 @@ fps_status fps_server_get_stats(fps_server sv, fps_server_stats* out)
     out->reserved = (int64_t)sv->reserved;
     out->peak_reserved = (int64_t)sv->peak_reserved;
     out->budget = sv->o.hbm_budget;
+    out->grows = sv->grows;
     return FPS_OK;
 }
 

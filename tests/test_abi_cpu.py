@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(B):
 
 
 def test_header_constants_and_version(B):
-    assert B.fps_abi_version() == B.FPS_ABI_VERSION == 1
+    assert B.fps_abi_version() == B.FPS_ABI_VERSION == 2
     assert B.FPS_MAX_S == 31
     assert C.sizeof(B.fps_stats) > 0
 

@@ -54,7 +54,7 @@ def test_small_reservation_retried_and_budget_respected():
     reqs = _mix(6, 4000, seed=7)
     dev = [upload(r["Z"]) for r in reqs]
     budget = 2 << 30
-    sv = api.Server(slots=3, hbm_budget=budget)
+    sv = api.Server(slots=3, hbm_budget=budget, no_grow=True)
     try:
         # far too small a first reservation: the plan's first allocation fails
         tickets = [sv.submit(d, r["coeffs"], r["m"], r["tau"], reserve_hint=4096) for d, r in zip(dev, reqs)]
@@ -67,6 +67,35 @@ def test_small_reservation_retried_and_budget_respected():
             assert_same_csr(download(sv.result(t)), want, r["name"])
         st = sv.stats()
         assert st["retries"] >= len(reqs) and st["peak_reserved"] <= budget
+    finally:
+        sv.close()
+
+
+def test_small_reservation_grown_in_place():
+    """The same requests with growth in place: every one runs once, its plan
+    raising the reservation as it allocates; results still equal the
+    oracle's bit for bit and the budget holds."""
+    from paper_2208_05683_amd import api
+
+    reqs = _mix(6, 4000, seed=7)
+    dev = [upload(r["Z"]) for r in reqs]
+    budget = 2 << 30
+    sv = api.Server(slots=3, hbm_budget=budget)
+    try:
+        tickets = [sv.submit(d, r["coeffs"], r["m"], r["tau"], reserve_hint=4096) for d, r in zip(dev, reqs)]
+        for t in tickets:
+            assert sv.wait(t, 60000) == 2
+        for t, r in zip(tickets, reqs):
+            info = sv.info(t)
+            assert info["attempts"] == 1 and info["status"] == 0
+            assert info["reserve"] > 4096
+            want, _ = O.filtered_ps(r["Z"], r["coeffs"], r["m"], info["s"], r["tau"])
+            assert_same_csr(download(sv.result(t)), want, r["name"])
+        st = sv.stats()
+        assert st["retries"] == 0 and st["grows"] >= len(reqs) and st["peak_reserved"] <= budget
+        for t in tickets:
+            sv.release(t)
+        assert sv.stats()["reserved"] == 0
     finally:
         sv.close()
 

@@ -2,7 +2,8 @@
 request of dimension n is held by a worker for n microseconds and charges
 100 n bytes against its reservation.  Admission is FIFO, bounded by the slots
 and by the device-memory budget; a request whose reservation is too small
-runs again with four times as much; a full queue refuses submissions."""
+grows it in place while the budget has room, else runs again with four times
+as much; a full queue refuses submissions."""
 
 import time
 
@@ -69,7 +70,7 @@ def test_memory_budget_limits_concurrency(B):
 
 
 def test_too_small_reservation_is_retried_larger(B):
-    sv = B.fps_server_create(slots=2, hbm_budget=1 << 40, fake_backend=True)
+    sv = B.fps_server_create(slots=2, hbm_budget=1 << 40, fake_backend=True, no_grow=True)
     try:
         n = 1000
         tickets, info = _run(B, sv, [n, n], [10 * n, 100 * n])
@@ -77,6 +78,42 @@ def test_too_small_reservation_is_retried_larger(B):
         assert info[0]["reserve"] == 160 * n
         assert info[1]["attempts"] == 1
         assert B.fps_server_get_stats(sv)["retries"] == 2
+    finally:
+        B.fps_server_destroy(sv)
+
+
+def test_too_small_reservation_grows_in_place(B):
+    sv = B.fps_server_create(slots=2, hbm_budget=1 << 40, fake_backend=True)
+    try:
+        n = 1000
+        tickets, info = _run(B, sv, [n, n], [10 * n, 100 * n])
+        assert info[0]["state"] == B.FPS_REQ_DONE and info[0]["attempts"] == 1
+        assert info[0]["reserve"] == 125 * n  # a quarter more than the 100 n it needed
+        assert info[1]["attempts"] == 1 and info[1]["reserve"] == 100 * n
+        st = B.fps_server_get_stats(sv)
+        assert st["retries"] == 0 and st["grows"] == 1 and st["completed"] == 2
+        for t in tickets:
+            B.fps_server_release(sv, t)
+        assert B.fps_server_get_stats(sv)["reserved"] == 0
+    finally:
+        B.fps_server_destroy(sv)
+
+
+def test_growth_refused_by_a_full_budget_runs_again(B):
+    # A (100 n, enough) runs for n microseconds; B starts beside it with 10 n
+    # and needs 100 n: 100 n + 100 n is past the budget of 130 n, so B goes
+    # back to the queue with 40 n, which fits only once A is done; then it
+    # grows in place (to 125 n)
+    n = 20000
+    sv = B.fps_server_create(slots=2, hbm_budget=130 * n, fake_backend=True)
+    try:
+        tickets, info = _run(B, sv, [n, n], [100 * n, 10 * n])
+        assert [x["state"] for x in info] == [B.FPS_REQ_DONE, B.FPS_REQ_DONE]
+        assert info[0]["attempts"] == 1
+        assert info[1]["attempts"] == 2 and info[1]["reserve"] == 125 * n
+        assert info[1]["t_start_ns"] >= info[0]["t_done_ns"]
+        st = B.fps_server_get_stats(sv)
+        assert st["retries"] == 1 and st["grows"] == 1 and st["peak_reserved"] <= 130 * n
     finally:
         B.fps_server_destroy(sv)
 
