@@ -76,6 +76,10 @@ struct MemAcct {
 };
 thread_local MemAcct* t_acct = nullptr;
 
+// A stage's rows get a fixed stride when that takes at most this many times
+// the room of the scanned upper bounds.
+constexpr int64_t kStrideRoom = 4;
+
 struct AcctScope {
     MemAcct* prev;
     explicit AcctScope(MemAcct* a) : prev(t_acct) { t_acct = a; }
@@ -619,14 +623,17 @@ struct Engine {
         a.scan_shift = analyze_shift(a.mode);
         const bool sizing = size || learned[(size_t)idx] < 0;
         // After sizing, rows get a fixed stride (the largest structural row
-        // seen, rounded up to 16 entries, at least 16) when that takes no more
-        // room than the scanned upper bounds, or when every row was empty: no
-        // scan, and the rows lie close together.
+        // seen, rounded up to 16 entries, at least 16) when that takes at most
+        // kStrideRoom times the room of the scanned upper bounds (rows of
+        // uneven length, as in a joined batch, still qualify), or when every
+        // row was empty: no offsets scan, and the small-row tier can take the
+        // row's analysis into its own kernel.
         a.row_stride = 0;
         if (!sizing) {
             const int64_t ns_max = learned_ns[(size_t)idx];
             const int64_t stride = std::max<int64_t>(16, (ns_max + 15) / 16 * 16);
-            if (ns_max == 0 || stride <= learned[(size_t)idx] / std::max<int64_t>(n, 1)) a.row_stride = stride;
+            if (ns_max == 0 || stride <= kStrideRoom * (learned[(size_t)idx] / std::max<int64_t>(n, 1)))
+                a.row_stride = stride;
         }
         FPS_TRY(out.ensure_cap(a.row_stride > 0 ? a.row_stride * n : std::max<int64_t>(learned[(size_t)idx], 0)));
         a.out = out.out();  // the analysis writes the row offsets (out.off)
