@@ -392,6 +392,7 @@ struct Engine {
     std::vector<int64_t> learned;  // per stage index: output capacity learned by a sizing run
     std::vector<int64_t> learned_ns;  // per stage index: largest structural row seen by a sizing run
     std::vector<int64_t> learned_words;  // per stage index: widest row window (32-column words) seen by a sizing run
+    std::vector<int64_t> learned_big;    // per stage index: rows beyond the small-row tier in a sizing run
     std::vector<int> fused;  // per stage index: the last run did the analysis in the small-row kernel
     std::vector<int64_t> learned_wide;    // per stage: rows a sizing run sent to the wide shared-memory tier
     std::vector<int64_t> learned_global;  // per stage: rows a sizing run sent to the device-memory kernel
@@ -422,7 +423,7 @@ struct Engine {
         std::vector<unsigned long long> h((size_t)(kPartCount * ws.part_stride));
         HIP_TRY(hipMemcpy(h.data(), part(i), sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost));
         for (int k = 0; k < kPartCount; ++k) {
-            const bool per_row_block = k == kPartKept || k == kPartMaxNs || k == kPartMaxWords ||
+            const bool per_row_block = k == kPartKept || k == kPartMaxNs || k == kPartMaxWords || k == kPartBig ||
                                        (fused[(size_t)i] && k <= kPartRowsSkipped);
             const bool maximum = k == kPartMaxNs || k == kPartMaxWords;
             const int64_t cnt = per_row_block ? nk : na;
@@ -446,6 +447,7 @@ struct Engine {
         learned.assign((size_t)stages, -1);
         learned_ns.assign((size_t)stages, 0);
         learned_words.assign((size_t)stages, 0);
+        learned_big.assign((size_t)stages, 0);
         fused.assign((size_t)stages, 0);
         learned_wide.assign((size_t)stages, 0);
         learned_global.assign((size_t)stages, 0);
@@ -643,10 +645,14 @@ struct Engine {
         // scan).  (Taking the analysis into the 64-lane kernel as well made
         // its long rows slower than the separate launch costs.)
         const bool wide_rows = !sizing && !a.force_global && learned_wide[(size_t)idx] * 8 > n;
+        // (or, with fixed row strides, most of them: the others, which the
+        // sizing run counted, go on to the wide tier)
+        const bool small_all = small_tier_fits(n, learned_ns[(size_t)idx], learned_words[(size_t)idx]);
         const bool small = !sizing && !wide_rows && !a.force_global && !a.has_e && !(flags & FPS_FLAG_NO_SMALL) &&
                            !learned_dense[(size_t)idx] && learned_wide[(size_t)idx] == 0 &&
                            learned_global[(size_t)idx] == 0 &&
-                           small_tier_fits(n, learned_ns[(size_t)idx], learned_words[(size_t)idx]);
+                           (small_all || (a.row_stride > 0 && small_tier_most(n, learned_big[(size_t)idx])));
+        const int64_t small_deferred = (small && !small_all) ? learned_big[(size_t)idx] : 0;
         a.fuse_analysis = (small && a.row_stride > 0 && a.prod_acc == nullptr) ? 1 : 0;
         fused[(size_t)idx] = a.fuse_analysis;
         if (!a.fuse_analysis) HIP_TRY(launch_analyze(a, s));
@@ -664,7 +670,7 @@ struct Engine {
             FPS_TRY(out.ensure_cap(total));
             learned[(size_t)idx] = std::max<int64_t>(learned[(size_t)idx], total);
         } else {
-            run_wide = learned_wide[(size_t)idx] > 0 && !a.force_global;
+            run_wide = (learned_wide[(size_t)idx] > 0 || small_deferred > 0) && !a.force_global;
             run_global = learned_global[(size_t)idx] > 0 || a.force_global;
         }
         // a dense path for a product stage whose work has gone dense
@@ -718,7 +724,8 @@ struct Engine {
             run_wide = c.fb_count > 0;
         }
         if (run_wide)
-            HIP_TRY(launch_numeric_wide(a, grid_for_rows(learned_wide[(size_t)idx], numeric_wide_blocks(n)), s));
+            HIP_TRY(launch_numeric_wide(
+                a, grid_for_rows(std::max(learned_wide[(size_t)idx], small_deferred), numeric_wide_blocks(n)), s));
         if (sizing) {
             HIP_TRY(hipMemcpyAsync(&c, ctr(idx), sizeof(c), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
@@ -741,6 +748,7 @@ struct Engine {
             FPS_TRY(stage_totals(idx, a.mode, tot));
             learned_ns[(size_t)idx] = std::max<int64_t>(learned_ns[(size_t)idx], (int64_t)tot[kPartMaxNs]);
             learned_words[(size_t)idx] = std::max<int64_t>(learned_words[(size_t)idx], (int64_t)tot[kPartMaxWords]);
+            learned_big[(size_t)idx] = std::max<int64_t>(learned_big[(size_t)idx], (int64_t)tot[kPartBig]);
         }
         return FPS_OK;
     }

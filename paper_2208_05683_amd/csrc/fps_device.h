@@ -105,7 +105,9 @@ struct Alg1Params {
 // the widest window of its rows in 32-column words (maxima, not sums; the
 // window width is written by the shared-memory tiers only).  kPartANnz is the
 // product analysis' count of the left operand's stored entries in the block's
-// rows (the dense-rows cost model reads it).
+// rows (the dense-rows cost model reads it).  kPartBig counts the block's
+// rows beyond the small-row tier (written by the 64-lane shared-memory
+// kernels).
 enum PartIndex : int {
     kPartProducts = 0,
     kPartProductsSkipped = 1,
@@ -114,7 +116,8 @@ enum PartIndex : int {
     kPartMaxNs = 4,
     kPartMaxWords = 5,
     kPartANnz = 6,
-    kPartCount = 7
+    kPartBig = 7,
+    kPartCount = 8
 };
 constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 
@@ -263,9 +266,12 @@ hipError_t launch_numeric_wide_rows(const StageArgs& a, hipStream_t s);
 // Every row of a stage on a 16-lane DPP row (four rows per wavefront); rows
 // beyond the tier go to the wide tier's list.  small_tier_fits tells
 // whether a stage of n rows whose largest structural row and widest window
-// (32-column words) are max_ns and max_words should run in the tier.
+// (32-column words) are max_ns and max_words should run in the tier;
+// small_tier_most, whether one with `big` rows beyond the tier should run
+// there all the same (those rows then go to the wide tier).
 hipError_t launch_numeric_small(const StageArgs& a, int64_t max_ns, int64_t max_words, hipStream_t s);
 bool small_tier_fits(int64_t n, int64_t max_ns, int64_t max_words);
+bool small_tier_most(int64_t n, int64_t big);
 // rows of fb_list (persistent blocks: the grid size only sets the parallelism)
 hipError_t launch_numeric_wide(const StageArgs& a, int grid, hipStream_t s);
 // rows of fb2_list

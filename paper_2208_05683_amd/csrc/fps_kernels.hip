@@ -38,6 +38,8 @@ namespace {
 // the narrow tier): 6912 columns and 512 entries, 26.5 KB per block, six
 // blocks per CU.  Larger rows take the device-memory kernel.
 constexpr int kNarrowWords = 192, kNarrowCap = 320;
+// small-row tier (four rows per wavefront): window words and entries per row
+constexpr int kSmallWords = 96, kSmallCap = 96;
 constexpr int kWideWords = 216, kWideCap = 512;
 // Rows beyond the wide tier: in the device-memory kernel, with structure and
 // accumulator still in shared memory up to 8192 columns and 2048 entries
@@ -1733,15 +1735,17 @@ __device__ __forceinline__ void numeric_rows(const StageArgs& P)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long t = 0, mx = 0, mw = 0;
+        unsigned long long t = 0, mx = 0, mw = 0, big = 0;
         for (int i = 0; i < kWavesPerBlock; ++i) {
             t += kept_sh[i];
             mx = max(mx, ns_sh[i]);
             mw = max(mw, words_sh[i]);
+            big += (ns_sh[i] > (unsigned long long)kSmallCap || words_sh[i] > (unsigned long long)kSmallWords) ? 1 : 0;
         }
         P.part[kPartKept * P.part_stride + blk] = t;
         P.part[kPartMaxNs * P.part_stride + blk] = mx;
         P.part[kPartMaxWords * P.part_stride + blk] = mw;
+        P.part[kPartBig * P.part_stride + blk] = big;
     }
 }
 
@@ -1777,11 +1781,13 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(6, 
 constexpr int kSmallLanes = 16;
 constexpr int kSmallRowsPerWave = kWave / kSmallLanes;
 constexpr int kSmallRowsPerBlock = kBlock / kSmallLanes;
-constexpr int kSmallWords = 96, kSmallCap = 96;
 // The tier pays only when a stage has more rows than the 64-lane kernel holds
 // at once (eight wavefronts per SIMD on 256 CUs): with fewer, both finish in
 // one round and a row's own chain, shorter on 64 lanes, sets the time.
 constexpr int64_t kSmallMinRows = 256 * 4 * 8;
+// ... and takes a stage most of whose rows fit it when at most one row in
+// kSmallBigShare does not (those go to the wide tier's list)
+constexpr int64_t kSmallBigShare = 16;
 constexpr int kSmallU = 2;  // terms whose first 32 entries are loaded together
 
 template <int kWords, int kCap>
@@ -2911,6 +2917,11 @@ hipError_t launch_numeric_small(const StageArgs& a, int64_t max_ns, int64_t max_
 bool small_tier_fits(int64_t n, int64_t max_ns, int64_t max_words)
 {
     return n > kSmallMinRows && max_ns <= kSmallCap && max_words <= kSmallWords;
+}
+
+bool small_tier_most(int64_t n, int64_t big)
+{
+    return n > kSmallMinRows && big * kSmallBigShare <= n;
 }
 
 hipError_t launch_numeric_wide_rows(const StageArgs& a, hipStream_t s)
