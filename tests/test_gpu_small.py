@@ -161,3 +161,29 @@ def test_small_tier_operand_change():
         assert_same_csr(download(plan.result()), want1, "first operand again")
     finally:
         plan.close()
+
+
+def test_small_tier_takes_a_stage_with_a_few_long_rows():
+    """A block-diagonal operand: 11,400 rows of a band of half-width 4 and
+    600 rows (5%, under one in 16) of a band of half-width 14, whose fourth
+    power's rows (113 entries) outgrow the small-row tier while the fixed
+    stride (128) stays within four times the mean row bound (35).  The stage
+    still runs in the tier and sends those rows on to the wide tier; every
+    evaluation equals the oracle and the 64-lane plan bit for bit."""
+    import scipy.sparse as sp
+
+    a = G.random_banded(11400, 4, 0.8, None, seed=41).to_scipy()
+    b = G.random_banded(600, 14, 1.0, None, seed=42).to_scipy()
+    M = sp.block_diag([a, b], format="csr")
+    M = M / abs(M).sum(axis=0).max()
+    Z = G._from_scipy(sp.csr_matrix(M))
+    c, m, s, tau = G.exp_coeffs(16), 16, 4, 1e-12
+    want, _ = O.filtered_ps(Z, c, m, s, tau)
+    got, gst, ref, rst = _run_both(Z, c, m, s, tau)
+    mixed = [i for i in _small_stages(gst) if gst["stage_max_ns"][i] > 96]
+    assert mixed, (gst["stage_small"], gst["stage_max_ns"])
+    assert gst["rows_wide"] > 0
+    for e, g in enumerate(got):
+        check_canonical(g)
+        assert_same_csr(g, want, f"mixed rows eval {e}")
+    assert_same_csr(ref[-1], want, "mixed rows on 64-lane wavefronts")
