@@ -598,6 +598,35 @@ struct Engine {
     // Runs one stage into `out`.  With `size` true the stream is synchronised to
     // read the output bound and the buffers are grown to fit; otherwise the
     // capacities learned earlier are used as they are.
+    // The fixed row stride of stage idx after its sizing run (0: scanned
+    // offsets; see run()).
+    int64_t fixed_stride(int idx, int64_t n) const
+    {
+        const int64_t ns_max = learned_ns[(size_t)idx];
+        const int64_t stride = std::max<int64_t>(16, (ns_max + 15) / 16 * 16);
+        if (ns_max == 0 || stride <= kStrideRoom * (learned[(size_t)idx] / std::max<int64_t>(n, 1))) return stride;
+        return 0;
+    }
+
+    // Output buffers that the fixed strides of the next evaluation will need
+    // larger than the sizing run left them: grown at the end of the sizing
+    // evaluation (once its work is done), so that the evaluation after it
+    // allocates nothing.
+    std::vector<std::pair<SlackMatrix*, int64_t>> grow_after_sizing;
+    void note_stride_room(int idx, SlackMatrix& out, int64_t n)
+    {
+        const int64_t stride = fixed_stride(idx, n);
+        if (stride > 0 && stride * n > out.cap) grow_after_sizing.emplace_back(&out, stride * n);
+    }
+    fps_status grow_for_strides(hipStream_t s)
+    {
+        if (grow_after_sizing.empty()) return FPS_OK;
+        HIP_TRY(hipStreamSynchronize(s));  // the buffers' sizing contents are no longer read
+        for (auto& g : grow_after_sizing) FPS_TRY(g.first->ensure_cap(g.second));
+        grow_after_sizing.clear();
+        return FPS_OK;
+    }
+
     fps_status run(int idx, StageArgs& a, SlackMatrix& out, hipStream_t s, bool size, StageRecord* rec)
     {
         const int64_t n = ws.n;
@@ -630,13 +659,7 @@ struct Engine {
         // uneven length, as in a joined batch, still qualify), or when every
         // row was empty: no offsets scan, and the small-row tier can take the
         // row's analysis into its own kernel.
-        a.row_stride = 0;
-        if (!sizing) {
-            const int64_t ns_max = learned_ns[(size_t)idx];
-            const int64_t stride = std::max<int64_t>(16, (ns_max + 15) / 16 * 16);
-            if (ns_max == 0 || stride <= kStrideRoom * (learned[(size_t)idx] / std::max<int64_t>(n, 1)))
-                a.row_stride = stride;
-        }
+        a.row_stride = sizing ? 0 : fixed_stride(idx, n);
         FPS_TRY(out.ensure_cap(a.row_stride > 0 ? a.row_stride * n : std::max<int64_t>(learned[(size_t)idx], 0)));
         a.out = out.out();  // the analysis writes the row offsets (out.off)
         // a stage whose sizing run kept every row within the small-row tier
@@ -690,6 +713,7 @@ struct Engine {
                 unsigned long long tot[kPartCount];
                 FPS_TRY(stage_totals(idx, a.mode, tot));
                 learned_ns[(size_t)idx] = std::max<int64_t>(learned_ns[(size_t)idx], (int64_t)tot[kPartMaxNs]);
+                note_stride_room(idx, out, n);
             }
             return FPS_OK;
         }
@@ -749,6 +773,7 @@ struct Engine {
             learned_ns[(size_t)idx] = std::max<int64_t>(learned_ns[(size_t)idx], (int64_t)tot[kPartMaxNs]);
             learned_words[(size_t)idx] = std::max<int64_t>(learned_words[(size_t)idx], (int64_t)tot[kPartMaxWords]);
             learned_big[(size_t)idx] = std::max<int64_t>(learned_big[(size_t)idx], (int64_t)tot[kPartBig]);
+            note_stride_room(idx, out, n);
         }
         return FPS_OK;
     }
@@ -896,7 +921,12 @@ struct Engine {
         const int64_t n = m.n;
         c.n = n;
         FPS_TRY(c.rp.ensure(sizeof(int64_t) * (size_t)(n + 1)));
-        const int64_t want = std::max<int64_t>(m.cap, 1);
+        // room for every entry m can hold, now and (after a sizing run) with
+        // the capacity its fixed stride will give it, so that the evaluations
+        // after the sizing one do not grow the result
+        int64_t want = std::max<int64_t>(m.cap, 1);
+        for (const auto& g : grow_after_sizing)
+            if (g.first == &m) want = std::max(want, g.second + g.second / 8);
         if (want > c.cap) {
             FPS_TRY(c.col.ensure(sizeof(int32_t) * (size_t)want));
             FPS_TRY(c.val.ensure(sizeof(double) * (size_t)want));
@@ -1371,6 +1401,7 @@ struct fps_plan_s {
             final_m = &S[cur];
         }
         FPS_TRY(eng.compact(*final_m, result, s));
+        if (size) FPS_TRY(eng.grow_for_strides(s));
         return FPS_OK;
     }
 };
