@@ -613,8 +613,10 @@ struct Engine {
     // evaluation (once its work is done), so that the evaluation after it
     // allocates nothing.
     std::vector<std::pair<SlackMatrix*, int64_t>> grow_after_sizing;
+    bool one_shot = false;  // the plan is evaluated once (a served request): nothing to prepare
     void note_stride_room(int idx, SlackMatrix& out, int64_t n)
     {
+        if (one_shot) return;
         const int64_t stride = fixed_stride(idx, n);
         if (stride > 0 && stride * n > out.cap) grow_after_sizing.emplace_back(&out, stride * n);
     }
@@ -2657,6 +2659,7 @@ struct fps_server_s {
         fps_status stt = plan_create_limited(&p, &r->Z, r->c.data(), r->m, r->s, &fo, o.flags,
                                              reinterpret_cast<fps_stream>(st), r->reserve,
                                              o.no_grow ? nullptr : &extend_hook, r);
+        if (stt == FPS_OK) p->eng.one_shot = true;  // one evaluation per request
         if (stt == FPS_OK) stt = fps_eval(p, reinterpret_cast<fps_stream>(st));
         if (stt == FPS_OK) stt = finish(p);
         if (stt == FPS_OK) {
