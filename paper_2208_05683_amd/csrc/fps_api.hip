@@ -2668,8 +2668,11 @@ struct fps_server_s {
             int64_t nnz = 0;
             stt = fps_result_nnz(p, &nnz);
             // the copy exists beside the plan for a moment: it must fit the
-            // reservation too
-            const size_t copy = sizeof(int64_t) * (size_t)(n + 1) + 12 * (size_t)std::max<int64_t>(nnz, 1) + 768;
+            // reservation too (its three buffers as the pool hands them out,
+            // rounded up to the pool's size classes)
+            auto cls = [](size_t b) { return DevPool::size_class(std::max<size_t>(b, 256)); };
+            const size_t e = (size_t)std::max<int64_t>(nnz, 1);
+            const size_t copy = cls(sizeof(int64_t) * (size_t)(n + 1)) + cls(sizeof(int32_t) * e) + cls(sizeof(double) * e);
             if (stt == FPS_OK && !p->acct.admit(copy))
                 stt = set_error(FPS_ERR_CAPACITY, "the result copy does not fit the reservation");
             if (stt == FPS_OK) stt = r->rp.ensure(sizeof(int64_t) * (size_t)(n + 1));
