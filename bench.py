@@ -145,8 +145,9 @@ def bench_serve(args, stream):
     m in 12..30, tau = 1e-12; a pool of distinct requests kept on the device
     and submitted in turn).  Throughputs: plain sequential evaluations (plan,
     evaluation, result size, release, one request after the other, as the
-    plain API does them) and, at saturation, a one-slot server (the plain
-    path behind a queue, buffers reused) and the multi-slot server.  Then
+    plain API does them) and, at saturation (the median of three runs), a
+    one-slot server (the plain path behind a queue, buffers reused) and the
+    multi-slot server.  Then
     Poisson arrivals at fractions of the plain rate and of the server's
     saturation rate, with p50/p99 of arrival-to-result-ready latency.  Both
     servers are long-lived and warmed on the request pool first."""
@@ -222,11 +223,16 @@ def bench_serve(args, stream):
     try:
         for sv in servers.values():  # warm: threads, streams and the buffer pools
             run(sv, None, len(pool), 0, 1)
+        # saturation: three runs of `count` requests submitted at once, the
+        # run of median throughput reported (one run alone can be spoiled by
+        # a single stall of the host or the device)
         sat = {}
         for name, sv in servers.items():
-            x, lat, failed = run(sv, None, count, 0, 2)
+            runs = sorted((run(sv, None, count, 0, 2 + k) for k in range(3)), key=lambda t: t[0])
+            x, lat, failed = runs[1]
             sat[name] = {"evals_per_s": x, "p50_ms": float(np.percentile(lat, 50)),
-                         "p99_ms": float(np.percentile(lat, 99)), "failed": failed}
+                         "p99_ms": float(np.percentile(lat, 99)), "failed": failed,
+                         "runs_evals_per_s": [t[0] for t in runs]}
         x_srv = sat["server"]["evals_per_s"]
         levels = []
         for base_name, base in (("plain", x_plain), ("server", x_srv)):
