@@ -393,6 +393,7 @@ struct Engine {
     std::vector<int64_t> learned_ns;  // per stage index: largest structural row seen by a sizing run
     std::vector<int64_t> learned_words;  // per stage index: widest row window (32-column words) seen by a sizing run
     std::vector<int64_t> learned_big;    // per stage index: rows beyond the small-row tier in a sizing run
+    std::vector<int64_t> learned_stride;  // per stage index: fixed row stride chosen by a sizing run (0: scanned)
     std::vector<int> fused;  // per stage index: the last run did the analysis in the small-row kernel
     std::vector<int64_t> learned_wide;    // per stage: rows a sizing run sent to the wide shared-memory tier
     std::vector<int64_t> learned_global;  // per stage: rows a sizing run sent to the device-memory kernel
@@ -448,6 +449,7 @@ struct Engine {
         learned_ns.assign((size_t)stages, 0);
         learned_words.assign((size_t)stages, 0);
         learned_big.assign((size_t)stages, 0);
+        learned_stride.assign((size_t)stages, 0);
         fused.assign((size_t)stages, 0);
         learned_wide.assign((size_t)stages, 0);
         learned_global.assign((size_t)stages, 0);
@@ -595,30 +597,37 @@ struct Engine {
         return FPS_OK;
     }
 
-    // Runs one stage into `out`.  With `size` true the stream is synchronised to
-    // read the output bound and the buffers are grown to fit; otherwise the
-    // capacities learned earlier are used as they are.
-    // The fixed row stride of stage idx after its sizing run (0: scanned
-    // offsets; see run()).
-    int64_t fixed_stride(int idx, int64_t n) const
-    {
-        const int64_t ns_max = learned_ns[(size_t)idx];
-        const int64_t stride = std::max<int64_t>(16, (ns_max + 15) / 16 * 16);
-        if (ns_max == 0 || stride <= kStrideRoom * (learned[(size_t)idx] / std::max<int64_t>(n, 1))) return stride;
-        return 0;
-    }
-
-    // Output buffers that the fixed strides of the next evaluation will need
-    // larger than the sizing run left them: grown at the end of the sizing
-    // evaluation (once its work is done), so that the evaluation after it
-    // allocates nothing.
+    // The row placement of stage idx after its sizing run: a fixed stride (the
+    // largest structural row rounded up to 16 entries, at least 16) when that
+    // takes no more room than the scanned row bounds, or up to kStrideRoom
+    // times that room if the extra device memory is at hand (a quarter of the
+    // free memory, within the plan's limit); else 0, scanned offsets.
+    // Output buffers that the stride needs larger than the sizing run left
+    // them are grown at the end of the sizing evaluation (once its work is
+    // done), so that the evaluation after it allocates nothing.
     std::vector<std::pair<SlackMatrix*, int64_t>> grow_after_sizing;
     bool one_shot = false;  // the plan is evaluated once (a served request): nothing to prepare
-    void note_stride_room(int idx, SlackMatrix& out, int64_t n)
+    void decide_stride(int idx, SlackMatrix& out, int64_t n)
     {
+        learned_stride[(size_t)idx] = 0;
         if (one_shot) return;
-        const int64_t stride = fixed_stride(idx, n);
-        if (stride > 0 && stride * n > out.cap) grow_after_sizing.emplace_back(&out, stride * n);
+        const int64_t ns_max = learned_ns[(size_t)idx];
+        const int64_t stride = std::max<int64_t>(16, (ns_max + 15) / 16 * 16);
+        const int64_t bound = learned[(size_t)idx] / std::max<int64_t>(n, 1);
+        bool ok = ns_max == 0 || stride <= bound;
+        if (!ok && stride <= kStrideRoom * bound) {
+            const double per_entry = sizeof(int32_t) + sizeof(double) + sizeof(uint2);  // column, value, word
+            const double extra = per_entry * (double)std::max<int64_t>(0, stride * n - out.cap);
+            size_t fr = 0, tot = 0;
+            if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+                (void)hipGetLastError();
+                fr = 0;
+            }
+            ok = extra <= 0.25 * (double)fr && (!t_acct || (double)t_acct->used + extra <= (double)t_acct->cap);
+        }
+        if (!ok) return;
+        learned_stride[(size_t)idx] = stride;
+        if (stride * n > out.cap) grow_after_sizing.emplace_back(&out, stride * n);
     }
     fps_status grow_for_strides(hipStream_t s)
     {
@@ -629,6 +638,9 @@ struct Engine {
         return FPS_OK;
     }
 
+    // Runs one stage into `out`.  With `size` true the stream is synchronised to
+    // read the output bound and the buffers are grown to fit; otherwise the
+    // capacities learned earlier are used as they are.
     fps_status run(int idx, StageArgs& a, SlackMatrix& out, hipStream_t s, bool size, StageRecord* rec)
     {
         const int64_t n = ws.n;
@@ -661,7 +673,7 @@ struct Engine {
         // uneven length, as in a joined batch, still qualify), or when every
         // row was empty: no offsets scan, and the small-row tier can take the
         // row's analysis into its own kernel.
-        a.row_stride = sizing ? 0 : fixed_stride(idx, n);
+        a.row_stride = sizing ? 0 : learned_stride[(size_t)idx];
         FPS_TRY(out.ensure_cap(a.row_stride > 0 ? a.row_stride * n : std::max<int64_t>(learned[(size_t)idx], 0)));
         a.out = out.out();  // the analysis writes the row offsets (out.off)
         // a stage whose sizing run kept every row within the small-row tier
@@ -715,7 +727,7 @@ struct Engine {
                 unsigned long long tot[kPartCount];
                 FPS_TRY(stage_totals(idx, a.mode, tot));
                 learned_ns[(size_t)idx] = std::max<int64_t>(learned_ns[(size_t)idx], (int64_t)tot[kPartMaxNs]);
-                note_stride_room(idx, out, n);
+                decide_stride(idx, out, n);
             }
             return FPS_OK;
         }
@@ -775,7 +787,7 @@ struct Engine {
             learned_ns[(size_t)idx] = std::max<int64_t>(learned_ns[(size_t)idx], (int64_t)tot[kPartMaxNs]);
             learned_words[(size_t)idx] = std::max<int64_t>(learned_words[(size_t)idx], (int64_t)tot[kPartMaxWords]);
             learned_big[(size_t)idx] = std::max<int64_t>(learned_big[(size_t)idx], (int64_t)tot[kPartBig]);
-            note_stride_room(idx, out, n);
+            decide_stride(idx, out, n);
         }
         return FPS_OK;
     }
