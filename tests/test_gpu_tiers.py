@@ -137,3 +137,33 @@ def test_repeated_evaluations_after_sizing(case):
         assert plan.stats()["resizes"] == 0
     finally:
         plan.close()
+
+
+def test_evaluation_after_sizing_allocates_nothing():
+    """A band whose products' rows are uneven (shorter at the band's ends):
+    the fixed row strides of some stages take more room than the scanned row
+    bounds, and the sizing evaluation grows those buffers (and the result) at
+    its end, so the evaluations after it allocate no device memory; every
+    evaluation equals the oracle bit for bit."""
+    import torch
+    from paper_2208_05683_amd import api
+
+    Z = G.banded_sweep_matrix(10, 1000, seed=10000)
+    c, m, s, tau = G.exp_coeffs(30), 30, 5, 0.0
+    want, _ = O.filtered_ps(Z, c, m, s, tau)
+    plan = api.Plan(upload(Z), c, m, s, tau)
+    try:
+        plan.eval()
+        assert_same_csr(download(plan.result()), want, "sizing evaluation")
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
+        for k in range(3):
+            plan.eval()
+            torch.cuda.synchronize()
+            assert torch.cuda.mem_get_info()[0] == free0, f"evaluation {k} after sizing changed free device memory"
+        got = download(plan.result())
+        check_canonical(got)
+        assert_same_csr(got, want, "evaluations after sizing")
+        assert plan.stats()["resizes"] == 0
+    finally:
+        plan.close()
