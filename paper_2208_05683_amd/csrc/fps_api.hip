@@ -566,10 +566,7 @@ struct Engine {
             // A stays sparse: its rows stream B's dense rows in term order
             HIP_TRY(launch_fill_u64(dB.as<unsigned long long>(), count, 0ull, s));
             HIP_TRY(launch_densify(a.B, n, ld, dB.as<double>(), s));
-            if (a.has_blk) {
-                HIP_TRY(launch_fill_u64(dE.as<unsigned long long>(), count, 0ull, s));
-                HIP_TRY(launch_dense_terms(a.T, n, ld, dE.as<double>(), s));
-            }
+            if (a.has_blk) HIP_TRY(launch_dense_terms(a.T, n, ld, dE.as<double>(), s));
             HIP_TRY(launch_spmm_rows(a.A, dB.as<double>(), dE.as<double>(), ld, n, a.has_blk, a.tau, a.tau_row, s));
             HIP_TRY(launch_dense_to_slack(dE.as<double>(), ld, a, s));
             return FPS_OK;
@@ -583,10 +580,7 @@ struct Engine {
         }
         HIP_TRY(launch_fill_u64(dB.as<unsigned long long>(), count, 0ull, s));
         HIP_TRY(launch_densify(a.B, n, ld, dB.as<double>(), s));
-        if (a.has_blk) {
-            HIP_TRY(launch_fill_u64(dE.as<unsigned long long>(), count, 0ull, s));
-            HIP_TRY(launch_dense_terms(a.T, n, ld, dE.as<double>(), s));
-        }
+        if (a.has_blk) HIP_TRY(launch_dense_terms(a.T, n, ld, dE.as<double>(), s));  // (every entry written)
         if (mode == kDenseOrdered)
             HIP_TRY(launch_dgemm_ordered(dA.as<double>(), dB.as<double>(), dE.as<double>(), ld, n, a.has_blk, a.tau,
                                          a.tau_row, s));

@@ -46,44 +46,90 @@ __global__ void __launch_bounds__(kB) k_densify(MatView M, int64_t n, int64_t ld
     for (int64_t p = b + l; p < e; p += kWave) row[M.col[p]] = M.val[p];
 }
 
-// E[r][.] = sum_t coef_t M_t[r][.] accumulated over ascending t with one
-// fused multiply-add per term from +0 (E zero beforehand; M_t the identity
-// when beg[t] is null).  One thread per (row, chunk of kTermCols columns):
-// for each term in order it finds the chunk's entries in the term's sorted
-// row by binary search and applies them, so every entry of E is owned and
-// updated in term order by one thread.
-constexpr int kTermCols = 32;
+// E[r][c] = sum_t coef_t M_t[r][c] for columns c < n, accumulated over
+// ascending t with one fused multiply-add per stored entry from +0 (M_t the
+// identity when beg[t] is null); every such entry of E is written, zeros
+// included, so E needs no clearing.  One wavefront per (row, chunk of
+// kTermCols columns): the chunk is summed in shared memory term by term (the
+// entries of one term row have distinct columns, so its lanes never meet on
+// one slot; terms are ordered by a wavefront barrier), then written out in
+// one coalesced pass.
+constexpr int kTermCols = 1024;  // 8 KB of shared memory per wavefront
+constexpr int kTermWaves = kB / kWave;
+
+__device__ __forceinline__ void dense_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The first position p in [lo, hi) of the sorted columns cl with
+// cl[p] >= key, hi if there is none; the same on every lane.  Each round
+// probes 64 evenly spaced positions at once and keeps the piece between the
+// last probe below the key and the first one at or above it (a 64-fold
+// narrowing per dependent load); the last piece, at most 64 positions, is
+// read whole.
+__device__ __forceinline__ int64_t first_at_least(const int32_t* __restrict__ cl, int64_t lo, int64_t hi, int32_t key)
+{
+    const int l = threadIdx.x % kWave;
+    while (hi - lo > kWave) {
+        const int64_t step = (hi - lo + kWave - 1) / kWave;
+        const int64_t q = min(lo + (int64_t)(l + 1) * step - 1, hi - 1);
+        const int j0 = __popcll(__ballot(cl[q] < key));  // probes below the key: a prefix
+        if (j0 == kWave) return hi;  // the last probe is hi - 1
+        const int64_t nlo = j0 > 0 ? min(lo + (int64_t)j0 * step - 1, hi - 1) + 1 : lo;
+        hi = min(lo + (int64_t)(j0 + 1) * step - 1, hi - 1);  // a probe at or above the key
+        lo = nlo;
+    }
+    const int64_t p = lo + l;
+    return lo + __popcll(__ballot(p < hi && cl[p] < key));
+}
 
 __global__ void __launch_bounds__(kB) k_dense_terms(Terms T, int64_t n, int64_t ld, double* E)
 {
+    __shared__ double acc_sh[kTermWaves][kTermCols];
+    const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
     const int64_t chunks = (n + kTermCols - 1) / kTermCols;
-    const int64_t id = (int64_t)blockIdx.x * kB + threadIdx.x;
-    if (id >= n * chunks) return;
-    const int64_t r = id / chunks;
-    const int32_t c0 = (int32_t)((id % chunks) * kTermCols), c1 = c0 + kTermCols;
-    double* row = E + r * ld;
+    const int64_t item = (int64_t)blockIdx.x * kTermWaves + wv;
+    if (item >= n * chunks) return;  // (no block-wide barrier below)
+    const int64_t r = item / chunks;
+    const int32_t c0 = (int32_t)((item % chunks) * kTermCols);
+    const int32_t c1 = (int32_t)min<int64_t>((int64_t)c0 + kTermCols, n);
+    double* acc = acc_sh[wv];
+    for (int i = l; i < kTermCols; i += kWave) acc[i] = 0.0;
+    dense_wave_sync();
     for (int t = 0; t < T.n; ++t) {
         const double c = T.coef[t];
         if (T.beg[t] == nullptr) {
-            if (r >= c0 && r < c1) row[r] = fma(c, 1.0, row[r]);
-            continue;
+            if (l == 0 && r >= c0 && r < c1) acc[r - c0] = fma(c, 1.0, acc[r - c0]);
+        } else {
+            const int32_t* __restrict__ cl = T.col[t];
+            const double* __restrict__ vl = T.val[t];
+            const int64_t e = T.end[t][r];
+            int64_t p0 = T.beg[t][r];
+            if (c0 > 0) p0 = first_at_least(cl, p0, e, c0);
+            // the chunk's entries in batches of 4 x 64 (column and value
+            // loads together); positions past the chunk come last in a sorted row
+            for (; p0 < e; p0 += 4 * kWave) {
+                int32_t k[4];
+                double v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t p = p0 + u * kWave + l;
+                    k[u] = p < e ? cl[p] : INT_MAX;
+                    v[u] = p < e ? vl[p] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (k[u] < c1) acc[k[u] - c0] = fma(c, v[u], acc[k[u] - c0]);
+                if (__ballot(k[3] >= c1) != 0ull) break;  // the batch's last position is past the chunk
+            }
         }
-        const int32_t* cl = T.col[t];
-        int64_t lo = T.beg[t][r], hi = T.end[t][r];  // first entry with column >= c0
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (cl[mid] < c0)
-                lo = mid + 1;
-            else
-                hi = mid;
-        }
-        const int64_t e = T.end[t][r];
-        for (int64_t p = lo; p < e; ++p) {
-            const int32_t k = cl[p];
-            if (k >= c1) break;
-            row[k] = fma(c, T.val[t][p], row[k]);
-        }
+        dense_wave_sync();
     }
+    double* row = E + r * ld;
+    for (int32_t i = c0 + l; i < c1; i += kWave) row[i] = acc[i - c0];
 }
 
 // ---- the product on the matrix cores ----------------------------------------
@@ -439,8 +485,9 @@ hipError_t launch_densify(const MatView& M, int64_t n, int64_t ld, double* D, hi
 
 hipError_t launch_dense_terms(const Terms& T, int64_t n, int64_t ld, double* E, hipStream_t s)
 {
-    const int64_t chunks = (n + kTermCols - 1) / kTermCols;
-    hipLaunchKernelGGL(k_dense_terms, dim3(grid_for(n * chunks)), dim3(kB), 0, s, T, n, ld, E);
+    const int64_t items = n * ((n + kTermCols - 1) / kTermCols);
+    hipLaunchKernelGGL(k_dense_terms, dim3((unsigned)((items + kTermWaves - 1) / kTermWaves)), dim3(kB), 0, s, T, n,
+                       ld, E);
     return hipGetLastError();
 }
 

@@ -231,7 +231,8 @@ hipError_t launch_batch_extract(const int64_t* frp, const int32_t* fcol, int64_t
 int64_t dense_ld(int64_t n);
 // D[r][col] = val over the stored entries of M (D zero beforehand)
 hipError_t launch_densify(const MatView& M, int64_t n, int64_t ld, double* D, hipStream_t s);
-// E += sum_t coef_t M_t row by row, terms in order, one fma each (E zero beforehand)
+// E = sum_t coef_t M_t in rows and columns < n, terms in order, one fma each
+// from +0 (every such entry written, zeros included)
 hipError_t launch_dense_terms(const Terms& T, int64_t n, int64_t ld, double* E, hipStream_t s);
 // E = D_tau((has_e ? E : 0) + A B) on the matrix cores (tau per row if tau_row)
 hipError_t launch_dgemm_mfma(const double* A, const double* B, double* E, int64_t ld, int64_t n, int has_e, double tau,
