@@ -561,10 +561,8 @@ struct Engine {
         FPS_TRY(dE.ensure(bytes));
         if (ld != d_ld) dA_key = nullptr;
         d_ld = ld;
-        const int64_t count = (int64_t)(bytes / 8);
         if (mode == kDenseRows) {
             // A stays sparse: its rows stream B's dense rows in term order
-            HIP_TRY(launch_fill_u64(dB.as<unsigned long long>(), count, 0ull, s));
             HIP_TRY(launch_densify(a.B, n, ld, dB.as<double>(), s));
             if (a.has_blk) HIP_TRY(launch_dense_terms(a.T, n, ld, dE.as<double>(), s));
             HIP_TRY(launch_spmm_rows(a.A, dB.as<double>(), dE.as<double>(), ld, n, a.has_blk, a.tau, a.tau_row, s));
@@ -573,12 +571,10 @@ struct Engine {
         }
         FPS_TRY(dA.ensure(bytes));
         if (!(dA_key == a.A.col && dA_eval == eval_id)) {
-            HIP_TRY(launch_fill_u64(dA.as<unsigned long long>(), count, 0ull, s));
             HIP_TRY(launch_densify(a.A, n, ld, dA.as<double>(), s));
             dA_key = a.A.col;
             dA_eval = eval_id;
         }
-        HIP_TRY(launch_fill_u64(dB.as<unsigned long long>(), count, 0ull, s));
         HIP_TRY(launch_densify(a.B, n, ld, dB.as<double>(), s));
         if (a.has_blk) HIP_TRY(launch_dense_terms(a.T, n, ld, dE.as<double>(), s));  // (every entry written)
         if (mode == kDenseOrdered)

@@ -32,20 +32,6 @@ __device__ __forceinline__ unsigned lanes_below64(unsigned long long mask)
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
-// ---- densify --------------------------------------------------------------
-
-// D[r][col] = val for the stored entries of M (D zero beforehand); one
-// wavefront per row (the columns of a row are distinct).
-__global__ void __launch_bounds__(kB) k_densify(MatView M, int64_t n, int64_t ld, double* D)
-{
-    const int64_t r = ((int64_t)blockIdx.x * kB + threadIdx.x) / kWave;
-    const int l = threadIdx.x % kWave;
-    if (r >= n) return;
-    const int64_t b = M.beg[r], e = M.end[r];
-    double* row = D + r * ld;
-    for (int64_t p = b + l; p < e; p += kWave) row[M.col[p]] = M.val[p];
-}
-
 // E[r][c] = sum_t coef_t M_t[r][c] for columns c < n, accumulated over
 // ascending t with one fused multiply-add per stored entry from +0 (M_t the
 // identity when beg[t] is null); every such entry of E is written, zeros
@@ -132,10 +118,54 @@ __global__ void __launch_bounds__(kB) k_dense_terms(Terms T, int64_t n, int64_t 
     for (int32_t i = c0 + l; i < c1; i += kWave) row[i] = acc[i - c0];
 }
 
+// ---- densify --------------------------------------------------------------
+
+// D = M as a dense ld x ld matrix with every entry written (zeros included,
+// the padding rows and columns beyond n too), so D needs no clearing.  One
+// wavefront per (row, chunk of kTermCols columns): the chunk is assembled in
+// shared memory (a row's columns are distinct) and written out whole.
+__global__ void __launch_bounds__(kB) k_densify(MatView M, int64_t n, int64_t ld, double* D)
+{
+    __shared__ double row_sh[kTermWaves][kTermCols];
+    const int wv = threadIdx.x / kWave, l = threadIdx.x % kWave;
+    const int64_t chunks = (ld + kTermCols - 1) / kTermCols;
+    const int64_t item = (int64_t)blockIdx.x * kTermWaves + wv;
+    if (item >= ld * chunks) return;  // (no block-wide barrier below)
+    const int64_t r = item / chunks;
+    const int32_t c0 = (int32_t)((item % chunks) * kTermCols);
+    const int32_t c1 = (int32_t)min<int64_t>((int64_t)c0 + kTermCols, ld);
+    double* sh = row_sh[wv];
+    for (int i = l; i < kTermCols; i += kWave) sh[i] = 0.0;
+    dense_wave_sync();
+    if (r < n) {
+        const int64_t e = M.end[r];
+        int64_t p0 = M.beg[r];
+        if (c0 > 0) p0 = first_at_least(M.col, p0, e, c0);
+        for (; p0 < e; p0 += 4 * kWave) {
+            int32_t k[4];
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t p = p0 + u * kWave + l;
+                k[u] = p < e ? M.col[p] : INT_MAX;
+                v[u] = p < e ? M.val[p] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (k[u] < c1) sh[k[u] - c0] = v[u];
+            if (__ballot(k[3] >= c1) != 0ull) break;  // the batch's last position is past the chunk
+        }
+        dense_wave_sync();
+    }
+    double* row = D + r * ld;
+    for (int32_t i = c0 + l; i < c1; i += kWave) row[i] = sh[i - c0];
+}
+
 // ---- the product on the matrix cores ----------------------------------------
 //
-// Block tile BM x BM of C, four wavefronts in 2 x 2, each a (BM/2) x (BM/2)
-// tile made of 16 x 16 MFMA tiles.  K advances in chunks of 16 staged in
+// Block tile BM x BM of C (128, 64 or 32: the largest that gives the chip
+// 512 blocks), four wavefronts in 2 x 2, each a (BM/2) x (BM/2) tile made
+// of 16 x 16 MFMA tiles.  K advances in chunks of 16 staged in
 // shared memory, A k-major and B row-major, so that the 16 lanes of a
 // quarter-wave read 16 consecutive doubles.  Lane layout of
 // v_mfma_f64_16x16x4f64 (wave64): lane l supplies A[l % 16][l / 16] and
@@ -473,13 +503,25 @@ __global__ void __launch_bounds__(kB) k_dense_to_slack(const double* __restrict_
     }
 }
 
+// Block tile of the dense products: the largest of 128, 64 and 32 whose
+// tiles number at least 512 (two blocks per CU), else 32; ld is a multiple
+// of 128.
+int dense_tile(int64_t ld)
+{
+    for (int bm = 128; bm > 32; bm /= 2)
+        if ((ld / bm) * (ld / bm) >= 512) return bm;
+    return 32;
+}
+
 }  // namespace
 
 int64_t dense_ld(int64_t n) { return (n + 127) / 128 * 128; }
 
 hipError_t launch_densify(const MatView& M, int64_t n, int64_t ld, double* D, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_densify, dim3(grid_for(n * kWave)), dim3(kB), 0, s, M, n, ld, D);
+    const int64_t items = ld * ((ld + kTermCols - 1) / kTermCols);
+    hipLaunchKernelGGL(k_densify, dim3((unsigned)((items + kTermWaves - 1) / kTermWaves)), dim3(kB), 0, s, M, n, ld,
+                       D);
     return hipGetLastError();
 }
 
@@ -494,32 +536,29 @@ hipError_t launch_dense_terms(const Terms& T, int64_t n, int64_t ld, double* E, 
 hipError_t launch_dgemm_mfma(const double* A, const double* B, double* E, int64_t ld, int64_t n, int has_e, double tau,
                              const double* tau_row, hipStream_t s)
 {
-    // 128 x 128 tiles when they give the chip enough blocks, else 64 x 64
-    const int64_t t128 = ld / 128;
-    if (t128 * t128 >= 512) {
-        hipLaunchKernelGGL(k_dgemm_mfma<128>, dim3((unsigned)t128, (unsigned)t128), dim3(kB), 0, s, A, B, E, ld, n,
-                           has_e, tau, tau_row);
-    } else {
-        const int64_t t64 = ld / 64;
-        hipLaunchKernelGGL(k_dgemm_mfma<64>, dim3((unsigned)t64, (unsigned)t64), dim3(kB), 0, s, A, B, E, ld, n, has_e,
-                           tau, tau_row);
-    }
+    // the largest tile (128, 64, 32) that gives the chip at least 512 blocks
+    const int bm = dense_tile(ld);
+    const unsigned t = (unsigned)(ld / bm);
+    if (bm == 128)
+        hipLaunchKernelGGL(k_dgemm_mfma<128>, dim3(t, t), dim3(kB), 0, s, A, B, E, ld, n, has_e, tau, tau_row);
+    else if (bm == 64)
+        hipLaunchKernelGGL(k_dgemm_mfma<64>, dim3(t, t), dim3(kB), 0, s, A, B, E, ld, n, has_e, tau, tau_row);
+    else
+        hipLaunchKernelGGL(k_dgemm_mfma<32>, dim3(t, t), dim3(kB), 0, s, A, B, E, ld, n, has_e, tau, tau_row);
     return hipGetLastError();
 }
 
 hipError_t launch_dgemm_ordered(const double* A, const double* B, double* E, int64_t ld, int64_t n, int has_e,
                                double tau, const double* tau_row, hipStream_t s)
 {
-    // 128 x 128 tiles when they give the chip enough blocks, else 64 x 64 (ld is a multiple of 128)
-    const int64_t t128 = ld / 128;
-    if (t128 * t128 >= 512) {
-        hipLaunchKernelGGL(k_dgemm_ordered<128>, dim3((unsigned)t128, (unsigned)t128), dim3(kB), 0, s, A, B, E, ld, n,
-                           has_e, tau, tau_row);
-    } else {
-        const int64_t t64 = ld / 64;
-        hipLaunchKernelGGL(k_dgemm_ordered<64>, dim3((unsigned)t64, (unsigned)t64), dim3(kB), 0, s, A, B, E, ld, n,
-                           has_e, tau, tau_row);
-    }
+    // as the matrix-core product, but not below 64 (ld is a multiple of 128):
+    // 32 x 32 tiles leave each thread four fma per two shared-memory reads
+    const int bt = std::max(64, dense_tile(ld));
+    const unsigned t = (unsigned)(ld / bt);
+    if (bt == 128)
+        hipLaunchKernelGGL(k_dgemm_ordered<128>, dim3(t, t), dim3(kB), 0, s, A, B, E, ld, n, has_e, tau, tau_row);
+    else
+        hipLaunchKernelGGL(k_dgemm_ordered<64>, dim3(t, t), dim3(kB), 0, s, A, B, E, ld, n, has_e, tau, tau_row);
     return hipGetLastError();
 }
 

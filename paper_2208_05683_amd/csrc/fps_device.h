@@ -229,7 +229,7 @@ hipError_t launch_batch_extract(const int64_t* frp, const int32_t* fcol, int64_t
 // ---- launch wrappers (fps_dense.hip) ------------------------------------
 // leading dimension of the dense operands: n rounded up to 128
 int64_t dense_ld(int64_t n);
-// D[r][col] = val over the stored entries of M (D zero beforehand)
+// D = M as a dense ld x ld matrix, every entry written (zeros included)
 hipError_t launch_densify(const MatView& M, int64_t n, int64_t ld, double* D, hipStream_t s);
 // E = sum_t coef_t M_t in rows and columns < n, terms in order, one fma each
 // from +0 (every such entry written, zeros included)

@@ -152,6 +152,29 @@ def test_dense_rows_horner_with_block_bitwise():
         assert_same_csr(got, want, f"q = 2 dense rows, evaluation {i}")
 
 
+@pytest.mark.parametrize("bw", [11, 15])
+def test_banded_series_mode_exact_dense_bitwise(bw):
+    # n = 1000 (ld = 1024: the smallest block tiles, 32 x 32) on the exact
+    # dense paths in series mode: the oracle's result bit for bit
+    from paper_2208_05683_amd import api, binding as B
+    from gpu_helpers import assert_same_csr
+
+    Z = G.banded_sweep_matrix(bw, 1000, seed=1000 * bw + 2)
+    a = G.exp_coeffs(199)
+    want, info, st, a1 = O.series(Z, a, 1e-14, 0.1)
+    plan = api.Plan.series(upload(Z), a, 1e-14, 0.1, flags=B.FPS_FLAG_DENSE_EXACT)
+    try:
+        for e in range(2):
+            plan.eval()
+            got = download(plan.result())
+            gst = plan.stats()
+            assert 3 in gst["stage_dense"], gst["stage_dense"]
+            check_canonical(got)
+            assert_same_csr(got, want, f"banded b = {bw}, exact dense paths, evaluation {e}")
+    finally:
+        plan.close()
+
+
 def test_lap3d_side20_dense_rows_against_stored_digest():
     # n = 8000 on the exact dense paths: the oracle's digest, bit for bit
     import hashlib
