@@ -437,29 +437,41 @@ __global__ void __launch_bounds__(kB) k_dense_to_slack(const double* __restrict_
         const double* row = C + r * ld;
         double amx = 0.0;
         int32_t first = INT_MAX, last = -1, nwd = 0;
-        for (int64_t c0 = 0; c0 < P.n; c0 += kWave) {
-            const int64_t c = c0 + l;
-            const double x = c < P.n ? row[c] : 0.0;
-            const bool nz = x != 0.0;
-            const unsigned long long m = __ballot(nz);
-            if (nz) {
-                const int64_t pos = kept + (int64_t)lanes_below64(m);
-                if (pos < room) {
-                    P.out.col[o + pos] = (int32_t)c;
-                    P.out.val[o + pos] = x;
-                }
-                amx = fmax(amx, fabs(x));
-                first = min(first, (int32_t)c);
-                last = max(last, (int32_t)c);
+        // 64 columns per step, the loads of four steps issued together
+        constexpr int kU = 4;
+        for (int64_t cb = 0; cb < P.n; cb += kU * kWave) {
+            double xs[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t c = cb + u * kWave + l;
+                xs[u] = c < P.n ? row[c] : 0.0;
             }
-            kept += __popcll(m);
-            // structure words: the chunk's two 32-column words (c0 is a multiple of 64)
-            const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
-            if (l == 0) {
-                if (lo && nwd < room) P.out.sw[o + nwd] = make_uint2((uint32_t)(c0 >> 5), lo);
-                nwd += lo ? 1 : 0;
-                if (hi && nwd < room) P.out.sw[o + nwd] = make_uint2((uint32_t)(c0 >> 5) + 1u, hi);
-                nwd += hi ? 1 : 0;
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t c0 = cb + u * kWave;
+                const int64_t c = c0 + l;
+                const double x = xs[u];
+                const bool nz = x != 0.0;
+                const unsigned long long m = __ballot(nz);
+                if (nz) {
+                    const int64_t pos = kept + (int64_t)lanes_below64(m);
+                    if (pos < room) {
+                        P.out.col[o + pos] = (int32_t)c;
+                        P.out.val[o + pos] = x;
+                    }
+                    amx = fmax(amx, fabs(x));
+                    first = min(first, (int32_t)c);
+                    last = max(last, (int32_t)c);
+                }
+                kept += __popcll(m);
+                // structure words: the step's two 32-column words (c0 is a multiple of 64)
+                const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+                if (l == 0) {
+                    if (lo && nwd < room) P.out.sw[o + nwd] = make_uint2((uint32_t)(c0 >> 5), lo);
+                    nwd += lo ? 1 : 0;
+                    if (hi && nwd < room) P.out.sw[o + nwd] = make_uint2((uint32_t)(c0 >> 5) + 1u, hi);
+                    nwd += hi ? 1 : 0;
+                }
             }
         }
 #pragma unroll
