@@ -16,9 +16,11 @@ on the mixed request stream, saturation and Poisson arrivals with p50/p99;
 skips it).
 
 Other lines (not the headline): --filter adaptive|series time Algorithm 1 and
-Algorithm 2 on the same matrix; --sweep banded times the paper's second test
-set (random banded 1000 x 1000, bandwidth 1..15, exp and cos, eps_tol 1e-14)
-against the unfiltered scheme and a dense fp64 Horner.
+Algorithm 2 on the same matrix; --workload lap3d|banded (with --side) and
+--dense|--dense-exact take other matrices and the dense paths; --sweep banded
+times the paper's second test set (random banded 1000 x 1000, bandwidth
+1..15, exp and cos, eps_tol 1e-14) against the unfiltered scheme and a dense
+fp64 Horner.
 """
 
 from __future__ import annotations
@@ -49,6 +51,12 @@ def workload(name, side=None):
         return G.config1()
     if name == "lap3d":
         return G.config3(side=side or 20)
+    if name == "banded":
+        # one matrix of the paper's second test set (n = 1000, half-bandwidth
+        # b = side, default 15, the sweep's first seed for that b)
+        b = side or 15
+        return dict(name=f"banded_n1000_b{b}_exp_m30_s6", Z=G.banded_sweep_matrix(b, 1000, seed=1000 * b),
+                    coeffs=G.exp_coeffs(30), m=30, s=6, tau=1e-12)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -459,8 +467,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="lap2d", help="lap2d (headline), lap1d, lap3d (with --side)")
-    ap.add_argument("--side", type=int, default=None, help="lap3d: grid side (default 20)")
+    ap.add_argument("--workload", default="lap2d",
+                    help="lap2d (headline), lap1d, lap3d (with --side), banded (n = 1000, half-bandwidth --side)")
+    ap.add_argument("--side", type=int, default=None, help="lap3d: grid side (default 20); banded: half-bandwidth (default 15)")
     ap.add_argument("--dense", action="store_true", help="FPS_FLAG_DENSE: dense products on the FP64 matrix cores")
     ap.add_argument("--dense-exact", action="store_true",
                     help="FPS_FLAG_DENSE_EXACT: filled-in products on the exact dense paths (bitwise)")
@@ -533,9 +542,12 @@ def main():
     elif args.filter == "series":
         from fps_inputs import generators as G
 
-        plan = api.Plan.series(Zd, G.exp_coeffs(59), args.eps_tol, args.e_r, flags=B.FPS_FLAG_TIMING)
+        plan = api.Plan.series(Zd, G.exp_coeffs(59), args.eps_tol, args.e_r,
+                               flags=B.FPS_FLAG_TIMING | (B.FPS_FLAG_DENSE if args.dense else 0)
+                               | (B.FPS_FLAG_DENSE_EXACT if args.dense_exact else 0))
         series_info = plan.series_info()
-        cfg = dict(cfg, name=cfg["name"].split("_m")[0] + f"_series_tol{args.eps_tol:g}",
+        dense_tag = "_dense" if args.dense else "_dense_exact" if args.dense_exact else ""
+        cfg = dict(cfg, name=cfg["name"].split("_m")[0] + f"_series_tol{args.eps_tol:g}" + dense_tag,
                    m=series_info["N"] - 1, s=series_info["q"])
         log(f"series mode: N = {series_info['N']}, q = {series_info['q']}, tail = {series_info['tail']:.3g}")
     else:
