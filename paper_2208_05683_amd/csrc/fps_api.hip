@@ -702,8 +702,12 @@ struct Engine {
         }
         // a dense path for a product stage whose work has gone dense
         int dense = kDenseNone;
+        // (not with dropped-entry statistics; Algorithm 1's first-iteration
+        // sums, without a drop, the dense write-out takes as well)
+        const bool sums_only =
+            a.dsum != nullptr && a.dcount == 0 && a.dthr > 0.0 && a.tau == 0.0 && a.tau_row == nullptr;
         if (a.mode == kModeProduct && !a.has_e && (flags & (FPS_FLAG_DENSE | FPS_FLAG_DENSE_EXACT)) &&
-            a.dsum == nullptr) {
+            (a.dsum == nullptr || sums_only)) {
             if (sizing) learned_dense[(size_t)idx] = want_dense(idx, learned[(size_t)idx], s);
             dense = learned_dense[(size_t)idx];
         }
@@ -811,16 +815,20 @@ struct Engine {
         alg1_fused = 0;
         if (device_iters == 0) device_iters = alg1_learned[(size_t)idx];
         if (device_iters <= 0 || !std::isfinite(eps_g) || !(eps_g > 0.0) || !kAlg1FuseFirst) return FPS_OK;
-        if (learned_dense[(size_t)idx]) return FPS_OK;  // the dense write-out takes no sums
+        // a stage on a dense path takes the first iteration's sums only (its
+        // product's write-out applies the stage's own threshold, which must
+        // then keep every nonzero)
+        const bool dense = learned_dense[(size_t)idx] != kDenseNone;
+        if (dense && (a.tau != 0.0 || a.tau_row != nullptr)) return FPS_OK;
         const int64_t n = ws.n;
         FPS_TRY(colsum.ensure(sizeof(unsigned long long) * (size_t)(3 * n + 3)));
         unsigned long long* cs = colsum.as<unsigned long long>();
         const double t_learned = alg1_learned_t[(size_t)idx];
-        const bool spec = device_iters >= 2 && kAlg1DropLearned && t_learned > 0.0 && t_learned < eps_g;
+        const bool spec = !dense && device_iters >= 2 && kAlg1DropLearned && t_learned > 0.0 && t_learned < eps_g;
         HIP_TRY(launch_fill_u64(cs, (spec ? 3 : 2) * n + 3, 0ull, s));
         a.dscale = std::ldexp(1.0, 40) / eps_g;
         a.dcount = 0;
-        if (device_iters == 1 && kAlg1DropFirst) {
+        if (!dense && device_iters == 1 && kAlg1DropFirst) {
             // keep |x| > eps_g: !(|x| < tau) with tau the next double above eps_g
             a.dsum = cs;
             a.tau = std::nextafter(eps_g, HUGE_VAL);

@@ -459,6 +459,10 @@ __global__ void __launch_bounds__(kB) k_dense_to_slack(const double* __restrict_
                         P.out.col[o + pos] = (int32_t)c;
                         P.out.val[o + pos] = x;
                     }
+                    // Algorithm 1's first-iteration candidates (|x| <= dthr), as
+                    // the sparse write-out sums them
+                    if (P.dsum != nullptr && fabs(x) <= P.dthr)
+                        atomicAdd(&P.dsum[c], (unsigned long long)ceil(fabs(x) * P.dscale));
                     amx = fmax(amx, fabs(x));
                     first = min(first, (int32_t)c);
                     last = max(last, (int32_t)c);

@@ -169,6 +169,9 @@ def test_banded_series_mode_exact_dense_bitwise(bw):
             got = download(plan.result())
             gst = plan.stats()
             assert 3 in gst["stage_dense"], gst["stage_dense"]
+            if e > 0:  # Algorithm 1's first sums taken by the dense write-out
+                modes = [m for m, d in zip(gst["stage_alg1_mode"], gst["stage_dense"]) if d]
+                assert modes and all(m == 1 for m in modes), (gst["stage_alg1_mode"], gst["stage_dense"])
             check_canonical(got)
             assert_same_csr(got, want, f"banded b = {bw}, exact dense paths, evaluation {e}")
     finally:
