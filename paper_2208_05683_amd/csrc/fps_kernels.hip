@@ -2656,8 +2656,9 @@ __global__ void __launch_bounds__(kAlg1Threads) k_alg1_iter(const int64_t* __res
     unsigned long long* mxs = cs + 2 * n;
     const Alg1State cur = alg1_state(pr, i, st, mxs);
     if (blockIdx.x == 0 && threadIdx.x == 0) st[i & 1] = cur;
-    // (first iteration summed by the numeric kernel's write-out: the host
-    // cleared every buffer before it, and a single block records the state)
+    // (a first iteration summed by the numeric kernel's write-out is not
+    // launched: the host cleared every buffer before it, and the maximum
+    // kernel records its state)
     if (cur.done || (i == 0 && fused0)) return;
     const int64_t nthreads = (int64_t)gridDim.x * kAlg1Threads;
     unsigned long long* next = cs + (int64_t)((i + 1) & 1) * n;
@@ -2669,9 +2670,16 @@ __global__ void __launch_bounds__(kAlg1Threads) k_alg1_iter(const int64_t* __res
     alg1_block_colsums(beg, end, col, val, info, n, cur.t, pr.scale, cs + (int64_t)(i & 1) * n);
 }
 
-__global__ void __launch_bounds__(kBlock) k_alg1_max(int64_t n, int i, const Alg1State* st, unsigned long long* cs)
+// first: iteration 0 whose sums the numeric write-out took (no iteration
+// launch before this one); block 0 records the first state.
+__global__ void __launch_bounds__(kBlock) k_alg1_max(int64_t n, int i, Alg1State* st, unsigned long long* cs,
+                                                     int first, double eps_g)
 {
-    if (st[i & 1].done) return;
+    if (first) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st[0] = Alg1State{eps_g, 0.0, 0, 0, 0, 0};  // m_0 = 1
+    } else if (st[i & 1].done) {
+        return;
+    }
     __shared__ unsigned long long sh[kBlock / kWave];
     const unsigned long long* sums = cs + (int64_t)(i & 1) * n;
     unsigned long long m = 0;
@@ -3016,11 +3024,14 @@ hipError_t launch_alg1_device(const int64_t* beg, int64_t* end, int32_t* col, do
         return hipGetLastError();
     }
     for (int i = 0; i < iters; ++i) {
-        hipLaunchKernelGGL(k_alg1_iter, dim3(i == 0 && fused0 ? 1u : iter_blocks), dim3(kAlg1Threads), 0, s,
-                           (const int64_t*)beg,
-                           (const int64_t*)end, (const int32_t*)col, (const double*)val, (const RowInfo*)info, n, pr,
-                           i, st, cs, fused0, base);
-        hipLaunchKernelGGL(k_alg1_max, dim3(max_blocks), dim3(kBlock), 0, s, n, i, (const Alg1State*)st, cs);
+        // (the first iteration of a write-out that took its sums has only its
+        // maximum to take)
+        const int first = i == 0 && fused0 ? 1 : 0;
+        if (!first)
+            hipLaunchKernelGGL(k_alg1_iter, dim3(iter_blocks), dim3(kAlg1Threads), 0, s, (const int64_t*)beg,
+                               (const int64_t*)end, (const int32_t*)col, (const double*)val, (const RowInfo*)info, n,
+                               pr, i, st, cs, fused0, base);
+        hipLaunchKernelGGL(k_alg1_max, dim3(max_blocks), dim3(kBlock), 0, s, n, i, st, cs, first, pr.eps_g);
     }
     // (finalize_only: the numeric write-out already applied the threshold; one
     // block records the final state and raises the flags)
