@@ -490,12 +490,14 @@ struct Engine {
     // the analysis' multiply-adds at the measured rate of the row kernel the
     // rows will take (2.5e11 per second in shared memory, 5e10 in the
     // device-memory kernel for rows beyond 512 entries on average); dense:
-    // 2 ld^3 flops at 4e13 per second on the matrix cores, five passes over
-    // ld^2 doubles at 3 TB/s (fills, densify, write-out) and 20 us of launches.
+    // 2 ld^3 flops at 5e13 per second on the matrix cores (4.9e13 measured at
+    // ld = 1024, 6.5e13 at 8064), four passes over ld^2 doubles at 4 TB/s
+    // (densify, Bhat, the product's and the slack write-outs) and 10 us of
+    // launches.
     // The path of a product stage by modelled time: sparse = the analysis'
     // multiply-adds at the rate of the row kernel its rows take (2.5e11/s in
     // shared memory, 5e10/s in the device-memory kernel, measured); matrix
-    // cores = 2 ld^3 at 4e13 flop/s plus five passes over ld^2 doubles; the
+    // cores = 2 ld^3 at 5e13 flop/s plus four passes over ld^2 doubles; the
     // ordered product on the vector units = 2 ld^3 at 3e13 flop/s plus five
     // passes; dense rows = one row of B (ld doubles) streamed per stored entry
     // of A at 4 TB/s plus four passes.  The matrix cores only with
@@ -521,7 +523,7 @@ struct Engine {
         const double ld = (double)dense_ld(ws.n);
         const double per_row = (double)bound_total / (double)std::max<int64_t>(ws.n, 1);
         const double t_sparse = (double)prods / (per_row > 512.0 ? 5e10 : 2.5e11);
-        const double t_mfma = (flags & FPS_FLAG_DENSE) ? 2.0 * ld * ld * ld / 4e13 + 5.0 * ld * ld * 8.0 / 3e12 + 20e-6
+        const double t_mfma = (flags & FPS_FLAG_DENSE) ? 2.0 * ld * ld * ld / 5e13 + 4.0 * ld * ld * 8.0 / 4e12 + 10e-6
                                                         : HUGE_VAL;
         const double t_rows = (double)a_nnz * ld * 8.0 / 4e12 + 4.0 * ld * ld * 8.0 / 3e12 + 20e-6;
         const double t_ordered = 2.0 * ld * ld * ld / 3e13 + 5.0 * ld * ld * 8.0 / 3e12 + 20e-6;
